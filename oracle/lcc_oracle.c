@@ -1,0 +1,724 @@
+/*
+ * lcc_oracle.c -- plain, slow, single-threaded CPU reference for the LambdaCC
+ * best-move local search, graph compression, objective and the multi-level
+ * driver (Shi, Dhulipala, Eisenstat, Lacki, Mirrokni, "Scalable Community
+ * Detection via Parallel Correlation Clustering", arXiv 2108.01731).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the parity oracle: only the test
+ * suite, the smoke check and the CPU-baseline leg of the benchmark may load it.
+ * The product library never links, loads or calls it, and it shares no code,
+ * header, table or helper with the GPU path.
+ *
+ * Everything is integer arithmetic: int64 weights, vertex weights, cluster
+ * totals and gains; __int128 only for the final objective numerator.  The
+ * resolution is a rational lambda = p/q (p >= 0, q >= 1), so every comparison
+ * the method makes is exact.
+ *
+ * Paper passages this follows (cited by section / equation / algorithm):
+ *   - Sec. 2 (Preliminaries): the rescaled weights w'_uv and the objective
+ *     CC(x) = sum over V x V of w'_ij (1 - x_ij); modularity as the special
+ *     case k_v = d_v, lambda = gamma / 2m.
+ *   - Appendix A: the change in objective when v moves from c to c'.
+ *   - Algorithm 1 (Best-Moves, Parallel-CC) and Sec. 3.2.1 (synchronous move
+ *     application), Sec. 3.2.2 (neighbors-of-moved-vertices frontier),
+ *     Sec. 3.2.3 (multi-level refinement).
+ *   - Sec. 3.1 and Appendix B (compress: one vertex per cluster, k'(c) = K_c,
+ *     parallel edges summed; flatten: C[v] <- C'[id(C[v])]).
+ *
+ * Readings where the paper is silent (each listed in the design notes):
+ *   - The move schedule is synchronous over seeded subsets: in iteration `it`
+ *     of a Best-Moves call at level `l`, phase `ph` (0 = coarsening, 1 =
+ *     refinement), vertex v belongs to sub-round color(v) = mix(h ^ v) mod S
+ *     with h = mix(seed ^ mix(l << 33 | ph << 32 | it)); mix is SplitMix64.
+ *     Each sub-round decides all its vertices against one snapshot, then
+ *     applies the moves together.  S = 1 is the paper's synchronous setting.
+ *   - Candidates for v in cluster c: every cluster holding a neighbor of v
+ *     (any arc, whatever its weight), plus "isolate" (a fresh empty cluster)
+ *     when allow_isolate is set and |c| >= 2.  Best target: highest gain,
+ *     ties to the lowest cluster id, isolate ranks after every id.  v moves
+ *     only on a strict improvement over staying.
+ *   - Isolated vertices take, in ascending vertex order, the ascending ids of
+ *     the clusters that are empty after the sub-round's moves.
+ *   - Frontier "neighbors of moved vertices": the union of N(v) over every v
+ *     that moved in any sub-round of the iteration (v itself is not added).
+ *   - Compress numbers clusters by the rank of their id among non-empty ids;
+ *     self-loops of the contracted graph are kept out of the adjacency, in a
+ *     per-vertex self weight s, and kk (sum of k^2 over original members) is
+ *     carried so the objective stays exact at every level.
+ *   - The objective reported is the unordered-pair sum (half of the V x V sum
+ *     in Sec. 2), as an exact numerator over q.
+ *   - Final labels: dense rank of each cluster's smallest member.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef __int128 i128;
+
+#define ORC_OK 0
+#define ORC_INVALID 1
+#define ORC_OVERFLOW 2
+#define ORC_NOMEM 3
+
+#define ORC_FRONTIER_ALL 0
+#define ORC_FRONTIER_NBR 1
+
+#define ORC_TERM_NO_MOVES 0
+#define ORC_TERM_NUM_ITER 1
+#define ORC_TERM_STOPPED 2
+
+#define ORC_ISO (-1)
+#define ORC_MAX_ITER_STATS 64
+#define ORC_MAX_LEVELS 64
+
+static const i128 I64LIM = (i128)INT64_MAX;
+
+/* A graph at some level.  Rows are sorted or not; no self-loops; symmetric.
+ * wt == NULL means every arc weighs 1.  s == NULL means all self weights 0;
+ * kk == NULL means kk_v = k_v^2 (an uncontracted graph). */
+typedef struct {
+  int64_t n;
+  int64_t arcs;
+  const int64_t *off;
+  const int32_t *col;
+  const int64_t *wt;
+  const int64_t *k;
+  const int64_t *s;
+  const int64_t *kk;
+} orc_graph;
+
+typedef struct {
+  int32_t S;
+  int32_t num_iter;
+  uint64_t seed;
+  int32_t frontier;
+  int32_t refine;
+  int32_t allow_isolate;
+  int32_t max_levels;
+  int64_t stop_after_subrounds; /* 0 = no limit */
+} orc_params;
+
+typedef struct {
+  int32_t iterations;
+  int32_t subrounds;
+  int32_t moved_any;
+  int32_t term;
+  int64_t moves;
+  int64_t arcs_scanned;
+  int64_t vertices_processed;
+  int64_t active_per_iter[ORC_MAX_ITER_STATS];
+  int64_t moves_per_iter[ORC_MAX_ITER_STATS];
+} orc_bm_stats;
+
+/* A graph the oracle allocated (compress output). */
+typedef struct {
+  int64_t n;
+  int64_t arcs;
+  int64_t *off;
+  int32_t *col;
+  int64_t *wt;
+  int64_t *k;
+  int64_t *s;
+  int64_t *kk;
+} orc_graph_out;
+
+typedef struct {
+  int32_t levels;          /* number of graphs in the hierarchy (>= 1) */
+  int32_t top_moved;       /* 1 if the top level stopped because of max_levels */
+  int64_t n_level[ORC_MAX_LEVELS];
+  int64_t arcs_level[ORC_MAX_LEVELS];
+  int32_t iters_coarsen[ORC_MAX_LEVELS];
+  int32_t iters_refine[ORC_MAX_LEVELS];
+  int64_t moves_total;
+  int64_t arcs_scanned_total;
+  int64_t clusters;
+} orc_cluster_stats;
+
+/* ---------------------------------------------------------------- hashing */
+
+/* SplitMix64 output function (Steele, Lea, Flood 2014; Vigna's public-domain
+ * splitmix64): the state is advanced by the golden-ratio increment and then
+ * scrambled by two xor-shift-multiply steps and a final xor-shift. */
+uint64_t orc_mix64(uint64_t x) {
+  uint64_t z = x + 0x9E3779B97F4A7C15ULL;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+uint64_t orc_round_hash(uint64_t seed, int32_t level, int32_t phase, int32_t it) {
+  uint64_t ctr = ((uint64_t)(uint32_t)level << 33) | ((uint64_t)(uint32_t)(phase & 1) << 32) |
+                 (uint64_t)(uint32_t)it;
+  return orc_mix64(seed ^ orc_mix64(ctr));
+}
+
+int32_t orc_color(uint64_t h, int64_t v, int32_t S) {
+  return (int32_t)(orc_mix64(h ^ (uint64_t)v) % (uint64_t)S);
+}
+
+/* --------------------------------------------------------- graph accessors */
+
+static int64_t W(const orc_graph *g, int64_t e) { return g->wt ? g->wt[e] : 1; }
+static int64_t S_of(const orc_graph *g, int64_t v) { return g->s ? g->s[v] : 0; }
+static i128 KK_of(const orc_graph *g, int64_t v) {
+  return g->kk ? (i128)g->kk[v] : (i128)g->k[v] * (i128)g->k[v];
+}
+
+/* ------------------------------------------------------ validation checks */
+
+/* Structural checks on a graph: sizes, offsets, column range, no self-loops,
+ * non-negative vertex weights.  Symmetry is a precondition checked separately
+ * (orc_check_symmetric) because it costs a sort. */
+int orc_validate(const orc_graph *g) {
+  if (!g || g->n < 0 || g->n >= (int64_t)INT32_MAX || g->arcs < 0) return ORC_INVALID;
+  if (g->n > 0 && (!g->off || !g->k)) return ORC_INVALID;
+  if (g->arcs > 0 && !g->col) return ORC_INVALID;
+  if (g->n == 0) return g->arcs == 0 ? ORC_OK : ORC_INVALID;
+  if (g->off[0] != 0 || g->off[g->n] != g->arcs) return ORC_INVALID;
+  for (int64_t v = 0; v < g->n; v++) {
+    if (g->off[v + 1] < g->off[v]) return ORC_INVALID;
+    if (g->k[v] < 0) return ORC_INVALID;
+    if (g->kk && g->kk[v] < 0) return ORC_INVALID;
+    for (int64_t e = g->off[v]; e < g->off[v + 1]; e++) {
+      int32_t u = g->col[e];
+      if (u < 0 || (int64_t)u >= g->n || (int64_t)u == v) return ORC_INVALID;
+    }
+  }
+  return ORC_OK;
+}
+
+/* Overflow bounds under which every gain the method forms fits in int64:
+ *   Wabs = (sum over arcs |w|) / 2 + sum |s|,  Ktot = sum k,  KK = sum kk;
+ *   Ktot, Wabs, KK, q*Wabs, p*Ktot, p*floor(Ktot^2/4) <= 2^63-1, and with any
+ *   negative weight also q*Wabs + p*floor(Ktot^2/4) <= 2^63-1.
+ * For v outside X, k_v + K_X <= Ktot so k_v*K_X <= Ktot^2/4; a row's weight
+ * sum is at most Wabs.  Contraction never increases Wabs, Ktot or KK, so the
+ * check made on the input graph covers every level. */
+int orc_precheck(const orc_graph *g, int64_t p, int64_t q) {
+  if (p < 0 || q < 1) return ORC_INVALID;
+  int rc = orc_validate(g);
+  if (rc) return rc;
+  i128 wabs2 = 0, ktot = 0, kksum = 0, sabs = 0;
+  int neg = 0;
+  for (int64_t e = 0; e < g->arcs; e++) {
+    int64_t w = W(g, e);
+    if (w < 0) { neg = 1; wabs2 -= w; } else wabs2 += w;
+    if (wabs2 > 2 * I64LIM + 2) return ORC_OVERFLOW;
+  }
+  for (int64_t v = 0; v < g->n; v++) {
+    int64_t sv = S_of(g, v);
+    if (sv < 0) { neg = 1; sabs -= sv; } else sabs += sv;
+    ktot += g->k[v];
+    kksum += KK_of(g, v);
+    if (sabs > I64LIM || ktot > I64LIM || kksum > I64LIM) return ORC_OVERFLOW;
+  }
+  i128 wabs = wabs2 / 2 + sabs;
+  if (wabs > I64LIM) return ORC_OVERFLOW;
+  i128 kq = (ktot * ktot) / 4;
+  if ((i128)q * wabs > I64LIM) return ORC_OVERFLOW;
+  if ((i128)p * ktot > I64LIM) return ORC_OVERFLOW;
+  if ((i128)p * kq > I64LIM) return ORC_OVERFLOW;
+  if (neg && (i128)q * wabs + (i128)p * kq > I64LIM) return ORC_OVERFLOW;
+  return ORC_OK;
+}
+
+static int cmp_triple(const void *a, const void *b) {
+  const int64_t *x = (const int64_t *)a, *y = (const int64_t *)b;
+  for (int i = 0; i < 3; i++) {
+    if (x[i] < y[i]) return -1;
+    if (x[i] > y[i]) return 1;
+  }
+  return 0;
+}
+
+/* 1 if the arc multiset equals its reverse (same weights both ways). */
+int orc_check_symmetric(const orc_graph *g) {
+  int64_t m = g->arcs;
+  if (m == 0) return 1;
+  int64_t *a = (int64_t *)malloc(sizeof(int64_t) * 3 * (size_t)m);
+  int64_t *b = (int64_t *)malloc(sizeof(int64_t) * 3 * (size_t)m);
+  if (!a || !b) { free(a); free(b); return -1; }
+  for (int64_t v = 0; v < g->n; v++)
+    for (int64_t e = g->off[v]; e < g->off[v + 1]; e++) {
+      a[3 * e] = v; a[3 * e + 1] = g->col[e]; a[3 * e + 2] = W(g, e);
+      b[3 * e] = g->col[e]; b[3 * e + 1] = v; b[3 * e + 2] = W(g, e);
+    }
+  qsort(a, (size_t)m, 3 * sizeof(int64_t), cmp_triple);
+  qsort(b, (size_t)m, 3 * sizeof(int64_t), cmp_triple);
+  int ok = memcmp(a, b, sizeof(int64_t) * 3 * (size_t)m) == 0;
+  free(a); free(b);
+  return ok;
+}
+
+/* ------------------------------------------------------ cluster bookkeeping */
+
+/* K_X = sum of k_v over v in X, cnt_X = |X|, for cluster ids in [0, n). */
+static int cluster_totals(const orc_graph *g, const int32_t *C, int64_t *K, int32_t *cnt) {
+  for (int64_t x = 0; x < g->n; x++) { K[x] = 0; cnt[x] = 0; }
+  for (int64_t v = 0; v < g->n; v++) {
+    int32_t c = C[v];
+    if (c < 0 || (int64_t)c >= g->n) return ORC_INVALID;
+    K[c] += g->k[v];
+    cnt[c] += 1;
+  }
+  return ORC_OK;
+}
+
+/* Scratch for one vertex decision: a dense accumulator indexed by cluster id
+ * plus the list of ids it touched, so a reset costs only the touched ids. */
+typedef struct {
+  int64_t *acc;
+  uint8_t *seen;
+  int32_t *list;
+} decide_scratch;
+
+static int scratch_init(decide_scratch *d, int64_t n) {
+  size_t m = (size_t)(n > 0 ? n : 1);
+  d->acc = (int64_t *)calloc(m, sizeof(int64_t));
+  d->seen = (uint8_t *)calloc(m, 1);
+  d->list = (int32_t *)malloc(m * sizeof(int32_t));
+  return (d->acc && d->seen && d->list) ? ORC_OK : ORC_NOMEM;
+}
+static void scratch_free(decide_scratch *d) { free(d->acc); free(d->seen); free(d->list); }
+
+/* The best move of v against a fixed snapshot (C, K, cnt), Algorithm 1's
+ * per-vertex step with the Appendix A change in objective.  The change for
+ * moving v from c to X != c, scaled by q, is
+ *     [q*w(v,X) - p*k_v*K_X] - [q*w(v,c) - p*k_v*(K_c - k_v)],
+ * and moving v to a fresh empty cluster has first bracket 0.  The bracketed
+ * terms are the "scores"; comparing scores compares the changes exactly.
+ * Returns the target id, ORC_ISO, or c to stay. */
+static int32_t decide(const orc_graph *g, int64_t p, int64_t q, int allow_iso, const int32_t *C,
+                      const int64_t *K, const int32_t *cnt, int64_t v, decide_scratch *d) {
+  int32_t c = C[v];
+  int64_t kv = g->k[v];
+  int64_t nl = 0;
+  for (int64_t e = g->off[v]; e < g->off[v + 1]; e++) {
+    int32_t X = C[g->col[e]];
+    if (!d->seen[X]) { d->seen[X] = 1; d->acc[X] = 0; d->list[nl++] = X; }
+    d->acc[X] += W(g, e);
+  }
+  int64_t w_c = d->seen[c] ? d->acc[c] : 0;
+  int64_t stay = q * w_c - (p * kv) * (K[c] - kv);
+  int have = 0;
+  int64_t best = 0;
+  int32_t best_id = 0;
+  for (int64_t i = 0; i < nl; i++) {
+    int32_t X = d->list[i];
+    if (X == c) continue;
+    int64_t sc = q * d->acc[X] - (p * kv) * K[X];
+    if (!have || sc > best || (sc == best && X < best_id)) { have = 1; best = sc; best_id = X; }
+  }
+  if (allow_iso && cnt[c] >= 2) {
+    /* isolate scores 0 and loses every tie against a real cluster id */
+    if (!have || 0 > best) { have = 1; best = 0; best_id = ORC_ISO; }
+  }
+  for (int64_t i = 0; i < nl; i++) d->seen[d->list[i]] = 0;
+  if (have && best > stay) return best_id;
+  return c;
+}
+
+/* Applies the decisions D of the vertices in U together (Sec. 3.2.1,
+ * synchronous setting), then hands the isolated vertices, in ascending vertex
+ * order, the ascending ids of the clusters that are empty after the moves.
+ * Returns the number of vertices whose decision differed from their cluster. */
+static int64_t apply_moves(const orc_graph *g, int32_t *C, int64_t *K, int32_t *cnt,
+                           const int32_t *U, int64_t nu, const int32_t *D, uint8_t *iso_flag) {
+  int64_t moved = 0, niso = 0;
+  for (int64_t i = 0; i < nu; i++) {
+    int32_t v = U[i];
+    int32_t c = C[v], d = D[i];
+    if (d == c) continue;
+    moved++;
+    K[c] -= g->k[v];
+    cnt[c] -= 1;
+    if (d == ORC_ISO) {
+      iso_flag[v] = 1;
+      niso++;
+      C[v] = ORC_ISO;
+    } else {
+      K[d] += g->k[v];
+      cnt[d] += 1;
+      C[v] = d;
+    }
+  }
+  if (niso) {
+    int64_t x = 0;
+    for (int64_t v = 0; v < g->n; v++) {
+      if (!iso_flag[v]) continue;
+      iso_flag[v] = 0;
+      while (cnt[x] != 0) x++; /* pigeonhole: at most n - niso ids are non-empty */
+      C[v] = (int32_t)x;
+      K[x] = g->k[v];
+      cnt[x] = 1;
+      x++;
+    }
+  }
+  return moved;
+}
+
+/* One synchronous sub-round over an explicit vertex list U (a test hook for
+ * the sub-round semantics; Best-Moves itself builds U from the hash colors).
+ * C is updated in place; D_out (length nu, may be NULL) receives the decisions
+ * (ORC_ISO for isolate).  Returns the number of movers, or -1 on error. */
+int64_t orc_subround(const orc_graph *g, int64_t p, int64_t q, int32_t allow_iso, int32_t *C,
+                     const int32_t *U, int64_t nu, int32_t *D_out) {
+  int64_t n = g->n;
+  int64_t *K = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n ? n : 1));
+  int32_t *cnt = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n ? n : 1));
+  int32_t *D = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nu ? nu : 1));
+  uint8_t *iso = (uint8_t *)calloc((size_t)(n ? n : 1), 1);
+  decide_scratch sc;
+  int64_t moved = -1;
+  if (!K || !cnt || !D || !iso || scratch_init(&sc, n)) goto out;
+  if (cluster_totals(g, C, K, cnt)) { scratch_free(&sc); goto out; }
+  for (int64_t i = 0; i < nu; i++) D[i] = decide(g, p, q, allow_iso, C, K, cnt, U[i], &sc);
+  if (D_out) memcpy(D_out, D, sizeof(int32_t) * (size_t)nu);
+  moved = apply_moves(g, C, K, cnt, U, nu, D, iso);
+  scratch_free(&sc);
+out:
+  free(K); free(cnt); free(D); free(iso);
+  return moved;
+}
+
+/* Decisions of the listed vertices against the clustering C, without moving
+ * anything (used to check sampled vertices of very large graphs). */
+int orc_decide_many(const orc_graph *g, int64_t p, int64_t q, int32_t allow_iso, const int32_t *C,
+                    const int32_t *U, int64_t nu, int32_t *D_out) {
+  int64_t n = g->n;
+  int64_t *K = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n ? n : 1));
+  int32_t *cnt = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n ? n : 1));
+  decide_scratch sc;
+  int rc = ORC_NOMEM;
+  if (!K || !cnt || scratch_init(&sc, n)) goto out;
+  rc = cluster_totals(g, C, K, cnt);
+  if (!rc)
+    for (int64_t i = 0; i < nu; i++) D_out[i] = decide(g, p, q, allow_iso, C, K, cnt, U[i], &sc);
+  scratch_free(&sc);
+out:
+  free(K); free(cnt);
+  return rc;
+}
+
+/* Frontier "neighbors of moved vertices" (Algorithm 1, Sec. 3.2.2):
+ * flags[u] = 1 for every neighbor u of a listed mover. */
+void orc_frontier_nbr(const orc_graph *g, const int32_t *movers, int64_t nm, uint8_t *flags) {
+  for (int64_t i = 0; i < nm; i++) {
+    int32_t v = movers[i];
+    for (int64_t e = g->off[v]; e < g->off[v + 1]; e++) flags[g->col[e]] = 1;
+  }
+}
+
+/* -------------------------------------------------------------- Best-Moves */
+
+/* Best-Moves (Algorithm 1, top) from the clustering in C, at hierarchy level
+ * `level` and phase 0 (coarsening) or 1 (refinement).  At most num_iter
+ * iterations; each iteration runs S sub-rounds over the active vertices;
+ * stops after an iteration with no move. */
+static int best_move_impl(const orc_graph *g, int64_t p, int64_t q, const orc_params *prm,
+                          int32_t level, int32_t phase, int32_t *C, orc_bm_stats *st) {
+  int64_t n = g->n;
+  orc_bm_stats local;
+  if (!st) st = &local;
+  memset(st, 0, sizeof(*st));
+  if (prm->S < 1 || prm->num_iter < 0) return ORC_INVALID;
+  size_t nn = (size_t)(n ? n : 1);
+  int64_t *K = (int64_t *)malloc(sizeof(int64_t) * nn);
+  int32_t *cnt = (int32_t *)malloc(sizeof(int32_t) * nn);
+  uint8_t *active = (uint8_t *)malloc(nn);
+  uint8_t *next = (uint8_t *)calloc(nn, 1);
+  uint8_t *iso = (uint8_t *)calloc(nn, 1);
+  int32_t *U = (int32_t *)malloc(sizeof(int32_t) * nn);
+  int32_t *D = (int32_t *)malloc(sizeof(int32_t) * nn);
+  decide_scratch sc;
+  int rc = ORC_NOMEM;
+  if (!K || !cnt || !active || !next || !iso || !U || !D || scratch_init(&sc, n)) goto out;
+  rc = cluster_totals(g, C, K, cnt);
+  if (rc) { scratch_free(&sc); goto out; }
+  memset(active, 1, nn);
+  st->term = ORC_TERM_NUM_ITER;
+  for (int32_t it = 0; it < prm->num_iter; it++) {
+    uint64_t h = orc_round_hash(prm->seed, level, phase, it);
+    int64_t moved_it = 0, active_it = 0;
+    for (int64_t v = 0; v < n; v++) active_it += active[v];
+    st->iterations++;
+    for (int32_t s = 0; s < prm->S; s++) {
+      if (prm->stop_after_subrounds > 0 && st->subrounds >= prm->stop_after_subrounds) {
+        st->term = ORC_TERM_STOPPED;
+        if (it < ORC_MAX_ITER_STATS) { st->active_per_iter[it] = active_it; st->moves_per_iter[it] = moved_it; }
+        goto done;
+      }
+      int64_t nu = 0;
+      for (int64_t v = 0; v < n; v++)
+        if (active[v] && orc_color(h, v, prm->S) == s) U[nu++] = (int32_t)v;
+      /* every decision of the sub-round reads the same snapshot */
+      for (int64_t i = 0; i < nu; i++) {
+        D[i] = decide(g, p, q, prm->allow_isolate, C, K, cnt, U[i], &sc);
+        st->arcs_scanned += g->off[U[i] + 1] - g->off[U[i]];
+      }
+      st->vertices_processed += nu;
+      for (int64_t i = 0; i < nu; i++)
+        if (D[i] != C[U[i]]) orc_frontier_nbr(g, &U[i], 1, next);
+      int64_t mv = apply_moves(g, C, K, cnt, U, nu, D, iso);
+      moved_it += mv;
+      st->subrounds++;
+    }
+    if (it < ORC_MAX_ITER_STATS) { st->active_per_iter[it] = active_it; st->moves_per_iter[it] = moved_it; }
+    st->moves += moved_it;
+    if (moved_it == 0) { st->term = ORC_TERM_NO_MOVES; break; }
+    st->moved_any = 1;
+    if (prm->frontier == ORC_FRONTIER_ALL) {
+      memset(active, 1, nn);
+    } else {
+      memcpy(active, next, nn);
+    }
+    memset(next, 0, nn);
+  }
+done:
+  /* moves of a partial (stopped) iteration also count */
+  if (st->term == ORC_TERM_STOPPED) {
+    int32_t it = st->iterations - 1;
+    int64_t mv = (it >= 0 && it < ORC_MAX_ITER_STATS) ? st->moves_per_iter[it] : 0;
+    st->moves += mv;
+    if (mv) st->moved_any = 1;
+  }
+  scratch_free(&sc);
+  rc = ORC_OK;
+out:
+  free(K); free(cnt); free(active); free(next); free(iso); free(U); free(D);
+  return rc;
+}
+
+int orc_best_move(const orc_graph *g, int64_t p, int64_t q, const orc_params *prm, int32_t level,
+                  int32_t phase, int32_t *C, orc_bm_stats *st) {
+  int rc = orc_precheck(g, p, q);
+  if (rc) return rc;
+  return best_move_impl(g, p, q, prm, level, phase, C, st);
+}
+
+/* ---------------------------------------------------------------- compress */
+
+void orc_graph_free(orc_graph_out *o) {
+  if (!o) return;
+  free(o->off); free(o->col); free(o->wt); free(o->k); free(o->s); free(o->kk);
+  memset(o, 0, sizeof(*o));
+}
+
+/* Compress (Sec. 3.1, Appendix B): one vertex per non-empty cluster, numbered
+ * by the rank of the cluster id among non-empty ids (map[v] = rank of C[v]);
+ * k'(c) = K_c; kk'(c) = sum of kk over members; s'(c) = sum of members' s plus
+ * the weight of the edges inside c; the edges between two clusters are
+ * combined into one edge carrying the summed weight (kept even when the sum
+ * is 0).  Rows of the output are sorted by neighbor id. */
+int orc_compress(const orc_graph *g, const int32_t *C, orc_graph_out *out, int32_t *map) {
+  int64_t n = g->n;
+  memset(out, 0, sizeof(*out));
+  if (orc_validate(g)) return ORC_INVALID;
+  size_t nn = (size_t)(n ? n : 1);
+  int32_t *rank = (int32_t *)malloc(sizeof(int32_t) * nn);
+  uint8_t *present = (uint8_t *)calloc(nn, 1);
+  int64_t *trip = NULL;
+  i128 *intra = NULL;
+  int rc = ORC_NOMEM;
+  if (!rank || !present) goto fail;
+  for (int64_t v = 0; v < n; v++) {
+    if (C[v] < 0 || (int64_t)C[v] >= n) { rc = ORC_INVALID; goto fail; }
+    present[C[v]] = 1;
+  }
+  int64_t n2 = 0;
+  for (int64_t x = 0; x < n; x++) rank[x] = present[x] ? (int32_t)n2++ : -1;
+  for (int64_t v = 0; v < n; v++) map[v] = rank[C[v]];
+  out->n = n2;
+  size_t n2s = (size_t)(n2 ? n2 : 1);
+  out->k = (int64_t *)calloc(n2s, sizeof(int64_t));
+  out->s = (int64_t *)calloc(n2s, sizeof(int64_t));
+  out->kk = (int64_t *)calloc(n2s, sizeof(int64_t));
+  out->off = (int64_t *)calloc(n2s + 1, sizeof(int64_t));
+  intra = (i128 *)calloc(n2s, sizeof(i128));
+  if (!out->k || !out->s || !out->kk || !out->off || !intra) goto fail;
+  int64_t ninter = 0;
+  for (int64_t v = 0; v < n; v++) {
+    int32_t cv = map[v];
+    out->k[cv] += g->k[v];
+    out->kk[cv] += (int64_t)KK_of(g, v);
+    intra[cv] += 2 * (i128)S_of(g, v);
+    for (int64_t e = g->off[v]; e < g->off[v + 1]; e++) {
+      if (map[g->col[e]] == cv) intra[cv] += W(g, e);
+      else ninter++;
+    }
+  }
+  /* each intra edge was seen from both endpoints, each self weight doubled */
+  for (int64_t c = 0; c < n2; c++) out->s[c] = (int64_t)(intra[c] / 2);
+  trip = (int64_t *)malloc(sizeof(int64_t) * 3 * (size_t)(ninter ? ninter : 1));
+  if (!trip) goto fail;
+  int64_t t = 0;
+  for (int64_t v = 0; v < n; v++)
+    for (int64_t e = g->off[v]; e < g->off[v + 1]; e++) {
+      int32_t a = map[v], b = map[g->col[e]];
+      if (a == b) continue;
+      trip[3 * t] = a; trip[3 * t + 1] = b; trip[3 * t + 2] = W(g, e);
+      t++;
+    }
+  /* sort by (row, column); the weight in the third slot only makes the order total */
+  qsort(trip, (size_t)ninter, 3 * sizeof(int64_t), cmp_triple);
+  int64_t m2 = 0;
+  for (int64_t i = 0; i < ninter; i++)
+    if (i == 0 || trip[3 * i] != trip[3 * (i - 1)] || trip[3 * i + 1] != trip[3 * (i - 1) + 1]) m2++;
+  out->arcs = m2;
+  out->col = (int32_t *)malloc(sizeof(int32_t) * (size_t)(m2 ? m2 : 1));
+  out->wt = (int64_t *)malloc(sizeof(int64_t) * (size_t)(m2 ? m2 : 1));
+  if (!out->col || !out->wt) goto fail;
+  int64_t j = -1;
+  for (int64_t i = 0; i < ninter; i++) {
+    if (i == 0 || trip[3 * i] != trip[3 * (i - 1)] || trip[3 * i + 1] != trip[3 * (i - 1) + 1]) {
+      j++;
+      out->col[j] = (int32_t)trip[3 * i + 1];
+      out->wt[j] = 0;
+      out->off[trip[3 * i] + 1]++;
+    }
+    out->wt[j] += trip[3 * i + 2];
+  }
+  for (int64_t c = 0; c < n2; c++) out->off[c + 1] += out->off[c];
+  free(rank); free(present); free(trip); free(intra);
+  return ORC_OK;
+fail:
+  free(rank); free(present); free(trip); free(intra);
+  orc_graph_free(out);
+  return rc;
+}
+
+/* --------------------------------------------------------------- objective */
+
+/* The objective of Sec. 2 over unordered pairs: the sum over pairs {i, j} in
+ * the same cluster of w'_ij, where w'_ij = w_ij - lambda*k_i*k_j on edges and
+ * -lambda*k_i*k_j on non-edges.  With lambda = p/q the value is N/q with
+ *   N = q*(sum_v s_v + W_in) - p * sum_X (K_X^2 - sum_{v in X} kk_v) / 2,
+ * W_in the weight of edges inside clusters (each edge once).  (The V x V sum
+ * of Sec. 2 counts every pair twice and equals 2N/q.)  Returns N split in two
+ * 64-bit halves. */
+int orc_objective(const orc_graph *g, int64_t p, int64_t q, const int32_t *C, int64_t *num_hi,
+                  uint64_t *num_lo) {
+  int rc = orc_precheck(g, p, q);
+  if (rc) return rc;
+  int64_t n = g->n;
+  size_t nn = (size_t)(n ? n : 1);
+  i128 *K = (i128 *)calloc(nn, sizeof(i128));
+  i128 *KK = (i128 *)calloc(nn, sizeof(i128));
+  if (!K || !KK) { free(K); free(KK); return ORC_NOMEM; }
+  i128 win2 = 0, ssum = 0;
+  for (int64_t v = 0; v < n; v++) {
+    if (C[v] < 0 || (int64_t)C[v] >= n) { free(K); free(KK); return ORC_INVALID; }
+    K[C[v]] += g->k[v];
+    KK[C[v]] += KK_of(g, v);
+    ssum += S_of(g, v);
+    for (int64_t e = g->off[v]; e < g->off[v + 1]; e++)
+      if (C[g->col[e]] == C[v]) win2 += W(g, e);
+  }
+  i128 pairs2 = 0;
+  for (int64_t x = 0; x < n; x++) pairs2 += K[x] * K[x] - KK[x];
+  i128 N = (i128)q * (ssum + win2 / 2) - (i128)p * (pairs2 / 2);
+  *num_hi = (int64_t)(N >> 64);
+  *num_lo = (uint64_t)N;
+  free(K); free(KK);
+  return ORC_OK;
+}
+
+/* -------------------------------------------------------- labels / cluster */
+
+/* Canonical labels: clusters numbered 0, 1, ... in the order of their
+ * smallest member. */
+int orc_canonical_labels(int64_t n, const int32_t *C, int32_t *labels) {
+  size_t nn = (size_t)(n ? n : 1);
+  int32_t *minv = (int32_t *)malloc(sizeof(int32_t) * nn);
+  int32_t *lab = (int32_t *)malloc(sizeof(int32_t) * nn);
+  if (!minv || !lab) { free(minv); free(lab); return ORC_NOMEM; }
+  for (int64_t x = 0; x < n; x++) minv[x] = INT32_MAX;
+  for (int64_t v = 0; v < n; v++) {
+    if (C[v] < 0 || (int64_t)C[v] >= n) { free(minv); free(lab); return ORC_INVALID; }
+    if ((int32_t)v < minv[C[v]]) minv[C[v]] = (int32_t)v;
+  }
+  int32_t next = 0;
+  for (int64_t v = 0; v < n; v++)
+    if (minv[C[v]] == (int32_t)v) lab[C[v]] = next++;
+  for (int64_t v = 0; v < n; v++) labels[v] = lab[C[v]];
+  free(minv); free(lab);
+  return ORC_OK;
+}
+
+/* Parallel-CC (Algorithm 1, bottom) with multi-level refinement (Sec. 3.2.3):
+ * Best-Moves from singletons; while it moved something (and the level cap is
+ * not reached) compress and recurse; on the way back flatten each level's
+ * clustering through its map and, with refinement, run Best-Moves again on
+ * that level.  Writes canonical labels and the objective numerator. */
+int orc_cluster(const orc_graph *g0, int64_t p, int64_t q, const orc_params *prm, int32_t *labels,
+                int64_t *num_hi, uint64_t *num_lo, orc_cluster_stats *cs) {
+  int rc = orc_precheck(g0, p, q);
+  if (rc) return rc;
+  if (prm->max_levels < 1 || prm->max_levels > ORC_MAX_LEVELS || prm->S < 1) return ORC_INVALID;
+  orc_cluster_stats local;
+  if (!cs) cs = &local;
+  memset(cs, 0, sizeof(*cs));
+  orc_graph G[ORC_MAX_LEVELS];
+  orc_graph_out owned[ORC_MAX_LEVELS];
+  int32_t *Cl[ORC_MAX_LEVELS];
+  int32_t *map[ORC_MAX_LEVELS];
+  memset(owned, 0, sizeof(owned));
+  memset(Cl, 0, sizeof(Cl));
+  memset(map, 0, sizeof(map));
+  G[0] = *g0;
+  int32_t top = 0;
+  rc = ORC_OK;
+  for (int32_t l = 0;; l++) {
+    int64_t n = G[l].n;
+    cs->n_level[l] = n;
+    cs->arcs_level[l] = G[l].arcs;
+    cs->levels = l + 1;
+    Cl[l] = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n ? n : 1));
+    if (!Cl[l]) { rc = ORC_NOMEM; goto out; }
+    for (int64_t v = 0; v < n; v++) Cl[l][v] = (int32_t)v;
+    orc_bm_stats st;
+    rc = best_move_impl(&G[l], p, q, prm, l, 0, Cl[l], &st);
+    if (rc) goto out;
+    cs->iters_coarsen[l] = st.iterations;
+    cs->moves_total += st.moves;
+    cs->arcs_scanned_total += st.arcs_scanned;
+    if (!st.moved_any || l + 1 == prm->max_levels) {
+      top = l;
+      cs->top_moved = st.moved_any;
+      break;
+    }
+    map[l] = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n ? n : 1));
+    if (!map[l]) { rc = ORC_NOMEM; goto out; }
+    rc = orc_compress(&G[l], Cl[l], &owned[l + 1], map[l]);
+    if (rc) goto out;
+    orc_graph_out *o = &owned[l + 1];
+    G[l + 1].n = o->n; G[l + 1].arcs = o->arcs; G[l + 1].off = o->off; G[l + 1].col = o->col;
+    G[l + 1].wt = o->wt; G[l + 1].k = o->k; G[l + 1].s = o->s; G[l + 1].kk = o->kk;
+  }
+  for (int32_t l = top - 1; l >= 0; l--) {
+    for (int64_t v = 0; v < G[l].n; v++) Cl[l][v] = Cl[l + 1][map[l][v]];
+    if (prm->refine) {
+      orc_bm_stats st;
+      rc = best_move_impl(&G[l], p, q, prm, l, 1, Cl[l], &st);
+      if (rc) goto out;
+      cs->iters_refine[l] = st.iterations;
+      cs->moves_total += st.moves;
+      cs->arcs_scanned_total += st.arcs_scanned;
+    }
+  }
+  rc = orc_canonical_labels(g0->n, Cl[0], labels);
+  if (rc) goto out;
+  {
+    int32_t mx = -1;
+    for (int64_t v = 0; v < g0->n; v++) if (labels[v] > mx) mx = labels[v];
+    cs->clusters = (int64_t)mx + 1;
+  }
+  rc = orc_objective(g0, p, q, labels, num_hi, num_lo);
+out:
+  for (int32_t l = 0; l < ORC_MAX_LEVELS; l++) {
+    free(Cl[l]);
+    free(map[l]);
+    orc_graph_free(&owned[l]);
+  }
+  return rc;
+}

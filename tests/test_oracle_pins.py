@@ -1,0 +1,486 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: the paper's
+definitions evaluated by brute force (tests/brute.py), exhaustive search over
+all partitions, a textbook formula (modularity), a library routine (union-find
+components, numpy's unique), the paper's worked examples (Fig. 1, the star
+graph of Sec. 3.2.2's footnote) and published hash test vectors.
+"""
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2108_01731_amd import graphgen as G
+from tests import brute as B
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def og(h):
+    """graphgen HostGraph (numpy) -> oracle Graph."""
+    h = h.numpy()
+    return O.Graph(off=h.off, col=h.col, k=h.k, wt=None if h.wt is None else h.wt.astype(np.int64),
+                   s=h.s, kk=h.kk)
+
+
+def small(n, m, seed, **kw):
+    return og(G.random_signed(n, m, seed, **kw))
+
+
+# ------------------------------------------------------------------ hashing
+
+
+def test_splitmix64_published_vectors():
+    """mix64 is SplitMix64's output function: published outputs for seeds 0
+    and 1234567 (tests/golden/splitmix64.txt)."""
+    gamma = 0x9E3779B97F4A7C15
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "splitmix64.txt")) if not l.startswith("#")]
+    assert rows
+    for r in rows:
+        state = int(r[0])
+        for i, want in enumerate(r[1:]):
+            assert O.mix64((state + i * gamma) % 2**64) == int(want)
+
+
+def test_color_is_uniformish_and_in_range():
+    h = O.round_hash(7, 2, 1, 3)
+    S = 4
+    cols = np.array([O.color(h, v, S) for v in range(4000)])
+    assert cols.min() >= 0 and cols.max() < S
+    counts = np.bincount(cols, minlength=S)
+    assert counts.min() > 900  # about 1000 each
+    assert O.color(h, 5, 1) == 0
+    # different (level, phase, iteration) give different hashes
+    hs = {O.round_hash(7, l, ph, it) for l in range(3) for ph in range(2) for it in range(3)}
+    assert len(hs) == 18
+
+
+# ---------------------------------------------------------------- objective
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_P1_objective_matches_pair_definition(seed):
+    """Sec. 2: the objective over unordered pairs, from the dense definition,
+    equals the oracle's N / q; the printed V x V form is exactly twice it."""
+    rng = np.random.default_rng(100 + seed)
+    n = int(rng.integers(1, 13))
+    g = small(n, int(rng.integers(0, 3 * n + 1)), seed, wmin=-4, wmax=6, kmax=4)
+    W, E = B.dense(g)
+    p, q = int(rng.integers(0, 5)), int(rng.integers(1, 7))
+    for _ in range(4):
+        C = rng.integers(0, n, size=n).astype(np.int32)
+        N = O.objective(g, p, q, C)
+        assert N == B.objective_q(W, E, g.k, p, q, list(C))
+        assert 2 * N == B.objective_vxv_q(W, E, g.k, p, q, list(C))
+
+
+# --------------------------------------------------------------- move rule
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_P2_decision_matches_brute_force_every_partition(seed):
+    """Appendix A's change in objective, the candidate set, the tie rules and
+    the strict-improvement rule: for every partition of a 6-vertex graph and
+    every vertex, the oracle's decision equals the brute-force best move."""
+    rng = np.random.default_rng(seed)
+    n = 6
+    g = small(n, 11, 50 + seed, wmin=-2, wmax=3, kmax=2)
+    W, E = B.dense(g)
+    p, q = [(1, 2), (1, 3), (0, 1), (2, 3), (1, 1), (3, 7)][seed]
+    allow = seed % 3 != 2
+    U = np.arange(n, dtype=np.int32)
+    checked = 0
+    for part in B.partitions(n):
+        D = O.decide_many(g, p, q, part, U, allow_isolate=int(allow))
+        for v in range(n):
+            want = B.best_single_move(W, E, g.k, p, q, part, v, allow_iso=allow)
+            assert D[v] == want, (part, v, D[v], want)
+            checked += 1
+    assert checked == 203 * n
+
+
+def test_P2_decision_7_vertices_unit_weights():
+    """Same on a 7-vertex unit-weight graph (many exact ties)."""
+    n = 7
+    g = small(n, 14, 999, unit=True)
+    W, E = B.dense(g)
+    U = np.arange(n, dtype=np.int32)
+    for p, q in [(1, 3), (1, 2)]:
+        for part in B.partitions(n):
+            D = O.decide_many(g, p, q, part, U)
+            for v in range(n):
+                assert D[v] == B.best_single_move(W, E, g.k, p, q, part, v)
+
+
+# ------------------------------------------------------------ search sanity
+
+
+def _max_objective(g, p, q):
+    W, E = B.dense(g)
+    return max(B.objective_q(W, E, g.k, p, q, part) for part in B.partitions(g.n))
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_P3_cluster_not_above_exhaustive_optimum(seed):
+    """The result never beats the best of all partitions (n = 8)."""
+    g = small(8, 14, 300 + seed, wmin=-1, wmax=4, kmax=2)
+    p, q = 1, 4
+    lab, N, st = O.cluster(g, p, q, O.Params(S=2, seed=seed))
+    assert N <= _max_objective(g, p, q)
+    W, E = B.dense(g)
+    assert N == B.objective_q(W, E, g.k, p, q, list(lab))
+
+
+def test_P3_cluster_reaches_optimum_on_two_cliques():
+    """Two 4-cliques joined by one edge, k = 1, lambda = 1/4: the optimum (the
+    two cliques) is found."""
+    edges = [(a, b) for a in range(4) for b in range(a + 1, 4)]
+    edges += [(a + 4, b + 4) for a, b in edges] + [(3, 4)]
+    u = np.array([e[0] for e in edges]); v = np.array([e[1] for e in edges])
+    import torch
+
+    off, col, _ = G.csr_from_edges(8, torch.from_numpy(u), torch.from_numpy(v))
+    g = O.Graph(off=off.numpy(), col=col.numpy(), k=np.ones(8, np.int64))
+    lab, N, _ = O.cluster(g, 1, 4, O.Params(S=4))
+    assert N == _max_objective(g, 1, 4)
+    assert list(lab) == [0, 0, 0, 0, 1, 1, 1, 1]
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_P3_all_frontier_ends_in_single_move_local_optimum(seed):
+    """With frontier = all vertices and termination by an iteration without
+    moves, no single vertex can improve the objective by brute force."""
+    g = small(9, 18, 400 + seed, wmin=-2, wmax=4, kmax=3)
+    W, E = B.dense(g)
+    p, q = 1, 5
+    prm = O.Params(S=3, num_iter=200, frontier=O.FRONTIER_ALL, seed=seed)
+    C, st = O.best_move(g, p, q, prm)
+    assert st["term"] == O.TERM_NO_MOVES
+    for v in range(g.n):
+        assert B.best_single_move(W, E, g.k, p, q, list(C), v) == C[v]
+
+
+def test_P3_cluster_vs_exhaustive_n10():
+    """One 10-vertex case against all 115,975 partitions."""
+    g = small(10, 20, 77, wmin=0, wmax=3, kmax=2)
+    p, q = 1, 6
+    W, E = B.dense(g)
+    best = max(B.objective_q(W, E, g.k, p, q, part) for part in B.partitions(10))
+    lab, N, _ = O.cluster(g, p, q, O.Params(S=4, num_iter=50, frontier=O.FRONTIER_ALL))
+    assert N <= best
+    assert N >= 0  # never worse than singletons... singletons have objective 0
+    # the exhaustive optimum is positive here, and local search gets some of it
+    assert best > 0 and N > 0
+
+
+# ---------------------------------------------------------------- modularity
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_P4_modularity_special_case(seed):
+    """Sec. 2: with k_v = d_v and lambda = 1/(2m) the objective is modularity.
+    The textbook Q = sum_X [L_X/m - (D_X/2m)^2] (float64) equals
+    CC/m - sum_v d_v^2 / (4m^2)."""
+    h = G.sbm([40, 40, 40], 0.2, 0.02, seed)
+    g = og(h)
+    deg = np.diff(g.off)
+    g.k = deg.astype(np.int64)
+    m = int(deg.sum()) // 2
+    p, q = 1, 2 * m
+    rng = np.random.default_rng(seed)
+    for C in [rng.integers(0, 6, g.n), O.cluster(g, p, q, O.Params(seed=seed))[0]]:
+        C = np.asarray(C, dtype=np.int64)
+        N = O.objective(g, p, q, C.astype(np.int32))
+        src = np.repeat(np.arange(g.n), deg)
+        intra_arcs = (C[src] == C[g.col]).sum()
+        Qtext = 0.0
+        for X in np.unique(C):
+            LX = ((C[src] == X) & (C[g.col] == X)).sum() / 2.0
+            DX = deg[C == X].sum()
+            Qtext += LX / m - (DX / (2.0 * m)) ** 2
+        cc = float(Fraction(N, q))
+        assert abs(Qtext - (cc / m - float((deg.astype(np.float64) ** 2).sum()) / (4.0 * m * m))) < 1e-12
+        assert intra_arcs % 2 == 0
+
+
+# ------------------------------------------------------------------ compress
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_P5_compress_contraction_invariant(seed):
+    """Compress (Sec. 3.1, Appendix B): for random C on G and C' on G',
+    CC_G(C' o map) == CC_G'(C'), in particular for singletons of G'; totals of
+    k and of self-plus-edge weight are preserved; G' is a valid symmetric
+    graph with sorted rows; map is the rank of C among the non-empty ids; each
+    coarse edge weight is the brute-force sum between the two clusters."""
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(1, 30))
+    g = small(n, int(rng.integers(0, 4 * n)), 700 + seed, wmin=-3, wmax=5, kmax=4)
+    p, q = int(rng.integers(0, 4)), int(rng.integers(1, 9))
+    C = rng.integers(0, max(1, n // 2 + 1), size=n).astype(np.int32)
+    g2, mp = O.compress(g, C)
+    # map is the dense rank of C among present ids
+    uniq, inv = np.unique(C, return_inverse=True)
+    assert np.array_equal(mp, inv.astype(np.int32))
+    assert g2.n == len(uniq)
+    assert O.validate(g2) == O.OK
+    assert O.check_symmetric(g2)
+    for r in range(g2.n):
+        row = g2.col[g2.off[r]:g2.off[r + 1]]
+        assert np.all(np.diff(row) > 0)
+    # coarse edges equal brute sums between clusters
+    W, E = B.dense(g)
+    for a in range(g2.n):
+        for e in range(g2.off[a], g2.off[a + 1]):
+            b = g2.col[e]
+            want = sum(W[i, j] for i in range(n) for j in range(n)
+                       if E[i, j] and mp[i] == a and mp[j] == b)
+            assert g2.wt[e] == want
+    assert g2.k.sum() == g.k.sum()
+    kk_want = [sum(int(g.k[i]) ** 2 for i in range(n) if mp[i] == a) for a in range(g2.n)]
+    assert list(g2.kk) == kk_want
+    tot = lambda h: (0 if h.s is None else int(h.s.sum())) + \
+        (len(h.col) if h.wt is None else int(h.wt.sum())) // 2
+    assert tot(g) == tot(g2)
+    # objective invariance
+    for Cp in [np.arange(g2.n), rng.integers(0, max(1, g2.n), size=g2.n)]:
+        Cp = np.asarray(Cp, dtype=np.int32)
+        assert O.objective(g, p, q, Cp[mp]) == O.objective(g2, p, q, Cp)
+    assert O.objective(g, p, q, C) == O.objective(g2, p, q, np.arange(g2.n, dtype=np.int32))
+
+
+def test_P5_two_level_compress_invariant():
+    """Contraction twice: objective of the composed clustering is preserved."""
+    h = G.sbm([30, 30, 30], 0.3, 0.03, 5)
+    g = og(h)
+    rng = np.random.default_rng(5)
+    C1 = rng.integers(0, 40, g.n).astype(np.int32)
+    g2, m1 = O.compress(g, C1)
+    C2 = rng.integers(0, 10, g2.n).astype(np.int32)
+    g3, m2 = O.compress(g2, C2)
+    C3 = rng.integers(0, 3, g3.n).astype(np.int32)
+    p, q = 1, 20
+    assert O.objective(g, p, q, C3[m2[m1]]) == O.objective(g3, p, q, C3)
+
+
+# ----------------------------------------------------------------- lambda = 0
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_P6_lambda_zero_gives_unions_of_components(seed):
+    """lambda = 0, w >= 0: when the top level stopped without moves, every
+    positive-weight edge lies inside a cluster, so the objective is the total
+    weight and every cluster is a union of connected components of the
+    positive-weight subgraph (union-find)."""
+    g = small(40, 50, 900 + seed, wmin=0, wmax=3, kmax=3)
+    lab, N, st = O.cluster(g, 0, 3, O.Params(seed=seed))
+    assert st["top_moved"] == 0
+    W, E = B.dense(g)
+    pos = [(i, j) for i in range(g.n) for j in range(i + 1, g.n) if E[i, j] and W[i, j] > 0]
+    total = sum(W[i, j] for i in range(g.n) for j in range(i + 1, g.n) if E[i, j])
+    assert N == 3 * total
+    rep = B.components(g.n, pos)
+    for i, j in pos:
+        assert lab[i] == lab[j]
+    # a component never spans two clusters
+    comp_label = {}
+    for v in range(g.n):
+        assert comp_label.setdefault(rep[v], lab[v]) == lab[v]
+
+
+# ------------------------------------------------------- worked examples
+
+
+def _graph_from_edges(n, edges, k=None):
+    off = np.zeros(n + 1, np.int64)
+    adj = [[] for _ in range(n)]
+    for a, b, w in edges:
+        adj[a].append((b, w))
+        adj[b].append((a, w))
+    col, wt = [], []
+    for v in range(n):
+        adj[v].sort()
+        off[v + 1] = off[v] + len(adj[v])
+        col += [u for u, _ in adj[v]]
+        wt += [w for _, w in adj[v]]
+    return O.Graph(off=off, col=np.array(col, np.int32), wt=np.array(wt, np.int64),
+                   k=np.ones(n, np.int64) if k is None else np.asarray(k, np.int64))
+
+
+def _fixture(name):
+    vals = {}
+    for line in open(os.path.join(GOLDEN, name)):
+        line = line.split("#")[0].strip()
+        if line:
+            key, val = line.split("=", 1)
+            vals[key.strip()] = val.strip()
+    return vals
+
+
+def test_P7_figure1_simultaneous_moves_lower_objective():
+    """Fig. 1: lambda = 0, singletons (objective 0); b and c, scheduled
+    together, both join {a} and the objective becomes -1.  Weights
+    reconstructed in tests/golden/fig1_triangle.txt."""
+    fx = _fixture("fig1_triangle.txt")
+    wab, wac, wbc = int(fx["w_ab"]), int(fx["w_ac"]), int(fx["w_bc"])
+    g = _graph_from_edges(3, [(0, 1, wab), (0, 2, wac), (1, 2, wbc)])
+    C0 = np.arange(3, dtype=np.int32)
+    assert O.objective(g, 0, 1, C0) == 0
+    C, D, moved = O.subround(g, 0, 1, C0, [1, 2])
+    assert list(D) == [0, 0] and moved == 2
+    assert list(C) == [0, 0, 0]
+    assert O.objective(g, 0, 1, C) == int(fx["objective_after"])
+    # one at a time: b joins a, then c stays out (objective 1)
+    C, _, _ = O.subround(g, 0, 1, C0, [1])
+    C, D, _ = O.subround(g, 0, 1, C, [2])
+    assert list(C) == [0, 0, 2] and O.objective(g, 0, 1, C) == 1
+
+
+def test_P8_star_frontier_footnote():
+    """Sec. 3.2.2 footnote: a star whose leaves have small positive weight to
+    the center.  After the leaves all join the center, the neighbors-of-moved
+    frontier holds only the center, which stays, so the leaves are stranded in
+    a cluster they would leave; considering all vertices lets them isolate.
+    Isolated leaves take the ascending empty ids."""
+    L = 10
+    g = _graph_from_edges(L + 1, [(0, i, 1) for i in range(1, L + 1)])
+    p, q = 1, 2  # lambda = 1/2: joining the center gains 1/2; staying in the big cluster loses
+    C0 = np.arange(L + 1, dtype=np.int32)
+    leaves = np.arange(1, L + 1, dtype=np.int32)
+    C1, D, moved = O.subround(g, p, q, C0, leaves)
+    assert moved == L and np.all(C1 == 0)
+    fr = O.frontier_nbr(g, leaves)
+    assert list(np.nonzero(fr)[0]) == [0]
+    C2, D, moved = O.subround(g, p, q, C1, [0])
+    assert moved == 0 and np.array_equal(C2, C1)
+    stranded = O.objective(g, p, q, C2)
+    # L unit edges inside, L(L+1)/2 pairs charged lambda each
+    assert Fraction(stranded, q) == L - Fraction(p, q) * (L + 1) * L / 2
+    W, E = B.dense(g)
+    assert stranded == B.objective_q(W, E, g.k, p, q, list(C2))
+    # all vertices: every leaf isolates, taking empty ids 1..L in order
+    C3, D, moved = O.subround(g, p, q, C1, np.arange(L + 1, dtype=np.int32))
+    assert list(D[1:]) == [O.ISO] * L and D[0] == 0
+    assert list(C3) == list(range(L + 1))
+    assert O.objective(g, p, q, C3) > stranded
+
+
+def test_isolation_takes_smallest_empty_ids():
+    """Isolated vertices take the smallest empty ids, in ascending vertex
+    order: four edgeless vertices in cluster 3, lambda = 1; vertices 1 and 2
+    leave (each pays lambda for 3 pairs) and get ids 0 and 1."""
+    g = O.Graph(off=np.zeros(5, np.int64), col=np.zeros(0, np.int32), k=np.ones(4, np.int64))
+    C0 = np.full(4, 3, dtype=np.int32)
+    C, D, moved = O.subround(g, 1, 1, C0, [2, 1])
+    assert list(D) == [O.ISO, O.ISO] and moved == 2
+    assert list(C) == [3, 0, 1, 3]
+    assert O.objective(g, 1, 1, C) == -1
+
+
+def test_P9_symmetric_pair_swaps_or_merges():
+    """Sec. 3.2.1 (symmetry in the synchronous setting): two singletons joined
+    by a positive edge swap cluster ids when scheduled together and merge when
+    scheduled apart."""
+    g = _graph_from_edges(2, [(0, 1, 1)])
+    C0 = np.arange(2, dtype=np.int32)
+    C, D, moved = O.subround(g, 0, 1, C0, [0, 1])
+    assert list(C) == [1, 0] and moved == 2
+    C, _, _ = O.subround(g, 0, 1, C0, [0])
+    C, _, moved = O.subround(g, 0, 1, C, [1])
+    assert list(C) == [1, 1] and moved == 0
+    # Best-Moves with S = 1 keeps swapping until num_iter
+    C, st = O.best_move(g, 0, 1, O.Params(S=1, num_iter=5))
+    assert st["term"] == O.TERM_NUM_ITER and st["moves"] == 10 and list(C) == [1, 0]
+
+
+# -------------------------------------------------------- schedule details
+
+
+def test_subround_schedule_matches_hash_colors():
+    """Best-Moves with a sub-round budget equals explicit sub-rounds over the
+    hash-colored active sets (first iteration: all vertices active)."""
+    g = og(G.sbm([25, 25], 0.3, 0.05, 3))
+    p, q, S, seed = 1, 10, 3, 11
+    h = O.round_hash(seed, 0, 0, 0)
+    C = np.arange(g.n, dtype=np.int32)
+    for s in range(S):
+        U = np.array([v for v in range(g.n) if O.color(h, v, S) == s], np.int32)
+        C, _, _ = O.subround(g, p, q, C, U)
+        Cb, st = O.best_move(g, p, q, O.Params(S=S, seed=seed, stop_after_subrounds=s + 1))
+        assert np.array_equal(C, Cb) and st["subrounds"] == s + 1
+
+
+def test_second_iteration_uses_neighbors_of_movers():
+    g = og(G.sbm([25, 25], 0.3, 0.05, 4))
+    p, q, S, seed = 1, 10, 2, 5
+    C = np.arange(g.n, dtype=np.int32)
+    movers = []
+    h = O.round_hash(seed, 0, 0, 0)
+    for s in range(S):
+        U = np.array([v for v in range(g.n) if O.color(h, v, S) == s], np.int32)
+        Cn, D, _ = O.subround(g, p, q, C, U)
+        movers += [int(u) for u, d in zip(U, D) if d != C[u]]
+        C = Cn
+    active = O.frontier_nbr(g, movers)
+    h1 = O.round_hash(seed, 0, 0, 1)
+    U = np.array([v for v in range(g.n) if active[v] and O.color(h1, v, S) == 0], np.int32)
+    C, _, _ = O.subround(g, p, q, C, U)
+    Cb, _ = O.best_move(g, p, q, O.Params(S=S, seed=seed, stop_after_subrounds=S + 1))
+    assert np.array_equal(C, Cb)
+
+
+def test_row_order_invariance_and_determinism():
+    """Shuffling the arcs inside each row changes nothing."""
+    h = G.random_signed(60, 200, 8, wmin=-2, wmax=4, kmax=3)
+    g = og(h)
+    rng = np.random.default_rng(1)
+    col, wt = g.col.copy(), g.wt.copy()
+    for v in range(g.n):
+        a, b = g.off[v], g.off[v + 1]
+        perm = rng.permutation(b - a) + a
+        col[a:b], wt[a:b] = col[perm], wt[perm]
+    g2 = O.Graph(off=g.off, col=col, wt=wt, k=g.k)
+    r1 = O.cluster(g, 1, 7, O.Params())
+    r2 = O.cluster(g2, 1, 7, O.Params())
+    r3 = O.cluster(g, 1, 7, O.Params())
+    assert np.array_equal(r1[0], r2[0]) and r1[1] == r2[1]
+    assert np.array_equal(r1[0], r3[0]) and r1[1] == r3[1]
+
+
+def test_canonical_labels_order_by_min_member():
+    C = np.array([5, 5, 2, 4, 2, 0], np.int32)
+    assert list(O.canonical_labels(C)) == [0, 0, 1, 2, 1, 3]
+
+
+# ------------------------------------------------------------- error paths
+
+
+def test_precheck_rejects_bad_inputs_and_overflow():
+    g = small(5, 8, 1)
+    assert O.precheck(g, 1, 2) == O.OK
+    assert O.precheck(g, -1, 2) == O.INVALID
+    assert O.precheck(g, 1, 0) == O.INVALID
+    bad = O.Graph(off=g.off, col=g.col.copy(), wt=g.wt, k=g.k)
+    if bad.arcs:
+        bad.col[0] = 99
+        assert O.precheck(bad, 1, 2) == O.INVALID
+    big = O.Graph(off=g.off, col=g.col, wt=g.wt, k=np.full(g.n, 2**40, np.int64))
+    assert O.precheck(big, 1, 1) == O.OVERFLOW
+    assert O.precheck(big, 0, 1) == O.OK or O.precheck(big, 0, 1) == O.OVERFLOW
+    hw = O.Graph(off=g.off, col=g.col, wt=np.full(g.arcs, 2**40, np.int64), k=g.k)
+    if g.arcs:
+        assert O.precheck(hw, 1, 2**30) == O.OVERFLOW
+    with pytest.raises(O.OracleError):
+        O.cluster(big, 1, 1, O.Params())
+
+
+def test_empty_and_edgeless_graphs():
+    e = O.Graph(off=np.zeros(1, np.int64), col=np.zeros(0, np.int32), k=np.zeros(0, np.int64))
+    lab, N, st = O.cluster(e, 1, 2, O.Params())
+    assert len(lab) == 0 and N == 0
+    iso = O.Graph(off=np.zeros(6, np.int64), col=np.zeros(0, np.int32), k=np.ones(5, np.int64))
+    lab, N, st = O.cluster(iso, 1, 2, O.Params())
+    assert list(lab) == [0, 1, 2, 3, 4] and N == 0 and st["levels"] == 1
