@@ -1,0 +1,607 @@
+// api.hip -- the exported C ABI of liblcc (declared in include/lcc.h):
+// argument checks, the read-only device validation pass, the exact int64
+// overflow bounds, and the Parallel-CC driver (paper Algorithm 1, bottom,
+// with the multi-level refinement of Sec. 3.2.3).
+#include <chrono>
+#include <memory>
+
+#include "ops.hpp"
+#include "prims.hpp"
+
+struct lcc_ctx {
+  lcc::Ctx c;
+};
+
+struct lcc_graph_owned {
+  lcc::OwnedGraph g;
+};
+
+namespace lcc {
+
+static thread_local std::string g_last_error;
+
+template <class F> static lcc_status guarded(F &&f) {
+  try {
+    f();
+    g_last_error.clear();
+    return LCC_OK;
+  } catch (const Error &e) {
+    g_last_error = e.what();
+    return e.code;
+  } catch (const std::bad_alloc &) {
+    g_last_error = "host allocation failed";
+    return LCC_ERR_OUT_OF_MEMORY;
+  } catch (const std::exception &e) {
+    g_last_error = e.what();
+    return LCC_ERR_DEVICE;
+  } catch (...) {
+    g_last_error = "unknown error";
+    return LCC_ERR_DEVICE;
+  }
+}
+
+// ------------------------------------------------------------- host checks
+
+// The pointer must lie in device memory of the context's device with at
+// least `bytes` bytes left in its allocation.
+static void check_dev(const Ctx &c, const void *p, size_t bytes, const char *what) {
+  if (bytes == 0) return;
+  if (!p) fail(LCC_ERR_INVALID_ARG, std::string(what) + " is NULL");
+  hipPointerAttribute_t attr;
+  if (hipPointerGetAttributes(&attr, p) != hipSuccess) {
+    (void)hipGetLastError();
+    fail(LCC_ERR_INVALID_ARG, std::string(what) + " is not a device pointer");
+  }
+  if (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged)
+    fail(LCC_ERR_INVALID_ARG, std::string(what) + " is not device memory");
+  if (attr.device != c.device) fail(LCC_ERR_INVALID_ARG, std::string(what) + " lives on another device");
+  hipDeviceptr_t base = nullptr;
+  size_t size = 0;
+  if (hipMemGetAddressRange(&base, &size, (hipDeviceptr_t)p) != hipSuccess) {
+    (void)hipGetLastError();
+    fail(LCC_ERR_INVALID_ARG, std::string(what) + ": allocation range unknown");
+  }
+  const char *b = static_cast<const char *>(base);
+  const char *q = static_cast<const char *>(p);
+  if (q < b || (size_t)(q - b) + bytes > size)
+    fail(LCC_ERR_INVALID_ARG, std::string(what) + " is smaller than the graph requires");
+}
+
+static void check_graph_args(const Ctx &c, const lcc_graph *g) {
+  if (!g) fail(LCC_ERR_INVALID_ARG, "graph is NULL");
+  if (g->n < 0 || g->n >= (int64_t)INT32_MAX) fail(LCC_ERR_INVALID_ARG, "n must be in [0, 2^31 - 1)");
+  if (g->arcs < 0) fail(LCC_ERR_INVALID_ARG, "arcs must be >= 0");
+  if (g->wt_kind < LCC_WT_UNIT || g->wt_kind > LCC_WT_I64) fail(LCC_ERR_INVALID_ARG, "unknown wt_kind");
+  if (g->wt_kind == LCC_WT_UNIT && g->wt != nullptr) fail(LCC_ERR_INVALID_ARG, "wt must be NULL for LCC_WT_UNIT");
+  if (g->wt_kind != LCC_WT_UNIT && g->wt == nullptr && g->arcs > 0)
+    fail(LCC_ERR_INVALID_ARG, "wt is NULL but wt_kind is not LCC_WT_UNIT");
+  if (g->n == 0 && g->arcs != 0) fail(LCC_ERR_INVALID_ARG, "an empty graph has no arcs");
+  const size_t n = (size_t)g->n, m = (size_t)g->arcs;
+  if (g->n > 0) check_dev(c, g->off, (n + 1) * sizeof(int64_t), "off");
+  check_dev(c, g->col, m * sizeof(int32_t), "col");
+  if (g->wt) check_dev(c, g->wt, m * (size_t)wt_bytes(g->wt_kind), "wt");
+  check_dev(c, g->k, n * sizeof(int64_t), "k");
+  if (g->s) check_dev(c, g->s, n * sizeof(int64_t), "s");
+  if (g->kk) check_dev(c, g->kk, n * sizeof(int64_t), "kk");
+}
+
+static void check_lambda(lcc_lambda lam) {
+  if (lam.p < 0) fail(LCC_ERR_INVALID_ARG, "lambda numerator p must be >= 0");
+  if (lam.q < 1) fail(LCC_ERR_INVALID_ARG, "lambda denominator q must be >= 1");
+}
+
+static void check_params(const lcc_params *prm) {
+  if (!prm) fail(LCC_ERR_INVALID_ARG, "params is NULL");
+  if (prm->S < 1 || prm->S > 64) fail(LCC_ERR_INVALID_ARG, "S must be in [1, 64]");
+  if (prm->num_iter < 0) fail(LCC_ERR_INVALID_ARG, "num_iter must be >= 0");
+  if (prm->frontier != LCC_FRONTIER_ALL && prm->frontier != LCC_FRONTIER_NBR)
+    fail(LCC_ERR_INVALID_ARG, "unknown frontier rule");
+  if (prm->allow_isolate != 0 && prm->allow_isolate != 1) fail(LCC_ERR_INVALID_ARG, "allow_isolate must be 0 or 1");
+  if (prm->refine != 0 && prm->refine != 1) fail(LCC_ERR_INVALID_ARG, "refine must be 0 or 1");
+  if (prm->stop_after_subrounds < 0) fail(LCC_ERR_INVALID_ARG, "stop_after_subrounds must be >= 0");
+}
+
+// --------------------------------------------------------- device validation
+
+__device__ __forceinline__ uint64_t sat_add(uint64_t a, uint64_t b) {
+  uint64_t s = a + b;
+  return s < a ? ~0ull : s;
+}
+
+__device__ __forceinline__ uint64_t wave_sat_sum(uint64_t x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x = sat_add(x, __shfl_xor(x, o, WAVE));
+  return x;
+}
+__device__ __forceinline__ uint64_t wave_or(uint64_t x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x |= __shfl_xor(x, o, WAVE);
+  return x;
+}
+__device__ __forceinline__ uint64_t wave_max(uint64_t x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    uint64_t y = __shfl_xor(x, o, WAVE);
+    x = y > x ? y : x;
+  }
+  return x;
+}
+
+enum : uint64_t {
+  E_OFF = 1, E_COL = 2, E_SELF = 4, E_K = 8, E_KK = 16, E_C = 32, E_ENDS = 64
+};
+
+constexpr int VA_NT = 256;
+constexpr int NPART = 8;  // err, ktot, kksum, sabs, neg, maxdeg, wabs2, (spare)
+
+// Per-vertex checks and sums.  part[b*NPART + i].
+__global__ __launch_bounds__(VA_NT) void k_validate_vertices(const int64_t *__restrict__ off, int64_t n, int64_t arcs,
+                                                             const int64_t *__restrict__ k,
+                                                             const int64_t *__restrict__ kk,
+                                                             const int64_t *__restrict__ s,
+                                                             const int32_t *__restrict__ C,
+                                                             uint64_t *__restrict__ part) {
+  __shared__ uint64_t red[NPART][VA_NT / WAVE];
+  uint64_t err = 0, ktot = 0, kks = 0, sabs = 0, neg = 0, maxdeg = 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0 && (off[0] != 0 || off[n] != arcs)) err |= E_ENDS;
+  for (int64_t v = (int64_t)blockIdx.x * VA_NT + threadIdx.x; v < n; v += (int64_t)gridDim.x * VA_NT) {
+    const int64_t a = off[v], b = off[v + 1];
+    if (b < a || a < 0 || b > arcs) err |= E_OFF;
+    else maxdeg = (uint64_t)(b - a) > maxdeg ? (uint64_t)(b - a) : maxdeg;
+    const int64_t kv = k[v];
+    if (kv < 0) err |= E_K;
+    else {
+      ktot = sat_add(ktot, (uint64_t)kv);
+      if (!kk) kks = sat_add(kks, (uint64_t)kv > 0xFFFFFFFFull ? ~0ull : (uint64_t)kv * (uint64_t)kv);
+    }
+    if (kk) {
+      if (kk[v] < 0) err |= E_KK;
+      else kks = sat_add(kks, (uint64_t)kk[v]);
+    }
+    if (s) {
+      const int64_t sv = s[v];
+      if (sv < 0) {
+        neg = 1;
+        sabs = sat_add(sabs, sv == INT64_MIN ? (1ull << 63) : (uint64_t)(-sv));
+      } else {
+        sabs = sat_add(sabs, (uint64_t)sv);
+      }
+    }
+    if (C && (C[v] < 0 || (int64_t)C[v] >= n)) err |= E_C;
+  }
+  uint64_t vals[NPART] = {wave_or(err), wave_sat_sum(ktot), wave_sat_sum(kks), wave_sat_sum(sabs), wave_or(neg),
+                          wave_max(maxdeg), 0, 0};
+  const int w = threadIdx.x / WAVE;
+  if (lane_id() == 0)
+    for (int i = 0; i < NPART; i++) red[i][w] = vals[i];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t r[NPART] = {0};
+    for (int j = 0; j < VA_NT / WAVE; j++) {
+      r[0] |= red[0][j];
+      r[1] = sat_add(r[1], red[1][j]);
+      r[2] = sat_add(r[2], red[2][j]);
+      r[3] = sat_add(r[3], red[3][j]);
+      r[4] |= red[4][j];
+      r[5] = red[5][j] > r[5] ? red[5][j] : r[5];
+    }
+    for (int i = 0; i < NPART; i++) part[(int64_t)blockIdx.x * NPART + i] = r[i];
+  }
+}
+
+// Per-arc checks (one wave per vertex): column range, self-loops, sum |w|.
+template <int WK>
+__global__ __launch_bounds__(VA_NT) void k_validate_arcs(const int64_t *__restrict__ off,
+                                                         const int32_t *__restrict__ col, const void *__restrict__ wt,
+                                                         int64_t n, int check, uint64_t *__restrict__ part) {
+  __shared__ uint64_t red[3][VA_NT / WAVE];
+  uint64_t err = 0, wabs = 0, neg = 0;
+  const int lane = lane_id();
+  const int64_t wave = ((int64_t)blockIdx.x * VA_NT + threadIdx.x) / WAVE;
+  const int64_t nwaves = ((int64_t)gridDim.x * VA_NT) / WAVE;
+  for (int64_t v = wave; v < n; v += nwaves) {
+    const int64_t b = off[v + 1];
+    for (int64_t e = off[v] + lane; e < b; e += WAVE) {
+      if (check) {
+        const int32_t u = col[e];
+        if (u < 0 || (int64_t)u >= n) err |= E_COL;
+        if ((int64_t)u == v) err |= E_SELF;
+      }
+      const int64_t w = load_w<WK>(wt, e);
+      if (w < 0) {
+        neg = 1;
+        wabs = sat_add(wabs, w == INT64_MIN ? (1ull << 63) : (uint64_t)(-w));
+      } else {
+        wabs = sat_add(wabs, (uint64_t)w);
+      }
+    }
+  }
+  err = wave_or(err);
+  wabs = wave_sat_sum(wabs);
+  neg = wave_or(neg);
+  const int w = threadIdx.x / WAVE;
+  if (lane == 0) {
+    red[0][w] = err;
+    red[1][w] = wabs;
+    red[2][w] = neg;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t r0 = 0, r1 = 0, r2 = 0;
+    for (int j = 0; j < VA_NT / WAVE; j++) {
+      r0 |= red[0][j];
+      r1 = sat_add(r1, red[1][j]);
+      r2 |= red[2][j];
+    }
+    part[(int64_t)blockIdx.x * 3 + 0] = r0;
+    part[(int64_t)blockIdx.x * 3 + 1] = r1;
+    part[(int64_t)blockIdx.x * 3 + 2] = r2;
+  }
+}
+
+static uint64_t host_sat_add(uint64_t a, uint64_t b) {
+  uint64_t s = a + b;
+  return s < a ? ~0ull : s;
+}
+
+static std::string err_text(uint64_t e) {
+  std::string s;
+  if (e & E_ENDS) s += "off[0] must be 0 and off[n] must equal arcs; ";
+  if (e & E_OFF) s += "offsets must be non-decreasing and within [0, arcs]; ";
+  if (e & E_COL) s += "a column id is outside [0, n); ";
+  if (e & E_SELF) s += "the adjacency holds a self-loop; ";
+  if (e & E_K) s += "a vertex weight k is negative; ";
+  if (e & E_KK) s += "a kk entry is negative; ";
+  if (e & E_C) s += "a cluster id is outside [0, n); ";
+  return s;
+}
+
+GraphSummary summarize_graph(Ctx &c, const lcc_graph &g, const int32_t *C, bool check_structure) {
+  GraphSummary s;
+  const int64_t n = g.n;
+  if (n == 0) return s;
+  Ctx::Timer tm(&c, "validate", (double)n * 40.0 + (double)g.arcs * (4.0 + wt_bytes(g.wt_kind)), (double)g.arcs);
+  const int64_t nb = std::min<int64_t>(cdiv(n, VA_NT), (int64_t)c.num_cu * 4);
+  uint64_t *part = c.buf<uint64_t>("va.part", (size_t)(nb * NPART));
+  hipLaunchKernelGGL(k_validate_vertices, dim3((unsigned)nb), dim3(VA_NT), 0, c.stream, g.off, n, g.arcs, g.k, g.kk,
+                     g.s, C, part);
+  LAUNCHCHECK();
+  std::vector<uint64_t> h((size_t)(nb * NPART));
+  d2h(c, h.data(), part, h.size() * sizeof(uint64_t));
+  uint64_t err = 0;
+  for (int64_t b = 0; b < nb; b++) {
+    const uint64_t *r = &h[(size_t)(b * NPART)];
+    err |= r[0];
+    s.ktot = host_sat_add(s.ktot, r[1]);
+    s.kksum = host_sat_add(s.kksum, r[2]);
+    s.sabs = host_sat_add(s.sabs, r[3]);
+    s.negative = s.negative || r[4];
+    s.maxdeg = std::max<int64_t>(s.maxdeg, (int64_t)r[5]);
+  }
+  if (err) {
+    // offsets or ids are unusable: stop before touching arcs
+    s.ok = false;
+    s.why = err_text(err);
+    return s;
+  }
+  if (g.arcs > 0 && (check_structure || g.wt_kind != LCC_WT_UNIT)) {
+    uint64_t *pa = c.buf<uint64_t>("va.parta", (size_t)(nb * 3));
+    switch (g.wt_kind) {
+      case LCC_WT_UNIT:
+        hipLaunchKernelGGL((k_validate_arcs<LCC_WT_UNIT>), dim3((unsigned)nb), dim3(VA_NT), 0, c.stream, g.off, g.col,
+                           g.wt, n, (int)check_structure, pa);
+        break;
+      case LCC_WT_I16:
+        hipLaunchKernelGGL((k_validate_arcs<LCC_WT_I16>), dim3((unsigned)nb), dim3(VA_NT), 0, c.stream, g.off, g.col,
+                           g.wt, n, (int)check_structure, pa);
+        break;
+      case LCC_WT_I32:
+        hipLaunchKernelGGL((k_validate_arcs<LCC_WT_I32>), dim3((unsigned)nb), dim3(VA_NT), 0, c.stream, g.off, g.col,
+                           g.wt, n, (int)check_structure, pa);
+        break;
+      default:
+        hipLaunchKernelGGL((k_validate_arcs<LCC_WT_I64>), dim3((unsigned)nb), dim3(VA_NT), 0, c.stream, g.off, g.col,
+                           g.wt, n, (int)check_structure, pa);
+    }
+    LAUNCHCHECK();
+    std::vector<uint64_t> ha((size_t)(nb * 3));
+    d2h(c, ha.data(), pa, ha.size() * sizeof(uint64_t));
+    uint64_t e2 = 0;
+    for (int64_t b = 0; b < nb; b++) {
+      e2 |= ha[(size_t)(b * 3)];
+      s.wabs2 = host_sat_add(s.wabs2, ha[(size_t)(b * 3 + 1)]);
+      s.negative = s.negative || ha[(size_t)(b * 3 + 2)];
+    }
+    if (e2) {
+      s.ok = false;
+      s.why = err_text(e2);
+    }
+  } else {
+    s.wabs2 = (uint64_t)g.arcs;  // unit weights
+  }
+  return s;
+}
+
+lcc_status overflow_bounds(const GraphSummary &s, int64_t p, int64_t q, std::string *why) {
+  const u128 LIM = (u128)INT64_MAX;
+  const u128 SAT = (u128)~0ull;
+  auto bad = [&](const char *m) {
+    if (why) *why = m;
+    return LCC_ERR_OVERFLOW;
+  };
+  if ((u128)s.wabs2 == SAT || (u128)s.sabs == SAT || (u128)s.ktot == SAT || (u128)s.kksum == SAT)
+    return bad("a weight sum exceeds 2^64");
+  const u128 wabs = (u128)(s.wabs2 / 2) + (u128)s.sabs;
+  const u128 kt = s.ktot;
+  if (kt > LIM) return bad("sum of k exceeds 2^63-1");
+  if (wabs > LIM) return bad("sum of |w| exceeds 2^63-1");
+  if ((u128)s.kksum > LIM) return bad("sum of kk exceeds 2^63-1");
+  const u128 kq = (kt * kt) / 4;
+  if ((u128)q * wabs > LIM) return bad("q * sum|w| exceeds 2^63-1");
+  if ((u128)p * kt > LIM) return bad("p * sum k exceeds 2^63-1");
+  if ((u128)p * kq > LIM) return bad("p * (sum k)^2 / 4 exceeds 2^63-1");
+  if (s.negative && (u128)q * wabs + (u128)p * kq > LIM)
+    return bad("with negative weights, q * sum|w| + p * (sum k)^2 / 4 exceeds 2^63-1");
+  return LCC_OK;
+}
+
+static GraphSummary checked_summary(Ctx &c, const lcc_graph &g, const int32_t *C, bool structure, int64_t p,
+                                    int64_t q) {
+  GraphSummary s = summarize_graph(c, g, C, structure);
+  if (!s.ok) fail(LCC_ERR_INVALID_ARG, s.why);
+  std::string why;
+  if (overflow_bounds(s, p, q, &why) != LCC_OK) fail(LCC_ERR_OVERFLOW, why);
+  return s;
+}
+
+static bool wide_weights(const GraphSummary &s) {
+  const u128 wabs = (u128)(s.wabs2 / 2) + (u128)s.sabs;
+  return wabs >= ((u128)1 << 31);
+}
+
+static void begin(Ctx &c, void *stream, const lcc_params *prm) {
+  HIPCHECK(hipSetDevice(c.device));
+  c.stream = (hipStream_t)stream;
+  c.timing = prm ? prm->timing != 0 : false;
+}
+
+static void fill_objective(i128 N, int64_t q, lcc_objective_out *o) {
+  o->num_hi = (int64_t)(N >> 64);
+  o->num_lo = (uint64_t)N;
+  o->den = q;
+  o->value = (double)N / (double)q;
+}
+
+}  // namespace lcc
+
+using namespace lcc;
+
+extern "C" {
+
+void lcc_params_default(lcc_params *prm) {
+  if (!prm) return;
+  std::memset(prm, 0, sizeof(*prm));
+  prm->S = 4;
+  prm->num_iter = 10;
+  prm->seed = 1;
+  prm->frontier = LCC_FRONTIER_NBR;
+  prm->refine = 1;
+  prm->allow_isolate = 1;
+  prm->max_levels = 64;
+  prm->stop_after_subrounds = 0;
+  prm->validate = 1;
+  prm->timing = 0;
+}
+
+const char *lcc_last_error(void) { return g_last_error.c_str(); }
+
+lcc_status lcc_ctx_create(int32_t device, lcc_ctx **out) {
+  return guarded([&] {
+    if (!out) fail(LCC_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    int count = 0;
+    HIPCHECK(hipGetDeviceCount(&count));
+    if (device < 0 || device >= count) fail(LCC_ERR_INVALID_ARG, "no such device");
+    HIPCHECK(hipSetDevice(device));
+    hipDeviceProp_t prop;
+    HIPCHECK(hipGetDeviceProperties(&prop, device));
+    std::unique_ptr<lcc_ctx> ctx(new lcc_ctx());
+    ctx->c.device = device;
+    ctx->c.num_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    *out = ctx.release();
+  });
+}
+
+lcc_status lcc_ctx_destroy(lcc_ctx *ctx) {
+  return guarded([&] {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->c.device);
+    (void)hipDeviceSynchronize();
+    delete ctx;
+  });
+}
+
+lcc_status lcc_best_move(lcc_ctx *ctx, const lcc_graph *g, lcc_lambda lam, const lcc_params *prm, int32_t level,
+                         int32_t phase, int32_t *C_inout, lcc_bm_stats *stats, void *stream) {
+  return guarded([&] {
+    if (!ctx) fail(LCC_ERR_INVALID_ARG, "ctx is NULL");
+    Ctx &c = ctx->c;
+    check_params(prm);
+    check_lambda(lam);
+    if (level < 0) fail(LCC_ERR_INVALID_ARG, "level must be >= 0");
+    if (phase != 0 && phase != 1) fail(LCC_ERR_INVALID_ARG, "phase must be 0 or 1");
+    begin(c, stream, prm);
+    check_graph_args(c, g);
+    check_dev(c, C_inout, (size_t)g->n * sizeof(int32_t), "C_inout");
+    GraphSummary s = checked_summary(c, *g, C_inout, prm->validate != 0, lam.p, lam.q);
+    lcc_bm_stats st;
+    best_moves(c, *g, lam.p, lam.q, *prm, level, phase, C_inout, false, s.maxdeg, st);
+    c.sync();
+    if (c.timing) c.collect_timing();
+    if (stats) *stats = st;
+  });
+}
+
+lcc_status lcc_compress(lcc_ctx *ctx, const lcc_graph *g, const int32_t *C, lcc_graph_owned **out, int32_t *map_out,
+                        void *stream) {
+  return guarded([&] {
+    if (!ctx) fail(LCC_ERR_INVALID_ARG, "ctx is NULL");
+    if (!out) fail(LCC_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    Ctx &c = ctx->c;
+    begin(c, stream, nullptr);
+    check_graph_args(c, g);
+    check_dev(c, C, (size_t)g->n * sizeof(int32_t), "C");
+    check_dev(c, map_out, (size_t)g->n * sizeof(int32_t), "map_out");
+    GraphSummary s = checked_summary(c, *g, C, true, 0, 1);
+    std::unique_ptr<lcc_graph_owned> h(new lcc_graph_owned());
+    int64_t md = 0;
+    compress_graph(c, *g, C, h->g, map_out, wide_weights(s), &md);
+    c.sync();
+    *out = h.release();
+  });
+}
+
+lcc_status lcc_graph_owned_view(const lcc_graph_owned *h, lcc_graph *view) {
+  return guarded([&] {
+    if (!h || !view) fail(LCC_ERR_INVALID_ARG, "NULL argument");
+    *view = h->g.view();
+  });
+}
+
+lcc_status lcc_graph_owned_free(lcc_ctx *ctx, lcc_graph_owned *h) {
+  return guarded([&] {
+    if (ctx) (void)hipSetDevice(ctx->c.device);
+    delete h;
+  });
+}
+
+lcc_status lcc_objective(lcc_ctx *ctx, const lcc_graph *g, lcc_lambda lam, const int32_t *C, lcc_objective_out *out,
+                         void *stream) {
+  return guarded([&] {
+    if (!ctx) fail(LCC_ERR_INVALID_ARG, "ctx is NULL");
+    if (!out) fail(LCC_ERR_INVALID_ARG, "out is NULL");
+    Ctx &c = ctx->c;
+    check_lambda(lam);
+    begin(c, stream, nullptr);
+    check_graph_args(c, g);
+    check_dev(c, C, (size_t)g->n * sizeof(int32_t), "C");
+    (void)checked_summary(c, *g, C, true, lam.p, lam.q);
+    i128 N = objective_num(c, *g, lam.p, lam.q, C);
+    c.sync();
+    fill_objective(N, lam.q, out);
+  });
+}
+
+lcc_status lcc_cluster(lcc_ctx *ctx, const lcc_graph *g, lcc_lambda lam, const lcc_params *prm, int32_t *labels_out,
+                       lcc_objective_out *obj, lcc_cluster_stats *stats, void *stream) {
+  return guarded([&] {
+    if (!ctx) fail(LCC_ERR_INVALID_ARG, "ctx is NULL");
+    Ctx &c = ctx->c;
+    check_params(prm);
+    check_lambda(lam);
+    if (prm->max_levels < 1 || prm->max_levels > LCC_MAX_LEVELS)
+      fail(LCC_ERR_INVALID_ARG, "max_levels must be in [1, 64]");
+    begin(c, stream, prm);
+    check_graph_args(c, g);
+    check_dev(c, labels_out, (size_t)g->n * sizeof(int32_t), "labels_out");
+    using clk = std::chrono::steady_clock;
+    auto t0 = clk::now();
+    lcc_cluster_stats cs;
+    std::memset(&cs, 0, sizeof(cs));
+    GraphSummary s = checked_summary(c, *g, nullptr, prm->validate != 0, lam.p, lam.q);
+    const bool wide = wide_weights(s);
+    std::vector<std::unique_ptr<OwnedGraph>> owned;
+    std::vector<lcc_graph> G;
+    std::vector<DevBuf> Cl, maps;
+    std::vector<int64_t> maxdeg;
+    G.push_back(*g);
+    maxdeg.push_back(s.maxdeg);
+    int top = 0;
+    double ms_bm = 0, ms_cp = 0;
+    for (int l = 0;; l++) {
+      const int64_t n = G[l].n;
+      cs.n_level[l] = n;
+      cs.arcs_level[l] = G[l].arcs;
+      cs.levels = l + 1;
+      Cl.emplace_back();
+      Cl.back().ensure((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+      int32_t *C = Cl.back().as<int32_t>();
+      iota_i32(c, C, n);
+      lcc_bm_stats st;
+      auto a = clk::now();
+      best_moves(c, G[l], lam.p, lam.q, *prm, l, 0, C, true, maxdeg[l], st);
+      ms_bm += std::chrono::duration<double, std::milli>(clk::now() - a).count();
+      cs.iters_coarsen[l] = st.iterations;
+      cs.moves_total += st.moves;
+      cs.arcs_scanned_total += st.arcs_scanned;
+      if (!st.moved_any || l + 1 == prm->max_levels) {
+        top = l;
+        cs.top_moved = st.moved_any;
+        break;
+      }
+      maps.emplace_back();
+      maps.back().ensure((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+      owned.emplace_back(new OwnedGraph());
+      int64_t md = 0;
+      a = clk::now();
+      compress_graph(c, G[l], C, *owned.back(), maps.back().as<int32_t>(), wide, &md);
+      ms_cp += std::chrono::duration<double, std::milli>(clk::now() - a).count();
+      G.push_back(owned.back()->view());
+      maxdeg.push_back(md);
+    }
+    for (int l = top - 1; l >= 0; l--) {
+      int32_t *C = Cl[l].as<int32_t>();
+      flatten(c, G[l].n, maps[l].as<int32_t>(), Cl[l + 1].as<int32_t>(), C);
+      if (prm->refine) {
+        lcc_bm_stats st;
+        auto a = clk::now();
+        best_moves(c, G[l], lam.p, lam.q, *prm, l, 1, C, false, maxdeg[l], st);
+        ms_bm += std::chrono::duration<double, std::milli>(clk::now() - a).count();
+        cs.iters_refine[l] = st.iterations;
+        cs.moves_total += st.moves;
+        cs.arcs_scanned_total += st.arcs_scanned;
+      }
+    }
+    cs.clusters = canonical_labels(c, g->n, Cl[0].as<int32_t>(), labels_out);
+    if (obj) {
+      i128 N = objective_num(c, *g, lam.p, lam.q, labels_out);
+      fill_objective(N, lam.q, obj);
+    }
+    c.sync();
+    if (c.timing) c.collect_timing();
+    cs.ms_best_move = ms_bm;
+    cs.ms_compress = ms_cp;
+    cs.ms_total = std::chrono::duration<double, std::milli>(clk::now() - t0).count();
+    if (stats) *stats = cs;
+  });
+}
+
+lcc_status lcc_ctx_kernel_stats(lcc_ctx *ctx, lcc_kernel_stat *out, int32_t max, int32_t *count) {
+  return guarded([&] {
+    if (!ctx || !count || (max > 0 && !out)) fail(LCC_ERR_INVALID_ARG, "NULL argument");
+    int32_t i = 0;
+    for (auto &kv : ctx->c.kstats) {
+      if (i < max) {
+        lcc_kernel_stat &o = out[i];
+        std::memset(&o, 0, sizeof(o));
+        std::strncpy(o.name, kv.first.c_str(), sizeof(o.name) - 1);
+        o.launches = kv.second.launches;
+        o.total_ms = kv.second.ms;
+        o.bytes = kv.second.bytes;
+        o.items = kv.second.items;
+      }
+      i++;
+    }
+    *count = i;
+  });
+}
+
+lcc_status lcc_ctx_reset_kernel_stats(lcc_ctx *ctx) {
+  return guarded([&] {
+    if (!ctx) fail(LCC_ERR_INVALID_ARG, "ctx is NULL");
+    ctx->c.kstats.clear();
+  });
+}
+
+}  // extern "C"

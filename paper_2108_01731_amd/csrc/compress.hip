@@ -1,0 +1,521 @@
+// compress.hip -- graph compression (paper Sec. 3.1 / Appendix B), flatten,
+// canonical labels and per-cluster totals on gfx950.
+//
+// Compress: clusters are renumbered by the rank of their id among non-empty
+// ids (a prefix sum over presence flags); every inter-cluster arc becomes a
+// 64-bit key (map[u] << b | map[v]) carrying its weight; a stable LSD radix
+// sort over the 2b significant bits groups equal endpoint pairs; heads of
+// equal-key runs give the unique coarse arcs, and run sums come from an
+// inclusive prefix sum (differences at run boundaries, exact in int64) or,
+// for unit weights, from run lengths.  Row offsets are lower bounds of each
+// coarse vertex in the sorted row ids.  Per-cluster sums of k, kk and the
+// self weight come from a radix sort of the vertices by cluster followed by
+// prefix-sum differences: no atomics, so huge clusters cost nothing extra.
+#include "ops.hpp"
+#include "prims.hpp"
+
+namespace lcc {
+
+constexpr int CP_NT = 256;
+
+__global__ void k_iota(int32_t *__restrict__ a, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    a[i] = (int32_t)i;
+}
+
+__global__ void k_copy_u32(const int32_t *__restrict__ a, uint32_t *__restrict__ b, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    b[i] = (uint32_t)a[i];
+}
+
+inline unsigned grid_for(int64_t n, int nt = 256) {
+  int64_t g = cdiv(n > 0 ? n : 1, nt);
+  return (unsigned)(g < 65536 ? g : 65536);
+}
+
+void iota_i32(Ctx &c, int32_t *C, int64_t n) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_iota, dim3(grid_for(n)), dim3(256), 0, c.stream, C, n);
+  LAUNCHCHECK();
+}
+
+// ------------------------------------------------------ sort vertices by key
+
+struct ByKey {
+  const uint32_t *key;  // sorted keys
+  const int32_t *perm;  // vertex at each sorted position (ascending inside a key)
+};
+
+// Stable sort of the vertices 0..n-1 by key[v] in [0, nkeys).
+static ByKey sort_by_key(Ctx &c, const int32_t *key, int64_t n, int64_t nkeys, const char *tag) {
+  std::string t(tag);
+  uint32_t *k0 = c.buf<uint32_t>(t + ".k0", (size_t)n);
+  uint32_t *k1 = c.buf<uint32_t>(t + ".k1", (size_t)n);
+  int32_t *p0 = c.buf<int32_t>(t + ".p0", (size_t)n);
+  int32_t *p1 = c.buf<int32_t>(t + ".p1", (size_t)n);
+  hipLaunchKernelGGL(k_copy_u32, dim3(grid_for(n)), dim3(256), 0, c.stream, key, k0, n);
+  LAUNCHCHECK();
+  hipLaunchKernelGGL(k_iota, dim3(grid_for(n)), dim3(256), 0, c.stream, p0, n);
+  LAUNCHCHECK();
+  bool flip = radix_sort<uint32_t, int32_t, true>(c, k0, p0, k1, p1, n, bits_for(nkeys - 1), (t + ".rs").c_str());
+  return flip ? ByKey{k1, p1} : ByKey{k0, p0};
+}
+
+// start[key] = first sorted position of the key (only keys that occur).
+__global__ void k_seg_heads(const uint32_t *__restrict__ sk, int64_t n, int64_t *__restrict__ start) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    if (i == 0 || sk[i] != sk[i - 1]) start[sk[i]] = i;
+}
+
+enum GatherKind { G_K = 0, G_KK = 1, G_SELF2 = 2 };
+
+// val[i] for the vertex at sorted position i: k, kk (or k^2), or 2*s + intra.
+__global__ void k_seg_gather(const int32_t *__restrict__ perm, int64_t n, int kind, const int64_t *__restrict__ k,
+                             const int64_t *__restrict__ kk, const int64_t *__restrict__ s,
+                             const int64_t *__restrict__ intra, int64_t *__restrict__ out) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t v = perm[i];
+    int64_t x;
+    if (kind == G_K) x = k[v];
+    else if (kind == G_KK) x = kk ? kk[v] : k[v] * k[v];
+    else x = 2 * (s ? s[v] : 0) + (intra ? intra[v] : 0);
+    out[i] = x;
+  }
+}
+
+// At the last position of each key's run: out[key] = run sum (from the
+// inclusive prefix P), cnt[key] = run length (if cnt), halve if requested.
+__global__ void k_seg_tails(const uint32_t *__restrict__ sk, int64_t n, const int64_t *__restrict__ start,
+                            const int64_t *__restrict__ P, int64_t *__restrict__ out, int32_t *__restrict__ cnt,
+                            int halve) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    if (i == n - 1 || sk[i] != sk[i + 1]) {
+      const uint32_t x = sk[i];
+      const int64_t st = start[x];
+      if (out) {
+        int64_t sum = P[i] - (st > 0 ? P[st - 1] : 0);
+        out[x] = halve ? sum / 2 : sum;
+      }
+      if (cnt) cnt[x] = (int32_t)(i - st + 1);
+    }
+  }
+}
+
+// Sums of one per-vertex quantity per key (keys that do not occur get 0).
+static void seg_sum(Ctx &c, const ByKey &bk, int64_t n, int64_t nkeys, const int64_t *start, int kind,
+                    const lcc_graph &g, const int64_t *intra, int64_t *out, int32_t *cnt, bool halve) {
+  int64_t *vals = c.buf<int64_t>("seg.vals", (size_t)n);
+  if (out) HIPCHECK(hipMemsetAsync(out, 0, (size_t)nkeys * sizeof(int64_t), c.stream));
+  if (cnt) HIPCHECK(hipMemsetAsync(cnt, 0, (size_t)nkeys * sizeof(int32_t), c.stream));
+  if (out) {
+    hipLaunchKernelGGL(k_seg_gather, dim3(grid_for(n)), dim3(256), 0, c.stream, bk.perm, n, kind, g.k, g.kk, g.s,
+                       intra, vals);
+    LAUNCHCHECK();
+    scan<int64_t, int64_t>(c, vals, vals, n, true, (int64_t *)nullptr);
+  }
+  hipLaunchKernelGGL(k_seg_tails, dim3(grid_for(n)), dim3(256), 0, c.stream, bk.key, n, start, vals, out, cnt,
+                     (int)halve);
+  LAUNCHCHECK();
+}
+
+void cluster_totals(Ctx &c, int64_t n, const int32_t *C, const int64_t *k, int64_t *K, int32_t *cnt) {
+  if (n <= 0) return;
+  ByKey bk = sort_by_key(c, C, n, n, "ct");
+  int64_t *start = c.buf<int64_t>("ct.start", (size_t)n);
+  hipLaunchKernelGGL(k_seg_heads, dim3(grid_for(n)), dim3(256), 0, c.stream, bk.key, n, start);
+  LAUNCHCHECK();
+  lcc_graph g;
+  std::memset(&g, 0, sizeof(g));
+  g.k = k;
+  seg_sum(c, bk, n, n, start, G_K, g, nullptr, K, cnt, false);
+}
+
+// Per-cluster sums of k and kk (kk = k^2 when absent) for ids in [0, n).
+void cluster_sums_k_kk(Ctx &c, const lcc_graph &g, const int32_t *C, int64_t *K, int64_t *KK) {
+  const int64_t n = g.n;
+  if (n <= 0) return;
+  ByKey bk = sort_by_key(c, C, n, n, "ct");
+  int64_t *start = c.buf<int64_t>("ct.start", (size_t)n);
+  hipLaunchKernelGGL(k_seg_heads, dim3(grid_for(n)), dim3(256), 0, c.stream, bk.key, n, start);
+  LAUNCHCHECK();
+  seg_sum(c, bk, n, n, start, G_K, g, nullptr, K, nullptr, false);
+  seg_sum(c, bk, n, n, start, G_KK, g, nullptr, KK, nullptr, false);
+}
+
+// ------------------------------------------------------------------ flatten
+
+__global__ void k_flatten(const int32_t *__restrict__ map, const int32_t *__restrict__ Cn, int32_t *__restrict__ C,
+                          int64_t n) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+    C[v] = Cn[map[v]];
+}
+
+void flatten(Ctx &c, int64_t n, const int32_t *map, const int32_t *Cnext, int32_t *C) {
+  if (n <= 0) return;
+  Ctx::Timer tm(&c, "flatten", 12.0 * (double)n, (double)n);
+  hipLaunchKernelGGL(k_flatten, dim3(grid_for(n)), dim3(256), 0, c.stream, map, Cnext, C, n);
+  LAUNCHCHECK();
+}
+
+// ---------------------------------------------------------- canonical labels
+
+__global__ void k_first_members(const uint32_t *__restrict__ sk, const int32_t *__restrict__ perm, int64_t n,
+                                uint8_t *__restrict__ first) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    if (i == 0 || sk[i] != sk[i - 1]) first[perm[i]] = 1;
+}
+
+__global__ void k_cluster_label(const uint32_t *__restrict__ sk, const int32_t *__restrict__ perm, int64_t n,
+                                const int32_t *__restrict__ rank, int32_t *__restrict__ lab) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    if (i == 0 || sk[i] != sk[i - 1]) lab[sk[i]] = rank[perm[i]];
+}
+
+__global__ void k_apply_label(const int32_t *__restrict__ C, const int32_t *__restrict__ lab, int32_t *__restrict__ out,
+                              int64_t n) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+    out[v] = lab[C[v]];
+}
+
+int64_t canonical_labels(Ctx &c, int64_t n, const int32_t *C, int32_t *labels) {
+  if (n <= 0) return 0;
+  Ctx::Timer tm(&c, "labels", 0.0, (double)n);
+  ByKey bk = sort_by_key(c, C, n, n, "lab");
+  uint8_t *first = c.buf<uint8_t>("lab.first", (size_t)n);
+  int32_t *rank = c.buf<int32_t>("lab.rank", (size_t)n);
+  int32_t *lab = c.buf<int32_t>("lab.lab", (size_t)n);
+  int64_t *tot = c.buf<int64_t>("lab.tot", 1);
+  HIPCHECK(hipMemsetAsync(first, 0, (size_t)n, c.stream));
+  hipLaunchKernelGGL(k_first_members, dim3(grid_for(n)), dim3(256), 0, c.stream, bk.key, bk.perm, n, first);
+  LAUNCHCHECK();
+  int32_t *tot32 = reinterpret_cast<int32_t *>(tot);
+  scan<uint8_t, int32_t>(c, first, rank, n, false, tot32);
+  hipLaunchKernelGGL(k_cluster_label, dim3(grid_for(n)), dim3(256), 0, c.stream, bk.key, bk.perm, n, rank, lab);
+  LAUNCHCHECK();
+  hipLaunchKernelGGL(k_apply_label, dim3(grid_for(n)), dim3(256), 0, c.stream, C, lab, labels, n);
+  LAUNCHCHECK();
+  int32_t h = 0;
+  d2h(c, &h, tot32, sizeof(int32_t));
+  return h;
+}
+
+// ------------------------------------------------------------------ compress
+
+__global__ void k_mark_present(const int32_t *__restrict__ C, int64_t n, uint8_t *__restrict__ present) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+    present[C[v]] = 1;
+}
+
+__global__ void k_map(const int32_t *__restrict__ C, const int32_t *__restrict__ rank, int64_t n,
+                      int32_t *__restrict__ map) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+    map[v] = rank[C[v]];
+}
+
+// G lanes per vertex: number of inter-cluster arcs and weight of intra arcs.
+template <int G, int WK>
+__global__ __launch_bounds__(CP_NT) void k_cp_count(const int64_t *__restrict__ off, const int32_t *__restrict__ col,
+                                                    const void *__restrict__ wt, const int32_t *__restrict__ map,
+                                                    int64_t n, int64_t *__restrict__ inter,
+                                                    int64_t *__restrict__ intra) {
+  const int gl = threadIdx.x % G;
+  const int64_t v = (int64_t)blockIdx.x * (CP_NT / G) + threadIdx.x / G;
+  int64_t ni = 0, wi = 0;
+  if (v < n) {
+    const int32_t mv = map[v];
+    for (int64_t e = off[v] + gl; e < off[v + 1]; e += G) {
+      if (map[col[e]] != mv) ni++;
+      else wi += load_w<WK>(wt, e);
+    }
+  }
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) {
+    ni += __shfl_xor(ni, o, WAVE);
+    wi += __shfl_xor(wi, o, WAVE);
+  }
+  if (v < n && gl == 0) {
+    inter[v] = ni;
+    intra[v] = wi;
+  }
+}
+
+// G lanes per vertex: writes the vertex's inter-cluster arcs, in row order,
+// as (map[v] << b | map[u], w) starting at eoff[v].
+template <int G, int WK, bool WEIGHTED>
+__global__ __launch_bounds__(CP_NT) void k_cp_emit(const int64_t *__restrict__ off, const int32_t *__restrict__ col,
+                                                   const void *__restrict__ wt, const int32_t *__restrict__ map,
+                                                   int64_t n, const int64_t *__restrict__ eoff, int b,
+                                                   uint64_t *__restrict__ keys, int64_t *__restrict__ vals) {
+  const int gl = threadIdx.x % G;
+  const int lane = lane_id();
+  const int g0 = lane - gl;
+  const int64_t v = (int64_t)blockIdx.x * (CP_NT / G) + threadIdx.x / G;
+  const uint64_t gmask = G >= 64 ? ~0ull : ((1ull << (G & 63)) - 1);
+  int64_t beg = 0, end = 0, pos = 0;
+  int32_t mv = 0;
+  if (v < n) {
+    beg = off[v];
+    end = off[v + 1];
+    pos = eoff[v];
+    mv = map[v];
+  }
+  // every lane of the wave runs the same number of rounds (ballots need it)
+  int64_t rounds = cdiv(end - beg, G);
+  int64_t maxr = rounds;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    int64_t y = __shfl_xor(maxr, o, WAVE);
+    maxr = y > maxr ? y : maxr;
+  }
+  for (int64_t r = 0; r < maxr; r++) {
+    const int64_t e = beg + r * G + gl;
+    bool is_inter = false;
+    int32_t mu = 0;
+    if (e < end) {
+      mu = map[col[e]];
+      is_inter = mu != mv;
+    }
+    const uint64_t bal = (__ballot(is_inter) >> g0) & gmask;
+    if (is_inter) {
+      const int64_t at = pos + __popcll(bal & ((1ull << gl) - 1));
+      keys[at] = ((uint64_t)(uint32_t)mv << b) | (uint64_t)(uint32_t)mu;
+      if constexpr (WEIGHTED) vals[at] = load_w<WK>(wt, e);
+    }
+    pos += __popcll(bal);
+  }
+}
+
+__global__ void k_cp_heads(const uint64_t *__restrict__ keys, int64_t T, uint8_t *__restrict__ head) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < T; i += (int64_t)gridDim.x * blockDim.x)
+    head[i] = (i == 0 || keys[i] != keys[i - 1]) ? 1 : 0;
+}
+
+__global__ void k_cp_ustart(const uint8_t *__restrict__ head, const int64_t *__restrict__ uidx, int64_t T,
+                            int64_t *__restrict__ ustart) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < T; i += (int64_t)gridDim.x * blockDim.x)
+    if (head[i]) ustart[uidx[i]] = i;
+}
+
+template <class WOut>
+__global__ void k_cp_unique(const uint64_t *__restrict__ keys, const int64_t *__restrict__ ustart, int64_t U,
+                            int64_t T, const int64_t *__restrict__ P, int b, int32_t *__restrict__ ocol,
+                            int32_t *__restrict__ orow, WOut *__restrict__ owt) {
+  const uint64_t mask = (b >= 64) ? ~0ull : ((1ull << b) - 1);
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < U; j += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t s = ustart[j];
+    const int64_t e = j + 1 < U ? ustart[j + 1] : T;
+    const uint64_t key = keys[s];
+    ocol[j] = (int32_t)(key & mask);
+    orow[j] = (int32_t)(key >> b);
+    const int64_t sum = P ? (P[e - 1] - (s > 0 ? P[s - 1] : 0)) : (e - s);
+    owt[j] = (WOut)sum;
+  }
+}
+
+// off[r] = first j with row[j] >= r, for r in [0, n2].
+__global__ void k_cp_offsets(const int32_t *__restrict__ row, int64_t U, int64_t n2, int64_t *__restrict__ off) {
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r <= n2; r += (int64_t)gridDim.x * blockDim.x) {
+    int64_t lo = 0, hi = U;
+    while (lo < hi) {
+      int64_t mid = (lo + hi) >> 1;
+      if (row[mid] < r) lo = mid + 1;
+      else hi = mid;
+    }
+    off[r] = lo;
+  }
+}
+
+__global__ void k_max_deg(const int64_t *__restrict__ off, int64_t n, unsigned long long *__restrict__ out) {
+  unsigned long long m = 0;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+    unsigned long long d = (unsigned long long)(off[v + 1] - off[v]);
+    m = d > m ? d : m;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    unsigned long long y = __shfl_xor(m, o, WAVE);
+    m = y > m ? y : m;
+  }
+  if (lane_id() == 0 && m) atomicMax(out, m);
+}
+
+int64_t max_degree(Ctx &c, const int64_t *off, int64_t n) {
+  if (n <= 0) return 0;
+  unsigned long long *d = c.buf<unsigned long long>("maxdeg", 1);
+  HIPCHECK(hipMemsetAsync(d, 0, sizeof(unsigned long long), c.stream));
+  hipLaunchKernelGGL(k_max_deg, dim3(grid_for(n)), dim3(256), 0, c.stream, off, n, d);
+  LAUNCHCHECK();
+  unsigned long long h = 0;
+  d2h(c, &h, d, sizeof(h));
+  return (int64_t)h;
+}
+
+namespace {
+
+int lanes_for(const lcc_graph &g) {
+  const double avg = g.n > 0 ? (double)g.arcs / (double)g.n : 0.0;
+  if (avg <= 8) return 8;
+  if (avg <= 16) return 16;
+  if (avg <= 32) return 32;
+  return 64;
+}
+
+template <int G, int WK>
+void launch_count(Ctx &c, const lcc_graph &g, const int32_t *map, int64_t *inter, int64_t *intra) {
+  hipLaunchKernelGGL((k_cp_count<G, WK>), dim3((unsigned)cdiv(g.n, CP_NT / G)), dim3(CP_NT), 0, c.stream, g.off,
+                     g.col, g.wt, map, g.n, inter, intra);
+  LAUNCHCHECK();
+}
+
+template <int G, int WK>
+void launch_emit(Ctx &c, const lcc_graph &g, const int32_t *map, const int64_t *eoff, int b, uint64_t *keys,
+                 int64_t *vals) {
+  if (WK == LCC_WT_UNIT)
+    hipLaunchKernelGGL((k_cp_emit<G, WK, false>), dim3((unsigned)cdiv(g.n, CP_NT / G)), dim3(CP_NT), 0, c.stream,
+                       g.off, g.col, g.wt, map, g.n, eoff, b, keys, vals);
+  else
+    hipLaunchKernelGGL((k_cp_emit<G, WK, true>), dim3((unsigned)cdiv(g.n, CP_NT / G)), dim3(CP_NT), 0, c.stream,
+                       g.off, g.col, g.wt, map, g.n, eoff, b, keys, vals);
+  LAUNCHCHECK();
+}
+
+template <int WK>
+void count_and_emit(Ctx &c, const lcc_graph &g, const int32_t *map, int64_t *inter, int64_t *intra,
+                    const int64_t *eoff, int b, uint64_t *keys, int64_t *vals, bool emit) {
+  switch (lanes_for(g)) {
+    case 8: emit ? launch_emit<8, WK>(c, g, map, eoff, b, keys, vals) : launch_count<8, WK>(c, g, map, inter, intra); break;
+    case 16: emit ? launch_emit<16, WK>(c, g, map, eoff, b, keys, vals) : launch_count<16, WK>(c, g, map, inter, intra); break;
+    case 32: emit ? launch_emit<32, WK>(c, g, map, eoff, b, keys, vals) : launch_count<32, WK>(c, g, map, inter, intra); break;
+    default: emit ? launch_emit<64, WK>(c, g, map, eoff, b, keys, vals) : launch_count<64, WK>(c, g, map, inter, intra); break;
+  }
+}
+
+void dispatch_ce(Ctx &c, const lcc_graph &g, const int32_t *map, int64_t *inter, int64_t *intra, const int64_t *eoff,
+                 int b, uint64_t *keys, int64_t *vals, bool emit) {
+  switch (g.wt_kind) {
+    case LCC_WT_UNIT: count_and_emit<LCC_WT_UNIT>(c, g, map, inter, intra, eoff, b, keys, vals, emit); break;
+    case LCC_WT_I16: count_and_emit<LCC_WT_I16>(c, g, map, inter, intra, eoff, b, keys, vals, emit); break;
+    case LCC_WT_I32: count_and_emit<LCC_WT_I32>(c, g, map, inter, intra, eoff, b, keys, vals, emit); break;
+    default: count_and_emit<LCC_WT_I64>(c, g, map, inter, intra, eoff, b, keys, vals, emit); break;
+  }
+}
+
+}  // namespace
+
+void compress_graph(Ctx &c, const lcc_graph &g, const int32_t *C, OwnedGraph &out, int32_t *map, bool wide,
+                    int64_t *maxdeg_out) {
+  const int64_t n = g.n;
+  out.n = 0;
+  out.arcs = 0;
+  out.wt_kind = wide ? LCC_WT_I64 : LCC_WT_I32;
+  if (n <= 0) {
+    out.off.ensure(sizeof(int64_t));
+    HIPCHECK(hipMemsetAsync(out.off.p, 0, sizeof(int64_t), c.stream));
+    if (maxdeg_out) *maxdeg_out = 0;
+    return;
+  }
+  const size_t nn = (size_t)n;
+  uint8_t *present = c.buf<uint8_t>("cp.present", nn);
+  int32_t *rank = c.buf<int32_t>("cp.rank", nn);
+  int64_t *inter = c.buf<int64_t>("cp.inter", nn + 1);
+  int64_t *intra = c.buf<int64_t>("cp.intra", nn);
+  int64_t *tots = c.buf<int64_t>("cp.tots", 4);
+  HIPCHECK(hipMemsetAsync(tots, 0, 4 * sizeof(int64_t), c.stream));
+  {
+    Ctx::Timer tm(&c, "cp_relabel", 13.0 * (double)n, (double)n);
+    HIPCHECK(hipMemsetAsync(present, 0, nn, c.stream));
+    hipLaunchKernelGGL(k_mark_present, dim3(grid_for(n)), dim3(256), 0, c.stream, C, n, present);
+    LAUNCHCHECK();
+    scan<uint8_t, int32_t>(c, present, rank, n, false, reinterpret_cast<int32_t *>(tots));
+    hipLaunchKernelGGL(k_map, dim3(grid_for(n)), dim3(256), 0, c.stream, C, rank, n, map);
+    LAUNCHCHECK();
+  }
+  const int wb = wt_bytes(g.wt_kind);
+  {
+    Ctx::Timer tm(&c, "cp_count", 28.0 * (double)n + (8.0 + wb) * (double)g.arcs, (double)g.arcs);
+    dispatch_ce(c, g, map, inter, intra, nullptr, 0, nullptr, nullptr, false);
+  }
+  scan<int64_t, int64_t>(c, inter, inter, n, false, tots + 1);
+  int64_t h[2] = {0, 0};
+  d2h(c, h, tots, 2 * sizeof(int64_t));
+  const int64_t n2 = (int64_t)(int32_t)(h[0] & 0xffffffff);
+  const int64_t T = h[1];
+  out.n = n2;
+  const int b = bits_for(n2 > 1 ? n2 - 1 : 1);
+  const bool weighted = g.wt_kind != LCC_WT_UNIT;
+  uint64_t *k0 = c.buf<uint64_t>("cp.k0", (size_t)(T > 0 ? T : 1));
+  uint64_t *k1 = c.buf<uint64_t>("cp.k1", (size_t)(T > 0 ? T : 1));
+  int64_t *v0 = weighted ? c.buf<int64_t>("cp.v0", (size_t)(T > 0 ? T : 1)) : nullptr;
+  int64_t *v1 = weighted ? c.buf<int64_t>("cp.v1", (size_t)(T > 0 ? T : 1)) : nullptr;
+  if (T > 0) {
+    Ctx::Timer tm(&c, "cp_emit", 28.0 * (double)n + (8.0 + wb) * (double)g.arcs + (8.0 + (weighted ? 8 : 0)) * (double)T,
+                  (double)g.arcs);
+    dispatch_ce(c, g, map, inter, intra, inter, b, k0, v0, true);
+  }
+  uint64_t *ks = k0;
+  int64_t *vs = v0;
+  if (T > 1) {
+    Ctx::Timer tm(&c, "cp_sort", 2.0 * (8.0 + (weighted ? 8 : 0)) * (double)T * (double)cdiv(2 * b, RS_BITS),
+                  (double)T);
+    bool flip = weighted ? radix_sort<uint64_t, int64_t, true>(c, k0, v0, k1, v1, T, 2 * b, "cp.rs")
+                         : radix_sort<uint64_t, int64_t, false>(c, k0, nullptr, k1, nullptr, T, 2 * b, "cp.rs");
+    if (flip) {
+      ks = k1;
+      vs = v1;
+    }
+  }
+  // unique coarse arcs
+  int64_t U = 0;
+  uint8_t *head = c.buf<uint8_t>("cp.head", (size_t)(T > 0 ? T : 1));
+  int64_t *uidx = c.buf<int64_t>("cp.uidx", (size_t)(T > 0 ? T : 1));
+  if (T > 0) {
+    Ctx::Timer tm(&c, "cp_reduce", (double)T * (8.0 + 1.0 + 8.0), (double)T);
+    hipLaunchKernelGGL(k_cp_heads, dim3(grid_for(T)), dim3(256), 0, c.stream, ks, T, head);
+    LAUNCHCHECK();
+    scan<uint8_t, int64_t>(c, head, uidx, T, false, tots + 2);
+    d2h(c, &U, tots + 2, sizeof(int64_t));
+  }
+  out.arcs = U;
+  out.off.ensure((size_t)(n2 + 1) * sizeof(int64_t));
+  out.col.ensure((size_t)(U > 0 ? U : 1) * sizeof(int32_t));
+  out.wt.ensure((size_t)(U > 0 ? U : 1) * (wide ? 8 : 4));
+  out.k.ensure((size_t)(n2 > 0 ? n2 : 1) * sizeof(int64_t));
+  out.s.ensure((size_t)(n2 > 0 ? n2 : 1) * sizeof(int64_t));
+  out.kk.ensure((size_t)(n2 > 0 ? n2 : 1) * sizeof(int64_t));
+  int32_t *orow = c.buf<int32_t>("cp.row", (size_t)(U > 0 ? U : 1));
+  if (U > 0) {
+    Ctx::Timer tm(&c, "cp_unique", (double)U * (8.0 + 8.0 + 4.0 + 4.0 + (wide ? 8 : 4)), (double)U);
+    int64_t *ustart = c.buf<int64_t>("cp.ustart", (size_t)U);
+    hipLaunchKernelGGL(k_cp_ustart, dim3(grid_for(T)), dim3(256), 0, c.stream, head, uidx, T, ustart);
+    LAUNCHCHECK();
+    int64_t *P = nullptr;
+    if (weighted) {
+      scan<int64_t, int64_t>(c, vs, vs, T, true, (int64_t *)nullptr);
+      P = vs;
+    }
+    if (wide)
+      hipLaunchKernelGGL((k_cp_unique<int64_t>), dim3(grid_for(U)), dim3(256), 0, c.stream, ks, ustart, U, T, P, b,
+                         out.col.as<int32_t>(), orow, out.wt.as<int64_t>());
+    else
+      hipLaunchKernelGGL((k_cp_unique<int32_t>), dim3(grid_for(U)), dim3(256), 0, c.stream, ks, ustart, U, T, P, b,
+                         out.col.as<int32_t>(), orow, out.wt.as<int32_t>());
+    LAUNCHCHECK();
+  }
+  hipLaunchKernelGGL(k_cp_offsets, dim3(grid_for(n2 + 1)), dim3(256), 0, c.stream, orow, U, n2,
+                     out.off.as<int64_t>());
+  LAUNCHCHECK();
+  // per-cluster k', kk', s'
+  {
+    Ctx::Timer tm(&c, "cp_totals", 0.0, (double)n);
+    ByKey bk = sort_by_key(c, map, n, n2, "cpv");
+    int64_t *start = c.buf<int64_t>("cpv.start", (size_t)(n2 > 0 ? n2 : 1));
+    hipLaunchKernelGGL(k_seg_heads, dim3(grid_for(n)), dim3(256), 0, c.stream, bk.key, n, start);
+    LAUNCHCHECK();
+    seg_sum(c, bk, n, n2, start, G_K, g, nullptr, out.k.as<int64_t>(), nullptr, false);
+    seg_sum(c, bk, n, n2, start, G_KK, g, nullptr, out.kk.as<int64_t>(), nullptr, false);
+    seg_sum(c, bk, n, n2, start, G_SELF2, g, intra, out.s.as<int64_t>(), nullptr, true);
+  }
+  if (maxdeg_out) *maxdeg_out = max_degree(c, out.off.as<int64_t>(), n2);
+}
+
+}  // namespace lcc

@@ -1,0 +1,106 @@
+// objective.hip -- exact objective of a clustering (paper Sec. 2), summed over
+// unordered pairs:  N = q*(sum s + W_in) - p * sum_X (K_X^2 - KK_X) / 2.
+// K_X and KK_X come from a stable sort of the vertices by cluster and prefix-
+// sum differences; the per-cluster squares and the intra-cluster arc weights
+// are accumulated in 128-bit integers (block partials, summed on the host).
+#include "ops.hpp"
+#include "prims.hpp"
+
+namespace lcc {
+
+constexpr int OB_NT = 256;
+
+// Block partial of sum over clusters x < n of (K[x]^2 - KK[x]).
+__global__ __launch_bounds__(OB_NT) void k_obj_pairs(const int64_t *__restrict__ K, const int64_t *__restrict__ KK,
+                                                     int64_t n, u128 *__restrict__ part) {
+  __shared__ i128 red[OB_NT];
+  i128 s = 0;
+  for (int64_t x = (int64_t)blockIdx.x * OB_NT + threadIdx.x; x < n; x += (int64_t)gridDim.x * OB_NT) {
+    const i128 kx = K[x];
+    s += kx * kx - (i128)KK[x];
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    i128 t = 0;
+    for (int i = 0; i < OB_NT; i++) t += red[i];
+    part[blockIdx.x] = (u128)t;
+  }
+}
+
+// Block partial of sum over arcs inside clusters of w, plus sum of s.
+template <int WK>
+__global__ __launch_bounds__(OB_NT) void k_obj_intra(const int64_t *__restrict__ off, const int32_t *__restrict__ col,
+                                                     const void *__restrict__ wt, const int64_t *__restrict__ s,
+                                                     const int32_t *__restrict__ C, int64_t n,
+                                                     u128 *__restrict__ part_w, u128 *__restrict__ part_s) {
+  __shared__ i128 rw[OB_NT];
+  __shared__ i128 rs[OB_NT];
+  i128 aw = 0, as = 0;
+  // one wave per vertex, lanes stride the row
+  const int lane = lane_id();
+  const int64_t wave = ((int64_t)blockIdx.x * OB_NT + threadIdx.x) / WAVE;
+  const int64_t nwaves = ((int64_t)gridDim.x * OB_NT) / WAVE;
+  for (int64_t v = wave; v < n; v += nwaves) {
+    const int32_t cv = C[v];
+    int64_t acc = 0;
+    for (int64_t e = off[v] + lane; e < off[v + 1]; e += WAVE)
+      if (C[col[e]] == cv) acc += load_w<WK>(wt, e);
+    aw += acc;
+    if (lane == 0 && s) as += s[v];
+  }
+  rw[threadIdx.x] = aw;
+  rs[threadIdx.x] = as;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    i128 t = 0, u = 0;
+    for (int i = 0; i < OB_NT; i++) {
+      t += rw[i];
+      u += rs[i];
+    }
+    part_w[blockIdx.x] = (u128)t;
+    part_s[blockIdx.x] = (u128)u;
+  }
+}
+
+i128 objective_num(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const int32_t *C) {
+  const int64_t n = g.n;
+  if (n <= 0) return 0;
+  Ctx::Timer tm(&c, "objective", (double)n * 36.0 + (double)g.arcs * (8.0 + wt_bytes(g.wt_kind)), (double)g.arcs);
+  int64_t *K = c.buf<int64_t>("ob.K", (size_t)n);
+  int64_t *KK = c.buf<int64_t>("ob.KK", (size_t)n);
+  cluster_sums_k_kk(c, g, C, K, KK);
+  const int64_t nb = std::min<int64_t>(cdiv(n, OB_NT), (int64_t)c.num_cu * 4);
+  u128 *part = c.buf<u128>("ob.part", (size_t)(3 * nb));
+  hipLaunchKernelGGL(k_obj_pairs, dim3((unsigned)nb), dim3(OB_NT), 0, c.stream, K, KK, n, part);
+  LAUNCHCHECK();
+  switch (g.wt_kind) {
+    case LCC_WT_UNIT:
+      hipLaunchKernelGGL((k_obj_intra<LCC_WT_UNIT>), dim3((unsigned)nb), dim3(OB_NT), 0, c.stream, g.off, g.col, g.wt,
+                         g.s, C, n, part + nb, part + 2 * nb);
+      break;
+    case LCC_WT_I16:
+      hipLaunchKernelGGL((k_obj_intra<LCC_WT_I16>), dim3((unsigned)nb), dim3(OB_NT), 0, c.stream, g.off, g.col, g.wt,
+                         g.s, C, n, part + nb, part + 2 * nb);
+      break;
+    case LCC_WT_I32:
+      hipLaunchKernelGGL((k_obj_intra<LCC_WT_I32>), dim3((unsigned)nb), dim3(OB_NT), 0, c.stream, g.off, g.col, g.wt,
+                         g.s, C, n, part + nb, part + 2 * nb);
+      break;
+    default:
+      hipLaunchKernelGGL((k_obj_intra<LCC_WT_I64>), dim3((unsigned)nb), dim3(OB_NT), 0, c.stream, g.off, g.col, g.wt,
+                         g.s, C, n, part + nb, part + 2 * nb);
+  }
+  LAUNCHCHECK();
+  std::vector<u128> h((size_t)(3 * nb));
+  d2h(c, h.data(), part, h.size() * sizeof(u128));
+  i128 pairs2 = 0, win2 = 0, ssum = 0;
+  for (int64_t i = 0; i < nb; i++) {
+    pairs2 += (i128)h[i];
+    win2 += (i128)h[nb + i];
+    ssum += (i128)h[2 * nb + i];
+  }
+  return (i128)q * (ssum + win2 / 2) - (i128)p * (pairs2 / 2);
+}
+
+}  // namespace lcc

@@ -1,0 +1,357 @@
+"""Python binding of liblcc (include/lcc.h): argument marshalling only.
+
+Every computation runs in the HIP library; this module converts torch tensors
+(device memory) and Python numbers into the C structs, calls the exported
+function of the same name and converts the outputs back.  There is no CPU
+fallback: if ``liblcc.so`` is missing or fails to load, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblcc.so")
+
+LCC_OK, LCC_ERR_INVALID_ARG, LCC_ERR_OVERFLOW, LCC_ERR_OUT_OF_MEMORY, LCC_ERR_DEVICE, LCC_ERR_UNSUPPORTED = range(6)
+LCC_WT_UNIT, LCC_WT_I16, LCC_WT_I32, LCC_WT_I64 = range(4)
+LCC_FRONTIER_ALL, LCC_FRONTIER_NBR = 0, 1
+LCC_TERM_NO_MOVES, LCC_TERM_NUM_ITER, LCC_TERM_STOPPED = 0, 1, 2
+MAX_ITER_STATS = 64
+MAX_LEVELS = 64
+
+_WT_KIND = {"none": LCC_WT_UNIT, "i16": LCC_WT_I16, "i32": LCC_WT_I32, "i64": LCC_WT_I64}
+_WT_DTYPE = {LCC_WT_I16: torch.int16, LCC_WT_I32: torch.int32, LCC_WT_I64: torch.int64}
+
+
+class LccError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"liblcc error {code}: {msg}")
+        self.code = code
+
+
+class _Graph(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int64), ("arcs", ctypes.c_int64), ("off", ctypes.c_void_p), ("col", ctypes.c_void_p),
+        ("wt", ctypes.c_void_p), ("wt_kind", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+        ("k", ctypes.c_void_p), ("s", ctypes.c_void_p), ("kk", ctypes.c_void_p),
+    ]
+
+
+class _Lambda(ctypes.Structure):
+    _fields_ = [("p", ctypes.c_int64), ("q", ctypes.c_int64)]
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [
+        ("S", ctypes.c_int32), ("num_iter", ctypes.c_int32), ("seed", ctypes.c_uint64),
+        ("frontier", ctypes.c_int32), ("refine", ctypes.c_int32), ("allow_isolate", ctypes.c_int32),
+        ("max_levels", ctypes.c_int32), ("stop_after_subrounds", ctypes.c_int64),
+        ("validate", ctypes.c_int32), ("timing", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6),
+    ]
+
+
+class _BMStats(ctypes.Structure):
+    _fields_ = [
+        ("iterations", ctypes.c_int32), ("subrounds", ctypes.c_int32), ("moved_any", ctypes.c_int32),
+        ("term", ctypes.c_int32), ("moves", ctypes.c_int64), ("arcs_scanned", ctypes.c_int64),
+        ("vertices_processed", ctypes.c_int64), ("candidates", ctypes.c_int64),
+        ("active_per_iter", ctypes.c_int64 * MAX_ITER_STATS), ("moves_per_iter", ctypes.c_int64 * MAX_ITER_STATS),
+    ]
+
+
+class _Objective(ctypes.Structure):
+    _fields_ = [("num_hi", ctypes.c_int64), ("num_lo", ctypes.c_uint64), ("den", ctypes.c_int64),
+                ("value", ctypes.c_double)]
+
+
+class _ClusterStats(ctypes.Structure):
+    _fields_ = [
+        ("levels", ctypes.c_int32), ("top_moved", ctypes.c_int32),
+        ("n_level", ctypes.c_int64 * MAX_LEVELS), ("arcs_level", ctypes.c_int64 * MAX_LEVELS),
+        ("iters_coarsen", ctypes.c_int32 * MAX_LEVELS), ("iters_refine", ctypes.c_int32 * MAX_LEVELS),
+        ("moves_total", ctypes.c_int64), ("arcs_scanned_total", ctypes.c_int64), ("clusters", ctypes.c_int64),
+        ("ms_best_move", ctypes.c_double), ("ms_compress", ctypes.c_double), ("ms_total", ctypes.c_double),
+    ]
+
+
+class _KernelStat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 64), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double),
+                ("bytes", ctypes.c_double), ("items", ctypes.c_double)]
+
+
+EXPORTS = (
+    "lcc_params_default", "lcc_last_error", "lcc_ctx_create", "lcc_ctx_destroy", "lcc_best_move", "lcc_compress",
+    "lcc_graph_owned_view", "lcc_graph_owned_free", "lcc_objective", "lcc_cluster", "lcc_ctx_kernel_stats",
+    "lcc_ctx_reset_kernel_stats",
+)
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Loads liblcc.so (raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built: run paper_2108_01731_amd.build.build() first")
+    lib = ctypes.CDLL(path)
+    P, i32, i64, st = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32
+    gp = ctypes.POINTER(_Graph)
+    lib.lcc_params_default.restype = None
+    lib.lcc_params_default.argtypes = [ctypes.POINTER(_Params)]
+    lib.lcc_last_error.restype = ctypes.c_char_p
+    lib.lcc_last_error.argtypes = []
+    lib.lcc_ctx_create.restype = st
+    lib.lcc_ctx_create.argtypes = [i32, ctypes.POINTER(P)]
+    lib.lcc_ctx_destroy.restype = st
+    lib.lcc_ctx_destroy.argtypes = [P]
+    lib.lcc_best_move.restype = st
+    lib.lcc_best_move.argtypes = [P, gp, _Lambda, ctypes.POINTER(_Params), i32, i32, P, ctypes.POINTER(_BMStats), P]
+    lib.lcc_compress.restype = st
+    lib.lcc_compress.argtypes = [P, gp, P, ctypes.POINTER(P), P, P]
+    lib.lcc_graph_owned_view.restype = st
+    lib.lcc_graph_owned_view.argtypes = [P, gp]
+    lib.lcc_graph_owned_free.restype = st
+    lib.lcc_graph_owned_free.argtypes = [P, P]
+    lib.lcc_objective.restype = st
+    lib.lcc_objective.argtypes = [P, gp, _Lambda, P, ctypes.POINTER(_Objective), P]
+    lib.lcc_cluster.restype = st
+    lib.lcc_cluster.argtypes = [P, gp, _Lambda, ctypes.POINTER(_Params), P, ctypes.POINTER(_Objective),
+                                ctypes.POINTER(_ClusterStats), P]
+    lib.lcc_ctx_kernel_stats.restype = st
+    lib.lcc_ctx_kernel_stats.argtypes = [P, ctypes.POINTER(_KernelStat), i32, ctypes.POINTER(i32)]
+    lib.lcc_ctx_reset_kernel_stats.restype = st
+    lib.lcc_ctx_reset_kernel_stats.argtypes = [P]
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != LCC_OK:
+        raise LccError(rc, _lib.lcc_last_error().decode(errors="replace"))
+
+
+# ------------------------------------------------------------------ data
+
+
+@dataclass
+class DeviceGraph:
+    """CSR arrays as torch tensors on one GPU (see lcc_graph in include/lcc.h)."""
+
+    off: torch.Tensor
+    col: torch.Tensor
+    k: torch.Tensor
+    wt: Optional[torch.Tensor] = None
+    s: Optional[torch.Tensor] = None
+    kk: Optional[torch.Tensor] = None
+
+    @property
+    def n(self) -> int:
+        return int(self.off.shape[0]) - 1
+
+    @property
+    def arcs(self) -> int:
+        return int(self.col.shape[0])
+
+    @property
+    def wt_kind(self) -> int:
+        if self.wt is None:
+            return LCC_WT_UNIT
+        return {torch.int16: LCC_WT_I16, torch.int32: LCC_WT_I32, torch.int64: LCC_WT_I64}[self.wt.dtype]
+
+    @staticmethod
+    def from_host(h, device="cuda") -> "DeviceGraph":
+        """From a graphgen.HostGraph (numpy or torch arrays)."""
+        t = h.to(device)
+        return DeviceGraph(off=t.off.contiguous(), col=t.col.contiguous(), k=t.k.contiguous(),
+                           wt=None if t.wt is None else t.wt.contiguous(),
+                           s=None if t.s is None else t.s.contiguous(),
+                           kk=None if t.kk is None else t.kk.contiguous())
+
+    def _c(self) -> _Graph:
+        def ptr(t):
+            return None if t is None else t.data_ptr()
+
+        for name, t, dt in (("off", self.off, torch.int64), ("col", self.col, torch.int32), ("k", self.k, torch.int64),
+                            ("s", self.s, torch.int64), ("kk", self.kk, torch.int64)):
+            if t is not None and (t.dtype != dt or not t.is_contiguous()):
+                raise TypeError(f"{name} must be a contiguous {dt} tensor")
+        if self.wt is not None and not self.wt.is_contiguous():
+            raise TypeError("wt must be contiguous")
+        return _Graph(self.n, self.arcs, ptr(self.off), ptr(self.col), ptr(self.wt), self.wt_kind, 0,
+                      ptr(self.k), ptr(self.s), ptr(self.kk))
+
+
+@dataclass
+class Params:
+    S: int = 4
+    num_iter: int = 10
+    seed: int = 1
+    frontier: int = LCC_FRONTIER_NBR
+    refine: int = 1
+    allow_isolate: int = 1
+    max_levels: int = 64
+    stop_after_subrounds: int = 0
+    validate: int = 1
+    timing: int = 0
+
+    def _c(self) -> _Params:
+        p = _Params()
+        p.S, p.num_iter, p.seed = self.S, self.num_iter, self.seed & (2**64 - 1)
+        p.frontier, p.refine, p.allow_isolate = self.frontier, self.refine, self.allow_isolate
+        p.max_levels, p.stop_after_subrounds = self.max_levels, self.stop_after_subrounds
+        p.validate, p.timing = self.validate, self.timing
+        return p
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Context:
+    """An lcc_ctx bound to one GPU."""
+
+    def __init__(self, device: int = 0):
+        lib = load_library()
+        self.device = device
+        h = ctypes.c_void_p()
+        _check(lib.lcc_ctx_create(device, ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if self._h:
+            _check(_lib.lcc_ctx_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def kernel_stats(self) -> dict:
+        cnt = ctypes.c_int32()
+        _check(_lib.lcc_ctx_kernel_stats(self._h, None, 0, ctypes.byref(cnt)))
+        arr = (_KernelStat * max(cnt.value, 1))()
+        _check(_lib.lcc_ctx_kernel_stats(self._h, arr, cnt.value, ctypes.byref(cnt)))
+        return {arr[i].name.decode(): {"launches": arr[i].launches, "ms": arr[i].total_ms, "bytes": arr[i].bytes,
+                                       "items": arr[i].items} for i in range(cnt.value)}
+
+    def reset_kernel_stats(self):
+        _check(_lib.lcc_ctx_reset_kernel_stats(self._h))
+
+
+_contexts = {}
+
+
+def context(device: int = 0) -> Context:
+    if device not in _contexts:
+        _contexts[device] = Context(device)
+    return _contexts[device]
+
+
+def _lam(p: int, q: int) -> _Lambda:
+    return _Lambda(int(p), int(q))
+
+
+def _bm_stats(st: _BMStats) -> dict:
+    it = min(st.iterations, MAX_ITER_STATS)
+    return {"iterations": st.iterations, "subrounds": st.subrounds, "moved_any": st.moved_any, "term": st.term,
+            "moves": st.moves, "arcs_scanned": st.arcs_scanned, "vertices_processed": st.vertices_processed,
+            "candidates": st.candidates, "active_per_iter": list(st.active_per_iter[:it]),
+            "moves_per_iter": list(st.moves_per_iter[:it])}
+
+
+# ------------------------------------------------------------- entry points
+
+
+def lcc_best_move(ctx: Context, g: DeviceGraph, p: int, q: int, params: Params, C: torch.Tensor, level: int = 0,
+                  phase: int = 0, stream=None) -> dict:
+    """Best-Moves from clustering C (int32 device tensor, updated in place)."""
+    if C.dtype != torch.int32 or not C.is_contiguous():
+        raise TypeError("C must be a contiguous int32 tensor")
+    st = _BMStats()
+    cg, cp = g._c(), params._c()
+    _check(_lib.lcc_best_move(ctx._h, ctypes.byref(cg), _lam(p, q), ctypes.byref(cp), level, phase,
+                              C.data_ptr() if C.numel() else None, ctypes.byref(st), _stream_ptr(stream)))
+    return _bm_stats(st)
+
+
+def _hip_copy(dst: torch.Tensor, src_ptr: int, nbytes: int):
+    if nbytes == 0:
+        return
+    hip = ctypes.CDLL("libamdhip64.so")
+    hip.hipMemcpy.restype = ctypes.c_int
+    hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+    rc = hip.hipMemcpy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src_ptr), nbytes, 3)
+    if rc != 0:
+        raise RuntimeError(f"hipMemcpy failed with {rc}")
+
+
+def lcc_compress(ctx: Context, g: DeviceGraph, C: torch.Tensor, stream=None):
+    """Returns (contracted DeviceGraph, map int32 tensor)."""
+    dev = g.off.device
+    mp = torch.empty(g.n, dtype=torch.int32, device=dev)
+    h = ctypes.c_void_p()
+    cg = g._c()
+    _check(_lib.lcc_compress(ctx._h, ctypes.byref(cg), C.data_ptr() if C.numel() else None, ctypes.byref(h),
+                             mp.data_ptr() if mp.numel() else None, _stream_ptr(stream)))
+    try:
+        v = _Graph()
+        _check(_lib.lcc_graph_owned_view(h, ctypes.byref(v)))
+        n2, m2 = v.n, v.arcs
+        out = DeviceGraph(off=torch.empty(n2 + 1, dtype=torch.int64, device=dev),
+                          col=torch.empty(m2, dtype=torch.int32, device=dev),
+                          k=torch.empty(n2, dtype=torch.int64, device=dev),
+                          wt=torch.empty(m2, dtype=_WT_DTYPE[v.wt_kind], device=dev),
+                          s=torch.empty(n2, dtype=torch.int64, device=dev),
+                          kk=torch.empty(n2, dtype=torch.int64, device=dev))
+        torch.cuda.synchronize(dev)
+        _hip_copy(out.off, v.off, (n2 + 1) * 8)
+        _hip_copy(out.col, v.col, m2 * 4)
+        _hip_copy(out.wt, v.wt, m2 * out.wt.element_size())
+        _hip_copy(out.k, v.k, n2 * 8)
+        _hip_copy(out.s, v.s, n2 * 8)
+        _hip_copy(out.kk, v.kk, n2 * 8)
+    finally:
+        _check(_lib.lcc_graph_owned_free(ctx._h, h))
+    return out, mp
+
+
+def _num(o: _Objective) -> int:
+    return (o.num_hi << 64) | o.num_lo
+
+
+def lcc_objective(ctx: Context, g: DeviceGraph, p: int, q: int, C: torch.Tensor, stream=None) -> int:
+    """Exact numerator N of the objective (value N / q)."""
+    o = _Objective()
+    cg = g._c()
+    _check(_lib.lcc_objective(ctx._h, ctypes.byref(cg), _lam(p, q), C.data_ptr() if C.numel() else None,
+                              ctypes.byref(o), _stream_ptr(stream)))
+    return _num(o)
+
+
+def lcc_cluster(ctx: Context, g: DeviceGraph, p: int, q: int, params: Params, stream=None):
+    """Parallel-CC with refinement.  Returns (labels int32 tensor, N, stats)."""
+    lab = torch.empty(g.n, dtype=torch.int32, device=g.off.device)
+    o = _Objective()
+    cs = _ClusterStats()
+    cg, cp = g._c(), params._c()
+    _check(_lib.lcc_cluster(ctx._h, ctypes.byref(cg), _lam(p, q), ctypes.byref(cp),
+                            lab.data_ptr() if lab.numel() else None, ctypes.byref(o), ctypes.byref(cs),
+                            _stream_ptr(stream)))
+    L = cs.levels
+    stats = {"levels": L, "top_moved": cs.top_moved, "n_level": list(cs.n_level[:L]),
+             "arcs_level": list(cs.arcs_level[:L]), "iters_coarsen": list(cs.iters_coarsen[:L]),
+             "iters_refine": list(cs.iters_refine[:L]), "moves_total": cs.moves_total,
+             "arcs_scanned_total": cs.arcs_scanned_total, "clusters": cs.clusters,
+             "ms_best_move": cs.ms_best_move, "ms_compress": cs.ms_compress, "ms_total": cs.ms_total}
+    return lab, _num(o), stats

@@ -1,0 +1,275 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle, element
+by element, on seeded inputs.  Everything is integer, so the bar is
+bit-exact equality of clusterings, contracted graphs, objectives and the
+schedule counters."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2108_01731_amd import graphgen as G
+from paper_2108_01731_amd import lcc as L
+from tests import helpers as H
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return L.context(0)
+
+
+def dev(h):
+    return L.DeviceGraph.from_host(h, "cuda")
+
+
+def oparams(**kw):
+    return O.Params(**kw)
+
+
+def dparams(**kw):
+    return L.Params(**kw)
+
+
+def run_pair_best_move(ctx, h, p, q, C0=None, level=0, phase=0, **kw):
+    g_o = H.to_oracle(h)
+    g_d = dev(h)
+    n = g_o.n
+    C0 = np.arange(n, dtype=np.int32) if C0 is None else np.asarray(C0, np.int32)
+    Co, so = O.best_move(g_o, p, q, oparams(**kw), C0, level, phase)
+    Cd = torch.from_numpy(C0.copy()).cuda()
+    sd = L.lcc_best_move(ctx, g_d, p, q, dparams(**kw), Cd, level, phase)
+    return Co, so, Cd.cpu().numpy(), sd
+
+
+def assert_same_bm(Co, so, Cd, sd):
+    assert np.array_equal(Co, Cd)
+    for key in ("iterations", "subrounds", "moved_any", "term", "moves", "arcs_scanned", "vertices_processed",
+                "active_per_iter", "moves_per_iter"):
+        assert so[key] == sd[key], (key, so[key], sd[key])
+
+
+def graphs():
+    """(name, HostGraph, p, q) cases spanning weight kinds, degree bins and
+    lambda regimes."""
+    c1 = G.c1_sbm(1)
+    cl = G.chung_lu_planted(30000, 400000, 2.1, 0.3, seed=2)
+    out = [
+        ("sbm_c1", c1, 1, 100),
+        ("sbm_c1_i16", H.with_weights(c1, "i16", 1, -3, 40), 1, 10),
+        ("sbm_c1_i64", H.with_weights(c1, "i64", 2, -2, 7), 3, 7),
+        ("chung_lu_mod", cl, 1, int(cl.arcs)),
+        ("hubs_i32", H.hub_graph(), 1, 40),
+        ("hubs_unit", H.hub_graph(weighted=False), 1, 500),
+        ("random_signed", G.random_signed(3000, 9000, 3, wmin=-4, wmax=6, kmax=3), 1, 9),
+    ]
+    return out
+
+
+GRAPHS = None
+
+
+def cases():
+    global GRAPHS
+    if GRAPHS is None:
+        GRAPHS = graphs()
+    return GRAPHS
+
+
+@pytest.mark.parametrize("idx", range(7))
+def test_subround_by_subround_parity(ctx, idx):
+    """C and the schedule counters after every one of the first sub-rounds."""
+    name, h, p, q = cases()[idx]
+    S = 3
+    for stop in range(1, 2 * S + 2):
+        Co, so, Cd, sd = run_pair_best_move(ctx, h, p, q, S=S, seed=7, stop_after_subrounds=stop)
+        assert_same_bm(Co, so, Cd, sd)
+
+
+@pytest.mark.parametrize("idx", range(7))
+@pytest.mark.parametrize("cfg", [dict(S=4), dict(S=1, num_iter=4), dict(S=2, frontier=0), dict(S=8, allow_isolate=0),
+                                 dict(S=4, seed=12345, num_iter=25)])
+def test_best_move_parity(ctx, idx, cfg):
+    name, h, p, q = cases()[idx]
+    Co, so, Cd, sd = run_pair_best_move(ctx, h, p, q, **cfg)
+    assert_same_bm(Co, so, Cd, sd)
+
+
+@pytest.mark.parametrize("idx", range(7))
+def test_best_move_from_given_clustering(ctx, idx):
+    """Refinement-style start: an arbitrary clustering, level 3, phase 1, and a
+    large lambda so isolation happens."""
+    name, h, p, q = cases()[idx]
+    n = h.n
+    rng = np.random.default_rng(idx)
+    C0 = rng.integers(0, max(1, n // 50), size=n).astype(np.int32)
+    for pp, qq in [(p, q), (p * 50, q)]:
+        Co, so, Cd, sd = run_pair_best_move(ctx, h, pp, qq, C0=C0, level=3, phase=1, S=4)
+        assert_same_bm(Co, so, Cd, sd)
+
+
+@pytest.mark.parametrize("idx", range(7))
+def test_compress_parity(ctx, idx):
+    name, h, p, q = cases()[idx]
+    n = h.n
+    rng = np.random.default_rng(100 + idx)
+    for C0 in [rng.integers(0, max(1, n // 30), size=n), rng.integers(0, n, size=n), np.zeros(n)]:
+        C0 = C0.astype(np.int32)
+        go, mo = O.compress(H.to_oracle(h), C0)
+        gd, md = L.lcc_compress(ctx, dev(h), torch.from_numpy(C0).cuda())
+        assert np.array_equal(mo, md.cpu().numpy())
+        assert np.array_equal(go.off, gd.off.cpu().numpy())
+        assert np.array_equal(go.col, gd.col.cpu().numpy())
+        assert np.array_equal(go.wt, gd.wt.cpu().numpy().astype(np.int64))
+        assert np.array_equal(go.k, gd.k.cpu().numpy())
+        assert np.array_equal(go.s, gd.s.cpu().numpy())
+        assert np.array_equal(go.kk, gd.kk.cpu().numpy())
+        # second level on the device's own output
+        C1 = rng.integers(0, max(1, go.n // 3), size=go.n).astype(np.int32)
+        go2, _ = O.compress(go, C1)
+        gd2, _ = L.lcc_compress(ctx, gd, torch.from_numpy(C1).cuda())
+        assert np.array_equal(go2.col, gd2.col.cpu().numpy())
+        assert np.array_equal(go2.wt, gd2.wt.cpu().numpy().astype(np.int64))
+        assert np.array_equal(go2.s, gd2.s.cpu().numpy())
+
+
+@pytest.mark.parametrize("idx", range(7))
+def test_objective_parity(ctx, idx):
+    name, h, p, q = cases()[idx]
+    n = h.n
+    rng = np.random.default_rng(200 + idx)
+    g_o = H.to_oracle(h)
+    g_d = dev(h)
+    for C0 in [np.arange(n), rng.integers(0, max(1, n // 40), size=n), np.zeros(n)]:
+        C0 = C0.astype(np.int32)
+        assert O.objective(g_o, p, q, C0) == L.lcc_objective(ctx, g_d, p, q, torch.from_numpy(C0).cuda())
+
+
+@pytest.mark.parametrize("idx", range(7))
+@pytest.mark.parametrize("cfg", [dict(), dict(S=2, refine=0), dict(S=8, frontier=0, num_iter=20)])
+def test_cluster_parity(ctx, idx, cfg):
+    name, h, p, q = cases()[idx]
+    lo, No, so = O.cluster(H.to_oracle(h), p, q, oparams(**cfg))
+    ld, Nd, sd = L.lcc_cluster(ctx, dev(h), p, q, dparams(**cfg))
+    assert np.array_equal(lo, ld.cpu().numpy())
+    assert No == Nd
+    for key in ("levels", "top_moved", "n_level", "arcs_level", "iters_coarsen", "iters_refine", "moves_total",
+                "arcs_scanned_total", "clusters"):
+        assert so[key] == sd[key], (key, so[key], sd[key])
+
+
+def test_cluster_parity_synchronous_pathology(ctx):
+    """S = 1 (the paper's synchronous setting) oscillates; the level cap ends it."""
+    h = G.c1_sbm(1)
+    cfg = dict(S=1, max_levels=6)
+    lo, No, so = O.cluster(H.to_oracle(h), 1, 100, oparams(**cfg))
+    ld, Nd, sd = L.lcc_cluster(ctx, dev(h), 1, 100, dparams(**cfg))
+    assert np.array_equal(lo, ld.cpu().numpy()) and No == Nd and so["levels"] == sd["levels"] == 6
+
+
+def test_determinism_and_row_order_invariance(ctx):
+    h = H.hub_graph(seed=9)
+    runs = [L.lcc_cluster(ctx, dev(h), 1, 40, dparams()) for _ in range(3)]
+    runs.append(L.lcc_cluster(ctx, dev(H.shuffle_rows(h, 3)), 1, 40, dparams()))
+    for lab, N, _ in runs[1:]:
+        assert torch.equal(lab, runs[0][0]) and N == runs[0][1]
+
+
+def test_tiny_and_degenerate_graphs(ctx):
+    cases_ = [
+        G.HostGraph(np.zeros(1, np.int64), np.zeros(0, np.int32), np.zeros(0, np.int64)),  # empty
+        G.HostGraph(np.zeros(2, np.int64), np.zeros(0, np.int32), np.ones(1, np.int64)),  # one vertex
+        G.HostGraph(np.zeros(6, np.int64), np.zeros(0, np.int32), np.ones(5, np.int64)),  # edgeless
+        G.HostGraph(np.array([0, 1, 2], np.int64), np.array([1, 0], np.int32), np.ones(2, np.int64)),  # one edge
+        G.random_signed(50, 10, 4),  # mostly isolated vertices
+        G.random_signed(40, 300, 5, wmin=0, wmax=0),  # all-zero weights
+        G.random_signed(40, 300, 6, wmin=-5, wmax=-1),  # all negative
+        H.with_k(G.random_signed(60, 200, 7, unit=True), np.zeros(60)),  # k = 0 everywhere
+    ]
+    for i, h in enumerate(cases_):
+        for p, q in [(1, 2), (0, 1), (5, 3)]:
+            lo, No, so = O.cluster(H.to_oracle(h), p, q, oparams())
+            ld, Nd, sd = L.lcc_cluster(ctx, dev(h), p, q, dparams())
+            assert np.array_equal(lo, ld.cpu().numpy()), (i, p, q)
+            assert No == Nd, (i, p, q)
+
+
+def test_lambda_zero_components_on_gpu(ctx):
+    """lambda = 0 with non-negative weights: every positive edge ends inside a
+    cluster (the objective is q times the total weight)."""
+    h = G.random_signed(2000, 2500, 11, wmin=0, wmax=4)
+    ld, Nd, sd = L.lcc_cluster(ctx, dev(h), 0, 3, dparams())
+    assert sd["top_moved"] == 0
+    assert Nd == 3 * int(np.asarray(h.numpy().wt).sum()) // 2
+
+
+def test_invalid_inputs_are_rejected_before_any_output(ctx):
+    h = G.random_signed(100, 300, 1)
+    g = dev(h)
+    C = torch.arange(100, dtype=torch.int32, device="cuda")
+    bad = L.DeviceGraph(off=g.off, col=g.col.clone(), k=g.k, wt=g.wt)
+    bad.col[0] = 1000
+    with pytest.raises(L.LccError) as e:
+        L.lcc_best_move(ctx, bad, 1, 2, dparams(), C)
+    assert e.value.code == L.LCC_ERR_INVALID_ARG
+    assert torch.equal(C, torch.arange(100, dtype=torch.int32, device="cuda"))
+    self_loop = L.DeviceGraph(off=g.off, col=g.col.clone(), k=g.k, wt=g.wt)
+    v = int(np.nonzero(np.diff(h.off))[0][0])
+    self_loop.col[int(h.off[v])] = v
+    with pytest.raises(L.LccError):
+        L.lcc_cluster(ctx, self_loop, 1, 2, dparams())
+    big = L.DeviceGraph(off=g.off, col=g.col, k=torch.full((100,), 2**40, dtype=torch.int64, device="cuda"), wt=g.wt)
+    with pytest.raises(L.LccError) as e:
+        L.lcc_cluster(ctx, big, 1, 1, dparams())
+    assert e.value.code == L.LCC_ERR_OVERFLOW
+    Cbad = C.clone()
+    Cbad[5] = 100
+    with pytest.raises(L.LccError) as e:
+        L.lcc_objective(ctx, g, 1, 2, Cbad)
+    assert e.value.code == L.LCC_ERR_INVALID_ARG
+    with pytest.raises(L.LccError):
+        L.lcc_best_move(ctx, g, -1, 2, dparams(), C)
+    short = torch.zeros(10, dtype=torch.int32, device="cuda")
+    with pytest.raises(L.LccError) as e:
+        L.lcc_best_move(ctx, g, 1, 2, dparams(), short)
+    assert e.value.code == L.LCC_ERR_INVALID_ARG
+    host_c = torch.arange(100, dtype=torch.int32)
+    with pytest.raises(L.LccError):
+        L.lcc_best_move(ctx, g, 1, 2, dparams(), host_c)
+
+
+def test_full_size_modularity_graph_sampled(ctx):
+    """The 4M-vertex / 100M-edge Chung-Lu modularity workload, in the launch
+    configuration the benchmark uses: the first full iteration of level-0
+    Best-Moves (every sub-round) equals the oracle's; sampled vertices of the
+    first sub-round equal the oracle's one-by-one decision; the final
+    clustering's objective from the GPU equals the oracle's evaluation."""
+    h = G.chung_lu_planted(4_000_000, 100_000_000, 2.1, 0.3, seed=1, device="cuda")
+    g_d = dev(h)
+    m2 = h.arcs
+    p, q = 1, m2
+    S = 4
+    C = torch.arange(h.n, dtype=torch.int32, device="cuda")
+    L.lcc_best_move(ctx, g_d, p, q, dparams(S=S, stop_after_subrounds=1), C)
+    Cd1 = C.cpu().numpy()
+    hh = h.numpy()
+    g_o = H.to_oracle(hh)
+    hr = O.round_hash(1, 0, 0, 0)
+    rng = np.random.default_rng(0)
+    cand = rng.choice(h.n, size=20000, replace=False)
+    U = np.array([v for v in cand if O.color(hr, int(v), S) == 0], dtype=np.int32)[:4000]
+    D = O.decide_many(g_o, p, q, np.arange(h.n, dtype=np.int32), U)
+    assert np.array_equal(D, Cd1[U])
+    # one full iteration, all four sub-rounds, bit-exact
+    C = torch.arange(h.n, dtype=torch.int32, device="cuda")
+    sd = L.lcc_best_move(ctx, g_d, p, q, dparams(S=S, stop_after_subrounds=S), C)
+    Co, so = O.best_move(g_o, p, q, oparams(S=S, stop_after_subrounds=S))
+    assert np.array_equal(Co, C.cpu().numpy())
+    assert so["moves"] == sd["moves"] and so["arcs_scanned"] == sd["arcs_scanned"]
+    # full clustering: objective re-evaluated by the oracle
+    lab, N, st = L.lcc_cluster(ctx, g_d, p, q, dparams())
+    labn = lab.cpu().numpy()
+    assert labn.min() == 0 and labn.max() + 1 == st["clusters"]
+    assert np.array_equal(O.canonical_labels(labn), labn)
+    assert O.objective(g_o, p, q, labn) == N
