@@ -43,6 +43,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="chung_lu_4m", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run one 1 GiB device-to-device copy, a reference for HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding of this "
@@ -56,6 +58,14 @@ def main():
     from paper_2108_01731_amd import lcc
 
     dev = "cuda:0"
+    if args.calibrate_copy:
+        src = torch.empty(1 << 30, dtype=torch.uint8, device=dev).fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("calibration copy: 1073741824 bytes read, 1073741824 bytes written")
+        del src, dst
     gen_kw, desc = WORKLOADS[args.workload]
     t0 = time.time()
     if gen_kw is None:
@@ -88,9 +98,11 @@ def main():
     ms_per_step = dt * 1e3 / args.steps
     ks = ctx.kernel_stats()
     for name, v in sorted(ks.items(), key=lambda kv: -kv[1]["ms"]):
-        log(f"  {name:24s} launches={v['launches']:6d} ms={v['ms']:9.2f} "
-            f"GB/s={(v['bytes'] / (v['ms'] * 1e-3) / 1e9) if v['ms'] > 0 and v['bytes'] > 0 else 0:8.1f}")
-    agg = {k: v for k, v in ks.items() if k.startswith("bm_aggregate")}
+        sec = v["ms"] * 1e-3
+        log(f"  {name:24s} launches={v['launches']:6d} ms/step={v['ms'] / args.steps:8.2f} "
+            f"GB/s={(v['bytes'] / sec / 1e9) if sec > 0 else 0:8.1f} "
+            f"Gitems/s={(v['items'] / sec / 1e9) if sec > 0 else 0:7.2f}")
+    agg = {k: v for k, v in ks.items() if k.startswith(("bm_aggregate", "bm_single"))}
     dom_name, dom = max(agg.items(), key=lambda kv: kv[1]["ms"])
     achieved = dom["bytes"] / (dom["ms"] * 1e-3) / 1e9
     agg_ms = sum(v["ms"] for v in agg.values())

@@ -79,7 +79,7 @@ enum { LCC_TERM_NO_MOVES = 0, LCC_TERM_NUM_ITER = 1, LCC_TERM_STOPPED = 2 };
 #define LCC_MAX_LEVELS 64
 
 /* A graph in CSR form (paper Sec. 2), all arrays in device memory.
- *   n          vertices, 0 <= n < 2^31 - 1
+ *   n          vertices, 0 <= n < 2^30
  *   arcs       stored arcs = 2 x undirected edges
  *   off        int64[n+1], off[0] = 0, non-decreasing, off[n] = arcs
  *   col        int32[arcs], neighbor ids in [0, n), no self-loops; rows need
@@ -203,9 +203,13 @@ const char *lcc_last_error(void);
  *                                               with allow_isolate and |c| >= 2)
  * q times the objective change of a move is score(target) - score(c).  The
  * best target is the highest score, ties to the lowest cluster id, iso after
- * every id; v moves only if it is strictly better than staying.  Isolated
- * vertices take, in ascending vertex order, the ascending ids that are empty
- * after the sub-round's moves.  The first iteration considers every vertex;
+ * every id; v moves only if it is strictly better than staying.  A vertex v
+ * that isolates moves to the fresh cluster n + v (v is in one sub-round per
+ * iteration, so that id is unused within the iteration; later sub-rounds may
+ * join it); at the end of the iteration the non-empty fresh clusters, in
+ * ascending id order, are renamed to the ascending ids in [0, n) that are
+ * empty, so C holds ids in [0, n) between iterations and on return.  The
+ * first iteration considers every vertex;
  * later ones follow params->frontier.  Stops after an iteration with no move,
  * after num_iter iterations, or after stop_after_subrounds sub-rounds.
  *

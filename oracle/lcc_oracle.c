@@ -37,8 +37,12 @@
  *     when allow_isolate is set and |c| >= 2.  Best target: highest gain,
  *     ties to the lowest cluster id, isolate ranks after every id.  v moves
  *     only on a strict improvement over staying.
- *   - Isolated vertices take, in ascending vertex order, the ascending ids of
- *     the clusters that are empty after the sub-round's moves.
+ *   - A vertex v that isolates moves to the fresh cluster n + v (each vertex
+ *     belongs to one sub-round per iteration, so that id is unused within the
+ *     iteration; other vertices may join it in later sub-rounds).  At the end
+ *     of every iteration the non-empty fresh clusters, in ascending id order,
+ *     are renamed to the ascending ids in [0, n) that are empty at that point,
+ *     so every clustering seen between iterations uses ids in [0, n).
  *   - Frontier "neighbors of moved vertices": the union of N(v) over every v
  *     that moved in any sub-round of the iteration (v itself is not added).
  *   - Compress numbers clusters by the rank of their id among non-empty ids;
@@ -70,6 +74,7 @@ typedef __int128 i128;
 #define ORC_ISO (-1)
 #define ORC_MAX_ITER_STATS 64
 #define ORC_MAX_LEVELS 64
+#define ORC_MAX_N ((int64_t)1 << 30) /* cluster ids, fresh ones included, stay below 2^31 */
 
 static const i128 I64LIM = (i128)INT64_MAX;
 
@@ -170,7 +175,7 @@ static i128 KK_of(const orc_graph *g, int64_t v) {
  * non-negative vertex weights.  Symmetry is a precondition checked separately
  * (orc_check_symmetric) because it costs a sort. */
 int orc_validate(const orc_graph *g) {
-  if (!g || g->n < 0 || g->n >= (int64_t)INT32_MAX || g->arcs < 0) return ORC_INVALID;
+  if (!g || g->n < 0 || g->n >= ORC_MAX_N || g->arcs < 0) return ORC_INVALID;
   if (g->n > 0 && (!g->off || !g->k)) return ORC_INVALID;
   if (g->arcs > 0 && !g->col) return ORC_INVALID;
   if (g->n == 0) return g->arcs == 0 ? ORC_OK : ORC_INVALID;
@@ -252,9 +257,10 @@ int orc_check_symmetric(const orc_graph *g) {
 
 /* ------------------------------------------------------ cluster bookkeeping */
 
-/* K_X = sum of k_v over v in X, cnt_X = |X|, for cluster ids in [0, n). */
+/* K_X = sum of k_v over v in X, cnt_X = |X|, for cluster ids in [0, n); the
+ * fresh ids [n, 2n) start empty. */
 static int cluster_totals(const orc_graph *g, const int32_t *C, int64_t *K, int32_t *cnt) {
-  for (int64_t x = 0; x < g->n; x++) { K[x] = 0; cnt[x] = 0; }
+  for (int64_t x = 0; x < 2 * g->n; x++) { K[x] = 0; cnt[x] = 0; }
   for (int64_t v = 0; v < g->n; v++) {
     int32_t c = C[v];
     if (c < 0 || (int64_t)c >= g->n) return ORC_INVALID;
@@ -273,7 +279,7 @@ typedef struct {
 } decide_scratch;
 
 static int scratch_init(decide_scratch *d, int64_t n) {
-  size_t m = (size_t)(n > 0 ? n : 1);
+  size_t m = (size_t)(n > 0 ? 2 * n : 1); /* ids in [0, 2n) */
   d->acc = (int64_t *)calloc(m, sizeof(int64_t));
   d->seen = (uint8_t *)calloc(m, 1);
   d->list = (int32_t *)malloc(m * sizeof(int32_t));
@@ -319,12 +325,12 @@ static int32_t decide(const orc_graph *g, int64_t p, int64_t q, int allow_iso, c
 }
 
 /* Applies the decisions D of the vertices in U together (Sec. 3.2.1,
- * synchronous setting), then hands the isolated vertices, in ascending vertex
- * order, the ascending ids of the clusters that are empty after the moves.
- * Returns the number of vertices whose decision differed from their cluster. */
+ * synchronous setting); a vertex that isolates moves to the fresh cluster
+ * n + v.  Returns the number of vertices whose decision differed from their
+ * cluster. */
 static int64_t apply_moves(const orc_graph *g, int32_t *C, int64_t *K, int32_t *cnt,
-                           const int32_t *U, int64_t nu, const int32_t *D, uint8_t *iso_flag) {
-  int64_t moved = 0, niso = 0;
+                           const int32_t *U, int64_t nu, const int32_t *D) {
+  int64_t moved = 0;
   for (int64_t i = 0; i < nu; i++) {
     int32_t v = U[i];
     int32_t c = C[v], d = D[i];
@@ -332,29 +338,35 @@ static int64_t apply_moves(const orc_graph *g, int32_t *C, int64_t *K, int32_t *
     moved++;
     K[c] -= g->k[v];
     cnt[c] -= 1;
-    if (d == ORC_ISO) {
-      iso_flag[v] = 1;
-      niso++;
-      C[v] = ORC_ISO;
-    } else {
-      K[d] += g->k[v];
-      cnt[d] += 1;
-      C[v] = d;
-    }
-  }
-  if (niso) {
-    int64_t x = 0;
-    for (int64_t v = 0; v < g->n; v++) {
-      if (!iso_flag[v]) continue;
-      iso_flag[v] = 0;
-      while (cnt[x] != 0) x++; /* pigeonhole: at most n - niso ids are non-empty */
-      C[v] = (int32_t)x;
-      K[x] = g->k[v];
-      cnt[x] = 1;
-      x++;
-    }
+    if (d == ORC_ISO) d = (int32_t)(g->n + v);
+    K[d] += g->k[v];
+    cnt[d] += 1;
+    C[v] = d;
   }
   return moved;
+}
+
+/* End of an iteration: the non-empty fresh clusters (ids in [n, 2n)), in
+ * ascending id order, take the ascending ids in [0, n) that are empty.  There
+ * are enough: with T non-empty fresh clusters at most n - T regular ids are
+ * in use. */
+static void rename_fresh(const orc_graph *g, int32_t *C, int64_t *K, int32_t *cnt, int32_t *newid) {
+  int64_t n = g->n, x = 0, any = 0;
+  for (int64_t t = 0; t < n; t++) {
+    newid[t] = -1;
+    if (cnt[n + t] == 0) continue;
+    while (cnt[x] != 0) x++;
+    newid[t] = (int32_t)x;
+    K[x] = K[n + t];
+    cnt[x] = cnt[n + t];
+    K[n + t] = 0;
+    cnt[n + t] = 0;
+    x++;
+    any = 1;
+  }
+  if (!any) return;
+  for (int64_t v = 0; v < n; v++)
+    if (C[v] >= n) C[v] = newid[C[v] - n];
 }
 
 /* One synchronous sub-round over an explicit vertex list U (a test hook for
@@ -364,20 +376,22 @@ static int64_t apply_moves(const orc_graph *g, int32_t *C, int64_t *K, int32_t *
 int64_t orc_subround(const orc_graph *g, int64_t p, int64_t q, int32_t allow_iso, int32_t *C,
                      const int32_t *U, int64_t nu, int32_t *D_out) {
   int64_t n = g->n;
-  int64_t *K = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n ? n : 1));
-  int32_t *cnt = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n ? n : 1));
+  size_t n2 = (size_t)(n ? 2 * n : 1);
+  int64_t *K = (int64_t *)malloc(sizeof(int64_t) * n2);
+  int32_t *cnt = (int32_t *)malloc(sizeof(int32_t) * n2);
   int32_t *D = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nu ? nu : 1));
-  uint8_t *iso = (uint8_t *)calloc((size_t)(n ? n : 1), 1);
+  int32_t *newid = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n ? n : 1));
   decide_scratch sc;
   int64_t moved = -1;
-  if (!K || !cnt || !D || !iso || scratch_init(&sc, n)) goto out;
+  if (!K || !cnt || !D || !newid || scratch_init(&sc, n)) goto out;
   if (cluster_totals(g, C, K, cnt)) { scratch_free(&sc); goto out; }
   for (int64_t i = 0; i < nu; i++) D[i] = decide(g, p, q, allow_iso, C, K, cnt, U[i], &sc);
   if (D_out) memcpy(D_out, D, sizeof(int32_t) * (size_t)nu);
-  moved = apply_moves(g, C, K, cnt, U, nu, D, iso);
+  moved = apply_moves(g, C, K, cnt, U, nu, D);
+  rename_fresh(g, C, K, cnt, newid);
   scratch_free(&sc);
 out:
-  free(K); free(cnt); free(D); free(iso);
+  free(K); free(cnt); free(D); free(newid);
   return moved;
 }
 
@@ -386,8 +400,8 @@ out:
 int orc_decide_many(const orc_graph *g, int64_t p, int64_t q, int32_t allow_iso, const int32_t *C,
                     const int32_t *U, int64_t nu, int32_t *D_out) {
   int64_t n = g->n;
-  int64_t *K = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n ? n : 1));
-  int32_t *cnt = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n ? n : 1));
+  int64_t *K = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n ? 2 * n : 1));
+  int32_t *cnt = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n ? 2 * n : 1));
   decide_scratch sc;
   int rc = ORC_NOMEM;
   if (!K || !cnt || scratch_init(&sc, n)) goto out;
@@ -423,16 +437,16 @@ static int best_move_impl(const orc_graph *g, int64_t p, int64_t q, const orc_pa
   memset(st, 0, sizeof(*st));
   if (prm->S < 1 || prm->num_iter < 0) return ORC_INVALID;
   size_t nn = (size_t)(n ? n : 1);
-  int64_t *K = (int64_t *)malloc(sizeof(int64_t) * nn);
-  int32_t *cnt = (int32_t *)malloc(sizeof(int32_t) * nn);
+  int64_t *K = (int64_t *)malloc(sizeof(int64_t) * 2 * nn);
+  int32_t *cnt = (int32_t *)malloc(sizeof(int32_t) * 2 * nn);
   uint8_t *active = (uint8_t *)malloc(nn);
   uint8_t *next = (uint8_t *)calloc(nn, 1);
-  uint8_t *iso = (uint8_t *)calloc(nn, 1);
+  int32_t *newid = (int32_t *)malloc(sizeof(int32_t) * nn);
   int32_t *U = (int32_t *)malloc(sizeof(int32_t) * nn);
   int32_t *D = (int32_t *)malloc(sizeof(int32_t) * nn);
   decide_scratch sc;
   int rc = ORC_NOMEM;
-  if (!K || !cnt || !active || !next || !iso || !U || !D || scratch_init(&sc, n)) goto out;
+  if (!K || !cnt || !active || !next || !newid || !U || !D || scratch_init(&sc, n)) goto out;
   rc = cluster_totals(g, C, K, cnt);
   if (rc) { scratch_free(&sc); goto out; }
   memset(active, 1, nn);
@@ -459,10 +473,11 @@ static int best_move_impl(const orc_graph *g, int64_t p, int64_t q, const orc_pa
       st->vertices_processed += nu;
       for (int64_t i = 0; i < nu; i++)
         if (D[i] != C[U[i]]) orc_frontier_nbr(g, &U[i], 1, next);
-      int64_t mv = apply_moves(g, C, K, cnt, U, nu, D, iso);
+      int64_t mv = apply_moves(g, C, K, cnt, U, nu, D);
       moved_it += mv;
       st->subrounds++;
     }
+    rename_fresh(g, C, K, cnt, newid);
     if (it < ORC_MAX_ITER_STATS) { st->active_per_iter[it] = active_it; st->moves_per_iter[it] = moved_it; }
     st->moves += moved_it;
     if (moved_it == 0) { st->term = ORC_TERM_NO_MOVES; break; }
@@ -477,6 +492,7 @@ static int best_move_impl(const orc_graph *g, int64_t p, int64_t q, const orc_pa
 done:
   /* moves of a partial (stopped) iteration also count */
   if (st->term == ORC_TERM_STOPPED) {
+    rename_fresh(g, C, K, cnt, newid);
     int32_t it = st->iterations - 1;
     int64_t mv = (it >= 0 && it < ORC_MAX_ITER_STATS) ? st->moves_per_iter[it] : 0;
     st->moves += mv;
@@ -485,7 +501,7 @@ done:
   scratch_free(&sc);
   rc = ORC_OK;
 out:
-  free(K); free(cnt); free(active); free(next); free(iso); free(U); free(D);
+  free(K); free(cnt); free(active); free(next); free(newid); free(U); free(D);
   return rc;
 }
 

@@ -69,7 +69,8 @@ static void check_dev(const Ctx &c, const void *p, size_t bytes, const char *wha
 
 static void check_graph_args(const Ctx &c, const lcc_graph *g) {
   if (!g) fail(LCC_ERR_INVALID_ARG, "graph is NULL");
-  if (g->n < 0 || g->n >= (int64_t)INT32_MAX) fail(LCC_ERR_INVALID_ARG, "n must be in [0, 2^31 - 1)");
+  // cluster ids, the fresh ids [n, 2n) of isolating vertices included, stay below 2^31
+  if (g->n < 0 || g->n >= ((int64_t)1 << 30)) fail(LCC_ERR_INVALID_ARG, "n must be in [0, 2^30)");
   if (g->arcs < 0) fail(LCC_ERR_INVALID_ARG, "arcs must be >= 0");
   if (g->wt_kind < LCC_WT_UNIT || g->wt_kind > LCC_WT_I64) fail(LCC_ERR_INVALID_ARG, "unknown wt_kind");
   if (g->wt_kind == LCC_WT_UNIT && g->wt != nullptr) fail(LCC_ERR_INVALID_ARG, "wt must be NULL for LCC_WT_UNIT");
@@ -128,7 +129,8 @@ __device__ __forceinline__ uint64_t wave_max(uint64_t x) {
 }
 
 enum : uint64_t {
-  E_OFF = 1, E_COL = 2, E_SELF = 4, E_K = 8, E_KK = 16, E_C = 32, E_ENDS = 64
+  E_OFF = 1, E_COL = 2, E_SELF = 4, E_K = 8, E_KK = 16, E_C = 32, E_ENDS = 64,
+  F_UNSORTED = 128  // not an error: some row is not strictly ascending
 };
 
 constexpr int VA_NT = 256;
@@ -206,6 +208,7 @@ __global__ __launch_bounds__(VA_NT) void k_validate_arcs(const int64_t *__restri
         const int32_t u = col[e];
         if (u < 0 || (int64_t)u >= n) err |= E_COL;
         if ((int64_t)u == v) err |= E_SELF;
+        if (e > off[v] && u <= col[e - 1]) err |= F_UNSORTED;
       }
       const int64_t w = load_w<WK>(wt, e);
       if (w < 0) {
@@ -312,12 +315,15 @@ GraphSummary summarize_graph(Ctx &c, const lcc_graph &g, const int32_t *C, bool 
       s.wabs2 = host_sat_add(s.wabs2, ha[(size_t)(b * 3 + 1)]);
       s.negative = s.negative || ha[(size_t)(b * 3 + 2)];
     }
+    s.sorted_rows = check_structure && !(e2 & F_UNSORTED);
+    e2 &= ~(uint64_t)F_UNSORTED;
     if (e2) {
       s.ok = false;
       s.why = err_text(e2);
     }
   } else {
     s.wabs2 = (uint64_t)g.arcs;  // unit weights
+    s.sorted_rows = g.arcs == 0;
   }
   return s;
 }
@@ -408,6 +414,7 @@ lcc_status lcc_ctx_create(int32_t device, lcc_ctx **out) {
     std::unique_ptr<lcc_ctx> ctx(new lcc_ctx());
     ctx->c.device = device;
     ctx->c.num_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    ctx->c.lds_per_block = prop.sharedMemPerBlock > 0 ? prop.sharedMemPerBlock : 65536;
     *out = ctx.release();
   });
 }
@@ -435,7 +442,8 @@ lcc_status lcc_best_move(lcc_ctx *ctx, const lcc_graph *g, lcc_lambda lam, const
     check_dev(c, C_inout, (size_t)g->n * sizeof(int32_t), "C_inout");
     GraphSummary s = checked_summary(c, *g, C_inout, prm->validate != 0, lam.p, lam.q);
     lcc_bm_stats st;
-    best_moves(c, *g, lam.p, lam.q, *prm, level, phase, C_inout, false, s.maxdeg, st);
+    best_moves(c, *g, lam.p, lam.q, *prm, level, phase, C_inout, BMShape{s.maxdeg, !wide_weights(s), false, false},
+               st);
     c.sync();
     if (c.timing) c.collect_timing();
     if (stats) *stats = st;
@@ -530,7 +538,9 @@ lcc_status lcc_cluster(lcc_ctx *ctx, const lcc_graph *g, lcc_lambda lam, const l
       iota_i32(c, C, n);
       lcc_bm_stats st;
       auto a = clk::now();
-      best_moves(c, G[l], lam.p, lam.q, *prm, l, 0, C, true, maxdeg[l], st);
+      // compressed levels have strictly ascending rows by construction
+      const bool simple = l > 0 || s.sorted_rows;
+      best_moves(c, G[l], lam.p, lam.q, *prm, l, 0, C, BMShape{maxdeg[l], !wide, true, simple}, st);
       ms_bm += std::chrono::duration<double, std::milli>(clk::now() - a).count();
       cs.iters_coarsen[l] = st.iterations;
       cs.moves_total += st.moves;
@@ -556,7 +566,7 @@ lcc_status lcc_cluster(lcc_ctx *ctx, const lcc_graph *g, lcc_lambda lam, const l
       if (prm->refine) {
         lcc_bm_stats st;
         auto a = clk::now();
-        best_moves(c, G[l], lam.p, lam.q, *prm, l, 1, C, false, maxdeg[l], st);
+        best_moves(c, G[l], lam.p, lam.q, *prm, l, 1, C, BMShape{maxdeg[l], !wide, false, false}, st);
         ms_bm += std::chrono::duration<double, std::milli>(clk::now() - a).count();
         cs.iters_refine[l] = st.iterations;
         cs.moves_total += st.moves;

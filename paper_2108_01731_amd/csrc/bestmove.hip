@@ -2,21 +2,28 @@
 //
 // One iteration = S synchronous sub-rounds.  For each iteration the active
 // vertices are partitioned into (sub-round, degree bin) buckets; every
-// sub-round then runs one aggregation kernel per non-empty degree bin and one
-// apply kernel:
+// sub-round then runs one aggregation kernel per non-empty degree bin, one
+// apply kernel and one isolation kernel:
 //
-//   aggregate  a group of G lanes per vertex streams the vertex's CSR row
-//              (coalesced col / weight reads), gathers C[u], and sums the
-//              weight per neighbor cluster in an LDS open-addressing hash
-//              (a global-memory hash for vertices above 2047 neighbors).  It
-//              then scores every distinct cluster against the snapshot
-//              (int64: q*w - p*k_v*K_X), reduces (score desc, id asc) across
-//              the group, decides, writes D[v], and for a mover marks its
-//              neighbors in the next frontier.
+//   aggregate  the vertex's CSR row is streamed (coalesced col / weight
+//              reads), C[u] gathered and the weight summed per neighbor
+//              cluster in an open-addressing hash table; every distinct
+//              cluster is then scored against the snapshot (int64:
+//              q*w - p*k_v*K_X), the best (score desc, id asc) is reduced
+//              across the lanes, the decision written to D[v], and a mover
+//              marks its neighbors in the next frontier.  Degree bins pick the
+//              shape: 8/16/32/64-lane groups with a private LDS table (degree
+//              < 256), a block per vertex with a degree-sized table in up to
+//              160 KB of LDS, and a 1024-thread block with a global-memory
+//              table for the rare rows beyond that.
 //   apply      movers update C and the cluster totals K / sizes with int64 /
-//              int32 atomics (integer adds commute, so the result does not
-//              depend on their order); isolating vertices are collected and
-//              handed the ascending empty ids by a guarded scan-and-pair pass.
+//              int32 atomics (integer adds commute, so the order of the
+//              atomics never matters); a vertex v that isolates moves to the
+//              fresh id n + v (a vertex is in one sub-round per iteration, so
+//              the id is unused within the iteration).
+//
+// At the end of an iteration in which someone isolated, the non-empty fresh
+// clusters are renamed, ascending, to the ascending empty ids in [0, n).
 //
 // Nothing in a sub-round reads what the same sub-round writes: aggregation
 // reads C, K, cnt and writes only D / flags / counters; apply runs after it.
@@ -26,20 +33,26 @@
 namespace lcc {
 
 constexpr int BM_NT = 256;
-constexpr int NBINS = 7;
+constexpr int WIDE_NT = 1024;
+constexpr int NBINS = 8;
+constexpr int NSPREAD = 8;   // counter copies per launch (spreads same-address atomics)
+constexpr int NCTR = 4;      // movers, candidates, arcs of movers, capacity errors
 constexpr int32_t ISO_ID = INT32_MAX;  // ranks after every real cluster id
+constexpr int MID_SLOTS = 4096;        // table of the block-per-vertex bin (degree < 2048)
 
-// Largest degree each bin accepts; bins 0-5 hash in LDS with >= 2(deg+1) slots.
-__host__ __device__ constexpr int64_t bin_limit(int b) {
-  return b == 0 ? 7 : b == 1 ? 15 : b == 2 ? 31 : b == 3 ? 63 : b == 4 ? 255 : b == 5 ? 2047 : INT64_MAX;
+// Largest degree of each bin; bin 6's limit depends on the LDS size and the
+// accumulator width and is passed at run time.
+__host__ __device__ constexpr int64_t bin_limit_fixed(int b) {
+  return b == 0 ? 7 : b == 1 ? 15 : b == 2 ? 31 : b == 3 ? 63 : b == 4 ? 255 : 2047;
 }
-__host__ __device__ inline int bin_of(int64_t deg) {
-  int b = 0;
-  while (b < NBINS - 1 && deg > bin_limit(b)) b++;
-  return b;
+__host__ __device__ inline int bin_of(int64_t deg, int64_t wide_max) {
+  if (deg <= 2047) {
+    int b = 0;
+    while (deg > bin_limit_fixed(b)) b++;
+    return b;
+  }
+  return deg <= wide_max ? 6 : 7;
 }
-
-__device__ __forceinline__ int64_t cdiv_dev(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 struct AggArgs {
   const int64_t *off;
@@ -55,10 +68,10 @@ struct AggArgs {
   int64_t count;
   int32_t *D;
   uint8_t *next_flag;  // nullptr: frontier = all vertices, no marking
-  int64_t *ctr;        // [0] movers, [1] candidates, [2] arcs of movers, [3] capacity errors
-  int32_t *gkeys;      // global hash (bin 6)
+  int64_t *ctr;        // NSPREAD x NCTR counters of this launch
+  int32_t *gkeys;      // global tables (bin 7)
   int64_t *gvals;
-  int64_t gcap;
+  int64_t hcap;        // table capacity in slots (dynamic-LDS or global bins)
 };
 
 // (score, id) order: higher score first, then lower id.
@@ -66,15 +79,22 @@ __device__ __forceinline__ bool better(int64_t s, int32_t id, int64_t bs, int32_
   return s > bs || (s == bs && id < bid);
 }
 
-template <int H> __device__ __forceinline__ uint32_t slot_of(int32_t X) {
-  constexpr int LOG = __builtin_ctz(H);
-  return ((uint32_t)X * 0x9E3779B1u) >> (32 - LOG);
+// Multiplicative hash reduced to [0, H) (H need not be a power of two).
+__device__ __forceinline__ uint32_t slot_of(int32_t X, uint32_t H) {
+  return (uint32_t)(((uint64_t)((uint32_t)X * 0x9E3779B1u) * (uint64_t)H) >> 32);
 }
 
-// Adds w to key X in an LDS table of H slots (keys -1 = empty).
-template <int H, class Acc>
-__device__ __forceinline__ void lds_insert(int32_t *keys, Acc *vals, int32_t X, int64_t w) {
-  uint32_t h = slot_of<H>(X);
+__device__ __forceinline__ uint32_t pow2_at_least(int64_t x) {
+  uint32_t h = 1;
+  while ((int64_t)h < x) h <<= 1;
+  return h;
+}
+
+// Adds w to key X in an LDS table of H slots (keys -1 = empty).  The caller
+// guarantees fewer distinct keys than slots.
+template <class Acc>
+__device__ __forceinline__ void lds_insert(int32_t *keys, Acc *vals, uint32_t H, int32_t X, int64_t w) {
+  uint32_t h = slot_of(X, H);
   while (true) {
     int32_t cur = keys[h];
     if (cur == -1) {
@@ -90,13 +110,12 @@ __device__ __forceinline__ void lds_insert(int32_t *keys, Acc *vals, int32_t X, 
       }
       return;
     }
-    h = (h + 1) & (H - 1);
+    h = (h + 1 == H) ? 0 : h + 1;
   }
 }
 
-// Decision from the reduced group results (identical in every lane).
-__device__ __forceinline__ int32_t decide(int64_t best_s, int32_t best_id, int64_t stay, bool iso_ok,
-                                          int32_t c) {
+// Decision from the reduced results (identical in every lane of the group).
+__device__ __forceinline__ int32_t decide(int64_t best_s, int32_t best_id, int64_t stay, bool iso_ok, int32_t c) {
   if (iso_ok && (best_s == INT64_MIN || 0 > best_s)) {
     best_s = 0;
     best_id = ISO_ID;
@@ -105,9 +124,11 @@ __device__ __forceinline__ int32_t decide(int64_t best_s, int32_t best_id, int64
   return c;
 }
 
-// Block-wide aggregation of the three counters, one atomic each per block.
+// Block-wide sum of the counters; one atomic per counter per block, spread
+// over NSPREAD copies.
+template <int NT>
 __device__ __forceinline__ void flush_counters(int64_t *ctr, int64_t movers, int64_t cands, int64_t marcs) {
-  __shared__ int64_t red[3][BM_NT / WAVE];
+  __shared__ int64_t red[3][NT / WAVE];
   movers = wave_sum(movers);
   cands = wave_sum(cands);
   marcs = wave_sum(marcs);
@@ -120,29 +141,62 @@ __device__ __forceinline__ void flush_counters(int64_t *ctr, int64_t movers, int
   __syncthreads();
   if (threadIdx.x < 3) {
     int64_t s = 0;
-    for (int i = 0; i < BM_NT / WAVE; i++) s += red[threadIdx.x][i];
-    if (s) atomic_add_i64(&ctr[threadIdx.x], s);
+    for (int i = 0; i < NT / WAVE; i++) s += red[threadIdx.x][i];
+    if (s) atomic_add_i64(&ctr[(blockIdx.x % NSPREAD) * NCTR + threadIdx.x], s);
   }
 }
 
-// G lanes per vertex (G <= 64, inside one wavefront), H LDS slots per vertex.
-template <int G, int H, int WK>
-__global__ __launch_bounds__(BM_NT) void k_bm_aggregate(AggArgs a) {
-  using Acc = typename std::conditional<(WK == LCC_WT_UNIT || WK == LCC_WT_I16), int32_t, int64_t>::type;
+// Reduces (best score, best id, own-cluster weight) over a block of NT
+// threads; the result is valid in thread 0.
+template <int NT>
+__device__ __forceinline__ void block_best(int64_t &best_s, int32_t &best_id, int64_t &wc) {
+#pragma unroll
+  for (int o = WAVE / 2; o > 0; o >>= 1) {
+    int64_t os = __shfl_xor(best_s, o, WAVE);
+    int32_t oid = __shfl_xor(best_id, o, WAVE);
+    if (better(os, oid, best_s, best_id)) {
+      best_s = os;
+      best_id = oid;
+    }
+    wc += __shfl_xor(wc, o, WAVE);
+  }
+  __shared__ int64_t rs[NT / WAVE];
+  __shared__ int32_t rid[NT / WAVE];
+  __shared__ int64_t rw[NT / WAVE];
+  const int w = threadIdx.x / WAVE;
+  if (lane_id() == 0) {
+    rs[w] = best_s;
+    rid[w] = best_id;
+    rw[w] = wc;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < NT / WAVE; i++) {
+      if (better(rs[i], rid[i], best_s, best_id)) {
+        best_s = rs[i];
+        best_id = rid[i];
+      }
+      wc += rw[i];
+    }
+  }
+}
+
+// ---------------------------------------------------------- lane groups
+
+// G lanes per vertex (G <= 64, inside one wavefront), a private LDS table of
+// up to HMAX slots per vertex (2G slots when HMAX == 2G: one arc per lane).
+template <int G, int HMAX, int WK, bool A32>
+__global__ __launch_bounds__(BM_NT) void k_bm_group(AggArgs a) {
+  using Acc = typename std::conditional<A32, int32_t, int64_t>::type;
   constexpr int GPB = BM_NT / G;
-  __shared__ int32_t hk[GPB * H];
-  __shared__ Acc hv[GPB * H];
+  constexpr bool ONE_PASS = HMAX == 2 * G;
+  __shared__ int32_t hk[GPB * HMAX];
+  __shared__ Acc hv[GPB * HMAX];
   const int t = threadIdx.x, grp = t / G, gl = t % G;
   const int64_t gi = (int64_t)blockIdx.x * GPB + grp;
   const bool valid = gi < a.count;
-  int32_t *keys = hk + grp * H;
-  Acc *vals = hv + grp * H;
-#pragma unroll
-  for (int j = gl; j < H; j += G) {
-    keys[j] = -1;
-    vals[j] = 0;
-  }
-  __syncthreads();
+  int32_t *keys = hk + grp * HMAX;
+  Acc *vals = hv + grp * HMAX;
   int32_t v = 0, c = 0;
   int64_t beg = 0, end = 0;
   if (valid) {
@@ -150,29 +204,66 @@ __global__ __launch_bounds__(BM_NT) void k_bm_aggregate(AggArgs a) {
     beg = a.off[v];
     end = a.off[v + 1];
     c = a.C[v];
-    if (gl == 0) lds_insert<H, Acc>(keys, vals, c, 0);
-    for (int64_t e = beg + gl; e < end; e += G) {
-      int32_t X = a.C[a.col[e]];
-      lds_insert<H, Acc>(keys, vals, X, load_w<WK>(a.wt, e));
+  }
+  uint32_t H = HMAX;
+  if constexpr (!ONE_PASS) {
+    H = pow2_at_least(2 * (end - beg + 1));
+    if (H > (uint32_t)HMAX) H = HMAX;
+  }
+  for (uint32_t j = gl; j < H; j += G) {
+    keys[j] = -1;
+    vals[j] = 0;
+  }
+  // loads the decision needs, issued before the row is walked
+  int64_t kv = 0, Kc = 0;
+  int32_t cntc = 0;
+  if (valid) {
+    kv = a.k[v];
+    Kc = a.K[c];
+    cntc = a.cnt[c];
+  }
+  __syncthreads();
+  int32_t u0 = -1;
+  if (valid) {
+    if (gl == 0) lds_insert<Acc>(keys, vals, H, c, 0);
+    if constexpr (ONE_PASS) {
+      const int64_t e = beg + gl;
+      if (e < end) {
+        u0 = a.col[e];
+        lds_insert<Acc>(keys, vals, H, a.C[u0], load_w<WK>(a.wt, e));
+      }
+    } else {
+      for (int64_t base = beg + gl; base < end; base += 4 * G) {
+        int32_t u[4], X[4];
+        int64_t w[4];
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+          const int64_t e = base + j * G;
+          u[j] = e < end ? a.col[e] : -1;
+          w[j] = e < end ? load_w<WK>(a.wt, e) : 0;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; j++) X[j] = u[j] >= 0 ? a.C[u[j]] : -1;
+#pragma unroll
+        for (int j = 0; j < 4; j++)
+          if (X[j] >= 0) lds_insert<Acc>(keys, vals, H, X[j], w[j]);
+      }
     }
   }
   __syncthreads();
   int64_t best_s = INT64_MIN, wc = 0, ncand = 0;
   int32_t best_id = ISO_ID;
-  int64_t kv = 0, pk = 0;
+  const int64_t pk = a.p * kv;
   if (valid) {
-    kv = a.k[v];
-    pk = a.p * kv;
-#pragma unroll
-    for (int j = gl; j < H; j += G) {
-      int32_t X = keys[j];
+    for (uint32_t j = gl; j < H; j += G) {
+      const int32_t X = keys[j];
       if (X < 0) continue;
       ncand++;
-      int64_t wx = (int64_t)vals[j];
+      const int64_t wx = (int64_t)vals[j];
       if (X == c) {
         wc = wx;
       } else {
-        int64_t s = a.q * wx - pk * a.K[X];
+        const int64_t s = a.q * wx - pk * a.K[X];
         if (better(s, X, best_s, best_id)) {
           best_s = s;
           best_id = X;
@@ -192,89 +283,86 @@ __global__ __launch_bounds__(BM_NT) void k_bm_aggregate(AggArgs a) {
   }
   bool moved = false;
   if (valid) {
-    int64_t stay = a.q * wc - pk * (a.K[c] - kv);
-    bool iso_ok = a.allow_iso && a.cnt[c] >= 2;
-    int32_t d = decide(best_s, best_id, stay, iso_ok, c);
+    const int64_t stay = a.q * wc - pk * (Kc - kv);
+    const int32_t d = decide(best_s, best_id, stay, a.allow_iso && cntc >= 2, c);
     moved = d != c;
     if (gl == 0) a.D[v] = d;
-    if (moved && a.next_flag)
-      for (int64_t e = beg + gl; e < end; e += G) a.next_flag[a.col[e]] = 1;
+    if (moved && a.next_flag) {
+      if constexpr (ONE_PASS) {
+        if (u0 >= 0) a.next_flag[u0] = 1;
+      } else {
+        for (int64_t e = beg + gl; e < end; e += G) a.next_flag[a.col[e]] = 1;
+      }
+    }
   }
-  flush_counters(a.ctr, (moved && gl == 0) ? 1 : 0, ncand, (moved && gl == 0) ? end - beg : 0);
+  flush_counters<BM_NT>(a.ctr, (moved && gl == 0) ? 1 : 0, ncand, (moved && gl == 0) ? end - beg : 0);
 }
 
-// Block per vertex, 4096-slot LDS hash (degrees 256..2047).
-template <int WK>
-__global__ __launch_bounds__(BM_NT) void k_bm_aggregate_block(AggArgs a) {
-  using Acc = typename std::conditional<(WK == LCC_WT_UNIT || WK == LCC_WT_I16), int32_t, int64_t>::type;
-  constexpr int H = 4096;
-  __shared__ int32_t keys[H];
-  __shared__ Acc vals[H];
-  __shared__ int64_t rs[BM_NT / WAVE];
-  __shared__ int32_t rid[BM_NT / WAVE];
-  __shared__ int64_t rw[BM_NT / WAVE];
+// ------------------------------------------------------- block per vertex
+
+// One vertex per block, a table of min(hcap, pow2 >= 2(deg+1)) slots in
+// dynamic LDS (keys then values).  The host admits a vertex only when its
+// distinct clusters (<= deg + 1) fill at most 70% of hcap.
+template <int NT, int WK, bool A32>
+__global__ __launch_bounds__(NT) void k_bm_wide(AggArgs a) {
+  using Acc = typename std::conditional<A32, int32_t, int64_t>::type;
+  extern __shared__ __align__(16) unsigned char smem[];
+  int32_t *keys = reinterpret_cast<int32_t *>(smem);
+  Acc *vals = reinterpret_cast<Acc *>(smem + ((a.hcap * 4 + 15) & ~15ll));
   __shared__ int32_t sh_d;
-  const int t = threadIdx.x, w = t / WAVE;
-  const int64_t gi = blockIdx.x;
-  for (int j = t; j < H; j += BM_NT) {
+  const int t = threadIdx.x;
+  const int32_t v = a.list[blockIdx.x];
+  const int64_t beg = a.off[v], end = a.off[v + 1];
+  const int32_t c = a.C[v];
+  uint32_t H = pow2_at_least(2 * (end - beg + 1));
+  if (H > (uint32_t)a.hcap) H = (uint32_t)a.hcap;
+  for (uint32_t j = t; j < H; j += NT) {
     keys[j] = -1;
     vals[j] = 0;
   }
+  const int64_t kv = a.k[v], Kc = a.K[c];
+  const int32_t cntc = a.cnt[c];
   __syncthreads();
-  const int32_t v = a.list[gi];
-  const int64_t beg = a.off[v], end = a.off[v + 1];
-  const int32_t c = a.C[v];
-  if (t == 0) lds_insert<H, Acc>(keys, vals, c, 0);
-  for (int64_t e = beg + t; e < end; e += BM_NT) lds_insert<H, Acc>(keys, vals, a.C[a.col[e]], load_w<WK>(a.wt, e));
+  if (t == 0) lds_insert<Acc>(keys, vals, H, c, 0);
+  for (int64_t base = beg + t; base < end; base += 4 * NT) {
+    int32_t u[4], X[4];
+    int64_t w[4];
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+      const int64_t e = base + j * NT;
+      u[j] = e < end ? a.col[e] : -1;
+      w[j] = e < end ? load_w<WK>(a.wt, e) : 0;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; j++) X[j] = u[j] >= 0 ? a.C[u[j]] : -1;
+#pragma unroll
+    for (int j = 0; j < 4; j++)
+      if (X[j] >= 0) lds_insert<Acc>(keys, vals, H, X[j], w[j]);
+  }
   __syncthreads();
-  const int64_t kv = a.k[v], pk = a.p * kv;
+  const int64_t pk = a.p * kv;
   int64_t best_s = INT64_MIN, wc = 0, cands = 0;
   int32_t best_id = ISO_ID;
-  for (int j = t; j < H; j += BM_NT) {
-    int32_t X = keys[j];
+  for (uint32_t j = t; j < H; j += NT) {
+    const int32_t X = keys[j];
     if (X < 0) continue;
     cands++;
-    int64_t wx = (int64_t)vals[j];
+    const int64_t wx = (int64_t)vals[j];
     if (X == c) {
       wc = wx;
     } else {
-      int64_t s = a.q * wx - pk * a.K[X];
+      const int64_t s = a.q * wx - pk * a.K[X];
       if (better(s, X, best_s, best_id)) {
         best_s = s;
         best_id = X;
       }
     }
   }
-#pragma unroll
-  for (int o = WAVE / 2; o > 0; o >>= 1) {
-    int64_t os = __shfl_xor(best_s, o, WAVE);
-    int32_t oid = __shfl_xor(best_id, o, WAVE);
-    if (better(os, oid, best_s, best_id)) {
-      best_s = os;
-      best_id = oid;
-    }
-    wc += __shfl_xor(wc, o, WAVE);
-  }
-  if (lane_id() == 0) {
-    rs[w] = best_s;
-    rid[w] = best_id;
-    rw[w] = wc;
-  }
-  __syncthreads();
+  block_best<NT>(best_s, best_id, wc);
   int64_t movers = 0, marcs = 0;
   if (t == 0) {
-    int64_t bs = rs[0], ww = rw[0];
-    int32_t bi = rid[0];
-    for (int i = 1; i < BM_NT / WAVE; i++) {
-      if (better(rs[i], rid[i], bs, bi)) {
-        bs = rs[i];
-        bi = rid[i];
-      }
-      ww += rw[i];
-    }
-    int64_t stay = a.q * ww - pk * (a.K[c] - kv);
-    bool iso_ok = a.allow_iso && a.cnt[c] >= 2;
-    int32_t d = decide(bs, bi, stay, iso_ok, c);
+    const int64_t stay = a.q * wc - pk * (Kc - kv);
+    const int32_t d = decide(best_s, best_id, stay, a.allow_iso && cntc >= 2, c);
     a.D[v] = d;
     sh_d = d;
     if (d != c) {
@@ -284,260 +372,302 @@ __global__ __launch_bounds__(BM_NT) void k_bm_aggregate_block(AggArgs a) {
   }
   __syncthreads();
   if (sh_d != c && a.next_flag)
-    for (int64_t e = beg + t; e < end; e += BM_NT) a.next_flag[a.col[e]] = 1;
-  flush_counters(a.ctr, movers, cands, marcs);
+    for (int64_t e = beg + t; e < end; e += NT) a.next_flag[a.col[e]] = 1;
+  flush_counters<NT>(a.ctr, movers, cands, marcs);
 }
 
-// Block per vertex (grid-stride), hash table in this block's global region.
-template <int WK>
-__global__ __launch_bounds__(BM_NT) void k_bm_aggregate_global(AggArgs a) {
-  __shared__ int64_t rs[BM_NT / WAVE];
-  __shared__ int32_t rid[BM_NT / WAVE];
-  __shared__ int64_t rw[BM_NT / WAVE];
-  __shared__ int32_t sh_d;
-  int32_t *keys = a.gkeys + (int64_t)blockIdx.x * a.gcap;
-  int64_t *vals = a.gvals + (int64_t)blockIdx.x * a.gcap;
-  const int t = threadIdx.x, w = t / WAVE;
-  int64_t movers = 0, cands = 0, marcs = 0;
-  for (int64_t gi = blockIdx.x; gi < a.count; gi += gridDim.x) {
-    const int32_t v = a.list[gi];
-    const int64_t beg = a.off[v], end = a.off[v + 1];
-    const int32_t c = a.C[v];
-    int64_t cap = 1;
-    while (cap < 2 * (end - beg + 1)) cap <<= 1;
-    if (cap > a.gcap) {  // the host sized the table from the maximum degree
-      if (t == 0) {
-        a.D[v] = c;
-        atomic_add_i64(&a.ctr[3], 1);
-      }
-      continue;
-    }
-    const uint32_t mask = (uint32_t)(cap - 1);
-    int lg = 0;
-    while ((1ll << lg) < cap) lg++;
-    for (int64_t j = t; j < cap; j += BM_NT) {
-      keys[j] = -1;
-      vals[j] = 0;
-    }
-    __threadfence();
-    __syncthreads();
-    auto insert = [&](int32_t X, int64_t wgt) {
-      uint32_t h = lg ? (((uint32_t)X * 0x9E3779B1u) >> (32 - lg)) : 0u;
-      while (true) {
-        int32_t cur = __hip_atomic_load(&keys[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (cur == -1) {
-          cur = atomicCAS(&keys[h], -1, X);
-          if (cur == -1) cur = X;
-        }
-        if (cur == X) {
-          if (wgt) atomic_add_i64(&vals[h], wgt);
-          return;
-        }
-        h = (h + 1) & mask;
-      }
-    };
-    if (t == 0) insert(c, 0);
-    for (int64_t e = beg + t; e < end; e += BM_NT) insert(a.C[a.col[e]], load_w<WK>(a.wt, e));
-    __threadfence();
-    __syncthreads();
-    const int64_t kv = a.k[v], pk = a.p * kv;
-    int64_t best_s = INT64_MIN, wc = 0;
-    int32_t best_id = ISO_ID;
-    for (int64_t j = t; j < cap; j += BM_NT) {
-      int32_t X = __hip_atomic_load(&keys[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (X < 0) continue;
-      cands++;
-      int64_t wx = __hip_atomic_load(&vals[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (X == c) {
-        wc = wx;
-      } else {
-        int64_t s = a.q * wx - pk * a.K[X];
-        if (better(s, X, best_s, best_id)) {
-          best_s = s;
-          best_id = X;
-        }
-      }
+// ------------------------------------------------ first iteration, singletons
+
+// First sub-round of a coarsening Best-Moves (C = identity) on rows without
+// repeated neighbors: every neighbor u is its own cluster with K_u = k_u, so
+// no aggregation is needed.  The best target is the neighbor maximizing
+// q*w(v,u) - p*k_v*k_u (ties to the lowest id); staying scores 0 and
+// isolation is not available (|c| = 1).  G lanes per vertex, or the whole
+// block when G == NT.
+template <int G, int NT, int WK>
+__global__ __launch_bounds__(NT) void k_bm_single(AggArgs a) {
+  constexpr int GPB = NT / G;
+  __shared__ int32_t sh_d[GPB];
+  const int t = threadIdx.x, grp = t / G, gl = t % G;
+  const int64_t gi = (int64_t)blockIdx.x * GPB + grp;
+  const bool valid = gi < a.count;
+  int32_t v = 0;
+  int64_t beg = 0, end = 0, kv = 0;
+  if (valid) {
+    v = a.list[gi];
+    beg = a.off[v];
+    end = a.off[v + 1];
+    kv = a.k[v];
+  }
+  const int64_t pk = a.p * kv;
+  int64_t best_s = INT64_MIN, wc = 0;
+  int32_t best_id = ISO_ID;
+  for (int64_t base = beg + gl; base < end; base += 4 * G) {
+    int32_t u[4];
+    int64_t w[4], ku[4];
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+      const int64_t e = base + j * G;
+      u[j] = e < end ? a.col[e] : -1;
+      w[j] = e < end ? load_w<WK>(a.wt, e) : 0;
     }
 #pragma unroll
-    for (int o = WAVE / 2; o > 0; o >>= 1) {
+    for (int j = 0; j < 4; j++) ku[j] = u[j] >= 0 ? a.k[u[j]] : 0;
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+      if (u[j] < 0) continue;
+      const int64_t sc = a.q * w[j] - pk * ku[j];
+      if (better(sc, u[j], best_s, best_id)) {
+        best_s = sc;
+        best_id = u[j];
+      }
+    }
+  }
+  int32_t d = v;
+  if constexpr (G < NT) {
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) {
       int64_t os = __shfl_xor(best_s, o, WAVE);
       int32_t oid = __shfl_xor(best_id, o, WAVE);
       if (better(os, oid, best_s, best_id)) {
         best_s = os;
         best_id = oid;
       }
-      wc += __shfl_xor(wc, o, WAVE);
     }
-    if (lane_id() == 0) {
-      rs[w] = best_s;
-      rid[w] = best_id;
-      rw[w] = wc;
-    }
+    d = decide(best_s, best_id, 0, false, v);
+  } else {
+    block_best<NT>(best_s, best_id, wc);
+    if (t == 0) sh_d[0] = decide(best_s, best_id, 0, false, v);
     __syncthreads();
-    if (t == 0) {
-      int64_t bs = rs[0], ww = rw[0];
-      int32_t bi = rid[0];
-      for (int i = 1; i < BM_NT / WAVE; i++) {
-        if (better(rs[i], rid[i], bs, bi)) {
-          bs = rs[i];
-          bi = rid[i];
-        }
-        ww += rw[i];
-      }
-      int64_t stay = a.q * ww - pk * (a.K[c] - kv);
-      bool iso_ok = a.allow_iso && a.cnt[c] >= 2;
-      int32_t d = decide(bs, bi, stay, iso_ok, c);
-      a.D[v] = d;
-      sh_d = d;
-      if (d != c) {
-        movers++;
-        marcs += end - beg;
-      }
-    }
-    __syncthreads();
-    if (sh_d != c && a.next_flag)
-      for (int64_t e = beg + t; e < end; e += BM_NT) a.next_flag[a.col[e]] = 1;
-    __syncthreads();
+    d = sh_d[0];
   }
-  flush_counters(a.ctr, movers, cands, marcs);
+  const bool moved = valid && d != v;
+  if (valid && gl == 0) a.D[v] = d;
+  if (moved && a.next_flag)
+    for (int64_t e = beg + gl; e < end; e += G) a.next_flag[a.col[e]] = 1;
+  flush_counters<NT>(a.ctr, (moved && gl == 0) ? 1 : 0, (valid && gl == 0) ? end - beg + 1 : 0,
+                     (moved && gl == 0) ? end - beg : 0);
 }
 
-// Applies the sub-round's decisions.
+// ------------------------------------------------------ flat hub aggregation
+
+// Rows too wide for LDS are aggregated arc-parallel: the rows of the bin are
+// laid end to end (astart = prefix of degrees) and every wave takes a
+// contiguous stretch of B7_WAVE_ARCS arcs, so a 400k-neighbor row is spread
+// over hundreds of waves.  Each row owns a table of cap = pow2 >= 2(deg+1)
+// slots in global memory (tstart = prefix of capacities).  A separate kernel
+// then scores every row's table.
+constexpr int B7_NT = 256;
+constexpr int B7_PER_LANE = 8;
+constexpr int64_t B7_WAVE_ARCS = (int64_t)WAVE * B7_PER_LANE;
+
+__global__ void k_b7_prep(const int32_t *__restrict__ list, int64_t n7, const int64_t *__restrict__ off,
+                          int64_t *__restrict__ deg, int64_t *__restrict__ cap) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n7; i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t v = list[i];
+    const int64_t d = off[v + 1] - off[v];
+    deg[i] = d;
+    cap[i] = pow2_at_least(2 * (d + 1));
+  }
+}
+
+__global__ void k_b7_clear(int32_t *__restrict__ keys, int64_t *__restrict__ vals, const int64_t *__restrict__ T) {
+  const int64_t total = *T;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < total; j += (int64_t)gridDim.x * blockDim.x) {
+    keys[j] = -1;
+    vals[j] = 0;
+  }
+}
+
+// Adds w to key X in a global table of H slots (keys -1 = empty).  Keys and
+// values only change through atomics inside this kernel.
+__device__ __forceinline__ void global_insert(int32_t *keys, int64_t *vals, uint32_t H, int32_t X, int64_t w) {
+  uint32_t h = slot_of(X, H);
+  while (true) {
+    int32_t cur = __hip_atomic_load(&keys[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (cur == -1) {
+      cur = atomicCAS(&keys[h], -1, X);
+      if (cur == -1) cur = X;
+    }
+    if (cur == X) {
+      if (w) atomic_add_i64(&vals[h], w);
+      return;
+    }
+    h = (h + 1 == H) ? 0 : h + 1;
+  }
+}
+
+// astart / tstart hold n7 + 1 entries (the last = totals).
+template <int WK>
+__global__ __launch_bounds__(B7_NT) void k_b7_insert(AggArgs a, int64_t n7, const int64_t *__restrict__ astart,
+                                                     const int64_t *__restrict__ tstart) {
+  const int lane = lane_id();
+  const int64_t A = astart[n7];
+  const int64_t wave = ((int64_t)blockIdx.x * B7_NT + threadIdx.x) / WAVE;
+  const int64_t nwaves = ((int64_t)gridDim.x * B7_NT) / WAVE;
+  for (int64_t base = wave * B7_WAVE_ARCS; base < A; base += nwaves * B7_WAVE_ARCS) {
+    // row holding the first arc of the stretch
+    int64_t i = 0;
+    if (lane == 0) {
+      int64_t lo = 0, hi = n7 - 1;
+      while (lo < hi) {
+        int64_t mid = (lo + hi + 1) >> 1;
+        if (astart[mid] <= base) lo = mid;
+        else hi = mid - 1;
+      }
+      i = lo;
+    }
+    i = __shfl(i, 0, WAVE);
+    int32_t v = -1;
+    int64_t a0 = 0, a1 = 0, e0 = 0, t0 = 0;
+    uint32_t H = 0;
+    for (int j = 0; j < B7_PER_LANE; j++) {
+      const int64_t x = base + (int64_t)j * WAVE + lane;
+      if (x >= A) break;
+      while (x >= astart[i + 1]) i++;
+      if (a0 != astart[i] || v < 0) {
+        v = a.list[i];
+        a0 = astart[i];
+        a1 = astart[i + 1];
+        e0 = a.off[v];
+        t0 = tstart[i];
+        H = (uint32_t)(tstart[i + 1] - t0);
+      }
+      const int64_t e = e0 + (x - a0);
+      if (x == a0) global_insert(a.gkeys + t0, a.gvals + t0, H, a.C[v], 0);
+      global_insert(a.gkeys + t0, a.gvals + t0, H, a.C[a.col[e]], load_w<WK>(a.wt, e));
+      (void)a1;
+    }
+  }
+}
+
+// One block per row: scores the row's table (written by the previous kernel).
+__global__ __launch_bounds__(B7_NT) void k_b7_score(AggArgs a, const int64_t *__restrict__ tstart) {
+  __shared__ int32_t sh_d;
+  const int t = threadIdx.x;
+  const int64_t i = blockIdx.x;
+  const int32_t v = a.list[i];
+  const int64_t beg = a.off[v], end = a.off[v + 1];
+  const int32_t c = a.C[v];
+  const int64_t kv = a.k[v], Kc = a.K[c];
+  const int32_t cntc = a.cnt[c];
+  const int64_t t0 = tstart[i], H = tstart[i + 1] - t0;
+  const int32_t *keys = a.gkeys + t0;
+  const int64_t *vals = a.gvals + t0;
+  const int64_t pk = a.p * kv;
+  int64_t best_s = INT64_MIN, wc = 0, cands = 0;
+  int32_t best_id = ISO_ID;
+  for (int64_t j = t; j < H; j += B7_NT) {
+    const int32_t X = keys[j];
+    if (X < 0) continue;
+    cands++;
+    const int64_t wx = vals[j];
+    if (X == c) {
+      wc = wx;
+    } else {
+      const int64_t sc = a.q * wx - pk * a.K[X];
+      if (better(sc, X, best_s, best_id)) {
+        best_s = sc;
+        best_id = X;
+      }
+    }
+  }
+  block_best<B7_NT>(best_s, best_id, wc);
+  int64_t movers = 0, marcs = 0;
+  if (t == 0) {
+    const int64_t stay = a.q * wc - pk * (Kc - kv);
+    const int32_t d = decide(best_s, best_id, stay, a.allow_iso && cntc >= 2, c);
+    a.D[v] = d;
+    sh_d = d;
+    if (d != c) {
+      movers = 1;
+      marcs = end - beg;
+    }
+  }
+  __syncthreads();
+  if (sh_d != c && a.next_flag)
+    for (int64_t e = beg + t; e < end; e += B7_NT) a.next_flag[a.col[e]] = 1;
+  flush_counters<B7_NT>(a.ctr, movers, cands, marcs);
+}
+
+// -------------------------------------------------------------- apply
+
+// Applies the sub-round's decisions; an isolating vertex v takes the fresh
+// id n + v.
 __global__ __launch_bounds__(BM_NT) void k_bm_apply(const int32_t *__restrict__ list, int64_t count,
                                                     const int32_t *__restrict__ D, int32_t *__restrict__ C,
                                                     int64_t *__restrict__ K, int32_t *__restrict__ cnt,
-                                                    const int64_t *__restrict__ k, uint8_t *__restrict__ iso_flag,
+                                                    const int64_t *__restrict__ k, int64_t n,
                                                     int64_t *__restrict__ iso_ctr) {
   const int64_t i = (int64_t)blockIdx.x * BM_NT + threadIdx.x;
   int64_t niso = 0;
   if (i < count) {
     const int32_t v = list[i];
-    const int32_t d = D[v], c = C[v];
+    int32_t d = D[v];
+    const int32_t c = C[v];
     if (d != c) {
       const int64_t kv = k[v];
-      if (kv) atomic_add_i64(&K[c], -kv);
-      atomicSub(&cnt[c], 1);
       if (d < 0) {
-        C[v] = -1;
-        iso_flag[v] = 1;
+        d = (int32_t)(n + v);
         niso = 1;
-      } else {
-        if (kv) atomic_add_i64(&K[d], kv);
-        atomicAdd(&cnt[d], 1);
-        C[v] = d;
       }
+      if (kv) {
+        atomic_add_i64(&K[c], -kv);
+        atomic_add_i64(&K[d], kv);
+      }
+      atomicSub(&cnt[c], 1);
+      atomicAdd(&cnt[d], 1);
+      C[v] = d;
     }
   }
   niso = wave_sum(niso);
   if (lane_id() == 0 && niso) atomic_add_i64(iso_ctr, niso);
 }
 
-// --- isolation: the j-th isolated vertex (ascending) gets the j-th empty id.
-constexpr int ISO_TILE = CMP_TILE;
+// ------------------------------------------------ renaming fresh clusters
 
-__global__ __launch_bounds__(CMP_NT) void k_iso_count(const uint8_t *__restrict__ iso_flag,
-                                                      const int32_t *__restrict__ cnt, int64_t n,
-                                                      const int64_t *__restrict__ iso_ctr,
-                                                      int64_t *__restrict__ part) {
-  if (*iso_ctr == 0) return;
-  const int64_t base = (int64_t)blockIdx.x * ISO_TILE + (int64_t)threadIdx.x * CMP_IPT;
-  int64_t a = 0, b = 0;
-#pragma unroll
-  for (int i = 0; i < CMP_IPT; i++) {
-    int64_t x = base + i;
-    if (x < n) {
-      a += iso_flag[x] != 0;
-      b += cnt[x] == 0;
-    }
-  }
-  int64_t ta, tb;
-  (void)block_excl_scan<int64_t, CMP_NT>(a, &ta);
-  (void)block_excl_scan<int64_t, CMP_NT>(b, &tb);
-  if (threadIdx.x == 0) {
-    part[2 * blockIdx.x] = ta;
-    part[2 * blockIdx.x + 1] = tb;
+// fresh[t] = cluster n + t is non-empty; empty[x] = cluster x (< n) is empty.
+__global__ void k_fresh_flags(const int32_t *__restrict__ cnt, int64_t n, uint8_t *__restrict__ fresh,
+                              uint8_t *__restrict__ empty) {
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) {
+    fresh[x] = cnt[n + x] > 0;
+    empty[x] = cnt[x] == 0;
   }
 }
 
-// Single-block exclusive scan of the (isolated, empty) pairs per tile.
-__global__ __launch_bounds__(1024) void k_iso_scan(int64_t *part, int64_t nb, const int64_t *iso_ctr) {
-  if (*iso_ctr == 0) return;
-  __shared__ int64_t carry[2];
-  if (threadIdx.x == 0) carry[0] = carry[1] = 0;
-  __syncthreads();
-  for (int64_t s = 0; s < nb; s += 1024) {
-    int64_t i = s + threadIdx.x;
-    int64_t a = i < nb ? part[2 * i] : 0, b = i < nb ? part[2 * i + 1] : 0;
-    int64_t ta, tb;
-    int64_t pa = block_excl_scan<int64_t, 1024>(a, &ta);
-    int64_t pb = block_excl_scan<int64_t, 1024>(b, &tb);
-    if (i < nb) {
-      part[2 * i] = carry[0] + pa;
-      part[2 * i + 1] = carry[1] + pb;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      carry[0] += ta;
-      carry[1] += tb;
-    }
-    __syncthreads();
-  }
+// elist[r] = the r-th empty id, for the first T ranks.
+__global__ void k_empty_list(const uint8_t *__restrict__ empty, const int32_t *__restrict__ rank_e, int64_t n,
+                             const int32_t *__restrict__ T, int32_t *__restrict__ elist) {
+  const int32_t t = *T;
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x)
+    if (empty[x] && rank_e[x] < t) elist[rank_e[x]] = (int32_t)x;
 }
 
-__global__ __launch_bounds__(CMP_NT) void k_iso_lists(const uint8_t *__restrict__ iso_flag,
-                                                      const int32_t *__restrict__ cnt, int64_t n,
-                                                      const int64_t *__restrict__ iso_ctr,
-                                                      const int64_t *__restrict__ part,
-                                                      int32_t *__restrict__ iso_list,
-                                                      int32_t *__restrict__ empty_list) {
-  const int64_t niso = *iso_ctr;
-  if (niso == 0) return;
-  const int64_t base = (int64_t)blockIdx.x * ISO_TILE + (int64_t)threadIdx.x * CMP_IPT;
-  int64_t a = 0, b = 0;
-#pragma unroll
-  for (int i = 0; i < CMP_IPT; i++) {
-    int64_t x = base + i;
-    if (x < n) {
-      a += iso_flag[x] != 0;
-      b += cnt[x] == 0;
-    }
-  }
-  int64_t ta, tb;
-  int64_t pa = block_excl_scan<int64_t, CMP_NT>(a, &ta) + part[2 * blockIdx.x];
-  int64_t pb = block_excl_scan<int64_t, CMP_NT>(b, &tb) + part[2 * blockIdx.x + 1];
-#pragma unroll
-  for (int i = 0; i < CMP_IPT; i++) {
-    int64_t x = base + i;
-    if (x < n) {
-      if (iso_flag[x]) iso_list[pa++] = (int32_t)x;
-      if (cnt[x] == 0) {
-        if (pb < niso) empty_list[pb] = (int32_t)x;
-        pb++;
-      }
-    }
-  }
-}
-
-__global__ __launch_bounds__(BM_NT) void k_iso_pair(const int64_t *__restrict__ iso_ctr,
-                                                    const int32_t *__restrict__ iso_list,
-                                                    const int32_t *__restrict__ empty_list,
-                                                    int32_t *__restrict__ C, int64_t *__restrict__ K,
-                                                    int32_t *__restrict__ cnt, const int64_t *__restrict__ k,
-                                                    uint8_t *__restrict__ iso_flag, int64_t n,
-                                                    int64_t *__restrict__ err) {
-  const int64_t niso = *iso_ctr;
-  for (int64_t j = (int64_t)blockIdx.x * BM_NT + threadIdx.x; j < niso; j += (int64_t)gridDim.x * BM_NT) {
-    const int32_t v = iso_list[j], x = empty_list[j];
-    // by counting, at least niso ids are empty after the moves; a violation
-    // is reported instead of indexing out of range
-    if (v < 0 || (int64_t)v >= n || x < 0 || (int64_t)x >= n) {
+// The r-th non-empty fresh cluster takes the r-th empty id (totals moved).
+__global__ void k_fresh_move(const uint8_t *__restrict__ fresh, const int32_t *__restrict__ rank_f,
+                             const int32_t *__restrict__ elist, int64_t n, int64_t *__restrict__ K,
+                             int32_t *__restrict__ cnt, int32_t *__restrict__ newid, int64_t *__restrict__ err) {
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+    if (!fresh[t]) continue;
+    const int32_t x = elist[rank_f[t]];
+    // by counting there are enough empty ids; a violation is reported
+    // instead of indexing out of range
+    if (x < 0 || (int64_t)x >= n) {
       atomic_add_i64(err, 1);
       continue;
     }
-    C[v] = x;
-    K[x] = k[v];
-    cnt[x] = 1;
-    iso_flag[v] = 0;
+    newid[t] = x;
+    K[x] = K[n + t];
+    cnt[x] = cnt[n + t];
+    K[n + t] = 0;
+    cnt[n + t] = 0;
+  }
+}
+
+__global__ void k_fresh_relabel(int32_t *__restrict__ C, int64_t n, const int32_t *__restrict__ newid) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t c = C[v];
+    if (c >= n) C[v] = newid[c - n];
   }
 }
 
@@ -545,7 +675,7 @@ __global__ __launch_bounds__(BM_NT) void k_iso_pair(const int64_t *__restrict__ 
 
 __global__ __launch_bounds__(BM_NT) void k_part_count(const int32_t *__restrict__ list, int64_t na,
                                                       const int64_t *__restrict__ off, uint64_t h, int32_t S,
-                                                      uint16_t *__restrict__ bucket_of,
+                                                      int64_t wide_max, uint16_t *__restrict__ bucket_of,
                                                       int64_t *__restrict__ bcnt, int64_t *__restrict__ barcs) {
   extern __shared__ int64_t sm[];
   const int NB = S * NBINS;
@@ -557,7 +687,7 @@ __global__ __launch_bounds__(BM_NT) void k_part_count(const int32_t *__restrict_
     const int32_t v = list ? list[i] : (int32_t)i;
     const int64_t deg = off[v + 1] - off[v];
     const int s = (int)(mix64(h ^ (uint64_t)(int64_t)v) % (uint64_t)S);
-    const int b = s * NBINS + bin_of(deg);
+    const int b = s * NBINS + bin_of(deg, wide_max);
     bucket_of[i] = (uint16_t)b;
     atomicAdd(reinterpret_cast<unsigned long long *>(&lc[b]), 1ull);
     if (deg) atomicAdd(reinterpret_cast<unsigned long long *>(&la[b]), (unsigned long long)deg);
@@ -580,17 +710,20 @@ __global__ void k_part_starts(const int64_t *__restrict__ bcnt, int64_t *__restr
   }
 }
 
+// Order inside a bucket is whatever the atomics give: no result depends on
+// it (decisions read a fixed snapshot; apply adds commute; isolation ranks
+// by vertex id).
 __global__ __launch_bounds__(BM_NT) void k_part_scatter(const int32_t *__restrict__ list, int64_t na,
                                                         const uint16_t *__restrict__ bucket_of, int32_t S,
                                                         int64_t *__restrict__ cursor, int32_t *__restrict__ out) {
   extern __shared__ int64_t sm[];
   const int NB = S * NBINS;
-  int64_t *lc = sm;        // items of this block per bucket
+  int64_t *lc = sm;          // items of this block per bucket
   int64_t *lbase = sm + NB;  // reserved global position per bucket
   for (int i = threadIdx.x; i < NB; i += BM_NT) lc[i] = 0;
   __syncthreads();
   // each block owns one contiguous range of the list
-  const int64_t per = cdiv_dev(na, gridDim.x);
+  const int64_t per = cdiv(na, (int64_t)gridDim.x);
   const int64_t beg = (int64_t)blockIdx.x * per;
   const int64_t end = beg + per < na ? beg + per : na;
   for (int64_t i = beg + threadIdx.x; i < end; i += BM_NT)
@@ -623,85 +756,205 @@ __global__ void k_init_identity(const int64_t *__restrict__ k, int64_t *__restri
 namespace {
 
 struct AggLaunch {
-  int bin;
-  int64_t verts, arcs;
   size_t pending_idx;  // index into ctx.pending when timed
   int slot;
 };
 
-template <int WK>
+// Dynamic LDS for the wide kernels: keys (int32) then 16-byte aligned values.
+size_t wide_lds_bytes(int64_t slots, bool a32) {
+  return (size_t)((slots * 4 + 15) & ~15ll) + (size_t)slots * (a32 ? 4 : 8);
+}
+
+// Largest table (slots) that fits the per-block LDS beside the kernel's own
+// reduction arrays.
+int64_t wide_slots(const Ctx &c, bool a32) {
+  const int64_t budget = (int64_t)c.lds_per_block - 4096;
+  return (budget - 16) / (a32 ? 8 : 12);
+}
+
+// Raises a kernel's dynamic-LDS limit once per context.
+template <class F> void allow_lds(Ctx &c, F kernel, size_t bytes) {
+  const void *f = reinterpret_cast<const void *>(kernel);
+  for (const void *x : c.lds_raised)
+    if (x == f) return;
+  HIPCHECK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+  c.lds_raised.push_back(f);
+}
+
+template <int WK, bool A32>
 void launch_bin(Ctx &c, int bin, AggArgs a) {
   const int64_t cnt = a.count;
   switch (bin) {
     case 0:
-      hipLaunchKernelGGL((k_bm_aggregate<8, 16, WK>), dim3((unsigned)cdiv(cnt, BM_NT / 8)), dim3(BM_NT), 0,
+      hipLaunchKernelGGL((k_bm_group<8, 16, WK, A32>), dim3((unsigned)cdiv(cnt, BM_NT / 8)), dim3(BM_NT), 0,
                          c.stream, a);
       break;
     case 1:
-      hipLaunchKernelGGL((k_bm_aggregate<16, 32, WK>), dim3((unsigned)cdiv(cnt, BM_NT / 16)), dim3(BM_NT), 0,
+      hipLaunchKernelGGL((k_bm_group<16, 32, WK, A32>), dim3((unsigned)cdiv(cnt, BM_NT / 16)), dim3(BM_NT), 0,
                          c.stream, a);
       break;
     case 2:
-      hipLaunchKernelGGL((k_bm_aggregate<32, 64, WK>), dim3((unsigned)cdiv(cnt, BM_NT / 32)), dim3(BM_NT), 0,
+      hipLaunchKernelGGL((k_bm_group<32, 64, WK, A32>), dim3((unsigned)cdiv(cnt, BM_NT / 32)), dim3(BM_NT), 0,
                          c.stream, a);
       break;
     case 3:
-      hipLaunchKernelGGL((k_bm_aggregate<64, 128, WK>), dim3((unsigned)cdiv(cnt, BM_NT / 64)), dim3(BM_NT), 0,
+      hipLaunchKernelGGL((k_bm_group<64, 128, WK, A32>), dim3((unsigned)cdiv(cnt, BM_NT / 64)), dim3(BM_NT), 0,
                          c.stream, a);
       break;
     case 4:
-      hipLaunchKernelGGL((k_bm_aggregate<64, 512, WK>), dim3((unsigned)cdiv(cnt, BM_NT / 64)), dim3(BM_NT), 0,
+      hipLaunchKernelGGL((k_bm_group<64, 512, WK, A32>), dim3((unsigned)cdiv(cnt, BM_NT / 64)), dim3(BM_NT), 0,
                          c.stream, a);
       break;
-    case 5:
-      hipLaunchKernelGGL((k_bm_aggregate_block<WK>), dim3((unsigned)cnt), dim3(BM_NT), 0, c.stream, a);
+    case 5: {
+      a.hcap = MID_SLOTS;
+      const size_t bytes = wide_lds_bytes(MID_SLOTS, A32);
+      hipLaunchKernelGGL((k_bm_wide<BM_NT, WK, A32>), dim3((unsigned)cnt), dim3(BM_NT), bytes, c.stream, a);
       break;
-    default: {
-      int64_t grid = cnt < (int64_t)c.num_cu * 2 ? cnt : (int64_t)c.num_cu * 2;
-      hipLaunchKernelGGL((k_bm_aggregate_global<WK>), dim3((unsigned)grid), dim3(BM_NT), 0, c.stream, a);
     }
+    case 6: {
+      a.hcap = wide_slots(c, A32);
+      const size_t bytes = wide_lds_bytes(a.hcap, A32);
+      allow_lds(c, k_bm_wide<WIDE_NT, WK, A32>, bytes);
+      hipLaunchKernelGGL((k_bm_wide<WIDE_NT, WK, A32>), dim3((unsigned)cnt), dim3(WIDE_NT), bytes, c.stream, a);
+      break;
+    }
+    default:
+      fail(LCC_ERR_DEVICE, "internal: the flat bin is launched by launch_flat");
   }
   LAUNCHCHECK();
 }
 
+// Singleton first iteration: lanes per vertex follow the degree bin.
+template <int WK> void launch_single(Ctx &c, int bin, AggArgs a) {
+  const int64_t cnt = a.count;
+  switch (bin) {
+    case 0:
+      hipLaunchKernelGGL((k_bm_single<8, BM_NT, WK>), dim3((unsigned)cdiv(cnt, BM_NT / 8)), dim3(BM_NT), 0,
+                         c.stream, a);
+      break;
+    case 1:
+      hipLaunchKernelGGL((k_bm_single<16, BM_NT, WK>), dim3((unsigned)cdiv(cnt, BM_NT / 16)), dim3(BM_NT), 0,
+                         c.stream, a);
+      break;
+    case 2:
+      hipLaunchKernelGGL((k_bm_single<32, BM_NT, WK>), dim3((unsigned)cdiv(cnt, BM_NT / 32)), dim3(BM_NT), 0,
+                         c.stream, a);
+      break;
+    case 3:
+    case 4:
+      hipLaunchKernelGGL((k_bm_single<64, BM_NT, WK>), dim3((unsigned)cdiv(cnt, BM_NT / 64)), dim3(BM_NT), 0,
+                         c.stream, a);
+      break;
+    case 5:
+      hipLaunchKernelGGL((k_bm_single<BM_NT, BM_NT, WK>), dim3((unsigned)cnt), dim3(BM_NT), 0, c.stream, a);
+      break;
+    default:
+      hipLaunchKernelGGL((k_bm_single<WIDE_NT, WIDE_NT, WK>), dim3((unsigned)cnt), dim3(WIDE_NT), 0, c.stream, a);
+  }
+  LAUNCHCHECK();
+}
+
+// Flat aggregation of the rows of bin 7 (see k_b7_insert).
+template <int WK> void launch_flat(Ctx &c, AggArgs a, int64_t arcs) {
+  const int64_t n7 = a.count;
+  int64_t *deg = c.buf<int64_t>("b7.deg", (size_t)n7 + 1);
+  int64_t *cap = c.buf<int64_t>("b7.cap", (size_t)n7 + 1);
+  int64_t *astart = c.buf<int64_t>("b7.astart", (size_t)n7 + 1);
+  int64_t *tstart = c.buf<int64_t>("b7.tstart", (size_t)n7 + 1);
+  // sum of capacities <= 4 (arcs + n7)
+  const size_t slots = (size_t)(4 * (arcs + n7));
+  a.gkeys = c.buf<int32_t>("b7.keys", slots);
+  a.gvals = c.buf<int64_t>("b7.vals", slots);
+  hipLaunchKernelGGL(k_b7_prep, dim3((unsigned)std::min<int64_t>(cdiv(n7, 256), 4096)), dim3(256), 0, c.stream,
+                     a.list, n7, a.off, deg, cap);
+  LAUNCHCHECK();
+  scan<int64_t, int64_t>(c, deg, astart, n7, false, astart + n7);
+  scan<int64_t, int64_t>(c, cap, tstart, n7, false, tstart + n7);
+  hipLaunchKernelGGL(k_b7_clear, dim3((unsigned)c.num_cu * 8), dim3(256), 0, c.stream, a.gkeys, a.gvals,
+                     tstart + n7);
+  LAUNCHCHECK();
+  const int64_t waves = cdiv(arcs, B7_WAVE_ARCS);
+  const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(cdiv(waves, B7_NT / WAVE), 65536));
+  hipLaunchKernelGGL((k_b7_insert<WK>), dim3((unsigned)grid), dim3(B7_NT), 0, c.stream, a, n7, astart, tstart);
+  LAUNCHCHECK();
+  hipLaunchKernelGGL(k_b7_score, dim3((unsigned)n7), dim3(B7_NT), 0, c.stream, a, tstart);
+  LAUNCHCHECK();
+}
+
+template <int WK> void launch_any(Ctx &c, int bin, bool a32, bool single, int64_t arcs, AggArgs a) {
+  if (single) launch_single<WK>(c, bin, a);
+  else if (bin == NBINS - 1) launch_flat<WK>(c, a, arcs);
+  else if (a32) launch_bin<WK, true>(c, bin, a);
+  else launch_bin<WK, false>(c, bin, a);
+}
+
 const char *bin_name(int b) {
-  static const char *names[NBINS] = {"bm_aggregate_g8", "bm_aggregate_g16", "bm_aggregate_g32",
-                                     "bm_aggregate_g64", "bm_aggregate_g64_h512", "bm_aggregate_block",
-                                     "bm_aggregate_global"};
+  static const char *names[NBINS] = {"bm_aggregate_g8",  "bm_aggregate_g16",  "bm_aggregate_g32",
+                                     "bm_aggregate_g64", "bm_aggregate_g64w", "bm_aggregate_block",
+                                     "bm_aggregate_wide", "bm_aggregate_global"};
   return names[b];
+}
+
+// Renames the non-empty fresh clusters to the smallest empty ids (see the
+// file comment); checks the pairing error counter.
+void rename_fresh(Ctx &c, int64_t n, int32_t *C, int64_t *K, int32_t *cnt, int64_t *err) {
+  Ctx::Timer tm(&c, "bm_rename", 0.0, (double)n);
+  const size_t nn = (size_t)n;
+  uint8_t *fresh = c.buf<uint8_t>("rn.fresh", nn);
+  uint8_t *empty = c.buf<uint8_t>("rn.empty", nn);
+  int32_t *rank_f = c.buf<int32_t>("rn.rankf", nn);
+  int32_t *rank_e = c.buf<int32_t>("rn.ranke", nn);
+  int32_t *elist = c.buf<int32_t>("rn.elist", nn);
+  int32_t *newid = c.buf<int32_t>("rn.newid", nn);
+  int32_t *T = c.buf<int32_t>("rn.T", 2);
+  const unsigned grid = (unsigned)std::min<int64_t>(cdiv(n, 256), 65536);
+  hipLaunchKernelGGL(k_fresh_flags, dim3(grid), dim3(256), 0, c.stream, cnt, n, fresh, empty);
+  LAUNCHCHECK();
+  scan<uint8_t, int32_t>(c, fresh, rank_f, n, false, T);
+  scan<uint8_t, int32_t>(c, empty, rank_e, n, false, T + 1);
+  hipLaunchKernelGGL(k_empty_list, dim3(grid), dim3(256), 0, c.stream, empty, rank_e, n, T, elist);
+  LAUNCHCHECK();
+  hipLaunchKernelGGL(k_fresh_move, dim3(grid), dim3(256), 0, c.stream, fresh, rank_f, elist, n, K, cnt, newid, err);
+  LAUNCHCHECK();
+  hipLaunchKernelGGL(k_fresh_relabel, dim3(grid), dim3(256), 0, c.stream, C, n, newid);
+  LAUNCHCHECK();
+  int64_t e = 0;
+  d2h(c, &e, err, sizeof(e));
+  if (e) fail(LCC_ERR_DEVICE, "internal: fresh clusters outnumbered the empty cluster ids");
 }
 
 }  // namespace
 
 void best_moves(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_params &prm, int32_t level,
-                int32_t phase, int32_t *C, bool identity, int64_t maxdeg, lcc_bm_stats &st) {
+                int32_t phase, int32_t *C, const BMShape &shape, lcc_bm_stats &st) {
+  const bool identity = shape.identity, acc32 = shape.acc32;
+  const int64_t maxdeg = shape.maxdeg;
   std::memset(&st, 0, sizeof(st));
   const int64_t n = g.n;
   const int S = prm.S;
   const int NB = S * NBINS;
   const size_t nn = (size_t)(n > 0 ? n : 1);
   int32_t *D = c.buf<int32_t>("bm.D", nn);
-  int64_t *K = c.buf<int64_t>("bm.K", nn);
-  int32_t *cnt = c.buf<int32_t>("bm.cnt", nn);
+  // cluster totals cover the regular ids [0, n) and the fresh ids [n, 2n)
+  int64_t *K = c.buf<int64_t>("bm.K", 2 * nn);
+  int32_t *cnt = c.buf<int32_t>("bm.cnt", 2 * nn);
   uint8_t *next = c.buf<uint8_t>("bm.next", nn);
-  uint8_t *iso = c.buf<uint8_t>("bm.iso", nn);
   int32_t *active = c.buf<int32_t>("bm.active", nn);
   int32_t *blist = c.buf<int32_t>("bm.blist", nn);
   uint16_t *bucket_of = c.buf<uint16_t>("bm.bucket", nn);
-  int32_t *iso_list = c.buf<int32_t>("bm.isolist", nn);
-  int32_t *empty_list = c.buf<int32_t>("bm.emptylist", nn);
-  const int64_t iso_nb = cdiv(n > 0 ? n : 1, ISO_TILE);
-  int64_t *iso_part = c.buf<int64_t>("bm.isopart", (size_t)(2 * iso_nb));
-  // per iteration: bucket counts, bucket arcs, cursors, per-launch counters, per-sub-round isolations
-  const size_t nctr = (size_t)NB * 3 + (size_t)NB * 4 + (size_t)S + 2;
+  // per iteration: bucket counts, bucket arcs, cursors, per-launch counters,
+  // per-sub-round isolations, next-frontier size, isolation errors
+  const int LC = NSPREAD * NCTR;
+  const size_t nctr = (size_t)NB * 3 + (size_t)NB * LC + (size_t)S + 2;
   int64_t *dctr = c.buf<int64_t>("bm.ctr", nctr);
   int64_t *bcnt = dctr, *barcs = dctr + NB, *cursor = dctr + 2 * NB, *lctr = dctr + 3 * NB;
-  int64_t *isoc = lctr + 4 * NB, *nact = isoc + S;
+  int64_t *isoc = lctr + (size_t)LC * NB, *nact = isoc + S, *iso_err = nact + 1;
   std::vector<int64_t> hctr(nctr);
 
   if (n > 0) {
     HIPCHECK(hipMemsetAsync(next, 0, nn, c.stream));
-    HIPCHECK(hipMemsetAsync(iso, 0, nn, c.stream));
+    HIPCHECK(hipMemsetAsync(K + n, 0, nn * sizeof(int64_t), c.stream));
+    HIPCHECK(hipMemsetAsync(cnt + n, 0, nn * sizeof(int32_t), c.stream));
     if (identity) {
       hipLaunchKernelGGL(k_init_identity, dim3((unsigned)std::min<int64_t>(cdiv(n, 256), 65535)), dim3(256), 0,
                          c.stream, g.k, K, cnt, n);
@@ -710,16 +963,10 @@ void best_moves(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_para
       cluster_totals(c, n, C, g.k, K, cnt);
     }
   }
-  // global hash for the top bin
-  int64_t gcap = 1;
-  while (gcap < 2 * (maxdeg + 1)) gcap <<= 1;
-  const int64_t ggrid = (int64_t)c.num_cu * 2;
-  int32_t *gkeys = nullptr;
-  int64_t *gvals = nullptr;
-  if (maxdeg > bin_limit(NBINS - 2)) {
-    gkeys = c.buf<int32_t>("bm.gkeys", (size_t)(gcap * ggrid));
-    gvals = c.buf<int64_t>("bm.gvals", (size_t)(gcap * ggrid));
-  }
+  // bin 6 takes rows whose distinct clusters fill at most 70% of the LDS table
+  const int64_t wslots = wide_slots(c, acc32);
+  const int64_t wide_max = wslots * 7 / 10 - 1;
+  (void)maxdeg;
   const int wb = wt_bytes(g.wt_kind);
   const bool nbr = prm.frontier == LCC_FRONTIER_NBR;
   const int32_t *list = nullptr;  // nullptr = every vertex
@@ -734,7 +981,7 @@ void best_moves(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_para
       const size_t smem = (size_t)2 * NB * sizeof(int64_t);
       int64_t grid = std::min<int64_t>(cdiv(na, BM_NT * 8), (int64_t)c.num_cu * 8);
       hipLaunchKernelGGL(k_part_count, dim3((unsigned)grid), dim3(BM_NT), smem, c.stream, list, na, g.off, h, S,
-                         bucket_of, bcnt, barcs);
+                         wide_max, bucket_of, bcnt, barcs);
       LAUNCHCHECK();
       hipLaunchKernelGGL(k_part_starts, dim3(1), dim3(1), 0, c.stream, bcnt, cursor, NB);
       LAUNCHCHECK();
@@ -774,22 +1021,35 @@ void best_moves(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_para
         a.count = cntb;
         a.D = D;
         a.next_flag = nbr ? next : nullptr;
-        a.ctr = lctr + 4 * bi;
-        a.gkeys = gkeys;
-        a.gvals = gvals;
-        a.gcap = gcap;
-        const double arcs_b = (double)hctr[NB + bi];
+        a.ctr = lctr + (size_t)LC * bi;
+        a.gkeys = nullptr;
+        a.gvals = nullptr;
+        a.hcap = 0;
+        const int64_t arcs_i = hctr[NB + bi];
+        const double arcs_b = (double)arcs_i;
+        // first sub-round from singletons on rows without repeats: no
+        // aggregation (later sub-rounds see the moves of earlier ones)
+        const bool single = it == 0 && s == 0 && identity && shape.simple;
         size_t pidx = c.pending.size();
         {
-          Ctx::Timer tm(&c, bin_name(b), (double)cntb * 48.0 + arcs_b * (8.0 + wb), arcs_b);
+          // algorithmic bytes: per vertex list, offsets, C, k, K, cnt, D (48 B);
+          // per arc col, C[u] (or k[u] for singletons) and the weight
+          const double per_arc = single ? 12.0 + wb : 8.0 + wb;
+          // the flat bin is a sequence of kernels: timed as one class, never
+          // taken as "the" kernel of a roofline
+          // one timing class per kernel instantiation (bin, weight storage)
+          static const char *wk_tag[4] = {"_unit", "_i16", "_i32", "_i64"};
+          std::string nm = std::string(single ? "bm_single" : (b == NBINS - 1 ? "bm_flat_seq" : bin_name(b))) +
+                           wk_tag[g.wt_kind];
+          Ctx::Timer tm(&c, nm.c_str(), (double)cntb * 48.0 + arcs_b * per_arc, arcs_b);
           switch (g.wt_kind) {
-            case LCC_WT_UNIT: launch_bin<LCC_WT_UNIT>(c, b, a); break;
-            case LCC_WT_I16: launch_bin<LCC_WT_I16>(c, b, a); break;
-            case LCC_WT_I32: launch_bin<LCC_WT_I32>(c, b, a); break;
-            default: launch_bin<LCC_WT_I64>(c, b, a); break;
+            case LCC_WT_UNIT: launch_any<LCC_WT_UNIT>(c, b, acc32, single, arcs_i, a); break;
+            case LCC_WT_I16: launch_any<LCC_WT_I16>(c, b, acc32, single, arcs_i, a); break;
+            case LCC_WT_I32: launch_any<LCC_WT_I32>(c, b, acc32, single, arcs_i, a); break;
+            default: launch_any<LCC_WT_I64>(c, b, acc32, single, arcs_i, a); break;
           }
         }
-        launches.push_back({b, cntb, hctr[NB + bi], c.timing ? pidx : (size_t)-1, bi});
+        launches.push_back({c.timing ? pidx : (size_t)-1, bi});
         st.vertices_processed += cntb;
         st.arcs_scanned += hctr[NB + bi];
       }
@@ -797,47 +1057,37 @@ void best_moves(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_para
         {
           Ctx::Timer tm(&c, "bm_apply", (double)total_s * 12.0, (double)total_s);
           hipLaunchKernelGGL(k_bm_apply, dim3((unsigned)cdiv(total_s, BM_NT)), dim3(BM_NT), 0, c.stream,
-                             blist + start[s * NBINS], total_s, D, C, K, cnt, g.k, iso, isoc + s);
-          LAUNCHCHECK();
-        }
-        if (prm.allow_isolate) {
-          Ctx::Timer tm(&c, "bm_isolate", 0.0, 0.0);
-          hipLaunchKernelGGL(k_iso_count, dim3((unsigned)iso_nb), dim3(CMP_NT), 0, c.stream, iso, cnt, n, isoc + s,
-                             iso_part);
-          LAUNCHCHECK();
-          hipLaunchKernelGGL(k_iso_scan, dim3(1), dim3(1024), 0, c.stream, iso_part, iso_nb, isoc + s);
-          LAUNCHCHECK();
-          hipLaunchKernelGGL(k_iso_lists, dim3((unsigned)iso_nb), dim3(CMP_NT), 0, c.stream, iso, cnt, n, isoc + s,
-                             iso_part, iso_list, empty_list);
-          LAUNCHCHECK();
-          hipLaunchKernelGGL(k_iso_pair, dim3((unsigned)std::min<int64_t>(cdiv(n, BM_NT), 1024)), dim3(BM_NT), 0,
-                             c.stream, isoc + s, iso_list, empty_list, C, K, cnt, g.k, iso, n, nact + 1);
+                             blist + start[s * NBINS], total_s, D, C, K, cnt, g.k, n, isoc + s);
           LAUNCHCHECK();
         }
       }
       st.subrounds++;
     }
     // next frontier
-    bool more = false;
-    if (nbr && n > 0) {
-      compact_flags(c, next, n, active, nact, true, "bm.cmp");
-    }
-    d2h(c, hctr.data() + 3 * NB, lctr, (size_t)(4 * NB + S + 2) * sizeof(int64_t));
+    if (nbr && n > 0) compact_flags(c, next, n, active, nact, true, "bm.cmp");
+    d2h(c, hctr.data() + 3 * NB, lctr, (size_t)(LC * NB + S + 2) * sizeof(int64_t));
     const int64_t *hl = hctr.data() + 3 * NB;
-    int64_t moved_it = 0;
-    int64_t cap_err = 0;
+    int64_t moved_it = 0, cap_err = 0;
+    std::vector<int64_t> lsum((size_t)NB * NCTR, 0);
+    for (int i = 0; i < NB; i++)
+      for (int r = 0; r < NSPREAD; r++)
+        for (int k = 0; k < NCTR; k++) lsum[(size_t)i * NCTR + k] += hl[(size_t)i * LC + r * NCTR + k];
     for (int i = 0; i < NB; i++) {
-      moved_it += hl[4 * i];
-      st.candidates += hl[4 * i + 1];
-      cap_err += hl[4 * i + 3];
+      moved_it += lsum[(size_t)i * NCTR + 0];
+      st.candidates += lsum[(size_t)i * NCTR + 1];
+      cap_err += lsum[(size_t)i * NCTR + 3];
     }
+    const int64_t hl_nact = hl[(size_t)LC * NB + S];
+    int64_t isolated = 0;
+    for (int s = 0; s < S; s++) isolated += hl[(size_t)LC * NB + s];
     if (cap_err) fail(LCC_ERR_DEVICE, "internal: a vertex degree exceeded the hash capacity sized from the maximum degree");
-    if (hl[4 * NB + S + 1]) fail(LCC_ERR_DEVICE, "internal: isolated vertices outnumbered the empty cluster ids");
+    if (isolated) rename_fresh(c, n, C, K, cnt, iso_err);
     if (c.timing) {
       for (auto &L : launches) {
         if (L.pending_idx < c.pending.size()) {
           // candidates gather K (8 B each); movers store one flag per neighbor
-          c.pending[L.pending_idx].bytes += 8.0 * (double)hl[4 * L.slot + 1] + (double)hl[4 * L.slot + 2];
+          c.pending[L.pending_idx].bytes +=
+              8.0 * (double)lsum[(size_t)L.slot * NCTR + 1] + (double)lsum[(size_t)L.slot * NCTR + 2];
         }
       }
     }
@@ -849,9 +1099,8 @@ void best_moves(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_para
       st.term = LCC_TERM_NO_MOVES;
       break;
     }
-    (void)more;
     if (nbr) {
-      na = hl[4 * NB + S];
+      na = hl_nact;
       list = active;
     } else {
       na = n;

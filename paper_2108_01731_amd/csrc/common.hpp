@@ -107,6 +107,9 @@ struct PendingEvent {
 struct Ctx {
   int device = 0;
   int num_cu = 256;
+  size_t lds_per_block = 65536;
+  // kernels whose dynamic-LDS limit has been raised on this device
+  std::vector<const void *> lds_raised;
   hipStream_t stream = nullptr;
   bool timing = false;
   std::map<std::string, KernelClass> kstats;

@@ -17,6 +17,7 @@ struct GraphSummary {
   uint64_t kksum = 0;  // sum of kk (or k^2)
   bool negative = false;
   int64_t maxdeg = 0;
+  bool sorted_rows = false;  // every row strictly ascending (so no repeated neighbor)
 };
 
 // Validation pass (read-only): offsets, column range, self-loops, k >= 0,
@@ -31,11 +32,19 @@ lcc_status overflow_bounds(const GraphSummary &s, int64_t p, int64_t q, std::str
 // cnt[x] = members.  Deterministic, contention-free (sort + prefix sums).
 void cluster_totals(Ctx &c, int64_t n, const int32_t *C, const int64_t *k, int64_t *K, int32_t *cnt);
 
-// Best-Moves on graph g from clustering C (device, updated in place).  When
-// `identity` is set, C must already hold C[v] = v.  On return K (device,
-// n entries, owned by the context as "bm.K") holds the cluster totals of C.
+// What Best-Moves may assume about its input (never changes a result).
+struct BMShape {
+  int64_t maxdeg;   // largest row length
+  bool acc32;       // every row's sum of |w| is below 2^31 (32-bit accumulators)
+  bool identity;    // C[v] = v on entry
+  bool simple;      // no row repeats a neighbor
+};
+
+// Best-Moves on graph g from clustering C (device, updated in place).  On
+// return K (device, owned by the context as "bm.K") holds the cluster totals
+// of C.
 void best_moves(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_params &prm, int32_t level,
-                int32_t phase, int32_t *C, bool identity, int64_t maxdeg, lcc_bm_stats &st);
+                int32_t phase, int32_t *C, const BMShape &shape, lcc_bm_stats &st);
 
 // Compress g by C into `out` (library-owned arrays); map (device int32[n]).
 // `wide` selects int64 output weights (else int32).

@@ -27,8 +27,9 @@ MUTATIONS = {
                                "qsort(trip, (size_t)ninter / 2, 3 * sizeof(int64_t), cmp_triple);"),
     "frontier_adds_mover": ("for (int64_t e = g->off[v]; e < g->off[v + 1]; e++) flags[g->col[e]] = 1;",
                             "flags[v] = 1; for (int64_t e = g->off[v]; e < g->off[v + 1]; e++) flags[g->col[e]] = 1;"),
-    "iso_ids_skip_first_empty": ("      while (cnt[x] != 0) x++; /* pigeonhole",
-                                 "      x += (x == 0); while (cnt[x] != 0) x++; /* pigeonhole"),
+    "fresh_ids_skip_first_empty": ("    while (cnt[x] != 0) x++;\n    newid[t] = (int32_t)x;",
+                                   "    x += (x == 0);\n    while (cnt[x] != 0) x++;\n    newid[t] = (int32_t)x;"),
+    "fresh_cluster_not_renamed": ("    if (C[v] >= n) C[v] = newid[C[v] - n];", "    if (0) C[v] = newid[C[v] - n];"),
     "isolate_score_positive": ("if (!have || 0 > best) { have = 1; best = 0; best_id = ORC_ISO; }",
                                "if (!have || 1 > best) { have = 1; best = 0; best_id = ORC_ISO; }"),
     "mix_wrong_constant": ("z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;",
