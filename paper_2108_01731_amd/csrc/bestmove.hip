@@ -541,27 +541,50 @@ __global__ __launch_bounds__(B7_NT) void k_b7_insert(AggArgs a, int64_t n7, cons
   }
 }
 
-// One block per row: scores the row's table (written by the previous kernel).
-__global__ __launch_bounds__(B7_NT) void k_b7_score(AggArgs a, const int64_t *__restrict__ tstart) {
-  __shared__ int32_t sh_d;
-  const int t = threadIdx.x;
-  const int64_t i = blockIdx.x;
+// Scoring of the hub tables, one block per B7_SEG-slot segment (a row's
+// table spans cdiv(cap, B7_SEG) segments, sstart = prefix of segment counts).
+constexpr int64_t B7_SEG = 4096;
+
+struct SegBest {
+  int64_t best_s;
+  int64_t wc;
+  int64_t cands;
+  int32_t best_id;
+  int32_t pad;
+};
+
+__global__ void k_b7_nseg(const int64_t *__restrict__ cap, int64_t n7, int64_t *__restrict__ nseg) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n7; i += (int64_t)gridDim.x * blockDim.x)
+    nseg[i] = cdiv(cap[i], B7_SEG);
+}
+
+__global__ __launch_bounds__(B7_NT) void k_b7_segscore(AggArgs a, int64_t n7, const int64_t *__restrict__ tstart,
+                                                       const int64_t *__restrict__ sstart,
+                                                       SegBest *__restrict__ part) {
+  const int64_t sg = blockIdx.x;
+  // row owning this segment
+  int64_t lo = 0, hi = n7 - 1;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (sstart[mid] <= sg) lo = mid;
+    else hi = mid - 1;
+  }
+  const int64_t i = lo;
   const int32_t v = a.list[i];
-  const int64_t beg = a.off[v], end = a.off[v + 1];
   const int32_t c = a.C[v];
-  const int64_t kv = a.k[v], Kc = a.K[c];
-  const int32_t cntc = a.cnt[c];
+  const int64_t pk = a.p * a.k[v];
   const int64_t t0 = tstart[i], H = tstart[i + 1] - t0;
-  const int32_t *keys = a.gkeys + t0;
-  const int64_t *vals = a.gvals + t0;
-  const int64_t pk = a.p * kv;
+  const int64_t j0 = (sg - sstart[i]) * B7_SEG;
+  const int64_t j1 = j0 + B7_SEG < H ? j0 + B7_SEG : H;
   int64_t best_s = INT64_MIN, wc = 0, cands = 0;
   int32_t best_id = ISO_ID;
-  for (int64_t j = t; j < H; j += B7_NT) {
-    const int32_t X = keys[j];
+  // the tables were filled by device-scope atomics in the previous kernel:
+  // read them with device-scope loads as well
+  for (int64_t j = j0 + threadIdx.x; j < j1; j += B7_NT) {
+    const int32_t X = __hip_atomic_load(&a.gkeys[t0 + j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (X < 0) continue;
     cands++;
-    const int64_t wx = vals[j];
+    const int64_t wx = __hip_atomic_load(&a.gvals[t0 + j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (X == c) {
       wc = wx;
     } else {
@@ -572,10 +595,43 @@ __global__ __launch_bounds__(B7_NT) void k_b7_score(AggArgs a, const int64_t *__
       }
     }
   }
+  cands = wave_sum(cands);
+  __shared__ int64_t rc[B7_NT / WAVE];
+  if (lane_id() == 0) rc[threadIdx.x / WAVE] = cands;
+  block_best<B7_NT>(best_s, best_id, wc);
+  if (threadIdx.x == 0) {
+    int64_t tc = 0;
+    for (int k = 0; k < B7_NT / WAVE; k++) tc += rc[k];
+    part[sg] = SegBest{best_s, wc, tc, best_id, 0};
+  }
+}
+
+// One block per row: combines the row's segments, decides, marks the frontier.
+__global__ __launch_bounds__(B7_NT) void k_b7_final(AggArgs a, const int64_t *__restrict__ sstart,
+                                                    const SegBest *__restrict__ part) {
+  __shared__ int32_t sh_d;
+  const int t = threadIdx.x;
+  const int64_t i = blockIdx.x;
+  const int32_t v = a.list[i];
+  const int64_t beg = a.off[v], end = a.off[v + 1];
+  const int32_t c = a.C[v];
+  const int64_t kv = a.k[v], Kc = a.K[c];
+  const int32_t cntc = a.cnt[c];
+  int64_t best_s = INT64_MIN, wc = 0, cands = 0;
+  int32_t best_id = ISO_ID;
+  for (int64_t sg = sstart[i] + t; sg < sstart[i + 1]; sg += B7_NT) {
+    const SegBest b = part[sg];
+    if (better(b.best_s, b.best_id, best_s, best_id)) {
+      best_s = b.best_s;
+      best_id = b.best_id;
+    }
+    wc += b.wc;
+    cands += b.cands;
+  }
   block_best<B7_NT>(best_s, best_id, wc);
   int64_t movers = 0, marcs = 0;
   if (t == 0) {
-    const int64_t stay = a.q * wc - pk * (Kc - kv);
+    const int64_t stay = a.q * wc - a.p * kv * (Kc - kv);
     const int32_t d = decide(best_s, best_id, stay, a.allow_iso && cntc >= 2, c);
     a.D[v] = d;
     sh_d = d;
@@ -877,7 +933,20 @@ template <int WK> void launch_flat(Ctx &c, AggArgs a, int64_t arcs) {
   const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(cdiv(waves, B7_NT / WAVE), 65536));
   hipLaunchKernelGGL((k_b7_insert<WK>), dim3((unsigned)grid), dim3(B7_NT), 0, c.stream, a, n7, astart, tstart);
   LAUNCHCHECK();
-  hipLaunchKernelGGL(k_b7_score, dim3((unsigned)n7), dim3(B7_NT), 0, c.stream, a, tstart);
+  // segments: at most (sum of capacities) / B7_SEG + n7
+  int64_t *nseg = c.buf<int64_t>("b7.nseg", (size_t)n7 + 1);
+  int64_t *sstart = c.buf<int64_t>("b7.sstart", (size_t)n7 + 1);
+  const int64_t max_seg = (int64_t)slots / B7_SEG + n7;
+  SegBest *part = c.buf<SegBest>("b7.part", (size_t)max_seg);
+  hipLaunchKernelGGL(k_b7_nseg, dim3((unsigned)std::min<int64_t>(cdiv(n7, 256), 4096)), dim3(256), 0, c.stream, cap,
+                     n7, nseg);
+  LAUNCHCHECK();
+  scan<int64_t, int64_t>(c, nseg, sstart, n7, false, sstart + n7);
+  int64_t nsegs = 0;
+  d2h(c, &nsegs, sstart + n7, sizeof(int64_t));
+  hipLaunchKernelGGL(k_b7_segscore, dim3((unsigned)nsegs), dim3(B7_NT), 0, c.stream, a, n7, tstart, sstart, part);
+  LAUNCHCHECK();
+  hipLaunchKernelGGL(k_b7_final, dim3((unsigned)n7), dim3(B7_NT), 0, c.stream, a, sstart, part);
   LAUNCHCHECK();
 }
 
