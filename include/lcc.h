@@ -261,6 +261,51 @@ lcc_status lcc_cluster(lcc_ctx *ctx, const lcc_graph *g, lcc_lambda lam, const l
                        int32_t *labels_out, lcc_objective_out *obj, lcc_cluster_stats *stats,
                        void *stream);
 
+/* Per-job result of a batched run. */
+typedef struct lcc_job_out {
+  lcc_objective_out obj; /* objective of the job's labels under the job's lambda */
+  int64_t clusters;      /* number of clusters of the job */
+  int32_t levels;        /* graphs in the job's hierarchy (as lcc_cluster_stats.levels) */
+  int32_t top_moved;     /* as lcc_cluster_stats.top_moved */
+} lcc_job_out;
+
+/* Batch statistics (summed over jobs; wall times cover the whole batch). */
+typedef struct lcc_batch_stats {
+  int32_t levels; /* batch levels (the largest job hierarchy) */
+  int32_t reserved0;
+  int64_t n_level[LCC_MAX_LEVELS];    /* vertices of the packed graph at each level */
+  int64_t arcs_level[LCC_MAX_LEVELS]; /* arcs of the packed graph at each level */
+  int64_t moves_total;
+  int64_t arcs_scanned_total;
+  double ms_best_move;
+  double ms_compress;
+  double ms_total;
+} lcc_batch_stats;
+
+/* Parallel-CC (as lcc_cluster) on many independent jobs in shared launches.
+ * g packs the jobs block-diagonally: job j owns the vertices
+ * [job_start[j], job_start[j+1]) and every arc of those rows stays inside that
+ * range.  job_start (host int64[jobs + 1]) is non-decreasing from 0 to g->n;
+ * empty jobs are allowed.  lambdas (host, jobs entries) gives each job its
+ * own resolution; prm is shared (stop_after_subrounds must be 0).
+ *
+ * Each job's result is the one lcc_cluster gives on that job's graph alone
+ * (vertex v of job j being vertex v - job_start[j] there) with the same
+ * params: the sub-round assignment hashes job-local vertex ids, a job stops
+ * iterating and stops coarsening on its own conditions, isolating vertices
+ * take the job's own empty ids, and compression keeps only the jobs still
+ * coarsening.  labels_out (device int32[g->n]) receives each job's canonical
+ * labels (0, 1, ... within the job, in the order of its smallest vertex).
+ * jobs_out (host, jobs entries) and stats (host) are nullable.
+ *
+ * Errors: as lcc_cluster, plus INVALID_ARG (jobs < 0, job_start not a
+ * partition of [0, n), an arc leaving its job, NULL job_start or lambdas,
+ * stop_after_subrounds != 0) and OVERFLOW (the bounds of lcc_best_move
+ * checked per job with that job's lambda). */
+lcc_status lcc_cluster_batch(lcc_ctx *ctx, const lcc_graph *g, int64_t jobs, const int64_t *job_start,
+                             const lcc_lambda *lambdas, const lcc_params *prm, int32_t *labels_out,
+                             lcc_job_out *jobs_out, lcc_batch_stats *stats, void *stream);
+
 /* Per-kernel timing collected while params.timing was set (HIP events around
  * every launch, on the launch stream).  bytes is the algorithmic HBM traffic
  * the launches must move (inputs read once, outputs written once), computed

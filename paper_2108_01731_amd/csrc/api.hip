@@ -587,6 +587,266 @@ lcc_status lcc_cluster(lcc_ctx *ctx, const lcc_graph *g, lcc_lambda lam, const l
   });
 }
 
+lcc_status lcc_cluster_batch(lcc_ctx *ctx, const lcc_graph *g, int64_t jobs, const int64_t *job_start,
+                             const lcc_lambda *lambdas, const lcc_params *prm, int32_t *labels_out,
+                             lcc_job_out *jobs_out, lcc_batch_stats *stats, void *stream) {
+  return guarded([&] {
+    if (!ctx) fail(LCC_ERR_INVALID_ARG, "ctx is NULL");
+    Ctx &c = ctx->c;
+    check_params(prm);
+    if (prm->max_levels < 1 || prm->max_levels > LCC_MAX_LEVELS)
+      fail(LCC_ERR_INVALID_ARG, "max_levels must be in [1, 64]");
+    if (prm->stop_after_subrounds != 0) fail(LCC_ERR_INVALID_ARG, "stop_after_subrounds must be 0 in a batch");
+    if (jobs < 0 || jobs > INT32_MAX) fail(LCC_ERR_INVALID_ARG, "jobs must be in [0, 2^31)");
+    if (jobs > 0 && (!job_start || !lambdas)) fail(LCC_ERR_INVALID_ARG, "job_start or lambdas is NULL");
+    begin(c, stream, prm);
+    check_graph_args(c, g);
+    if (jobs == 0 && g->n != 0) fail(LCC_ERR_INVALID_ARG, "a batch without jobs must have n = 0");
+    if (jobs > 0) {
+      if (job_start[0] != 0 || job_start[jobs] != g->n)
+        fail(LCC_ERR_INVALID_ARG, "job_start must run from 0 to n");
+      for (int64_t j = 0; j < jobs; j++) {
+        if (job_start[j + 1] < job_start[j]) fail(LCC_ERR_INVALID_ARG, "job_start must be non-decreasing");
+        check_lambda(lambdas[j]);
+      }
+    }
+    check_dev(c, labels_out, (size_t)g->n * sizeof(int32_t), "labels_out");
+    using clk = std::chrono::steady_clock;
+    auto t0 = clk::now();
+    lcc_batch_stats bs;
+    std::memset(&bs, 0, sizeof(bs));
+    std::vector<lcc_job_out> jo((size_t)jobs);
+    for (auto &o : jo) {
+      std::memset(&o, 0, sizeof(o));
+      o.levels = 1;
+      o.obj.den = 1;
+    }
+    if (g->n == 0) {
+      for (int64_t j = 0; j < jobs; j++) fill_objective(0, lambdas[j].q, &jo[(size_t)j].obj);
+      if (jobs_out) std::copy(jo.begin(), jo.end(), jobs_out);
+      bs.levels = 1;
+      if (stats) *stats = bs;
+      return;
+    }
+    const int64_t J = jobs;
+    const std::vector<int64_t> hstart(job_start, job_start + J + 1);
+    // vertex chunks of level 0: (job, first, end), never spanning two jobs
+    std::vector<int64_t> vch;
+    for (int64_t j = 0; j < J; j++)
+      for (int64_t b = hstart[(size_t)j]; b < hstart[(size_t)j + 1]; b += BATCH_CHUNK) {
+        vch.push_back(j);
+        vch.push_back(b);
+        vch.push_back(std::min<int64_t>(b + BATCH_CHUNK, hstart[(size_t)j + 1]));
+      }
+    DevBuf d_start, d_jp, d_jq, d_cont;
+    d_start.ensure((size_t)(J + 1) * sizeof(int64_t));
+    d_jp.ensure((size_t)J * sizeof(int64_t));
+    d_jq.ensure((size_t)J * sizeof(int64_t));
+    d_cont.ensure((size_t)J);
+    {
+      std::vector<int64_t> hp((size_t)J), hq((size_t)J);
+      for (int64_t j = 0; j < J; j++) {
+        hp[(size_t)j] = lambdas[j].p;
+        hq[(size_t)j] = lambdas[j].q;
+      }
+      h2d(c, d_start.p, hstart.data(), (size_t)(J + 1) * sizeof(int64_t));
+      h2d(c, d_jp.p, hp.data(), (size_t)J * sizeof(int64_t));
+      h2d(c, d_jq.p, hq.data(), (size_t)J * sizeof(int64_t));
+      c.sync();
+    }
+    // validation: structure of the packed graph, then per-job sums (arcs that
+    // leave their job, and each job's overflow bounds under its own lambda)
+    GraphSummary s = summarize_graph(c, *g, nullptr, prm->validate != 0);
+    if (!s.ok) fail(LCC_ERR_INVALID_ARG, s.why);
+    bool wide = false;
+    {
+      std::vector<uint64_t> part = batch_vertex_sums(c, *g, d_start.as<int64_t>(), vch, true);
+      std::vector<GraphSummary> sj((size_t)J);
+      auto sat = [](uint64_t a, uint64_t b) {
+        uint64_t r = a + b;
+        return r < a ? ~0ull : r;
+      };
+      for (size_t i = 0; i < vch.size() / 3; i++) {
+        GraphSummary &t = sj[(size_t)vch[3 * i]];
+        const uint64_t *r = &part[6 * i];
+        t.wabs2 = sat(t.wabs2, r[0]);
+        t.ktot = sat(t.ktot, r[1]);
+        t.kksum = sat(t.kksum, r[2]);
+        t.sabs = sat(t.sabs, r[3]);
+        t.negative = t.negative || r[4];
+        if (r[5]) fail(LCC_ERR_INVALID_ARG, "an arc of job " + std::to_string(vch[3 * i]) + " leaves the job");
+      }
+      for (int64_t j = 0; j < J; j++) {
+        std::string why;
+        if (overflow_bounds(sj[(size_t)j], lambdas[j].p, lambdas[j].q, &why) != LCC_OK)
+          fail(LCC_ERR_OVERFLOW, "job " + std::to_string(j) + ": " + why);
+        wide = wide || wide_weights(sj[(size_t)j]);
+      }
+    }
+    // level 0 job layout
+    std::vector<DevBuf> jidl, jbasel, Cl, maps;
+    std::vector<std::unique_ptr<OwnedGraph>> owned;
+    std::vector<lcc_graph> G;
+    std::vector<int64_t> maxdeg;
+    jidl.emplace_back();
+    jidl.back().ensure((size_t)g->n * sizeof(int32_t));
+    batch_fill_jid(c, d_start.as<int64_t>(), J, g->n, jidl.back().as<int32_t>());
+    jbasel.emplace_back();
+    jbasel.back().ensure((size_t)(J + 1) * sizeof(int64_t));
+    HIPCHECK(hipMemcpyAsync(jbasel.back().p, d_start.p, (size_t)(J + 1) * sizeof(int64_t), hipMemcpyDeviceToDevice,
+                            c.stream));
+    G.push_back(*g);
+    maxdeg.push_back(s.maxdeg);
+    std::vector<uint8_t> run((size_t)J), cont((size_t)J), moved((size_t)J);
+    std::vector<int32_t> top((size_t)J, 0), iters((size_t)J);
+    for (int64_t j = 0; j < J; j++) run[(size_t)j] = hstart[(size_t)j + 1] > hstart[(size_t)j];
+    int maxtop = 0;
+    double ms_bm = 0, ms_cp = 0;
+    for (int l = 0;; l++) {
+      const int64_t n = G[l].n;
+      bs.n_level[l] = n;
+      bs.arcs_level[l] = G[l].arcs;
+      bs.levels = l + 1;
+      Cl.emplace_back();
+      Cl.back().ensure((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+      int32_t *C = Cl.back().as<int32_t>();
+      iota_i32(c, C, n);
+      BatchLevel bl;
+      bl.jobs = J;
+      bl.jid = jidl[l].as<int32_t>();
+      bl.jbase = jbasel[l].as<int64_t>();
+      bl.jp = d_jp.as<int64_t>();
+      bl.jq = d_jq.as<int64_t>();
+      bl.active = run.data();
+      bl.iters = iters.data();
+      bl.moved_any = moved.data();
+      lcc_bm_stats st;
+      auto a = clk::now();
+      const bool simple = l > 0 || s.sorted_rows;
+      best_moves(c, G[l], 0, 1, *prm, l, 0, C, BMShape{maxdeg[l], !wide, true, simple}, st, &bl);
+      ms_bm += std::chrono::duration<double, std::milli>(clk::now() - a).count();
+      bs.moves_total += st.moves;
+      bs.arcs_scanned_total += st.arcs_scanned;
+      bool any = false;
+      for (int64_t j = 0; j < J; j++) {
+        cont[(size_t)j] = 0;
+        if (!run[(size_t)j]) continue;
+        if (moved[(size_t)j] && l + 1 < prm->max_levels) {
+          cont[(size_t)j] = 1;
+          any = true;
+        } else {
+          top[(size_t)j] = l;
+          jo[(size_t)j].top_moved = moved[(size_t)j];
+        }
+      }
+      if (!any) {
+        maxtop = l;
+        break;
+      }
+      h2d(c, d_cont.p, cont.data(), (size_t)J);
+      maps.emplace_back();
+      maps.back().ensure((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+      owned.emplace_back(new OwnedGraph());
+      // the next level's job of every vertex and job bases
+      jidl.emplace_back();
+      jidl.back().ensure((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+      jbasel.emplace_back();
+      jbasel.back().ensure((size_t)(J + 1) * sizeof(int64_t));
+      CompressJobs cj;
+      cj.jobs = J;
+      cj.jid = jidl[l].as<int32_t>();
+      cj.jcont = d_cont.as<uint8_t>();
+      cj.jid_next = jidl[l + 1].as<int32_t>();
+      cj.jbase_next = jbasel[l + 1].as<int64_t>();
+      int64_t md = 0;
+      a = clk::now();
+      compress_graph(c, G[l], C, *owned.back(), maps.back().as<int32_t>(), wide, &md, &cj);
+      ms_cp += std::chrono::duration<double, std::milli>(clk::now() - a).count();
+      G.push_back(owned.back()->view());
+      maxdeg.push_back(md);
+      run = cont;
+    }
+    for (int l = maxtop - 1; l >= 0; l--) {
+      int32_t *C = Cl[l].as<int32_t>();
+      // jobs that stopped coarsening at this level keep their clustering (map < 0)
+      batch_flatten(c, G[l].n, maps[l].as<int32_t>(), Cl[l + 1].as<int32_t>(), jidl[l].as<int32_t>(),
+                    jbasel[l].as<int64_t>(), jbasel[l + 1].as<int64_t>(), C);
+      if (prm->refine) {
+        bool any = false;
+        for (int64_t j = 0; j < J; j++) {
+          run[(size_t)j] = top[(size_t)j] > l;
+          any = any || run[(size_t)j];
+        }
+        if (!any) continue;
+        BatchLevel bl;
+        bl.jobs = J;
+        bl.jid = jidl[l].as<int32_t>();
+        bl.jbase = jbasel[l].as<int64_t>();
+        bl.jp = d_jp.as<int64_t>();
+        bl.jq = d_jq.as<int64_t>();
+        bl.active = run.data();
+        bl.iters = iters.data();
+        bl.moved_any = moved.data();
+        lcc_bm_stats st;
+        auto a = clk::now();
+        best_moves(c, G[l], 0, 1, *prm, l, 1, C, BMShape{maxdeg[l], !wide, false, false}, st, &bl);
+        ms_bm += std::chrono::duration<double, std::milli>(clk::now() - a).count();
+        bs.moves_total += st.moves;
+        bs.arcs_scanned_total += st.arcs_scanned;
+      }
+    }
+    // canonical labels over the packed graph, then made job-local
+    const int64_t n0 = g->n;
+    int32_t *glab = c.buf<int32_t>("bt.glab", (size_t)n0);
+    const int64_t total = canonical_labels(c, n0, Cl[0].as<int32_t>(), glab);
+    batch_local_labels(c, glab, jidl[0].as<int32_t>(), d_start.as<int64_t>(), n0, labels_out);
+    std::vector<int32_t> first = batch_first_labels(c, glab, d_start.as<int64_t>(), J);
+    // clusters of job j are the global labels [first_j, first of the next non-empty job)
+    int64_t nxt = total;
+    for (int64_t j = J - 1; j >= 0; j--) {
+      if (first[(size_t)j] < 0) continue;
+      jo[(size_t)j].clusters = nxt - first[(size_t)j];
+      nxt = first[(size_t)j];
+    }
+    for (int64_t j = 0; j < J; j++) jo[(size_t)j].levels = top[(size_t)j] + 1;
+    if (jobs_out) {
+      int64_t *K = c.buf<int64_t>("bt.K", (size_t)n0);
+      int64_t *KK = c.buf<int64_t>("bt.KK", (size_t)n0);
+      cluster_sums_k_kk(c, *g, glab, K, KK);
+      std::vector<int64_t> cch;
+      for (int64_t j = 0; j < J; j++) {
+        if (first[(size_t)j] < 0) continue;
+        const int64_t xb = first[(size_t)j], xe = xb + jo[(size_t)j].clusters;
+        for (int64_t x = xb; x < xe; x += BATCH_CHUNK) {
+          cch.push_back(j);
+          cch.push_back(x);
+          cch.push_back(std::min<int64_t>(x + BATCH_CHUNK, xe));
+        }
+      }
+      std::vector<i128> intra, self, pairs;
+      batch_objective_parts(c, *g, glab, vch, K, KK, cch, intra, self, pairs);
+      std::vector<i128> w2((size_t)J, 0), ss((size_t)J, 0), pp((size_t)J, 0);
+      for (size_t i = 0; i < vch.size() / 3; i++) {
+        w2[(size_t)vch[3 * i]] += intra[i];
+        ss[(size_t)vch[3 * i]] += self[i];
+      }
+      for (size_t i = 0; i < cch.size() / 3; i++) pp[(size_t)cch[3 * i]] += pairs[i];
+      for (int64_t j = 0; j < J; j++) {
+        const size_t u = (size_t)j;
+        const i128 N = (i128)lambdas[j].q * (ss[u] + w2[u] / 2) - (i128)lambdas[j].p * (pp[u] / 2);
+        fill_objective(N, lambdas[j].q, &jo[u].obj);
+      }
+    }
+    c.sync();
+    if (c.timing) c.collect_timing();
+    bs.ms_best_move = ms_bm;
+    bs.ms_compress = ms_cp;
+    bs.ms_total = std::chrono::duration<double, std::milli>(clk::now() - t0).count();
+    if (jobs_out) std::copy(jo.begin(), jo.end(), jobs_out);
+    if (stats) *stats = bs;
+  });
+}
+
 lcc_status lcc_ctx_kernel_stats(lcc_ctx *ctx, lcc_kernel_stat *out, int32_t max, int32_t *count) {
   return guarded([&] {
     if (!ctx || !count || (max > 0 && !out)) fail(LCC_ERR_INVALID_ARG, "NULL argument");

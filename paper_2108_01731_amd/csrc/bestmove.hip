@@ -54,6 +54,19 @@ __host__ __device__ inline int bin_of(int64_t deg, int64_t wide_max) {
   return deg <= wide_max ? 6 : 7;
 }
 
+// Batched runs: several independent jobs packed block-diagonally in one graph.
+// Each vertex belongs to one job; the job supplies lambda, the base that
+// turns a vertex id into its job-local id (the sub-round hash uses local
+// ids), whether the job is still iterating, and a per-job mover counter.
+struct JobView {
+  const int32_t *jid = nullptr;  // nullptr: one job, scalar lambda
+  const int64_t *jbase = nullptr;
+  const int64_t *jp = nullptr;
+  const int64_t *jq = nullptr;
+  const uint8_t *jrun = nullptr;
+  int64_t *jmoved = nullptr;
+};
+
 struct AggArgs {
   const int64_t *off;
   const int32_t *col;
@@ -72,7 +85,25 @@ struct AggArgs {
   int32_t *gkeys;      // global tables (bin 7)
   int64_t *gvals;
   int64_t hcap;        // table capacity in slots (dynamic-LDS or global bins)
+  JobView jv;
 };
+
+// lambda of the job owning v (the scalar lambda outside batched runs).
+__device__ __forceinline__ void job_lambda(const AggArgs &a, int32_t v, int64_t &p, int64_t &q, int32_t &job) {
+  if (a.jv.jid) {
+    job = a.jv.jid[v];
+    p = a.jv.jp[job];
+    q = a.jv.jq[job];
+  } else {
+    job = 0;
+    p = a.p;
+    q = a.q;
+  }
+}
+
+__device__ __forceinline__ void count_job_mover(const AggArgs &a, int32_t job) {
+  if (a.jv.jmoved) atomic_add_i64(&a.jv.jmoved[job], 1);
+}
 
 // (score, id) order: higher score first, then lower id.
 __device__ __forceinline__ bool better(int64_t s, int32_t id, int64_t bs, int32_t bid) {
@@ -253,7 +284,10 @@ __global__ __launch_bounds__(BM_NT) void k_bm_group(AggArgs a) {
   __syncthreads();
   int64_t best_s = INT64_MIN, wc = 0, ncand = 0;
   int32_t best_id = ISO_ID;
-  const int64_t pk = a.p * kv;
+  int64_t lp = 0, lq = 1;
+  int32_t job = 0;
+  if (valid) job_lambda(a, v, lp, lq, job);
+  const int64_t pk = lp * kv;
   if (valid) {
     for (uint32_t j = gl; j < H; j += G) {
       const int32_t X = keys[j];
@@ -263,7 +297,7 @@ __global__ __launch_bounds__(BM_NT) void k_bm_group(AggArgs a) {
       if (X == c) {
         wc = wx;
       } else {
-        const int64_t s = a.q * wx - pk * a.K[X];
+        const int64_t s = lq * wx - pk * a.K[X];
         if (better(s, X, best_s, best_id)) {
           best_s = s;
           best_id = X;
@@ -283,10 +317,11 @@ __global__ __launch_bounds__(BM_NT) void k_bm_group(AggArgs a) {
   }
   bool moved = false;
   if (valid) {
-    const int64_t stay = a.q * wc - pk * (Kc - kv);
+    const int64_t stay = lq * wc - pk * (Kc - kv);
     const int32_t d = decide(best_s, best_id, stay, a.allow_iso && cntc >= 2, c);
     moved = d != c;
     if (gl == 0) a.D[v] = d;
+    if (moved && gl == 0) count_job_mover(a, job);
     if (moved && a.next_flag) {
       if constexpr (ONE_PASS) {
         if (u0 >= 0) a.next_flag[u0] = 1;
@@ -340,7 +375,10 @@ __global__ __launch_bounds__(NT) void k_bm_wide(AggArgs a) {
       if (X[j] >= 0) lds_insert<Acc>(keys, vals, H, X[j], w[j]);
   }
   __syncthreads();
-  const int64_t pk = a.p * kv;
+  int64_t lp, lq;
+  int32_t job;
+  job_lambda(a, v, lp, lq, job);
+  const int64_t pk = lp * kv;
   int64_t best_s = INT64_MIN, wc = 0, cands = 0;
   int32_t best_id = ISO_ID;
   for (uint32_t j = t; j < H; j += NT) {
@@ -351,7 +389,7 @@ __global__ __launch_bounds__(NT) void k_bm_wide(AggArgs a) {
     if (X == c) {
       wc = wx;
     } else {
-      const int64_t s = a.q * wx - pk * a.K[X];
+      const int64_t s = lq * wx - pk * a.K[X];
       if (better(s, X, best_s, best_id)) {
         best_s = s;
         best_id = X;
@@ -361,13 +399,14 @@ __global__ __launch_bounds__(NT) void k_bm_wide(AggArgs a) {
   block_best<NT>(best_s, best_id, wc);
   int64_t movers = 0, marcs = 0;
   if (t == 0) {
-    const int64_t stay = a.q * wc - pk * (Kc - kv);
+    const int64_t stay = lq * wc - pk * (Kc - kv);
     const int32_t d = decide(best_s, best_id, stay, a.allow_iso && cntc >= 2, c);
     a.D[v] = d;
     sh_d = d;
     if (d != c) {
       movers = 1;
       marcs = end - beg;
+      count_job_mover(a, job);
     }
   }
   __syncthreads();
@@ -399,7 +438,10 @@ __global__ __launch_bounds__(NT) void k_bm_single(AggArgs a) {
     end = a.off[v + 1];
     kv = a.k[v];
   }
-  const int64_t pk = a.p * kv;
+  int64_t lp = 0, lq = 1;
+  int32_t job = 0;
+  if (valid) job_lambda(a, v, lp, lq, job);
+  const int64_t pk = lp * kv;
   int64_t best_s = INT64_MIN, wc = 0;
   int32_t best_id = ISO_ID;
   for (int64_t base = beg + gl; base < end; base += 4 * G) {
@@ -416,7 +458,7 @@ __global__ __launch_bounds__(NT) void k_bm_single(AggArgs a) {
 #pragma unroll
     for (int j = 0; j < 4; j++) {
       if (u[j] < 0) continue;
-      const int64_t sc = a.q * w[j] - pk * ku[j];
+      const int64_t sc = lq * w[j] - pk * ku[j];
       if (better(sc, u[j], best_s, best_id)) {
         best_s = sc;
         best_id = u[j];
@@ -443,6 +485,7 @@ __global__ __launch_bounds__(NT) void k_bm_single(AggArgs a) {
   }
   const bool moved = valid && d != v;
   if (valid && gl == 0) a.D[v] = d;
+  if (moved && gl == 0) count_job_mover(a, job);
   if (moved && a.next_flag)
     for (int64_t e = beg + gl; e < end; e += G) a.next_flag[a.col[e]] = 1;
   flush_counters<NT>(a.ctr, (moved && gl == 0) ? 1 : 0, (valid && gl == 0) ? end - beg + 1 : 0,
@@ -572,7 +615,10 @@ __global__ __launch_bounds__(B7_NT) void k_b7_segscore(AggArgs a, int64_t n7, co
   const int64_t i = lo;
   const int32_t v = a.list[i];
   const int32_t c = a.C[v];
-  const int64_t pk = a.p * a.k[v];
+  int64_t lp, lq;
+  int32_t job;
+  job_lambda(a, v, lp, lq, job);
+  const int64_t pk = lp * a.k[v];
   const int64_t t0 = tstart[i], H = tstart[i + 1] - t0;
   const int64_t j0 = (sg - sstart[i]) * B7_SEG;
   const int64_t j1 = j0 + B7_SEG < H ? j0 + B7_SEG : H;
@@ -588,7 +634,7 @@ __global__ __launch_bounds__(B7_NT) void k_b7_segscore(AggArgs a, int64_t n7, co
     if (X == c) {
       wc = wx;
     } else {
-      const int64_t sc = a.q * wx - pk * a.K[X];
+      const int64_t sc = lq * wx - pk * a.K[X];
       if (better(sc, X, best_s, best_id)) {
         best_s = sc;
         best_id = X;
@@ -631,13 +677,17 @@ __global__ __launch_bounds__(B7_NT) void k_b7_final(AggArgs a, const int64_t *__
   block_best<B7_NT>(best_s, best_id, wc);
   int64_t movers = 0, marcs = 0;
   if (t == 0) {
-    const int64_t stay = a.q * wc - a.p * kv * (Kc - kv);
+    int64_t lp, lq;
+    int32_t job;
+    job_lambda(a, v, lp, lq, job);
+    const int64_t stay = lq * wc - lp * kv * (Kc - kv);
     const int32_t d = decide(best_s, best_id, stay, a.allow_iso && cntc >= 2, c);
     a.D[v] = d;
     sh_d = d;
     if (d != c) {
       movers = 1;
       marcs = end - beg;
+      count_job_mover(a, job);
     }
   }
   __syncthreads();
@@ -691,12 +741,24 @@ __global__ void k_fresh_flags(const int32_t *__restrict__ cnt, int64_t n, uint8_
   }
 }
 
-// elist[r] = the r-th empty id, for the first T ranks.
-__global__ void k_empty_list(const uint8_t *__restrict__ empty, const int32_t *__restrict__ rank_e, int64_t n,
-                             const int32_t *__restrict__ T, int32_t *__restrict__ elist) {
-  const int32_t t = *T;
-  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x)
-    if (empty[x] && rank_e[x] < t) elist[rank_e[x]] = (int32_t)x;
+// Ranks are taken per job (one job: the whole id range).  rank_f / rank_e
+// are exclusive prefix counts with the total stored at index n.  The empty id
+// of local rank r inside job j is stored at elist[rank_f[base_j] + r], the
+// slot of the job's r-th fresh cluster, for r below the job's fresh count.
+__global__ void k_empty_list(const uint8_t *__restrict__ empty, const int32_t *__restrict__ rank_e,
+                             const int32_t *__restrict__ rank_f, int64_t n, JobView jv,
+                             int32_t *__restrict__ elist) {
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) {
+    if (!empty[x]) continue;
+    int64_t b = 0, e = n;
+    if (jv.jid) {
+      const int32_t j = jv.jid[x];
+      b = jv.jbase[j];
+      e = jv.jbase[j + 1];
+    }
+    const int32_t r = rank_e[x] - rank_e[b];
+    if (r < rank_f[e] - rank_f[b]) elist[rank_f[b] + r] = (int32_t)x;
+  }
 }
 
 // The r-th non-empty fresh cluster takes the r-th empty id (totals moved).
@@ -729,9 +791,12 @@ __global__ void k_fresh_relabel(int32_t *__restrict__ C, int64_t n, const int32_
 
 // --- partition of the active vertices into (sub-round, bin) buckets
 
+// Vertices of stopped jobs get bucket NOBUCKET and are left out.
+constexpr uint16_t NOBUCKET = 0xFFFF;
+
 __global__ __launch_bounds__(BM_NT) void k_part_count(const int32_t *__restrict__ list, int64_t na,
                                                       const int64_t *__restrict__ off, uint64_t h, int32_t S,
-                                                      int64_t wide_max, uint16_t *__restrict__ bucket_of,
+                                                      int64_t wide_max, JobView jv, uint16_t *__restrict__ bucket_of,
                                                       int64_t *__restrict__ bcnt, int64_t *__restrict__ barcs) {
   extern __shared__ int64_t sm[];
   const int NB = S * NBINS;
@@ -741,8 +806,17 @@ __global__ __launch_bounds__(BM_NT) void k_part_count(const int32_t *__restrict_
   __syncthreads();
   for (int64_t i = (int64_t)blockIdx.x * BM_NT + threadIdx.x; i < na; i += (int64_t)gridDim.x * BM_NT) {
     const int32_t v = list ? list[i] : (int32_t)i;
+    int64_t local = v;
+    if (jv.jid) {
+      const int32_t j = jv.jid[v];
+      if (!jv.jrun[j]) {
+        bucket_of[i] = NOBUCKET;
+        continue;
+      }
+      local = v - jv.jbase[j];
+    }
     const int64_t deg = off[v + 1] - off[v];
-    const int s = (int)(mix64(h ^ (uint64_t)(int64_t)v) % (uint64_t)S);
+    const int s = (int)(mix64(h ^ (uint64_t)local) % (uint64_t)S);
     const int b = s * NBINS + bin_of(deg, wide_max);
     bucket_of[i] = (uint16_t)b;
     atomicAdd(reinterpret_cast<unsigned long long *>(&lc[b]), 1ull);
@@ -783,7 +857,7 @@ __global__ __launch_bounds__(BM_NT) void k_part_scatter(const int32_t *__restric
   const int64_t beg = (int64_t)blockIdx.x * per;
   const int64_t end = beg + per < na ? beg + per : na;
   for (int64_t i = beg + threadIdx.x; i < end; i += BM_NT)
-    atomicAdd(reinterpret_cast<unsigned long long *>(&lc[bucket_of[i]]), 1ull);
+    if (bucket_of[i] != NOBUCKET) atomicAdd(reinterpret_cast<unsigned long long *>(&lc[bucket_of[i]]), 1ull);
   __syncthreads();
   for (int i = threadIdx.x; i < NB; i += BM_NT) {
     lbase[i] = lc[i] ? (int64_t)atomicAdd(reinterpret_cast<unsigned long long *>(&cursor[i]),
@@ -794,6 +868,7 @@ __global__ __launch_bounds__(BM_NT) void k_part_scatter(const int32_t *__restric
   __syncthreads();
   for (int64_t i = beg + threadIdx.x; i < end; i += BM_NT) {
     const int b = bucket_of[i];
+    if (b == NOBUCKET) continue;
     const int64_t r = (int64_t)atomicAdd(reinterpret_cast<unsigned long long *>(&lc[b]), 1ull);
     out[lbase[b] + r] = list ? list[i] : (int32_t)i;
   }
@@ -966,22 +1041,21 @@ const char *bin_name(int b) {
 
 // Renames the non-empty fresh clusters to the smallest empty ids (see the
 // file comment); checks the pairing error counter.
-void rename_fresh(Ctx &c, int64_t n, int32_t *C, int64_t *K, int32_t *cnt, int64_t *err) {
+void rename_fresh(Ctx &c, int64_t n, int32_t *C, int64_t *K, int32_t *cnt, int64_t *err, const JobView &jv) {
   Ctx::Timer tm(&c, "bm_rename", 0.0, (double)n);
   const size_t nn = (size_t)n;
   uint8_t *fresh = c.buf<uint8_t>("rn.fresh", nn);
   uint8_t *empty = c.buf<uint8_t>("rn.empty", nn);
-  int32_t *rank_f = c.buf<int32_t>("rn.rankf", nn);
-  int32_t *rank_e = c.buf<int32_t>("rn.ranke", nn);
+  int32_t *rank_f = c.buf<int32_t>("rn.rankf", nn + 1);
+  int32_t *rank_e = c.buf<int32_t>("rn.ranke", nn + 1);
   int32_t *elist = c.buf<int32_t>("rn.elist", nn);
   int32_t *newid = c.buf<int32_t>("rn.newid", nn);
-  int32_t *T = c.buf<int32_t>("rn.T", 2);
   const unsigned grid = (unsigned)std::min<int64_t>(cdiv(n, 256), 65536);
   hipLaunchKernelGGL(k_fresh_flags, dim3(grid), dim3(256), 0, c.stream, cnt, n, fresh, empty);
   LAUNCHCHECK();
-  scan<uint8_t, int32_t>(c, fresh, rank_f, n, false, T);
-  scan<uint8_t, int32_t>(c, empty, rank_e, n, false, T + 1);
-  hipLaunchKernelGGL(k_empty_list, dim3(grid), dim3(256), 0, c.stream, empty, rank_e, n, T, elist);
+  scan<uint8_t, int32_t>(c, fresh, rank_f, n, false, rank_f + n);
+  scan<uint8_t, int32_t>(c, empty, rank_e, n, false, rank_e + n);
+  hipLaunchKernelGGL(k_empty_list, dim3(grid), dim3(256), 0, c.stream, empty, rank_e, rank_f, n, jv, elist);
   LAUNCHCHECK();
   hipLaunchKernelGGL(k_fresh_move, dim3(grid), dim3(256), 0, c.stream, fresh, rank_f, elist, n, K, cnt, newid, err);
   LAUNCHCHECK();
@@ -995,7 +1069,24 @@ void rename_fresh(Ctx &c, int64_t n, int32_t *C, int64_t *K, int32_t *cnt, int64
 }  // namespace
 
 void best_moves(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_params &prm, int32_t level,
-                int32_t phase, int32_t *C, const BMShape &shape, lcc_bm_stats &st) {
+                int32_t phase, int32_t *C, const BMShape &shape, lcc_bm_stats &st, const BatchLevel *bl) {
+  JobView jv;
+  int64_t J = 0;
+  std::vector<uint8_t> hrun;
+  if (bl) {
+    J = bl->jobs;
+    jv.jid = bl->jid;
+    jv.jbase = bl->jbase;
+    jv.jp = bl->jp;
+    jv.jq = bl->jq;
+    jv.jrun = c.buf<uint8_t>("bt.run", (size_t)J);
+    jv.jmoved = c.buf<int64_t>("bt.moved", (size_t)J);
+    hrun.assign(bl->active, bl->active + J);
+    h2d(c, const_cast<uint8_t *>(jv.jrun), hrun.data(), (size_t)J);
+    c.sync();
+    std::fill(bl->iters, bl->iters + J, 0);
+    std::fill(bl->moved_any, bl->moved_any + J, 0);
+  }
   const bool identity = shape.identity, acc32 = shape.acc32;
   const int64_t maxdeg = shape.maxdeg;
   std::memset(&st, 0, sizeof(st));
@@ -1046,11 +1137,16 @@ void best_moves(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_para
     const uint64_t h = round_hash(prm.seed, level, phase, it);
     st.iterations++;
     HIPCHECK(hipMemsetAsync(dctr, 0, nctr * sizeof(int64_t), c.stream));
+    if (bl) {
+      HIPCHECK(hipMemsetAsync(jv.jmoved, 0, (size_t)J * sizeof(int64_t), c.stream));
+      for (int64_t j = 0; j < J; j++)
+        if (hrun[j]) bl->iters[j]++;
+    }
     if (na > 0) {
       const size_t smem = (size_t)2 * NB * sizeof(int64_t);
       int64_t grid = std::min<int64_t>(cdiv(na, BM_NT * 8), (int64_t)c.num_cu * 8);
       hipLaunchKernelGGL(k_part_count, dim3((unsigned)grid), dim3(BM_NT), smem, c.stream, list, na, g.off, h, S,
-                         wide_max, bucket_of, bcnt, barcs);
+                         wide_max, jv, bucket_of, bcnt, barcs);
       LAUNCHCHECK();
       hipLaunchKernelGGL(k_part_starts, dim3(1), dim3(1), 0, c.stream, bcnt, cursor, NB);
       LAUNCHCHECK();
@@ -1094,6 +1190,7 @@ void best_moves(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_para
         a.gkeys = nullptr;
         a.gvals = nullptr;
         a.hcap = 0;
+        a.jv = jv;
         const int64_t arcs_i = hctr[NB + bi];
         const double arcs_b = (double)arcs_i;
         // first sub-round from singletons on rows without repeats: no
@@ -1150,7 +1247,25 @@ void best_moves(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_para
     int64_t isolated = 0;
     for (int s = 0; s < S; s++) isolated += hl[(size_t)LC * NB + s];
     if (cap_err) fail(LCC_ERR_DEVICE, "internal: a vertex degree exceeded the hash capacity sized from the maximum degree");
-    if (isolated) rename_fresh(c, n, C, K, cnt, iso_err);
+    if (isolated) rename_fresh(c, n, C, K, cnt, iso_err, jv);
+    if (bl) {
+      // per-job termination: a job without moves in this iteration stops
+      std::vector<int64_t> hm((size_t)J);
+      d2h(c, hm.data(), jv.jmoved, (size_t)J * sizeof(int64_t));
+      bool changed = false;
+      for (int64_t j = 0; j < J; j++) {
+        if (!hrun[j]) continue;
+        if (hm[j]) bl->moved_any[j] = 1;
+        if (!hm[j] && !stopped) {
+          hrun[j] = 0;
+          changed = true;
+        }
+      }
+      if (changed) {
+        h2d(c, const_cast<uint8_t *>(jv.jrun), hrun.data(), (size_t)J);
+        c.sync();
+      }
+    }
     if (c.timing) {
       for (auto &L : launches) {
         if (L.pending_idx < c.pending.size()) {

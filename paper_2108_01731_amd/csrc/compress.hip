@@ -146,8 +146,10 @@ void cluster_sums_k_kk(Ctx &c, const lcc_graph &g, const int32_t *C, int64_t *K,
 
 __global__ void k_flatten(const int32_t *__restrict__ map, const int32_t *__restrict__ Cn, int32_t *__restrict__ C,
                           int64_t n) {
-  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
-    C[v] = Cn[map[v]];
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t m = map[v];
+    if (m >= 0) C[v] = Cn[m];  // map < 0: the vertex's job stopped coarsening at this level
+  }
 }
 
 void flatten(Ctx &c, int64_t n, const int32_t *map, const int32_t *Cnext, int32_t *C) {
@@ -201,15 +203,48 @@ int64_t canonical_labels(Ctx &c, int64_t n, const int32_t *C, int32_t *labels) {
 
 // ------------------------------------------------------------------ compress
 
-__global__ void k_mark_present(const int32_t *__restrict__ C, int64_t n, uint8_t *__restrict__ present) {
+// In batched runs only the vertices of continuing jobs are kept; the others
+// get map = -1 and take no part in the contracted graph.
+__device__ __forceinline__ bool kept(const int32_t *jid, const uint8_t *jcont, int64_t v) {
+  return !jid || jcont[jid[v]];
+}
+
+__global__ void k_mark_present(const int32_t *__restrict__ C, int64_t n, const int32_t *__restrict__ jid,
+                               const uint8_t *__restrict__ jcont, uint8_t *__restrict__ present) {
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
-    present[C[v]] = 1;
+    if (kept(jid, jcont, v)) present[C[v]] = 1;
 }
 
 __global__ void k_map(const int32_t *__restrict__ C, const int32_t *__restrict__ rank, int64_t n,
-                      int32_t *__restrict__ map) {
+                      const int32_t *__restrict__ jid, const uint8_t *__restrict__ jcont, int32_t *__restrict__ map) {
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
-    map[v] = rank[C[v]];
+    map[v] = kept(jid, jcont, v) ? rank[C[v]] : -1;
+}
+
+// Sort keys for the per-cluster sums: dropped vertices go to the extra key n2.
+__global__ void k_keys_with_sentinel(const int32_t *__restrict__ map, int64_t n, int32_t n2, int32_t *__restrict__ key) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+    key[v] = map[v] < 0 ? n2 : map[v];
+}
+
+// Job of every contracted vertex, and the job bases of the next level.
+__global__ void k_next_jid(const int32_t *__restrict__ map, const int32_t *__restrict__ jid, int64_t n,
+                           int32_t *__restrict__ jid_next) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+    if (map[v] >= 0) jid_next[map[v]] = jid[v];
+}
+
+__global__ void k_next_jbase(const int32_t *__restrict__ jid_next, int64_t n2, int64_t jobs,
+                             int64_t *__restrict__ jbase_next) {
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j <= jobs; j += (int64_t)gridDim.x * blockDim.x) {
+    int64_t lo = 0, hi = n2;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (jid_next[mid] < j) lo = mid + 1;
+      else hi = mid;
+    }
+    jbase_next[j] = lo;
+  }
 }
 
 // G lanes per vertex: number of inter-cluster arcs and weight of intra arcs.
@@ -221,7 +256,7 @@ __global__ __launch_bounds__(CP_NT) void k_cp_count(const int64_t *__restrict__ 
   const int gl = threadIdx.x % G;
   const int64_t v = (int64_t)blockIdx.x * (CP_NT / G) + threadIdx.x / G;
   int64_t ni = 0, wi = 0;
-  if (v < n) {
+  if (v < n && map[v] >= 0) {
     const int32_t mv = map[v];
     for (int64_t e = off[v] + gl; e < off[v + 1]; e += G) {
       if (map[col[e]] != mv) ni++;
@@ -253,7 +288,7 @@ __global__ __launch_bounds__(CP_NT) void k_cp_emit(const int64_t *__restrict__ o
   const uint64_t gmask = G >= 64 ? ~0ull : ((1ull << (G & 63)) - 1);
   int64_t beg = 0, end = 0, pos = 0;
   int32_t mv = 0;
-  if (v < n) {
+  if (v < n && map[v] >= 0) {
     beg = off[v];
     end = off[v + 1];
     pos = eoff[v];
@@ -403,7 +438,9 @@ void dispatch_ce(Ctx &c, const lcc_graph &g, const int32_t *map, int64_t *inter,
 }  // namespace
 
 void compress_graph(Ctx &c, const lcc_graph &g, const int32_t *C, OwnedGraph &out, int32_t *map, bool wide,
-                    int64_t *maxdeg_out) {
+                    int64_t *maxdeg_out, const CompressJobs *cj) {
+  const int32_t *jid = cj ? cj->jid : nullptr;
+  const uint8_t *jcont = cj ? cj->jcont : nullptr;
   const int64_t n = g.n;
   out.n = 0;
   out.arcs = 0;
@@ -424,10 +461,10 @@ void compress_graph(Ctx &c, const lcc_graph &g, const int32_t *C, OwnedGraph &ou
   {
     Ctx::Timer tm(&c, "cp_relabel", 13.0 * (double)n, (double)n);
     HIPCHECK(hipMemsetAsync(present, 0, nn, c.stream));
-    hipLaunchKernelGGL(k_mark_present, dim3(grid_for(n)), dim3(256), 0, c.stream, C, n, present);
+    hipLaunchKernelGGL(k_mark_present, dim3(grid_for(n)), dim3(256), 0, c.stream, C, n, jid, jcont, present);
     LAUNCHCHECK();
     scan<uint8_t, int32_t>(c, present, rank, n, false, reinterpret_cast<int32_t *>(tots));
-    hipLaunchKernelGGL(k_map, dim3(grid_for(n)), dim3(256), 0, c.stream, C, rank, n, map);
+    hipLaunchKernelGGL(k_map, dim3(grid_for(n)), dim3(256), 0, c.stream, C, rank, n, jid, jcont, map);
     LAUNCHCHECK();
   }
   const int wb = wt_bytes(g.wt_kind);
@@ -479,9 +516,10 @@ void compress_graph(Ctx &c, const lcc_graph &g, const int32_t *C, OwnedGraph &ou
   out.off.ensure((size_t)(n2 + 1) * sizeof(int64_t));
   out.col.ensure((size_t)(U > 0 ? U : 1) * sizeof(int32_t));
   out.wt.ensure((size_t)(U > 0 ? U : 1) * (wide ? 8 : 4));
-  out.k.ensure((size_t)(n2 > 0 ? n2 : 1) * sizeof(int64_t));
-  out.s.ensure((size_t)(n2 > 0 ? n2 : 1) * sizeof(int64_t));
-  out.kk.ensure((size_t)(n2 > 0 ? n2 : 1) * sizeof(int64_t));
+  // one extra slot: the per-cluster sums park dropped vertices at key n2
+  out.k.ensure((size_t)(n2 + 1) * sizeof(int64_t));
+  out.s.ensure((size_t)(n2 + 1) * sizeof(int64_t));
+  out.kk.ensure((size_t)(n2 + 1) * sizeof(int64_t));
   int32_t *orow = c.buf<int32_t>("cp.row", (size_t)(U > 0 ? U : 1));
   if (U > 0) {
     Ctx::Timer tm(&c, "cp_unique", (double)U * (8.0 + 8.0 + 4.0 + 4.0 + (wide ? 8 : 4)), (double)U);
@@ -507,13 +545,29 @@ void compress_graph(Ctx &c, const lcc_graph &g, const int32_t *C, OwnedGraph &ou
   // per-cluster k', kk', s'
   {
     Ctx::Timer tm(&c, "cp_totals", 0.0, (double)n);
-    ByKey bk = sort_by_key(c, map, n, n2, "cpv");
-    int64_t *start = c.buf<int64_t>("cpv.start", (size_t)(n2 > 0 ? n2 : 1));
+    const int32_t *keys = map;
+    int64_t nkeys = n2;
+    if (jid) {
+      int32_t *kb = c.buf<int32_t>("cpv.keys", nn);
+      hipLaunchKernelGGL(k_keys_with_sentinel, dim3(grid_for(n)), dim3(256), 0, c.stream, map, n, (int32_t)n2, kb);
+      LAUNCHCHECK();
+      keys = kb;
+      nkeys = n2 + 1;
+    }
+    ByKey bk = sort_by_key(c, keys, n, nkeys, "cpv");
+    int64_t *start = c.buf<int64_t>("cpv.start", (size_t)(nkeys > 0 ? nkeys : 1));
     hipLaunchKernelGGL(k_seg_heads, dim3(grid_for(n)), dim3(256), 0, c.stream, bk.key, n, start);
     LAUNCHCHECK();
-    seg_sum(c, bk, n, n2, start, G_K, g, nullptr, out.k.as<int64_t>(), nullptr, false);
-    seg_sum(c, bk, n, n2, start, G_KK, g, nullptr, out.kk.as<int64_t>(), nullptr, false);
-    seg_sum(c, bk, n, n2, start, G_SELF2, g, intra, out.s.as<int64_t>(), nullptr, true);
+    seg_sum(c, bk, n, nkeys, start, G_K, g, nullptr, out.k.as<int64_t>(), nullptr, false);
+    seg_sum(c, bk, n, nkeys, start, G_KK, g, nullptr, out.kk.as<int64_t>(), nullptr, false);
+    seg_sum(c, bk, n, nkeys, start, G_SELF2, g, intra, out.s.as<int64_t>(), nullptr, true);
+  }
+  if (jid) {
+    hipLaunchKernelGGL(k_next_jid, dim3(grid_for(n)), dim3(256), 0, c.stream, map, jid, n, cj->jid_next);
+    LAUNCHCHECK();
+    hipLaunchKernelGGL(k_next_jbase, dim3(grid_for(cj->jobs + 1)), dim3(256), 0, c.stream, cj->jid_next, n2,
+                       cj->jobs, cj->jbase_next);
+    LAUNCHCHECK();
   }
   if (maxdeg_out) *maxdeg_out = max_degree(c, out.off.as<int64_t>(), n2);
 }

@@ -40,16 +40,43 @@ struct BMShape {
   bool simple;      // no row repeats a neighbor
 };
 
+// Jobs of a batched run at one level: the graph holds the jobs' vertices
+// block-diagonally in job order; jobs absent from the level have empty
+// ranges.
+struct BatchLevel {
+  int64_t jobs = 0;
+  const int32_t *jid = nullptr;    // device, job of every vertex
+  const int64_t *jbase = nullptr;  // device, jobs + 1 prefix of per-job vertex counts
+  const int64_t *jp = nullptr;     // device, per-job lambda
+  const int64_t *jq = nullptr;
+  const uint8_t *active = nullptr; // host, per job: takes part in this Best-Moves call
+  int32_t *iters = nullptr;        // host out, per job: iterations started
+  uint8_t *moved_any = nullptr;    // host out, per job
+};
+
 // Best-Moves on graph g from clustering C (device, updated in place).  On
 // return K (device, owned by the context as "bm.K") holds the cluster totals
-// of C.
+// of C.  With `bl`, every job runs its own Best-Moves (own lambda, own
+// termination) in the same launches.
 void best_moves(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_params &prm, int32_t level,
-                int32_t phase, int32_t *C, const BMShape &shape, lcc_bm_stats &st);
+                int32_t phase, int32_t *C, const BMShape &shape, lcc_bm_stats &st,
+                const BatchLevel *bl = nullptr);
+
+// Batched compress: only vertices of jobs with jcont[job] = 1 are kept
+// (the others get map = -1); the jobs of the contracted vertices and the next
+// level's job bases (jobs + 1 entries) are written out.
+struct CompressJobs {
+  int64_t jobs = 0;
+  const int32_t *jid = nullptr;   // device, per vertex
+  const uint8_t *jcont = nullptr; // device, per job
+  int32_t *jid_next = nullptr;    // device out, per contracted vertex
+  int64_t *jbase_next = nullptr;  // device out, jobs + 1
+};
 
 // Compress g by C into `out` (library-owned arrays); map (device int32[n]).
 // `wide` selects int64 output weights (else int32).
 void compress_graph(Ctx &c, const lcc_graph &g, const int32_t *C, OwnedGraph &out, int32_t *map, bool wide,
-                    int64_t *maxdeg_out);
+                    int64_t *maxdeg_out, const CompressJobs *cj = nullptr);
 
 // Exact objective numerator of clustering C (ids in [0, n)).
 i128 objective_num(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const int32_t *C);
@@ -64,10 +91,43 @@ void cluster_sums_k_kk(Ctx &c, const lcc_graph &g, const int32_t *C, int64_t *K,
 // Largest row length of a CSR offset array.
 int64_t max_degree(Ctx &c, const int64_t *off, int64_t n);
 
-// C[v] = Cnext[map[v]] for v < n.
+// C[v] = Cnext[map[v]] for v < n with map[v] >= 0.
 void flatten(Ctx &c, int64_t n, const int32_t *map, const int32_t *Cnext, int32_t *C);
 
 // C[v] = v.
 void iota_i32(Ctx &c, int32_t *C, int64_t n);
+
+// ---- batched runs (jobs packed block-diagonally, job j owns [start_j, start_j+1))
+
+// Largest vertex range handled by one block of the per-job sums; chunks are
+// (job, first vertex, end vertex) triples that never span two jobs.
+constexpr int64_t BATCH_CHUNK = 2048;
+
+// jid[v] = job owning v (jstart: device, jobs + 1 entries).
+void batch_fill_jid(Ctx &c, const int64_t *jstart, int64_t jobs, int64_t n, int32_t *jid);
+
+// Per chunk: {sum |w| over arcs, sum k, sum kk (k^2 when absent), sum |s|,
+// negative flag, arc-leaves-job flag}, saturating at 2^64 - 1.  Arcs are read
+// when check_arcs is set or weights are stored; else sum |w| is the arc count.
+std::vector<uint64_t> batch_vertex_sums(Ctx &c, const lcc_graph &g, const int64_t *jstart,
+                                        const std::vector<int64_t> &chunks, bool check_arcs);
+
+// Batched flatten: C[v] = Cnext[map[v]] - jbase_next[job] + jbase[job] for
+// map[v] >= 0 (a job's ids move from its coarser range to its range here).
+void batch_flatten(Ctx &c, int64_t n, const int32_t *map, const int32_t *Cnext, const int32_t *jid,
+                   const int64_t *jbase, const int64_t *jbase_next, int32_t *C);
+
+// labels[v] = glab[v] - glab[first vertex of v's job].
+void batch_local_labels(Ctx &c, const int32_t *glab, const int32_t *jid, const int64_t *jstart, int64_t n,
+                        int32_t *labels);
+
+// glab of every job's first vertex (-1 for empty jobs).
+std::vector<int32_t> batch_first_labels(Ctx &c, const int32_t *glab, const int64_t *jstart, int64_t jobs);
+
+// Objective pieces per chunk: intra-cluster arc weight and sum s over vertex
+// chunks of C, sum (K^2 - KK) over cluster-id chunks.
+void batch_objective_parts(Ctx &c, const lcc_graph &g, const int32_t *C, const std::vector<int64_t> &vchunks,
+                           const int64_t *K, const int64_t *KK, const std::vector<int64_t> &cchunks,
+                           std::vector<i128> &intra, std::vector<i128> &self, std::vector<i128> &pairs);
 
 }  // namespace lcc

@@ -394,3 +394,108 @@ def c1_sbm(seed: int = 1, device="cpu") -> HostGraph:
     """The small plain-method workload: 10,000 vertices in 20 blocks of 500,
     p_in = 0.02, p_out = 0.0005, k = 1 (run with lambda = 1/100)."""
     return sbm([500] * 20, 0.02, 0.0005, seed, device)
+
+
+# ------------------------------------------------------------- batched jobs
+
+
+def sbm_blocks(n: int, block: int, avg_deg: float, mixing: float, seed: int, device="cpu") -> HostGraph:
+    """SBM on n vertices in max(1, round(n / block)) near-equal blocks with
+    expected degree avg_deg, a fraction `mixing` of it across blocks.  Every
+    pair is an independent Bernoulli trial (p_in inside a block, p_out
+    across): all pairs are drawn at p_out and the pairs inside blocks again at
+    (p_in - p_out) / (1 - p_out); the union has the SBM law.  Unit weights,
+    k = 1, seeded vertex relabel."""
+    device = torch.device(device)
+    gen = _gen(seed, device)
+    nb = max(1, int(round(n / block)))
+    base_size, extra = divmod(n, nb)
+    sizes = torch.full((nb,), base_size, dtype=torch.int64, device=device)
+    sizes[:extra] += 1
+    starts = torch.zeros(nb, dtype=torch.int64, device=device)
+    starts[1:] = torch.cumsum(sizes, 0)[:-1]
+    smax = base_size + (1 if extra else 0)
+    mean_s = n / nb
+    p_in = min(1.0, avg_deg * (1.0 - mixing) / max(mean_s - 1.0, 1.0)) if mean_s > 1 else 0.0
+    p_out = min(1.0, avg_deg * mixing / max(n - mean_s, 1.0)) if nb > 1 else 0.0
+    us, vs = [], []
+    if p_out > 0:
+        idx = _bernoulli_positions(n * n, p_out, gen, device)
+        i, j = idx // n, idx % n
+        keep = i < j
+        us.append(i[keep])
+        vs.append(j[keep])
+    p2 = (p_in - p_out) / (1.0 - p_out) if p_out < 1.0 else 0.0
+    if p2 > 0 and smax > 1:
+        idx = _bernoulli_positions(nb * smax * smax, p2, gen, device)
+        blk = idx // (smax * smax)
+        r = idx % (smax * smax)
+        i, j = r // smax, r % smax
+        sz = sizes[blk]
+        keep = (i < j) & (j < sz)
+        us.append(i[keep] + starts[blk[keep]])
+        vs.append(j[keep] + starts[blk[keep]])
+    u = torch.cat(us) if us else torch.zeros(0, dtype=torch.int64, device=device)
+    v = torch.cat(vs) if vs else torch.zeros(0, dtype=torch.int64, device=device)
+    off, col, _ = csr_from_edges(n, u, v, device=device)
+    perm = torch.randperm(n, generator=gen, device=device)
+    off, col, _ = relabel(off, col, None, perm)
+    return HostGraph(off, col, torch.ones(n, dtype=torch.int64, device=device))
+
+
+def sbm_job_spec(i: int, seed: int = 0, nmin: int = 100, nmax: int = 50000):
+    """Shape of job i of the many-graph batch: n log-uniform in [nmin, nmax],
+    average degree uniform in [8, 40], lambda = p / 1000 with p uniform in
+    [1, 500].  Returns (n, avg_deg, p, q)."""
+    rng = np.random.default_rng([seed, i])
+    n = int(round(math.exp(rng.uniform(math.log(nmin), math.log(nmax)))))
+    d = float(rng.uniform(8.0, 40.0))
+    p = int(rng.integers(1, 501))
+    return n, d, p, 1000
+
+
+def pack(graphs) -> tuple:
+    """Packs graphs block-diagonally into one HostGraph (numpy arrays).
+    Returns (graph, job_start int64[len(graphs) + 1]).  Weight storage must
+    agree (all unit or all the same integer type); missing s is 0 and missing
+    kk is k^2."""
+    gs = [g.numpy() for g in graphs]
+    ns = np.array([g.n for g in gs], dtype=np.int64)
+    ms = np.array([g.arcs for g in gs], dtype=np.int64)
+    vstart = np.zeros(len(gs) + 1, dtype=np.int64)
+    vstart[1:] = np.cumsum(ns)
+    astart = np.zeros(len(gs) + 1, dtype=np.int64)
+    astart[1:] = np.cumsum(ms)
+    kinds = {g.wt_kind if g.wt is not None else "none" for g in gs}
+    if len(kinds) > 1:
+        raise ValueError(f"mixed weight storage in one batch: {sorted(kinds)}")
+    kind = kinds.pop() if kinds else "none"
+    off = np.concatenate([np.asarray(g.off[:-1], dtype=np.int64) + astart[j] for j, g in enumerate(gs)] +
+                         [np.array([astart[-1]], dtype=np.int64)])
+    col = np.concatenate([np.asarray(g.col, dtype=np.int64) + vstart[j] for j, g in enumerate(gs)] +
+                         [np.zeros(0, dtype=np.int64)]).astype(np.int32)
+    k = np.concatenate([np.asarray(g.k, dtype=np.int64) for g in gs] + [np.zeros(0, dtype=np.int64)])
+    wt = None
+    if kind != "none":
+        wt = np.concatenate([np.asarray(g.wt) for g in gs])
+    s = None
+    if any(g.s is not None for g in gs):
+        s = np.concatenate([np.asarray(g.s, dtype=np.int64) if g.s is not None else np.zeros(g.n, dtype=np.int64)
+                            for g in gs])
+    kk = None
+    if any(g.kk is not None for g in gs):
+        kk = np.concatenate([np.asarray(g.kk, dtype=np.int64) if g.kk is not None
+                             else np.asarray(g.k, dtype=np.int64) ** 2 for g in gs])
+    return HostGraph(off, col, k, wt, s, kk, kind), vstart
+
+
+def job_slice(g: HostGraph, job_start, j: int) -> HostGraph:
+    """Job j of a packed graph as a graph of its own (numpy arrays)."""
+    h = g.numpy()
+    a, b = int(job_start[j]), int(job_start[j + 1])
+    off = np.asarray(h.off[a:b + 1], dtype=np.int64)
+    e0, e1 = int(off[0]), int(off[-1])
+    col = (np.asarray(h.col[e0:e1], dtype=np.int64) - a).astype(np.int32)
+    return HostGraph(off - e0, col, np.asarray(h.k[a:b]), None if h.wt is None else np.asarray(h.wt[e0:e1]),
+                     None if h.s is None else np.asarray(h.s[a:b]), None if h.kk is None else np.asarray(h.kk[a:b]),
+                     h.wt_kind)

@@ -79,6 +79,20 @@ class _ClusterStats(ctypes.Structure):
     ]
 
 
+class _JobOut(ctypes.Structure):
+    _fields_ = [("obj", _Objective), ("clusters", ctypes.c_int64), ("levels", ctypes.c_int32),
+                ("top_moved", ctypes.c_int32)]
+
+
+class _BatchStats(ctypes.Structure):
+    _fields_ = [
+        ("levels", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+        ("n_level", ctypes.c_int64 * MAX_LEVELS), ("arcs_level", ctypes.c_int64 * MAX_LEVELS),
+        ("moves_total", ctypes.c_int64), ("arcs_scanned_total", ctypes.c_int64),
+        ("ms_best_move", ctypes.c_double), ("ms_compress", ctypes.c_double), ("ms_total", ctypes.c_double),
+    ]
+
+
 class _KernelStat(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 64), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double),
                 ("bytes", ctypes.c_double), ("items", ctypes.c_double)]
@@ -86,8 +100,8 @@ class _KernelStat(ctypes.Structure):
 
 EXPORTS = (
     "lcc_params_default", "lcc_last_error", "lcc_ctx_create", "lcc_ctx_destroy", "lcc_best_move", "lcc_compress",
-    "lcc_graph_owned_view", "lcc_graph_owned_free", "lcc_objective", "lcc_cluster", "lcc_ctx_kernel_stats",
-    "lcc_ctx_reset_kernel_stats",
+    "lcc_graph_owned_view", "lcc_graph_owned_free", "lcc_objective", "lcc_cluster", "lcc_cluster_batch",
+    "lcc_ctx_kernel_stats", "lcc_ctx_reset_kernel_stats",
 )
 
 _lib = None
@@ -124,6 +138,10 @@ def load_library(path: str = LIB_PATH):
     lib.lcc_cluster.restype = st
     lib.lcc_cluster.argtypes = [P, gp, _Lambda, ctypes.POINTER(_Params), P, ctypes.POINTER(_Objective),
                                 ctypes.POINTER(_ClusterStats), P]
+    lib.lcc_cluster_batch.restype = st
+    lib.lcc_cluster_batch.argtypes = [P, gp, i64, ctypes.POINTER(i64), ctypes.POINTER(_Lambda),
+                                      ctypes.POINTER(_Params), P, ctypes.POINTER(_JobOut),
+                                      ctypes.POINTER(_BatchStats), P]
     lib.lcc_ctx_kernel_stats.restype = st
     lib.lcc_ctx_kernel_stats.argtypes = [P, ctypes.POINTER(_KernelStat), i32, ctypes.POINTER(i32)]
     lib.lcc_ctx_reset_kernel_stats.restype = st
@@ -355,3 +373,29 @@ def lcc_cluster(ctx: Context, g: DeviceGraph, p: int, q: int, params: Params, st
              "arcs_scanned_total": cs.arcs_scanned_total, "clusters": cs.clusters,
              "ms_best_move": cs.ms_best_move, "ms_compress": cs.ms_compress, "ms_total": cs.ms_total}
     return lab, _num(o), stats
+
+
+def lcc_cluster_batch(ctx: Context, g: DeviceGraph, job_start, lambdas, params: Params, stream=None):
+    """Parallel-CC on jobs packed block-diagonally in g (job j owns vertices
+    [job_start[j], job_start[j+1])), each with its own (p, q).  Returns
+    (labels int32 tensor of job-local canonical labels, per-job list of dicts
+    {N, clusters, levels, top_moved}, batch stats)."""
+    J = len(lambdas)
+    if len(job_start) != J + 1:
+        raise ValueError("job_start needs one more entry than lambdas")
+    starts = (ctypes.c_int64 * (J + 1))(*[int(x) for x in job_start])
+    lams = (_Lambda * max(J, 1))(*[_lam(int(p), int(q)) for p, q in lambdas])
+    outs = (_JobOut * max(J, 1))()
+    bs = _BatchStats()
+    lab = torch.empty(g.n, dtype=torch.int32, device=g.off.device)
+    cg, cp = g._c(), params._c()
+    _check(_lib.lcc_cluster_batch(ctx._h, ctypes.byref(cg), J, starts, lams, ctypes.byref(cp),
+                                  lab.data_ptr() if lab.numel() else None, outs, ctypes.byref(bs),
+                                  _stream_ptr(stream)))
+    jobs = [{"N": _num(outs[j].obj), "clusters": outs[j].clusters, "levels": outs[j].levels,
+             "top_moved": outs[j].top_moved} for j in range(J)]
+    L = bs.levels
+    stats = {"levels": L, "n_level": list(bs.n_level[:L]), "arcs_level": list(bs.arcs_level[:L]),
+             "moves_total": bs.moves_total, "arcs_scanned_total": bs.arcs_scanned_total,
+             "ms_best_move": bs.ms_best_move, "ms_compress": bs.ms_compress, "ms_total": bs.ms_total}
+    return lab, jobs, stats

@@ -46,6 +46,8 @@ def test_struct_layout_matches_header(tmp_path):
         "lcc_bm_stats": (L._BMStats, ["iterations", "moves", "candidates", "active_per_iter", "moves_per_iter"]),
         "lcc_objective_out": (L._Objective, ["num_hi", "num_lo", "den", "value"]),
         "lcc_cluster_stats": (L._ClusterStats, ["levels", "n_level", "iters_refine", "clusters", "ms_total"]),
+        "lcc_job_out": (L._JobOut, ["obj", "clusters", "levels", "top_moved"]),
+        "lcc_batch_stats": (L._BatchStats, ["levels", "n_level", "arcs_level", "moves_total", "ms_total"]),
         "lcc_kernel_stat": (L._KernelStat, ["name", "launches", "total_ms", "bytes", "items"]),
     }
     src = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void) {"]
