@@ -29,6 +29,21 @@ WORKLOADS = {
     "sbm_10k": (None, "SBM 20 blocks x 500, p_in=0.02, p_out=0.0005, k=1, lambda=1/100"),
 }
 
+# Many-job workloads: one lcc_cluster_batch call against the plain path (one
+# lcc_cluster call per job, back to back), with every job's result compared.
+BATCH_WORKLOADS = {
+    "batch_sbm_4096": (dict(kind="sbm", jobs=4096, seed=0),
+                       "4096 SBM graphs, n log-uniform in [100, 50000], blocks of ~500, average degree "
+                       "uniform in [8, 40] (20% across blocks), k=1, lambda_i = p_i/1000 with p_i uniform "
+                       "in [1, 500], graph seed i"),
+    "sweep_knn_1m": (dict(kind="sweep", points=1_000_000, centers=1000, dim=64, knn=50, sigma=1.0, seed=1,
+                          count=16),
+                     "16-value lambda sweep on one cosine kNN graph: 1M points of a 1000-center 64-d Gaussian "
+                     "mixture (centers N(0,I), sigma 1.0), k=50 exact neighbours symmetrized by union, weights "
+                     "round(cos*2^15) as int16 (Q1.15), k_v=1; lambda = r*2^15 for r geometric in "
+                     "[0.01, 0.85] as p/1000"),
+}
+
 HBM_PEAK_GBS = 8000.0
 
 
@@ -41,7 +56,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="chung_lu_4m", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="chung_lu_4m", choices=sorted(WORKLOADS) + sorted(BATCH_WORKLOADS))
+    ap.add_argument("--jobs", type=int, default=0, help="batch workloads: use only the first JOBS jobs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one 1 GiB device-to-device copy, a reference for HBM byte counters")
@@ -66,6 +82,8 @@ def main():
         torch.cuda.synchronize()
         log("calibration copy: 1073741824 bytes read, 1073741824 bytes written")
         del src, dst
+    if args.workload in BATCH_WORKLOADS:
+        return run_batch(args, dev)
     gen_kw, desc = WORKLOADS[args.workload]
     t0 = time.time()
     if gen_kw is None:
@@ -149,6 +167,122 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def dominant_kernel(ks):
+    agg = {k: v for k, v in ks.items() if k.startswith(("bm_aggregate", "bm_single"))}
+    name, d = max(agg.items(), key=lambda kv: kv[1]["ms"])
+    achieved = d["bytes"] / (d["ms"] * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": name,
+            "avg_launch_ms": d["ms"] / d["launches"], "launches": d["launches"]}
+
+
+def run_batch(args, dev):
+    import numpy as np
+    import torch
+
+    from paper_2108_01731_amd import graphgen as G
+    from paper_2108_01731_amd import lcc
+
+    spec, desc = BATCH_WORKLOADS[args.workload]
+    t0 = time.time()
+    if spec["kind"] == "sbm":
+        jobs = args.jobs or spec["jobs"]
+        graphs, lams = G.sbm_batch(jobs, spec["seed"], device=dev)
+    else:
+        h = G.knn_gaussian(spec["points"], spec["centers"], spec["dim"], spec["knn"], spec["sigma"], spec["seed"],
+                           device=dev)
+        rs = np.geomspace(0.01, 0.85, spec["count"])
+        lams = [(int(round(r * 1000)) * 32768, 1000) for r in rs]
+        if args.jobs:
+            lams = lams[:args.jobs]
+        graphs = [h] * len(lams)
+    P, start = G.pack_torch(graphs, dev)
+    gp = lcc.DeviceGraph.from_host(P, dev)
+    singles = [lcc.DeviceGraph.from_host(g, dev) for g in graphs]
+    torch.cuda.synchronize()
+    J = len(graphs)
+    log(f"workload {args.workload}: {J} jobs, n={gp.n} arcs={gp.arcs} generated in {time.time() - t0:.1f}s")
+    ctx = lcc.context(0)
+    prm = lcc.Params()
+    for i in range(args.warmup):
+        lab_b, jobs_b, st = lcc.lcc_cluster_batch(ctx, gp, start, lams, prm)
+        log(f"warmup {i}: {st['ms_total']:.1f} ms, levels={st['levels']}")
+    for j in range(min(J, 4)):
+        lcc.lcc_cluster(ctx, singles[j], *lams[j], prm)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        lab_b, jobs_b, st = lcc.lcc_cluster_batch(ctx, gp, start, lams, prm)
+    torch.cuda.synchronize()
+    dt_b = (time.perf_counter() - t0) / args.steps
+    log(f"batched: {dt_b * 1e3:.1f} ms per batch ({J} jobs, levels={st['levels']})")
+    # the plain path: one job at a time
+    labs_p, Ns_p = [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for j in range(J):
+        lab, N, _ = lcc.lcc_cluster(ctx, singles[j], *lams[j], prm)
+        labs_p.append(lab)
+        Ns_p.append(N)
+    torch.cuda.synchronize()
+    dt_p = time.perf_counter() - t0
+    log(f"plain: {dt_p * 1e3:.1f} ms for {J} jobs one at a time; speedup {dt_p / dt_b:.2f}x")
+    same = all(torch.equal(lab_b[int(start[j]):int(start[j + 1])], labs_p[j]) and jobs_b[j]["N"] == Ns_p[j]
+               for j in range(J))
+    log(f"every job identical to its plain run: {same}")
+    # kernel classes of one more batched run, timed per launch
+    ctx.reset_kernel_stats()
+    lcc.lcc_cluster_batch(ctx, gp, start, lams, lcc.Params(timing=1))
+    ks = ctx.kernel_stats()
+    for name, v in sorted(ks.items(), key=lambda kv: -kv[1]["ms"])[:12]:
+        sec = v["ms"] * 1e-3
+        log(f"  {name:24s} launches={v['launches']:6d} ms={v['ms']:8.2f} "
+            f"GB/s={(v['bytes'] / sec / 1e9) if sec > 0 else 0:8.1f}")
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle as O
+
+        t1 = time.perf_counter()
+        arcs_o, done = 0, 0
+        for j in range(J):
+            hn = G.HostGraph(graphs[j].off, graphs[j].col, graphs[j].k, graphs[j].wt, None, None,
+                             graphs[j].wt_kind).numpy()
+            g_o = O.Graph(off=hn.off, col=hn.col, k=hn.k, wt=None if hn.wt is None else hn.wt.astype(np.int64))
+            O.cluster(g_o, *lams[j], O.Params())
+            arcs_o += g_o.arcs
+            done += 1
+            if time.perf_counter() - t1 > 15.0:
+                break
+        cdt = time.perf_counter() - t1
+        cpu = {"value": arcs_o / cdt, "unit": "edges/s", "cores": 1, "kind": "oracle",
+               "sample": f"full clustering of the first {done} of the {J} jobs ({arcs_o} arcs), "
+                         f"{cdt:.1f} s single-threaded"}
+        log(f"cpu oracle: {cpu['value']:.3e} arcs/s over {cdt:.1f}s ({done} jobs)")
+    out = {
+        "metric": "batched clustering edges/s",
+        "value": gp.arcs / dt_b,
+        "unit": "edges/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt_b * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "description": desc, "jobs": J, "n_total": gp.n,
+                   "arcs_total": gp.arcs, "batched_ms": dt_b * 1e3, "plain_ms": dt_p * 1e3,
+                   "speedup_vs_plain": dt_p / dt_b, "jobs_per_s_batched": J / dt_b,
+                   "jobs_per_s_plain": J / dt_p, "identical_results": same},
+        "roofline": dominant_kernel(ks),
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    if not same:
+        sys.exit(1)
 
 
 if __name__ == "__main__":

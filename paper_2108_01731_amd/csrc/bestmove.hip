@@ -101,10 +101,6 @@ __device__ __forceinline__ void job_lambda(const AggArgs &a, int32_t v, int64_t 
   }
 }
 
-__device__ __forceinline__ void count_job_mover(const AggArgs &a, int32_t job) {
-  if (a.jv.jmoved) atomic_add_i64(&a.jv.jmoved[job], 1);
-}
-
 // (score, id) order: higher score first, then lower id.
 __device__ __forceinline__ bool better(int64_t s, int32_t id, int64_t bs, int32_t bid) {
   return s > bs || (s == bs && id < bid);
@@ -321,7 +317,6 @@ __global__ __launch_bounds__(BM_NT) void k_bm_group(AggArgs a) {
     const int32_t d = decide(best_s, best_id, stay, a.allow_iso && cntc >= 2, c);
     moved = d != c;
     if (gl == 0) a.D[v] = d;
-    if (moved && gl == 0) count_job_mover(a, job);
     if (moved && a.next_flag) {
       if constexpr (ONE_PASS) {
         if (u0 >= 0) a.next_flag[u0] = 1;
@@ -406,7 +401,6 @@ __global__ __launch_bounds__(NT) void k_bm_wide(AggArgs a) {
     if (d != c) {
       movers = 1;
       marcs = end - beg;
-      count_job_mover(a, job);
     }
   }
   __syncthreads();
@@ -485,7 +479,6 @@ __global__ __launch_bounds__(NT) void k_bm_single(AggArgs a) {
   }
   const bool moved = valid && d != v;
   if (valid && gl == 0) a.D[v] = d;
-  if (moved && gl == 0) count_job_mover(a, job);
   if (moved && a.next_flag)
     for (int64_t e = beg + gl; e < end; e += G) a.next_flag[a.col[e]] = 1;
   flush_counters<NT>(a.ctr, (moved && gl == 0) ? 1 : 0, (valid && gl == 0) ? end - beg + 1 : 0,
@@ -687,7 +680,6 @@ __global__ __launch_bounds__(B7_NT) void k_b7_final(AggArgs a, const int64_t *__
     if (d != c) {
       movers = 1;
       marcs = end - beg;
-      count_job_mover(a, job);
     }
   }
   __syncthreads();
@@ -700,17 +692,36 @@ __global__ __launch_bounds__(B7_NT) void k_b7_final(AggArgs a, const int64_t *__
 
 // Applies the sub-round's decisions; an isolating vertex v takes the fresh
 // id n + v.
+//
+// Batched runs (jid set) also flag the jobs that moved: the list keeps vertex
+// order within each bin, so a block's movers mostly share a few consecutive
+// jobs; their flags gather in LDS and leave as one plain store per job
+// instead of one global atomic per mover on a handful of addresses.
 __global__ __launch_bounds__(BM_NT) void k_bm_apply(const int32_t *__restrict__ list, int64_t count,
                                                     const int32_t *__restrict__ D, int32_t *__restrict__ C,
                                                     int64_t *__restrict__ K, int32_t *__restrict__ cnt,
                                                     const int64_t *__restrict__ k, int64_t n,
-                                                    int64_t *__restrict__ iso_ctr) {
+                                                    int64_t *__restrict__ iso_ctr, const int32_t *__restrict__ jid,
+                                                    int64_t *__restrict__ jmoved) {
+  constexpr int JW = 64;  // jobs flagged in LDS per block
+  __shared__ int32_t j0;
+  __shared__ int32_t jflag[JW];
   const int64_t i = (int64_t)blockIdx.x * BM_NT + threadIdx.x;
+  if (jid) {
+    if (threadIdx.x == 0) j0 = jid[list[(int64_t)blockIdx.x * BM_NT]];
+    if (threadIdx.x < JW) jflag[threadIdx.x] = 0;
+    __syncthreads();
+  }
   int64_t niso = 0;
   if (i < count) {
     const int32_t v = list[i];
     int32_t d = D[v];
     const int32_t c = C[v];
+    if (d != c && jid) {
+      const int32_t j = jid[v];
+      if (j >= j0 && j - j0 < JW) jflag[j - j0] = 1;
+      else jmoved[j] = 1;
+    }
     if (d != c) {
       const int64_t kv = k[v];
       if (d < 0) {
@@ -728,6 +739,10 @@ __global__ __launch_bounds__(BM_NT) void k_bm_apply(const int32_t *__restrict__ 
   }
   niso = wave_sum(niso);
   if (lane_id() == 0 && niso) atomic_add_i64(iso_ctr, niso);
+  if (jid) {
+    __syncthreads();
+    if (threadIdx.x < JW && jflag[threadIdx.x]) jmoved[j0 + threadIdx.x] = 1;
+  }
 }
 
 // ------------------------------------------------ renaming fresh clusters
@@ -794,17 +809,31 @@ __global__ void k_fresh_relabel(int32_t *__restrict__ C, int64_t n, const int32_
 // Vertices of stopped jobs get bucket NOBUCKET and are left out.
 constexpr uint16_t NOBUCKET = 0xFFFF;
 
+// Each block owns one contiguous range of the active list; a bucket holds the
+// ranges' members in range order, so a launch walks the vertex ids roughly in
+// ascending order (cluster ids of one job stay together in L2).
+__device__ __forceinline__ void part_range(int64_t na, int64_t &beg, int64_t &end) {
+  const int64_t per = cdiv(na, (int64_t)gridDim.x);
+  beg = (int64_t)blockIdx.x * per;
+  end = beg + per < na ? beg + per : na;
+}
+
+// Per block and bucket: members (blkcnt[b * grid + block]); per bucket: total
+// members and arcs.
 __global__ __launch_bounds__(BM_NT) void k_part_count(const int32_t *__restrict__ list, int64_t na,
                                                       const int64_t *__restrict__ off, uint64_t h, int32_t S,
                                                       int64_t wide_max, JobView jv, uint16_t *__restrict__ bucket_of,
-                                                      int64_t *__restrict__ bcnt, int64_t *__restrict__ barcs) {
+                                                      int32_t *__restrict__ blkcnt, int64_t *__restrict__ bcnt,
+                                                      int64_t *__restrict__ barcs) {
   extern __shared__ int64_t sm[];
   const int NB = S * NBINS;
   int64_t *lc = sm;
   int64_t *la = sm + NB;
   for (int i = threadIdx.x; i < 2 * NB; i += BM_NT) sm[i] = 0;
   __syncthreads();
-  for (int64_t i = (int64_t)blockIdx.x * BM_NT + threadIdx.x; i < na; i += (int64_t)gridDim.x * BM_NT) {
+  int64_t beg, end;
+  part_range(na, beg, end);
+  for (int64_t i = beg + threadIdx.x; i < end; i += BM_NT) {
     const int32_t v = list ? list[i] : (int32_t)i;
     int64_t local = v;
     if (jv.jid) {
@@ -824,48 +853,56 @@ __global__ __launch_bounds__(BM_NT) void k_part_count(const int32_t *__restrict_
   }
   __syncthreads();
   for (int i = threadIdx.x; i < NB; i += BM_NT) {
+    blkcnt[(int64_t)i * gridDim.x + blockIdx.x] = (int32_t)lc[i];
     if (lc[i]) atomic_add_i64(&bcnt[i], lc[i]);
     if (la[i]) atomic_add_i64(&barcs[i], la[i]);
   }
 }
 
-// Bucket starts (exclusive scan of the counts) into the scatter cursors.
-__global__ void k_part_starts(const int64_t *__restrict__ bcnt, int64_t *__restrict__ cursor, int NB) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    int64_t s = 0;
-    for (int i = 0; i < NB; i++) {
-      cursor[i] = s;
-      s += bcnt[i];
-    }
+// One block per bucket b: cursor[b * nblk + k] = start of bucket b + members
+// of b in the ranges of blocks < k.
+__global__ __launch_bounds__(BM_NT) void k_part_offsets(const int64_t *__restrict__ bcnt,
+                                                        const int32_t *__restrict__ blkcnt, int64_t nblk,
+                                                        int64_t *__restrict__ cursor) {
+  const int b = blockIdx.x;
+  __shared__ int64_t base;
+  if (threadIdx.x == 0) {
+    int64_t t = 0;
+    for (int i = 0; i < b; i++) t += bcnt[i];
+    base = t;
+  }
+  __syncthreads();
+  int64_t carry = base;
+  const int32_t *row = blkcnt + (int64_t)b * nblk;
+  int64_t *out = cursor + (int64_t)b * nblk;
+  for (int64_t k0 = 0; k0 < nblk; k0 += BM_NT) {
+    const int64_t k = k0 + threadIdx.x;
+    const int64_t x = k < nblk ? row[k] : 0;
+    int64_t tot;
+    const int64_t ex = block_excl_scan<int64_t, BM_NT>(x, &tot);
+    if (k < nblk) out[k] = carry + ex;
+    carry += tot;
   }
 }
 
-// Order inside a bucket is whatever the atomics give: no result depends on
-// it (decisions read a fixed snapshot; apply adds commute; isolation ranks
-// by vertex id).
+// Order inside one block's share of a bucket is whatever the LDS atomics
+// give: no result depends on it (decisions read a fixed snapshot; apply adds
+// commute; isolation ranks by vertex id).
 __global__ __launch_bounds__(BM_NT) void k_part_scatter(const int32_t *__restrict__ list, int64_t na,
                                                         const uint16_t *__restrict__ bucket_of, int32_t S,
-                                                        int64_t *__restrict__ cursor, int32_t *__restrict__ out) {
+                                                        const int64_t *__restrict__ cursor,
+                                                        int32_t *__restrict__ out) {
   extern __shared__ int64_t sm[];
   const int NB = S * NBINS;
-  int64_t *lc = sm;          // items of this block per bucket
-  int64_t *lbase = sm + NB;  // reserved global position per bucket
-  for (int i = threadIdx.x; i < NB; i += BM_NT) lc[i] = 0;
-  __syncthreads();
-  // each block owns one contiguous range of the list
-  const int64_t per = cdiv(na, (int64_t)gridDim.x);
-  const int64_t beg = (int64_t)blockIdx.x * per;
-  const int64_t end = beg + per < na ? beg + per : na;
-  for (int64_t i = beg + threadIdx.x; i < end; i += BM_NT)
-    if (bucket_of[i] != NOBUCKET) atomicAdd(reinterpret_cast<unsigned long long *>(&lc[bucket_of[i]]), 1ull);
-  __syncthreads();
+  int64_t *lc = sm;          // members placed so far per bucket
+  int64_t *lbase = sm + NB;  // this block's first position per bucket
   for (int i = threadIdx.x; i < NB; i += BM_NT) {
-    lbase[i] = lc[i] ? (int64_t)atomicAdd(reinterpret_cast<unsigned long long *>(&cursor[i]),
-                                          (unsigned long long)lc[i])
-                     : 0;
     lc[i] = 0;
+    lbase[i] = cursor[(int64_t)i * gridDim.x + blockIdx.x];
   }
   __syncthreads();
+  int64_t beg, end;
+  part_range(na, beg, end);
   for (int64_t i = beg + threadIdx.x; i < end; i += BM_NT) {
     const int b = bucket_of[i];
     if (b == NOBUCKET) continue;
@@ -1107,7 +1144,7 @@ void best_moves(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_para
   const int LC = NSPREAD * NCTR;
   const size_t nctr = (size_t)NB * 3 + (size_t)NB * LC + (size_t)S + 2;
   int64_t *dctr = c.buf<int64_t>("bm.ctr", nctr);
-  int64_t *bcnt = dctr, *barcs = dctr + NB, *cursor = dctr + 2 * NB, *lctr = dctr + 3 * NB;
+  int64_t *bcnt = dctr, *barcs = dctr + NB, *lctr = dctr + 3 * NB;  // dctr + 2 * NB: spare
   int64_t *isoc = lctr + (size_t)LC * NB, *nact = isoc + S, *iso_err = nact + 1;
   std::vector<int64_t> hctr(nctr);
 
@@ -1145,13 +1182,15 @@ void best_moves(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_para
     if (na > 0) {
       const size_t smem = (size_t)2 * NB * sizeof(int64_t);
       int64_t grid = std::min<int64_t>(cdiv(na, BM_NT * 8), (int64_t)c.num_cu * 8);
+      int32_t *blkcnt = c.buf<int32_t>("bm.pblk", (size_t)(grid * NB));
+      int64_t *pcur = c.buf<int64_t>("bm.pcur", (size_t)(grid * NB));
       hipLaunchKernelGGL(k_part_count, dim3((unsigned)grid), dim3(BM_NT), smem, c.stream, list, na, g.off, h, S,
-                         wide_max, jv, bucket_of, bcnt, barcs);
+                         wide_max, jv, bucket_of, blkcnt, bcnt, barcs);
       LAUNCHCHECK();
-      hipLaunchKernelGGL(k_part_starts, dim3(1), dim3(1), 0, c.stream, bcnt, cursor, NB);
+      hipLaunchKernelGGL(k_part_offsets, dim3((unsigned)NB), dim3(BM_NT), 0, c.stream, bcnt, blkcnt, grid, pcur);
       LAUNCHCHECK();
       hipLaunchKernelGGL(k_part_scatter, dim3((unsigned)grid), dim3(BM_NT), smem, c.stream, list, na, bucket_of,
-                         S, cursor, blist);
+                         S, pcur, blist);
       LAUNCHCHECK();
     }
     d2h(c, hctr.data(), dctr, (size_t)2 * NB * sizeof(int64_t));
@@ -1223,7 +1262,7 @@ void best_moves(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_para
         {
           Ctx::Timer tm(&c, "bm_apply", (double)total_s * 12.0, (double)total_s);
           hipLaunchKernelGGL(k_bm_apply, dim3((unsigned)cdiv(total_s, BM_NT)), dim3(BM_NT), 0, c.stream,
-                             blist + start[s * NBINS], total_s, D, C, K, cnt, g.k, n, isoc + s);
+                             blist + start[s * NBINS], total_s, D, C, K, cnt, g.k, n, isoc + s, jv.jid, jv.jmoved);
           LAUNCHCHECK();
         }
       }

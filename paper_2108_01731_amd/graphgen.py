@@ -499,3 +499,48 @@ def job_slice(g: HostGraph, job_start, j: int) -> HostGraph:
     return HostGraph(off - e0, col, np.asarray(h.k[a:b]), None if h.wt is None else np.asarray(h.wt[e0:e1]),
                      None if h.s is None else np.asarray(h.s[a:b]), None if h.kk is None else np.asarray(h.kk[a:b]),
                      h.wt_kind)
+
+
+def pack_torch(graphs, device) -> tuple:
+    """pack() for graphs held as torch tensors (e.g. on the GPU): the packed
+    arrays are built on `device`.  Returns (graph, job_start int64 numpy)."""
+    ns = [g.n for g in graphs]
+    ms = [g.arcs for g in graphs]
+    vstart = np.zeros(len(graphs) + 1, dtype=np.int64)
+    vstart[1:] = np.cumsum(ns)
+    astart = np.zeros(len(graphs) + 1, dtype=np.int64)
+    astart[1:] = np.cumsum(ms)
+    kinds = {g.wt_kind if g.wt is not None else "none" for g in graphs}
+    if len(kinds) > 1:
+        raise ValueError(f"mixed weight storage in one batch: {sorted(kinds)}")
+    kind = kinds.pop() if kinds else "none"
+    t = lambda a, dt: torch.as_tensor(a).to(device=device, dtype=dt)
+    off = torch.cat([t(g.off[:-1], torch.int64) + int(astart[j]) for j, g in enumerate(graphs)] +
+                    [torch.tensor([int(astart[-1])], dtype=torch.int64, device=device)])
+    col = torch.cat([(t(g.col, torch.int32) + int(vstart[j])) for j, g in enumerate(graphs)] +
+                    [torch.zeros(0, dtype=torch.int32, device=device)])
+    k = torch.cat([t(g.k, torch.int64) for g in graphs] + [torch.zeros(0, dtype=torch.int64, device=device)])
+    wt = None
+    if kind != "none":
+        wt = torch.cat([torch.as_tensor(g.wt).to(device) for g in graphs])
+    s = None
+    if any(g.s is not None for g in graphs):
+        s = torch.cat([t(g.s, torch.int64) if g.s is not None else torch.zeros(g.n, dtype=torch.int64, device=device)
+                       for g in graphs])
+    kk = None
+    if any(g.kk is not None for g in graphs):
+        kk = torch.cat([t(g.kk, torch.int64) if g.kk is not None else t(g.k, torch.int64) ** 2 for g in graphs])
+    return HostGraph(off, col, k, wt, s, kk, kind), vstart
+
+
+def sbm_batch(jobs: int, seed: int = 0, device="cpu", nmin: int = 100, nmax: int = 50000, block: int = 500,
+              mixing: float = 0.2):
+    """The many-graph batch: job i is sbm_blocks(n_i, block, d_i, mixing,
+    seed = i) with (n_i, d_i, lambda_i) from sbm_job_spec(i, seed).  Returns
+    (graphs, lambdas as (p, q))."""
+    graphs, lams = [], []
+    for i in range(jobs):
+        n, d, p, q = sbm_job_spec(i, seed, nmin, nmax)
+        graphs.append(sbm_blocks(n, block, d, mixing, seed=i, device=device))
+        lams.append((p, q))
+    return graphs, lams
