@@ -519,9 +519,9 @@ lcc_status lcc_cluster(lcc_ctx *ctx, const lcc_graph *g, lcc_lambda lam, const l
     std::memset(&cs, 0, sizeof(cs));
     GraphSummary s = checked_summary(c, *g, nullptr, prm->validate != 0, lam.p, lam.q);
     const bool wide = wide_weights(s);
-    std::vector<std::unique_ptr<OwnedGraph>> owned;
+    // per-level arrays live in the context and are reused by later calls
     std::vector<lcc_graph> G;
-    std::vector<DevBuf> Cl, maps;
+    std::vector<int32_t *> Cl, maps;
     std::vector<int64_t> maxdeg;
     G.push_back(*g);
     maxdeg.push_back(s.maxdeg);
@@ -532,9 +532,8 @@ lcc_status lcc_cluster(lcc_ctx *ctx, const lcc_graph *g, lcc_lambda lam, const l
       cs.n_level[l] = n;
       cs.arcs_level[l] = G[l].arcs;
       cs.levels = l + 1;
-      Cl.emplace_back();
-      Cl.back().ensure((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
-      int32_t *C = Cl.back().as<int32_t>();
+      Cl.push_back(c.buf<int32_t>("lv.C" + std::to_string(l), (size_t)(n > 0 ? n : 1)));
+      int32_t *C = Cl.back();
       iota_i32(c, C, n);
       lcc_bm_stats st;
       auto a = clk::now();
@@ -550,19 +549,18 @@ lcc_status lcc_cluster(lcc_ctx *ctx, const lcc_graph *g, lcc_lambda lam, const l
         cs.top_moved = st.moved_any;
         break;
       }
-      maps.emplace_back();
-      maps.back().ensure((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
-      owned.emplace_back(new OwnedGraph());
+      maps.push_back(c.buf<int32_t>("lv.map" + std::to_string(l), (size_t)(n > 0 ? n : 1)));
+      OwnedGraph &next = c.level_graph((size_t)l + 1);
       int64_t md = 0;
       a = clk::now();
-      compress_graph(c, G[l], C, *owned.back(), maps.back().as<int32_t>(), wide, &md);
+      compress_graph(c, G[l], C, next, maps.back(), wide, &md);
       ms_cp += std::chrono::duration<double, std::milli>(clk::now() - a).count();
-      G.push_back(owned.back()->view());
+      G.push_back(next.view());
       maxdeg.push_back(md);
     }
     for (int l = top - 1; l >= 0; l--) {
-      int32_t *C = Cl[l].as<int32_t>();
-      flatten(c, G[l].n, maps[l].as<int32_t>(), Cl[l + 1].as<int32_t>(), C);
+      int32_t *C = Cl[l];
+      flatten(c, G[l].n, maps[l], Cl[l + 1], C);
       if (prm->refine) {
         lcc_bm_stats st;
         auto a = clk::now();
@@ -573,7 +571,7 @@ lcc_status lcc_cluster(lcc_ctx *ctx, const lcc_graph *g, lcc_lambda lam, const l
         cs.arcs_scanned_total += st.arcs_scanned;
       }
     }
-    cs.clusters = canonical_labels(c, g->n, Cl[0].as<int32_t>(), labels_out);
+    cs.clusters = canonical_labels(c, g->n, Cl[0], labels_out);
     if (obj) {
       i128 N = objective_num(c, *g, lam.p, lam.q, labels_out);
       fill_objective(N, lam.q, obj);
@@ -638,20 +636,19 @@ lcc_status lcc_cluster_batch(lcc_ctx *ctx, const lcc_graph *g, int64_t jobs, con
         vch.push_back(b);
         vch.push_back(std::min<int64_t>(b + BATCH_CHUNK, hstart[(size_t)j + 1]));
       }
-    DevBuf d_start, d_jp, d_jq, d_cont;
-    d_start.ensure((size_t)(J + 1) * sizeof(int64_t));
-    d_jp.ensure((size_t)J * sizeof(int64_t));
-    d_jq.ensure((size_t)J * sizeof(int64_t));
-    d_cont.ensure((size_t)J);
+    int64_t *d_start = c.buf<int64_t>("bt.start", (size_t)(J + 1));
+    int64_t *d_jp = c.buf<int64_t>("bt.jp", (size_t)J);
+    int64_t *d_jq = c.buf<int64_t>("bt.jq", (size_t)J);
+    uint8_t *d_cont = c.buf<uint8_t>("bt.cont", (size_t)J);
     {
       std::vector<int64_t> hp((size_t)J), hq((size_t)J);
       for (int64_t j = 0; j < J; j++) {
         hp[(size_t)j] = lambdas[j].p;
         hq[(size_t)j] = lambdas[j].q;
       }
-      h2d(c, d_start.p, hstart.data(), (size_t)(J + 1) * sizeof(int64_t));
-      h2d(c, d_jp.p, hp.data(), (size_t)J * sizeof(int64_t));
-      h2d(c, d_jq.p, hq.data(), (size_t)J * sizeof(int64_t));
+      h2d(c, d_start, hstart.data(), (size_t)(J + 1) * sizeof(int64_t));
+      h2d(c, d_jp, hp.data(), (size_t)J * sizeof(int64_t));
+      h2d(c, d_jq, hq.data(), (size_t)J * sizeof(int64_t));
       c.sync();
     }
     // validation: structure of the packed graph, then per-job sums (arcs that
@@ -660,7 +657,7 @@ lcc_status lcc_cluster_batch(lcc_ctx *ctx, const lcc_graph *g, int64_t jobs, con
     if (!s.ok) fail(LCC_ERR_INVALID_ARG, s.why);
     bool wide = false;
     {
-      std::vector<uint64_t> part = batch_vertex_sums(c, *g, d_start.as<int64_t>(), vch, true);
+      std::vector<uint64_t> part = batch_vertex_sums(c, *g, d_start, vch, true);
       std::vector<GraphSummary> sj((size_t)J);
       auto sat = [](uint64_t a, uint64_t b) {
         uint64_t r = a + b;
@@ -683,18 +680,14 @@ lcc_status lcc_cluster_batch(lcc_ctx *ctx, const lcc_graph *g, int64_t jobs, con
         wide = wide || wide_weights(sj[(size_t)j]);
       }
     }
-    // level 0 job layout
-    std::vector<DevBuf> jidl, jbasel, Cl, maps;
-    std::vector<std::unique_ptr<OwnedGraph>> owned;
+    // level 0 job layout; per-level arrays live in the context
+    std::vector<int32_t *> jidl, Cl, maps;
+    std::vector<int64_t *> jbasel;
     std::vector<lcc_graph> G;
     std::vector<int64_t> maxdeg;
-    jidl.emplace_back();
-    jidl.back().ensure((size_t)g->n * sizeof(int32_t));
-    batch_fill_jid(c, d_start.as<int64_t>(), J, g->n, jidl.back().as<int32_t>());
-    jbasel.emplace_back();
-    jbasel.back().ensure((size_t)(J + 1) * sizeof(int64_t));
-    HIPCHECK(hipMemcpyAsync(jbasel.back().p, d_start.p, (size_t)(J + 1) * sizeof(int64_t), hipMemcpyDeviceToDevice,
-                            c.stream));
+    jidl.push_back(c.buf<int32_t>("lv.jid0", (size_t)g->n));
+    batch_fill_jid(c, d_start, J, g->n, jidl.back());
+    jbasel.push_back(d_start);
     G.push_back(*g);
     maxdeg.push_back(s.maxdeg);
     std::vector<uint8_t> run((size_t)J), cont((size_t)J), moved((size_t)J);
@@ -707,16 +700,15 @@ lcc_status lcc_cluster_batch(lcc_ctx *ctx, const lcc_graph *g, int64_t jobs, con
       bs.n_level[l] = n;
       bs.arcs_level[l] = G[l].arcs;
       bs.levels = l + 1;
-      Cl.emplace_back();
-      Cl.back().ensure((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
-      int32_t *C = Cl.back().as<int32_t>();
+      Cl.push_back(c.buf<int32_t>("lv.C" + std::to_string(l), (size_t)(n > 0 ? n : 1)));
+      int32_t *C = Cl.back();
       iota_i32(c, C, n);
       BatchLevel bl;
       bl.jobs = J;
-      bl.jid = jidl[l].as<int32_t>();
-      bl.jbase = jbasel[l].as<int64_t>();
-      bl.jp = d_jp.as<int64_t>();
-      bl.jq = d_jq.as<int64_t>();
+      bl.jid = jidl[l];
+      bl.jbase = jbasel[l];
+      bl.jp = d_jp;
+      bl.jq = d_jq;
       bl.active = run.data();
       bl.iters = iters.data();
       bl.moved_any = moved.data();
@@ -743,34 +735,30 @@ lcc_status lcc_cluster_batch(lcc_ctx *ctx, const lcc_graph *g, int64_t jobs, con
         maxtop = l;
         break;
       }
-      h2d(c, d_cont.p, cont.data(), (size_t)J);
-      maps.emplace_back();
-      maps.back().ensure((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
-      owned.emplace_back(new OwnedGraph());
+      h2d(c, d_cont, cont.data(), (size_t)J);
+      maps.push_back(c.buf<int32_t>("lv.map" + std::to_string(l), (size_t)(n > 0 ? n : 1)));
+      OwnedGraph &next = c.level_graph((size_t)l + 1);
       // the next level's job of every vertex and job bases
-      jidl.emplace_back();
-      jidl.back().ensure((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
-      jbasel.emplace_back();
-      jbasel.back().ensure((size_t)(J + 1) * sizeof(int64_t));
+      jidl.push_back(c.buf<int32_t>("lv.jid" + std::to_string(l + 1), (size_t)(n > 0 ? n : 1)));
+      jbasel.push_back(c.buf<int64_t>("lv.jbase" + std::to_string(l + 1), (size_t)(J + 1)));
       CompressJobs cj;
       cj.jobs = J;
-      cj.jid = jidl[l].as<int32_t>();
-      cj.jcont = d_cont.as<uint8_t>();
-      cj.jid_next = jidl[l + 1].as<int32_t>();
-      cj.jbase_next = jbasel[l + 1].as<int64_t>();
+      cj.jid = jidl[l];
+      cj.jcont = d_cont;
+      cj.jid_next = jidl[l + 1];
+      cj.jbase_next = jbasel[l + 1];
       int64_t md = 0;
       a = clk::now();
-      compress_graph(c, G[l], C, *owned.back(), maps.back().as<int32_t>(), wide, &md, &cj);
+      compress_graph(c, G[l], C, next, maps.back(), wide, &md, &cj);
       ms_cp += std::chrono::duration<double, std::milli>(clk::now() - a).count();
-      G.push_back(owned.back()->view());
+      G.push_back(next.view());
       maxdeg.push_back(md);
       run = cont;
     }
     for (int l = maxtop - 1; l >= 0; l--) {
-      int32_t *C = Cl[l].as<int32_t>();
+      int32_t *C = Cl[l];
       // jobs that stopped coarsening at this level keep their clustering (map < 0)
-      batch_flatten(c, G[l].n, maps[l].as<int32_t>(), Cl[l + 1].as<int32_t>(), jidl[l].as<int32_t>(),
-                    jbasel[l].as<int64_t>(), jbasel[l + 1].as<int64_t>(), C);
+      batch_flatten(c, G[l].n, maps[l], Cl[l + 1], jidl[l], jbasel[l], jbasel[l + 1], C);
       if (prm->refine) {
         bool any = false;
         for (int64_t j = 0; j < J; j++) {
@@ -780,10 +768,10 @@ lcc_status lcc_cluster_batch(lcc_ctx *ctx, const lcc_graph *g, int64_t jobs, con
         if (!any) continue;
         BatchLevel bl;
         bl.jobs = J;
-        bl.jid = jidl[l].as<int32_t>();
-        bl.jbase = jbasel[l].as<int64_t>();
-        bl.jp = d_jp.as<int64_t>();
-        bl.jq = d_jq.as<int64_t>();
+        bl.jid = jidl[l];
+        bl.jbase = jbasel[l];
+        bl.jp = d_jp;
+        bl.jq = d_jq;
         bl.active = run.data();
         bl.iters = iters.data();
         bl.moved_any = moved.data();
@@ -798,9 +786,9 @@ lcc_status lcc_cluster_batch(lcc_ctx *ctx, const lcc_graph *g, int64_t jobs, con
     // canonical labels over the packed graph, then made job-local
     const int64_t n0 = g->n;
     int32_t *glab = c.buf<int32_t>("bt.glab", (size_t)n0);
-    const int64_t total = canonical_labels(c, n0, Cl[0].as<int32_t>(), glab);
-    batch_local_labels(c, glab, jidl[0].as<int32_t>(), d_start.as<int64_t>(), n0, labels_out);
-    std::vector<int32_t> first = batch_first_labels(c, glab, d_start.as<int64_t>(), J);
+    const int64_t total = canonical_labels(c, n0, Cl[0], glab);
+    batch_local_labels(c, glab, jidl[0], d_start, n0, labels_out);
+    std::vector<int32_t> first = batch_first_labels(c, glab, d_start, J);
     // clusters of job j are the global labels [first_j, first of the next non-empty job)
     int64_t nxt = total;
     for (int64_t j = J - 1; j >= 0; j--) {

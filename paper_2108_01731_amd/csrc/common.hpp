@@ -8,6 +8,7 @@
 #include <cstdint>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -119,6 +120,13 @@ struct Ctx {
   std::map<std::string, DevBuf> scratch;
   // pinned host mailbox for small device->host reads
   void *host_mail = nullptr;
+  // contracted graphs of the hierarchy levels, reused across calls
+  std::vector<std::unique_ptr<OwnedGraph>> level_graphs;
+
+  OwnedGraph &level_graph(size_t l) {
+    while (level_graphs.size() <= l) level_graphs.emplace_back(new OwnedGraph());
+    return *level_graphs[l];
+  }
 
   template <class T> T *buf(const std::string &name, size_t count) {
     DevBuf &b = scratch[name];
