@@ -86,7 +86,25 @@ struct AggArgs {
   int64_t *gvals;
   int64_t hcap;        // table capacity in slots (dynamic-LDS or global bins)
   JobView jv;
+  // device-driven launches: the vertices are
+  // list[dstart[bucket] .. dstart[bucket + nbuckets]) (consecutive buckets)
+  const int64_t *dstart;
+  int32_t bucket;
+  int32_t nbuckets;
 };
+
+// The launch's vertex list and count (host-given, or read from the bucket
+// starts in device memory).
+__device__ __forceinline__ void work_of(const AggArgs &a, const int32_t *&list, int64_t &count) {
+  if (a.dstart) {
+    const int64_t b0 = a.dstart[a.bucket];
+    list = a.list + b0;
+    count = a.dstart[a.bucket + a.nbuckets] - b0;
+  } else {
+    list = a.list;
+    count = a.count;
+  }
+}
 
 // lambda of the job owning v (the scalar lambda outside batched runs).
 __device__ __forceinline__ void job_lambda(const AggArgs &a, int32_t v, int64_t &p, int64_t &q, int32_t &job) {
@@ -220,14 +238,19 @@ __global__ __launch_bounds__(BM_NT) void k_bm_group(AggArgs a) {
   __shared__ int32_t hk[GPB * HMAX];
   __shared__ Acc hv[GPB * HMAX];
   const int t = threadIdx.x, grp = t / G, gl = t % G;
-  const int64_t gi = (int64_t)blockIdx.x * GPB + grp;
-  const bool valid = gi < a.count;
+  const int32_t *list;
+  int64_t count;
+  work_of(a, list, count);
+  int64_t c_movers = 0, c_cands = 0, c_marcs = 0;
+  for (int64_t g0 = (int64_t)blockIdx.x * GPB; g0 < count; g0 += (int64_t)gridDim.x * GPB) {
+  const int64_t gi = g0 + grp;
+  const bool valid = gi < count;
   int32_t *keys = hk + grp * HMAX;
   Acc *vals = hv + grp * HMAX;
   int32_t v = 0, c = 0;
   int64_t beg = 0, end = 0;
   if (valid) {
-    v = a.list[gi];
+    v = list[gi];
     beg = a.off[v];
     end = a.off[v + 1];
     c = a.C[v];
@@ -325,7 +348,12 @@ __global__ __launch_bounds__(BM_NT) void k_bm_group(AggArgs a) {
       }
     }
   }
-  flush_counters<BM_NT>(a.ctr, (moved && gl == 0) ? 1 : 0, ncand, (moved && gl == 0) ? end - beg : 0);
+  c_movers += (moved && gl == 0) ? 1 : 0;
+  c_cands += ncand;
+  c_marcs += (moved && gl == 0) ? end - beg : 0;
+  __syncthreads();  // the tables are cleared again for the next vertices
+  }
+  flush_counters<BM_NT>(a.ctr, c_movers, c_cands, c_marcs);
 }
 
 // ------------------------------------------------------- block per vertex
@@ -341,7 +369,12 @@ __global__ __launch_bounds__(NT) void k_bm_wide(AggArgs a) {
   Acc *vals = reinterpret_cast<Acc *>(smem + ((a.hcap * 4 + 15) & ~15ll));
   __shared__ int32_t sh_d;
   const int t = threadIdx.x;
-  const int32_t v = a.list[blockIdx.x];
+  const int32_t *list;
+  int64_t count;
+  work_of(a, list, count);
+  int64_t movers = 0, marcs = 0, cands = 0;
+  for (int64_t vi = blockIdx.x; vi < count; vi += gridDim.x) {
+  const int32_t v = list[vi];
   const int64_t beg = a.off[v], end = a.off[v + 1];
   const int32_t c = a.C[v];
   uint32_t H = pow2_at_least(2 * (end - beg + 1));
@@ -374,7 +407,7 @@ __global__ __launch_bounds__(NT) void k_bm_wide(AggArgs a) {
   int32_t job;
   job_lambda(a, v, lp, lq, job);
   const int64_t pk = lp * kv;
-  int64_t best_s = INT64_MIN, wc = 0, cands = 0;
+  int64_t best_s = INT64_MIN, wc = 0;
   int32_t best_id = ISO_ID;
   for (uint32_t j = t; j < H; j += NT) {
     const int32_t X = keys[j];
@@ -392,20 +425,21 @@ __global__ __launch_bounds__(NT) void k_bm_wide(AggArgs a) {
     }
   }
   block_best<NT>(best_s, best_id, wc);
-  int64_t movers = 0, marcs = 0;
   if (t == 0) {
     const int64_t stay = lq * wc - pk * (Kc - kv);
     const int32_t d = decide(best_s, best_id, stay, a.allow_iso && cntc >= 2, c);
     a.D[v] = d;
     sh_d = d;
     if (d != c) {
-      movers = 1;
-      marcs = end - beg;
+      movers += 1;
+      marcs += end - beg;
     }
   }
   __syncthreads();
   if (sh_d != c && a.next_flag)
     for (int64_t e = beg + t; e < end; e += NT) a.next_flag[a.col[e]] = 1;
+  __syncthreads();  // table and sh_d are reused by the next vertex
+  }
   flush_counters<NT>(a.ctr, movers, cands, marcs);
 }
 
@@ -422,12 +456,17 @@ __global__ __launch_bounds__(NT) void k_bm_single(AggArgs a) {
   constexpr int GPB = NT / G;
   __shared__ int32_t sh_d[GPB];
   const int t = threadIdx.x, grp = t / G, gl = t % G;
-  const int64_t gi = (int64_t)blockIdx.x * GPB + grp;
-  const bool valid = gi < a.count;
+  const int32_t *list;
+  int64_t count;
+  work_of(a, list, count);
+  int64_t c_movers = 0, c_cands = 0, c_marcs = 0;
+  for (int64_t g0 = (int64_t)blockIdx.x * GPB; g0 < count; g0 += (int64_t)gridDim.x * GPB) {
+  const int64_t gi = g0 + grp;
+  const bool valid = gi < count;
   int32_t v = 0;
   int64_t beg = 0, end = 0, kv = 0;
   if (valid) {
-    v = a.list[gi];
+    v = list[gi];
     beg = a.off[v];
     end = a.off[v + 1];
     kv = a.k[v];
@@ -481,8 +520,12 @@ __global__ __launch_bounds__(NT) void k_bm_single(AggArgs a) {
   if (valid && gl == 0) a.D[v] = d;
   if (moved && a.next_flag)
     for (int64_t e = beg + gl; e < end; e += G) a.next_flag[a.col[e]] = 1;
-  flush_counters<NT>(a.ctr, (moved && gl == 0) ? 1 : 0, (valid && gl == 0) ? end - beg + 1 : 0,
-                     (moved && gl == 0) ? end - beg : 0);
+  c_movers += (moved && gl == 0) ? 1 : 0;
+  c_cands += (valid && gl == 0) ? end - beg + 1 : 0;
+  c_marcs += (moved && gl == 0) ? end - beg : 0;
+  if constexpr (G == NT) __syncthreads();  // sh_d is reused by the next vertex
+  }
+  flush_counters<NT>(a.ctr, c_movers, c_cands, c_marcs);
 }
 
 // ------------------------------------------------------ flat hub aggregation
@@ -697,7 +740,8 @@ __global__ __launch_bounds__(B7_NT) void k_b7_final(AggArgs a, const int64_t *__
 // order within each bin, so a block's movers mostly share a few consecutive
 // jobs; their flags gather in LDS and leave as one plain store per job
 // instead of one global atomic per mover on a handful of addresses.
-__global__ __launch_bounds__(BM_NT) void k_bm_apply(const int32_t *__restrict__ list, int64_t count,
+__global__ __launch_bounds__(BM_NT) void k_bm_apply(const int32_t *__restrict__ list0, int64_t count0,
+                                                    const int64_t *__restrict__ dstart, int32_t bfirst, int32_t blast,
                                                     const int32_t *__restrict__ D, int32_t *__restrict__ C,
                                                     int64_t *__restrict__ K, int32_t *__restrict__ cnt,
                                                     const int64_t *__restrict__ k, int64_t n,
@@ -706,50 +750,69 @@ __global__ __launch_bounds__(BM_NT) void k_bm_apply(const int32_t *__restrict__ 
   constexpr int JW = 64;  // jobs flagged in LDS per block
   __shared__ int32_t j0;
   __shared__ int32_t jflag[JW];
-  const int64_t i = (int64_t)blockIdx.x * BM_NT + threadIdx.x;
-  if (jid) {
-    if (threadIdx.x == 0) j0 = jid[list[(int64_t)blockIdx.x * BM_NT]];
-    if (threadIdx.x < JW) jflag[threadIdx.x] = 0;
-    __syncthreads();
+  const int32_t *list = list0;
+  int64_t count = count0;
+  if (dstart) {  // the sub-round's buckets are contiguous in the list
+    list = list0 + dstart[bfirst];
+    count = dstart[blast] - dstart[bfirst];
   }
   int64_t niso = 0;
-  if (i < count) {
-    const int32_t v = list[i];
-    int32_t d = D[v];
-    const int32_t c = C[v];
-    if (d != c && jid) {
-      const int32_t j = jid[v];
-      if (j >= j0 && j - j0 < JW) jflag[j - j0] = 1;
-      else jmoved[j] = 1;
+  for (int64_t base = (int64_t)blockIdx.x * BM_NT; base < count; base += (int64_t)gridDim.x * BM_NT) {
+    const int64_t i = base + threadIdx.x;
+    if (jid) {
+      if (threadIdx.x == 0) j0 = jid[list[base]];
+      if (threadIdx.x < JW) jflag[threadIdx.x] = 0;
+      __syncthreads();
     }
-    if (d != c) {
-      const int64_t kv = k[v];
-      if (d < 0) {
-        d = (int32_t)(n + v);
-        niso = 1;
+    if (i < count) {
+      const int32_t v = list[i];
+      int32_t d = D[v];
+      const int32_t c = C[v];
+      if (d != c && jid) {
+        const int32_t j = jid[v];
+        if (j >= j0 && j - j0 < JW) jflag[j - j0] = 1;
+        else jmoved[j] = 1;
       }
-      if (kv) {
-        atomic_add_i64(&K[c], -kv);
-        atomic_add_i64(&K[d], kv);
+      if (d != c) {
+        const int64_t kv = k[v];
+        if (d < 0) {
+          d = (int32_t)(n + v);
+          niso++;
+        }
+        if (kv) {
+          atomic_add_i64(&K[c], -kv);
+          atomic_add_i64(&K[d], kv);
+        }
+        atomicSub(&cnt[c], 1);
+        atomicAdd(&cnt[d], 1);
+        C[v] = d;
       }
-      atomicSub(&cnt[c], 1);
-      atomicAdd(&cnt[d], 1);
-      C[v] = d;
+    }
+    if (jid) {
+      __syncthreads();
+      if (threadIdx.x < JW && jflag[threadIdx.x]) jmoved[j0 + threadIdx.x] = 1;
+      __syncthreads();
     }
   }
   niso = wave_sum(niso);
   if (lane_id() == 0 && niso) atomic_add_i64(iso_ctr, niso);
-  if (jid) {
-    __syncthreads();
-    if (threadIdx.x < JW && jflag[threadIdx.x]) jmoved[j0 + threadIdx.x] = 1;
-  }
 }
 
 // ------------------------------------------------ renaming fresh clusters
 
+// Renaming is needed only after an iteration with an isolating vertex;
+// device-driven iterations queue it always and let it skip itself.
+__device__ __forceinline__ bool no_isolation(const int64_t *isoc, int S) {
+  if (!isoc) return false;
+  int64_t t = 0;
+  for (int s = 0; s < S; s++) t += isoc[s];
+  return t == 0;
+}
+
 // fresh[t] = cluster n + t is non-empty; empty[x] = cluster x (< n) is empty.
 __global__ void k_fresh_flags(const int32_t *__restrict__ cnt, int64_t n, uint8_t *__restrict__ fresh,
-                              uint8_t *__restrict__ empty) {
+                              uint8_t *__restrict__ empty, const int64_t *__restrict__ isoc, int S) {
+  if (no_isolation(isoc, S)) return;
   for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) {
     fresh[x] = cnt[n + x] > 0;
     empty[x] = cnt[x] == 0;
@@ -762,7 +825,8 @@ __global__ void k_fresh_flags(const int32_t *__restrict__ cnt, int64_t n, uint8_
 // slot of the job's r-th fresh cluster, for r below the job's fresh count.
 __global__ void k_empty_list(const uint8_t *__restrict__ empty, const int32_t *__restrict__ rank_e,
                              const int32_t *__restrict__ rank_f, int64_t n, JobView jv,
-                             int32_t *__restrict__ elist) {
+                             int32_t *__restrict__ elist, const int64_t *__restrict__ isoc, int S) {
+  if (no_isolation(isoc, S)) return;
   for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) {
     if (!empty[x]) continue;
     int64_t b = 0, e = n;
@@ -779,7 +843,9 @@ __global__ void k_empty_list(const uint8_t *__restrict__ empty, const int32_t *_
 // The r-th non-empty fresh cluster takes the r-th empty id (totals moved).
 __global__ void k_fresh_move(const uint8_t *__restrict__ fresh, const int32_t *__restrict__ rank_f,
                              const int32_t *__restrict__ elist, int64_t n, int64_t *__restrict__ K,
-                             int32_t *__restrict__ cnt, int32_t *__restrict__ newid, int64_t *__restrict__ err) {
+                             int32_t *__restrict__ cnt, int32_t *__restrict__ newid, int64_t *__restrict__ err,
+                             const int64_t *__restrict__ isoc, int S) {
+  if (no_isolation(isoc, S)) return;
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
     if (!fresh[t]) continue;
     const int32_t x = elist[rank_f[t]];
@@ -797,11 +863,102 @@ __global__ void k_fresh_move(const uint8_t *__restrict__ fresh, const int32_t *_
   }
 }
 
-__global__ void k_fresh_relabel(int32_t *__restrict__ C, int64_t n, const int32_t *__restrict__ newid) {
+__global__ void k_fresh_relabel(int32_t *__restrict__ C, int64_t n, const int32_t *__restrict__ newid,
+                                const int64_t *__restrict__ isoc, int S) {
+  if (no_isolation(isoc, S)) return;
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
     const int32_t c = C[v];
     if (c >= n) C[v] = newid[c - n];
   }
+}
+
+// The same renaming in one block for small n (one launch): exclusive ranks
+// of fresh and empty ids tile by tile, then the pairing, the moves and the
+// relabel, each phase behind a block barrier.
+constexpr int RN_NT = 1024;
+constexpr int64_t RN_SMALL = 16384;
+
+__global__ __launch_bounds__(RN_NT) void k_rename_small(int32_t *__restrict__ C, int64_t n, int64_t *__restrict__ K,
+                                                        int32_t *__restrict__ cnt, int32_t *__restrict__ rank_f,
+                                                        int32_t *__restrict__ rank_e, int32_t *__restrict__ elist,
+                                                        int32_t *__restrict__ newid, JobView jv,
+                                                        int64_t *__restrict__ err, const int64_t *__restrict__ isoc,
+                                                        int S) {
+  if (no_isolation(isoc, S)) return;
+  int32_t carry_f = 0, carry_e = 0;
+  for (int64_t x0 = 0; x0 < n; x0 += RN_NT) {
+    const int64_t x = x0 + threadIdx.x;
+    const int32_t f = x < n && cnt[n + x] > 0, e = x < n && cnt[x] == 0;
+    int32_t tf, te;
+    const int32_t pf = block_excl_scan<int32_t, RN_NT>(f, &tf), pe = block_excl_scan<int32_t, RN_NT>(e, &te);
+    if (x < n) {
+      rank_f[x] = carry_f + pf;
+      rank_e[x] = carry_e + pe;
+    }
+    carry_f += tf;
+    carry_e += te;
+  }
+  if (threadIdx.x == 0) {
+    rank_f[n] = carry_f;
+    rank_e[n] = carry_e;
+  }
+  __syncthreads();
+  for (int64_t x = threadIdx.x; x < n; x += RN_NT) {
+    if (cnt[x] != 0) continue;
+    int64_t b = 0, e = n;
+    if (jv.jid) {
+      const int32_t j = jv.jid[x];
+      b = jv.jbase[j];
+      e = jv.jbase[j + 1];
+    }
+    const int32_t r = rank_e[x] - rank_e[b];
+    if (r < rank_f[e] - rank_f[b]) elist[rank_f[b] + r] = (int32_t)x;
+  }
+  __syncthreads();
+  for (int64_t t = threadIdx.x; t < n; t += RN_NT) {
+    if (cnt[n + t] <= 0) continue;
+    const int32_t x = elist[rank_f[t]];
+    if (x < 0 || (int64_t)x >= n) {
+      atomic_add_i64(err, 1);
+      continue;
+    }
+    newid[t] = x;
+    K[x] = K[n + t];
+    cnt[x] = cnt[n + t];
+    K[n + t] = 0;
+    cnt[n + t] = 0;
+  }
+  __syncthreads();
+  for (int64_t v = threadIdx.x; v < n; v += RN_NT) {
+    const int32_t c = C[v];
+    if (c >= n) C[v] = newid[c - n];
+  }
+}
+
+// Per-job termination of a device-driven iteration: a running job counts the
+// iteration and stops when none of its vertices moved.
+__global__ void k_job_update(uint8_t *__restrict__ jrun, int64_t *__restrict__ jmoved, int32_t *__restrict__ iters,
+                             uint8_t *__restrict__ moved_any, int64_t jobs) {
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < jobs; j += (int64_t)gridDim.x * blockDim.x) {
+    if (jrun[j]) {
+      iters[j]++;
+      if (jmoved[j]) moved_any[j] = 1;
+      else jrun[j] = 0;
+    }
+    jmoved[j] = 0;
+  }
+}
+
+// Vertices per degree bin (upper bounds of every bucket of a Best-Moves call).
+__global__ __launch_bounds__(BM_NT) void k_bin_hist(const int64_t *__restrict__ off, int64_t n, int64_t wide_max,
+                                                    int64_t *__restrict__ hist) {
+  __shared__ int64_t lh[NBINS];
+  if (threadIdx.x < NBINS) lh[threadIdx.x] = 0;
+  __syncthreads();
+  for (int64_t v = (int64_t)blockIdx.x * BM_NT + threadIdx.x; v < n; v += (int64_t)gridDim.x * BM_NT)
+    atomicAdd(reinterpret_cast<unsigned long long *>(&lh[bin_of(off[v + 1] - off[v], wide_max)]), 1ull);
+  __syncthreads();
+  if (threadIdx.x < NBINS && lh[threadIdx.x]) atomic_add_i64(&hist[threadIdx.x], lh[threadIdx.x]);
 }
 
 // --- partition of the active vertices into (sub-round, bin) buckets
@@ -812,6 +969,8 @@ constexpr uint16_t NOBUCKET = 0xFFFF;
 // Each block owns one contiguous range of the active list; a bucket holds the
 // ranges' members in range order, so a launch walks the vertex ids roughly in
 // ascending order (cluster ids of one job stay together in L2).
+__device__ __forceinline__ int64_t active_count(int64_t na, const int64_t *na_dev) { return na_dev ? *na_dev : na; }
+
 __device__ __forceinline__ void part_range(int64_t na, int64_t &beg, int64_t &end) {
   const int64_t per = cdiv(na, (int64_t)gridDim.x);
   beg = (int64_t)blockIdx.x * per;
@@ -820,7 +979,8 @@ __device__ __forceinline__ void part_range(int64_t na, int64_t &beg, int64_t &en
 
 // Per block and bucket: members (blkcnt[b * grid + block]); per bucket: total
 // members and arcs.
-__global__ __launch_bounds__(BM_NT) void k_part_count(const int32_t *__restrict__ list, int64_t na,
+__global__ __launch_bounds__(BM_NT) void k_part_count(const int32_t *__restrict__ list, int64_t na0,
+                                                      const int64_t *__restrict__ na_dev,
                                                       const int64_t *__restrict__ off, uint64_t h, int32_t S,
                                                       int64_t wide_max, JobView jv, uint16_t *__restrict__ bucket_of,
                                                       int32_t *__restrict__ blkcnt, int64_t *__restrict__ bcnt,
@@ -831,6 +991,7 @@ __global__ __launch_bounds__(BM_NT) void k_part_count(const int32_t *__restrict_
   int64_t *la = sm + NB;
   for (int i = threadIdx.x; i < 2 * NB; i += BM_NT) sm[i] = 0;
   __syncthreads();
+  const int64_t na = active_count(na0, na_dev);
   int64_t beg, end;
   part_range(na, beg, end);
   for (int64_t i = beg + threadIdx.x; i < end; i += BM_NT) {
@@ -859,17 +1020,78 @@ __global__ __launch_bounds__(BM_NT) void k_part_count(const int32_t *__restrict_
   }
 }
 
+// The partition of a small level in one block and one launch: bucket counts
+// and arcs, bucket starts (NB + 1) and the bucket lists.
+constexpr int PS_NT = 1024;
+constexpr int64_t SMALL_LEVEL = 8192;
+
+__global__ __launch_bounds__(PS_NT) void k_part_small(const int32_t *__restrict__ list, int64_t na0,
+                                                      const int64_t *__restrict__ na_dev,
+                                                      const int64_t *__restrict__ off, uint64_t h, int32_t S,
+                                                      int64_t wide_max, JobView jv, uint16_t *__restrict__ bucket_of,
+                                                      int64_t *__restrict__ bcnt, int64_t *__restrict__ barcs,
+                                                      int64_t *__restrict__ dstart, int32_t *__restrict__ out) {
+  extern __shared__ int64_t sm[];
+  const int NB = S * NBINS;
+  int64_t *lc = sm;       // members, then cursor
+  int64_t *la = sm + NB;  // arcs
+  for (int i = threadIdx.x; i < 2 * NB; i += PS_NT) sm[i] = 0;
+  __syncthreads();
+  const int64_t na = active_count(na0, na_dev);
+  for (int64_t i = threadIdx.x; i < na; i += PS_NT) {
+    const int32_t v = list ? list[i] : (int32_t)i;
+    int64_t local = v;
+    if (jv.jid) {
+      const int32_t j = jv.jid[v];
+      if (!jv.jrun[j]) {
+        bucket_of[i] = NOBUCKET;
+        continue;
+      }
+      local = v - jv.jbase[j];
+    }
+    const int64_t deg = off[v + 1] - off[v];
+    const int sr = (int)(mix64(h ^ (uint64_t)local) % (uint64_t)S);
+    const int b = sr * NBINS + bin_of(deg, wide_max);
+    bucket_of[i] = (uint16_t)b;
+    atomicAdd(reinterpret_cast<unsigned long long *>(&lc[b]), 1ull);
+    if (deg) atomicAdd(reinterpret_cast<unsigned long long *>(&la[b]), (unsigned long long)deg);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t t = 0;
+    for (int b = 0; b < NB; b++) {
+      bcnt[b] = lc[b];
+      barcs[b] = la[b];
+      dstart[b] = t;
+      const int64_t cb = lc[b];
+      lc[b] = t;  // becomes the cursor
+      t += cb;
+    }
+    dstart[NB] = t;
+  }
+  __syncthreads();
+  for (int64_t i = threadIdx.x; i < na; i += PS_NT) {
+    const int b = bucket_of[i];
+    if (b == NOBUCKET) continue;
+    const int64_t pos = (int64_t)atomicAdd(reinterpret_cast<unsigned long long *>(&lc[b]), 1ull);
+    out[pos] = list ? list[i] : (int32_t)i;
+  }
+}
+
 // One block per bucket b: cursor[b * nblk + k] = start of bucket b + members
 // of b in the ranges of blocks < k.
 __global__ __launch_bounds__(BM_NT) void k_part_offsets(const int64_t *__restrict__ bcnt,
                                                         const int32_t *__restrict__ blkcnt, int64_t nblk,
-                                                        int64_t *__restrict__ cursor) {
+                                                        int64_t *__restrict__ cursor, int64_t *__restrict__ dstart) {
   const int b = blockIdx.x;
   __shared__ int64_t base;
   if (threadIdx.x == 0) {
     int64_t t = 0;
     for (int i = 0; i < b; i++) t += bcnt[i];
     base = t;
+    // bucket starts for device-driven launches (NB + 1 entries)
+    dstart[b] = t;
+    if (b == (int)gridDim.x - 1) dstart[b + 1] = t + bcnt[b];
   }
   __syncthreads();
   int64_t carry = base;
@@ -888,7 +1110,8 @@ __global__ __launch_bounds__(BM_NT) void k_part_offsets(const int64_t *__restric
 // Order inside one block's share of a bucket is whatever the LDS atomics
 // give: no result depends on it (decisions read a fixed snapshot; apply adds
 // commute; isolation ranks by vertex id).
-__global__ __launch_bounds__(BM_NT) void k_part_scatter(const int32_t *__restrict__ list, int64_t na,
+__global__ __launch_bounds__(BM_NT) void k_part_scatter(const int32_t *__restrict__ list, int64_t na0,
+                                                        const int64_t *__restrict__ na_dev,
                                                         const uint16_t *__restrict__ bucket_of, int32_t S,
                                                         const int64_t *__restrict__ cursor,
                                                         int32_t *__restrict__ out) {
@@ -901,6 +1124,7 @@ __global__ __launch_bounds__(BM_NT) void k_part_scatter(const int32_t *__restric
     lbase[i] = cursor[(int64_t)i * gridDim.x + blockIdx.x];
   }
   __syncthreads();
+  const int64_t na = active_count(na0, na_dev);
   int64_t beg, end;
   part_range(na, beg, end);
   for (int64_t i = beg + threadIdx.x; i < end; i += BM_NT) {
@@ -949,41 +1173,41 @@ template <class F> void allow_lds(Ctx &c, F kernel, size_t bytes) {
   c.lds_raised.push_back(f);
 }
 
+// Vertices one block of a bin's kernel handles at a time.
+int bin_vpb(int bin) {
+  static const int group[NBINS] = {BM_NT / 8, BM_NT / 16, BM_NT / 32, BM_NT / 64, BM_NT / 64, 1, 1, 1};
+  return group[bin];
+}
+
+// Grid of a bin launch: one pass when the count is known, else a resident
+// grid that loops over the bucket (device-driven launches).
+int64_t bin_grid(const Ctx &c, int bin, int64_t count, bool exact) {
+  const int64_t need = std::max<int64_t>(1, cdiv(count, bin_vpb(bin)));
+  if (exact) return need;
+  const int64_t cap = (int64_t)c.num_cu * (bin < 5 ? 8 : bin == 5 ? 4 : 2);
+  return std::min(need, cap);
+}
+
 template <int WK, bool A32>
-void launch_bin(Ctx &c, int bin, AggArgs a) {
-  const int64_t cnt = a.count;
+void launch_bin(Ctx &c, int bin, AggArgs a, int64_t grid) {
+  const dim3 gr((unsigned)grid);
   switch (bin) {
-    case 0:
-      hipLaunchKernelGGL((k_bm_group<8, 16, WK, A32>), dim3((unsigned)cdiv(cnt, BM_NT / 8)), dim3(BM_NT), 0,
-                         c.stream, a);
-      break;
-    case 1:
-      hipLaunchKernelGGL((k_bm_group<16, 32, WK, A32>), dim3((unsigned)cdiv(cnt, BM_NT / 16)), dim3(BM_NT), 0,
-                         c.stream, a);
-      break;
-    case 2:
-      hipLaunchKernelGGL((k_bm_group<32, 64, WK, A32>), dim3((unsigned)cdiv(cnt, BM_NT / 32)), dim3(BM_NT), 0,
-                         c.stream, a);
-      break;
-    case 3:
-      hipLaunchKernelGGL((k_bm_group<64, 128, WK, A32>), dim3((unsigned)cdiv(cnt, BM_NT / 64)), dim3(BM_NT), 0,
-                         c.stream, a);
-      break;
-    case 4:
-      hipLaunchKernelGGL((k_bm_group<64, 512, WK, A32>), dim3((unsigned)cdiv(cnt, BM_NT / 64)), dim3(BM_NT), 0,
-                         c.stream, a);
-      break;
+    case 0: hipLaunchKernelGGL((k_bm_group<8, 16, WK, A32>), gr, dim3(BM_NT), 0, c.stream, a); break;
+    case 1: hipLaunchKernelGGL((k_bm_group<16, 32, WK, A32>), gr, dim3(BM_NT), 0, c.stream, a); break;
+    case 2: hipLaunchKernelGGL((k_bm_group<32, 64, WK, A32>), gr, dim3(BM_NT), 0, c.stream, a); break;
+    case 3: hipLaunchKernelGGL((k_bm_group<64, 128, WK, A32>), gr, dim3(BM_NT), 0, c.stream, a); break;
+    case 4: hipLaunchKernelGGL((k_bm_group<64, 512, WK, A32>), gr, dim3(BM_NT), 0, c.stream, a); break;
     case 5: {
       a.hcap = MID_SLOTS;
       const size_t bytes = wide_lds_bytes(MID_SLOTS, A32);
-      hipLaunchKernelGGL((k_bm_wide<BM_NT, WK, A32>), dim3((unsigned)cnt), dim3(BM_NT), bytes, c.stream, a);
+      hipLaunchKernelGGL((k_bm_wide<BM_NT, WK, A32>), gr, dim3(BM_NT), bytes, c.stream, a);
       break;
     }
     case 6: {
       a.hcap = wide_slots(c, A32);
       const size_t bytes = wide_lds_bytes(a.hcap, A32);
       allow_lds(c, k_bm_wide<WIDE_NT, WK, A32>, bytes);
-      hipLaunchKernelGGL((k_bm_wide<WIDE_NT, WK, A32>), dim3((unsigned)cnt), dim3(WIDE_NT), bytes, c.stream, a);
+      hipLaunchKernelGGL((k_bm_wide<WIDE_NT, WK, A32>), gr, dim3(WIDE_NT), bytes, c.stream, a);
       break;
     }
     default:
@@ -993,31 +1217,16 @@ void launch_bin(Ctx &c, int bin, AggArgs a) {
 }
 
 // Singleton first iteration: lanes per vertex follow the degree bin.
-template <int WK> void launch_single(Ctx &c, int bin, AggArgs a) {
-  const int64_t cnt = a.count;
+template <int WK> void launch_single(Ctx &c, int bin, AggArgs a, int64_t grid) {
+  const dim3 gr((unsigned)grid);
   switch (bin) {
-    case 0:
-      hipLaunchKernelGGL((k_bm_single<8, BM_NT, WK>), dim3((unsigned)cdiv(cnt, BM_NT / 8)), dim3(BM_NT), 0,
-                         c.stream, a);
-      break;
-    case 1:
-      hipLaunchKernelGGL((k_bm_single<16, BM_NT, WK>), dim3((unsigned)cdiv(cnt, BM_NT / 16)), dim3(BM_NT), 0,
-                         c.stream, a);
-      break;
-    case 2:
-      hipLaunchKernelGGL((k_bm_single<32, BM_NT, WK>), dim3((unsigned)cdiv(cnt, BM_NT / 32)), dim3(BM_NT), 0,
-                         c.stream, a);
-      break;
+    case 0: hipLaunchKernelGGL((k_bm_single<8, BM_NT, WK>), gr, dim3(BM_NT), 0, c.stream, a); break;
+    case 1: hipLaunchKernelGGL((k_bm_single<16, BM_NT, WK>), gr, dim3(BM_NT), 0, c.stream, a); break;
+    case 2: hipLaunchKernelGGL((k_bm_single<32, BM_NT, WK>), gr, dim3(BM_NT), 0, c.stream, a); break;
     case 3:
-    case 4:
-      hipLaunchKernelGGL((k_bm_single<64, BM_NT, WK>), dim3((unsigned)cdiv(cnt, BM_NT / 64)), dim3(BM_NT), 0,
-                         c.stream, a);
-      break;
-    case 5:
-      hipLaunchKernelGGL((k_bm_single<BM_NT, BM_NT, WK>), dim3((unsigned)cnt), dim3(BM_NT), 0, c.stream, a);
-      break;
-    default:
-      hipLaunchKernelGGL((k_bm_single<WIDE_NT, WIDE_NT, WK>), dim3((unsigned)cnt), dim3(WIDE_NT), 0, c.stream, a);
+    case 4: hipLaunchKernelGGL((k_bm_single<64, BM_NT, WK>), gr, dim3(BM_NT), 0, c.stream, a); break;
+    case 5: hipLaunchKernelGGL((k_bm_single<BM_NT, BM_NT, WK>), gr, dim3(BM_NT), 0, c.stream, a); break;
+    default: hipLaunchKernelGGL((k_bm_single<WIDE_NT, WIDE_NT, WK>), gr, dim3(WIDE_NT), 0, c.stream, a);
   }
   LAUNCHCHECK();
 }
@@ -1062,11 +1271,56 @@ template <int WK> void launch_flat(Ctx &c, AggArgs a, int64_t arcs) {
   LAUNCHCHECK();
 }
 
-template <int WK> void launch_any(Ctx &c, int bin, bool a32, bool single, int64_t arcs, AggArgs a) {
-  if (single) launch_single<WK>(c, bin, a);
+template <int WK>
+void launch_any(Ctx &c, int bin, bool a32, bool single, int64_t arcs, AggArgs a, int64_t grid) {
+  if (single) launch_single<WK>(c, bin, a, grid);
   else if (bin == NBINS - 1) launch_flat<WK>(c, a, arcs);
-  else if (a32) launch_bin<WK, true>(c, bin, a);
-  else launch_bin<WK, false>(c, bin, a);
+  else if (a32) launch_bin<WK, true>(c, bin, a, grid);
+  else launch_bin<WK, false>(c, bin, a, grid);
+}
+
+int64_t pow2_host(int64_t x) {
+  int64_t h = 1;
+  while (h < x) h <<= 1;
+  return h;
+}
+
+// A small level's sub-round in one launch: one block per vertex, any degree
+// (the singleton sub-round needs no table).
+template <int WK> void launch_small_wk(Ctx &c, bool a32, bool single, AggArgs a, int64_t slots, int64_t grid) {
+  const dim3 gr((unsigned)grid);
+  if (single) {
+    hipLaunchKernelGGL((k_bm_single<BM_NT, BM_NT, WK>), gr, dim3(BM_NT), 0, c.stream, a);
+  } else if (a32) {
+    a.hcap = slots;
+    const size_t bytes = wide_lds_bytes(slots, true);
+    allow_lds(c, k_bm_wide<BM_NT, WK, true>, bytes);
+    hipLaunchKernelGGL((k_bm_wide<BM_NT, WK, true>), gr, dim3(BM_NT), bytes, c.stream, a);
+  } else {
+    a.hcap = slots;
+    const size_t bytes = wide_lds_bytes(slots, false);
+    allow_lds(c, k_bm_wide<BM_NT, WK, false>, bytes);
+    hipLaunchKernelGGL((k_bm_wide<BM_NT, WK, false>), gr, dim3(BM_NT), bytes, c.stream, a);
+  }
+  LAUNCHCHECK();
+}
+
+void launch_small(Ctx &c, int wk, bool a32, bool single, const AggArgs &a, int64_t slots, int64_t grid) {
+  switch (wk) {
+    case LCC_WT_UNIT: launch_small_wk<LCC_WT_UNIT>(c, a32, single, a, slots, grid); break;
+    case LCC_WT_I16: launch_small_wk<LCC_WT_I16>(c, a32, single, a, slots, grid); break;
+    case LCC_WT_I32: launch_small_wk<LCC_WT_I32>(c, a32, single, a, slots, grid); break;
+    default: launch_small_wk<LCC_WT_I64>(c, a32, single, a, slots, grid); break;
+  }
+}
+
+void launch_agg(Ctx &c, int wk, int bin, bool a32, bool single, int64_t arcs, const AggArgs &a, int64_t grid) {
+  switch (wk) {
+    case LCC_WT_UNIT: launch_any<LCC_WT_UNIT>(c, bin, a32, single, arcs, a, grid); break;
+    case LCC_WT_I16: launch_any<LCC_WT_I16>(c, bin, a32, single, arcs, a, grid); break;
+    case LCC_WT_I32: launch_any<LCC_WT_I32>(c, bin, a32, single, arcs, a, grid); break;
+    default: launch_any<LCC_WT_I64>(c, bin, a32, single, arcs, a, grid); break;
+  }
 }
 
 const char *bin_name(int b) {
@@ -1077,30 +1331,45 @@ const char *bin_name(int b) {
 }
 
 // Renames the non-empty fresh clusters to the smallest empty ids (see the
-// file comment); checks the pairing error counter.
-void rename_fresh(Ctx &c, int64_t n, int32_t *C, int64_t *K, int32_t *cnt, int64_t *err, const JobView &jv) {
+// file comment).  With `isoc` (device-driven iterations) the kernels skip
+// themselves after an iteration without isolation and a pairing error stays
+// in `err` for the caller's next read; without it the error is checked here.
+void rename_fresh(Ctx &c, int64_t n, int32_t *C, int64_t *K, int32_t *cnt, int64_t *err, const JobView &jv,
+                  const int64_t *isoc = nullptr, int S = 0) {
   Ctx::Timer tm(&c, "bm_rename", 0.0, (double)n);
   const size_t nn = (size_t)n;
-  uint8_t *fresh = c.buf<uint8_t>("rn.fresh", nn);
-  uint8_t *empty = c.buf<uint8_t>("rn.empty", nn);
   int32_t *rank_f = c.buf<int32_t>("rn.rankf", nn + 1);
   int32_t *rank_e = c.buf<int32_t>("rn.ranke", nn + 1);
   int32_t *elist = c.buf<int32_t>("rn.elist", nn);
   int32_t *newid = c.buf<int32_t>("rn.newid", nn);
-  const unsigned grid = (unsigned)std::min<int64_t>(cdiv(n, 256), 65536);
-  hipLaunchKernelGGL(k_fresh_flags, dim3(grid), dim3(256), 0, c.stream, cnt, n, fresh, empty);
-  LAUNCHCHECK();
-  scan<uint8_t, int32_t>(c, fresh, rank_f, n, false, rank_f + n);
-  scan<uint8_t, int32_t>(c, empty, rank_e, n, false, rank_e + n);
-  hipLaunchKernelGGL(k_empty_list, dim3(grid), dim3(256), 0, c.stream, empty, rank_e, rank_f, n, jv, elist);
-  LAUNCHCHECK();
-  hipLaunchKernelGGL(k_fresh_move, dim3(grid), dim3(256), 0, c.stream, fresh, rank_f, elist, n, K, cnt, newid, err);
-  LAUNCHCHECK();
-  hipLaunchKernelGGL(k_fresh_relabel, dim3(grid), dim3(256), 0, c.stream, C, n, newid);
-  LAUNCHCHECK();
-  int64_t e = 0;
-  d2h(c, &e, err, sizeof(e));
-  if (e) fail(LCC_ERR_DEVICE, "internal: fresh clusters outnumbered the empty cluster ids");
+  if (n <= RN_SMALL) {
+    hipLaunchKernelGGL(k_rename_small, dim3(1), dim3(RN_NT), 0, c.stream, C, n, K, cnt, rank_f, rank_e, elist, newid,
+                       jv, err, isoc, S);
+    LAUNCHCHECK();
+  } else {
+    uint8_t *fresh = c.buf<uint8_t>("rn.fresh", nn);
+    uint8_t *empty = c.buf<uint8_t>("rn.empty", nn);
+    const unsigned grid = (unsigned)std::min<int64_t>(cdiv(n, 256), 65536);
+    hipLaunchKernelGGL(k_fresh_flags, dim3(grid), dim3(256), 0, c.stream, cnt, n, fresh, empty, isoc, S);
+    LAUNCHCHECK();
+    // (after an iteration without isolation the flags are stale and every
+    // kernel reading the ranks skips itself)
+    scan<uint8_t, int32_t>(c, fresh, rank_f, n, false, rank_f + n);
+    scan<uint8_t, int32_t>(c, empty, rank_e, n, false, rank_e + n);
+    hipLaunchKernelGGL(k_empty_list, dim3(grid), dim3(256), 0, c.stream, empty, rank_e, rank_f, n, jv, elist, isoc,
+                       S);
+    LAUNCHCHECK();
+    hipLaunchKernelGGL(k_fresh_move, dim3(grid), dim3(256), 0, c.stream, fresh, rank_f, elist, n, K, cnt, newid, err,
+                       isoc, S);
+    LAUNCHCHECK();
+    hipLaunchKernelGGL(k_fresh_relabel, dim3(grid), dim3(256), 0, c.stream, C, n, newid, isoc, S);
+    LAUNCHCHECK();
+  }
+  if (!isoc) {
+    int64_t e = 0;
+    d2h(c, &e, err, sizeof(e));
+    if (e) fail(LCC_ERR_DEVICE, "internal: fresh clusters outnumbered the empty cluster ids");
+  }
 }
 
 }  // namespace
@@ -1120,13 +1389,13 @@ void best_moves(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_para
     jv.jmoved = c.buf<int64_t>("bt.moved", (size_t)J);
     hrun.assign(bl->active, bl->active + J);
     h2d(c, const_cast<uint8_t *>(jv.jrun), hrun.data(), (size_t)J);
-    c.sync();
+    HIPCHECK(hipMemsetAsync(jv.jmoved, 0, (size_t)J * sizeof(int64_t), c.stream));
     std::fill(bl->iters, bl->iters + J, 0);
     std::fill(bl->moved_any, bl->moved_any + J, 0);
   }
   const bool identity = shape.identity, acc32 = shape.acc32;
-  const int64_t maxdeg = shape.maxdeg;
   std::memset(&st, 0, sizeof(st));
+  st.term = LCC_TERM_NUM_ITER;
   const int64_t n = g.n;
   const int S = prm.S;
   const int NB = S * NBINS;
@@ -1139,15 +1408,6 @@ void best_moves(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_para
   int32_t *active = c.buf<int32_t>("bm.active", nn);
   int32_t *blist = c.buf<int32_t>("bm.blist", nn);
   uint16_t *bucket_of = c.buf<uint16_t>("bm.bucket", nn);
-  // per iteration: bucket counts, bucket arcs, cursors, per-launch counters,
-  // per-sub-round isolations, next-frontier size, isolation errors
-  const int LC = NSPREAD * NCTR;
-  const size_t nctr = (size_t)NB * 3 + (size_t)NB * LC + (size_t)S + 2;
-  int64_t *dctr = c.buf<int64_t>("bm.ctr", nctr);
-  int64_t *bcnt = dctr, *barcs = dctr + NB, *lctr = dctr + 3 * NB;  // dctr + 2 * NB: spare
-  int64_t *isoc = lctr + (size_t)LC * NB, *nact = isoc + S, *iso_err = nact + 1;
-  std::vector<int64_t> hctr(nctr);
-
   if (n > 0) {
     HIPCHECK(hipMemsetAsync(next, 0, nn, c.stream));
     HIPCHECK(hipMemsetAsync(K + n, 0, nn * sizeof(int64_t), c.stream));
@@ -1163,15 +1423,234 @@ void best_moves(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_para
   // bin 6 takes rows whose distinct clusters fill at most 70% of the LDS table
   const int64_t wslots = wide_slots(c, acc32);
   const int64_t wide_max = wslots * 7 / 10 - 1;
-  (void)maxdeg;
   const int wb = wt_bytes(g.wt_kind);
   const bool nbr = prm.frontier == LCC_FRONTIER_NBR;
+  const int LC = NSPREAD * NCTR;
+  static const char *wk_tag[4] = {"_unit", "_i16", "_i32", "_i64"};
+
+  // Per-iteration device counters: bucket counts, bucket arcs, bucket starts
+  // (NB + 1), per-launch counters, per-sub-round isolations, next-frontier
+  // size, pairing errors.
+  const int64_t o_bcnt = 0, o_barcs = NB, o_start = 2 * NB, o_lctr = 3 * NB + 1;
+  const int64_t o_isoc = o_lctr + (int64_t)LC * NB, o_nact = o_isoc + S, o_err = o_nact + 1, IB = o_err + 1;
+  const int64_t part_grid = std::min<int64_t>(std::max<int64_t>(1, cdiv(n, BM_NT * 8)), (int64_t)c.num_cu * 8);
+  int32_t *blkcnt = c.buf<int32_t>("bm.pblk", (size_t)(part_grid * NB));
+  int64_t *pcur = c.buf<int64_t>("bm.pcur", (size_t)(part_grid * NB));
+  const size_t part_smem = (size_t)2 * NB * sizeof(int64_t);
+
+  auto agg_args = [&](int bi, const int64_t *dstart, int64_t *ctr) {
+    AggArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.off = g.off;
+    a.col = g.col;
+    a.wt = g.wt;
+    a.k = g.k;
+    a.C = C;
+    a.K = K;
+    a.cnt = cnt;
+    a.p = p;
+    a.q = q;
+    a.allow_iso = prm.allow_isolate;
+    a.list = blist;
+    a.D = D;
+    a.next_flag = nbr ? next : nullptr;
+    a.ctr = ctr + (size_t)LC * bi;
+    a.jv = jv;
+    a.dstart = dstart;
+    a.bucket = bi;
+    a.nbuckets = 1;
+    return a;
+  };
+  auto class_name = [&](int b, bool single) {
+    return std::string(single ? "bm_single" : (b == NBINS - 1 ? "bm_flat_seq" : bin_name(b))) + wk_tag[g.wt_kind];
+  };
+  // Sums of the NSPREAD copies of a launch's counters.
+  auto launch_sums = [&](const int64_t *lctr, int bi, int k) {
+    int64_t t = 0;
+    for (int r = 0; r < NSPREAD; r++) t += lctr[(size_t)bi * LC + r * NCTR + k];
+    return t;
+  };
+
+  // Device-driven iterations: every kernel takes its bucket from device
+  // memory, so the host queues iterations without waiting and reads the
+  // counters back once per chunk of iterations.  An iteration queued after
+  // the one that ended the call changes nothing (no vertex moves against an
+  // unchanged state, and an empty frontier has no work), so only the
+  // counters up to the stopping iteration are used.  Rows wider than the
+  // LDS tables (the flat path sizes its tables on the host) and stopping
+  // inside an iteration take the host-driven path below.
+  const bool dd = n > 0 && prm.stop_after_subrounds == 0 && shape.maxdeg <= wide_max;
+  if (dd) {
+    // Small levels: one block partitions, and one block-per-vertex launch per
+    // sub-round covers every degree bin (fewer launches where the host's
+    // launch rate, not the work, sets the pace).  Larger levels: one launch
+    // per degree bin present in the level.
+    const bool small = n <= SMALL_LEVEL;
+    int64_t hist[NBINS] = {0};
+    if (!small) {
+      int64_t *hist_d = c.buf<int64_t>("bm.hist", NBINS);
+      HIPCHECK(hipMemsetAsync(hist_d, 0, NBINS * sizeof(int64_t), c.stream));
+      hipLaunchKernelGGL(k_bin_hist, dim3((unsigned)std::min<int64_t>(cdiv(n, BM_NT), (int64_t)c.num_cu * 4)),
+                         dim3(BM_NT), 0, c.stream, g.off, n, wide_max, hist_d);
+      LAUNCHCHECK();
+      d2h(c, hist, hist_d, sizeof(hist));
+    }
+    // table of the small-level kernel: room for the widest row of the level
+    const int64_t small_slots = std::min<int64_t>(pow2_host(2 * (shape.maxdeg + 1)), wslots);
+    const int32_t NI = std::max<int32_t>(prm.num_iter, 1);
+    int64_t *ctrs = c.buf<int64_t>("bm.ctrs", (size_t)(NI * IB));
+    HIPCHECK(hipMemsetAsync(ctrs, 0, (size_t)(NI * IB) * sizeof(int64_t), c.stream));
+    int32_t *jiters = nullptr;
+    uint8_t *jmoved_any = nullptr;
+    if (bl) {
+      jiters = c.buf<int32_t>("bt.iters", (size_t)J);
+      jmoved_any = c.buf<uint8_t>("bt.movedany", (size_t)J);
+      HIPCHECK(hipMemsetAsync(jiters, 0, (size_t)J * sizeof(int32_t), c.stream));
+      HIPCHECK(hipMemsetAsync(jmoved_any, 0, (size_t)J, c.stream));
+    }
+    const int64_t apply_grid = std::min<int64_t>(cdiv(n, BM_NT), (int64_t)c.num_cu * 8);
+    struct Timed {
+      size_t idx;
+      int32_t it, bi, nb;
+      bool single;
+    };
+    std::vector<Timed> timed;
+    std::vector<int64_t> h((size_t)(NI * IB));
+    int32_t queued = 0, chunk = 1;
+    bool done = false;
+    while (!done && queued < prm.num_iter) {
+      const int32_t first = queued, last = std::min<int32_t>(prm.num_iter, queued + chunk);
+      for (int32_t it = first; it < last; it++) {
+        int64_t *blk = ctrs + (size_t)it * IB;
+        const uint64_t hh = round_hash(prm.seed, level, phase, it);
+        // the first iteration and the "all vertices" rule take every vertex
+        const bool all = it == 0 || !nbr;
+        const int32_t *list = all ? nullptr : active;
+        const int64_t *na_dev = all ? nullptr : blk - IB + o_nact;
+        if (small) {
+          hipLaunchKernelGGL(k_part_small, dim3(1), dim3(PS_NT), part_smem, c.stream, list, n, na_dev, g.off, hh, S,
+                             wide_max, jv, bucket_of, blk + o_bcnt, blk + o_barcs, blk + o_start, blist);
+          LAUNCHCHECK();
+        } else {
+          hipLaunchKernelGGL(k_part_count, dim3((unsigned)part_grid), dim3(BM_NT), part_smem, c.stream, list, n,
+                             na_dev, g.off, hh, S, wide_max, jv, bucket_of, blkcnt, blk + o_bcnt, blk + o_barcs);
+          LAUNCHCHECK();
+          hipLaunchKernelGGL(k_part_offsets, dim3((unsigned)NB), dim3(BM_NT), 0, c.stream, blk + o_bcnt, blkcnt,
+                             part_grid, pcur, blk + o_start);
+          LAUNCHCHECK();
+          hipLaunchKernelGGL(k_part_scatter, dim3((unsigned)part_grid), dim3(BM_NT), part_smem, c.stream, list, n,
+                             na_dev, bucket_of, S, pcur, blist);
+          LAUNCHCHECK();
+        }
+        for (int s = 0; s < S; s++) {
+          const bool single = it == 0 && s == 0 && identity && shape.simple;
+          if (small) {
+            const int bi = s * NBINS;
+            AggArgs a = agg_args(bi, blk + o_start, blk + o_lctr);
+            a.nbuckets = NBINS;
+            const size_t pidx = c.pending.size();
+            {
+              Ctx::Timer tm(&c, (std::string(single ? "bm_single_small" : "bm_aggregate_small") + wk_tag[g.wt_kind]).c_str(),
+                            0.0, 0.0);
+              launch_small(c, g.wt_kind, acc32, single, a, small_slots, std::min<int64_t>(n, (int64_t)c.num_cu * 4));
+            }
+            if (c.timing) timed.push_back({pidx, it, bi, NBINS, single});
+          }
+          for (int b = 0; b < NBINS - 1 && !small; b++) {
+            if (!hist[b]) continue;
+            const int bi = s * NBINS + b;
+            const AggArgs a = agg_args(bi, blk + o_start, blk + o_lctr);
+            const size_t pidx = c.pending.size();
+            {
+              Ctx::Timer tm(&c, class_name(b, single).c_str(), 0.0, 0.0);
+              launch_agg(c, g.wt_kind, b, acc32, single, 0, a, bin_grid(c, b, hist[b], false));
+            }
+            if (c.timing) timed.push_back({pidx, it, bi, 1, single});
+          }
+          {
+            Ctx::Timer tm(&c, "bm_apply", 0.0, 0.0);
+            hipLaunchKernelGGL(k_bm_apply, dim3((unsigned)apply_grid), dim3(BM_NT), 0, c.stream, blist, (int64_t)0,
+                               blk + o_start, s * NBINS, (s + 1) * NBINS, D, C, K, cnt, g.k, n, blk + o_isoc + s,
+                               jv.jid, jv.jmoved);
+            LAUNCHCHECK();
+          }
+        }
+        if (nbr) compact_flags(c, next, n, active, blk + o_nact, true, "bm.cmp");
+        rename_fresh(c, n, C, K, cnt, blk + o_err, jv, blk + o_isoc, S);
+        if (bl) {
+          hipLaunchKernelGGL(k_job_update, dim3((unsigned)std::min<int64_t>(cdiv(J, 256), 1024)), dim3(256), 0,
+                             c.stream, const_cast<uint8_t *>(jv.jrun), jv.jmoved, jiters, jmoved_any, J);
+          LAUNCHCHECK();
+        }
+      }
+      queued = last;
+      d2h(c, h.data() + (size_t)first * IB, ctrs + (size_t)first * IB, (size_t)(last - first) * IB * sizeof(int64_t));
+      for (int32_t it = first; it < last && !done; it++) {
+        const int64_t *hb = h.data() + (size_t)it * IB;
+        const int64_t *hl = hb + o_lctr;
+        int64_t moved_it = 0, cap_err = 0;
+        for (int bi = 0; bi < NB; bi++) {
+          moved_it += launch_sums(hl, bi, 0);
+          st.candidates += launch_sums(hl, bi, 1);
+          cap_err += launch_sums(hl, bi, 3);
+          st.vertices_processed += hb[o_bcnt + bi];
+          st.arcs_scanned += hb[o_barcs + bi];
+        }
+        if (cap_err)
+          fail(LCC_ERR_DEVICE, "internal: a vertex degree exceeded the hash capacity sized from the maximum degree");
+        if (hb[o_err]) fail(LCC_ERR_DEVICE, "internal: fresh clusters outnumbered the empty cluster ids");
+        if (it < LCC_MAX_ITER_STATS) {
+          st.active_per_iter[it] = (it == 0 || !nbr) ? n : h[(size_t)(it - 1) * IB + o_nact];
+          st.moves_per_iter[it] = moved_it;
+        }
+        st.iterations++;
+        st.subrounds += S;
+        st.moves += moved_it;
+        if (moved_it) st.moved_any = 1;
+        if (moved_it == 0) {
+          st.term = LCC_TERM_NO_MOVES;
+          done = true;
+        }
+      }
+      // later chunks are longer only where a finished call leaves no work
+      if (nbr) chunk++;
+    }
+    if (c.timing) {
+      for (const Timed &t : timed) {
+        if (t.idx >= c.pending.size()) continue;
+        const int64_t *hb = h.data() + (size_t)t.it * IB;
+        double cntb = 0, arcs = 0;
+        for (int k = 0; k < t.nb; k++) {
+          cntb += (double)hb[o_bcnt + t.bi + k];
+          arcs += (double)hb[o_barcs + t.bi + k];
+        }
+        const double per_arc = t.single ? 12.0 + wb : 8.0 + wb;
+        // candidates gather K (8 B each); movers store one flag per neighbor
+        c.pending[t.idx].bytes = cntb * 48.0 + arcs * per_arc + 8.0 * (double)launch_sums(hb + o_lctr, t.bi, 1) +
+                                 (double)launch_sums(hb + o_lctr, t.bi, 2);
+        c.pending[t.idx].items = arcs;
+      }
+    }
+    if (bl) {
+      d2h(c, bl->iters, jiters, (size_t)J * sizeof(int32_t));
+      d2h(c, bl->moved_any, jmoved_any, (size_t)J);
+    }
+    if (c.timing) c.collect_timing();
+    return;
+  }
+
+  // Host-driven iterations: bucket sizes are read back before the launches.
+  const size_t nctr = (size_t)IB;
+  int64_t *dctr = c.buf<int64_t>("bm.ctr", nctr);
+  int64_t *bcnt = dctr + o_bcnt, *barcs = dctr + o_barcs, *dstart = dctr + o_start, *lctr = dctr + o_lctr;
+  int64_t *isoc = dctr + o_isoc, *nact = dctr + o_nact, *iso_err = dctr + o_err;
+  std::vector<int64_t> hctr(nctr);
   const int32_t *list = nullptr;  // nullptr = every vertex
   int64_t na = n;
-  st.term = LCC_TERM_NUM_ITER;
+  if (bl) c.sync();
   bool stopped = false;
   for (int32_t it = 0; it < prm.num_iter && !stopped; it++) {
-    const uint64_t h = round_hash(prm.seed, level, phase, it);
+    const uint64_t hh = round_hash(prm.seed, level, phase, it);
     st.iterations++;
     HIPCHECK(hipMemsetAsync(dctr, 0, nctr * sizeof(int64_t), c.stream));
     if (bl) {
@@ -1180,17 +1659,14 @@ void best_moves(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_para
         if (hrun[j]) bl->iters[j]++;
     }
     if (na > 0) {
-      const size_t smem = (size_t)2 * NB * sizeof(int64_t);
-      int64_t grid = std::min<int64_t>(cdiv(na, BM_NT * 8), (int64_t)c.num_cu * 8);
-      int32_t *blkcnt = c.buf<int32_t>("bm.pblk", (size_t)(grid * NB));
-      int64_t *pcur = c.buf<int64_t>("bm.pcur", (size_t)(grid * NB));
-      hipLaunchKernelGGL(k_part_count, dim3((unsigned)grid), dim3(BM_NT), smem, c.stream, list, na, g.off, h, S,
-                         wide_max, jv, bucket_of, blkcnt, bcnt, barcs);
+      hipLaunchKernelGGL(k_part_count, dim3((unsigned)part_grid), dim3(BM_NT), part_smem, c.stream, list, na,
+                         (const int64_t *)nullptr, g.off, hh, S, wide_max, jv, bucket_of, blkcnt, bcnt, barcs);
       LAUNCHCHECK();
-      hipLaunchKernelGGL(k_part_offsets, dim3((unsigned)NB), dim3(BM_NT), 0, c.stream, bcnt, blkcnt, grid, pcur);
+      hipLaunchKernelGGL(k_part_offsets, dim3((unsigned)NB), dim3(BM_NT), 0, c.stream, bcnt, blkcnt, part_grid, pcur,
+                         dstart);
       LAUNCHCHECK();
-      hipLaunchKernelGGL(k_part_scatter, dim3((unsigned)grid), dim3(BM_NT), smem, c.stream, list, na, bucket_of,
-                         S, pcur, blist);
+      hipLaunchKernelGGL(k_part_scatter, dim3((unsigned)part_grid), dim3(BM_NT), part_smem, c.stream, list, na,
+                         (const int64_t *)nullptr, bucket_of, S, pcur, blist);
       LAUNCHCHECK();
     }
     d2h(c, hctr.data(), dctr, (size_t)2 * NB * sizeof(int64_t));
@@ -1210,26 +1686,9 @@ void best_moves(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_para
         const int64_t cntb = hctr[bi];
         if (!cntb) continue;
         total_s += cntb;
-        AggArgs a;
-        a.off = g.off;
-        a.col = g.col;
-        a.wt = g.wt;
-        a.k = g.k;
-        a.C = C;
-        a.K = K;
-        a.cnt = cnt;
-        a.p = p;
-        a.q = q;
-        a.allow_iso = prm.allow_isolate;
+        AggArgs a = agg_args(bi, nullptr, lctr);
         a.list = blist + start[bi];
         a.count = cntb;
-        a.D = D;
-        a.next_flag = nbr ? next : nullptr;
-        a.ctr = lctr + (size_t)LC * bi;
-        a.gkeys = nullptr;
-        a.gvals = nullptr;
-        a.hcap = 0;
-        a.jv = jv;
         const int64_t arcs_i = hctr[NB + bi];
         const double arcs_b = (double)arcs_i;
         // first sub-round from singletons on rows without repeats: no
@@ -1238,53 +1697,39 @@ void best_moves(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_para
         size_t pidx = c.pending.size();
         {
           // algorithmic bytes: per vertex list, offsets, C, k, K, cnt, D (48 B);
-          // per arc col, C[u] (or k[u] for singletons) and the weight
+          // per arc col, C[u] (or k[u] for singletons) and the weight.  The
+          // flat bin is a sequence of kernels: timed as one class, never taken
+          // as "the" kernel of a roofline
           const double per_arc = single ? 12.0 + wb : 8.0 + wb;
-          // the flat bin is a sequence of kernels: timed as one class, never
-          // taken as "the" kernel of a roofline
-          // one timing class per kernel instantiation (bin, weight storage)
-          static const char *wk_tag[4] = {"_unit", "_i16", "_i32", "_i64"};
-          std::string nm = std::string(single ? "bm_single" : (b == NBINS - 1 ? "bm_flat_seq" : bin_name(b))) +
-                           wk_tag[g.wt_kind];
-          Ctx::Timer tm(&c, nm.c_str(), (double)cntb * 48.0 + arcs_b * per_arc, arcs_b);
-          switch (g.wt_kind) {
-            case LCC_WT_UNIT: launch_any<LCC_WT_UNIT>(c, b, acc32, single, arcs_i, a); break;
-            case LCC_WT_I16: launch_any<LCC_WT_I16>(c, b, acc32, single, arcs_i, a); break;
-            case LCC_WT_I32: launch_any<LCC_WT_I32>(c, b, acc32, single, arcs_i, a); break;
-            default: launch_any<LCC_WT_I64>(c, b, acc32, single, arcs_i, a); break;
-          }
+          Ctx::Timer tm(&c, class_name(b, single).c_str(), (double)cntb * 48.0 + arcs_b * per_arc, arcs_b);
+          launch_agg(c, g.wt_kind, b, acc32, single, arcs_i, a, bin_grid(c, b, cntb, true));
         }
         launches.push_back({c.timing ? pidx : (size_t)-1, bi});
         st.vertices_processed += cntb;
         st.arcs_scanned += hctr[NB + bi];
       }
       if (total_s > 0) {
-        {
-          Ctx::Timer tm(&c, "bm_apply", (double)total_s * 12.0, (double)total_s);
-          hipLaunchKernelGGL(k_bm_apply, dim3((unsigned)cdiv(total_s, BM_NT)), dim3(BM_NT), 0, c.stream,
-                             blist + start[s * NBINS], total_s, D, C, K, cnt, g.k, n, isoc + s, jv.jid, jv.jmoved);
-          LAUNCHCHECK();
-        }
+        Ctx::Timer tm(&c, "bm_apply", (double)total_s * 12.0, (double)total_s);
+        hipLaunchKernelGGL(k_bm_apply, dim3((unsigned)cdiv(total_s, BM_NT)), dim3(BM_NT), 0, c.stream,
+                           blist + start[s * NBINS], total_s, (const int64_t *)nullptr, 0, 0, D, C, K, cnt, g.k, n,
+                           isoc + s, jv.jid, jv.jmoved);
+        LAUNCHCHECK();
       }
       st.subrounds++;
     }
     // next frontier
     if (nbr && n > 0) compact_flags(c, next, n, active, nact, true, "bm.cmp");
-    d2h(c, hctr.data() + 3 * NB, lctr, (size_t)(LC * NB + S + 2) * sizeof(int64_t));
-    const int64_t *hl = hctr.data() + 3 * NB;
+    d2h(c, hctr.data() + o_lctr, lctr, (size_t)(LC * NB + S + 2) * sizeof(int64_t));
+    const int64_t *hl = hctr.data() + o_lctr;
     int64_t moved_it = 0, cap_err = 0;
-    std::vector<int64_t> lsum((size_t)NB * NCTR, 0);
-    for (int i = 0; i < NB; i++)
-      for (int r = 0; r < NSPREAD; r++)
-        for (int k = 0; k < NCTR; k++) lsum[(size_t)i * NCTR + k] += hl[(size_t)i * LC + r * NCTR + k];
-    for (int i = 0; i < NB; i++) {
-      moved_it += lsum[(size_t)i * NCTR + 0];
-      st.candidates += lsum[(size_t)i * NCTR + 1];
-      cap_err += lsum[(size_t)i * NCTR + 3];
+    for (int bi = 0; bi < NB; bi++) {
+      moved_it += launch_sums(hl, bi, 0);
+      st.candidates += launch_sums(hl, bi, 1);
+      cap_err += launch_sums(hl, bi, 3);
     }
-    const int64_t hl_nact = hl[(size_t)LC * NB + S];
+    const int64_t hl_nact = hctr[o_nact];
     int64_t isolated = 0;
-    for (int s = 0; s < S; s++) isolated += hl[(size_t)LC * NB + s];
+    for (int s = 0; s < S; s++) isolated += hctr[o_isoc + s];
     if (cap_err) fail(LCC_ERR_DEVICE, "internal: a vertex degree exceeded the hash capacity sized from the maximum degree");
     if (isolated) rename_fresh(c, n, C, K, cnt, iso_err, jv);
     if (bl) {
@@ -1310,7 +1755,7 @@ void best_moves(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_para
         if (L.pending_idx < c.pending.size()) {
           // candidates gather K (8 B each); movers store one flag per neighbor
           c.pending[L.pending_idx].bytes +=
-              8.0 * (double)lsum[(size_t)L.slot * NCTR + 1] + (double)lsum[(size_t)L.slot * NCTR + 2];
+              8.0 * (double)launch_sums(hl, L.slot, 1) + (double)launch_sums(hl, L.slot, 2);
         }
       }
     }

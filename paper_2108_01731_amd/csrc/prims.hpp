@@ -191,11 +191,39 @@ static __global__ __launch_bounds__(CMP_NT) void k_flag_scatter(uint8_t *__restr
   }
 }
 
+// Small inputs in one block and one launch: tiles of CMP_SMALL_NT flags in order.
+constexpr int CMP_SMALL_NT = 1024;
+constexpr int64_t CMP_SMALL = 16384;
+
+static __global__ __launch_bounds__(CMP_SMALL_NT) void k_flag_compact_small(uint8_t *__restrict__ flags, int64_t n,
+                                                                            int32_t *__restrict__ list,
+                                                                            int64_t *__restrict__ count, int clear) {
+  int64_t carry = 0;
+  for (int64_t x0 = 0; x0 < n; x0 += CMP_SMALL_NT) {
+    const int64_t x = x0 + threadIdx.x;
+    const int64_t f = x < n && flags[x] != 0;
+    int64_t tot;
+    const int64_t pos = carry + block_excl_scan<int64_t, CMP_SMALL_NT>(f, &tot);
+    if (f) {
+      list[pos] = (int32_t)x;
+      if (clear) flags[x] = 0;
+    }
+    carry += tot;
+  }
+  if (threadIdx.x == 0) *count = carry;
+}
+
 // list <- ascending indices i with flags[i] != 0; *count_dev <- their number.
 inline void compact_flags(Ctx &c, uint8_t *flags, int64_t n, int32_t *list, int64_t *count_dev, bool clear,
                           const char *tag = "cmp") {
   if (n <= 0) {
     HIPCHECK(hipMemsetAsync(count_dev, 0, sizeof(int64_t), c.stream));
+    return;
+  }
+  if (n <= CMP_SMALL) {
+    hipLaunchKernelGGL(k_flag_compact_small, dim3(1), dim3(CMP_SMALL_NT), 0, c.stream, flags, n, list, count_dev,
+                       (int)clear);
+    LAUNCHCHECK();
     return;
   }
   int64_t nb = cdiv(n, CMP_TILE);
