@@ -106,21 +106,27 @@ def main():
     prm = lcc.Params()
     for i in range(args.warmup):
         lab, N, st = lcc.lcc_cluster(ctx, g, p, q, prm)
-        log(f"warmup {i}: {st['ms_total']:.1f} ms, levels={st['levels']} clusters={st['clusters']}")
+        log(f"warmup {i}: {st['ms_total']:.1f} ms, levels={st['levels']} clusters={st['clusters']} N={N}")
     arcs_total = 0
+    Ns = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
         lab, N, st = lcc.lcc_cluster(ctx, g, p, q, prm)
         arcs_total += st["arcs_scanned_total"]
+        Ns.append(N)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    if len(set(Ns)) != 1:
+        log(f"WARNING: the timed steps disagree on the objective numerator: {Ns}")
     ms_per_step = dt * 1e3 / args.steps
     # one more step with HIP events around every launch (on the launch
     # stream): per-kernel times for the table below and the roofline
     ctx.reset_kernel_stats()
-    _, _, st_t = lcc.lcc_cluster(ctx, g, p, q, lcc.Params(timing=1))
+    _, N_t, st_t = lcc.lcc_cluster(ctx, g, p, q, lcc.Params(timing=1))
     log(f"instrumented step: {st_t['ms_total']:.1f} ms")
+    if N_t != Ns[-1]:
+        log(f"WARNING: the instrumented step's objective numerator {N_t} differs from {Ns[-1]}")
     ks = ctx.kernel_stats()
     for name, v in sorted(ks.items(), key=lambda kv: -kv[1]["ms"]):
         sec = v["ms"] * 1e-3

@@ -540,18 +540,55 @@ constexpr int B7_NT = 256;
 constexpr int B7_PER_LANE = 8;
 constexpr int64_t B7_WAVE_ARCS = (int64_t)WAVE * B7_PER_LANE;
 
-__global__ void k_b7_prep(const int32_t *__restrict__ list, int64_t n7, const int64_t *__restrict__ off,
-                          int64_t *__restrict__ deg, int64_t *__restrict__ cap) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n7; i += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t v = list[i];
-    const int64_t d = off[v + 1] - off[v];
-    deg[i] = d;
-    cap[i] = pow2_at_least(2 * (d + 1));
+// Layout of the bucket's hub rows, in one block: exclusive prefixes of the
+// degrees (astart), table capacities (tstart, cap = pow2 >= 2(deg + 1)) and
+// scoring segments (sstart), n7 + 1 entries each; tot = {arcs, slots,
+// segments, n7}.
+constexpr int B7L_NT = 1024;
+constexpr int64_t B7_SEG = 4096;
+
+__global__ __launch_bounds__(B7L_NT) void k_b7_layout(AggArgs a, int64_t *__restrict__ astart,
+                                                      int64_t *__restrict__ tstart, int64_t *__restrict__ sstart,
+                                                      int64_t *__restrict__ tot) {
+  const int32_t *list;
+  int64_t n7;
+  work_of(a, list, n7);
+  int64_t ca = 0, ct = 0, cs = 0;
+  for (int64_t i0 = 0; i0 < n7; i0 += B7L_NT) {
+    const int64_t i = i0 + threadIdx.x;
+    int64_t d = 0, cap = 0, ns = 0;
+    if (i < n7) {
+      const int32_t v = list[i];
+      d = a.off[v + 1] - a.off[v];
+      cap = pow2_at_least(2 * (d + 1));
+      ns = cdiv(cap, B7_SEG);
+    }
+    int64_t td, tc, tn;
+    const int64_t pd = block_excl_scan<int64_t, B7L_NT>(d, &td);
+    const int64_t pc = block_excl_scan<int64_t, B7L_NT>(cap, &tc);
+    const int64_t pn = block_excl_scan<int64_t, B7L_NT>(ns, &tn);
+    if (i < n7) {
+      astart[i] = ca + pd;
+      tstart[i] = ct + pc;
+      sstart[i] = cs + pn;
+    }
+    ca += td;
+    ct += tc;
+    cs += tn;
+  }
+  if (threadIdx.x == 0) {
+    astart[n7] = ca;
+    tstart[n7] = ct;
+    sstart[n7] = cs;
+    tot[0] = ca;
+    tot[1] = ct;
+    tot[2] = cs;
+    tot[3] = n7;
   }
 }
 
-__global__ void k_b7_clear(int32_t *__restrict__ keys, int64_t *__restrict__ vals, const int64_t *__restrict__ T) {
-  const int64_t total = *T;
+__global__ void k_b7_clear(int32_t *__restrict__ keys, int64_t *__restrict__ vals, const int64_t *__restrict__ tot) {
+  const int64_t total = tot[1];
   for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < total; j += (int64_t)gridDim.x * blockDim.x) {
     keys[j] = -1;
     vals[j] = 0;
@@ -578,10 +615,14 @@ __device__ __forceinline__ void global_insert(int32_t *keys, int64_t *vals, uint
 
 // astart / tstart hold n7 + 1 entries (the last = totals).
 template <int WK>
-__global__ __launch_bounds__(B7_NT) void k_b7_insert(AggArgs a, int64_t n7, const int64_t *__restrict__ astart,
+__global__ __launch_bounds__(B7_NT) void k_b7_insert(AggArgs a, const int64_t *__restrict__ tot,
+                                                     const int64_t *__restrict__ astart,
                                                      const int64_t *__restrict__ tstart) {
   const int lane = lane_id();
-  const int64_t A = astart[n7];
+  const int32_t *list;
+  int64_t cnt7;
+  work_of(a, list, cnt7);
+  const int64_t A = tot[0], n7 = tot[3];
   const int64_t wave = ((int64_t)blockIdx.x * B7_NT + threadIdx.x) / WAVE;
   const int64_t nwaves = ((int64_t)gridDim.x * B7_NT) / WAVE;
   for (int64_t base = wave * B7_WAVE_ARCS; base < A; base += nwaves * B7_WAVE_ARCS) {
@@ -605,7 +646,7 @@ __global__ __launch_bounds__(B7_NT) void k_b7_insert(AggArgs a, int64_t n7, cons
       if (x >= A) break;
       while (x >= astart[i + 1]) i++;
       if (a0 != astart[i] || v < 0) {
-        v = a.list[i];
+        v = list[i];
         a0 = astart[i];
         a1 = astart[i + 1];
         e0 = a.off[v];
@@ -622,7 +663,6 @@ __global__ __launch_bounds__(B7_NT) void k_b7_insert(AggArgs a, int64_t n7, cons
 
 // Scoring of the hub tables, one block per B7_SEG-slot segment (a row's
 // table spans cdiv(cap, B7_SEG) segments, sstart = prefix of segment counts).
-constexpr int64_t B7_SEG = 4096;
 
 struct SegBest {
   int64_t best_s;
@@ -632,15 +672,15 @@ struct SegBest {
   int32_t pad;
 };
 
-__global__ void k_b7_nseg(const int64_t *__restrict__ cap, int64_t n7, int64_t *__restrict__ nseg) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n7; i += (int64_t)gridDim.x * blockDim.x)
-    nseg[i] = cdiv(cap[i], B7_SEG);
-}
-
-__global__ __launch_bounds__(B7_NT) void k_b7_segscore(AggArgs a, int64_t n7, const int64_t *__restrict__ tstart,
+__global__ __launch_bounds__(B7_NT) void k_b7_segscore(AggArgs a, const int64_t *__restrict__ tot,
+                                                       const int64_t *__restrict__ tstart,
                                                        const int64_t *__restrict__ sstart,
                                                        SegBest *__restrict__ part) {
-  const int64_t sg = blockIdx.x;
+  const int32_t *list;
+  int64_t cnt7;
+  work_of(a, list, cnt7);
+  const int64_t nsg = tot[2], n7 = tot[3];
+  for (int64_t sg = blockIdx.x; sg < nsg; sg += gridDim.x) {
   // row owning this segment
   int64_t lo = 0, hi = n7 - 1;
   while (lo < hi) {
@@ -649,7 +689,7 @@ __global__ __launch_bounds__(B7_NT) void k_b7_segscore(AggArgs a, int64_t n7, co
     else hi = mid - 1;
   }
   const int64_t i = lo;
-  const int32_t v = a.list[i];
+  const int32_t v = list[i];
   const int32_t c = a.C[v];
   int64_t lp, lq;
   int32_t job;
@@ -686,6 +726,8 @@ __global__ __launch_bounds__(B7_NT) void k_b7_segscore(AggArgs a, int64_t n7, co
     for (int k = 0; k < B7_NT / WAVE; k++) tc += rc[k];
     part[sg] = SegBest{best_s, wc, tc, best_id, 0};
   }
+  __syncthreads();  // rc is reused by the next segment
+  }
 }
 
 // One block per row: combines the row's segments, decides, marks the frontier.
@@ -693,13 +735,17 @@ __global__ __launch_bounds__(B7_NT) void k_b7_final(AggArgs a, const int64_t *__
                                                     const SegBest *__restrict__ part) {
   __shared__ int32_t sh_d;
   const int t = threadIdx.x;
-  const int64_t i = blockIdx.x;
-  const int32_t v = a.list[i];
+  const int32_t *list;
+  int64_t n7;
+  work_of(a, list, n7);
+  int64_t movers = 0, marcs = 0, cands = 0;
+  for (int64_t i = blockIdx.x; i < n7; i += gridDim.x) {
+  const int32_t v = list[i];
   const int64_t beg = a.off[v], end = a.off[v + 1];
   const int32_t c = a.C[v];
   const int64_t kv = a.k[v], Kc = a.K[c];
   const int32_t cntc = a.cnt[c];
-  int64_t best_s = INT64_MIN, wc = 0, cands = 0;
+  int64_t best_s = INT64_MIN, wc = 0;
   int32_t best_id = ISO_ID;
   for (int64_t sg = sstart[i] + t; sg < sstart[i + 1]; sg += B7_NT) {
     const SegBest b = part[sg];
@@ -711,7 +757,6 @@ __global__ __launch_bounds__(B7_NT) void k_b7_final(AggArgs a, const int64_t *__
     cands += b.cands;
   }
   block_best<B7_NT>(best_s, best_id, wc);
-  int64_t movers = 0, marcs = 0;
   if (t == 0) {
     int64_t lp, lq;
     int32_t job;
@@ -721,13 +766,15 @@ __global__ __launch_bounds__(B7_NT) void k_b7_final(AggArgs a, const int64_t *__
     a.D[v] = d;
     sh_d = d;
     if (d != c) {
-      movers = 1;
-      marcs = end - beg;
+      movers += 1;
+      marcs += end - beg;
     }
   }
   __syncthreads();
   if (sh_d != c && a.next_flag)
     for (int64_t e = beg + t; e < end; e += B7_NT) a.next_flag[a.col[e]] = 1;
+  __syncthreads();  // sh_d is reused by the next row
+  }
   flush_counters<B7_NT>(a.ctr, movers, cands, marcs);
 }
 
@@ -949,16 +996,21 @@ __global__ void k_job_update(uint8_t *__restrict__ jrun, int64_t *__restrict__ j
   }
 }
 
-// Vertices per degree bin (upper bounds of every bucket of a Best-Moves call).
+// Vertices and arcs per degree bin (upper bounds of every bucket of a
+// Best-Moves call): hist[b], hist[NBINS + b].
 __global__ __launch_bounds__(BM_NT) void k_bin_hist(const int64_t *__restrict__ off, int64_t n, int64_t wide_max,
                                                     int64_t *__restrict__ hist) {
-  __shared__ int64_t lh[NBINS];
-  if (threadIdx.x < NBINS) lh[threadIdx.x] = 0;
+  __shared__ int64_t lh[2 * NBINS];
+  if (threadIdx.x < 2 * NBINS) lh[threadIdx.x] = 0;
   __syncthreads();
-  for (int64_t v = (int64_t)blockIdx.x * BM_NT + threadIdx.x; v < n; v += (int64_t)gridDim.x * BM_NT)
-    atomicAdd(reinterpret_cast<unsigned long long *>(&lh[bin_of(off[v + 1] - off[v], wide_max)]), 1ull);
+  for (int64_t v = (int64_t)blockIdx.x * BM_NT + threadIdx.x; v < n; v += (int64_t)gridDim.x * BM_NT) {
+    const int64_t d = off[v + 1] - off[v];
+    const int b = bin_of(d, wide_max);
+    atomicAdd(reinterpret_cast<unsigned long long *>(&lh[b]), 1ull);
+    if (d) atomicAdd(reinterpret_cast<unsigned long long *>(&lh[NBINS + b]), (unsigned long long)d);
+  }
   __syncthreads();
-  if (threadIdx.x < NBINS && lh[threadIdx.x]) atomic_add_i64(&hist[threadIdx.x], lh[threadIdx.x]);
+  if (threadIdx.x < 2 * NBINS && lh[threadIdx.x]) atomic_add_i64(&hist[threadIdx.x], lh[threadIdx.x]);
 }
 
 // --- partition of the active vertices into (sub-round, bin) buckets
@@ -1231,50 +1283,43 @@ template <int WK> void launch_single(Ctx &c, int bin, AggArgs a, int64_t grid) {
   LAUNCHCHECK();
 }
 
-// Flat aggregation of the rows of bin 7 (see k_b7_insert).
-template <int WK> void launch_flat(Ctx &c, AggArgs a, int64_t arcs) {
-  const int64_t n7 = a.count;
-  int64_t *deg = c.buf<int64_t>("b7.deg", (size_t)n7 + 1);
-  int64_t *cap = c.buf<int64_t>("b7.cap", (size_t)n7 + 1);
-  int64_t *astart = c.buf<int64_t>("b7.astart", (size_t)n7 + 1);
-  int64_t *tstart = c.buf<int64_t>("b7.tstart", (size_t)n7 + 1);
-  // sum of capacities <= 4 (arcs + n7)
-  const size_t slots = (size_t)(4 * (arcs + n7));
+// Flat aggregation of the rows of bin 7 (see k_b7_insert).  Sizes are upper
+// bounds (at most n7_ub rows holding at most a7_ub arcs); the kernels read
+// the actual ones from the layout, so nothing is read back.
+template <int WK> void launch_flat(Ctx &c, AggArgs a, int64_t n7_ub, int64_t a7_ub) {
+  n7_ub = std::max<int64_t>(n7_ub, 1);
+  int64_t *astart = c.buf<int64_t>("b7.astart", (size_t)n7_ub + 1);
+  int64_t *tstart = c.buf<int64_t>("b7.tstart", (size_t)n7_ub + 1);
+  int64_t *sstart = c.buf<int64_t>("b7.sstart", (size_t)n7_ub + 1);
+  int64_t *tot = c.buf<int64_t>("b7.tot", 4);
+  // capacities: pow2 >= 2(deg + 1) <= 4(deg + 1)
+  const size_t slots = (size_t)(4 * (a7_ub + n7_ub));
   a.gkeys = c.buf<int32_t>("b7.keys", slots);
   a.gvals = c.buf<int64_t>("b7.vals", slots);
-  hipLaunchKernelGGL(k_b7_prep, dim3((unsigned)std::min<int64_t>(cdiv(n7, 256), 4096)), dim3(256), 0, c.stream,
-                     a.list, n7, a.off, deg, cap);
-  LAUNCHCHECK();
-  scan<int64_t, int64_t>(c, deg, astart, n7, false, astart + n7);
-  scan<int64_t, int64_t>(c, cap, tstart, n7, false, tstart + n7);
-  hipLaunchKernelGGL(k_b7_clear, dim3((unsigned)c.num_cu * 8), dim3(256), 0, c.stream, a.gkeys, a.gvals,
-                     tstart + n7);
-  LAUNCHCHECK();
-  const int64_t waves = cdiv(arcs, B7_WAVE_ARCS);
-  const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(cdiv(waves, B7_NT / WAVE), 65536));
-  hipLaunchKernelGGL((k_b7_insert<WK>), dim3((unsigned)grid), dim3(B7_NT), 0, c.stream, a, n7, astart, tstart);
-  LAUNCHCHECK();
-  // segments: at most (sum of capacities) / B7_SEG + n7
-  int64_t *nseg = c.buf<int64_t>("b7.nseg", (size_t)n7 + 1);
-  int64_t *sstart = c.buf<int64_t>("b7.sstart", (size_t)n7 + 1);
-  const int64_t max_seg = (int64_t)slots / B7_SEG + n7;
+  const int64_t max_seg = (int64_t)slots / B7_SEG + n7_ub;
   SegBest *part = c.buf<SegBest>("b7.part", (size_t)max_seg);
-  hipLaunchKernelGGL(k_b7_nseg, dim3((unsigned)std::min<int64_t>(cdiv(n7, 256), 4096)), dim3(256), 0, c.stream, cap,
-                     n7, nseg);
+  hipLaunchKernelGGL(k_b7_layout, dim3(1), dim3(B7L_NT), 0, c.stream, a, astart, tstart, sstart, tot);
   LAUNCHCHECK();
-  scan<int64_t, int64_t>(c, nseg, sstart, n7, false, sstart + n7);
-  int64_t nsegs = 0;
-  d2h(c, &nsegs, sstart + n7, sizeof(int64_t));
-  hipLaunchKernelGGL(k_b7_segscore, dim3((unsigned)nsegs), dim3(B7_NT), 0, c.stream, a, n7, tstart, sstart, part);
+  hipLaunchKernelGGL(k_b7_clear, dim3((unsigned)c.num_cu * 8), dim3(256), 0, c.stream, a.gkeys, a.gvals, tot);
   LAUNCHCHECK();
-  hipLaunchKernelGGL(k_b7_final, dim3((unsigned)n7), dim3(B7_NT), 0, c.stream, a, sstart, part);
+  const int64_t waves = cdiv(std::max<int64_t>(a7_ub, 1), B7_WAVE_ARCS);
+  const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(cdiv(waves, B7_NT / WAVE), 65536));
+  hipLaunchKernelGGL((k_b7_insert<WK>), dim3((unsigned)grid), dim3(B7_NT), 0, c.stream, a, tot, astart, tstart);
+  LAUNCHCHECK();
+  hipLaunchKernelGGL(k_b7_segscore, dim3((unsigned)std::min<int64_t>(max_seg, (int64_t)c.num_cu * 8)), dim3(B7_NT), 0,
+                     c.stream, a, tot, tstart, sstart, part);
+  LAUNCHCHECK();
+  hipLaunchKernelGGL(k_b7_final, dim3((unsigned)std::min<int64_t>(n7_ub, (int64_t)c.num_cu * 4)), dim3(B7_NT), 0,
+                     c.stream, a, sstart, part);
   LAUNCHCHECK();
 }
 
+// ub_count / ub_arcs: upper bounds of the bucket's vertices and arcs.
 template <int WK>
-void launch_any(Ctx &c, int bin, bool a32, bool single, int64_t arcs, AggArgs a, int64_t grid) {
+void launch_any(Ctx &c, int bin, bool a32, bool single, int64_t ub_count, int64_t ub_arcs, AggArgs a,
+                int64_t grid) {
   if (single) launch_single<WK>(c, bin, a, grid);
-  else if (bin == NBINS - 1) launch_flat<WK>(c, a, arcs);
+  else if (bin == NBINS - 1) launch_flat<WK>(c, a, ub_count, ub_arcs);
   else if (a32) launch_bin<WK, true>(c, bin, a, grid);
   else launch_bin<WK, false>(c, bin, a, grid);
 }
@@ -1314,12 +1359,13 @@ void launch_small(Ctx &c, int wk, bool a32, bool single, const AggArgs &a, int64
   }
 }
 
-void launch_agg(Ctx &c, int wk, int bin, bool a32, bool single, int64_t arcs, const AggArgs &a, int64_t grid) {
+void launch_agg(Ctx &c, int wk, int bin, bool a32, bool single, int64_t ub_count, int64_t ub_arcs,
+                const AggArgs &a, int64_t grid) {
   switch (wk) {
-    case LCC_WT_UNIT: launch_any<LCC_WT_UNIT>(c, bin, a32, single, arcs, a, grid); break;
-    case LCC_WT_I16: launch_any<LCC_WT_I16>(c, bin, a32, single, arcs, a, grid); break;
-    case LCC_WT_I32: launch_any<LCC_WT_I32>(c, bin, a32, single, arcs, a, grid); break;
-    default: launch_any<LCC_WT_I64>(c, bin, a32, single, arcs, a, grid); break;
+    case LCC_WT_UNIT: launch_any<LCC_WT_UNIT>(c, bin, a32, single, ub_count, ub_arcs, a, grid); break;
+    case LCC_WT_I16: launch_any<LCC_WT_I16>(c, bin, a32, single, ub_count, ub_arcs, a, grid); break;
+    case LCC_WT_I32: launch_any<LCC_WT_I32>(c, bin, a32, single, ub_count, ub_arcs, a, grid); break;
+    default: launch_any<LCC_WT_I64>(c, bin, a32, single, ub_count, ub_arcs, a, grid); break;
   }
 }
 
@@ -1479,17 +1525,17 @@ void best_moves(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_para
   // counters up to the stopping iteration are used.  Rows wider than the
   // LDS tables (the flat path sizes its tables on the host) and stopping
   // inside an iteration take the host-driven path below.
-  const bool dd = n > 0 && prm.stop_after_subrounds == 0 && shape.maxdeg <= wide_max;
+  const bool dd = n > 0 && prm.stop_after_subrounds == 0;
   if (dd) {
     // Small levels: one block partitions, and one block-per-vertex launch per
     // sub-round covers every degree bin (fewer launches where the host's
     // launch rate, not the work, sets the pace).  Larger levels: one launch
     // per degree bin present in the level.
-    const bool small = n <= SMALL_LEVEL;
-    int64_t hist[NBINS] = {0};
+    const bool small = n <= SMALL_LEVEL && shape.maxdeg <= wide_max;
+    int64_t hist[2 * NBINS] = {0};
     if (!small) {
-      int64_t *hist_d = c.buf<int64_t>("bm.hist", NBINS);
-      HIPCHECK(hipMemsetAsync(hist_d, 0, NBINS * sizeof(int64_t), c.stream));
+      int64_t *hist_d = c.buf<int64_t>("bm.hist", 2 * NBINS);
+      HIPCHECK(hipMemsetAsync(hist_d, 0, 2 * NBINS * sizeof(int64_t), c.stream));
       hipLaunchKernelGGL(k_bin_hist, dim3((unsigned)std::min<int64_t>(cdiv(n, BM_NT), (int64_t)c.num_cu * 4)),
                          dim3(BM_NT), 0, c.stream, g.off, n, wide_max, hist_d);
       LAUNCHCHECK();
@@ -1556,14 +1602,14 @@ void best_moves(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_para
             }
             if (c.timing) timed.push_back({pidx, it, bi, NBINS, single});
           }
-          for (int b = 0; b < NBINS - 1 && !small; b++) {
+          for (int b = 0; b < NBINS && !small; b++) {
             if (!hist[b]) continue;
             const int bi = s * NBINS + b;
             const AggArgs a = agg_args(bi, blk + o_start, blk + o_lctr);
             const size_t pidx = c.pending.size();
             {
               Ctx::Timer tm(&c, class_name(b, single).c_str(), 0.0, 0.0);
-              launch_agg(c, g.wt_kind, b, acc32, single, 0, a, bin_grid(c, b, hist[b], false));
+              launch_agg(c, g.wt_kind, b, acc32, single, hist[b], hist[NBINS + b], a, bin_grid(c, b, hist[b], false));
             }
             if (c.timing) timed.push_back({pidx, it, bi, 1, single});
           }
@@ -1702,7 +1748,7 @@ void best_moves(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_para
           // as "the" kernel of a roofline
           const double per_arc = single ? 12.0 + wb : 8.0 + wb;
           Ctx::Timer tm(&c, class_name(b, single).c_str(), (double)cntb * 48.0 + arcs_b * per_arc, arcs_b);
-          launch_agg(c, g.wt_kind, b, acc32, single, arcs_i, a, bin_grid(c, b, cntb, true));
+          launch_agg(c, g.wt_kind, b, acc32, single, cntb, arcs_i, a, bin_grid(c, b, cntb, true));
         }
         launches.push_back({c.timing ? pidx : (size_t)-1, bi});
         st.vertices_processed += cntb;
