@@ -100,6 +100,7 @@ def main():
         p, q = 1, int(h.arcs)  # lambda = 1/(2m)
     g = lcc.DeviceGraph.from_host(h, dev)
     torch.cuda.synchronize()
+    torch.cuda.empty_cache()  # the generator's scratch goes back to the device for the library
     log(f"workload {args.workload}: n={g.n} arcs={g.arcs} generated in {time.time() - t0:.1f}s")
 
     ctx = lcc.context(0)

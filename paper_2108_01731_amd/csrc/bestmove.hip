@@ -1330,32 +1330,44 @@ int64_t pow2_host(int64_t x) {
   return h;
 }
 
-// A small level's sub-round in one launch: one block per vertex, any degree
-// (the singleton sub-round needs no table).
-template <int WK> void launch_small_wk(Ctx &c, bool a32, bool single, AggArgs a, int64_t slots, int64_t grid) {
+// A small level's sub-round: one block per vertex, the degree bins below
+// 2048 in one launch (256 threads, MID_SLOTS table) and the wider bin in a
+// second one (WIDE_NT threads, table up to `slots`) when the level has such
+// rows.  The singleton sub-round needs no table.
+template <int NT, int WK> void launch_small_wk(Ctx &c, bool a32, bool single, AggArgs a, int64_t slots, int64_t grid) {
   const dim3 gr((unsigned)grid);
   if (single) {
-    hipLaunchKernelGGL((k_bm_single<BM_NT, BM_NT, WK>), gr, dim3(BM_NT), 0, c.stream, a);
+    hipLaunchKernelGGL((k_bm_single<NT, NT, WK>), gr, dim3(NT), 0, c.stream, a);
   } else if (a32) {
     a.hcap = slots;
     const size_t bytes = wide_lds_bytes(slots, true);
-    allow_lds(c, k_bm_wide<BM_NT, WK, true>, bytes);
-    hipLaunchKernelGGL((k_bm_wide<BM_NT, WK, true>), gr, dim3(BM_NT), bytes, c.stream, a);
+    allow_lds(c, k_bm_wide<NT, WK, true>, bytes);
+    hipLaunchKernelGGL((k_bm_wide<NT, WK, true>), gr, dim3(NT), bytes, c.stream, a);
   } else {
     a.hcap = slots;
     const size_t bytes = wide_lds_bytes(slots, false);
-    allow_lds(c, k_bm_wide<BM_NT, WK, false>, bytes);
-    hipLaunchKernelGGL((k_bm_wide<BM_NT, WK, false>), gr, dim3(BM_NT), bytes, c.stream, a);
+    allow_lds(c, k_bm_wide<NT, WK, false>, bytes);
+    hipLaunchKernelGGL((k_bm_wide<NT, WK, false>), gr, dim3(NT), bytes, c.stream, a);
   }
   LAUNCHCHECK();
 }
 
-void launch_small(Ctx &c, int wk, bool a32, bool single, const AggArgs &a, int64_t slots, int64_t grid) {
-  switch (wk) {
-    case LCC_WT_UNIT: launch_small_wk<LCC_WT_UNIT>(c, a32, single, a, slots, grid); break;
-    case LCC_WT_I16: launch_small_wk<LCC_WT_I16>(c, a32, single, a, slots, grid); break;
-    case LCC_WT_I32: launch_small_wk<LCC_WT_I32>(c, a32, single, a, slots, grid); break;
-    default: launch_small_wk<LCC_WT_I64>(c, a32, single, a, slots, grid); break;
+void launch_small(Ctx &c, int wk, bool wide_rows, bool a32, bool single, const AggArgs &a, int64_t slots,
+                  int64_t grid) {
+  if (wide_rows) {
+    switch (wk) {
+      case LCC_WT_UNIT: launch_small_wk<WIDE_NT, LCC_WT_UNIT>(c, a32, single, a, slots, grid); break;
+      case LCC_WT_I16: launch_small_wk<WIDE_NT, LCC_WT_I16>(c, a32, single, a, slots, grid); break;
+      case LCC_WT_I32: launch_small_wk<WIDE_NT, LCC_WT_I32>(c, a32, single, a, slots, grid); break;
+      default: launch_small_wk<WIDE_NT, LCC_WT_I64>(c, a32, single, a, slots, grid); break;
+    }
+  } else {
+    switch (wk) {
+      case LCC_WT_UNIT: launch_small_wk<BM_NT, LCC_WT_UNIT>(c, a32, single, a, slots, grid); break;
+      case LCC_WT_I16: launch_small_wk<BM_NT, LCC_WT_I16>(c, a32, single, a, slots, grid); break;
+      case LCC_WT_I32: launch_small_wk<BM_NT, LCC_WT_I32>(c, a32, single, a, slots, grid); break;
+      default: launch_small_wk<BM_NT, LCC_WT_I64>(c, a32, single, a, slots, grid); break;
+    }
   }
 }
 
@@ -1541,7 +1553,9 @@ void best_moves(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_para
       LAUNCHCHECK();
       d2h(c, hist, hist_d, sizeof(hist));
     }
-    // table of the small-level kernel: room for the widest row of the level
+    // tables of the small-level kernels: MID_SLOTS below degree 2048, else
+    // room for the widest row of the level
+    const bool wide_rows = shape.maxdeg > 2047;
     const int64_t small_slots = std::min<int64_t>(pow2_host(2 * (shape.maxdeg + 1)), wslots);
     const int32_t NI = std::max<int32_t>(prm.num_iter, 1);
     int64_t *ctrs = c.buf<int64_t>("bm.ctrs", (size_t)(NI * IB));
@@ -1591,16 +1605,21 @@ void best_moves(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_para
         for (int s = 0; s < S; s++) {
           const bool single = it == 0 && s == 0 && identity && shape.simple;
           if (small) {
-            const int bi = s * NBINS;
-            AggArgs a = agg_args(bi, blk + o_start, blk + o_lctr);
-            a.nbuckets = NBINS;
-            const size_t pidx = c.pending.size();
-            {
-              Ctx::Timer tm(&c, (std::string(single ? "bm_single_small" : "bm_aggregate_small") + wk_tag[g.wt_kind]).c_str(),
-                            0.0, 0.0);
-              launch_small(c, g.wt_kind, acc32, single, a, small_slots, std::min<int64_t>(n, (int64_t)c.num_cu * 4));
+            // bins 0-5 (degree < 2048), then bin 6 if the level has wider rows
+            for (int part = 0; part < (wide_rows ? 2 : 1); part++) {
+              const int bi = s * NBINS + (part ? 6 : 0);
+              AggArgs a = agg_args(bi, blk + o_start, blk + o_lctr);
+              a.nbuckets = part ? 1 : 6;
+              const size_t pidx = c.pending.size();
+              {
+                Ctx::Timer tm(&c, (std::string(single ? "bm_single_small" : "bm_aggregate_small") +
+                                   (part ? "_wide" : "") + wk_tag[g.wt_kind]).c_str(),
+                              0.0, 0.0);
+                launch_small(c, g.wt_kind, part == 1, acc32, single, a, part ? small_slots : MID_SLOTS,
+                             std::min<int64_t>(n, (int64_t)c.num_cu * (part ? 2 : 4)));
+              }
+              if (c.timing) timed.push_back({pidx, it, bi, a.nbuckets, single});
             }
-            if (c.timing) timed.push_back({pidx, it, bi, NBINS, single});
           }
           for (int b = 0; b < NBINS && !small; b++) {
             if (!hist[b]) continue;

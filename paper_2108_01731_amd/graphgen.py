@@ -78,6 +78,27 @@ class HostGraph:
                          cv(self.kk), self.wt_kind)
 
 
+def _hash64(x: torch.Tensor, salt: int) -> torch.Tensor:
+    """A seeded 64-bit mixing of int64 values (SplitMix64's finalizer with
+    logical shifts), used as random sort keys: unlike torch.randperm it gives
+    the same order on every run and every device at any size."""
+    def srl(t, k):
+        return (t >> k) & ((1 << (64 - k)) - 1)
+
+    def s64(c):
+        return c - (1 << 64) if c >= (1 << 63) else c
+
+    z = x + s64((0x9E3779B97F4A7C15 * (salt + 1)) % (1 << 64))
+    z = (z ^ srl(z, 30)) * s64(0xBF58476D1CE4E5B9)
+    z = (z ^ srl(z, 27)) * s64(0x94D049BB133111EB)
+    return z ^ srl(z, 31)
+
+
+def _hash_perm(n: int, salt: int, device) -> torch.Tensor:
+    """A seeded permutation of [0, n): indices sorted by their hash (stable)."""
+    return torch.sort(_hash64(torch.arange(n, device=device, dtype=torch.int64), salt), stable=True).indices
+
+
 def _gen(seed: int, device) -> torch.Generator:
     g = torch.Generator(device=device)
     g.manual_seed(int(seed) & (2**63 - 1))
@@ -123,6 +144,43 @@ def csr_from_edges(n: int, u: torch.Tensor, v: torch.Tensor, w: Optional[torch.T
     if ww is not None:
         wt = torch.cat([ww, ww])[order]
     return off, col, wt
+
+
+def csr_relabeled(n: int, a: torch.Tensor, b: torch.Tensor, perm: torch.Tensor, max_arcs: int = 1 << 30):
+    """Symmetric CSR of the distinct undirected edges (a, b), a != b, after
+    the vertex relabel old -> perm[old], rows ascending; the same result as
+    relabel(csr_from_edges(...)).  Rows are built range by range (at most
+    max_arcs arcs sorted at a time), so graphs beyond 2^31 arcs fit."""
+    device = a.device
+    a = perm[a]
+    b = perm[b]
+    deg = torch.zeros(n, dtype=torch.int64, device=device)
+    step = 1 << 28
+    for s0 in range(0, a.numel(), step):
+        deg += torch.bincount(a[s0:s0 + step], minlength=n)
+        deg += torch.bincount(b[s0:s0 + step], minlength=n)
+    off = torch.zeros(n + 1, dtype=torch.int64, device=device)
+    off[1:] = torch.cumsum(deg, 0)
+    arcs = int(off[-1])
+    col = torch.empty(arcs, dtype=torch.int32, device=device)
+    r0 = 0
+    while r0 < n:
+        # rows [r0, r1) hold at most max_arcs arcs (a single wider row alone)
+        r1 = int(torch.searchsorted(off, off[r0] + max_arcs, right=True)) - 1
+        r1 = min(max(r1, r0 + 1), n)
+        parts = []
+        for s0 in range(0, a.numel(), step):
+            x, y = a[s0:s0 + step], b[s0:s0 + step]
+            m1 = (x >= r0) & (x < r1)
+            m2 = (y >= r0) & (y < r1)
+            parts.append((x[m1] - r0) * n + y[m1])
+            parts.append((y[m2] - r0) * n + x[m2])
+        key = torch.sort(torch.cat(parts)).values
+        del parts
+        col[int(off[r0]):int(off[r1])] = (key % n).to(torch.int32)
+        del key
+        r0 = r1
+    return off, col
 
 
 def relabel(off: torch.Tensor, col: torch.Tensor, wt, perm: torch.Tensor):
@@ -278,10 +336,12 @@ def chung_lu_planted(n: int, m: int, gamma: float, mixing: float, seed: int, dev
     slot_vertex_np = np.empty(n, dtype=np.int64)
     slot_vertex_np[np.argsort(-slot_key, kind="stable")] = np.argsort(-vert_key, kind="stable")
     slot_vertex = torch.from_numpy(slot_vertex_np).to(device)
-    wt_slot = torch.from_numpy(w).to(device)[slot_vertex]
-    cum = torch.zeros(n + 1, dtype=torch.float64, device=device)
-    cum[1:] = torch.cumsum(wt_slot, 0)
-    total = float(cum[-1])
+    # cumulative weights on the host: a sequential sum rounds the same way on
+    # every run (a parallel device scan of floats need not)
+    cum_np = np.zeros(n + 1, dtype=np.float64)
+    np.cumsum(w[slot_vertex_np], out=cum_np[1:])
+    cum = torch.from_numpy(cum_np).to(device)
+    total = float(cum_np[-1])
     comm_of_slot = torch.from_numpy(comm_of_slot_np).to(device)
     cs_t = torch.from_numpy(comm_start).to(device)
     keys = torch.zeros(0, dtype=torch.int64, device=device)
@@ -315,14 +375,16 @@ def chung_lu_planted(n: int, m: int, gamma: float, mixing: float, seed: int, dev
         keys = torch.unique(torch.cat(parts))
         del parts
     if keys.numel() > m:
-        pick = torch.randperm(keys.numel(), generator=gen, device=device)[:m]
+        # a seeded uniform subset of size m: the m keys of smallest hash
+        # (stable sort: the same subset on every run at any size)
+        pick = torch.sort(_hash64(keys, 2 * seed + 1), stable=True).indices[:m]
         keys = torch.sort(keys[pick]).values
+        del pick
     u, v = keys // n, keys % n
     del keys
-    off, col, _ = csr_from_edges(n, u, v, device=device)
+    perm = _hash_perm(n, 2 * seed + 2, device)
+    off, col = csr_relabeled(n, u, v, perm)
     del u, v
-    perm = torch.randperm(n, generator=gen, device=device)
-    off, col, _ = relabel(off, col, None, perm)
     deg = off[1:] - off[:-1]
     k = deg.clone() if k_is_degree else torch.ones(n, dtype=torch.int64, device=device)
     return HostGraph(off, col, k)
