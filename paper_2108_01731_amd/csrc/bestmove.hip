@@ -530,24 +530,24 @@ __global__ __launch_bounds__(NT) void k_bm_single(AggArgs a) {
 
 // ------------------------------------------------------ flat hub aggregation
 
-// Rows too wide for LDS are aggregated arc-parallel: the rows of the bin are
-// laid end to end (astart = prefix of degrees) and every wave takes a
-// contiguous stretch of B7_WAVE_ARCS arcs, so a 400k-neighbor row is spread
-// over hundreds of waves.  Each row owns a table of cap = pow2 >= 2(deg+1)
-// slots in global memory (tstart = prefix of capacities).  A separate kernel
-// then scores every row's table.
+// Rows too wide for LDS are aggregated chunk-parallel: every row is cut into
+// chunks of B7_CHUNK arcs, one block per chunk, so a 400k-neighbor row is
+// spread over hundreds of blocks.  A chunk is first summed by cluster in an
+// LDS table, then its distinct clusters go to the row's table of
+// cap = pow2 >= 2(deg+1) slots in global memory, so repeated clusters cost
+// one global atomic per chunk instead of one per arc.  A separate kernel
+// then scores every row's table in segments of B7_SEG slots.
 constexpr int B7_NT = 256;
-constexpr int B7_PER_LANE = 8;
-constexpr int64_t B7_WAVE_ARCS = (int64_t)WAVE * B7_PER_LANE;
-
-// Layout of the bucket's hub rows, in one block: exclusive prefixes of the
-// degrees (astart), table capacities (tstart, cap = pow2 >= 2(deg + 1)) and
-// scoring segments (sstart), n7 + 1 entries each; tot = {arcs, slots,
-// segments, n7}.
 constexpr int B7L_NT = 1024;
 constexpr int64_t B7_SEG = 4096;
+constexpr int64_t B7_CHUNK = 2048;
+constexpr int B7_CHUNK_SLOTS = 4096;
 
-__global__ __launch_bounds__(B7L_NT) void k_b7_layout(AggArgs a, int64_t *__restrict__ astart,
+// Layout of the bucket's hub rows, in one block: exclusive prefixes of the
+// chunk counts (cstart), table capacities (tstart) and scoring segments
+// (sstart), n7 + 1 entries each; tot = {chunks, slots, segments, n7}.
+
+__global__ __launch_bounds__(B7L_NT) void k_b7_layout(AggArgs a, int64_t *__restrict__ cstart,
                                                       int64_t *__restrict__ tstart, int64_t *__restrict__ sstart,
                                                       int64_t *__restrict__ tot) {
   const int32_t *list;
@@ -556,19 +556,20 @@ __global__ __launch_bounds__(B7L_NT) void k_b7_layout(AggArgs a, int64_t *__rest
   int64_t ca = 0, ct = 0, cs = 0;
   for (int64_t i0 = 0; i0 < n7; i0 += B7L_NT) {
     const int64_t i = i0 + threadIdx.x;
-    int64_t d = 0, cap = 0, ns = 0;
+    int64_t nc = 0, cap = 0, ns = 0;
     if (i < n7) {
       const int32_t v = list[i];
-      d = a.off[v + 1] - a.off[v];
+      const int64_t d = a.off[v + 1] - a.off[v];
+      nc = cdiv(d, B7_CHUNK);
       cap = pow2_at_least(2 * (d + 1));
       ns = cdiv(cap, B7_SEG);
     }
     int64_t td, tc, tn;
-    const int64_t pd = block_excl_scan<int64_t, B7L_NT>(d, &td);
+    const int64_t pd = block_excl_scan<int64_t, B7L_NT>(nc, &td);
     const int64_t pc = block_excl_scan<int64_t, B7L_NT>(cap, &tc);
     const int64_t pn = block_excl_scan<int64_t, B7L_NT>(ns, &tn);
     if (i < n7) {
-      astart[i] = ca + pd;
+      cstart[i] = ca + pd;
       tstart[i] = ct + pc;
       sstart[i] = cs + pn;
     }
@@ -577,7 +578,7 @@ __global__ __launch_bounds__(B7L_NT) void k_b7_layout(AggArgs a, int64_t *__rest
     cs += tn;
   }
   if (threadIdx.x == 0) {
-    astart[n7] = ca;
+    cstart[n7] = ca;
     tstart[n7] = ct;
     sstart[n7] = cs;
     tot[0] = ca;
@@ -613,51 +614,63 @@ __device__ __forceinline__ void global_insert(int32_t *keys, int64_t *vals, uint
   }
 }
 
-// astart / tstart hold n7 + 1 entries (the last = totals).
+// One block per chunk (cstart / tstart hold n7 + 1 entries): the chunk's
+// arcs are summed by cluster in LDS, then each distinct cluster is added to
+// the row's global table; the row's first chunk also enters its own cluster.
 template <int WK>
 __global__ __launch_bounds__(B7_NT) void k_b7_insert(AggArgs a, const int64_t *__restrict__ tot,
-                                                     const int64_t *__restrict__ astart,
+                                                     const int64_t *__restrict__ cstart,
                                                      const int64_t *__restrict__ tstart) {
-  const int lane = lane_id();
+  __shared__ int32_t lk[B7_CHUNK_SLOTS];
+  __shared__ int64_t lv[B7_CHUNK_SLOTS];
+  __shared__ int64_t sh_row;
   const int32_t *list;
   int64_t cnt7;
   work_of(a, list, cnt7);
-  const int64_t A = tot[0], n7 = tot[3];
-  const int64_t wave = ((int64_t)blockIdx.x * B7_NT + threadIdx.x) / WAVE;
-  const int64_t nwaves = ((int64_t)gridDim.x * B7_NT) / WAVE;
-  for (int64_t base = wave * B7_WAVE_ARCS; base < A; base += nwaves * B7_WAVE_ARCS) {
-    // row holding the first arc of the stretch
-    int64_t i = 0;
-    if (lane == 0) {
+  const int64_t nch = tot[0], n7 = tot[3];
+  const int t = threadIdx.x;
+  for (int64_t ch = blockIdx.x; ch < nch; ch += gridDim.x) {
+    if (t == 0) {  // row holding this chunk
       int64_t lo = 0, hi = n7 - 1;
       while (lo < hi) {
-        int64_t mid = (lo + hi + 1) >> 1;
-        if (astart[mid] <= base) lo = mid;
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if (cstart[mid] <= ch) lo = mid;
         else hi = mid - 1;
       }
-      i = lo;
+      sh_row = lo;
     }
-    i = __shfl(i, 0, WAVE);
-    int32_t v = -1;
-    int64_t a0 = 0, a1 = 0, e0 = 0, t0 = 0;
-    uint32_t H = 0;
-    for (int j = 0; j < B7_PER_LANE; j++) {
-      const int64_t x = base + (int64_t)j * WAVE + lane;
-      if (x >= A) break;
-      while (x >= astart[i + 1]) i++;
-      if (a0 != astart[i] || v < 0) {
-        v = list[i];
-        a0 = astart[i];
-        a1 = astart[i + 1];
-        e0 = a.off[v];
-        t0 = tstart[i];
-        H = (uint32_t)(tstart[i + 1] - t0);
+    for (int j = t; j < B7_CHUNK_SLOTS; j += B7_NT) {
+      lk[j] = -1;
+      lv[j] = 0;
+    }
+    __syncthreads();
+    const int64_t i = sh_row;
+    const int32_t v = list[i];
+    const int64_t beg = a.off[v], end = a.off[v + 1];
+    const int64_t e0 = beg + (ch - cstart[i]) * B7_CHUNK;
+    const int64_t e1 = e0 + B7_CHUNK < end ? e0 + B7_CHUNK : end;
+    if (e0 == beg && t == 0) lds_insert<int64_t>(lk, lv, B7_CHUNK_SLOTS, a.C[v], 0);
+    for (int64_t base = e0 + t; base < e1; base += 4 * B7_NT) {
+      int32_t u[4], X[4];
+      int64_t w[4];
+#pragma unroll
+      for (int j = 0; j < 4; j++) {
+        const int64_t e = base + j * B7_NT;
+        u[j] = e < e1 ? a.col[e] : -1;
+        w[j] = e < e1 ? load_w<WK>(a.wt, e) : 0;
       }
-      const int64_t e = e0 + (x - a0);
-      if (x == a0) global_insert(a.gkeys + t0, a.gvals + t0, H, a.C[v], 0);
-      global_insert(a.gkeys + t0, a.gvals + t0, H, a.C[a.col[e]], load_w<WK>(a.wt, e));
-      (void)a1;
+#pragma unroll
+      for (int j = 0; j < 4; j++) X[j] = u[j] >= 0 ? a.C[u[j]] : -1;
+#pragma unroll
+      for (int j = 0; j < 4; j++)
+        if (X[j] >= 0) lds_insert<int64_t>(lk, lv, B7_CHUNK_SLOTS, X[j], w[j]);
     }
+    __syncthreads();
+    const int64_t t0 = tstart[i];
+    const uint32_t H = (uint32_t)(tstart[i + 1] - t0);
+    for (int j = t; j < B7_CHUNK_SLOTS; j += B7_NT)
+      if (lk[j] >= 0) global_insert(a.gkeys + t0, a.gvals + t0, H, lk[j], lv[j]);
+    __syncthreads();  // the LDS table and sh_row are reused by the next chunk
   }
 }
 
@@ -1288,7 +1301,7 @@ template <int WK> void launch_single(Ctx &c, int bin, AggArgs a, int64_t grid) {
 // the actual ones from the layout, so nothing is read back.
 template <int WK> void launch_flat(Ctx &c, AggArgs a, int64_t n7_ub, int64_t a7_ub) {
   n7_ub = std::max<int64_t>(n7_ub, 1);
-  int64_t *astart = c.buf<int64_t>("b7.astart", (size_t)n7_ub + 1);
+  int64_t *cstart = c.buf<int64_t>("b7.cstart", (size_t)n7_ub + 1);
   int64_t *tstart = c.buf<int64_t>("b7.tstart", (size_t)n7_ub + 1);
   int64_t *sstart = c.buf<int64_t>("b7.sstart", (size_t)n7_ub + 1);
   int64_t *tot = c.buf<int64_t>("b7.tot", 4);
@@ -1298,13 +1311,14 @@ template <int WK> void launch_flat(Ctx &c, AggArgs a, int64_t n7_ub, int64_t a7_
   a.gvals = c.buf<int64_t>("b7.vals", slots);
   const int64_t max_seg = (int64_t)slots / B7_SEG + n7_ub;
   SegBest *part = c.buf<SegBest>("b7.part", (size_t)max_seg);
-  hipLaunchKernelGGL(k_b7_layout, dim3(1), dim3(B7L_NT), 0, c.stream, a, astart, tstart, sstart, tot);
+  hipLaunchKernelGGL(k_b7_layout, dim3(1), dim3(B7L_NT), 0, c.stream, a, cstart, tstart, sstart, tot);
   LAUNCHCHECK();
   hipLaunchKernelGGL(k_b7_clear, dim3((unsigned)c.num_cu * 8), dim3(256), 0, c.stream, a.gkeys, a.gvals, tot);
   LAUNCHCHECK();
-  const int64_t waves = cdiv(std::max<int64_t>(a7_ub, 1), B7_WAVE_ARCS);
-  const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(cdiv(waves, B7_NT / WAVE), 65536));
-  hipLaunchKernelGGL((k_b7_insert<WK>), dim3((unsigned)grid), dim3(B7_NT), 0, c.stream, a, tot, astart, tstart);
+  // chunks: at most a7_ub / B7_CHUNK + n7_ub
+  const int64_t chunks = a7_ub / B7_CHUNK + n7_ub;
+  const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(chunks, (int64_t)c.num_cu * 4));
+  hipLaunchKernelGGL((k_b7_insert<WK>), dim3((unsigned)grid), dim3(B7_NT), 0, c.stream, a, tot, cstart, tstart);
   LAUNCHCHECK();
   hipLaunchKernelGGL(k_b7_segscore, dim3((unsigned)std::min<int64_t>(max_seg, (int64_t)c.num_cu * 8)), dim3(B7_NT), 0,
                      c.stream, a, tot, tstart, sstart, part);
@@ -1545,7 +1559,7 @@ void best_moves(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_para
     // per degree bin present in the level.
     const bool small = n <= SMALL_LEVEL && shape.maxdeg <= wide_max;
     int64_t hist[2 * NBINS] = {0};
-    if (!small) {
+    {
       int64_t *hist_d = c.buf<int64_t>("bm.hist", 2 * NBINS);
       HIPCHECK(hipMemsetAsync(hist_d, 0, 2 * NBINS * sizeof(int64_t), c.stream));
       hipLaunchKernelGGL(k_bin_hist, dim3((unsigned)std::min<int64_t>(cdiv(n, BM_NT), (int64_t)c.num_cu * 4)),
@@ -1555,7 +1569,9 @@ void best_moves(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_para
     }
     // tables of the small-level kernels: MID_SLOTS below degree 2048, else
     // room for the widest row of the level
-    const bool wide_rows = shape.maxdeg > 2047;
+    const bool wide_rows = hist[6] > 0;
+    bool narrow_rows = false;
+    for (int b = 0; b < 6; b++) narrow_rows = narrow_rows || hist[b] > 0;
     const int64_t small_slots = std::min<int64_t>(pow2_host(2 * (shape.maxdeg + 1)), wslots);
     const int32_t NI = std::max<int32_t>(prm.num_iter, 1);
     int64_t *ctrs = c.buf<int64_t>("bm.ctrs", (size_t)(NI * IB));
@@ -1606,7 +1622,8 @@ void best_moves(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_para
           const bool single = it == 0 && s == 0 && identity && shape.simple;
           if (small) {
             // bins 0-5 (degree < 2048), then bin 6 if the level has wider rows
-            for (int part = 0; part < (wide_rows ? 2 : 1); part++) {
+            for (int part = 0; part < 2; part++) {
+              if (part == 0 ? !narrow_rows : !wide_rows) continue;
               const int bi = s * NBINS + (part ? 6 : 0);
               AggArgs a = agg_args(bi, blk + o_start, blk + o_lctr);
               a.nbuckets = part ? 1 : 6;
