@@ -341,7 +341,7 @@ def run_serve(args, dev):
         t1 = time.perf_counter()
         done, a_o = 0, 0
         for r in trace:
-            h = r.graph
+            h = r.graph.numpy()
             g_o = O.Graph(off=h.off, col=h.col, k=h.k, wt=None if h.wt is None else h.wt.astype(np.int64))
             O.cluster(g_o, r.p, r.q, O.Params())
             done += 1

@@ -4,8 +4,9 @@ continuous batching on one GPU.
 Pipeline (one condition variable guards the queues and the HBM ledger):
 
   arrival -> pending (FIFO) -> admitted: graph uploaded and resident in HBM
-          -> ready -> a free worker takes every ready request (up to its caps),
-             packs them block-diagonally on its own stream and runs one
+          -> ready -> a free worker takes every ready request that stores its
+             weights like the oldest ready one (up to its caps), packs them
+             block-diagonally on its own stream and runs one
              lcc_cluster_batch -> labels copied out, HBM released -> done
 
 Admission: a request is admitted only while the sum of the HBM estimates of
@@ -69,7 +70,7 @@ def hbm_estimate(g: G.HostGraph) -> int:
     vertex over the hierarchy) and the compression sort buffers (about 40 B
     per arc)."""
     n, m = g.n, g.arcs
-    wb = 0 if g.wt is None else np.asarray(g.wt).dtype.itemsize
+    wb = 0 if g.wt is None else g.wt.element_size() if isinstance(g.wt, torch.Tensor) else np.asarray(g.wt).itemsize
     resident = 8 * (n + 1) + (4 + wb) * m + 8 * n * (1 + (g.s is not None) + (g.kk is not None))
     return 2 * resident + 64 * n + 40 * m + 4096
 
@@ -105,11 +106,22 @@ def request_graph(kind: str, m: int, seed: int, device="cpu"):
     raise ValueError(kind)
 
 
+def pinned(g: G.HostGraph) -> G.HostGraph:
+    """The graph's arrays as page-locked host tensors (fast uploads)."""
+    def pin(a):
+        if a is None:
+            return None
+        t = a if isinstance(a, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(a))
+        return t.cpu().pin_memory() if torch.cuda.is_available() else t.cpu()
+
+    return G.HostGraph(pin(g.off), pin(g.col), pin(g.k), pin(g.wt), pin(g.s), pin(g.kk), g.wt_kind)
+
+
 def make_trace(count: int, qps: float, seed: int = 0, mmin: int = 1000, mmax: int = 5_000_000,
                device="cpu", kinds=("sbm", "chung_lu", "knn")) -> List[Request]:
     """Seeded Poisson arrivals at rate qps; request type uniform over kinds,
     edge count log-uniform in [mmin, mmax].  Graphs are generated on
-    `device` and kept as host arrays."""
+    `device` and kept in host memory (page-locked when a GPU is present)."""
     rng = np.random.default_rng(seed)
     t = 0.0
     out = []
@@ -118,7 +130,7 @@ def make_trace(count: int, qps: float, seed: int = 0, mmin: int = 1000, mmax: in
         kind = kinds[int(rng.integers(0, len(kinds)))]
         m = int(round(math.exp(rng.uniform(math.log(mmin), math.log(mmax)))))
         g, (p, q) = request_graph(kind, m, seed * 1_000_003 + i, device=device)
-        out.append(Request(i, t, g.numpy(), p, q, kind))
+        out.append(Request(i, t, pinned(g), p, q, kind))
     return out
 
 
@@ -294,13 +306,20 @@ class Server:
                         cv.wait()
                     if state["finished"] >= total or state["error"] is not None:
                         return
-                    take, arcs = [], 0
-                    while ready and len(take) < self.max_jobs:
-                        r = ready[0]
-                        if take and arcs + r.req.graph.arcs > self.max_arcs:
-                            break
-                        take.append(ready.popleft())
-                        arcs += r.req.graph.arcs
+                    # the ready requests that store weights like the oldest one
+                    # (one weight storage per launch), in arrival order
+                    kind = ready[0].req.graph.wt_kind if ready[0].req.graph.wt is not None else "none"
+                    take, rest, arcs = [], deque(), 0
+                    while ready:
+                        r = ready.popleft()
+                        rk = r.req.graph.wt_kind if r.req.graph.wt is not None else "none"
+                        if rk == kind and len(take) < self.max_jobs and (
+                                not take or arcs + r.req.graph.arcs <= self.max_arcs):
+                            take.append(r)
+                            arcs += r.req.graph.arcs
+                        else:
+                            rest.append(r)
+                    ready.extend(rest)
                     stats.batches += 1
                 t_start = now()
                 try:
