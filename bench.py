@@ -137,6 +137,7 @@ def main():
     agg = {k: v for k, v in ks.items() if k.startswith(("bm_aggregate", "bm_single"))}
     dom_name, dom = max(agg.items(), key=lambda kv: kv[1]["ms"])
     achieved = dom["bytes"] / (dom["ms"] * 1e-3) / 1e9
+    traffic = measured_traffic(args.workload, dom_name)
     agg_ms = sum(v["ms"] for v in agg.values())
     agg_arcs = sum(v["items"] for v in agg.values())
     log(f"step: {ms_per_step:.1f} ms; levels={st['levels']} clusters={st['clusters']} "
@@ -176,11 +177,44 @@ def main():
                    "best_move_arcs_per_step": arcs_total // args.steps,
                    "best_move_kernel_edges_per_s": agg_arcs / (agg_ms * 1e-3) if agg_ms > 0 else None},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": dom_name,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_unit": "bytes/launch",
+                     "algorithmic_bytes_per_launch": dom["bytes"] / dom["launches"], "kernel": dom_name,
                      "avg_launch_ms": dom["ms"] / dom["launches"], "launches": dom["launches"]},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+KERNEL_SOURCES = ("common.hpp", "prims.hpp", "ops.hpp", "bestmove.hip")
+
+
+def kernel_source_sha1():
+    """Hash of the sources the aggregation kernels are compiled from."""
+    import hashlib
+
+    h = hashlib.sha1()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2108_01731_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload, kernel_class):
+    """HBM bytes per launch of the kernel class from the committed rocprofv3
+    counter runs (FETCH_SIZE and WRITE_SIZE, scaled by the copy calibration),
+    or None when there is none for this workload and class or the kernel
+    sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            entries = json.load(f)
+    except (OSError, ValueError):
+        return None
+    sha = kernel_source_sha1()
+    for e in entries:
+        if e.get("workload") == workload and e.get("class") == kernel_class and e.get("source_sha1") == sha:
+            return e["fetch_bytes_per_launch"] + e["write_bytes_per_launch"]
+    return None
 
 
 def dominant_kernel(ks):

@@ -361,7 +361,8 @@ __global__ __launch_bounds__(BM_NT) void k_bm_group(AggArgs a) {
 // One vertex per block, a table of min(hcap, pow2 >= 2(deg+1)) slots in
 // dynamic LDS (keys then values).  The host admits a vertex only when its
 // distinct clusters (<= deg + 1) fill at most 70% of hcap.
-template <int NT, int WK, bool A32>
+// TAG only separates launch classes in kernel traces (1 = small levels).
+template <int NT, int WK, bool A32, int TAG = 0>
 __global__ __launch_bounds__(NT) void k_bm_wide(AggArgs a) {
   using Acc = typename std::conditional<A32, int32_t, int64_t>::type;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -451,7 +452,7 @@ __global__ __launch_bounds__(NT) void k_bm_wide(AggArgs a) {
 // q*w(v,u) - p*k_v*k_u (ties to the lowest id); staying scores 0 and
 // isolation is not available (|c| = 1).  G lanes per vertex, or the whole
 // block when G == NT.
-template <int G, int NT, int WK>
+template <int G, int NT, int WK, int TAG = 0>
 __global__ __launch_bounds__(NT) void k_bm_single(AggArgs a) {
   constexpr int GPB = NT / G;
   __shared__ int32_t sh_d[GPB];
@@ -1257,22 +1258,22 @@ template <int WK, bool A32>
 void launch_bin(Ctx &c, int bin, AggArgs a, int64_t grid) {
   const dim3 gr((unsigned)grid);
   switch (bin) {
-    case 0: hipLaunchKernelGGL((k_bm_group<8, 16, WK, A32>), gr, dim3(BM_NT), 0, c.stream, a); break;
-    case 1: hipLaunchKernelGGL((k_bm_group<16, 32, WK, A32>), gr, dim3(BM_NT), 0, c.stream, a); break;
-    case 2: hipLaunchKernelGGL((k_bm_group<32, 64, WK, A32>), gr, dim3(BM_NT), 0, c.stream, a); break;
-    case 3: hipLaunchKernelGGL((k_bm_group<64, 128, WK, A32>), gr, dim3(BM_NT), 0, c.stream, a); break;
-    case 4: hipLaunchKernelGGL((k_bm_group<64, 512, WK, A32>), gr, dim3(BM_NT), 0, c.stream, a); break;
+    case 0: c.launch(k_bm_group<8, 16, WK, A32>, gr, dim3(BM_NT), 0, a); break;
+    case 1: c.launch(k_bm_group<16, 32, WK, A32>, gr, dim3(BM_NT), 0, a); break;
+    case 2: c.launch(k_bm_group<32, 64, WK, A32>, gr, dim3(BM_NT), 0, a); break;
+    case 3: c.launch(k_bm_group<64, 128, WK, A32>, gr, dim3(BM_NT), 0, a); break;
+    case 4: c.launch(k_bm_group<64, 512, WK, A32>, gr, dim3(BM_NT), 0, a); break;
     case 5: {
       a.hcap = MID_SLOTS;
       const size_t bytes = wide_lds_bytes(MID_SLOTS, A32);
-      hipLaunchKernelGGL((k_bm_wide<BM_NT, WK, A32>), gr, dim3(BM_NT), bytes, c.stream, a);
+      c.launch(k_bm_wide<BM_NT, WK, A32>, gr, dim3(BM_NT), bytes, a);
       break;
     }
     case 6: {
       a.hcap = wide_slots(c, A32);
       const size_t bytes = wide_lds_bytes(a.hcap, A32);
       allow_lds(c, k_bm_wide<WIDE_NT, WK, A32>, bytes);
-      hipLaunchKernelGGL((k_bm_wide<WIDE_NT, WK, A32>), gr, dim3(WIDE_NT), bytes, c.stream, a);
+      c.launch(k_bm_wide<WIDE_NT, WK, A32>, gr, dim3(WIDE_NT), bytes, a);
       break;
     }
     default:
@@ -1285,13 +1286,13 @@ void launch_bin(Ctx &c, int bin, AggArgs a, int64_t grid) {
 template <int WK> void launch_single(Ctx &c, int bin, AggArgs a, int64_t grid) {
   const dim3 gr((unsigned)grid);
   switch (bin) {
-    case 0: hipLaunchKernelGGL((k_bm_single<8, BM_NT, WK>), gr, dim3(BM_NT), 0, c.stream, a); break;
-    case 1: hipLaunchKernelGGL((k_bm_single<16, BM_NT, WK>), gr, dim3(BM_NT), 0, c.stream, a); break;
-    case 2: hipLaunchKernelGGL((k_bm_single<32, BM_NT, WK>), gr, dim3(BM_NT), 0, c.stream, a); break;
+    case 0: c.launch(k_bm_single<8, BM_NT, WK>, gr, dim3(BM_NT), 0, a); break;
+    case 1: c.launch(k_bm_single<16, BM_NT, WK>, gr, dim3(BM_NT), 0, a); break;
+    case 2: c.launch(k_bm_single<32, BM_NT, WK>, gr, dim3(BM_NT), 0, a); break;
     case 3:
-    case 4: hipLaunchKernelGGL((k_bm_single<64, BM_NT, WK>), gr, dim3(BM_NT), 0, c.stream, a); break;
-    case 5: hipLaunchKernelGGL((k_bm_single<BM_NT, BM_NT, WK>), gr, dim3(BM_NT), 0, c.stream, a); break;
-    default: hipLaunchKernelGGL((k_bm_single<WIDE_NT, WIDE_NT, WK>), gr, dim3(WIDE_NT), 0, c.stream, a);
+    case 4: c.launch(k_bm_single<64, BM_NT, WK>, gr, dim3(BM_NT), 0, a); break;
+    case 5: c.launch(k_bm_single<BM_NT, BM_NT, WK>, gr, dim3(BM_NT), 0, a); break;
+    default: c.launch(k_bm_single<WIDE_NT, WIDE_NT, WK>, gr, dim3(WIDE_NT), 0, a);
   }
   LAUNCHCHECK();
 }
@@ -1351,17 +1352,17 @@ int64_t pow2_host(int64_t x) {
 template <int NT, int WK> void launch_small_wk(Ctx &c, bool a32, bool single, AggArgs a, int64_t slots, int64_t grid) {
   const dim3 gr((unsigned)grid);
   if (single) {
-    hipLaunchKernelGGL((k_bm_single<NT, NT, WK>), gr, dim3(NT), 0, c.stream, a);
+    c.launch(k_bm_single<NT, NT, WK, 1>, gr, dim3(NT), 0, a);
   } else if (a32) {
     a.hcap = slots;
     const size_t bytes = wide_lds_bytes(slots, true);
-    allow_lds(c, k_bm_wide<NT, WK, true>, bytes);
-    hipLaunchKernelGGL((k_bm_wide<NT, WK, true>), gr, dim3(NT), bytes, c.stream, a);
+    allow_lds(c, k_bm_wide<NT, WK, true, 1>, bytes);
+    c.launch(k_bm_wide<NT, WK, true, 1>, gr, dim3(NT), bytes, a);
   } else {
     a.hcap = slots;
     const size_t bytes = wide_lds_bytes(slots, false);
-    allow_lds(c, k_bm_wide<NT, WK, false>, bytes);
-    hipLaunchKernelGGL((k_bm_wide<NT, WK, false>), gr, dim3(NT), bytes, c.stream, a);
+    allow_lds(c, k_bm_wide<NT, WK, false, 1>, bytes);
+    c.launch(k_bm_wide<NT, WK, false, 1>, gr, dim3(NT), bytes, a);
   }
   LAUNCHCHECK();
 }
@@ -1631,7 +1632,7 @@ void best_moves(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_para
               {
                 Ctx::Timer tm(&c, (std::string(single ? "bm_single_small" : "bm_aggregate_small") +
                                    (part ? "_wide" : "") + wk_tag[g.wt_kind]).c_str(),
-                              0.0, 0.0);
+                              0.0, 0.0, true);
                 launch_small(c, g.wt_kind, part == 1, acc32, single, a, part ? small_slots : MID_SLOTS,
                              std::min<int64_t>(n, (int64_t)c.num_cu * (part ? 2 : 4)));
               }
@@ -1644,16 +1645,16 @@ void best_moves(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_para
             const AggArgs a = agg_args(bi, blk + o_start, blk + o_lctr);
             const size_t pidx = c.pending.size();
             {
-              Ctx::Timer tm(&c, class_name(b, single).c_str(), 0.0, 0.0);
+              Ctx::Timer tm(&c, class_name(b, single).c_str(), 0.0, 0.0, single || b != NBINS - 1);
               launch_agg(c, g.wt_kind, b, acc32, single, hist[b], hist[NBINS + b], a, bin_grid(c, b, hist[b], false));
             }
             if (c.timing) timed.push_back({pidx, it, bi, 1, single});
           }
           {
-            Ctx::Timer tm(&c, "bm_apply", 0.0, 0.0);
-            hipLaunchKernelGGL(k_bm_apply, dim3((unsigned)apply_grid), dim3(BM_NT), 0, c.stream, blist, (int64_t)0,
-                               blk + o_start, s * NBINS, (s + 1) * NBINS, D, C, K, cnt, g.k, n, blk + o_isoc + s,
-                               jv.jid, jv.jmoved);
+            Ctx::Timer tm(&c, "bm_apply", 0.0, 0.0, true);
+            c.launch(k_bm_apply, dim3((unsigned)apply_grid), dim3(BM_NT), 0, (const int32_t *)blist, (int64_t)0,
+                     (const int64_t *)(blk + o_start), (int32_t)(s * NBINS), (int32_t)((s + 1) * NBINS),
+                     (const int32_t *)D, C, K, cnt, g.k, n, blk + o_isoc + s, jv.jid, jv.jmoved);
             LAUNCHCHECK();
           }
         }
@@ -1783,7 +1784,8 @@ void best_moves(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_para
           // flat bin is a sequence of kernels: timed as one class, never taken
           // as "the" kernel of a roofline
           const double per_arc = single ? 12.0 + wb : 8.0 + wb;
-          Ctx::Timer tm(&c, class_name(b, single).c_str(), (double)cntb * 48.0 + arcs_b * per_arc, arcs_b);
+          Ctx::Timer tm(&c, class_name(b, single).c_str(), (double)cntb * 48.0 + arcs_b * per_arc, arcs_b,
+                        single || b != NBINS - 1);
           launch_agg(c, g.wt_kind, b, acc32, single, cntb, arcs_i, a, bin_grid(c, b, cntb, true));
         }
         launches.push_back({c.timing ? pidx : (size_t)-1, bi});

@@ -4,6 +4,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <cstdint>
 #include <cstring>
@@ -145,26 +146,54 @@ struct Ctx {
     return e;
   }
 
-  // Brackets one launch with events when timing is on.
+  // Brackets launches with events when timing is on.  With `on_dispatch`
+  // the scope holds exactly one kernel launch, issued through launch():
+  // the events then mark that dispatch's own start and end (as a kernel
+  // trace does) instead of being separate commands around it.
   struct Timer {
     Ctx *c;
     std::string name;
     double bytes, items;
+    bool on_dispatch = false, used = false;
     hipEvent_t a = nullptr, b = nullptr;
-    Timer(Ctx *ctx, const char *n, double by, double it) : c(ctx), name(n), bytes(by), items(it) {
+    Timer(Ctx *ctx, const char *n, double by, double it, bool dispatch = false)
+        : c(ctx), name(n), bytes(by), items(it), on_dispatch(dispatch) {
       if (c->timing) {
         a = c->get_event();
         b = c->get_event();
-        HIPCHECK(hipEventRecord(a, c->stream));
+        if (on_dispatch) c->dispatch_timer = this;
+        else HIPCHECK(hipEventRecord(a, c->stream));
       }
     }
     ~Timer() {
-      if (c->timing && a) {
+      if (!c->timing || !a) return;
+      if (on_dispatch) {
+        c->dispatch_timer = nullptr;
+        if (!used) {  // nothing was launched: return the events
+          c->event_pool.push_back(a);
+          c->event_pool.push_back(b);
+          return;
+        }
+      } else {
         (void)hipEventRecord(b, c->stream);
-        c->pending.push_back({name, a, b, bytes, items});
       }
+      c->pending.push_back({name, a, b, bytes, items});
     }
   };
+  Timer *dispatch_timer = nullptr;
+
+  // Launches a kernel on the context stream; inside an on-dispatch Timer the
+  // launch carries the timer's events.
+  template <class F, class... Args>
+  void launch(F kernel, dim3 grid, dim3 block, size_t shmem, Args... args) {
+    Timer *t = dispatch_timer;
+    if (t && !t->used) {
+      t->used = true;
+      hipExtLaunchKernelGGL(kernel, grid, block, (uint32_t)shmem, stream, t->a, t->b, 0u, args...);
+    } else {
+      hipLaunchKernelGGL(kernel, grid, block, shmem, stream, args...);
+    }
+  }
 
   // Resolves recorded events (the stream must have been synchronized).
   void collect_timing() {
