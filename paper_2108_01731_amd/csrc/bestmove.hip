@@ -243,115 +243,115 @@ __global__ __launch_bounds__(BM_NT) void k_bm_group(AggArgs a) {
   work_of(a, list, count);
   int64_t c_movers = 0, c_cands = 0, c_marcs = 0;
   for (int64_t g0 = (int64_t)blockIdx.x * GPB; g0 < count; g0 += (int64_t)gridDim.x * GPB) {
-  const int64_t gi = g0 + grp;
-  const bool valid = gi < count;
-  int32_t *keys = hk + grp * HMAX;
-  Acc *vals = hv + grp * HMAX;
-  int32_t v = 0, c = 0;
-  int64_t beg = 0, end = 0;
-  if (valid) {
-    v = list[gi];
-    beg = a.off[v];
-    end = a.off[v + 1];
-    c = a.C[v];
-  }
-  uint32_t H = HMAX;
-  if constexpr (!ONE_PASS) {
-    H = pow2_at_least(2 * (end - beg + 1));
-    if (H > (uint32_t)HMAX) H = HMAX;
-  }
-  for (uint32_t j = gl; j < H; j += G) {
-    keys[j] = -1;
-    vals[j] = 0;
-  }
-  // loads the decision needs, issued before the row is walked
-  int64_t kv = 0, Kc = 0;
-  int32_t cntc = 0;
-  if (valid) {
-    kv = a.k[v];
-    Kc = a.K[c];
-    cntc = a.cnt[c];
-  }
-  __syncthreads();
-  int32_t u0 = -1;
-  if (valid) {
-    if (gl == 0) lds_insert<Acc>(keys, vals, H, c, 0);
-    if constexpr (ONE_PASS) {
-      const int64_t e = beg + gl;
-      if (e < end) {
-        u0 = a.col[e];
-        lds_insert<Acc>(keys, vals, H, a.C[u0], load_w<WK>(a.wt, e));
-      }
-    } else {
-      for (int64_t base = beg + gl; base < end; base += 4 * G) {
-        int32_t u[4], X[4];
-        int64_t w[4];
-#pragma unroll
-        for (int j = 0; j < 4; j++) {
-          const int64_t e = base + j * G;
-          u[j] = e < end ? a.col[e] : -1;
-          w[j] = e < end ? load_w<WK>(a.wt, e) : 0;
-        }
-#pragma unroll
-        for (int j = 0; j < 4; j++) X[j] = u[j] >= 0 ? a.C[u[j]] : -1;
-#pragma unroll
-        for (int j = 0; j < 4; j++)
-          if (X[j] >= 0) lds_insert<Acc>(keys, vals, H, X[j], w[j]);
-      }
+    const int64_t gi = g0 + grp;
+    const bool valid = gi < count;
+    int32_t *keys = hk + grp * HMAX;
+    Acc *vals = hv + grp * HMAX;
+    int32_t v = 0, c = 0;
+    int64_t beg = 0, end = 0;
+    if (valid) {
+      v = list[gi];
+      beg = a.off[v];
+      end = a.off[v + 1];
+      c = a.C[v];
     }
-  }
-  __syncthreads();
-  int64_t best_s = INT64_MIN, wc = 0, ncand = 0;
-  int32_t best_id = ISO_ID;
-  int64_t lp = 0, lq = 1;
-  int32_t job = 0;
-  if (valid) job_lambda(a, v, lp, lq, job);
-  const int64_t pk = lp * kv;
-  if (valid) {
+    uint32_t H = HMAX;
+    if constexpr (!ONE_PASS) {
+      H = pow2_at_least(2 * (end - beg + 1));
+      if (H > (uint32_t)HMAX) H = HMAX;
+    }
     for (uint32_t j = gl; j < H; j += G) {
-      const int32_t X = keys[j];
-      if (X < 0) continue;
-      ncand++;
-      const int64_t wx = (int64_t)vals[j];
-      if (X == c) {
-        wc = wx;
+      keys[j] = -1;
+      vals[j] = 0;
+    }
+    // loads the decision needs, issued before the row is walked
+    int64_t kv = 0, Kc = 0;
+    int32_t cntc = 0;
+    if (valid) {
+      kv = a.k[v];
+      Kc = a.K[c];
+      cntc = a.cnt[c];
+    }
+    __syncthreads();
+    int32_t u0 = -1;
+    if (valid) {
+      if (gl == 0) lds_insert<Acc>(keys, vals, H, c, 0);
+      if constexpr (ONE_PASS) {
+        const int64_t e = beg + gl;
+        if (e < end) {
+          u0 = a.col[e];
+          lds_insert<Acc>(keys, vals, H, a.C[u0], load_w<WK>(a.wt, e));
+        }
       } else {
-        const int64_t s = lq * wx - pk * a.K[X];
-        if (better(s, X, best_s, best_id)) {
-          best_s = s;
-          best_id = X;
+        for (int64_t base = beg + gl; base < end; base += 4 * G) {
+          int32_t u[4], X[4];
+          int64_t w[4];
+  #pragma unroll
+          for (int j = 0; j < 4; j++) {
+            const int64_t e = base + j * G;
+            u[j] = e < end ? a.col[e] : -1;
+            w[j] = e < end ? load_w<WK>(a.wt, e) : 0;
+          }
+  #pragma unroll
+          for (int j = 0; j < 4; j++) X[j] = u[j] >= 0 ? a.C[u[j]] : -1;
+  #pragma unroll
+          for (int j = 0; j < 4; j++)
+            if (X[j] >= 0) lds_insert<Acc>(keys, vals, H, X[j], w[j]);
         }
       }
     }
-  }
-#pragma unroll
-  for (int o = G / 2; o > 0; o >>= 1) {
-    int64_t os = __shfl_xor(best_s, o, WAVE);
-    int32_t oid = __shfl_xor(best_id, o, WAVE);
-    if (better(os, oid, best_s, best_id)) {
-      best_s = os;
-      best_id = oid;
-    }
-    wc += __shfl_xor(wc, o, WAVE);
-  }
-  bool moved = false;
-  if (valid) {
-    const int64_t stay = lq * wc - pk * (Kc - kv);
-    const int32_t d = decide(best_s, best_id, stay, a.allow_iso && cntc >= 2, c);
-    moved = d != c;
-    if (gl == 0) a.D[v] = d;
-    if (moved && a.next_flag) {
-      if constexpr (ONE_PASS) {
-        if (u0 >= 0) a.next_flag[u0] = 1;
-      } else {
-        for (int64_t e = beg + gl; e < end; e += G) a.next_flag[a.col[e]] = 1;
+    __syncthreads();
+    int64_t best_s = INT64_MIN, wc = 0, ncand = 0;
+    int32_t best_id = ISO_ID;
+    int64_t lp = 0, lq = 1;
+    int32_t job = 0;
+    if (valid) job_lambda(a, v, lp, lq, job);
+    const int64_t pk = lp * kv;
+    if (valid) {
+      for (uint32_t j = gl; j < H; j += G) {
+        const int32_t X = keys[j];
+        if (X < 0) continue;
+        ncand++;
+        const int64_t wx = (int64_t)vals[j];
+        if (X == c) {
+          wc = wx;
+        } else {
+          const int64_t s = lq * wx - pk * a.K[X];
+          if (better(s, X, best_s, best_id)) {
+            best_s = s;
+            best_id = X;
+          }
+        }
       }
     }
-  }
-  c_movers += (moved && gl == 0) ? 1 : 0;
-  c_cands += ncand;
-  c_marcs += (moved && gl == 0) ? end - beg : 0;
-  __syncthreads();  // the tables are cleared again for the next vertices
+  #pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) {
+      int64_t os = __shfl_xor(best_s, o, WAVE);
+      int32_t oid = __shfl_xor(best_id, o, WAVE);
+      if (better(os, oid, best_s, best_id)) {
+        best_s = os;
+        best_id = oid;
+      }
+      wc += __shfl_xor(wc, o, WAVE);
+    }
+    bool moved = false;
+    if (valid) {
+      const int64_t stay = lq * wc - pk * (Kc - kv);
+      const int32_t d = decide(best_s, best_id, stay, a.allow_iso && cntc >= 2, c);
+      moved = d != c;
+      if (gl == 0) a.D[v] = d;
+      if (moved && a.next_flag) {
+        if constexpr (ONE_PASS) {
+          if (u0 >= 0) a.next_flag[u0] = 1;
+        } else {
+          for (int64_t e = beg + gl; e < end; e += G) a.next_flag[a.col[e]] = 1;
+        }
+      }
+    }
+    c_movers += (moved && gl == 0) ? 1 : 0;
+    c_cands += ncand;
+    c_marcs += (moved && gl == 0) ? end - beg : 0;
+    __syncthreads();  // the tables are cleared again for the next vertices
   }
   flush_counters<BM_NT>(a.ctr, c_movers, c_cands, c_marcs);
 }
@@ -375,71 +375,71 @@ __global__ __launch_bounds__(NT) void k_bm_wide(AggArgs a) {
   work_of(a, list, count);
   int64_t movers = 0, marcs = 0, cands = 0;
   for (int64_t vi = blockIdx.x; vi < count; vi += gridDim.x) {
-  const int32_t v = list[vi];
-  const int64_t beg = a.off[v], end = a.off[v + 1];
-  const int32_t c = a.C[v];
-  uint32_t H = pow2_at_least(2 * (end - beg + 1));
-  if (H > (uint32_t)a.hcap) H = (uint32_t)a.hcap;
-  for (uint32_t j = t; j < H; j += NT) {
-    keys[j] = -1;
-    vals[j] = 0;
-  }
-  const int64_t kv = a.k[v], Kc = a.K[c];
-  const int32_t cntc = a.cnt[c];
-  __syncthreads();
-  if (t == 0) lds_insert<Acc>(keys, vals, H, c, 0);
-  for (int64_t base = beg + t; base < end; base += 4 * NT) {
-    int32_t u[4], X[4];
-    int64_t w[4];
-#pragma unroll
-    for (int j = 0; j < 4; j++) {
-      const int64_t e = base + j * NT;
-      u[j] = e < end ? a.col[e] : -1;
-      w[j] = e < end ? load_w<WK>(a.wt, e) : 0;
+    const int32_t v = list[vi];
+    const int64_t beg = a.off[v], end = a.off[v + 1];
+    const int32_t c = a.C[v];
+    uint32_t H = pow2_at_least(2 * (end - beg + 1));
+    if (H > (uint32_t)a.hcap) H = (uint32_t)a.hcap;
+    for (uint32_t j = t; j < H; j += NT) {
+      keys[j] = -1;
+      vals[j] = 0;
     }
-#pragma unroll
-    for (int j = 0; j < 4; j++) X[j] = u[j] >= 0 ? a.C[u[j]] : -1;
-#pragma unroll
-    for (int j = 0; j < 4; j++)
-      if (X[j] >= 0) lds_insert<Acc>(keys, vals, H, X[j], w[j]);
-  }
-  __syncthreads();
-  int64_t lp, lq;
-  int32_t job;
-  job_lambda(a, v, lp, lq, job);
-  const int64_t pk = lp * kv;
-  int64_t best_s = INT64_MIN, wc = 0;
-  int32_t best_id = ISO_ID;
-  for (uint32_t j = t; j < H; j += NT) {
-    const int32_t X = keys[j];
-    if (X < 0) continue;
-    cands++;
-    const int64_t wx = (int64_t)vals[j];
-    if (X == c) {
-      wc = wx;
-    } else {
-      const int64_t s = lq * wx - pk * a.K[X];
-      if (better(s, X, best_s, best_id)) {
-        best_s = s;
-        best_id = X;
+    const int64_t kv = a.k[v], Kc = a.K[c];
+    const int32_t cntc = a.cnt[c];
+    __syncthreads();
+    if (t == 0) lds_insert<Acc>(keys, vals, H, c, 0);
+    for (int64_t base = beg + t; base < end; base += 4 * NT) {
+      int32_t u[4], X[4];
+      int64_t w[4];
+  #pragma unroll
+      for (int j = 0; j < 4; j++) {
+        const int64_t e = base + j * NT;
+        u[j] = e < end ? a.col[e] : -1;
+        w[j] = e < end ? load_w<WK>(a.wt, e) : 0;
+      }
+  #pragma unroll
+      for (int j = 0; j < 4; j++) X[j] = u[j] >= 0 ? a.C[u[j]] : -1;
+  #pragma unroll
+      for (int j = 0; j < 4; j++)
+        if (X[j] >= 0) lds_insert<Acc>(keys, vals, H, X[j], w[j]);
+    }
+    __syncthreads();
+    int64_t lp, lq;
+    int32_t job;
+    job_lambda(a, v, lp, lq, job);
+    const int64_t pk = lp * kv;
+    int64_t best_s = INT64_MIN, wc = 0;
+    int32_t best_id = ISO_ID;
+    for (uint32_t j = t; j < H; j += NT) {
+      const int32_t X = keys[j];
+      if (X < 0) continue;
+      cands++;
+      const int64_t wx = (int64_t)vals[j];
+      if (X == c) {
+        wc = wx;
+      } else {
+        const int64_t s = lq * wx - pk * a.K[X];
+        if (better(s, X, best_s, best_id)) {
+          best_s = s;
+          best_id = X;
+        }
       }
     }
-  }
-  block_best<NT>(best_s, best_id, wc);
-  if (t == 0) {
-    const int64_t stay = lq * wc - pk * (Kc - kv);
-    const int32_t d = decide(best_s, best_id, stay, a.allow_iso && cntc >= 2, c);
-    a.D[v] = d;
-    sh_d = d;
-    if (d != c) {
-      movers += 1;
-      marcs += end - beg;
+    block_best<NT>(best_s, best_id, wc);
+    if (t == 0) {
+      const int64_t stay = lq * wc - pk * (Kc - kv);
+      const int32_t d = decide(best_s, best_id, stay, a.allow_iso && cntc >= 2, c);
+      a.D[v] = d;
+      sh_d = d;
+      if (d != c) {
+        movers += 1;
+        marcs += end - beg;
+      }
     }
-  }
-  __syncthreads();
-  if (sh_d != c && a.next_flag)
-    for (int64_t e = beg + t; e < end; e += NT) a.next_flag[a.col[e]] = 1;
-  __syncthreads();  // table and sh_d are reused by the next vertex
+    __syncthreads();
+    if (sh_d != c && a.next_flag)
+      for (int64_t e = beg + t; e < end; e += NT) a.next_flag[a.col[e]] = 1;
+    __syncthreads();  // table and sh_d are reused by the next vertex
   }
   flush_counters<NT>(a.ctr, movers, cands, marcs);
 }
@@ -462,69 +462,69 @@ __global__ __launch_bounds__(NT) void k_bm_single(AggArgs a) {
   work_of(a, list, count);
   int64_t c_movers = 0, c_cands = 0, c_marcs = 0;
   for (int64_t g0 = (int64_t)blockIdx.x * GPB; g0 < count; g0 += (int64_t)gridDim.x * GPB) {
-  const int64_t gi = g0 + grp;
-  const bool valid = gi < count;
-  int32_t v = 0;
-  int64_t beg = 0, end = 0, kv = 0;
-  if (valid) {
-    v = list[gi];
-    beg = a.off[v];
-    end = a.off[v + 1];
-    kv = a.k[v];
-  }
-  int64_t lp = 0, lq = 1;
-  int32_t job = 0;
-  if (valid) job_lambda(a, v, lp, lq, job);
-  const int64_t pk = lp * kv;
-  int64_t best_s = INT64_MIN, wc = 0;
-  int32_t best_id = ISO_ID;
-  for (int64_t base = beg + gl; base < end; base += 4 * G) {
-    int32_t u[4];
-    int64_t w[4], ku[4];
-#pragma unroll
-    for (int j = 0; j < 4; j++) {
-      const int64_t e = base + j * G;
-      u[j] = e < end ? a.col[e] : -1;
-      w[j] = e < end ? load_w<WK>(a.wt, e) : 0;
+    const int64_t gi = g0 + grp;
+    const bool valid = gi < count;
+    int32_t v = 0;
+    int64_t beg = 0, end = 0, kv = 0;
+    if (valid) {
+      v = list[gi];
+      beg = a.off[v];
+      end = a.off[v + 1];
+      kv = a.k[v];
     }
-#pragma unroll
-    for (int j = 0; j < 4; j++) ku[j] = u[j] >= 0 ? a.k[u[j]] : 0;
-#pragma unroll
-    for (int j = 0; j < 4; j++) {
-      if (u[j] < 0) continue;
-      const int64_t sc = lq * w[j] - pk * ku[j];
-      if (better(sc, u[j], best_s, best_id)) {
-        best_s = sc;
-        best_id = u[j];
+    int64_t lp = 0, lq = 1;
+    int32_t job = 0;
+    if (valid) job_lambda(a, v, lp, lq, job);
+    const int64_t pk = lp * kv;
+    int64_t best_s = INT64_MIN, wc = 0;
+    int32_t best_id = ISO_ID;
+    for (int64_t base = beg + gl; base < end; base += 4 * G) {
+      int32_t u[4];
+      int64_t w[4], ku[4];
+  #pragma unroll
+      for (int j = 0; j < 4; j++) {
+        const int64_t e = base + j * G;
+        u[j] = e < end ? a.col[e] : -1;
+        w[j] = e < end ? load_w<WK>(a.wt, e) : 0;
+      }
+  #pragma unroll
+      for (int j = 0; j < 4; j++) ku[j] = u[j] >= 0 ? a.k[u[j]] : 0;
+  #pragma unroll
+      for (int j = 0; j < 4; j++) {
+        if (u[j] < 0) continue;
+        const int64_t sc = lq * w[j] - pk * ku[j];
+        if (better(sc, u[j], best_s, best_id)) {
+          best_s = sc;
+          best_id = u[j];
+        }
       }
     }
-  }
-  int32_t d = v;
-  if constexpr (G < NT) {
-#pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1) {
-      int64_t os = __shfl_xor(best_s, o, WAVE);
-      int32_t oid = __shfl_xor(best_id, o, WAVE);
-      if (better(os, oid, best_s, best_id)) {
-        best_s = os;
-        best_id = oid;
+    int32_t d = v;
+    if constexpr (G < NT) {
+  #pragma unroll
+      for (int o = G / 2; o > 0; o >>= 1) {
+        int64_t os = __shfl_xor(best_s, o, WAVE);
+        int32_t oid = __shfl_xor(best_id, o, WAVE);
+        if (better(os, oid, best_s, best_id)) {
+          best_s = os;
+          best_id = oid;
+        }
       }
+      d = decide(best_s, best_id, 0, false, v);
+    } else {
+      block_best<NT>(best_s, best_id, wc);
+      if (t == 0) sh_d[0] = decide(best_s, best_id, 0, false, v);
+      __syncthreads();
+      d = sh_d[0];
     }
-    d = decide(best_s, best_id, 0, false, v);
-  } else {
-    block_best<NT>(best_s, best_id, wc);
-    if (t == 0) sh_d[0] = decide(best_s, best_id, 0, false, v);
-    __syncthreads();
-    d = sh_d[0];
-  }
-  const bool moved = valid && d != v;
-  if (valid && gl == 0) a.D[v] = d;
-  if (moved && a.next_flag)
-    for (int64_t e = beg + gl; e < end; e += G) a.next_flag[a.col[e]] = 1;
-  c_movers += (moved && gl == 0) ? 1 : 0;
-  c_cands += (valid && gl == 0) ? end - beg + 1 : 0;
-  c_marcs += (moved && gl == 0) ? end - beg : 0;
-  if constexpr (G == NT) __syncthreads();  // sh_d is reused by the next vertex
+    const bool moved = valid && d != v;
+    if (valid && gl == 0) a.D[v] = d;
+    if (moved && a.next_flag)
+      for (int64_t e = beg + gl; e < end; e += G) a.next_flag[a.col[e]] = 1;
+    c_movers += (moved && gl == 0) ? 1 : 0;
+    c_cands += (valid && gl == 0) ? end - beg + 1 : 0;
+    c_marcs += (moved && gl == 0) ? end - beg : 0;
+    if constexpr (G == NT) __syncthreads();  // sh_d is reused by the next vertex
   }
   flush_counters<NT>(a.ctr, c_movers, c_cands, c_marcs);
 }
@@ -695,52 +695,52 @@ __global__ __launch_bounds__(B7_NT) void k_b7_segscore(AggArgs a, const int64_t 
   work_of(a, list, cnt7);
   const int64_t nsg = tot[2], n7 = tot[3];
   for (int64_t sg = blockIdx.x; sg < nsg; sg += gridDim.x) {
-  // row owning this segment
-  int64_t lo = 0, hi = n7 - 1;
-  while (lo < hi) {
-    const int64_t mid = (lo + hi + 1) >> 1;
-    if (sstart[mid] <= sg) lo = mid;
-    else hi = mid - 1;
-  }
-  const int64_t i = lo;
-  const int32_t v = list[i];
-  const int32_t c = a.C[v];
-  int64_t lp, lq;
-  int32_t job;
-  job_lambda(a, v, lp, lq, job);
-  const int64_t pk = lp * a.k[v];
-  const int64_t t0 = tstart[i], H = tstart[i + 1] - t0;
-  const int64_t j0 = (sg - sstart[i]) * B7_SEG;
-  const int64_t j1 = j0 + B7_SEG < H ? j0 + B7_SEG : H;
-  int64_t best_s = INT64_MIN, wc = 0, cands = 0;
-  int32_t best_id = ISO_ID;
-  // the tables were filled by device-scope atomics in the previous kernel:
-  // read them with device-scope loads as well
-  for (int64_t j = j0 + threadIdx.x; j < j1; j += B7_NT) {
-    const int32_t X = __hip_atomic_load(&a.gkeys[t0 + j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (X < 0) continue;
-    cands++;
-    const int64_t wx = __hip_atomic_load(&a.gvals[t0 + j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (X == c) {
-      wc = wx;
-    } else {
-      const int64_t sc = lq * wx - pk * a.K[X];
-      if (better(sc, X, best_s, best_id)) {
-        best_s = sc;
-        best_id = X;
+    // row owning this segment
+    int64_t lo = 0, hi = n7 - 1;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi + 1) >> 1;
+      if (sstart[mid] <= sg) lo = mid;
+      else hi = mid - 1;
+    }
+    const int64_t i = lo;
+    const int32_t v = list[i];
+    const int32_t c = a.C[v];
+    int64_t lp, lq;
+    int32_t job;
+    job_lambda(a, v, lp, lq, job);
+    const int64_t pk = lp * a.k[v];
+    const int64_t t0 = tstart[i], H = tstart[i + 1] - t0;
+    const int64_t j0 = (sg - sstart[i]) * B7_SEG;
+    const int64_t j1 = j0 + B7_SEG < H ? j0 + B7_SEG : H;
+    int64_t best_s = INT64_MIN, wc = 0, cands = 0;
+    int32_t best_id = ISO_ID;
+    // the tables were filled by device-scope atomics in the previous kernel:
+    // read them with device-scope loads as well
+    for (int64_t j = j0 + threadIdx.x; j < j1; j += B7_NT) {
+      const int32_t X = __hip_atomic_load(&a.gkeys[t0 + j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (X < 0) continue;
+      cands++;
+      const int64_t wx = __hip_atomic_load(&a.gvals[t0 + j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (X == c) {
+        wc = wx;
+      } else {
+        const int64_t sc = lq * wx - pk * a.K[X];
+        if (better(sc, X, best_s, best_id)) {
+          best_s = sc;
+          best_id = X;
+        }
       }
     }
-  }
-  cands = wave_sum(cands);
-  __shared__ int64_t rc[B7_NT / WAVE];
-  if (lane_id() == 0) rc[threadIdx.x / WAVE] = cands;
-  block_best<B7_NT>(best_s, best_id, wc);
-  if (threadIdx.x == 0) {
-    int64_t tc = 0;
-    for (int k = 0; k < B7_NT / WAVE; k++) tc += rc[k];
-    part[sg] = SegBest{best_s, wc, tc, best_id, 0};
-  }
-  __syncthreads();  // rc is reused by the next segment
+    cands = wave_sum(cands);
+    __shared__ int64_t rc[B7_NT / WAVE];
+    if (lane_id() == 0) rc[threadIdx.x / WAVE] = cands;
+    block_best<B7_NT>(best_s, best_id, wc);
+    if (threadIdx.x == 0) {
+      int64_t tc = 0;
+      for (int k = 0; k < B7_NT / WAVE; k++) tc += rc[k];
+      part[sg] = SegBest{best_s, wc, tc, best_id, 0};
+    }
+    __syncthreads();  // rc is reused by the next segment
   }
 }
 
@@ -754,40 +754,40 @@ __global__ __launch_bounds__(B7_NT) void k_b7_final(AggArgs a, const int64_t *__
   work_of(a, list, n7);
   int64_t movers = 0, marcs = 0, cands = 0;
   for (int64_t i = blockIdx.x; i < n7; i += gridDim.x) {
-  const int32_t v = list[i];
-  const int64_t beg = a.off[v], end = a.off[v + 1];
-  const int32_t c = a.C[v];
-  const int64_t kv = a.k[v], Kc = a.K[c];
-  const int32_t cntc = a.cnt[c];
-  int64_t best_s = INT64_MIN, wc = 0;
-  int32_t best_id = ISO_ID;
-  for (int64_t sg = sstart[i] + t; sg < sstart[i + 1]; sg += B7_NT) {
-    const SegBest b = part[sg];
-    if (better(b.best_s, b.best_id, best_s, best_id)) {
-      best_s = b.best_s;
-      best_id = b.best_id;
+    const int32_t v = list[i];
+    const int64_t beg = a.off[v], end = a.off[v + 1];
+    const int32_t c = a.C[v];
+    const int64_t kv = a.k[v], Kc = a.K[c];
+    const int32_t cntc = a.cnt[c];
+    int64_t best_s = INT64_MIN, wc = 0;
+    int32_t best_id = ISO_ID;
+    for (int64_t sg = sstart[i] + t; sg < sstart[i + 1]; sg += B7_NT) {
+      const SegBest b = part[sg];
+      if (better(b.best_s, b.best_id, best_s, best_id)) {
+        best_s = b.best_s;
+        best_id = b.best_id;
+      }
+      wc += b.wc;
+      cands += b.cands;
     }
-    wc += b.wc;
-    cands += b.cands;
-  }
-  block_best<B7_NT>(best_s, best_id, wc);
-  if (t == 0) {
-    int64_t lp, lq;
-    int32_t job;
-    job_lambda(a, v, lp, lq, job);
-    const int64_t stay = lq * wc - lp * kv * (Kc - kv);
-    const int32_t d = decide(best_s, best_id, stay, a.allow_iso && cntc >= 2, c);
-    a.D[v] = d;
-    sh_d = d;
-    if (d != c) {
-      movers += 1;
-      marcs += end - beg;
+    block_best<B7_NT>(best_s, best_id, wc);
+    if (t == 0) {
+      int64_t lp, lq;
+      int32_t job;
+      job_lambda(a, v, lp, lq, job);
+      const int64_t stay = lq * wc - lp * kv * (Kc - kv);
+      const int32_t d = decide(best_s, best_id, stay, a.allow_iso && cntc >= 2, c);
+      a.D[v] = d;
+      sh_d = d;
+      if (d != c) {
+        movers += 1;
+        marcs += end - beg;
+      }
     }
-  }
-  __syncthreads();
-  if (sh_d != c && a.next_flag)
-    for (int64_t e = beg + t; e < end; e += B7_NT) a.next_flag[a.col[e]] = 1;
-  __syncthreads();  // sh_d is reused by the next row
+    __syncthreads();
+    if (sh_d != c && a.next_flag)
+      for (int64_t e = beg + t; e < end; e += B7_NT) a.next_flag[a.col[e]] = 1;
+    __syncthreads();  // sh_d is reused by the next row
   }
   flush_counters<B7_NT>(a.ctr, movers, cands, marcs);
 }
@@ -1814,7 +1814,8 @@ void best_moves(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_para
     const int64_t hl_nact = hctr[o_nact];
     int64_t isolated = 0;
     for (int s = 0; s < S; s++) isolated += hctr[o_isoc + s];
-    if (cap_err) fail(LCC_ERR_DEVICE, "internal: a vertex degree exceeded the hash capacity sized from the maximum degree");
+    if (cap_err)
+      fail(LCC_ERR_DEVICE, "internal: a vertex degree exceeded the hash capacity sized from the maximum degree");
     if (isolated) rename_fresh(c, n, C, K, cnt, iso_err, jv);
     if (bl) {
       // per-job termination: a job without moves in this iteration stops
