@@ -159,6 +159,45 @@ __device__ __forceinline__ void lds_insert(int32_t *keys, Acc *vals, uint32_t H,
   }
 }
 
+// lds_insert that reports the slot it claimed for a new key (-1 otherwise).
+template <class Acc>
+__device__ __forceinline__ int32_t lds_insert_claim(int32_t *keys, Acc *vals, uint32_t H, int32_t X, int64_t w) {
+  uint32_t h = slot_of(X, H);
+  int32_t claimed = -1;
+  while (true) {
+    int32_t cur = keys[h];
+    if (cur == -1) {
+      cur = atomicCAS(&keys[h], -1, X);
+      if (cur == -1) {
+        claimed = (int32_t)h;
+        cur = X;
+      }
+    }
+    if (cur == X) {
+      if (w) {
+        if constexpr (sizeof(Acc) == 8)
+          atomicAdd(reinterpret_cast<unsigned long long *>(&vals[h]), (unsigned long long)w);
+        else
+          atomicAdd(&vals[h], (Acc)w);
+      }
+      return claimed;
+    }
+    h = (h + 1 == H) ? 0 : h + 1;
+  }
+}
+
+// Appends the slots the lanes of a wave claimed (claimed >= 0) to the
+// occupied list: one LDS atomic per wave.  Every lane of the wave calls it.
+__device__ __forceinline__ void list_claims(int32_t claimed, uint16_t *occ, int32_t *occ_n) {
+  const uint64_t m = __ballot(claimed >= 0);
+  if (!m) return;
+  const int lead = __ffsll((unsigned long long)m) - 1;
+  int32_t base = 0;
+  if (lane_id() == lead) base = atomicAdd(occ_n, (int32_t)__popcll(m));
+  base = __shfl(base, lead, WAVE);
+  if (claimed >= 0) occ[base + __popcll(m & __lanemask_lt())] = (uint16_t)claimed;
+}
+
 // Decision from the reduced results (identical in every lane of the group).
 __device__ __forceinline__ int32_t decide(int64_t best_s, int32_t best_id, int64_t stay, bool iso_ok, int32_t c) {
   if (iso_ok && (best_s == INT64_MIN || 0 > best_s)) {
@@ -286,15 +325,15 @@ __global__ __launch_bounds__(BM_NT) void k_bm_group(AggArgs a) {
         for (int64_t base = beg + gl; base < end; base += 4 * G) {
           int32_t u[4], X[4];
           int64_t w[4];
-  #pragma unroll
+#pragma unroll
           for (int j = 0; j < 4; j++) {
             const int64_t e = base + j * G;
             u[j] = e < end ? a.col[e] : -1;
             w[j] = e < end ? load_w<WK>(a.wt, e) : 0;
           }
-  #pragma unroll
+#pragma unroll
           for (int j = 0; j < 4; j++) X[j] = u[j] >= 0 ? a.C[u[j]] : -1;
-  #pragma unroll
+#pragma unroll
           for (int j = 0; j < 4; j++)
             if (X[j] >= 0) lds_insert<Acc>(keys, vals, H, X[j], w[j]);
         }
@@ -324,7 +363,7 @@ __global__ __launch_bounds__(BM_NT) void k_bm_group(AggArgs a) {
         }
       }
     }
-  #pragma unroll
+#pragma unroll
     for (int o = G / 2; o > 0; o >>= 1) {
       int64_t os = __shfl_xor(best_s, o, WAVE);
       int32_t oid = __shfl_xor(best_id, o, WAVE);
@@ -362,17 +401,26 @@ __global__ __launch_bounds__(BM_NT) void k_bm_group(AggArgs a) {
 // dynamic LDS (keys then values).  The host admits a vertex only when its
 // distinct clusters (<= deg + 1) fill at most 70% of hcap.
 // TAG only separates launch classes in kernel traces (1 = small levels).
-template <int NT, int WK, bool A32, int TAG = 0>
+// With LIST, a slot is cleared the first time a vertex of the block reaches
+// it; after that the slots a vertex filled (listed in occ, one uint16 per
+// slot after the values) are all that scoring reads and all that is reset for
+// the next vertex, so a row with few distinct clusters costs little in a large
+// table.  Without LIST each vertex clears and scans its H slots (less LDS per
+// block, so more resident blocks).
+template <int NT, int WK, bool A32, int TAG = 0, bool LIST = true>
 __global__ __launch_bounds__(NT) void k_bm_wide(AggArgs a) {
   using Acc = typename std::conditional<A32, int32_t, int64_t>::type;
   extern __shared__ __align__(16) unsigned char smem[];
   int32_t *keys = reinterpret_cast<int32_t *>(smem);
   Acc *vals = reinterpret_cast<Acc *>(smem + ((a.hcap * 4 + 15) & ~15ll));
-  __shared__ int32_t sh_d;
+  uint16_t *occ = reinterpret_cast<uint16_t *>(smem + ((a.hcap * 4 + 15) & ~15ll) + a.hcap * sizeof(Acc));
+  __shared__ int32_t sh_d, occ_n;
   const int t = threadIdx.x;
   const int32_t *list;
   int64_t count;
   work_of(a, list, count);
+  if (t == 0) occ_n = 0;
+  uint32_t clean = 0;  // slots [0, clean) hold no key (block-uniform)
   int64_t movers = 0, marcs = 0, cands = 0;
   for (int64_t vi = blockIdx.x; vi < count; vi += gridDim.x) {
     const int32_t v = list[vi];
@@ -380,28 +428,34 @@ __global__ __launch_bounds__(NT) void k_bm_wide(AggArgs a) {
     const int32_t c = a.C[v];
     uint32_t H = pow2_at_least(2 * (end - beg + 1));
     if (H > (uint32_t)a.hcap) H = (uint32_t)a.hcap;
-    for (uint32_t j = t; j < H; j += NT) {
+    const int64_t kv = a.k[v], Kc = a.K[c];
+    const int32_t cntc = a.cnt[c];
+    for (uint32_t j = (LIST ? clean : 0) + t; j < H; j += NT) {
       keys[j] = -1;
       vals[j] = 0;
     }
-    const int64_t kv = a.k[v], Kc = a.K[c];
-    const int32_t cntc = a.cnt[c];
+    if (H > clean) clean = H;
     __syncthreads();
-    if (t == 0) lds_insert<Acc>(keys, vals, H, c, 0);
+    if (t == 0) {
+      const int32_t h0 = lds_insert_claim<Acc>(keys, vals, H, c, 0);
+      if (LIST && h0 >= 0) occ[atomicAdd(&occ_n, 1)] = (uint16_t)h0;
+    }
     for (int64_t base = beg + t; base < end; base += 4 * NT) {
       int32_t u[4], X[4];
       int64_t w[4];
-  #pragma unroll
+#pragma unroll
       for (int j = 0; j < 4; j++) {
         const int64_t e = base + j * NT;
         u[j] = e < end ? a.col[e] : -1;
         w[j] = e < end ? load_w<WK>(a.wt, e) : 0;
       }
-  #pragma unroll
+#pragma unroll
       for (int j = 0; j < 4; j++) X[j] = u[j] >= 0 ? a.C[u[j]] : -1;
-  #pragma unroll
-      for (int j = 0; j < 4; j++)
-        if (X[j] >= 0) lds_insert<Acc>(keys, vals, H, X[j], w[j]);
+#pragma unroll
+      for (int j = 0; j < 4; j++) {
+        const int32_t claimed = X[j] >= 0 ? lds_insert_claim<Acc>(keys, vals, H, X[j], w[j]) : -1;
+        if constexpr (LIST) list_claims(claimed, occ, &occ_n);
+      }
     }
     __syncthreads();
     int64_t lp, lq;
@@ -410,11 +464,13 @@ __global__ __launch_bounds__(NT) void k_bm_wide(AggArgs a) {
     const int64_t pk = lp * kv;
     int64_t best_s = INT64_MIN, wc = 0;
     int32_t best_id = ISO_ID;
-    for (uint32_t j = t; j < H; j += NT) {
-      const int32_t X = keys[j];
-      if (X < 0) continue;
+    const int32_t nocc = LIST ? occ_n : (int32_t)H;
+    for (int32_t j = t; j < nocc; j += NT) {
+      const uint32_t h = LIST ? occ[j] : (uint32_t)j;
+      const int32_t X = keys[h];
+      if (!LIST && X < 0) continue;
       cands++;
-      const int64_t wx = (int64_t)vals[j];
+      const int64_t wx = (int64_t)vals[h];
       if (X == c) {
         wc = wx;
       } else {
@@ -439,7 +495,14 @@ __global__ __launch_bounds__(NT) void k_bm_wide(AggArgs a) {
     __syncthreads();
     if (sh_d != c && a.next_flag)
       for (int64_t e = beg + t; e < end; e += NT) a.next_flag[a.col[e]] = 1;
-    __syncthreads();  // table and sh_d are reused by the next vertex
+    if constexpr (LIST) {  // leave the table clean for the next vertex
+      for (int32_t j = t; j < nocc; j += NT) {
+        keys[occ[j]] = -1;
+        vals[occ[j]] = 0;
+      }
+    }
+    __syncthreads();  // table, occ and sh_d are reused by the next vertex
+    if (t == 0) occ_n = 0;
   }
   flush_counters<NT>(a.ctr, movers, cands, marcs);
 }
@@ -481,15 +544,15 @@ __global__ __launch_bounds__(NT) void k_bm_single(AggArgs a) {
     for (int64_t base = beg + gl; base < end; base += 4 * G) {
       int32_t u[4];
       int64_t w[4], ku[4];
-  #pragma unroll
+#pragma unroll
       for (int j = 0; j < 4; j++) {
         const int64_t e = base + j * G;
         u[j] = e < end ? a.col[e] : -1;
         w[j] = e < end ? load_w<WK>(a.wt, e) : 0;
       }
-  #pragma unroll
+#pragma unroll
       for (int j = 0; j < 4; j++) ku[j] = u[j] >= 0 ? a.k[u[j]] : 0;
-  #pragma unroll
+#pragma unroll
       for (int j = 0; j < 4; j++) {
         if (u[j] < 0) continue;
         const int64_t sc = lq * w[j] - pk * ku[j];
@@ -501,7 +564,7 @@ __global__ __launch_bounds__(NT) void k_bm_single(AggArgs a) {
     }
     int32_t d = v;
     if constexpr (G < NT) {
-  #pragma unroll
+#pragma unroll
       for (int o = G / 2; o > 0; o >>= 1) {
         int64_t os = __shfl_xor(best_s, o, WAVE);
         int32_t oid = __shfl_xor(best_id, o, WAVE);
@@ -1218,16 +1281,18 @@ struct AggLaunch {
   int slot;
 };
 
-// Dynamic LDS for the wide kernels: keys (int32) then 16-byte aligned values.
-size_t wide_lds_bytes(int64_t slots, bool a32) {
-  return (size_t)((slots * 4 + 15) & ~15ll) + (size_t)slots * (a32 ? 4 : 8);
+// Dynamic LDS for the wide kernels: keys (int32), 16-byte aligned values,
+// then (list) the occupied-slot list (uint16, one entry per slot).
+size_t wide_lds_bytes(int64_t slots, bool a32, bool list = true) {
+  return (size_t)((slots * 4 + 15) & ~15ll) + (size_t)slots * (a32 ? 4 : 8) + (list ? (size_t)slots * 2 : 0);
 }
 
 // Largest table (slots) that fits the per-block LDS beside the kernel's own
 // reduction arrays.
 int64_t wide_slots(const Ctx &c, bool a32) {
   const int64_t budget = (int64_t)c.lds_per_block - 4096;
-  return (budget - 16) / (a32 ? 8 : 12);
+  const int64_t slots = (budget - 16) / (a32 ? 10 : 14);
+  return slots < 65536 ? slots : 65535;  // occupied-slot indices are uint16
 }
 
 // Raises a kernel's dynamic-LDS limit once per context.
@@ -1263,10 +1328,10 @@ void launch_bin(Ctx &c, int bin, AggArgs a, int64_t grid) {
     case 2: c.launch(k_bm_group<32, 64, WK, A32>, gr, dim3(BM_NT), 0, a); break;
     case 3: c.launch(k_bm_group<64, 128, WK, A32>, gr, dim3(BM_NT), 0, a); break;
     case 4: c.launch(k_bm_group<64, 512, WK, A32>, gr, dim3(BM_NT), 0, a); break;
-    case 5: {
+    case 5: {  // without the slot list: 48 KB of LDS keeps 3 blocks per CU
       a.hcap = MID_SLOTS;
-      const size_t bytes = wide_lds_bytes(MID_SLOTS, A32);
-      c.launch(k_bm_wide<BM_NT, WK, A32>, gr, dim3(BM_NT), bytes, a);
+      const size_t bytes = wide_lds_bytes(MID_SLOTS, A32, false);
+      c.launch(k_bm_wide<BM_NT, WK, A32, 0, false>, gr, dim3(BM_NT), bytes, a);
       break;
     }
     case 6: {
