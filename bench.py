@@ -254,18 +254,39 @@ def run_batch(args, dev):
     log(f"workload {args.workload}: {J} jobs, n={gp.n} arcs={gp.arcs} generated in {time.time() - t0:.1f}s")
     ctx = lcc.context(0)
     prm = lcc.Params()
+    sweep = spec["kind"] == "sweep"
+
+    def run_one(params):
+        # a sweep clusters the one graph under every lambda in one call; a
+        # batch takes the jobs packed block-diagonally
+        if sweep:
+            return lcc.lcc_sweep(ctx, singles[0], lams, params)
+        return lcc.lcc_cluster_batch(ctx, gp, start, lams, params)
+
     for i in range(args.warmup):
-        lab_b, jobs_b, st = lcc.lcc_cluster_batch(ctx, gp, start, lams, prm)
+        _, _, st = run_one(prm)
         log(f"warmup {i}: {st['ms_total']:.1f} ms, levels={st['levels']}")
     for j in range(min(J, 4)):
         lcc.lcc_cluster(ctx, singles[j], *lams[j], prm)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
-        lab_b, jobs_b, st = lcc.lcc_cluster_batch(ctx, gp, start, lams, prm)
+        lab_b, jobs_b, st = run_one(prm)
     torch.cuda.synchronize()
     dt_b = (time.perf_counter() - t0) / args.steps
-    log(f"batched: {dt_b * 1e3:.1f} ms per batch ({J} jobs, levels={st['levels']})")
+    log(f"{'sweep' if sweep else 'batched'}: {dt_b * 1e3:.1f} ms per call ({J} jobs, levels={st['levels']})")
+    dt_pk = None
+    if sweep:
+        # the same jobs as a plain packed batch (no shared rows), for reference
+        lcc.lcc_cluster_batch(ctx, gp, start, lams, prm)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            lab_pk, jobs_pk, _ = lcc.lcc_cluster_batch(ctx, gp, start, lams, prm)
+        torch.cuda.synchronize()
+        dt_pk = (time.perf_counter() - t0) / args.steps
+        log(f"packed batch of the same jobs: {dt_pk * 1e3:.1f} ms; sweep speedup {dt_pk / dt_b:.2f}x")
+        lab_b = lab_b.reshape(-1)
     # the plain path: one job at a time
     labs_p, Ns_p = [], []
     torch.cuda.synchronize()
@@ -279,15 +300,19 @@ def run_batch(args, dev):
     log(f"plain: {dt_p * 1e3:.1f} ms for {J} jobs one at a time; speedup {dt_p / dt_b:.2f}x")
     same = all(torch.equal(lab_b[int(start[j]):int(start[j + 1])], labs_p[j]) and jobs_b[j]["N"] == Ns_p[j]
                for j in range(J))
+    if sweep:
+        same = same and all(torch.equal(lab_pk[int(start[j]):int(start[j + 1])], labs_p[j]) and
+                            jobs_pk[j]["N"] == Ns_p[j] for j in range(J))
     log(f"every job identical to its plain run: {same}")
-    # kernel classes of one more batched run, timed per launch
+    # kernel classes of one more run, timed per launch
     ctx.reset_kernel_stats()
-    lcc.lcc_cluster_batch(ctx, gp, start, lams, lcc.Params(timing=1))
+    run_one(lcc.Params(timing=1))
     ks = ctx.kernel_stats()
     for name, v in sorted(ks.items(), key=lambda kv: -kv[1]["ms"])[:12]:
         sec = v["ms"] * 1e-3
         log(f"  {name:24s} launches={v['launches']:6d} ms={v['ms']:8.2f} "
-            f"GB/s={(v['bytes'] / sec / 1e9) if sec > 0 else 0:8.1f}")
+            f"GB/s={(v['bytes'] / sec / 1e9) if sec > 0 else 0:8.1f} "
+            f"Gitems/s={(v['items'] / sec / 1e9) if sec > 0 else 0:7.2f}")
     cpu = None
     if not args.no_cpu_baseline:
         import oracle as O
@@ -322,9 +347,11 @@ def run_batch(args, dev):
         "dtype": "int64",
         "data": "synthetic",
         "config": {"workload": args.workload, "description": desc, "jobs": J, "n_total": gp.n,
-                   "arcs_total": gp.arcs, "batched_ms": dt_b * 1e3, "plain_ms": dt_p * 1e3,
+                   "arcs_total": gp.arcs, "entry": "lcc_sweep" if sweep else "lcc_cluster_batch",
+                   "batched_ms": dt_b * 1e3, "plain_ms": dt_p * 1e3,
                    "speedup_vs_plain": dt_p / dt_b, "jobs_per_s_batched": J / dt_b,
-                   "jobs_per_s_plain": J / dt_p, "identical_results": same},
+                   "jobs_per_s_plain": J / dt_p, "identical_results": same,
+                   **({"packed_batch_ms": dt_pk * 1e3, "speedup_vs_packed_batch": dt_pk / dt_b} if sweep else {})},
         "roofline": dominant_kernel(ks),
         "cpu_baseline": cpu,
     }

@@ -306,6 +306,32 @@ lcc_status lcc_cluster_batch(lcc_ctx *ctx, const lcc_graph *g, int64_t jobs, con
                              const lcc_lambda *lambdas, const lcc_params *prm, int32_t *labels_out,
                              lcc_job_out *jobs_out, lcc_batch_stats *stats, void *stream);
 
+/* Most resolutions one lcc_sweep call takes. */
+#define LCC_SWEEP_MAX 16
+
+/* Parallel-CC (as lcc_cluster) of ONE graph under several resolutions at
+ * once: the quality experiments of Section 4.3 cluster each graph over a
+ * grid of lambda values, and every value is a separate run of Algorithm 1
+ * with the objective of Section 2.  Result j is exactly the result of
+ * lcc_cluster(g, lambdas[j], prm) run alone.
+ *
+ * count (0..LCC_SWEEP_MAX) resolutions; lambdas (host, count entries); prm is
+ * shared (stop_after_subrounds must be 0).  labels_out (device int32,
+ * count * g->n entries) receives at offset j * g->n the canonical labels of
+ * resolution j; jobs_out (host, count entries) and stats (host) are nullable.
+ * The library packs count copies of g into its own device buffers (count
+ * times the graph's arrays, kept until the context is destroyed or the next
+ * sweep) and runs them as one batch in which the level-0 rows of degree
+ * below 256 are read once for all resolutions, with the cluster ids of each
+ * vertex under all resolutions held in one 64-byte line.
+ *
+ * Errors: as lcc_cluster_batch, plus INVALID_ARG for count outside
+ * [0, LCC_SWEEP_MAX] or count * n >= 2^30; OVERFLOW names the first
+ * resolution whose bounds fail. */
+lcc_status lcc_sweep(lcc_ctx *ctx, const lcc_graph *g, int64_t count, const lcc_lambda *lambdas,
+                     const lcc_params *prm, int32_t *labels_out, lcc_job_out *jobs_out, lcc_batch_stats *stats,
+                     void *stream);
+
 /* Per-kernel timing collected while params.timing was set (HIP events around
  * every launch, on the launch stream).  bytes is the algorithmic HBM traffic
  * the launches must move (inputs read once, outputs written once), computed

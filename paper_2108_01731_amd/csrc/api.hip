@@ -585,6 +585,169 @@ lcc_status lcc_cluster(lcc_ctx *ctx, const lcc_graph *g, lcc_lambda lam, const l
   });
 }
 
+// The level loop of a batched run, after validation: coarsening with per-job
+// Best-Moves and compression, then the unwinding with flatten and refinement,
+// canonical per-job labels and (want_obj) per-job objectives.  shared_n1 > 0
+// marks the jobs as identical copies of one graph of shared_n1 vertices.
+static void batch_levels(Ctx &c, const lcc_graph *g, int64_t J, const std::vector<int64_t> &hstart,
+                         const std::vector<int64_t> &vch, int64_t *d_start, const int64_t *d_jp, const int64_t *d_jq,
+                         uint8_t *d_cont, const lcc_lambda *lambdas, const lcc_params *prm, const GraphSummary &s,
+                         bool wide, int32_t *labels_out, bool want_obj, std::vector<lcc_job_out> &jo,
+                         lcc_batch_stats &bs, int64_t shared_n1) {
+  using clk = std::chrono::steady_clock;
+  // level 0 job layout; per-level arrays live in the context
+  std::vector<int32_t *> jidl, Cl, maps;
+  std::vector<int64_t *> jbasel;
+  std::vector<lcc_graph> G;
+  std::vector<int64_t> maxdeg;
+  jidl.push_back(c.buf<int32_t>("lv.jid0", (size_t)g->n));
+  batch_fill_jid(c, d_start, J, g->n, jidl.back());
+  jbasel.push_back(d_start);
+  G.push_back(*g);
+  maxdeg.push_back(s.maxdeg);
+  std::vector<uint8_t> run((size_t)J), cont((size_t)J), moved((size_t)J);
+  std::vector<int32_t> top((size_t)J, 0), iters((size_t)J);
+  for (int64_t j = 0; j < J; j++) run[(size_t)j] = hstart[(size_t)j + 1] > hstart[(size_t)j];
+  int maxtop = 0;
+  double ms_bm = 0, ms_cp = 0;
+  for (int l = 0;; l++) {
+    const int64_t n = G[l].n;
+    bs.n_level[l] = n;
+    bs.arcs_level[l] = G[l].arcs;
+    bs.levels = l + 1;
+    Cl.push_back(c.buf<int32_t>("lv.C" + std::to_string(l), (size_t)(n > 0 ? n : 1)));
+    int32_t *C = Cl.back();
+    iota_i32(c, C, n);
+    BatchLevel bl;
+    bl.jobs = J;
+    bl.jid = jidl[l];
+    bl.jbase = jbasel[l];
+    bl.jp = d_jp;
+    bl.jq = d_jq;
+    bl.active = run.data();
+    bl.iters = iters.data();
+    bl.moved_any = moved.data();
+    bl.shared_n = l == 0 ? shared_n1 : 0;
+    lcc_bm_stats st;
+    auto a = clk::now();
+    const bool simple = l > 0 || s.sorted_rows;
+    best_moves(c, G[l], 0, 1, *prm, l, 0, C, BMShape{maxdeg[l], !wide, true, simple}, st, &bl);
+    ms_bm += std::chrono::duration<double, std::milli>(clk::now() - a).count();
+    bs.moves_total += st.moves;
+    bs.arcs_scanned_total += st.arcs_scanned;
+    bool any = false;
+    for (int64_t j = 0; j < J; j++) {
+      cont[(size_t)j] = 0;
+      if (!run[(size_t)j]) continue;
+      if (moved[(size_t)j] && l + 1 < prm->max_levels) {
+        cont[(size_t)j] = 1;
+        any = true;
+      } else {
+        top[(size_t)j] = l;
+        jo[(size_t)j].top_moved = moved[(size_t)j];
+      }
+    }
+    if (!any) {
+      maxtop = l;
+      break;
+    }
+    h2d(c, d_cont, cont.data(), (size_t)J);
+    maps.push_back(c.buf<int32_t>("lv.map" + std::to_string(l), (size_t)(n > 0 ? n : 1)));
+    OwnedGraph &next = c.level_graph((size_t)l + 1);
+    // the next level's job of every vertex and job bases
+    jidl.push_back(c.buf<int32_t>("lv.jid" + std::to_string(l + 1), (size_t)(n > 0 ? n : 1)));
+    jbasel.push_back(c.buf<int64_t>("lv.jbase" + std::to_string(l + 1), (size_t)(J + 1)));
+    CompressJobs cj;
+    cj.jobs = J;
+    cj.jid = jidl[l];
+    cj.jcont = d_cont;
+    cj.jid_next = jidl[l + 1];
+    cj.jbase_next = jbasel[l + 1];
+    int64_t md = 0;
+    a = clk::now();
+    compress_graph(c, G[l], C, next, maps.back(), wide, &md, &cj);
+    ms_cp += std::chrono::duration<double, std::milli>(clk::now() - a).count();
+    G.push_back(next.view());
+    maxdeg.push_back(md);
+    run = cont;
+  }
+  for (int l = maxtop - 1; l >= 0; l--) {
+    int32_t *C = Cl[l];
+    // jobs that stopped coarsening at this level keep their clustering (map < 0)
+    batch_flatten(c, G[l].n, maps[l], Cl[l + 1], jidl[l], jbasel[l], jbasel[l + 1], C);
+    if (prm->refine) {
+      bool any = false;
+      for (int64_t j = 0; j < J; j++) {
+        run[(size_t)j] = top[(size_t)j] > l;
+        any = any || run[(size_t)j];
+      }
+      if (!any) continue;
+      BatchLevel bl;
+      bl.jobs = J;
+      bl.jid = jidl[l];
+      bl.jbase = jbasel[l];
+      bl.jp = d_jp;
+      bl.jq = d_jq;
+      bl.active = run.data();
+      bl.iters = iters.data();
+      bl.moved_any = moved.data();
+      bl.shared_n = l == 0 ? shared_n1 : 0;
+      lcc_bm_stats st;
+      auto a = clk::now();
+      best_moves(c, G[l], 0, 1, *prm, l, 1, C, BMShape{maxdeg[l], !wide, false, false}, st, &bl);
+      ms_bm += std::chrono::duration<double, std::milli>(clk::now() - a).count();
+      bs.moves_total += st.moves;
+      bs.arcs_scanned_total += st.arcs_scanned;
+    }
+  }
+  // canonical labels over the packed graph, then made job-local
+  const int64_t n0 = g->n;
+  int32_t *glab = c.buf<int32_t>("bt.glab", (size_t)n0);
+  const int64_t total = canonical_labels(c, n0, Cl[0], glab);
+  batch_local_labels(c, glab, jidl[0], d_start, n0, labels_out);
+  std::vector<int32_t> first = batch_first_labels(c, glab, d_start, J);
+  // clusters of job j are the global labels [first_j, first of the next non-empty job)
+  int64_t nxt = total;
+  for (int64_t j = J - 1; j >= 0; j--) {
+    if (first[(size_t)j] < 0) continue;
+    jo[(size_t)j].clusters = nxt - first[(size_t)j];
+    nxt = first[(size_t)j];
+  }
+  for (int64_t j = 0; j < J; j++) jo[(size_t)j].levels = top[(size_t)j] + 1;
+  if (want_obj) {
+    int64_t *K = c.buf<int64_t>("bt.K", (size_t)n0);
+    int64_t *KK = c.buf<int64_t>("bt.KK", (size_t)n0);
+    cluster_sums_k_kk(c, *g, glab, K, KK);
+    std::vector<int64_t> cch;
+    for (int64_t j = 0; j < J; j++) {
+      if (first[(size_t)j] < 0) continue;
+      const int64_t xb = first[(size_t)j], xe = xb + jo[(size_t)j].clusters;
+      for (int64_t x = xb; x < xe; x += BATCH_CHUNK) {
+        cch.push_back(j);
+        cch.push_back(x);
+        cch.push_back(std::min<int64_t>(x + BATCH_CHUNK, xe));
+      }
+    }
+    std::vector<i128> intra, self, pairs;
+    batch_objective_parts(c, *g, glab, vch, K, KK, cch, intra, self, pairs);
+    std::vector<i128> w2((size_t)J, 0), ss((size_t)J, 0), pp((size_t)J, 0);
+    for (size_t i = 0; i < vch.size() / 3; i++) {
+      w2[(size_t)vch[3 * i]] += intra[i];
+      ss[(size_t)vch[3 * i]] += self[i];
+    }
+    for (size_t i = 0; i < cch.size() / 3; i++) pp[(size_t)cch[3 * i]] += pairs[i];
+    for (int64_t j = 0; j < J; j++) {
+      const size_t u = (size_t)j;
+      const i128 N = (i128)lambdas[j].q * (ss[u] + w2[u] / 2) - (i128)lambdas[j].p * (pp[u] / 2);
+      fill_objective(N, lambdas[j].q, &jo[u].obj);
+    }
+  }
+  c.sync();
+  if (c.timing) c.collect_timing();
+  bs.ms_best_move = ms_bm;
+  bs.ms_compress = ms_cp;
+}
+
 lcc_status lcc_cluster_batch(lcc_ctx *ctx, const lcc_graph *g, int64_t jobs, const int64_t *job_start,
                              const lcc_lambda *lambdas, const lcc_params *prm, int32_t *labels_out,
                              lcc_job_out *jobs_out, lcc_batch_stats *stats, void *stream) {
@@ -680,155 +843,85 @@ lcc_status lcc_cluster_batch(lcc_ctx *ctx, const lcc_graph *g, int64_t jobs, con
         wide = wide || wide_weights(sj[(size_t)j]);
       }
     }
-    // level 0 job layout; per-level arrays live in the context
-    std::vector<int32_t *> jidl, Cl, maps;
-    std::vector<int64_t *> jbasel;
-    std::vector<lcc_graph> G;
-    std::vector<int64_t> maxdeg;
-    jidl.push_back(c.buf<int32_t>("lv.jid0", (size_t)g->n));
-    batch_fill_jid(c, d_start, J, g->n, jidl.back());
-    jbasel.push_back(d_start);
-    G.push_back(*g);
-    maxdeg.push_back(s.maxdeg);
-    std::vector<uint8_t> run((size_t)J), cont((size_t)J), moved((size_t)J);
-    std::vector<int32_t> top((size_t)J, 0), iters((size_t)J);
-    for (int64_t j = 0; j < J; j++) run[(size_t)j] = hstart[(size_t)j + 1] > hstart[(size_t)j];
-    int maxtop = 0;
-    double ms_bm = 0, ms_cp = 0;
-    for (int l = 0;; l++) {
-      const int64_t n = G[l].n;
-      bs.n_level[l] = n;
-      bs.arcs_level[l] = G[l].arcs;
-      bs.levels = l + 1;
-      Cl.push_back(c.buf<int32_t>("lv.C" + std::to_string(l), (size_t)(n > 0 ? n : 1)));
-      int32_t *C = Cl.back();
-      iota_i32(c, C, n);
-      BatchLevel bl;
-      bl.jobs = J;
-      bl.jid = jidl[l];
-      bl.jbase = jbasel[l];
-      bl.jp = d_jp;
-      bl.jq = d_jq;
-      bl.active = run.data();
-      bl.iters = iters.data();
-      bl.moved_any = moved.data();
-      lcc_bm_stats st;
-      auto a = clk::now();
-      const bool simple = l > 0 || s.sorted_rows;
-      best_moves(c, G[l], 0, 1, *prm, l, 0, C, BMShape{maxdeg[l], !wide, true, simple}, st, &bl);
-      ms_bm += std::chrono::duration<double, std::milli>(clk::now() - a).count();
-      bs.moves_total += st.moves;
-      bs.arcs_scanned_total += st.arcs_scanned;
-      bool any = false;
+    batch_levels(c, g, J, hstart, vch, d_start, d_jp, d_jq, d_cont, lambdas, prm, s, wide, labels_out,
+                 jobs_out != nullptr, jo, bs, 0);
+    bs.ms_total = std::chrono::duration<double, std::milli>(clk::now() - t0).count();
+    if (jobs_out) std::copy(jo.begin(), jo.end(), jobs_out);
+    if (stats) *stats = bs;
+  });
+}
+
+lcc_status lcc_sweep(lcc_ctx *ctx, const lcc_graph *g, int64_t count, const lcc_lambda *lambdas,
+                     const lcc_params *prm, int32_t *labels_out, lcc_job_out *jobs_out, lcc_batch_stats *stats,
+                     void *stream) {
+  return guarded([&] {
+    if (!ctx) fail(LCC_ERR_INVALID_ARG, "ctx is NULL");
+    Ctx &c = ctx->c;
+    check_params(prm);
+    if (prm->max_levels < 1 || prm->max_levels > LCC_MAX_LEVELS)
+      fail(LCC_ERR_INVALID_ARG, "max_levels must be in [1, 64]");
+    if (prm->stop_after_subrounds != 0) fail(LCC_ERR_INVALID_ARG, "stop_after_subrounds must be 0 in a sweep");
+    if (count < 0 || count > LCC_SWEEP_MAX) fail(LCC_ERR_INVALID_ARG, "count must be in [0, 16]");
+    if (count > 0 && !lambdas) fail(LCC_ERR_INVALID_ARG, "lambdas is NULL");
+    begin(c, stream, prm);
+    check_graph_args(c, g);
+    for (int64_t j = 0; j < count; j++) check_lambda(lambdas[j]);
+    const int64_t J = count, n1 = g->n;
+    if (J * n1 >= ((int64_t)1 << 30)) fail(LCC_ERR_INVALID_ARG, "count * n must be below 2^30");
+    check_dev(c, labels_out, (size_t)(J * n1) * sizeof(int32_t), "labels_out");
+    using clk = std::chrono::steady_clock;
+    auto t0 = clk::now();
+    lcc_batch_stats bs;
+    std::memset(&bs, 0, sizeof(bs));
+    std::vector<lcc_job_out> jo((size_t)J);
+    for (auto &o : jo) {
+      std::memset(&o, 0, sizeof(o));
+      o.levels = 1;
+      o.obj.den = 1;
+    }
+    if (J == 0 || n1 == 0) {
+      for (int64_t j = 0; j < J; j++) fill_objective(0, lambdas[j].q, &jo[(size_t)j].obj);
+      if (jobs_out) std::copy(jo.begin(), jo.end(), jobs_out);
+      bs.levels = 1;
+      if (stats) *stats = bs;
+      return;
+    }
+    // the graph is validated once; every resolution checks its own bounds
+    GraphSummary s = summarize_graph(c, *g, nullptr, prm->validate != 0);
+    if (!s.ok) fail(LCC_ERR_INVALID_ARG, s.why);
+    for (int64_t j = 0; j < J; j++) {
+      std::string why;
+      if (overflow_bounds(s, lambdas[j].p, lambdas[j].q, &why) != LCC_OK)
+        fail(LCC_ERR_OVERFLOW, "lambda " + std::to_string(j) + ": " + why);
+    }
+    const bool wide = wide_weights(s);
+    // J copies packed block-diagonally (level 0 of the batch)
+    const lcc_graph gp = batch_replicate(c, *g, J, c.level_graph(0));
+    std::vector<int64_t> hstart((size_t)J + 1), vch;
+    for (int64_t j = 0; j <= J; j++) hstart[(size_t)j] = j * n1;
+    for (int64_t j = 0; j < J; j++)
+      for (int64_t b = j * n1; b < (j + 1) * n1; b += BATCH_CHUNK) {
+        vch.push_back(j);
+        vch.push_back(b);
+        vch.push_back(std::min<int64_t>(b + BATCH_CHUNK, (j + 1) * n1));
+      }
+    int64_t *d_start = c.buf<int64_t>("bt.start", (size_t)(J + 1));
+    int64_t *d_jp = c.buf<int64_t>("bt.jp", (size_t)J);
+    int64_t *d_jq = c.buf<int64_t>("bt.jq", (size_t)J);
+    uint8_t *d_cont = c.buf<uint8_t>("bt.cont", (size_t)J);
+    {
+      std::vector<int64_t> hp((size_t)J), hq((size_t)J);
       for (int64_t j = 0; j < J; j++) {
-        cont[(size_t)j] = 0;
-        if (!run[(size_t)j]) continue;
-        if (moved[(size_t)j] && l + 1 < prm->max_levels) {
-          cont[(size_t)j] = 1;
-          any = true;
-        } else {
-          top[(size_t)j] = l;
-          jo[(size_t)j].top_moved = moved[(size_t)j];
-        }
+        hp[(size_t)j] = lambdas[j].p;
+        hq[(size_t)j] = lambdas[j].q;
       }
-      if (!any) {
-        maxtop = l;
-        break;
-      }
-      h2d(c, d_cont, cont.data(), (size_t)J);
-      maps.push_back(c.buf<int32_t>("lv.map" + std::to_string(l), (size_t)(n > 0 ? n : 1)));
-      OwnedGraph &next = c.level_graph((size_t)l + 1);
-      // the next level's job of every vertex and job bases
-      jidl.push_back(c.buf<int32_t>("lv.jid" + std::to_string(l + 1), (size_t)(n > 0 ? n : 1)));
-      jbasel.push_back(c.buf<int64_t>("lv.jbase" + std::to_string(l + 1), (size_t)(J + 1)));
-      CompressJobs cj;
-      cj.jobs = J;
-      cj.jid = jidl[l];
-      cj.jcont = d_cont;
-      cj.jid_next = jidl[l + 1];
-      cj.jbase_next = jbasel[l + 1];
-      int64_t md = 0;
-      a = clk::now();
-      compress_graph(c, G[l], C, next, maps.back(), wide, &md, &cj);
-      ms_cp += std::chrono::duration<double, std::milli>(clk::now() - a).count();
-      G.push_back(next.view());
-      maxdeg.push_back(md);
-      run = cont;
+      h2d(c, d_start, hstart.data(), (size_t)(J + 1) * sizeof(int64_t));
+      h2d(c, d_jp, hp.data(), (size_t)J * sizeof(int64_t));
+      h2d(c, d_jq, hq.data(), (size_t)J * sizeof(int64_t));
+      c.sync();
     }
-    for (int l = maxtop - 1; l >= 0; l--) {
-      int32_t *C = Cl[l];
-      // jobs that stopped coarsening at this level keep their clustering (map < 0)
-      batch_flatten(c, G[l].n, maps[l], Cl[l + 1], jidl[l], jbasel[l], jbasel[l + 1], C);
-      if (prm->refine) {
-        bool any = false;
-        for (int64_t j = 0; j < J; j++) {
-          run[(size_t)j] = top[(size_t)j] > l;
-          any = any || run[(size_t)j];
-        }
-        if (!any) continue;
-        BatchLevel bl;
-        bl.jobs = J;
-        bl.jid = jidl[l];
-        bl.jbase = jbasel[l];
-        bl.jp = d_jp;
-        bl.jq = d_jq;
-        bl.active = run.data();
-        bl.iters = iters.data();
-        bl.moved_any = moved.data();
-        lcc_bm_stats st;
-        auto a = clk::now();
-        best_moves(c, G[l], 0, 1, *prm, l, 1, C, BMShape{maxdeg[l], !wide, false, false}, st, &bl);
-        ms_bm += std::chrono::duration<double, std::milli>(clk::now() - a).count();
-        bs.moves_total += st.moves;
-        bs.arcs_scanned_total += st.arcs_scanned;
-      }
-    }
-    // canonical labels over the packed graph, then made job-local
-    const int64_t n0 = g->n;
-    int32_t *glab = c.buf<int32_t>("bt.glab", (size_t)n0);
-    const int64_t total = canonical_labels(c, n0, Cl[0], glab);
-    batch_local_labels(c, glab, jidl[0], d_start, n0, labels_out);
-    std::vector<int32_t> first = batch_first_labels(c, glab, d_start, J);
-    // clusters of job j are the global labels [first_j, first of the next non-empty job)
-    int64_t nxt = total;
-    for (int64_t j = J - 1; j >= 0; j--) {
-      if (first[(size_t)j] < 0) continue;
-      jo[(size_t)j].clusters = nxt - first[(size_t)j];
-      nxt = first[(size_t)j];
-    }
-    for (int64_t j = 0; j < J; j++) jo[(size_t)j].levels = top[(size_t)j] + 1;
-    if (jobs_out) {
-      int64_t *K = c.buf<int64_t>("bt.K", (size_t)n0);
-      int64_t *KK = c.buf<int64_t>("bt.KK", (size_t)n0);
-      cluster_sums_k_kk(c, *g, glab, K, KK);
-      std::vector<int64_t> cch;
-      for (int64_t j = 0; j < J; j++) {
-        if (first[(size_t)j] < 0) continue;
-        const int64_t xb = first[(size_t)j], xe = xb + jo[(size_t)j].clusters;
-        for (int64_t x = xb; x < xe; x += BATCH_CHUNK) {
-          cch.push_back(j);
-          cch.push_back(x);
-          cch.push_back(std::min<int64_t>(x + BATCH_CHUNK, xe));
-        }
-      }
-      std::vector<i128> intra, self, pairs;
-      batch_objective_parts(c, *g, glab, vch, K, KK, cch, intra, self, pairs);
-      std::vector<i128> w2((size_t)J, 0), ss((size_t)J, 0), pp((size_t)J, 0);
-      for (size_t i = 0; i < vch.size() / 3; i++) {
-        w2[(size_t)vch[3 * i]] += intra[i];
-        ss[(size_t)vch[3 * i]] += self[i];
-      }
-      for (size_t i = 0; i < cch.size() / 3; i++) pp[(size_t)cch[3 * i]] += pairs[i];
-      for (int64_t j = 0; j < J; j++) {
-        const size_t u = (size_t)j;
-        const i128 N = (i128)lambdas[j].q * (ss[u] + w2[u] / 2) - (i128)lambdas[j].p * (pp[u] / 2);
-        fill_objective(N, lambdas[j].q, &jo[u].obj);
-      }
-    }
-    c.sync();
-    if (c.timing) c.collect_timing();
-    bs.ms_best_move = ms_bm;
-    bs.ms_compress = ms_cp;
+    batch_levels(c, &gp, J, hstart, vch, d_start, d_jp, d_jq, d_cont, lambdas, prm, s, wide, labels_out,
+                 jobs_out != nullptr, jo, bs, n1);
     bs.ms_total = std::chrono::duration<double, std::milli>(clk::now() - t0).count();
     if (jobs_out) std::copy(jo.begin(), jo.end(), jobs_out);
     if (stats) *stats = bs;

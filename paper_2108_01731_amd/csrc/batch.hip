@@ -292,4 +292,71 @@ void batch_objective_parts(Ctx &c, const lcc_graph &g, const int32_t *C, const s
   }
 }
 
+// ------------------------------------------------------------- replication
+
+// off[j*n1 + v] = j*arcs1 + off1[v] for the J copies, and off[J*n1] = J*arcs1.
+__global__ void k_rep_off(const int64_t *__restrict__ off1, int64_t n1, int64_t arcs1, int64_t J,
+                          int64_t *__restrict__ off) {
+  const int64_t total = J * n1;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= total; i += (int64_t)gridDim.x * blockDim.x) {
+    if (i == total) {
+      off[i] = J * arcs1;
+    } else {
+      const int64_t j = i / n1;
+      off[i] = j * arcs1 + off1[i - j * n1];
+    }
+  }
+}
+
+// col[j*arcs1 + e] = col1[e] + j*n1.
+__global__ void k_rep_col(const int32_t *__restrict__ col1, int64_t arcs1, int64_t n1, int64_t J,
+                          int32_t *__restrict__ col) {
+  const int64_t total = J * arcs1;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t j = i / arcs1;
+    col[i] = col1[i - j * arcs1] + (int32_t)(j * n1);
+  }
+}
+
+lcc_graph batch_replicate(Ctx &c, const lcc_graph &g1, int64_t J, OwnedGraph &out) {
+  const int64_t n1 = g1.n, a1 = g1.arcs, n = J * n1, arcs = J * a1;
+  out.n = n;
+  out.arcs = arcs;
+  out.wt_kind = g1.wt_kind;
+  out.off.ensure((size_t)(n + 1) * sizeof(int64_t));
+  out.col.ensure((size_t)(arcs > 0 ? arcs : 1) * sizeof(int32_t));
+  const unsigned grid_v = (unsigned)std::min<int64_t>(std::max<int64_t>(1, cdiv(n + 1, BT_NT)), 65536);
+  const unsigned grid_a = (unsigned)std::min<int64_t>(std::max<int64_t>(1, cdiv(arcs, BT_NT)), 65536);
+  if (n1 > 0) {
+    hipLaunchKernelGGL(k_rep_off, dim3(grid_v), dim3(BT_NT), 0, c.stream, g1.off, n1, a1, J, out.off.as<int64_t>());
+    LAUNCHCHECK();
+  } else {
+    HIPCHECK(hipMemsetAsync(out.off.p, 0, sizeof(int64_t), c.stream));
+  }
+  if (arcs > 0) {
+    hipLaunchKernelGGL(k_rep_col, dim3(grid_a), dim3(BT_NT), 0, c.stream, g1.col, a1, n1, J, out.col.as<int32_t>());
+    LAUNCHCHECK();
+  }
+  lcc_graph g;
+  std::memset(&g, 0, sizeof(g));
+  g.n = n;
+  g.arcs = arcs;
+  g.off = out.off.as<int64_t>();
+  g.col = out.col.as<int32_t>();
+  g.wt_kind = g1.wt_kind;
+  const size_t wb = (size_t)wt_bytes(g1.wt_kind);
+  auto copies = [&](DevBuf &dst, const void *src, size_t each) {
+    dst.ensure(each * (size_t)J);
+    for (int64_t j = 0; j < J && each > 0; j++)
+      HIPCHECK(hipMemcpyAsync(static_cast<char *>(dst.p) + (size_t)j * each, src, each, hipMemcpyDeviceToDevice,
+                              c.stream));
+    return dst.p;
+  };
+  if (g1.wt_kind != LCC_WT_UNIT) g.wt = copies(out.wt, g1.wt, (size_t)a1 * wb);
+  g.k = static_cast<const int64_t *>(copies(out.k, g1.k, (size_t)n1 * sizeof(int64_t)));
+  if (g1.s) g.s = static_cast<const int64_t *>(copies(out.s, g1.s, (size_t)n1 * sizeof(int64_t)));
+  if (g1.kk) g.kk = static_cast<const int64_t *>(copies(out.kk, g1.kk, (size_t)n1 * sizeof(int64_t)));
+  return g;
+}
+
 }  // namespace lcc

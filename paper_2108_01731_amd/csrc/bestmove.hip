@@ -36,7 +36,7 @@ constexpr int BM_NT = 256;
 constexpr int WIDE_NT = 1024;
 constexpr int NBINS = 8;
 constexpr int NSPREAD = 8;   // counter copies per launch (spreads same-address atomics)
-constexpr int NCTR = 4;      // movers, candidates, arcs of movers, capacity errors
+constexpr int NCTR = 6;      // movers, candidates, arcs of movers, capacity errors, shared rows, their arcs
 constexpr int32_t ISO_ID = INT32_MAX;  // ranks after every real cluster id
 constexpr int MID_SLOTS = 4096;        // table of the block-per-vertex bin (degree < 2048)
 
@@ -210,23 +210,24 @@ __device__ __forceinline__ int32_t decide(int64_t best_s, int32_t best_id, int64
 
 // Block-wide sum of the counters; one atomic per counter per block, spread
 // over NSPREAD copies.
-template <int NT>
-__device__ __forceinline__ void flush_counters(int64_t *ctr, int64_t movers, int64_t cands, int64_t marcs) {
-  __shared__ int64_t red[3][NT / WAVE];
-  movers = wave_sum(movers);
-  cands = wave_sum(cands);
-  marcs = wave_sum(marcs);
+template <int NT, int NV = 3>
+__device__ __forceinline__ void flush_counters(int64_t *ctr, int64_t movers, int64_t cands, int64_t marcs,
+                                               int64_t rows = 0, int64_t row_arcs = 0) {
+  __shared__ int64_t red[NV][NT / WAVE];
+  int64_t x[5] = {movers, cands, marcs, rows, row_arcs};
   const int w = threadIdx.x / WAVE;
-  if (lane_id() == 0) {
-    red[0][w] = movers;
-    red[1][w] = cands;
-    red[2][w] = marcs;
+#pragma unroll
+  for (int k = 0; k < NV; k++) {
+    const int64_t t = wave_sum(x[k]);
+    if (lane_id() == 0) red[k][w] = t;
   }
   __syncthreads();
-  if (threadIdx.x < 3) {
+  if (threadIdx.x < NV) {
     int64_t s = 0;
     for (int i = 0; i < NT / WAVE; i++) s += red[threadIdx.x][i];
-    if (s) atomic_add_i64(&ctr[(blockIdx.x % NSPREAD) * NCTR + threadIdx.x], s);
+    // counters 0-2, then (NV = 5) 4-5: slot 3 holds capacity errors
+    const int slot = threadIdx.x < 3 ? threadIdx.x : threadIdx.x + 1;
+    if (s) atomic_add_i64(&ctr[(blockIdx.x % NSPREAD) * NCTR + slot], s);
   }
 }
 
@@ -506,6 +507,222 @@ __global__ __launch_bounds__(NT) void k_bm_wide(AggArgs a) {
   }
   flush_counters<NT>(a.ctr, movers, cands, marcs);
 }
+
+// ------------------------------------- lambda sweep: shared level-0 rows
+
+// A sweep runs up to SH_MAXJ clusterings of one graph (one per lambda) as a
+// batch whose jobs are identical copies: job j owns vertices [j*n1, (j+1)*n1)
+// and its rows are job 0's rows shifted by j*n1.  For rows of degree < 256 one
+// launch serves every job: the block takes a vertex v, wave j aggregates job
+// j's row of v, and the cluster ids of neighbor u for all jobs sit in one
+// 64-byte line C16[u][0..15], so the 16 waves share each row read and each
+// neighbor's line (fetched once into L1, hit by the other waves).  Decisions
+// equal those of the per-job kernels: same table, same scores, same order.
+constexpr int SH_MAXJ = 16;
+constexpr int SH_BIN_HI = 4;   // bins 0..SH_BIN_HI (degree <= 255) share rows
+constexpr int SH_SLOTS = 512;  // per-wave table: pow2 >= 2 (255 + 1)
+
+// C16[v][j] = C[j*n1 + v] for j < J, -1 beyond: one thread per vertex writes
+// its 64-byte line (reads of each job's C are coalesced across the wave).
+__global__ void k_sh_transpose(const int32_t *__restrict__ C, int64_t n1, int32_t J, int32_t *__restrict__ C16) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n1; v += (int64_t)gridDim.x * blockDim.x) {
+    int32_t x[SH_MAXJ];
+#pragma unroll
+    for (int j = 0; j < SH_MAXJ; j++) x[j] = j < J ? C[(int64_t)j * n1 + v] : -1;
+    int4 *line = reinterpret_cast<int4 *>(C16 + v * SH_MAXJ);
+#pragma unroll
+    for (int q = 0; q < SH_MAXJ / 4; q++) line[q] = make_int4(x[4 * q], x[4 * q + 1], x[4 * q + 2], x[4 * q + 3]);
+  }
+}
+
+// From the sub-round's buckets b0 .. b1-1 (packed ids j*n1 + v): mask[v] |=
+// 1 << j, and every v whose mask was empty is appended to one of NSPREAD
+// list segments (segment k = blocks with blockIdx % NSPREAD == k, capacity n1
+// each, count in seg_cnt[k]), one atomic per block and step.  The list order
+// varies from run to run; nothing downstream depends on it.
+__global__ __launch_bounds__(BM_NT) void k_sh_mask(const int32_t *__restrict__ list0,
+                                                   const int64_t *__restrict__ dstart, int32_t b0, int32_t b1,
+                                                   int64_t n1, uint32_t *__restrict__ mask,
+                                                   int32_t *__restrict__ seglist, int64_t *__restrict__ seg_cnt) {
+  __shared__ int32_t wcnt[BM_NT / WAVE];
+  __shared__ int64_t bbase;
+  const int64_t lo = dstart[b0], hi = dstart[b1];
+  const int seg = blockIdx.x % NSPREAD, wv = threadIdx.x / WAVE;
+  int32_t *out = seglist + (int64_t)seg * n1;
+  for (int64_t base = lo + (int64_t)blockIdx.x * BM_NT; base < hi; base += (int64_t)gridDim.x * BM_NT) {
+    const int64_t i = base + threadIdx.x;
+    bool first = false;
+    int32_t v = 0;
+    if (i < hi) {
+      const int32_t vp = list0[i];
+      const int32_t j = (int32_t)(vp / n1);
+      v = (int32_t)(vp - (int64_t)j * n1);
+      first = atomicOr(&mask[v], 1u << j) == 0;
+    }
+    const uint64_t m = __ballot(first);
+    if (lane_id() == 0) wcnt[wv] = (int32_t)__popcll(m);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int32_t tot = 0;
+      for (int w = 0; w < BM_NT / WAVE; w++) tot += wcnt[w];
+      bbase = tot ? (int64_t)atomicAdd(reinterpret_cast<unsigned long long *>(&seg_cnt[seg]),
+                                       (unsigned long long)tot)
+                  : 0;
+    }
+    __syncthreads();
+    if (first) {
+      int64_t pos = bbase + __popcll(m & __lanemask_lt());
+      for (int w = 0; w < wv; w++) pos += wcnt[w];
+      out[pos] = v;
+    }
+    __syncthreads();  // wcnt and bbase are reused by the next step
+  }
+}
+
+// The id of job j (wave-uniform) among the 16 ids of a neighbor's line.
+__device__ __forceinline__ int32_t pick16(const int4 &a, const int4 &b, const int4 &c, const int4 &d, int j) {
+  const int4 q = j < 8 ? (j < 4 ? a : b) : (j < 12 ? c : d);
+  const int r = j & 3;
+  return r == 0 ? q.x : r == 1 ? q.y : r == 2 ? q.z : q.w;
+}
+
+// One wave per listed vertex (SH_WPB waves per block, each on its own
+// vertex and its own table).  The wave loads the row (from job 0, the first
+// n1 vertices) and every neighbor's line of 16 ids once, into registers, then
+// runs the jobs of the vertex's mask one after another: insert, score against
+// job j's C, K and cnt, decide, mark job j's frontier.  The scoring scan
+// resets each slot it reads, so the table is clean for the next job without a
+// clearing pass.  The vertex's mask is cleared for the next sub-round.
+constexpr int SH_WPB = BM_NT / WAVE;
+
+template <int WK, bool A32>
+__global__ __launch_bounds__(BM_NT) void k_bm_shared(AggArgs a, const int32_t *__restrict__ C16, int64_t n1,
+                                                     uint32_t *__restrict__ mask, const int32_t *__restrict__ seglist,
+                                                     const int64_t *__restrict__ seg_cnt) {
+  using Acc = typename std::conditional<A32, int32_t, int64_t>::type;
+  __shared__ int32_t hk[SH_WPB * SH_SLOTS];
+  __shared__ Acc hv[SH_WPB * SH_SLOTS];
+  const int wv = threadIdx.x / WAVE, gl = lane_id();
+  int32_t *keys = hk + wv * SH_SLOTS;
+  Acc *vals = hv + wv * SH_SLOTS;
+  for (int s = gl; s < SH_SLOTS; s += WAVE) {
+    keys[s] = -1;
+    vals[s] = 0;
+  }
+  __builtin_amdgcn_wave_barrier();
+  int64_t total = 0;
+  for (int k = 0; k < NSPREAD; k++) total += seg_cnt[k];
+  int64_t c_movers = 0, c_cands = 0, c_marcs = 0, c_rows = 0, c_rarcs = 0;
+  for (int64_t vi = (int64_t)blockIdx.x * SH_WPB + wv; vi < total; vi += (int64_t)gridDim.x * SH_WPB) {
+    int k = 0;
+    int64_t r = vi;
+    while (r >= seg_cnt[k]) r -= seg_cnt[k++];  // vi < total: ends at a segment below NSPREAD
+    const int32_t v = seglist[(int64_t)k * n1 + r];
+    const uint32_t m = mask[v];
+    __builtin_amdgcn_wave_barrier();
+    if (gl == 0) mask[v] = 0;
+    const int64_t beg = a.off[v], end = a.off[v + 1];
+    const uint32_t H = pow2_at_least(2 * (end - beg + 1));
+    const int64_t kv = a.k[v];
+    int32_t u[4];
+    int64_t w[4];
+    int4 q0[4], q1[4], q2[4], q3[4];
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+      const int64_t e = beg + gl + i * WAVE;
+      u[i] = e < end ? a.col[e] : -1;
+      w[i] = e < end ? load_w<WK>(a.wt, e) : 0;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+      if (u[i] >= 0) {
+        const int4 *line = reinterpret_cast<const int4 *>(C16 + (int64_t)u[i] * SH_MAXJ);
+        q0[i] = line[0];
+        q1[i] = line[1];
+        q2[i] = line[2];
+        q3[i] = line[3];
+      } else {
+        q0[i] = q1[i] = q2[i] = q3[i] = make_int4(-1, -1, -1, -1);
+      }
+    }
+    // lane j < 16 fetches job j's cluster of v (from v's own line), its
+    // total and its size: one round trip for all jobs
+    int32_t cj = 0, cntj = 0;
+    int64_t Kj = 0;
+    if (gl < SH_MAXJ && ((m >> gl) & 1u)) {
+      cj = C16[(int64_t)v * SH_MAXJ + gl];
+      Kj = a.K[cj];
+      cntj = a.cnt[cj];
+    }
+    for (uint32_t mm = m; mm; mm &= mm - 1) {
+      const int j = __ffs((int)mm) - 1;
+      const int64_t vp = (int64_t)j * n1 + v;
+      const int32_t c = __shfl(cj, j, WAVE);
+      const int64_t Kc = __shfl(Kj, j, WAVE);
+      const int32_t cntc = __shfl(cntj, j, WAVE);
+      if (gl == 0) lds_insert<Acc>(keys, vals, H, c, 0);
+#pragma unroll
+      for (int i = 0; i < 4; i++)
+        if (u[i] >= 0) lds_insert<Acc>(keys, vals, H, pick16(q0[i], q1[i], q2[i], q3[i], j), w[i]);
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      const int64_t lp = a.jv.jp[j], lq = a.jv.jq[j];
+      const int64_t pk = lp * kv;
+      int64_t best_s = INT64_MIN, wc = 0;
+      int32_t best_id = ISO_ID;
+      for (uint32_t s = gl; s < H; s += WAVE) {
+        const int32_t X = keys[s];
+        if (X < 0) continue;
+        const int64_t wx = (int64_t)vals[s];
+        keys[s] = -1;
+        vals[s] = 0;
+        c_cands++;
+        if (X == c) {
+          wc = wx;
+        } else {
+          const int64_t sc = lq * wx - pk * a.K[X];
+          if (better(sc, X, best_s, best_id)) {
+            best_s = sc;
+            best_id = X;
+          }
+        }
+      }
+#pragma unroll
+      for (int o = WAVE / 2; o > 0; o >>= 1) {
+        const int64_t os = __shfl_xor(best_s, o, WAVE);
+        const int32_t oid = __shfl_xor(best_id, o, WAVE);
+        if (better(os, oid, best_s, best_id)) {
+          best_s = os;
+          best_id = oid;
+        }
+        wc += __shfl_xor(wc, o, WAVE);
+      }
+      const int64_t stay = lq * wc - pk * (Kc - kv);
+      const int32_t d = decide(best_s, best_id, stay, a.allow_iso && cntc >= 2, c);
+      if (gl == 0) a.D[vp] = d;
+      if (d != c) {
+        if (a.next_flag) {
+          const int64_t jb = (int64_t)j * n1;
+#pragma unroll
+          for (int i = 0; i < 4; i++)
+            if (u[i] >= 0) a.next_flag[jb + u[i]] = 1;
+        }
+        if (gl == 0) {
+          c_movers++;
+          c_marcs += end - beg;
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();  // the table is clean for the next job
+    }
+    if (gl == 0) {
+      c_rows++;
+      c_rarcs += end - beg;
+    }
+  }
+  flush_counters<BM_NT, 5>(a.ctr, c_movers, c_cands, c_marcs, c_rows, c_rarcs);
+}
+
 
 // ------------------------------------------------ first iteration, singletons
 
@@ -1410,6 +1627,26 @@ int64_t pow2_host(int64_t x) {
   return h;
 }
 
+template <int WK>
+void launch_shared_wk(Ctx &c, bool a32, const AggArgs &a, const int32_t *C16, int64_t n1, uint32_t *mask,
+                      const int32_t *seglist, const int64_t *seg_cnt, int64_t grid) {
+  if (a32)
+    c.launch(k_bm_shared<WK, true>, dim3((unsigned)grid), dim3(BM_NT), 0, a, C16, n1, mask, seglist, seg_cnt);
+  else
+    c.launch(k_bm_shared<WK, false>, dim3((unsigned)grid), dim3(BM_NT), 0, a, C16, n1, mask, seglist, seg_cnt);
+  LAUNCHCHECK();
+}
+
+void launch_shared(Ctx &c, int wk, bool a32, const AggArgs &a, const int32_t *C16, int64_t n1, uint32_t *mask,
+                   const int32_t *seglist, const int64_t *seg_cnt, int64_t grid) {
+  switch (wk) {
+    case LCC_WT_UNIT: launch_shared_wk<LCC_WT_UNIT>(c, a32, a, C16, n1, mask, seglist, seg_cnt, grid); break;
+    case LCC_WT_I16: launch_shared_wk<LCC_WT_I16>(c, a32, a, C16, n1, mask, seglist, seg_cnt, grid); break;
+    case LCC_WT_I32: launch_shared_wk<LCC_WT_I32>(c, a32, a, C16, n1, mask, seglist, seg_cnt, grid); break;
+    default: launch_shared_wk<LCC_WT_I64>(c, a32, a, C16, n1, mask, seglist, seg_cnt, grid); break;
+  }
+}
+
 // A small level's sub-round: one block per vertex, the degree bins below
 // 2048 in one launch (256 threads, MID_SLOTS table) and the wider bin in a
 // second one (WIDE_NT threads, table up to `slots`) when the level has such
@@ -1570,7 +1807,9 @@ void best_moves(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_para
   // (NB + 1), per-launch counters, per-sub-round isolations, next-frontier
   // size, pairing errors.
   const int64_t o_bcnt = 0, o_barcs = NB, o_start = 2 * NB, o_lctr = 3 * NB + 1;
-  const int64_t o_isoc = o_lctr + (int64_t)LC * NB, o_nact = o_isoc + S, o_err = o_nact + 1, IB = o_err + 1;
+  // (then NSPREAD list-segment counts per sub-round for the shared-row launch)
+  const int64_t o_isoc = o_lctr + (int64_t)LC * NB, o_nact = o_isoc + S, o_err = o_nact + 1, o_seg = o_err + 1,
+                IB = o_seg + (int64_t)NSPREAD * S;
   const int64_t part_grid = std::min<int64_t>(std::max<int64_t>(1, cdiv(n, BM_NT * 8)), (int64_t)c.num_cu * 8);
   int32_t *blkcnt = c.buf<int32_t>("bm.pblk", (size_t)(part_grid * NB));
   int64_t *pcur = c.buf<int64_t>("bm.pcur", (size_t)(part_grid * NB));
@@ -1639,6 +1878,19 @@ void best_moves(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_para
     bool narrow_rows = false;
     for (int b = 0; b < 6; b++) narrow_rows = narrow_rows || hist[b] > 0;
     const int64_t small_slots = std::min<int64_t>(pow2_host(2 * (shape.maxdeg + 1)), wslots);
+    // lambda sweeps: rows of degree < 256 read once for all jobs (see k_bm_shared)
+    bool shared_rows = false;
+    for (int b = 0; b <= SH_BIN_HI; b++) shared_rows = shared_rows || hist[b] > 0;
+    shared_rows = shared_rows && bl && bl->shared_n > 0 && !small && J >= 2 && J <= SH_MAXJ && J * bl->shared_n == n;
+    const int64_t n1 = shared_rows ? bl->shared_n : 0;
+    int32_t *C16 = nullptr, *seglist = nullptr;
+    uint32_t *shmask = nullptr;
+    if (shared_rows) {
+      C16 = c.buf<int32_t>("sh.C16", (size_t)(n1 * SH_MAXJ));
+      seglist = c.buf<int32_t>("sh.seglist", (size_t)(n1 * NSPREAD));
+      shmask = c.buf<uint32_t>("sh.mask", (size_t)n1);
+      HIPCHECK(hipMemsetAsync(shmask, 0, (size_t)n1 * sizeof(uint32_t), c.stream));
+    }
     const int32_t NI = std::max<int32_t>(prm.num_iter, 1);
     int64_t *ctrs = c.buf<int64_t>("bm.ctrs", (size_t)(NI * IB));
     HIPCHECK(hipMemsetAsync(ctrs, 0, (size_t)(NI * IB) * sizeof(int64_t), c.stream));
@@ -1655,6 +1907,7 @@ void best_moves(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_para
       size_t idx;
       int32_t it, bi, nb;
       bool single;
+      int32_t shared_s = -1;  // sub-round of a shared-row launch
     };
     std::vector<Timed> timed;
     std::vector<int64_t> h((size_t)(NI * IB));
@@ -1704,8 +1957,38 @@ void best_moves(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_para
               if (c.timing) timed.push_back({pidx, it, bi, a.nbuckets, single});
             }
           }
+          const bool sh_now = shared_rows && !single;
+          if (sh_now) {
+            const int32_t b0 = s * NBINS, b1 = s * NBINS + SH_BIN_HI + 1;
+            {
+              Ctx::Timer tm(&c, "bm_shared_transpose", 8.0 * (double)n, (double)n, true);
+              c.launch(k_sh_transpose, dim3((unsigned)std::min<int64_t>(cdiv(n1, 256), 65536)), dim3(256), 0,
+                       (const int32_t *)C, n1, (int32_t)J, C16);
+              LAUNCHCHECK();
+            }
+            {
+              Ctx::Timer tm(&c, "bm_shared_mask", 0.0, 0.0, true);
+              c.launch(k_sh_mask, dim3((unsigned)std::min<int64_t>(cdiv(n, BM_NT), (int64_t)c.num_cu * 8)),
+                       dim3(BM_NT), 0, (const int32_t *)blist, (const int64_t *)(blk + o_start), b0, b1, n1, shmask,
+                       seglist, blk + o_seg + (int64_t)NSPREAD * s);
+              LAUNCHCHECK();
+            }
+            const int bi = s * NBINS;
+            const AggArgs a = agg_args(bi, blk + o_start, blk + o_lctr);
+            const size_t pidx = c.pending.size();
+            {
+              Ctx::Timer tm(&c, (std::string("bm_aggregate_shared") + wk_tag[g.wt_kind]).c_str(), 0.0, 0.0, true);
+              launch_shared(c, g.wt_kind, acc32, a, C16, n1, shmask, seglist, blk + o_seg + (int64_t)NSPREAD * s,
+                            std::min<int64_t>(cdiv(n1, SH_WPB), (int64_t)c.num_cu * 8));
+            }
+            if (c.timing) {
+              Timed t{pidx, it, bi, SH_BIN_HI + 1, false};
+              t.shared_s = s;
+              timed.push_back(t);
+            }
+          }
           for (int b = 0; b < NBINS && !small; b++) {
-            if (!hist[b]) continue;
+            if (!hist[b] || (sh_now && b <= SH_BIN_HI)) continue;
             const int bi = s * NBINS + b;
             const AggArgs a = agg_args(bi, blk + o_start, blk + o_lctr);
             const size_t pidx = c.pending.size();
@@ -1774,8 +2057,16 @@ void best_moves(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_para
         }
         const double per_arc = t.single ? 12.0 + wb : 8.0 + wb;
         // candidates gather K (8 B each); movers store one flag per neighbor
-        c.pending[t.idx].bytes = cntb * 48.0 + arcs * per_arc + 8.0 * (double)launch_sums(hb + o_lctr, t.bi, 1) +
-                                 (double)launch_sums(hb + o_lctr, t.bi, 2);
+        const double extra = 8.0 * (double)launch_sums(hb + o_lctr, t.bi, 1) + (double)launch_sums(hb + o_lctr, t.bi, 2);
+        if (t.shared_s >= 0) {
+          // per listed vertex: list, mask, offsets, k (32 B); per row arc,
+          // once for all jobs: col, weight, the 64-byte id line; per (vertex,
+          // job): C, K and size of its cluster, D (20 B)
+          const double uv = (double)launch_sums(hb + o_lctr, t.bi, 4), ua = (double)launch_sums(hb + o_lctr, t.bi, 5);
+          c.pending[t.idx].bytes = uv * 32.0 + ua * (4.0 + wb + 4.0 * SH_MAXJ) + cntb * 20.0 + extra;
+        } else {
+          c.pending[t.idx].bytes = cntb * 48.0 + arcs * per_arc + extra;
+        }
         c.pending[t.idx].items = arcs;
       }
     }

@@ -52,6 +52,10 @@ struct BatchLevel {
   const uint8_t *active = nullptr; // host, per job: takes part in this Best-Moves call
   int32_t *iters = nullptr;        // host out, per job: iterations started
   uint8_t *moved_any = nullptr;    // host out, per job
+  // > 0: the jobs are identical copies of one graph of shared_n vertices (job
+  // j owns [j * shared_n, (j + 1) * shared_n), rows shifted by j * shared_n),
+  // so rows of low degree are read once for all jobs (at most 16 jobs)
+  int64_t shared_n = 0;
 };
 
 // Best-Moves on graph g from clustering C (device, updated in place).  On
@@ -116,6 +120,10 @@ std::vector<uint64_t> batch_vertex_sums(Ctx &c, const lcc_graph &g, const int64_
 // map[v] >= 0 (a job's ids move from its coarser range to its range here).
 void batch_flatten(Ctx &c, int64_t n, const int32_t *map, const int32_t *Cnext, const int32_t *jid,
                    const int64_t *jbase, const int64_t *jbase_next, int32_t *C);
+
+// J copies of g1 packed block-diagonally into `out` (job j: vertices
+// shifted by j * g1.n, arcs by j * g1.arcs); returns the packed graph's view.
+lcc_graph batch_replicate(Ctx &c, const lcc_graph &g1, int64_t J, OwnedGraph &out);
 
 // labels[v] = glab[v] - glab[first vertex of v's job].
 void batch_local_labels(Ctx &c, const int32_t *glab, const int32_t *jid, const int64_t *jstart, int64_t n,

@@ -101,7 +101,7 @@ class _KernelStat(ctypes.Structure):
 EXPORTS = (
     "lcc_params_default", "lcc_last_error", "lcc_ctx_create", "lcc_ctx_destroy", "lcc_best_move", "lcc_compress",
     "lcc_graph_owned_view", "lcc_graph_owned_free", "lcc_objective", "lcc_cluster", "lcc_cluster_batch",
-    "lcc_ctx_kernel_stats", "lcc_ctx_reset_kernel_stats",
+    "lcc_sweep", "lcc_ctx_kernel_stats", "lcc_ctx_reset_kernel_stats",
 )
 
 _lib = None
@@ -142,6 +142,9 @@ def load_library(path: str = LIB_PATH):
     lib.lcc_cluster_batch.argtypes = [P, gp, i64, ctypes.POINTER(i64), ctypes.POINTER(_Lambda),
                                       ctypes.POINTER(_Params), P, ctypes.POINTER(_JobOut),
                                       ctypes.POINTER(_BatchStats), P]
+    lib.lcc_sweep.restype = st
+    lib.lcc_sweep.argtypes = [P, gp, i64, ctypes.POINTER(_Lambda), ctypes.POINTER(_Params), P,
+                              ctypes.POINTER(_JobOut), ctypes.POINTER(_BatchStats), P]
     lib.lcc_ctx_kernel_stats.restype = st
     lib.lcc_ctx_kernel_stats.argtypes = [P, ctypes.POINTER(_KernelStat), i32, ctypes.POINTER(i32)]
     lib.lcc_ctx_reset_kernel_stats.restype = st
@@ -375,6 +378,36 @@ def lcc_cluster(ctx: Context, g: DeviceGraph, p: int, q: int, params: Params, st
     return lab, _num(o), stats
 
 
+SWEEP_MAX = 16
+
+
+def _batch_results(outs, bs, J):
+    jobs = [{"N": _num(outs[j].obj), "clusters": outs[j].clusters, "levels": outs[j].levels,
+             "top_moved": outs[j].top_moved} for j in range(J)]
+    L = bs.levels
+    stats = {"levels": L, "n_level": list(bs.n_level[:L]), "arcs_level": list(bs.arcs_level[:L]),
+             "moves_total": bs.moves_total, "arcs_scanned_total": bs.arcs_scanned_total,
+             "ms_best_move": bs.ms_best_move, "ms_compress": bs.ms_compress, "ms_total": bs.ms_total}
+    return jobs, stats
+
+
+def lcc_sweep(ctx: Context, g: DeviceGraph, lambdas, params: Params, stream=None):
+    """Parallel-CC of one graph under up to 16 resolutions (p, q) at once;
+    resolution j gives exactly lcc_cluster(g, *lambdas[j]).  Returns (labels
+    int32 tensor of shape [len(lambdas), n], per-resolution list of dicts
+    {N, clusters, levels, top_moved}, batch stats)."""
+    J = len(lambdas)
+    lams = (_Lambda * max(J, 1))(*[_lam(int(p), int(q)) for p, q in lambdas])
+    outs = (_JobOut * max(J, 1))()
+    bs = _BatchStats()
+    lab = torch.empty((J, g.n), dtype=torch.int32, device=g.off.device)
+    cg, cp = g._c(), params._c()
+    _check(_lib.lcc_sweep(ctx._h, ctypes.byref(cg), J, lams, ctypes.byref(cp),
+                          lab.data_ptr() if lab.numel() else None, outs, ctypes.byref(bs), _stream_ptr(stream)))
+    jobs, stats = _batch_results(outs, bs, J)
+    return lab, jobs, stats
+
+
 def lcc_cluster_batch(ctx: Context, g: DeviceGraph, job_start, lambdas, params: Params, stream=None):
     """Parallel-CC on jobs packed block-diagonally in g (job j owns vertices
     [job_start[j], job_start[j+1])), each with its own (p, q).  Returns
@@ -392,10 +425,5 @@ def lcc_cluster_batch(ctx: Context, g: DeviceGraph, job_start, lambdas, params: 
     _check(_lib.lcc_cluster_batch(ctx._h, ctypes.byref(cg), J, starts, lams, ctypes.byref(cp),
                                   lab.data_ptr() if lab.numel() else None, outs, ctypes.byref(bs),
                                   _stream_ptr(stream)))
-    jobs = [{"N": _num(outs[j].obj), "clusters": outs[j].clusters, "levels": outs[j].levels,
-             "top_moved": outs[j].top_moved} for j in range(J)]
-    L = bs.levels
-    stats = {"levels": L, "n_level": list(bs.n_level[:L]), "arcs_level": list(bs.arcs_level[:L]),
-             "moves_total": bs.moves_total, "arcs_scanned_total": bs.arcs_scanned_total,
-             "ms_best_move": bs.ms_best_move, "ms_compress": bs.ms_compress, "ms_total": bs.ms_total}
+    jobs, stats = _batch_results(outs, bs, J)
     return lab, jobs, stats
