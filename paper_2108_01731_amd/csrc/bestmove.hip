@@ -1219,13 +1219,12 @@ __global__ void k_fresh_relabel(int32_t *__restrict__ C, int64_t n, const int32_
 constexpr int RN_NT = 1024;
 constexpr int64_t RN_SMALL = 16384;
 
-__global__ __launch_bounds__(RN_NT) void k_rename_small(int32_t *__restrict__ C, int64_t n, int64_t *__restrict__ K,
-                                                        int32_t *__restrict__ cnt, int32_t *__restrict__ rank_f,
-                                                        int32_t *__restrict__ rank_e, int32_t *__restrict__ elist,
-                                                        int32_t *__restrict__ newid, JobView jv,
-                                                        int64_t *__restrict__ err, const int64_t *__restrict__ isoc,
-                                                        int S) {
-  if (no_isolation(isoc, S)) return;
+// One block of RN_NT threads (the caller checks that someone isolated).
+__device__ __forceinline__ void rename_small_body(int32_t *__restrict__ C, int64_t n, int64_t *__restrict__ K,
+                                                  int32_t *__restrict__ cnt, int32_t *__restrict__ rank_f,
+                                                  int32_t *__restrict__ rank_e, int32_t *__restrict__ elist,
+                                                  int32_t *__restrict__ newid, const JobView &jv,
+                                                  int64_t *__restrict__ err) {
   int32_t carry_f = 0, carry_e = 0;
   for (int64_t x0 = 0; x0 < n; x0 += RN_NT) {
     const int64_t x = x0 + threadIdx.x;
@@ -1274,6 +1273,16 @@ __global__ __launch_bounds__(RN_NT) void k_rename_small(int32_t *__restrict__ C,
     const int32_t c = C[v];
     if (c >= n) C[v] = newid[c - n];
   }
+}
+
+__global__ __launch_bounds__(RN_NT) void k_rename_small(int32_t *__restrict__ C, int64_t n, int64_t *__restrict__ K,
+                                                        int32_t *__restrict__ cnt, int32_t *__restrict__ rank_f,
+                                                        int32_t *__restrict__ rank_e, int32_t *__restrict__ elist,
+                                                        int32_t *__restrict__ newid, JobView jv,
+                                                        int64_t *__restrict__ err, const int64_t *__restrict__ isoc,
+                                                        int S) {
+  if (no_isolation(isoc, S)) return;
+  rename_small_body(C, n, K, cnt, rank_f, rank_e, elist, newid, jv, err);
 }
 
 // Per-job termination of a device-driven iteration: a running job counts the
@@ -1371,13 +1380,13 @@ __global__ __launch_bounds__(BM_NT) void k_part_count(const int32_t *__restrict_
 constexpr int PS_NT = 1024;
 constexpr int64_t SMALL_LEVEL = 8192;
 
-__global__ __launch_bounds__(PS_NT) void k_part_small(const int32_t *__restrict__ list, int64_t na0,
-                                                      const int64_t *__restrict__ na_dev,
-                                                      const int64_t *__restrict__ off, uint64_t h, int32_t S,
-                                                      int64_t wide_max, JobView jv, uint16_t *__restrict__ bucket_of,
-                                                      int64_t *__restrict__ bcnt, int64_t *__restrict__ barcs,
-                                                      int64_t *__restrict__ dstart, int32_t *__restrict__ out) {
-  extern __shared__ int64_t sm[];
+// One block of PS_NT threads; sm holds 2 * S * NBINS int64.
+__device__ __forceinline__ void part_small_body(const int32_t *__restrict__ list, int64_t na0,
+                                                const int64_t *__restrict__ na_dev, const int64_t *__restrict__ off,
+                                                uint64_t h, int32_t S, int64_t wide_max, const JobView &jv,
+                                                uint16_t *__restrict__ bucket_of, int64_t *__restrict__ bcnt,
+                                                int64_t *__restrict__ barcs, int64_t *__restrict__ dstart,
+                                                int32_t *__restrict__ out, int64_t *sm) {
   const int NB = S * NBINS;
   int64_t *lc = sm;       // members, then cursor
   int64_t *la = sm + NB;  // arcs
@@ -1421,6 +1430,72 @@ __global__ __launch_bounds__(PS_NT) void k_part_small(const int32_t *__restrict_
     if (b == NOBUCKET) continue;
     const int64_t pos = (int64_t)atomicAdd(reinterpret_cast<unsigned long long *>(&lc[b]), 1ull);
     out[pos] = list ? list[i] : (int32_t)i;
+  }
+}
+
+__global__ __launch_bounds__(PS_NT) void k_part_small(const int32_t *__restrict__ list, int64_t na0,
+                                                      const int64_t *__restrict__ na_dev,
+                                                      const int64_t *__restrict__ off, uint64_t h, int32_t S,
+                                                      int64_t wide_max, JobView jv, uint16_t *__restrict__ bucket_of,
+                                                      int64_t *__restrict__ bcnt, int64_t *__restrict__ barcs,
+                                                      int64_t *__restrict__ dstart, int32_t *__restrict__ out) {
+  extern __shared__ int64_t sm[];
+  part_small_body(list, na0, na_dev, off, h, S, wide_max, jv, bucket_of, bcnt, barcs, dstart, out, sm);
+}
+
+// The end of a small level's iteration in one block: the next frontier
+// (compaction of the flags), the renaming of fresh clusters (when someone
+// isolated), per-job termination in batches, then the partition of the next
+// iteration (when there is one) into that iteration's counter block.
+struct IterEndSmall {
+  // frontier
+  uint8_t *next;
+  int32_t *active;
+  int64_t *nact;
+  int32_t compact;
+  // renaming
+  int32_t *C;
+  int64_t *K;
+  int32_t *cnt;
+  int32_t *rank_f, *rank_e, *elist, *newid;
+  int64_t *err;
+  const int64_t *isoc;
+  // batches
+  int32_t *jiters;
+  uint8_t *jmoved_any;
+  int64_t jobs;
+  // next partition
+  int32_t part;
+  const int64_t *off;
+  uint64_t h_next;
+  int64_t wide_max;
+  uint16_t *bucket_of;
+  int64_t *bcnt, *barcs, *dstart;
+  int32_t *blist;
+};
+
+__global__ __launch_bounds__(PS_NT) void k_iter_end_small(IterEndSmall e, int64_t n, int32_t S, JobView jv) {
+  extern __shared__ int64_t sm[];
+  if (e.compact) compact_small_body(e.next, n, e.active, e.nact, 1);
+  if (!no_isolation(e.isoc, S)) {
+    __syncthreads();
+    rename_small_body(e.C, n, e.K, e.cnt, e.rank_f, e.rank_e, e.elist, e.newid, jv, e.err);
+  }
+  if (e.jobs > 0) {
+    uint8_t *jrun = const_cast<uint8_t *>(jv.jrun);
+    for (int64_t j = threadIdx.x; j < e.jobs; j += PS_NT) {
+      if (jrun[j]) {
+        e.jiters[j]++;
+        if (jv.jmoved[j]) e.jmoved_any[j] = 1;
+        else jrun[j] = 0;
+      }
+      jv.jmoved[j] = 0;
+    }
+  }
+  if (e.part) {
+    __syncthreads();  // the active list, its count and the running flags are complete
+    part_small_body(e.compact ? e.active : nullptr, n, e.compact ? e.nact : nullptr, e.off, e.h_next, S, e.wide_max,
+                    jv, e.bucket_of, e.bcnt, e.barcs, e.dstart, e.blist, sm);
   }
 }
 
@@ -1891,6 +1966,14 @@ void best_moves(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_para
       shmask = c.buf<uint32_t>("sh.mask", (size_t)n1);
       HIPCHECK(hipMemsetAsync(shmask, 0, (size_t)n1 * sizeof(uint32_t), c.stream));
     }
+    // renaming buffers of the small-level iteration end (as rename_fresh's)
+    int32_t *rn_rank_f = nullptr, *rn_rank_e = nullptr, *rn_elist = nullptr, *rn_newid = nullptr;
+    if (small) {
+      rn_rank_f = c.buf<int32_t>("rn.rankf", nn + 1);
+      rn_rank_e = c.buf<int32_t>("rn.ranke", nn + 1);
+      rn_elist = c.buf<int32_t>("rn.elist", nn);
+      rn_newid = c.buf<int32_t>("rn.newid", nn);
+    }
     const int32_t NI = std::max<int32_t>(prm.num_iter, 1);
     int64_t *ctrs = c.buf<int64_t>("bm.ctrs", (size_t)(NI * IB));
     HIPCHECK(hipMemsetAsync(ctrs, 0, (size_t)(NI * IB) * sizeof(int64_t), c.stream));
@@ -1923,9 +2006,12 @@ void best_moves(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_para
         const int32_t *list = all ? nullptr : active;
         const int64_t *na_dev = all ? nullptr : blk - IB + o_nact;
         if (small) {
-          hipLaunchKernelGGL(k_part_small, dim3(1), dim3(PS_NT), part_smem, c.stream, list, n, na_dev, g.off, hh, S,
-                             wide_max, jv, bucket_of, blk + o_bcnt, blk + o_barcs, blk + o_start, blist);
-          LAUNCHCHECK();
+          // later iterations were partitioned at the end of the previous one
+          if (it == 0) {
+            hipLaunchKernelGGL(k_part_small, dim3(1), dim3(PS_NT), part_smem, c.stream, list, n, na_dev, g.off, hh, S,
+                               wide_max, jv, bucket_of, blk + o_bcnt, blk + o_barcs, blk + o_start, blist);
+            LAUNCHCHECK();
+          }
         } else {
           hipLaunchKernelGGL(k_part_count, dim3((unsigned)part_grid), dim3(BM_NT), part_smem, c.stream, list, n,
                              na_dev, g.off, hh, S, wide_max, jv, bucket_of, blkcnt, blk + o_bcnt, blk + o_barcs);
@@ -2006,12 +2092,48 @@ void best_moves(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_para
             LAUNCHCHECK();
           }
         }
-        if (nbr) compact_flags(c, next, n, active, blk + o_nact, true, "bm.cmp");
-        rename_fresh(c, n, C, K, cnt, blk + o_err, jv, blk + o_isoc, S);
-        if (bl) {
-          hipLaunchKernelGGL(k_job_update, dim3((unsigned)std::min<int64_t>(cdiv(J, 256), 1024)), dim3(256), 0,
-                             c.stream, const_cast<uint8_t *>(jv.jrun), jv.jmoved, jiters, jmoved_any, J);
+        if (small) {
+          IterEndSmall e;
+          std::memset(&e, 0, sizeof(e));
+          e.next = next;
+          e.active = active;
+          e.nact = blk + o_nact;
+          e.compact = nbr;
+          e.C = C;
+          e.K = K;
+          e.cnt = cnt;
+          e.rank_f = rn_rank_f;
+          e.rank_e = rn_rank_e;
+          e.elist = rn_elist;
+          e.newid = rn_newid;
+          e.err = blk + o_err;
+          e.isoc = blk + o_isoc;
+          e.jiters = jiters;
+          e.jmoved_any = jmoved_any;
+          e.jobs = bl ? J : 0;
+          e.part = it + 1 < prm.num_iter;
+          if (e.part) {
+            int64_t *nb = blk + IB;  // the next iteration's counter block
+            e.off = g.off;
+            e.h_next = round_hash(prm.seed, level, phase, it + 1);
+            e.wide_max = wide_max;
+            e.bucket_of = bucket_of;
+            e.bcnt = nb + o_bcnt;
+            e.barcs = nb + o_barcs;
+            e.dstart = nb + o_start;
+            e.blist = blist;
+          }
+          Ctx::Timer tm(&c, "bm_iter_end_small", 0.0, (double)n, true);
+          c.launch(k_iter_end_small, dim3(1), dim3(PS_NT), part_smem, e, n, (int32_t)S, jv);
           LAUNCHCHECK();
+        } else {
+          if (nbr) compact_flags(c, next, n, active, blk + o_nact, true, "bm.cmp");
+          rename_fresh(c, n, C, K, cnt, blk + o_err, jv, blk + o_isoc, S);
+          if (bl) {
+            hipLaunchKernelGGL(k_job_update, dim3((unsigned)std::min<int64_t>(cdiv(J, 256), 1024)), dim3(256), 0,
+                               c.stream, const_cast<uint8_t *>(jv.jrun), jv.jmoved, jiters, jmoved_any, J);
+            LAUNCHCHECK();
+          }
         }
       }
       queued = last;

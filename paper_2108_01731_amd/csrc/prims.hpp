@@ -195,9 +195,9 @@ static __global__ __launch_bounds__(CMP_NT) void k_flag_scatter(uint8_t *__restr
 constexpr int CMP_SMALL_NT = 1024;
 constexpr int64_t CMP_SMALL = 16384;
 
-static __global__ __launch_bounds__(CMP_SMALL_NT) void k_flag_compact_small(uint8_t *__restrict__ flags, int64_t n,
-                                                                            int32_t *__restrict__ list,
-                                                                            int64_t *__restrict__ count, int clear) {
+// One block of CMP_SMALL_NT threads: list <- ascending i with flags[i] != 0.
+__device__ __forceinline__ void compact_small_body(uint8_t *__restrict__ flags, int64_t n, int32_t *__restrict__ list,
+                                                   int64_t *__restrict__ count, int clear) {
   int64_t carry = 0;
   for (int64_t x0 = 0; x0 < n; x0 += CMP_SMALL_NT) {
     const int64_t x = x0 + threadIdx.x;
@@ -211,6 +211,12 @@ static __global__ __launch_bounds__(CMP_SMALL_NT) void k_flag_compact_small(uint
     carry += tot;
   }
   if (threadIdx.x == 0) *count = carry;
+}
+
+static __global__ __launch_bounds__(CMP_SMALL_NT) void k_flag_compact_small(uint8_t *__restrict__ flags, int64_t n,
+                                                                            int32_t *__restrict__ list,
+                                                                            int64_t *__restrict__ count, int clear) {
+  compact_small_body(flags, n, list, count, clear);
 }
 
 // list <- ascending indices i with flags[i] != 0; *count_dev <- their number.
