@@ -91,6 +91,16 @@ struct AggArgs {
   const int64_t *dstart;
   int32_t bucket;
   int32_t nbuckets;
+  // small levels keep two copies of (C, K, cnt): a sub-round reads one and
+  // applies its own moves to the other (Cw, Kw, cntw), into which it also
+  // replays the previous sub-round's moves (buckets rb0 .. rb1-1 of list;
+  // none when rb1 <= rb0).  Cw == nullptr: a separate apply kernel runs.
+  int32_t *Cw;
+  int64_t *Kw;
+  int32_t *cntw;
+  int64_t nlev;       // vertices of the level (fresh ids are nlev + v)
+  int64_t *iso_ctr;   // isolations of the sub-round
+  int32_t rb0, rb1;
 };
 
 // The launch's vertex list and count (host-given, or read from the bucket
@@ -116,6 +126,40 @@ __device__ __forceinline__ void job_lambda(const AggArgs &a, int32_t v, int64_t 
     job = 0;
     p = a.p;
     q = a.q;
+  }
+}
+
+// Applies v's move c -> d (d < 0: to the fresh id nlev + v) to the copy
+// (Cw, Kw, cntw); integer atomics, so the order of moves never matters.
+__device__ __forceinline__ void apply_to_copy(const AggArgs &a, int32_t v, int32_t c, int32_t d, int64_t kv) {
+  const int32_t t = d < 0 ? (int32_t)(a.nlev + v) : d;
+  if (kv) {
+    atomic_add_i64(&a.Kw[c], -kv);
+    atomic_add_i64(&a.Kw[t], kv);
+  }
+  atomicSub(&a.cntw[c], 1);
+  atomicAdd(&a.cntw[t], 1);
+  a.Cw[v] = t;
+}
+
+// A vertex's own move in the copy, counted (isolations, moved jobs).
+__device__ __forceinline__ void own_move(const AggArgs &a, int32_t v, int32_t c, int32_t d, int64_t kv,
+                                         int64_t &niso) {
+  apply_to_copy(a, v, c, d, kv);
+  if (d < 0) niso++;
+  if (a.jv.jid) a.jv.jmoved[a.jv.jid[v]] = 1;
+}
+
+// The previous sub-round's moves replayed into the copy (whole grid).  The
+// copy still holds those vertices' old clusters, so a decision that differs
+// from it is a move.
+template <int NT> __device__ __forceinline__ void replay_prev(const AggArgs &a) {
+  if (a.rb1 <= a.rb0) return;
+  const int64_t lo = a.dstart[a.rb0], hi = a.dstart[a.rb1];
+  for (int64_t i = lo + (int64_t)blockIdx.x * NT + threadIdx.x; i < hi; i += (int64_t)gridDim.x * NT) {
+    const int32_t v = a.list[i];
+    const int32_t d = a.D[v], c = a.Cw[v];
+    if (d != c) apply_to_copy(a, v, c, d, a.k[v]);
   }
 }
 
@@ -422,7 +466,8 @@ __global__ __launch_bounds__(NT) void k_bm_wide(AggArgs a) {
   work_of(a, list, count);
   if (t == 0) occ_n = 0;
   uint32_t clean = 0;  // slots [0, clean) hold no key (block-uniform)
-  int64_t movers = 0, marcs = 0, cands = 0;
+  int64_t movers = 0, marcs = 0, cands = 0, niso = 0;
+  if (a.Cw) replay_prev<NT>(a);
   for (int64_t vi = blockIdx.x; vi < count; vi += gridDim.x) {
     const int32_t v = list[vi];
     const int64_t beg = a.off[v], end = a.off[v + 1];
@@ -491,6 +536,7 @@ __global__ __launch_bounds__(NT) void k_bm_wide(AggArgs a) {
       if (d != c) {
         movers += 1;
         marcs += end - beg;
+        if (a.Cw) own_move(a, v, c, d, kv, niso);
       }
     }
     __syncthreads();
@@ -505,6 +551,7 @@ __global__ __launch_bounds__(NT) void k_bm_wide(AggArgs a) {
     __syncthreads();  // table, occ and sh_d are reused by the next vertex
     if (t == 0) occ_n = 0;
   }
+  if (t == 0 && niso) atomic_add_i64(a.iso_ctr, niso);
   flush_counters<NT>(a.ctr, movers, cands, marcs);
 }
 
@@ -740,7 +787,8 @@ __global__ __launch_bounds__(NT) void k_bm_single(AggArgs a) {
   const int32_t *list;
   int64_t count;
   work_of(a, list, count);
-  int64_t c_movers = 0, c_cands = 0, c_marcs = 0;
+  int64_t c_movers = 0, c_cands = 0, c_marcs = 0, c_iso = 0;  // (singletons never isolate)
+  if (a.Cw) replay_prev<NT>(a);
   for (int64_t g0 = (int64_t)blockIdx.x * GPB; g0 < count; g0 += (int64_t)gridDim.x * GPB) {
     const int64_t gi = g0 + grp;
     const bool valid = gi < count;
@@ -799,6 +847,7 @@ __global__ __launch_bounds__(NT) void k_bm_single(AggArgs a) {
     }
     const bool moved = valid && d != v;
     if (valid && gl == 0) a.D[v] = d;
+    if (moved && gl == 0 && a.Cw) own_move(a, v, v, d, kv, c_iso);
     if (moved && a.next_flag)
       for (int64_t e = beg + gl; e < end; e += G) a.next_flag[a.col[e]] = 1;
     c_movers += (moved && gl == 0) ? 1 : 0;
@@ -1443,11 +1492,37 @@ __global__ __launch_bounds__(PS_NT) void k_part_small(const int32_t *__restrict_
   part_small_body(list, na0, na_dev, off, h, S, wide_max, jv, bucket_of, bcnt, barcs, dstart, out, sm);
 }
 
+// The second copy of a small level's state: C2 = C (n), K2 = K, cnt2 = cnt
+// (2n: regular then fresh ids).
+__global__ void k_copy_state(const int32_t *__restrict__ C, const int64_t *__restrict__ K,
+                             const int32_t *__restrict__ cnt, int64_t n, int32_t *__restrict__ C2,
+                             int64_t *__restrict__ K2, int32_t *__restrict__ cnt2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) C2[i] = C[i];
+  if (i < 2 * n) {
+    K2[i] = K[i];
+    cnt2[i] = cnt[i];
+  }
+}
+
 // The end of a small level's iteration in one block: the next frontier
 // (compaction of the flags), the renaming of fresh clusters (when someone
 // isolated), per-job termination in batches, then the partition of the next
 // iteration (when there is one) into that iteration's counter block.
 struct IterEndSmall {
+  // the copy of (C, K, cnt) that missed the last sub-round's moves (its
+  // buckets rb0 .. rb1-1 of blist, decisions in D), brought up to date
+  const int32_t *D;
+  const int64_t *k;
+  const int64_t *dstart_cur;
+  int32_t rb0, rb1;
+  int32_t *Cl;
+  int64_t *Kl;
+  int32_t *cntl;
+  // the second copy, renamed like the first
+  int32_t *C2;
+  int64_t *K2;
+  int32_t *cnt2;
   // frontier
   uint8_t *next;
   int32_t *active;
@@ -1476,10 +1551,31 @@ struct IterEndSmall {
 
 __global__ __launch_bounds__(PS_NT) void k_iter_end_small(IterEndSmall e, int64_t n, int32_t S, JobView jv) {
   extern __shared__ int64_t sm[];
+  if (e.Cl) {
+    const int64_t lo = e.dstart_cur[e.rb0], hi = e.dstart_cur[e.rb1];
+    for (int64_t i = lo + threadIdx.x; i < hi; i += PS_NT) {
+      const int32_t v = e.blist[i];
+      const int32_t d = e.D[v], c = e.Cl[v];
+      if (d == c) continue;
+      const int32_t t = d < 0 ? (int32_t)(n + v) : d;
+      const int64_t kv = e.k[v];
+      if (kv) {
+        atomic_add_i64(&e.Kl[c], -kv);
+        atomic_add_i64(&e.Kl[t], kv);
+      }
+      atomicSub(&e.cntl[c], 1);
+      atomicAdd(&e.cntl[t], 1);
+      e.Cl[v] = t;
+    }
+  }
   if (e.compact) compact_small_body(e.next, n, e.active, e.nact, 1);
   if (!no_isolation(e.isoc, S)) {
-    __syncthreads();
+    __syncthreads();  // both copies are equal
     rename_small_body(e.C, n, e.K, e.cnt, e.rank_f, e.rank_e, e.elist, e.newid, jv, e.err);
+    if (e.C2) {
+      __syncthreads();  // the rank arrays are reused
+      rename_small_body(e.C2, n, e.K2, e.cnt2, e.rank_f, e.rank_e, e.elist, e.newid, jv, e.err);
+    }
   }
   if (e.jobs > 0) {
     uint8_t *jrun = const_cast<uint8_t *>(jv.jrun);
@@ -1938,8 +2034,11 @@ void best_moves(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_para
     // launch rate, not the work, sets the pace).  Larger levels: one launch
     // per degree bin present in the level.
     const bool small = n <= SMALL_LEVEL && shape.maxdeg <= wide_max;
+    // degree histogram of the level (larger levels launch one kernel per
+    // non-empty bin); a small level needs only the largest degree: its
+    // narrow launch (degree < 2048) always runs, empty or not
     int64_t hist[2 * NBINS] = {0};
-    {
+    if (!small) {
       int64_t *hist_d = c.buf<int64_t>("bm.hist", 2 * NBINS);
       HIPCHECK(hipMemsetAsync(hist_d, 0, 2 * NBINS * sizeof(int64_t), c.stream));
       hipLaunchKernelGGL(k_bin_hist, dim3((unsigned)std::min<int64_t>(cdiv(n, BM_NT), (int64_t)c.num_cu * 4)),
@@ -1949,8 +2048,8 @@ void best_moves(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_para
     }
     // tables of the small-level kernels: MID_SLOTS below degree 2048, else
     // room for the widest row of the level
-    const bool wide_rows = hist[6] > 0;
-    bool narrow_rows = false;
+    const bool wide_rows = small ? shape.maxdeg > bin_limit_fixed(5) : hist[6] > 0;
+    bool narrow_rows = small;
     for (int b = 0; b < 6; b++) narrow_rows = narrow_rows || hist[b] > 0;
     const int64_t small_slots = std::min<int64_t>(pow2_host(2 * (shape.maxdeg + 1)), wslots);
     // lambda sweeps: rows of degree < 256 read once for all jobs (see k_bm_shared)
@@ -1966,9 +2065,18 @@ void best_moves(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_para
       shmask = c.buf<uint32_t>("sh.mask", (size_t)n1);
       HIPCHECK(hipMemsetAsync(shmask, 0, (size_t)n1 * sizeof(uint32_t), c.stream));
     }
-    // renaming buffers of the small-level iteration end (as rename_fresh's)
+    // renaming buffers of the small-level iteration end (as rename_fresh's),
+    // and the second copy of the state (sub-rounds alternate between them)
     int32_t *rn_rank_f = nullptr, *rn_rank_e = nullptr, *rn_elist = nullptr, *rn_newid = nullptr;
+    int32_t *C2 = nullptr, *cnt2 = nullptr;
+    int64_t *K2 = nullptr;
     if (small) {
+      C2 = c.buf<int32_t>("bm.C2", nn);
+      K2 = c.buf<int64_t>("bm.K2", 2 * nn);
+      cnt2 = c.buf<int32_t>("bm.cnt2", 2 * nn);
+      hipLaunchKernelGGL(k_copy_state, dim3((unsigned)cdiv(2 * n, 1024)), dim3(1024), 0, c.stream,
+                         (const int32_t *)C, (const int64_t *)K, (const int32_t *)cnt, n, C2, K2, cnt2);
+      LAUNCHCHECK();
       rn_rank_f = c.buf<int32_t>("rn.rankf", nn + 1);
       rn_rank_e = c.buf<int32_t>("rn.ranke", nn + 1);
       rn_elist = c.buf<int32_t>("rn.elist", nn);
@@ -1994,7 +2102,9 @@ void best_moves(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_para
     };
     std::vector<Timed> timed;
     std::vector<int64_t> h((size_t)(NI * IB));
-    int32_t queued = 0, chunk = 1;
+    // (with the all-vertices rule an iteration past the end redoes all the
+    // work, so only the neighbor frontier queues ahead)
+    int32_t queued = 0, chunk = small && nbr ? std::max<int32_t>(1, c.small_iter_hint[phase & 1]) : 1;
     bool done = false;
     while (!done && queued < prm.num_iter) {
       const int32_t first = queued, last = std::min<int32_t>(prm.num_iter, queued + chunk);
@@ -2027,11 +2137,28 @@ void best_moves(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_para
           const bool single = it == 0 && s == 0 && identity && shape.simple;
           if (small) {
             // bins 0-5 (degree < 2048), then bin 6 if the level has wider rows
+            // sub-round s reads copy s % 2 and applies to the other, into
+            // which its first launch replays sub-round s - 1
+            const bool odd = s % 2 == 1;
+            bool replay = s > 0;
             for (int part = 0; part < 2; part++) {
               if (part == 0 ? !narrow_rows : !wide_rows) continue;
               const int bi = s * NBINS + (part ? 6 : 0);
               AggArgs a = agg_args(bi, blk + o_start, blk + o_lctr);
               a.nbuckets = part ? 1 : 6;
+              a.C = odd ? C2 : C;
+              a.K = odd ? K2 : K;
+              a.cnt = odd ? cnt2 : cnt;
+              a.Cw = odd ? C : C2;
+              a.Kw = odd ? K : K2;
+              a.cntw = odd ? cnt : cnt2;
+              a.nlev = n;
+              a.iso_ctr = blk + o_isoc + s;
+              if (replay) {
+                a.rb0 = (s - 1) * NBINS;
+                a.rb1 = s * NBINS;
+                replay = false;
+              }
               const size_t pidx = c.pending.size();
               {
                 Ctx::Timer tm(&c, (std::string(single ? "bm_single_small" : "bm_aggregate_small") +
@@ -2084,7 +2211,7 @@ void best_moves(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_para
             }
             if (c.timing) timed.push_back({pidx, it, bi, 1, single});
           }
-          {
+          if (!small) {
             Ctx::Timer tm(&c, "bm_apply", 0.0, 0.0, true);
             c.launch(k_bm_apply, dim3((unsigned)apply_grid), dim3(BM_NT), 0, (const int32_t *)blist, (int64_t)0,
                      (const int64_t *)(blk + o_start), (int32_t)(s * NBINS), (int32_t)((s + 1) * NBINS),
@@ -2095,6 +2222,21 @@ void best_moves(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_para
         if (small) {
           IterEndSmall e;
           std::memset(&e, 0, sizeof(e));
+          // the last sub-round S - 1 read copy (S - 1) % 2 and applied to the
+          // other, so copy (S - 1) % 2 lags by that sub-round's moves
+          const bool lag_first = (S - 1) % 2 == 0;
+          e.D = D;
+          e.k = g.k;
+          e.dstart_cur = blk + o_start;
+          e.rb0 = (S - 1) * NBINS;
+          e.rb1 = S * NBINS;
+          e.Cl = lag_first ? C : C2;
+          e.Kl = lag_first ? K : K2;
+          e.cntl = lag_first ? cnt : cnt2;
+          e.blist = blist;
+          e.C2 = C2;
+          e.K2 = K2;
+          e.cnt2 = cnt2;
           e.next = next;
           e.active = active;
           e.nact = blk + o_nact;
@@ -2121,7 +2263,6 @@ void best_moves(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_para
             e.bcnt = nb + o_bcnt;
             e.barcs = nb + o_barcs;
             e.dstart = nb + o_start;
-            e.blist = blist;
           }
           Ctx::Timer tm(&c, "bm_iter_end_small", 0.0, (double)n, true);
           c.launch(k_iter_end_small, dim3(1), dim3(PS_NT), part_smem, e, n, (int32_t)S, jv);
@@ -2192,6 +2333,7 @@ void best_moves(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_para
         c.pending[t.idx].items = arcs;
       }
     }
+    if (small && nbr) c.small_iter_hint[phase & 1] = st.iterations;
     if (bl) {
       d2h(c, bl->iters, jiters, (size_t)J * sizeof(int32_t));
       d2h(c, bl->moved_any, jmoved_any, (size_t)J);

@@ -121,6 +121,10 @@ struct Ctx {
   std::map<std::string, DevBuf> scratch;
   // pinned host mailbox for small device->host reads
   void *host_mail = nullptr;
+  // iterations the last small-level Best-Moves call of each phase ran: the
+  // next such call queues that many before its first read-back (a timing
+  // choice only; iterations past the end change nothing)
+  int32_t small_iter_hint[2] = {1, 1};
   // contracted graphs of the hierarchy levels, reused across calls
   std::vector<std::unique_ptr<OwnedGraph>> level_graphs;
 
