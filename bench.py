@@ -140,6 +140,8 @@ def main():
     traffic = measured_traffic(args.workload, dom_name)
     agg_ms = sum(v["ms"] for v in agg.values())
     agg_arcs = sum(v["items"] for v in agg.values())
+    log(f"last step: best-move {st['ms_best_move']:.1f} ms, compress {st['ms_compress']:.1f} ms, "
+        f"total {st['ms_total']:.1f} ms (host wall time)")
     log(f"step: {ms_per_step:.1f} ms; levels={st['levels']} clusters={st['clusters']} "
         f"objective={N / q:.4f} (modularity-scaled {N / q / (g.arcs / 2):.6f})")
 

@@ -437,6 +437,246 @@ void dispatch_ce(Ctx &c, const lcc_graph &g, const int32_t *map, int64_t *inter,
 
 }  // namespace
 
+// ---------------------------------------------- dense compress, small graphs
+
+// A graph of at most DN_MAX vertices (one clustering, no batch) contracts
+// through an n' x n' matrix: arc counts F (an entry with F > 0 is a coarse
+// arc, also when its weights sum to zero) and weight sums W (absent for unit
+// weights, where the count is the weight).  Rows come out in column order, as
+// the sorting path gives them.  Six launches and one read-back replace the
+// relabel scan, the key sort and the run sums, which cost far more than the
+// work on the coarse levels of a hierarchy.  info: n', coarse arcs, largest
+// coarse degree.
+constexpr int64_t DN_MAX = 2048;
+constexpr int DN_NT = 1024;
+
+// One block: present ids and their ranks (in LDS), n', map, and the
+// per-cluster sums of k, kk (k^2 when absent) and 2s (halved with the intra
+// weight later), each cleared first (n' + 1 entries: the sorting path's
+// extra slot stays zero).
+__global__ __launch_bounds__(DN_NT) void k_dn_relabel(const int32_t *__restrict__ C, int64_t n,
+                                                      const int64_t *__restrict__ k, const int64_t *__restrict__ kk,
+                                                      const int64_t *__restrict__ s, int32_t *__restrict__ map,
+                                                      int64_t *__restrict__ ok, int64_t *__restrict__ okk,
+                                                      int64_t *__restrict__ os2, int64_t *__restrict__ info) {
+  __shared__ int32_t pres[DN_MAX];
+  __shared__ int32_t rank[DN_MAX];
+  for (int64_t i = threadIdx.x; i < n; i += DN_NT) pres[i] = 0;
+  __syncthreads();
+  for (int64_t v = threadIdx.x; v < n; v += DN_NT) pres[C[v]] = 1;
+  __syncthreads();
+  int32_t carry = 0;
+  for (int64_t x0 = 0; x0 < n; x0 += DN_NT) {
+    const int64_t x = x0 + threadIdx.x;
+    int32_t tot;
+    const int32_t r = carry + block_excl_scan<int32_t, DN_NT>(x < n ? pres[x] : 0, &tot);
+    if (x < n) rank[x] = r;
+    carry += tot;
+  }
+  const int64_t n2 = carry;
+  for (int64_t x = threadIdx.x; x <= n2; x += DN_NT) {
+    ok[x] = 0;
+    okk[x] = 0;
+    os2[x] = 0;
+  }
+  __syncthreads();
+  for (int64_t v = threadIdx.x; v < n; v += DN_NT) {
+    const int32_t m = rank[C[v]];
+    map[v] = m;
+    const int64_t kv = k[v];
+    atomic_add_i64(&ok[m], kv);
+    atomic_add_i64(&okk[m], kk ? kk[v] : kv * kv);
+    if (s && s[v]) atomic_add_i64(&os2[m], 2 * s[v]);
+  }
+  if (threadIdx.x == 0) info[0] = n2;
+}
+
+__global__ void k_dn_clear(uint32_t *__restrict__ F, int64_t *__restrict__ W, const int64_t *__restrict__ info) {
+  const int64_t n2 = info[0], total = n2 * n2;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    F[i] = 0;
+    if (W) W[i] = 0;
+  }
+}
+
+// G lanes per vertex: inter arcs counted (and weighed) into row map[v] of the
+// matrix, intra weight added to the cluster's 2s'.
+template <int G, int WK>
+__global__ __launch_bounds__(CP_NT) void k_dn_scatter(const int64_t *__restrict__ off, const int32_t *__restrict__ col,
+                                                      const void *__restrict__ wt, const int32_t *__restrict__ map,
+                                                      int64_t n, const int64_t *__restrict__ info,
+                                                      uint32_t *__restrict__ F, int64_t *__restrict__ W,
+                                                      int64_t *__restrict__ os2) {
+  const int gl = threadIdx.x % G;
+  const int64_t v = (int64_t)blockIdx.x * (CP_NT / G) + threadIdx.x / G;
+  const int64_t n2 = info[0];
+  int64_t wi = 0;
+  int32_t mv = 0;
+  if (v < n) {
+    mv = map[v];
+    for (int64_t e = off[v] + gl; e < off[v + 1]; e += G) {
+      const int32_t mu = map[col[e]];
+      const int64_t w = load_w<WK>(wt, e);
+      if (mu != mv) {
+        const int64_t idx = (int64_t)mv * n2 + mu;
+        atomicAdd(&F[idx], 1u);
+        if constexpr (WK != LCC_WT_UNIT) atomic_add_i64(&W[idx], w);
+      } else {
+        wi += w;
+      }
+    }
+  }
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) wi += __shfl_xor(wi, o, WAVE);
+  if (v < n && gl == 0 && wi) atomic_add_i64(&os2[mv], wi);
+}
+
+// One block per coarse row: its number of coarse arcs.
+__global__ __launch_bounds__(CP_NT) void k_dn_rowcount(const uint32_t *__restrict__ F, const int64_t *__restrict__ info,
+                                                       int64_t *__restrict__ rowcnt) {
+  const int64_t n2 = info[0], r = blockIdx.x;
+  if (r >= n2) return;
+  int64_t c = 0;
+  for (int64_t j = threadIdx.x; j < n2; j += CP_NT) c += F[r * n2 + j] != 0;
+  int64_t tot;
+  block_excl_scan<int64_t, CP_NT>(c, &tot);
+  if (threadIdx.x == 0) rowcnt[r] = tot;
+}
+
+// One block: row offsets (off[n'] = coarse arcs), the largest row, and s' =
+// (sum of 2s + intra weight) / 2.
+__global__ __launch_bounds__(DN_NT) void k_dn_finish(const int64_t *__restrict__ rowcnt, int64_t *__restrict__ off,
+                                                     int64_t *__restrict__ os2, int64_t *__restrict__ info) {
+  const int64_t n2 = info[0];
+  int64_t carry = 0, mx = 0;
+  for (int64_t r0 = 0; r0 < n2; r0 += DN_NT) {
+    const int64_t r = r0 + threadIdx.x;
+    const int64_t c = r < n2 ? rowcnt[r] : 0;
+    mx = c > mx ? c : mx;
+    int64_t tot;
+    const int64_t pre = carry + block_excl_scan<int64_t, DN_NT>(c, &tot);
+    if (r < n2) off[r] = pre;
+    carry += tot;
+  }
+  for (int64_t x = threadIdx.x; x < n2; x += DN_NT) os2[x] /= 2;
+  __shared__ int64_t red[DN_NT / WAVE];
+#pragma unroll
+  for (int o = WAVE / 2; o > 0; o >>= 1) {
+    const int64_t y = __shfl_xor(mx, o, WAVE);
+    mx = y > mx ? y : mx;
+  }
+  if (lane_id() == 0) red[threadIdx.x / WAVE] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < DN_NT / WAVE; i++) mx = red[i] > mx ? red[i] : mx;
+    off[n2] = carry;
+    info[1] = carry;
+    info[2] = mx;
+  }
+}
+
+// One block per coarse row: its arcs in column order.
+template <class WOut>
+__global__ __launch_bounds__(CP_NT) void k_dn_emit(const uint32_t *__restrict__ F, const int64_t *__restrict__ W,
+                                                   const int64_t *__restrict__ info, const int64_t *__restrict__ off,
+                                                   int32_t *__restrict__ ocol, WOut *__restrict__ owt) {
+  const int64_t n2 = info[0], r = blockIdx.x;
+  if (r >= n2) return;
+  int64_t pos = off[r];
+  for (int64_t j0 = 0; j0 < n2; j0 += CP_NT) {
+    const int64_t j = j0 + threadIdx.x;
+    const uint32_t f = j < n2 ? F[r * n2 + j] : 0;
+    int64_t tot;
+    const int64_t at = pos + block_excl_scan<int64_t, CP_NT>(f != 0, &tot);
+    if (f) {
+      ocol[at] = (int32_t)j;
+      owt[at] = (WOut)(W ? W[r * n2 + j] : (int64_t)f);
+    }
+    pos += tot;
+  }
+}
+
+namespace {
+
+template <int G>
+void launch_dn_scatter(Ctx &c, const lcc_graph &g, const int32_t *map, const int64_t *info, uint32_t *F, int64_t *W,
+                       int64_t *os2) {
+  const dim3 gr((unsigned)cdiv(g.n, CP_NT / G));
+  switch (g.wt_kind) {
+    case LCC_WT_UNIT:
+      hipLaunchKernelGGL((k_dn_scatter<G, LCC_WT_UNIT>), gr, dim3(CP_NT), 0, c.stream, g.off, g.col, g.wt, map, g.n,
+                         info, F, W, os2);
+      break;
+    case LCC_WT_I16:
+      hipLaunchKernelGGL((k_dn_scatter<G, LCC_WT_I16>), gr, dim3(CP_NT), 0, c.stream, g.off, g.col, g.wt, map, g.n,
+                         info, F, W, os2);
+      break;
+    case LCC_WT_I32:
+      hipLaunchKernelGGL((k_dn_scatter<G, LCC_WT_I32>), gr, dim3(CP_NT), 0, c.stream, g.off, g.col, g.wt, map, g.n,
+                         info, F, W, os2);
+      break;
+    default:
+      hipLaunchKernelGGL((k_dn_scatter<G, LCC_WT_I64>), gr, dim3(CP_NT), 0, c.stream, g.off, g.col, g.wt, map, g.n,
+                         info, F, W, os2);
+      break;
+  }
+  LAUNCHCHECK();
+}
+
+void compress_dense(Ctx &c, const lcc_graph &g, const int32_t *C, OwnedGraph &out, int32_t *map, bool wide,
+                    int64_t *maxdeg_out) {
+  const int64_t n = g.n;
+  const size_t nn = (size_t)n;
+  const bool weighted = g.wt_kind != LCC_WT_UNIT;
+  Ctx::Timer tm(&c, "cp_dense", 40.0 * (double)n + (8.0 + wt_bytes(g.wt_kind)) * (double)g.arcs, (double)g.arcs);
+  // capacities from host-known bounds: n' <= n, coarse arcs <= min(arcs, n^2)
+  const int64_t ub = std::max<int64_t>(1, std::min<int64_t>(g.arcs, n * n));
+  out.off.ensure((nn + 1) * sizeof(int64_t));
+  out.col.ensure((size_t)ub * sizeof(int32_t));
+  out.wt.ensure((size_t)ub * (wide ? 8 : 4));
+  out.k.ensure((nn + 1) * sizeof(int64_t));
+  out.s.ensure((nn + 1) * sizeof(int64_t));
+  out.kk.ensure((nn + 1) * sizeof(int64_t));
+  int64_t *info = c.buf<int64_t>("dn.info", 4);
+  uint32_t *F = c.buf<uint32_t>("dn.F", nn * nn);
+  int64_t *W = weighted ? c.buf<int64_t>("dn.W", nn * nn) : nullptr;
+  int64_t *rowcnt = c.buf<int64_t>("dn.rowcnt", nn);
+  int64_t *os2 = out.s.as<int64_t>();
+  hipLaunchKernelGGL(k_dn_relabel, dim3(1), dim3(DN_NT), 0, c.stream, C, n, g.k, g.kk, g.s, map, out.k.as<int64_t>(),
+                     out.kk.as<int64_t>(), os2, info);
+  LAUNCHCHECK();
+  hipLaunchKernelGGL(k_dn_clear, dim3(grid_for(n * n)), dim3(256), 0, c.stream, F, W, (const int64_t *)info);
+  LAUNCHCHECK();
+  switch (lanes_for(g)) {
+    case 8: launch_dn_scatter<8>(c, g, map, info, F, W, os2); break;
+    case 16: launch_dn_scatter<16>(c, g, map, info, F, W, os2); break;
+    case 32: launch_dn_scatter<32>(c, g, map, info, F, W, os2); break;
+    default: launch_dn_scatter<64>(c, g, map, info, F, W, os2); break;
+  }
+  hipLaunchKernelGGL(k_dn_rowcount, dim3((unsigned)n), dim3(CP_NT), 0, c.stream, (const uint32_t *)F,
+                     (const int64_t *)info, rowcnt);
+  LAUNCHCHECK();
+  hipLaunchKernelGGL(k_dn_finish, dim3(1), dim3(DN_NT), 0, c.stream, (const int64_t *)rowcnt, out.off.as<int64_t>(),
+                     os2, info);
+  LAUNCHCHECK();
+  if (wide)
+    hipLaunchKernelGGL((k_dn_emit<int64_t>), dim3((unsigned)n), dim3(CP_NT), 0, c.stream, (const uint32_t *)F,
+                       (const int64_t *)W, (const int64_t *)info, (const int64_t *)out.off.as<int64_t>(),
+                       out.col.as<int32_t>(), out.wt.as<int64_t>());
+  else
+    hipLaunchKernelGGL((k_dn_emit<int32_t>), dim3((unsigned)n), dim3(CP_NT), 0, c.stream, (const uint32_t *)F,
+                       (const int64_t *)W, (const int64_t *)info, (const int64_t *)out.off.as<int64_t>(),
+                       out.col.as<int32_t>(), out.wt.as<int32_t>());
+  LAUNCHCHECK();
+  int64_t h[3] = {0, 0, 0};
+  d2h(c, h, info, sizeof(h));
+  out.n = h[0];
+  out.arcs = h[1];
+  if (maxdeg_out) *maxdeg_out = h[2];
+}
+
+}  // namespace
+
 void compress_graph(Ctx &c, const lcc_graph &g, const int32_t *C, OwnedGraph &out, int32_t *map, bool wide,
                     int64_t *maxdeg_out, const CompressJobs *cj) {
   const int32_t *jid = cj ? cj->jid : nullptr;
@@ -449,6 +689,10 @@ void compress_graph(Ctx &c, const lcc_graph &g, const int32_t *C, OwnedGraph &ou
     out.off.ensure(sizeof(int64_t));
     HIPCHECK(hipMemsetAsync(out.off.p, 0, sizeof(int64_t), c.stream));
     if (maxdeg_out) *maxdeg_out = 0;
+    return;
+  }
+  if (!cj && n <= DN_MAX) {
+    compress_dense(c, g, C, out, map, wide, maxdeg_out);
     return;
   }
   const size_t nn = (size_t)n;

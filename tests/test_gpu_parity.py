@@ -136,6 +136,40 @@ def test_compress_parity(ctx, idx):
         assert np.array_equal(go2.s, gd2.s.cpu().numpy())
 
 
+def assert_same_graph(go, gd):
+    assert gd.n == go.n and gd.arcs == len(go.col)
+    assert np.array_equal(go.off, gd.off.cpu().numpy())
+    assert np.array_equal(go.col, gd.col.cpu().numpy())
+    assert np.array_equal(go.wt, gd.wt.cpu().numpy().astype(np.int64))
+    assert np.array_equal(go.k, gd.k.cpu().numpy())
+    assert np.array_equal(go.s, gd.s.cpu().numpy())
+    assert np.array_equal(go.kk, gd.kk.cpu().numpy())
+
+
+@pytest.mark.parametrize("kind", ["unit", "i16", "i32", "i64"])
+def test_compress_parity_small_graphs(ctx, kind):
+    """Graphs of at most 2048 vertices contract through the dense path; every
+    output array equals the oracle's, zero-sum coarse edges included (weights
+    in [-3, 3] cancel), and so does a second level on the device's output
+    (self weights and kk present)."""
+    rng = np.random.default_rng(7)
+    for n, m, seed in [(2, 1, 2), (37, 60, 3), (300, 2000, 4), (1500, 40000, 5), (2048, 9000, 6)]:
+        h = G.random_signed(n, m, seed, wmin=-3, wmax=3, kmax=4, unit=kind == "unit")
+        if kind != "unit":
+            h = H.with_weights(h, kind, seed=seed, lo=-3, hi=3)
+        for C0 in [np.zeros(n), np.arange(n), rng.integers(0, max(1, n // 7), size=n), rng.integers(0, n, size=n)]:
+            C0 = C0.astype(np.int32)
+            go, mo = O.compress(H.to_oracle(h), C0)
+            gd, md = L.lcc_compress(ctx, dev(h), torch.from_numpy(C0).cuda())
+            assert np.array_equal(mo, md.cpu().numpy()), (n, kind)
+            assert_same_graph(go, gd)
+            C1 = rng.integers(0, max(1, go.n // 3), size=go.n).astype(np.int32)
+            go2, mo2 = O.compress(go, C1)
+            gd2, md2 = L.lcc_compress(ctx, gd, torch.from_numpy(C1).cuda())
+            assert np.array_equal(mo2, md2.cpu().numpy())
+            assert_same_graph(go2, gd2)
+
+
 @pytest.mark.parametrize("idx", range(8))
 def test_objective_parity(ctx, idx):
     name, h, p, q = cases()[idx]
