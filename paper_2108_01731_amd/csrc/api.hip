@@ -191,24 +191,36 @@ __global__ __launch_bounds__(VA_NT) void k_validate_vertices(const int64_t *__re
   }
 }
 
-// Per-arc checks (one wave per vertex): column range, self-loops, sum |w|.
+// Per-arc checks: column range, self-loops, ascending rows, sum |w|.  A
+// block takes VA_NT consecutive vertices at a time (offsets already checked
+// by the vertex pass), stages their offsets in LDS and walks their arcs
+// coalesced, finding each arc's row by binary search in LDS.
 template <int WK>
 __global__ __launch_bounds__(VA_NT) void k_validate_arcs(const int64_t *__restrict__ off,
                                                          const int32_t *__restrict__ col, const void *__restrict__ wt,
                                                          int64_t n, int check, uint64_t *__restrict__ part) {
   __shared__ uint64_t red[3][VA_NT / WAVE];
+  __shared__ int64_t so[VA_NT + 1];
   uint64_t err = 0, wabs = 0, neg = 0;
   const int lane = lane_id();
-  const int64_t wave = ((int64_t)blockIdx.x * VA_NT + threadIdx.x) / WAVE;
-  const int64_t nwaves = ((int64_t)gridDim.x * VA_NT) / WAVE;
-  for (int64_t v = wave; v < n; v += nwaves) {
-    const int64_t b = off[v + 1];
-    for (int64_t e = off[v] + lane; e < b; e += WAVE) {
+  for (int64_t vb = (int64_t)blockIdx.x * VA_NT; vb < n; vb += (int64_t)gridDim.x * VA_NT) {
+    const int nv = (int)(vb + VA_NT < n ? VA_NT : n - vb);
+    __syncthreads();  // so is reused
+    for (int i = threadIdx.x; i <= nv; i += VA_NT) so[i] = off[vb + i];
+    __syncthreads();
+    const int64_t eb = so[0], ee = so[nv];
+    for (int64_t e = eb + threadIdx.x; e < ee; e += VA_NT) {
       if (check) {
+        int lo = 0, hi = nv - 1;  // the row: last r with so[r] <= e
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (so[mid] <= e) lo = mid;
+          else hi = mid - 1;
+        }
         const int32_t u = col[e];
         if (u < 0 || (int64_t)u >= n) err |= E_COL;
-        if ((int64_t)u == v) err |= E_SELF;
-        if (e > off[v] && u <= col[e - 1]) err |= F_UNSORTED;
+        if ((int64_t)u == vb + lo) err |= E_SELF;
+        if (e > so[lo] && u <= col[e - 1]) err |= F_UNSORTED;
       }
       const int64_t w = load_w<WK>(wt, e);
       if (w < 0) {

@@ -65,3 +65,27 @@ def shuffle_rows(h, seed=0):
         if wt is not None:
             wt[a:b] = wt[p]
     return G.HostGraph(h.off, col, h.k, wt=wt, s=h.s, kk=h.kk, wt_kind=h.wt_kind)
+
+
+def split_arcs(h, every: int = 3):
+    """The same graph with every `every`-th edge stored as two parallel arcs
+    in both rows (weights w1 and w - w1, w1 fixed by the vertex pair), so rows
+    repeat a neighbor and are no longer strictly ascending."""
+    h = h.numpy()
+    n = len(h.off) - 1
+    wt = np.ones(len(h.col), np.int64) if h.wt is None else np.asarray(h.wt).astype(np.int64)
+    off, col, w = [0], [], []
+    for v in range(n):
+        for e in range(h.off[v], h.off[v + 1]):
+            u = int(h.col[e])
+            key = min(u, v) * n + max(u, v)
+            if key % every == 0:
+                w1 = key % 5 - 2
+                col += [u, u]
+                w += [w1, int(wt[e]) - w1]
+            else:
+                col.append(u)
+                w.append(int(wt[e]))
+        off.append(len(col))
+    return G.HostGraph(np.array(off, np.int64), np.array(col, np.int32), h.k, wt=np.array(w, np.int64),
+                       s=h.s, kk=h.kk, wt_kind="i64")

@@ -212,6 +212,21 @@ def test_determinism_and_row_order_invariance(ctx):
         assert torch.equal(lab, runs[0][0]) and N == runs[0][1]
 
 
+def test_repeated_neighbors_equal_merged_arcs(ctx):
+    """Parallel arcs (rows repeating a neighbor, so the validation pass must
+    report them as not strictly ascending) cluster exactly like the merged
+    graph, and like the oracle on the same arcs."""
+    h = H.with_weights(G.random_signed(400, 2500, 11), "i64", seed=4, lo=-2, hi=6)
+    hs = H.split_arcs(h)
+    assert hs.arcs > h.arcs
+    for cfg in [dict(), dict(S=2, refine=0)]:
+        lo, No, _ = O.cluster(H.to_oracle(hs), 1, 30, oparams(**cfg))
+        ls, Ns, _ = L.lcc_cluster(ctx, dev(hs), 1, 30, dparams(**cfg))
+        lm, Nm, _ = L.lcc_cluster(ctx, dev(h), 1, 30, dparams(**cfg))
+        assert np.array_equal(lo, ls.cpu().numpy()) and No == Ns
+        assert torch.equal(ls, lm) and Ns == Nm
+
+
 def test_tiny_and_degenerate_graphs(ctx):
     cases_ = [
         G.HostGraph(np.zeros(1, np.int64), np.zeros(0, np.int32), np.zeros(0, np.int64)),  # empty

@@ -484,3 +484,18 @@ def test_empty_and_edgeless_graphs():
     iso = O.Graph(off=np.zeros(6, np.int64), col=np.zeros(0, np.int32), k=np.ones(5, np.int64))
     lab, N, st = O.cluster(iso, 1, 2, O.Params())
     assert list(lab) == [0, 1, 2, 3, 4] and N == 0 and st["levels"] == 1
+
+
+def test_parallel_arcs_sum_like_one_edge():
+    """w(v, X) is a sum over arcs (Section 2's objective sums edge weights),
+    so storing an edge as two parallel arcs whose weights add up to it changes
+    no decision, no label and no objective."""
+    from tests import helpers as H
+
+    h = H.with_weights(G.random_signed(400, 2500, 11), "i64", seed=4, lo=-2, hi=6)
+    hs = H.split_arcs(h)
+    assert hs.arcs > h.arcs
+    for prm in [O.Params(), O.Params(S=2, refine=0)]:
+        a = O.cluster(H.to_oracle(hs), 1, 30, prm)
+        b = O.cluster(H.to_oracle(h), 1, 30, prm)
+        assert np.array_equal(a[0], b[0]) and a[1] == b[1]
