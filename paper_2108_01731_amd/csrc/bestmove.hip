@@ -2057,6 +2057,14 @@ void best_moves(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_para
     for (int b = 0; b <= SH_BIN_HI; b++) shared_rows = shared_rows || hist[b] > 0;
     shared_rows = shared_rows && bl && bl->shared_n > 0 && !small && J >= 2 && J <= SH_MAXJ && J * bl->shared_n == n;
     const int64_t n1 = shared_rows ? bl->shared_n : 0;
+    // rows of degree < 256 (bins 0-4): one launch when they are few
+    int64_t low_rows = 0;
+    int low_bins = 0;
+    for (int b = 0; b <= SH_BIN_HI; b++) {
+      low_rows += hist[b];
+      low_bins += hist[b] > 0;
+    }
+    const bool low_merged = !small && low_bins > 1 && low_rows <= 32768;
     int32_t *C16 = nullptr, *seglist = nullptr;
     uint32_t *shmask = nullptr;
     if (shared_rows) {
@@ -2203,13 +2211,20 @@ void best_moves(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_para
           for (int b = 0; b < NBINS && !small; b++) {
             if (!hist[b] || (sh_now && b <= SH_BIN_HI)) continue;
             const int bi = s * NBINS + b;
-            const AggArgs a = agg_args(bi, blk + o_start, blk + o_lctr);
+            AggArgs a = agg_args(bi, blk + o_start, blk + o_lctr);
+            // few rows below degree 256 in the level: their buckets (consecutive)
+            // go to bin 4's kernel in one launch
+            const bool merged = b <= SH_BIN_HI && !sh_now && low_merged;
+            const int lb = merged ? SH_BIN_HI : b;
+            if (merged) a.nbuckets = SH_BIN_HI + 1 - b;
             const size_t pidx = c.pending.size();
             {
-              Ctx::Timer tm(&c, class_name(b, single).c_str(), 0.0, 0.0, single || b != NBINS - 1);
-              launch_agg(c, g.wt_kind, b, acc32, single, hist[b], hist[NBINS + b], a, bin_grid(c, b, hist[b], false));
+              Ctx::Timer tm(&c, class_name(lb, single).c_str(), 0.0, 0.0, single || lb != NBINS - 1);
+              launch_agg(c, g.wt_kind, lb, acc32, single, merged ? low_rows : hist[b], hist[NBINS + b], a,
+                         bin_grid(c, lb, merged ? low_rows : hist[b], false));
             }
-            if (c.timing) timed.push_back({pidx, it, bi, 1, single});
+            if (c.timing) timed.push_back({pidx, it, bi, a.nbuckets, single});
+            if (merged) b = SH_BIN_HI;
           }
           if (!small) {
             Ctx::Timer tm(&c, "bm_apply", 0.0, 0.0, true);
