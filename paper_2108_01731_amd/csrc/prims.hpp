@@ -264,58 +264,99 @@ __global__ __launch_bounds__(RS_NT) void k_rs_hist(const K *__restrict__ keys, i
   for (int d = threadIdx.x; d < RS_BINS; d += RS_NT) hist[(int64_t)d * gridDim.x + blockIdx.x] = cnt[d];
 }
 
-// Stable scatter: every block walks its contiguous range in order, 256 items
-// per row; ranks among equal digits inside a wave come from 8 ballots.
+// Stable scatter: every block walks its contiguous range in order, in tiles
+// of RS_TILE keys.  A tile is first counted per digit (LDS), then ranked row
+// by row (256 keys; ranks among equal digits inside a wave come from 8
+// ballots, rows and waves in input order), placed in LDS in digit order, and
+// finally written out run by run, so consecutive threads store consecutive
+// addresses of one digit's output range.
+constexpr int RS_IPT = 8;
+constexpr int RS_TILE = RS_NT * RS_IPT;
+
 template <class K, class V, bool HASV>
 __global__ __launch_bounds__(RS_NT) void k_rs_scatter(const K *__restrict__ keys, const V *__restrict__ vals,
                                                       K *__restrict__ okeys, V *__restrict__ ovals, int64_t n,
                                                       int shift, int64_t per_block,
                                                       const int64_t *__restrict__ offs) {
   constexpr int NW = RS_NT / WAVE;
-  __shared__ int64_t base[RS_BINS];
+  __shared__ int64_t base[RS_BINS];  // output position of the block's next key of digit d
+  __shared__ int cnt[RS_BINS];       // keys of digit d in the tile
+  __shared__ int tstart[RS_BINS];    // first tile slot of digit d
+  __shared__ int run[RS_BINS];       // tile keys of digit d placed so far
   __shared__ int wcnt[NW][RS_BINS];
-  const int t = threadIdx.x, w = t / WAVE, l = lane_id();
+  __shared__ K sk[RS_TILE];
+  __shared__ V sv[HASV ? RS_TILE : 1];
+  const int t = threadIdx.x, w = t / WAVE;
   for (int d = t; d < RS_BINS; d += RS_NT) {
     base[d] = offs[(int64_t)d * gridDim.x + blockIdx.x];
     for (int j = 0; j < NW; j++) wcnt[j][d] = 0;
   }
-  __syncthreads();
   const int64_t beg = (int64_t)blockIdx.x * per_block;
   const int64_t end = beg + per_block < n ? beg + per_block : n;
   const uint64_t lt = __lanemask_lt();
-  for (int64_t row = beg; row < end; row += RS_NT) {
-    const int64_t i = row + t;
-    const bool valid = i < end;
-    K key = valid ? keys[i] : (K)0;
-    int d = (int)((key >> shift) & (RS_BINS - 1));
-    uint64_t peers = __ballot(valid);
+  for (int64_t tb = beg; tb < end; tb += RS_TILE) {
+    const int tn = (int)(end - tb < RS_TILE ? end - tb : RS_TILE);
+    for (int d = t; d < RS_BINS; d += RS_NT) {
+      cnt[d] = 0;
+      run[d] = 0;
+    }
+    __syncthreads();
+    K key[RS_IPT];
 #pragma unroll
-    for (int b = 0; b < RS_BITS; b++) {
-      uint64_t bb = __ballot((d >> b) & 1);
-      peers &= ((d >> b) & 1) ? bb : ~bb;
-    }
-    int rank = __popcll(peers & lt);
-    int cntp = __popcll(peers);
-    if (valid && rank == cntp - 1) wcnt[w][d] = cntp;
-    __syncthreads();
-    if (valid) {
-      int64_t pos = base[d] + rank;
-      for (int j = 0; j < w; j++) pos += wcnt[j][d];
-      okeys[pos] = key;
-      if constexpr (HASV) ovals[pos] = vals[i];
+    for (int j = 0; j < RS_IPT; j++) {
+      const int r = j * RS_NT + t;
+      key[j] = r < tn ? keys[tb + r] : (K)0;
+      if (r < tn) atomicAdd(&cnt[(int)((key[j] >> shift) & (RS_BINS - 1))], 1);
     }
     __syncthreads();
-    for (int dd = t; dd < RS_BINS; dd += RS_NT) {
-      int64_t s = 0;
-      for (int j = 0; j < NW; j++) {
-        s += wcnt[j][dd];
-        wcnt[j][dd] = 0;
+    {
+      int tot;
+      const int pre = block_excl_scan<int, RS_NT>(t < RS_BINS ? cnt[t] : 0, &tot);
+      if (t < RS_BINS) tstart[t] = pre;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < RS_IPT; j++) {
+      const int r = j * RS_NT + t;
+      const bool valid = r < tn;
+      const int d = (int)((key[j] >> shift) & (RS_BINS - 1));
+      uint64_t peers = __ballot(valid);
+#pragma unroll
+      for (int b = 0; b < RS_BITS; b++) {
+        const uint64_t bb = __ballot((d >> b) & 1);
+        peers &= ((d >> b) & 1) ? bb : ~bb;
       }
-      base[dd] += s;
+      const int rank = __popcll(peers & lt);
+      const int cntp = __popcll(peers);
+      if (valid && rank == cntp - 1) wcnt[w][d] = cntp;
+      __syncthreads();
+      if (valid) {
+        int pos = tstart[d] + run[d] + rank;
+        for (int q = 0; q < w; q++) pos += wcnt[q][d];
+        sk[pos] = key[j];
+        if constexpr (HASV) sv[pos] = vals[tb + r];
+      }
+      __syncthreads();
+      for (int dd = t; dd < RS_BINS; dd += RS_NT) {
+        int s2 = 0;
+        for (int q = 0; q < NW; q++) {
+          s2 += wcnt[q][dd];
+          wcnt[q][dd] = 0;
+        }
+        run[dd] += s2;
+      }
+      __syncthreads();
+    }
+    for (int p = t; p < tn; p += RS_NT) {
+      const K k2 = sk[p];
+      const int d = (int)((k2 >> shift) & (RS_BINS - 1));
+      const int64_t at = base[d] + (p - tstart[d]);
+      okeys[at] = k2;
+      if constexpr (HASV) ovals[at] = sv[p];
     }
     __syncthreads();
+    for (int d = t; d < RS_BINS; d += RS_NT) base[d] += cnt[d];
   }
-  (void)l;
 }
 
 // Stable LSD sort of n keys on their low `bits` bits, carrying vals when
