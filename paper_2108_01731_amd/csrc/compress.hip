@@ -247,19 +247,23 @@ __global__ void k_next_jbase(const int32_t *__restrict__ jid_next, int64_t n2, i
   }
 }
 
-// G lanes per vertex: number of inter-cluster arcs and weight of intra arcs.
+// G lanes per vertex: number of inter-cluster arcs and weight of intra arcs;
+// mu[e] = map[col[e]] is kept for the emit pass, which then streams it
+// instead of gathering map a second time.
 template <int G, int WK>
 __global__ __launch_bounds__(CP_NT) void k_cp_count(const int64_t *__restrict__ off, const int32_t *__restrict__ col,
                                                     const void *__restrict__ wt, const int32_t *__restrict__ map,
                                                     int64_t n, int64_t *__restrict__ inter,
-                                                    int64_t *__restrict__ intra) {
+                                                    int64_t *__restrict__ intra, int32_t *__restrict__ mu) {
   const int gl = threadIdx.x % G;
   const int64_t v = (int64_t)blockIdx.x * (CP_NT / G) + threadIdx.x / G;
   int64_t ni = 0, wi = 0;
   if (v < n && map[v] >= 0) {
     const int32_t mv = map[v];
     for (int64_t e = off[v] + gl; e < off[v + 1]; e += G) {
-      if (map[col[e]] != mv) ni++;
+      const int32_t m = map[col[e]];
+      mu[e] = m;
+      if (m != mv) ni++;
       else wi += load_w<WK>(wt, e);
     }
   }
@@ -277,7 +281,7 @@ __global__ __launch_bounds__(CP_NT) void k_cp_count(const int64_t *__restrict__ 
 // G lanes per vertex: writes the vertex's inter-cluster arcs, in row order,
 // as (map[v] << b | map[u], w) starting at eoff[v].
 template <int G, int WK, bool WEIGHTED>
-__global__ __launch_bounds__(CP_NT) void k_cp_emit(const int64_t *__restrict__ off, const int32_t *__restrict__ col,
+__global__ __launch_bounds__(CP_NT) void k_cp_emit(const int64_t *__restrict__ off, const int32_t *__restrict__ mu,
                                                    const void *__restrict__ wt, const int32_t *__restrict__ map,
                                                    int64_t n, const int64_t *__restrict__ eoff, int b,
                                                    uint64_t *__restrict__ keys, int64_t *__restrict__ vals) {
@@ -305,15 +309,15 @@ __global__ __launch_bounds__(CP_NT) void k_cp_emit(const int64_t *__restrict__ o
   for (int64_t r = 0; r < maxr; r++) {
     const int64_t e = beg + r * G + gl;
     bool is_inter = false;
-    int32_t mu = 0;
+    int32_t m = 0;
     if (e < end) {
-      mu = map[col[e]];
-      is_inter = mu != mv;
+      m = mu[e];
+      is_inter = m != mv;
     }
     const uint64_t bal = (__ballot(is_inter) >> g0) & gmask;
     if (is_inter) {
       const int64_t at = pos + __popcll(bal & ((1ull << gl) - 1));
-      keys[at] = ((uint64_t)(uint32_t)mv << b) | (uint64_t)(uint32_t)mu;
+      keys[at] = ((uint64_t)(uint32_t)mv << b) | (uint64_t)(uint32_t)m;
       if constexpr (WEIGHTED) vals[at] = load_w<WK>(wt, e);
     }
     pos += __popcll(bal);
@@ -396,42 +400,42 @@ int lanes_for(const lcc_graph &g) {
 }
 
 template <int G, int WK>
-void launch_count(Ctx &c, const lcc_graph &g, const int32_t *map, int64_t *inter, int64_t *intra) {
+void launch_count(Ctx &c, const lcc_graph &g, const int32_t *map, int64_t *inter, int64_t *intra, int32_t *mu) {
   hipLaunchKernelGGL((k_cp_count<G, WK>), dim3((unsigned)cdiv(g.n, CP_NT / G)), dim3(CP_NT), 0, c.stream, g.off,
-                     g.col, g.wt, map, g.n, inter, intra);
+                     g.col, g.wt, map, g.n, inter, intra, mu);
   LAUNCHCHECK();
 }
 
 template <int G, int WK>
-void launch_emit(Ctx &c, const lcc_graph &g, const int32_t *map, const int64_t *eoff, int b, uint64_t *keys,
-                 int64_t *vals) {
+void launch_emit(Ctx &c, const lcc_graph &g, const int32_t *map, const int32_t *mu, const int64_t *eoff, int b,
+                 uint64_t *keys, int64_t *vals) {
   if (WK == LCC_WT_UNIT)
     hipLaunchKernelGGL((k_cp_emit<G, WK, false>), dim3((unsigned)cdiv(g.n, CP_NT / G)), dim3(CP_NT), 0, c.stream,
-                       g.off, g.col, g.wt, map, g.n, eoff, b, keys, vals);
+                       g.off, mu, g.wt, map, g.n, eoff, b, keys, vals);
   else
     hipLaunchKernelGGL((k_cp_emit<G, WK, true>), dim3((unsigned)cdiv(g.n, CP_NT / G)), dim3(CP_NT), 0, c.stream,
-                       g.off, g.col, g.wt, map, g.n, eoff, b, keys, vals);
+                       g.off, mu, g.wt, map, g.n, eoff, b, keys, vals);
   LAUNCHCHECK();
 }
 
 template <int WK>
-void count_and_emit(Ctx &c, const lcc_graph &g, const int32_t *map, int64_t *inter, int64_t *intra,
+void count_and_emit(Ctx &c, const lcc_graph &g, const int32_t *map, int32_t *mu, int64_t *inter, int64_t *intra,
                     const int64_t *eoff, int b, uint64_t *keys, int64_t *vals, bool emit) {
   switch (lanes_for(g)) {
-    case 8: emit ? launch_emit<8, WK>(c, g, map, eoff, b, keys, vals) : launch_count<8, WK>(c, g, map, inter, intra); break;
-    case 16: emit ? launch_emit<16, WK>(c, g, map, eoff, b, keys, vals) : launch_count<16, WK>(c, g, map, inter, intra); break;
-    case 32: emit ? launch_emit<32, WK>(c, g, map, eoff, b, keys, vals) : launch_count<32, WK>(c, g, map, inter, intra); break;
-    default: emit ? launch_emit<64, WK>(c, g, map, eoff, b, keys, vals) : launch_count<64, WK>(c, g, map, inter, intra); break;
+    case 8: emit ? launch_emit<8, WK>(c, g, map, mu, eoff, b, keys, vals) : launch_count<8, WK>(c, g, map, inter, intra, mu); break;
+    case 16: emit ? launch_emit<16, WK>(c, g, map, mu, eoff, b, keys, vals) : launch_count<16, WK>(c, g, map, inter, intra, mu); break;
+    case 32: emit ? launch_emit<32, WK>(c, g, map, mu, eoff, b, keys, vals) : launch_count<32, WK>(c, g, map, inter, intra, mu); break;
+    default: emit ? launch_emit<64, WK>(c, g, map, mu, eoff, b, keys, vals) : launch_count<64, WK>(c, g, map, inter, intra, mu); break;
   }
 }
 
-void dispatch_ce(Ctx &c, const lcc_graph &g, const int32_t *map, int64_t *inter, int64_t *intra, const int64_t *eoff,
-                 int b, uint64_t *keys, int64_t *vals, bool emit) {
+void dispatch_ce(Ctx &c, const lcc_graph &g, const int32_t *map, int32_t *mu, int64_t *inter, int64_t *intra,
+                 const int64_t *eoff, int b, uint64_t *keys, int64_t *vals, bool emit) {
   switch (g.wt_kind) {
-    case LCC_WT_UNIT: count_and_emit<LCC_WT_UNIT>(c, g, map, inter, intra, eoff, b, keys, vals, emit); break;
-    case LCC_WT_I16: count_and_emit<LCC_WT_I16>(c, g, map, inter, intra, eoff, b, keys, vals, emit); break;
-    case LCC_WT_I32: count_and_emit<LCC_WT_I32>(c, g, map, inter, intra, eoff, b, keys, vals, emit); break;
-    default: count_and_emit<LCC_WT_I64>(c, g, map, inter, intra, eoff, b, keys, vals, emit); break;
+    case LCC_WT_UNIT: count_and_emit<LCC_WT_UNIT>(c, g, map, mu, inter, intra, eoff, b, keys, vals, emit); break;
+    case LCC_WT_I16: count_and_emit<LCC_WT_I16>(c, g, map, mu, inter, intra, eoff, b, keys, vals, emit); break;
+    case LCC_WT_I32: count_and_emit<LCC_WT_I32>(c, g, map, mu, inter, intra, eoff, b, keys, vals, emit); break;
+    default: count_and_emit<LCC_WT_I64>(c, g, map, mu, inter, intra, eoff, b, keys, vals, emit); break;
   }
 }
 
@@ -701,6 +705,7 @@ void compress_graph(Ctx &c, const lcc_graph &g, const int32_t *C, OwnedGraph &ou
   int64_t *inter = c.buf<int64_t>("cp.inter", nn + 1);
   int64_t *intra = c.buf<int64_t>("cp.intra", nn);
   int64_t *tots = c.buf<int64_t>("cp.tots", 4);
+  int32_t *mu = c.buf<int32_t>("cp.mu", (size_t)(g.arcs > 0 ? g.arcs : 1));  // map[col[e]] per arc
   HIPCHECK(hipMemsetAsync(tots, 0, 4 * sizeof(int64_t), c.stream));
   {
     Ctx::Timer tm(&c, "cp_relabel", 13.0 * (double)n, (double)n);
@@ -713,8 +718,8 @@ void compress_graph(Ctx &c, const lcc_graph &g, const int32_t *C, OwnedGraph &ou
   }
   const int wb = wt_bytes(g.wt_kind);
   {
-    Ctx::Timer tm(&c, "cp_count", 28.0 * (double)n + (8.0 + wb) * (double)g.arcs, (double)g.arcs);
-    dispatch_ce(c, g, map, inter, intra, nullptr, 0, nullptr, nullptr, false);
+    Ctx::Timer tm(&c, "cp_count", 28.0 * (double)n + (12.0 + wb) * (double)g.arcs, (double)g.arcs);
+    dispatch_ce(c, g, map, mu, inter, intra, nullptr, 0, nullptr, nullptr, false);
   }
   scan<int64_t, int64_t>(c, inter, inter, n, false, tots + 1);
   int64_t h[2] = {0, 0};
@@ -729,9 +734,9 @@ void compress_graph(Ctx &c, const lcc_graph &g, const int32_t *C, OwnedGraph &ou
   int64_t *v0 = weighted ? c.buf<int64_t>("cp.v0", (size_t)(T > 0 ? T : 1)) : nullptr;
   int64_t *v1 = weighted ? c.buf<int64_t>("cp.v1", (size_t)(T > 0 ? T : 1)) : nullptr;
   if (T > 0) {
-    Ctx::Timer tm(&c, "cp_emit", 28.0 * (double)n + (8.0 + wb) * (double)g.arcs + (8.0 + (weighted ? 8 : 0)) * (double)T,
+    Ctx::Timer tm(&c, "cp_emit", 28.0 * (double)n + (4.0 + wb) * (double)g.arcs + (8.0 + (weighted ? 8 : 0)) * (double)T,
                   (double)g.arcs);
-    dispatch_ce(c, g, map, inter, intra, inter, b, k0, v0, true);
+    dispatch_ce(c, g, map, mu, inter, intra, inter, b, k0, v0, true);
   }
   uint64_t *ks = k0;
   int64_t *vs = v0;
