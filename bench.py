@@ -65,8 +65,8 @@ def main():
                     help="first run one 1 GiB device-to-device copy, a reference for HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding of this "
-              "path is a design note, not part of this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); sharding this path over several "
+              "GPUs is described, not implemented", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
