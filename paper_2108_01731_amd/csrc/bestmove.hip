@@ -918,11 +918,22 @@ __global__ __launch_bounds__(B7L_NT) void k_b7_layout(AggArgs a, int64_t *__rest
   }
 }
 
+// Packed tables (every row's sum of |w| below 2^31, so every partial sum
+// fits 32 bits): one 64-bit slot holds the key (high half) and its weight
+// sum (low half), so a new key is claimed with its first weight in one CAS
+// and repeated keys add to the low half with a 32-bit atomic.
+constexpr unsigned long long PK_EMPTY = 0xFFFFFFFF00000000ull;
+
+template <bool PK>
 __global__ void k_b7_clear(int32_t *__restrict__ keys, int64_t *__restrict__ vals, const int64_t *__restrict__ tot) {
   const int64_t total = tot[1];
   for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < total; j += (int64_t)gridDim.x * blockDim.x) {
-    keys[j] = -1;
-    vals[j] = 0;
+    if constexpr (PK) {
+      reinterpret_cast<unsigned long long *>(vals)[j] = PK_EMPTY;
+    } else {
+      keys[j] = -1;
+      vals[j] = 0;
+    }
   }
 }
 
@@ -944,10 +955,29 @@ __device__ __forceinline__ void global_insert(int32_t *keys, int64_t *vals, uint
   }
 }
 
+__device__ __forceinline__ void global_insert_packed(unsigned long long *tab, uint32_t H, int32_t X, int32_t w) {
+  uint32_t h = slot_of(X, H);
+  const unsigned long long mine = ((unsigned long long)(uint32_t)X << 32) | (unsigned long long)(uint32_t)w;
+  while (true) {
+    unsigned long long cur = __hip_atomic_load(&tab[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (cur == PK_EMPTY) {
+      const unsigned long long old = atomicCAS(&tab[h], PK_EMPTY, mine);
+      if (old == PK_EMPTY) return;  // claimed with the first weight
+      cur = old;
+    }
+    if ((int32_t)(cur >> 32) == X) {
+      // the low half (little-endian), never the key
+      if (w) atomicAdd(reinterpret_cast<int32_t *>(&tab[h]), w);
+      return;
+    }
+    h = (h + 1 == H) ? 0 : h + 1;
+  }
+}
+
 // One block per chunk (cstart / tstart hold n7 + 1 entries): the chunk's
 // arcs are summed by cluster in LDS, then each distinct cluster is added to
 // the row's global table; the row's first chunk also enters its own cluster.
-template <int WK>
+template <int WK, bool PK>
 __global__ __launch_bounds__(B7_NT) void k_b7_insert(AggArgs a, const int64_t *__restrict__ tot,
                                                      const int64_t *__restrict__ cstart,
                                                      const int64_t *__restrict__ tstart) {
@@ -998,8 +1028,13 @@ __global__ __launch_bounds__(B7_NT) void k_b7_insert(AggArgs a, const int64_t *_
     __syncthreads();
     const int64_t t0 = tstart[i];
     const uint32_t H = (uint32_t)(tstart[i + 1] - t0);
-    for (int j = t; j < B7_CHUNK_SLOTS; j += B7_NT)
-      if (lk[j] >= 0) global_insert(a.gkeys + t0, a.gvals + t0, H, lk[j], lv[j]);
+    for (int j = t; j < B7_CHUNK_SLOTS; j += B7_NT) {
+      if (lk[j] < 0) continue;
+      if constexpr (PK)
+        global_insert_packed(reinterpret_cast<unsigned long long *>(a.gvals) + t0, H, lk[j], (int32_t)lv[j]);
+      else
+        global_insert(a.gkeys + t0, a.gvals + t0, H, lk[j], lv[j]);
+    }
     __syncthreads();  // the LDS table and sh_row are reused by the next chunk
   }
 }
@@ -1015,6 +1050,7 @@ struct SegBest {
   int32_t pad;
 };
 
+template <bool PK>
 __global__ __launch_bounds__(B7_NT) void k_b7_segscore(AggArgs a, const int64_t *__restrict__ tot,
                                                        const int64_t *__restrict__ tstart,
                                                        const int64_t *__restrict__ sstart,
@@ -1046,10 +1082,19 @@ __global__ __launch_bounds__(B7_NT) void k_b7_segscore(AggArgs a, const int64_t 
     // the tables were filled by device-scope atomics in the previous kernel:
     // read them with device-scope loads as well
     for (int64_t j = j0 + threadIdx.x; j < j1; j += B7_NT) {
-      const int32_t X = __hip_atomic_load(&a.gkeys[t0 + j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      int32_t X;
+      int64_t wx;
+      if constexpr (PK) {
+        const unsigned long long sl = __hip_atomic_load(reinterpret_cast<unsigned long long *>(a.gvals) + t0 + j,
+                                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        X = (int32_t)(sl >> 32);
+        wx = (int64_t)(int32_t)(uint32_t)sl;
+      } else {
+        X = __hip_atomic_load(&a.gkeys[t0 + j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (X >= 0) wx = __hip_atomic_load(&a.gvals[t0 + j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
       if (X < 0) continue;
       cands++;
-      const int64_t wx = __hip_atomic_load(&a.gvals[t0 + j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       if (X == c) {
         wc = wx;
       } else {
@@ -1730,7 +1775,7 @@ void launch_bin(Ctx &c, int bin, AggArgs a, int64_t grid) {
       break;
     }
     default:
-      fail(LCC_ERR_DEVICE, "internal: the flat bin is launched by launch_flat");
+      fail(LCC_ERR_DEVICE, "internal: the flat bin is launched by launch_flat_pk");
   }
   LAUNCHCHECK();
 }
@@ -1753,7 +1798,7 @@ template <int WK> void launch_single(Ctx &c, int bin, AggArgs a, int64_t grid) {
 // Flat aggregation of the rows of bin 7 (see k_b7_insert).  Sizes are upper
 // bounds (at most n7_ub rows holding at most a7_ub arcs); the kernels read
 // the actual ones from the layout, so nothing is read back.
-template <int WK> void launch_flat(Ctx &c, AggArgs a, int64_t n7_ub, int64_t a7_ub) {
+template <int WK, bool PK> void launch_flat_pk(Ctx &c, AggArgs a, int64_t n7_ub, int64_t a7_ub) {
   n7_ub = std::max<int64_t>(n7_ub, 1);
   int64_t *cstart = c.buf<int64_t>("b7.cstart", (size_t)n7_ub + 1);
   int64_t *tstart = c.buf<int64_t>("b7.tstart", (size_t)n7_ub + 1);
@@ -1767,14 +1812,14 @@ template <int WK> void launch_flat(Ctx &c, AggArgs a, int64_t n7_ub, int64_t a7_
   SegBest *part = c.buf<SegBest>("b7.part", (size_t)max_seg);
   hipLaunchKernelGGL(k_b7_layout, dim3(1), dim3(B7L_NT), 0, c.stream, a, cstart, tstart, sstart, tot);
   LAUNCHCHECK();
-  hipLaunchKernelGGL(k_b7_clear, dim3((unsigned)c.num_cu * 8), dim3(256), 0, c.stream, a.gkeys, a.gvals, tot);
+  hipLaunchKernelGGL(k_b7_clear<PK>, dim3((unsigned)c.num_cu * 8), dim3(256), 0, c.stream, a.gkeys, a.gvals, tot);
   LAUNCHCHECK();
   // chunks: at most a7_ub / B7_CHUNK + n7_ub
   const int64_t chunks = a7_ub / B7_CHUNK + n7_ub;
   const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(chunks, (int64_t)c.num_cu * 4));
-  hipLaunchKernelGGL((k_b7_insert<WK>), dim3((unsigned)grid), dim3(B7_NT), 0, c.stream, a, tot, cstart, tstart);
+  hipLaunchKernelGGL((k_b7_insert<WK, PK>), dim3((unsigned)grid), dim3(B7_NT), 0, c.stream, a, tot, cstart, tstart);
   LAUNCHCHECK();
-  hipLaunchKernelGGL(k_b7_segscore, dim3((unsigned)std::min<int64_t>(max_seg, (int64_t)c.num_cu * 8)), dim3(B7_NT), 0,
+  hipLaunchKernelGGL(k_b7_segscore<PK>, dim3((unsigned)std::min<int64_t>(max_seg, (int64_t)c.num_cu * 8)), dim3(B7_NT), 0,
                      c.stream, a, tot, tstart, sstart, part);
   LAUNCHCHECK();
   hipLaunchKernelGGL(k_b7_final, dim3((unsigned)std::min<int64_t>(n7_ub, (int64_t)c.num_cu * 4)), dim3(B7_NT), 0,
@@ -1787,7 +1832,8 @@ template <int WK>
 void launch_any(Ctx &c, int bin, bool a32, bool single, int64_t ub_count, int64_t ub_arcs, AggArgs a,
                 int64_t grid) {
   if (single) launch_single<WK>(c, bin, a, grid);
-  else if (bin == NBINS - 1) launch_flat<WK>(c, a, ub_count, ub_arcs);
+  else if (bin == NBINS - 1 && a32) launch_flat_pk<WK, true>(c, a, ub_count, ub_arcs);
+  else if (bin == NBINS - 1) launch_flat_pk<WK, false>(c, a, ub_count, ub_arcs);
   else if (a32) launch_bin<WK, true>(c, bin, a, grid);
   else launch_bin<WK, false>(c, bin, a, grid);
 }

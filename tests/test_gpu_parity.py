@@ -227,6 +227,18 @@ def test_repeated_neighbors_equal_merged_arcs(ctx):
         assert torch.equal(ls, lm) and Ns == Nm
 
 
+def test_hub_rows_with_64_bit_sums(ctx):
+    """Hub rows (beyond the LDS tables) whose weight sums need 64 bits take
+    the unpacked global tables; rows below 2^31 take the packed ones (the
+    other hub cases)."""
+    h = H.with_weights(H.hub_graph(n=40000, m=60000, hubs=(16000, 25000), seed=23, weighted=False), "i64", seed=5,
+                       lo=1 << 27, hi=1 << 28)
+    for cfg in [dict(), dict(S=2, refine=0)]:
+        lo, No, _ = O.cluster(H.to_oracle(h), 1, 60, oparams(**cfg))
+        ld, Nd, _ = L.lcc_cluster(ctx, dev(h), 1, 60, dparams(**cfg))
+        assert np.array_equal(lo, ld.cpu().numpy()) and No == Nd
+
+
 def test_tiny_and_degenerate_graphs(ctx):
     cases_ = [
         G.HostGraph(np.zeros(1, np.int64), np.zeros(0, np.int32), np.zeros(0, np.int64)),  # empty
