@@ -130,7 +130,10 @@ typedef struct lcc_params {
   /* tuning */
   int32_t validate; /* 1 = run the device validation pass on input graphs (default) */
   int32_t timing;   /* 1 = time every kernel launch with HIP events (see lcc_ctx_kernel_stats) */
-  int32_t reserved[6];
+  int32_t hub_limit; /* 0 = default; > 0: distinct clusters a hash partition of a row beyond the LDS
+                        tables may hold before the call is redone with global tables (lowering it
+                        forces that path, for tests) */
+  int32_t reserved[5];
 } lcc_params;
 
 /* Fills the defaults: S = 4, num_iter = 10, seed = 1, frontier = NBR,

@@ -36,8 +36,12 @@ constexpr int BM_NT = 256;
 constexpr int WIDE_NT = 1024;
 constexpr int NBINS = 8;
 constexpr int NSPREAD = 8;   // counter copies per launch (spreads same-address atomics)
-constexpr int NCTR = 6;      // movers, candidates, arcs of movers, capacity errors, shared rows, their arcs
+constexpr int NCTR = 7;  // movers, candidates, arcs of movers, capacity errors, shared rows, their arcs,
+                         // hub partitions that overflowed
 constexpr int32_t ISO_ID = INT32_MAX;  // ranks after every real cluster id
+
+// Thrown by a Best-Moves call whose hub partitions overflowed (see k_hp_part).
+struct HubOverflow {};
 constexpr int MID_SLOTS = 4096;        // table of the block-per-vertex bin (degree < 2048)
 
 // Largest degree of each bin; bin 6's limit depends on the LDS size and the
@@ -101,6 +105,7 @@ struct AggArgs {
   int64_t nlev;       // vertices of the level (fresh ids are nlev + v)
   int64_t *iso_ctr;   // isolations of the sub-round
   int32_t rb0, rb1;
+  int32_t hub_limit;  // distinct clusters a hub partition may hold (see k_hp_part)
 };
 
 // The launch's vertex list and count (host-given, or read from the bucket
@@ -1166,6 +1171,233 @@ __global__ __launch_bounds__(B7_NT) void k_b7_final(AggArgs a, const int64_t *__
   flush_counters<B7_NT>(a.ctr, movers, cands, marcs);
 }
 
+// ------------------------------------------- partitioned hub aggregation
+
+// Hub rows without global atomics: every hub arc's cluster id is gathered
+// once into a per-row buffer (xs), then each row is cut into P hash
+// partitions of its clusters (a multiplier independent of the table hash),
+// one 1024-thread block per partition, aggregated and scored in LDS.  P is
+// chosen so that a partition expects half of HP_LIMIT distinct clusters.  A
+// partition that meets more than the limit stops claiming slots before its
+// table fills (so probing always ends) and counts an overflow; the host then
+// redoes the whole Best-Moves call with the global tables, which give the
+// same result.
+constexpr int HP_NT = 1024;
+constexpr int HP_SLOTS = 12288;
+constexpr int HP_LIMIT = HP_SLOTS * 7 / 10;
+constexpr int HP_STOP = HP_SLOTS - 2 * HP_NT;  // claims never exceed this
+// Every partition reads its whole row, so a level takes the partitions only
+// while its widest row needs at most 16 of them.
+constexpr int64_t HP_MAX_DEG = 65536;
+
+__host__ __device__ inline int64_t hp_parts(int64_t deg) { return cdiv(2 * (deg + 1), HP_LIMIT); }
+
+__device__ __forceinline__ uint32_t part_of(int32_t X, uint32_t P) {
+  return (uint32_t)(((uint64_t)((uint32_t)X * 0x85EBCA6Bu) * (uint64_t)P) >> 32);
+}
+
+// Layout of the bucket's hub rows, in one block: prefixes of gather chunks
+// (cstart), degrees (xoff) and partitions (pstart), n7 + 1 entries each;
+// tot = {chunks, arcs, partitions, n7}.
+__global__ __launch_bounds__(B7L_NT) void k_hp_layout(AggArgs a, int64_t *__restrict__ cstart,
+                                                      int64_t *__restrict__ xoff, int64_t *__restrict__ pstart,
+                                                      int64_t *__restrict__ tot) {
+  const int32_t *list;
+  int64_t n7;
+  work_of(a, list, n7);
+  int64_t ca = 0, cx = 0, cp = 0;
+  for (int64_t i0 = 0; i0 < n7; i0 += B7L_NT) {
+    const int64_t i = i0 + threadIdx.x;
+    int64_t nc = 0, d = 0, np = 0;
+    if (i < n7) {
+      const int32_t v = list[i];
+      d = a.off[v + 1] - a.off[v];
+      nc = cdiv(d, B7_CHUNK);
+      np = hp_parts(d);
+    }
+    int64_t tc, tx, tp;
+    const int64_t pc = block_excl_scan<int64_t, B7L_NT>(nc, &tc);
+    const int64_t px = block_excl_scan<int64_t, B7L_NT>(d, &tx);
+    const int64_t pp = block_excl_scan<int64_t, B7L_NT>(np, &tp);
+    if (i < n7) {
+      cstart[i] = ca + pc;
+      xoff[i] = cx + px;
+      pstart[i] = cp + pp;
+    }
+    ca += tc;
+    cx += tx;
+    cp += tp;
+  }
+  if (threadIdx.x == 0) {
+    cstart[n7] = ca;
+    xoff[n7] = cx;
+    pstart[n7] = cp;
+    tot[0] = ca;
+    tot[1] = cx;
+    tot[2] = cp;
+    tot[3] = n7;
+  }
+}
+
+// One block per chunk of B7_CHUNK arcs: xs[xoff[row] + j] = C[col[beg + j]].
+__global__ __launch_bounds__(B7_NT) void k_hp_gather(AggArgs a, const int64_t *__restrict__ tot,
+                                                     const int64_t *__restrict__ cstart,
+                                                     const int64_t *__restrict__ xoff, int32_t *__restrict__ xs) {
+  __shared__ int64_t sh_row;
+  const int32_t *list;
+  int64_t cnt7;
+  work_of(a, list, cnt7);
+  const int64_t nch = tot[0], n7 = tot[3];
+  for (int64_t ch = blockIdx.x; ch < nch; ch += gridDim.x) {
+    __syncthreads();  // sh_row is reused
+    if (threadIdx.x == 0) {
+      int64_t lo = 0, hi = n7 - 1;
+      while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if (cstart[mid] <= ch) lo = mid;
+        else hi = mid - 1;
+      }
+      sh_row = lo;
+    }
+    __syncthreads();
+    const int64_t i = sh_row;
+    const int32_t v = list[i];
+    const int64_t beg = a.off[v], end = a.off[v + 1];
+    const int64_t e0 = beg + (ch - cstart[i]) * B7_CHUNK;
+    const int64_t e1 = e0 + B7_CHUNK < end ? e0 + B7_CHUNK : end;
+    int32_t *out = xs + xoff[i] - beg;
+    for (int64_t base = e0 + threadIdx.x; base < e1; base += 4 * B7_NT) {
+      int32_t u[4];
+#pragma unroll
+      for (int j = 0; j < 4; j++) u[j] = base + j * B7_NT < e1 ? a.col[base + j * B7_NT] : -1;
+#pragma unroll
+      for (int j = 0; j < 4; j++)
+        if (u[j] >= 0) out[base + j * B7_NT] = a.C[u[j]];
+    }
+  }
+}
+
+// Adds w to key X unless the table already holds `stop` claims (then false).
+template <class Acc>
+__device__ __forceinline__ bool lds_insert_bounded(int32_t *keys, Acc *vals, int32_t X, int64_t w, int32_t *nclaim,
+                                                   int32_t stop) {
+  uint32_t h = slot_of(X, HP_SLOTS);
+  while (true) {
+    int32_t cur = keys[h];
+    if (cur == -1) {
+      if (atomicAdd(nclaim, 1) >= stop) return false;
+      cur = atomicCAS(&keys[h], -1, X);
+      if (cur == -1) {
+        cur = X;
+      } else {
+        atomicSub(nclaim, 1);  // another key took the slot first
+      }
+    }
+    if (cur == X) {
+      if (w) {
+        if constexpr (sizeof(Acc) == 8)
+          atomicAdd(reinterpret_cast<unsigned long long *>(&vals[h]), (unsigned long long)w);
+        else
+          atomicAdd(&vals[h], (Acc)w);
+      }
+      return true;
+    }
+    h = (h + 1 == (uint32_t)HP_SLOTS) ? 0 : h + 1;
+  }
+}
+
+// One block per partition: its clusters' weights summed in LDS, then scored
+// (as the per-row kernels do) into part[partition]; an overflow counts in
+// counter 6 of the launch.
+template <int WK, bool A32>
+__global__ __launch_bounds__(HP_NT) void k_hp_part(AggArgs a, const int64_t *__restrict__ tot,
+                                                   const int64_t *__restrict__ xoff,
+                                                   const int64_t *__restrict__ pstart,
+                                                   const int32_t *__restrict__ xs, SegBest *__restrict__ part) {
+  using Acc = typename std::conditional<A32, int32_t, int64_t>::type;
+  extern __shared__ __align__(16) unsigned char smem[];
+  int32_t *keys = reinterpret_cast<int32_t *>(smem);
+  Acc *vals = reinterpret_cast<Acc *>(smem + (size_t)HP_SLOTS * sizeof(int32_t));
+  __shared__ int32_t nclaim;
+  __shared__ int64_t sh_row;
+  const int t = threadIdx.x;
+  const int32_t *list;
+  int64_t cnt7;
+  work_of(a, list, cnt7);
+  const int64_t np = tot[2], n7 = tot[3];
+  const int32_t limit = a.hub_limit > 0 ? a.hub_limit : HP_LIMIT;
+  int64_t overflows = 0;
+  for (int64_t pi = blockIdx.x; pi < np; pi += gridDim.x) {
+    __syncthreads();  // the table, nclaim and sh_row are reused
+    for (int s = t; s < HP_SLOTS; s += HP_NT) {
+      keys[s] = -1;
+      vals[s] = 0;
+    }
+    if (t == 0) {
+      nclaim = 0;
+      int64_t lo = 0, hi = n7 - 1;
+      while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if (pstart[mid] <= pi) lo = mid;
+        else hi = mid - 1;
+      }
+      sh_row = lo;
+    }
+    __syncthreads();
+    const int64_t i = sh_row;
+    const int32_t v = list[i];
+    const int64_t beg = a.off[v], deg = a.off[v + 1] - beg;
+    const uint32_t P = (uint32_t)(pstart[i + 1] - pstart[i]), p = (uint32_t)(pi - pstart[i]);
+    const int32_t c = a.C[v];
+    const int32_t *x = xs + xoff[i];
+    if (t == 0 && part_of(c, P) == p) lds_insert_bounded<Acc>(keys, vals, c, 0, &nclaim, HP_STOP);
+    for (int64_t j = t; j < deg; j += HP_NT) {
+      const int32_t X = x[j];
+      if (part_of(X, P) != p) continue;
+      lds_insert_bounded<Acc>(keys, vals, X, load_w<WK>(a.wt, beg + j), &nclaim, HP_STOP);
+    }
+    __syncthreads();
+    const bool over = nclaim > limit;  // block-uniform
+    int64_t lp, lq;
+    int32_t job;
+    job_lambda(a, v, lp, lq, job);
+    const int64_t pk = lp * a.k[v];
+    int64_t best_s = INT64_MIN, wc = 0, cands = 0;
+    int32_t best_id = ISO_ID;
+    if (!over) {
+      for (int s = t; s < HP_SLOTS; s += HP_NT) {
+        const int32_t X = keys[s];
+        if (X < 0) continue;
+        cands++;
+        const int64_t wx = (int64_t)vals[s];
+        if (X == c) {
+          wc = wx;
+        } else {
+          const int64_t sc = lq * wx - pk * a.K[X];
+          if (better(sc, X, best_s, best_id)) {
+            best_s = sc;
+            best_id = X;
+          }
+        }
+      }
+    }
+    cands = wave_sum(cands);
+    __shared__ int64_t rc[HP_NT / WAVE];
+    if (lane_id() == 0) rc[t / WAVE] = cands;
+    block_best<HP_NT>(best_s, best_id, wc);
+    if (t == 0) {
+      int64_t tc = 0;
+      for (int k = 0; k < HP_NT / WAVE; k++) tc += rc[k];
+      part[pi] = SegBest{best_s, wc, tc, best_id, 0};
+      overflows += over ? 1 : 0;
+    }
+  }
+  if (t == 0 && overflows) atomic_add_i64(&a.ctr[(blockIdx.x % NSPREAD) * NCTR + 6], overflows);
+}
+
+size_t hp_lds_bytes(bool a32) { return (size_t)HP_SLOTS * (sizeof(int32_t) + (a32 ? 4 : 8)); }
+
+
 // -------------------------------------------------------------- apply
 
 // Applies the sub-round's decisions; an isolating vertex v takes the fresh
@@ -1827,11 +2059,47 @@ template <int WK, bool PK> void launch_flat_pk(Ctx &c, AggArgs a, int64_t n7_ub,
   LAUNCHCHECK();
 }
 
+// Rows beyond the LDS tables through hash partitions in LDS (see k_hp_part).
+template <int WK> void launch_hub_part(Ctx &c, AggArgs a, int64_t n7_ub, int64_t a7_ub, bool a32) {
+  n7_ub = std::max<int64_t>(n7_ub, 1);
+  int64_t *cstart = c.buf<int64_t>("hp.cstart", (size_t)n7_ub + 1);
+  int64_t *xoff = c.buf<int64_t>("hp.xoff", (size_t)n7_ub + 1);
+  int64_t *pstart = c.buf<int64_t>("hp.pstart", (size_t)n7_ub + 1);
+  int64_t *tot = c.buf<int64_t>("hp.tot", 4);
+  int32_t *xs = c.buf<int32_t>("hp.xs", (size_t)std::max<int64_t>(a7_ub, 1));
+  // partitions: cdiv(2 (d + 1), HP_LIMIT) <= 2 (d + 1) / HP_LIMIT + 1 per row
+  const int64_t parts_ub = 2 * (a7_ub + n7_ub) / HP_LIMIT + n7_ub + 1;
+  SegBest *part = c.buf<SegBest>("hp.part", (size_t)parts_ub);
+  hipLaunchKernelGGL(k_hp_layout, dim3(1), dim3(B7L_NT), 0, c.stream, a, cstart, xoff, pstart, tot);
+  LAUNCHCHECK();
+  const int64_t chunks = a7_ub / B7_CHUNK + n7_ub;
+  hipLaunchKernelGGL(k_hp_gather, dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(chunks, (int64_t)c.num_cu * 8))),
+                     dim3(B7_NT), 0, c.stream, a, (const int64_t *)tot, (const int64_t *)cstart,
+                     (const int64_t *)xoff, xs);
+  LAUNCHCHECK();
+  const size_t bytes = hp_lds_bytes(a32);
+  const dim3 gp((unsigned)std::max<int64_t>(1, std::min<int64_t>(parts_ub, (int64_t)c.num_cu * 2)));
+  if (a32) {
+    allow_lds(c, k_hp_part<WK, true>, bytes);
+    hipLaunchKernelGGL((k_hp_part<WK, true>), gp, dim3(HP_NT), bytes, c.stream, a, (const int64_t *)tot,
+                       (const int64_t *)xoff, (const int64_t *)pstart, (const int32_t *)xs, part);
+  } else {
+    allow_lds(c, k_hp_part<WK, false>, bytes);
+    hipLaunchKernelGGL((k_hp_part<WK, false>), gp, dim3(HP_NT), bytes, c.stream, a, (const int64_t *)tot,
+                       (const int64_t *)xoff, (const int64_t *)pstart, (const int32_t *)xs, part);
+  }
+  LAUNCHCHECK();
+  hipLaunchKernelGGL(k_b7_final, dim3((unsigned)std::min<int64_t>(n7_ub, (int64_t)c.num_cu * 4)), dim3(B7_NT), 0,
+                     c.stream, a, (const int64_t *)pstart, (const SegBest *)part);
+  LAUNCHCHECK();
+}
+
 // ub_count / ub_arcs: upper bounds of the bucket's vertices and arcs.
 template <int WK>
 void launch_any(Ctx &c, int bin, bool a32, bool single, int64_t ub_count, int64_t ub_arcs, AggArgs a,
                 int64_t grid) {
   if (single) launch_single<WK>(c, bin, a, grid);
+  else if (bin == NBINS - 1 && c.hub_partition) launch_hub_part<WK>(c, a, ub_count, ub_arcs, a32);
   else if (bin == NBINS - 1 && a32) launch_flat_pk<WK, true>(c, a, ub_count, ub_arcs);
   else if (bin == NBINS - 1) launch_flat_pk<WK, false>(c, a, ub_count, ub_arcs);
   else if (a32) launch_bin<WK, true>(c, bin, a, grid);
@@ -1966,8 +2234,8 @@ void rename_fresh(Ctx &c, int64_t n, int32_t *C, int64_t *K, int32_t *cnt, int64
 
 }  // namespace
 
-void best_moves(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_params &prm, int32_t level,
-                int32_t phase, int32_t *C, const BMShape &shape, lcc_bm_stats &st, const BatchLevel *bl) {
+void best_moves_run(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_params &prm, int32_t level,
+                    int32_t phase, int32_t *C, const BMShape &shape, lcc_bm_stats &st, const BatchLevel *bl) {
   JobView jv;
   int64_t J = 0;
   std::vector<uint8_t> hrun;
@@ -2045,6 +2313,7 @@ void best_moves(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_para
     a.p = p;
     a.q = q;
     a.allow_iso = prm.allow_isolate;
+    a.hub_limit = prm.hub_limit;
     a.list = blist;
     a.D = D;
     a.next_flag = nbr ? next : nullptr;
@@ -2343,14 +2612,16 @@ void best_moves(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_para
       for (int32_t it = first; it < last && !done; it++) {
         const int64_t *hb = h.data() + (size_t)it * IB;
         const int64_t *hl = hb + o_lctr;
-        int64_t moved_it = 0, cap_err = 0;
+        int64_t moved_it = 0, cap_err = 0, hub_over = 0;
         for (int bi = 0; bi < NB; bi++) {
           moved_it += launch_sums(hl, bi, 0);
           st.candidates += launch_sums(hl, bi, 1);
           cap_err += launch_sums(hl, bi, 3);
+          hub_over += launch_sums(hl, bi, 6);
           st.vertices_processed += hb[o_bcnt + bi];
           st.arcs_scanned += hb[o_barcs + bi];
         }
+        if (hub_over) throw HubOverflow{};
         if (cap_err)
           fail(LCC_ERR_DEVICE, "internal: a vertex degree exceeded the hash capacity sized from the maximum degree");
         if (hb[o_err]) fail(LCC_ERR_DEVICE, "internal: fresh clusters outnumbered the empty cluster ids");
@@ -2486,12 +2757,14 @@ void best_moves(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_para
     if (nbr && n > 0) compact_flags(c, next, n, active, nact, true, "bm.cmp");
     d2h(c, hctr.data() + o_lctr, lctr, (size_t)(LC * NB + S + 2) * sizeof(int64_t));
     const int64_t *hl = hctr.data() + o_lctr;
-    int64_t moved_it = 0, cap_err = 0;
+    int64_t moved_it = 0, cap_err = 0, hub_over = 0;
     for (int bi = 0; bi < NB; bi++) {
       moved_it += launch_sums(hl, bi, 0);
       st.candidates += launch_sums(hl, bi, 1);
       cap_err += launch_sums(hl, bi, 3);
+      hub_over += launch_sums(hl, bi, 6);
     }
+    if (hub_over) throw HubOverflow{};
     const int64_t hl_nact = hctr[o_nact];
     int64_t isolated = 0;
     for (int s = 0; s < S; s++) isolated += hctr[o_isoc + s];
@@ -2542,6 +2815,42 @@ void best_moves(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_para
     }
   }
   if (c.timing) c.collect_timing();
+}
+
+__global__ void k_copy_i32(const int32_t *__restrict__ a, int32_t *__restrict__ b, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    b[i] = a[i];
+}
+
+// A call whose rows beyond the LDS tables go through hash partitions keeps
+// a copy of C: if a partition overflowed (k_hp_part), the call is redone from
+// that copy with the global tables, so the result never depends on it.
+void best_moves(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_params &prm, int32_t level,
+                int32_t phase, int32_t *C, const BMShape &shape, lcc_bm_stats &st, const BatchLevel *bl) {
+  const int64_t wide_max = wide_slots(c, shape.acc32) * 7 / 10 - 1;
+  c.hub_partition = false;
+  if (g.n <= 0 || shape.maxdeg <= wide_max || shape.maxdeg > HP_MAX_DEG) {
+    best_moves_run(c, g, p, q, prm, level, phase, C, shape, st, bl);
+    return;
+  }
+  const unsigned grid = (unsigned)std::min<int64_t>(cdiv(g.n, 256), 65536);
+  int32_t *snap = c.buf<int32_t>("bm.Csnap", (size_t)g.n);
+  hipLaunchKernelGGL(k_copy_i32, dim3(grid), dim3(256), 0, c.stream, (const int32_t *)C, snap, g.n);
+  LAUNCHCHECK();
+  c.hub_partition = true;
+  try {
+    best_moves_run(c, g, p, q, prm, level, phase, C, shape, st, bl);
+    c.hub_partition = false;
+  } catch (const HubOverflow &) {
+    c.hub_partition = false;
+    c.sync();
+    hipLaunchKernelGGL(k_copy_i32, dim3(grid), dim3(256), 0, c.stream, (const int32_t *)snap, C, g.n);
+    LAUNCHCHECK();
+    best_moves_run(c, g, p, q, prm, level, phase, C, shape, st, bl);
+  } catch (...) {
+    c.hub_partition = false;
+    throw;
+  }
 }
 
 }  // namespace lcc

@@ -112,6 +112,9 @@ struct Ctx {
   size_t lds_per_block = 65536;
   // kernels whose dynamic-LDS limit has been raised on this device
   std::vector<const void *> lds_raised;
+  // rows beyond the LDS tables go through LDS hash partitions in the current
+  // Best-Moves call (else through global tables)
+  bool hub_partition = false;
   hipStream_t stream = nullptr;
   bool timing = false;
   std::map<std::string, KernelClass> kstats;

@@ -51,7 +51,8 @@ class _Params(ctypes.Structure):
         ("S", ctypes.c_int32), ("num_iter", ctypes.c_int32), ("seed", ctypes.c_uint64),
         ("frontier", ctypes.c_int32), ("refine", ctypes.c_int32), ("allow_isolate", ctypes.c_int32),
         ("max_levels", ctypes.c_int32), ("stop_after_subrounds", ctypes.c_int64),
-        ("validate", ctypes.c_int32), ("timing", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6),
+        ("validate", ctypes.c_int32), ("timing", ctypes.c_int32), ("hub_limit", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 5),
     ]
 
 
@@ -221,13 +222,14 @@ class Params:
     stop_after_subrounds: int = 0
     validate: int = 1
     timing: int = 0
+    hub_limit: int = 0
 
     def _c(self) -> _Params:
         p = _Params()
         p.S, p.num_iter, p.seed = self.S, self.num_iter, self.seed & (2**64 - 1)
         p.frontier, p.refine, p.allow_isolate = self.frontier, self.refine, self.allow_isolate
         p.max_levels, p.stop_after_subrounds = self.max_levels, self.stop_after_subrounds
-        p.validate, p.timing = self.validate, self.timing
+        p.validate, p.timing, p.hub_limit = self.validate, self.timing, self.hub_limit
         return p
 
 

@@ -239,6 +239,30 @@ def test_hub_rows_with_64_bit_sums(ctx):
         assert np.array_equal(lo, ld.cpu().numpy()) and No == Nd
 
 
+def test_hub_partition_overflow_redoes_the_call(ctx):
+    """Rows beyond the LDS tables are aggregated in hash partitions; a tiny
+    hub_limit makes partitions overflow, so the call is redone from its saved
+    clustering with the global tables.  Both ways give the oracle's result."""
+    graphs = [H.hub_graph(n=40000, m=60000, hubs=(16000, 25000, 31000, 14500), seed=21),
+              H.hub_graph(n=40000, m=60000, hubs=(16000, 25000), seed=22, weighted=False)]
+    for h in graphs:
+        lo, No, _ = O.cluster(H.to_oracle(h), 1, 60, oparams())
+        for limit in [0, 64]:
+            ld, Nd, _ = L.lcc_cluster(ctx, dev(h), 1, 60, dparams(hub_limit=limit))
+            assert np.array_equal(lo, ld.cpu().numpy()) and No == Nd, limit
+    # a single call from a given clustering, device-driven and stopped inside
+    # an iteration (host-driven)
+    h = graphs[0]
+    g_o, g_d = H.to_oracle(h), dev(h)
+    C0 = np.random.default_rng(3).integers(0, 200, size=h.n).astype(np.int32)
+    for cfg in [dict(S=3), dict(S=3, stop_after_subrounds=5)]:
+        Co, so = O.best_move(g_o, 1, 60, oparams(**cfg), C0, 2, 1)
+        for limit in [0, 64]:
+            Cd = torch.from_numpy(C0.copy()).cuda()
+            sd = L.lcc_best_move(ctx, g_d, 1, 60, dparams(hub_limit=limit, **cfg), Cd, 2, 1)
+            assert_same_bm(Co, so, Cd.cpu().numpy(), sd)
+
+
 def test_tiny_and_degenerate_graphs(ctx):
     cases_ = [
         G.HostGraph(np.zeros(1, np.int64), np.zeros(0, np.int32), np.zeros(0, np.int64)),  # empty
