@@ -42,7 +42,8 @@ def check_against_alone(ctx, graphs, lambdas, cfg, oracle_jobs=None):
         assert jobs[j]["levels"] == sd["levels"], (j, jobs[j]["levels"], sd["levels"])
         assert jobs[j]["top_moved"] == sd["top_moved"], j
         if oracle_jobs is None or j in oracle_jobs:
-            lo, No, so = O.cluster(H.to_oracle(h), p, q, O.Params(**cfg))
+            ocfg = {k: v for k, v in cfg.items() if k != "hub_limit"}  # a tuning field: no oracle counterpart
+            lo, No, so = O.cluster(H.to_oracle(h), p, q, O.Params(**ocfg))
             assert np.array_equal(labs[j], lo), f"job {j} labels differ from the oracle"
             assert jobs[j]["N"] == No, j
     return labs, jobs
@@ -102,6 +103,15 @@ def test_batch_hub_rows_every_bin(ctx):
               H.hub_graph(n=40000, m=60000, hubs=(16000, 25000, 31000, 14500), seed=21)]
     lams = [(1, 40), (1, 25), (1, 60)]
     check_against_alone(ctx, graphs, lams, dict())
+
+
+def test_batch_hub_partition_overflow_redo(ctx):
+    """A tiny hub_limit makes the hub partitions overflow inside a batch: the
+    batched call is redone with the global tables and every job still equals
+    the job alone (and the oracle)."""
+    graphs = [H.hub_graph(n=40000, m=60000, hubs=(16000, 25000, 31000, 14500), seed=21), H.hub_graph(seed=9)]
+    lams = [(1, 60), (1, 40)]
+    check_against_alone(ctx, graphs, lams, dict(hub_limit=64), oracle_jobs={0})
 
 
 def test_many_small_jobs_deterministic(ctx):
