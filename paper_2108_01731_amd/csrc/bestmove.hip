@@ -1186,11 +1186,18 @@ constexpr int HP_NT = 1024;
 constexpr int HP_SLOTS = 12288;
 constexpr int HP_LIMIT = HP_SLOTS * 7 / 10;
 constexpr int HP_STOP = HP_SLOTS - 2 * HP_NT;  // claims never exceed this
-// Every partition reads its whole row, so a level takes the partitions only
-// while its widest row needs at most 16 of them.
+// Up to this widest row every partition reads its whole row (at most 16
+// partitions); a level with wider rows first scatters each row's ids by
+// partition (k_hps_count, k_hps_scatter), so a partition reads only its own.
 constexpr int64_t HP_MAX_DEG = 65536;
+// Partitions per row are capped (LDS histograms); a row so wide that its
+// partitions then overflow takes the redo with the global tables.
+constexpr int HPS_MAXP = 4096;
 
-__host__ __device__ inline int64_t hp_parts(int64_t deg) { return cdiv(2 * (deg + 1), HP_LIMIT); }
+__host__ __device__ inline int64_t hp_parts(int64_t deg) {
+  const int64_t p = cdiv(2 * (deg + 1), HP_LIMIT);
+  return p < HPS_MAXP ? p : HPS_MAXP;
+}
 
 __device__ __forceinline__ uint32_t part_of(int32_t X, uint32_t P) {
   return (uint32_t)(((uint64_t)((uint32_t)X * 0x85EBCA6Bu) * (uint64_t)P) >> 32);
@@ -1309,11 +1316,14 @@ __device__ __forceinline__ bool lds_insert_bounded(int32_t *keys, Acc *vals, int
 // One block per partition: its clusters' weights summed in LDS, then scored
 // (as the per-row kernels do) into part[partition]; an overflow counts in
 // counter 6 of the launch.
-template <int WK, bool A32>
+template <int WK, bool A32, bool SEG>
 __global__ __launch_bounds__(HP_NT) void k_hp_part(AggArgs a, const int64_t *__restrict__ tot,
                                                    const int64_t *__restrict__ xoff,
                                                    const int64_t *__restrict__ pstart,
-                                                   const int32_t *__restrict__ xs, SegBest *__restrict__ part) {
+                                                   const int32_t *__restrict__ xs, SegBest *__restrict__ part,
+                                                   const int64_t *__restrict__ segstart,
+                                                   const int64_t *__restrict__ pcnt,
+                                                   const int64_t *__restrict__ ws) {
   using Acc = typename std::conditional<A32, int32_t, int64_t>::type;
   extern __shared__ __align__(16) unsigned char smem[];
   int32_t *keys = reinterpret_cast<int32_t *>(smem);
@@ -1349,12 +1359,17 @@ __global__ __launch_bounds__(HP_NT) void k_hp_part(AggArgs a, const int64_t *__r
     const int64_t beg = a.off[v], deg = a.off[v + 1] - beg;
     const uint32_t P = (uint32_t)(pstart[i + 1] - pstart[i]), p = (uint32_t)(pi - pstart[i]);
     const int32_t c = a.C[v];
-    const int32_t *x = xs + xoff[i];
+    const int32_t *x = SEG ? xs : xs + xoff[i];
     if (t == 0 && part_of(c, P) == p) lds_insert_bounded<Acc>(keys, vals, c, 0, &nclaim, HP_STOP);
-    for (int64_t j = t; j < deg; j += HP_NT) {
-      const int32_t X = x[j];
-      if (part_of(X, P) != p) continue;
-      lds_insert_bounded<Acc>(keys, vals, X, load_w<WK>(a.wt, beg + j), &nclaim, HP_STOP);
+    if constexpr (SEG) {  // this partition's ids and weights, scattered
+      const int64_t s0 = segstart[pi], s1 = s0 + pcnt[pi];
+      for (int64_t j = s0 + t; j < s1; j += HP_NT) lds_insert_bounded<Acc>(keys, vals, xs[j], ws[j], &nclaim, HP_STOP);
+    } else {
+      for (int64_t j = t; j < deg; j += HP_NT) {
+        const int32_t X = x[j];
+        if (part_of(X, P) != p) continue;
+        lds_insert_bounded<Acc>(keys, vals, X, load_w<WK>(a.wt, beg + j), &nclaim, HP_STOP);
+      }
     }
     __syncthreads();
     const bool over = nclaim > limit;  // block-uniform
@@ -1393,6 +1408,113 @@ __global__ __launch_bounds__(HP_NT) void k_hp_part(AggArgs a, const int64_t *__r
     }
   }
   if (t == 0 && overflows) atomic_add_i64(&a.ctr[(blockIdx.x % NSPREAD) * NCTR + 6], overflows);
+}
+
+// Chunk-parallel, as k_hp_gather, and counts the chunk's arcs per partition
+// of its row (LDS histogram, one global atomic per touched partition).
+__global__ __launch_bounds__(B7_NT) void k_hps_count(AggArgs a, const int64_t *__restrict__ tot,
+                                                     const int64_t *__restrict__ cstart,
+                                                     const int64_t *__restrict__ xoff,
+                                                     const int64_t *__restrict__ pstart, int32_t *__restrict__ xs,
+                                                     int64_t *__restrict__ pcnt) {
+  __shared__ int32_t hist[HPS_MAXP];
+  __shared__ int64_t sh_row;
+  const int32_t *list;
+  int64_t cnt7;
+  work_of(a, list, cnt7);
+  const int64_t nch = tot[0], n7 = tot[3];
+  const int t = threadIdx.x;
+  for (int64_t ch = blockIdx.x; ch < nch; ch += gridDim.x) {
+    __syncthreads();  // hist and sh_row are reused
+    if (t == 0) {
+      int64_t lo = 0, hi = n7 - 1;
+      while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if (cstart[mid] <= ch) lo = mid;
+        else hi = mid - 1;
+      }
+      sh_row = lo;
+    }
+    __syncthreads();
+    const int64_t i = sh_row;
+    const int32_t v = list[i];
+    const int64_t beg = a.off[v], end = a.off[v + 1];
+    const int64_t e0 = beg + (ch - cstart[i]) * B7_CHUNK;
+    const int64_t e1 = e0 + B7_CHUNK < end ? e0 + B7_CHUNK : end;
+    const uint32_t P = (uint32_t)(pstart[i + 1] - pstart[i]);
+    for (uint32_t k = t; k < P; k += B7_NT) hist[k] = 0;
+    __syncthreads();
+    int32_t *out = xs + xoff[i] - beg;
+    for (int64_t e = e0 + t; e < e1; e += B7_NT) {
+      const int32_t X = a.C[a.col[e]];
+      out[e] = X;
+      atomicAdd(&hist[part_of(X, P)], 1);
+    }
+    __syncthreads();
+    for (uint32_t k = t; k < P; k += B7_NT)
+      if (hist[k]) atomic_add_i64(&pcnt[pstart[i] + k], hist[k]);
+  }
+}
+
+// Chunk-parallel: reserves the chunk's range in each touched partition's
+// segment (one global atomic per partition) and places its ids and weights
+// there by LDS rank (the order inside a segment is immaterial: integer sums).
+template <int WK>
+__global__ __launch_bounds__(B7_NT) void k_hps_scatter(AggArgs a, const int64_t *__restrict__ tot,
+                                                       const int64_t *__restrict__ cstart,
+                                                       const int64_t *__restrict__ xoff,
+                                                       const int64_t *__restrict__ pstart,
+                                                       const int32_t *__restrict__ xs,
+                                                       const int64_t *__restrict__ segstart,
+                                                       int64_t *__restrict__ cursor, int32_t *__restrict__ ys,
+                                                       int64_t *__restrict__ ws) {
+  __shared__ int32_t hist[HPS_MAXP];
+  __shared__ int64_t base[HPS_MAXP];
+  __shared__ int64_t sh_row;
+  const int32_t *list;
+  int64_t cnt7;
+  work_of(a, list, cnt7);
+  const int64_t nch = tot[0], n7 = tot[3];
+  const int t = threadIdx.x;
+  for (int64_t ch = blockIdx.x; ch < nch; ch += gridDim.x) {
+    __syncthreads();
+    if (t == 0) {
+      int64_t lo = 0, hi = n7 - 1;
+      while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if (cstart[mid] <= ch) lo = mid;
+        else hi = mid - 1;
+      }
+      sh_row = lo;
+    }
+    __syncthreads();
+    const int64_t i = sh_row;
+    const int32_t v = list[i];
+    const int64_t beg = a.off[v], end = a.off[v + 1];
+    const int64_t e0 = beg + (ch - cstart[i]) * B7_CHUNK;
+    const int64_t e1 = e0 + B7_CHUNK < end ? e0 + B7_CHUNK : end;
+    const uint32_t P = (uint32_t)(pstart[i + 1] - pstart[i]);
+    const int64_t p0 = pstart[i];
+    const int32_t *x = xs + xoff[i] - beg;
+    for (uint32_t k = t; k < P; k += B7_NT) hist[k] = 0;
+    __syncthreads();
+    for (int64_t e = e0 + t; e < e1; e += B7_NT) atomicAdd(&hist[part_of(x[e], P)], 1);
+    __syncthreads();
+    for (uint32_t k = t; k < P; k += B7_NT) {
+      const int32_t h = hist[k];
+      if (h) base[k] = segstart[p0 + k] + (int64_t)atomicAdd(reinterpret_cast<unsigned long long *>(&cursor[p0 + k]),
+                                                             (unsigned long long)h);
+      hist[k] = 0;
+    }
+    __syncthreads();
+    for (int64_t e = e0 + t; e < e1; e += B7_NT) {
+      const int32_t X = x[e];
+      const uint32_t k = part_of(X, P);
+      const int64_t at = base[k] + atomicAdd(&hist[k], 1);
+      ys[at] = X;
+      ws[at] = load_w<WK>(a.wt, e);
+    }
+  }
 }
 
 size_t hp_lds_bytes(bool a32) { return (size_t)HP_SLOTS * (sizeof(int32_t) + (a32 ? 4 : 8)); }
@@ -2059,35 +2181,61 @@ template <int WK, bool PK> void launch_flat_pk(Ctx &c, AggArgs a, int64_t n7_ub,
   LAUNCHCHECK();
 }
 
-// Rows beyond the LDS tables through hash partitions in LDS (see k_hp_part).
+// Rows beyond the LDS tables through hash partitions in LDS (see k_hp_part),
+// reading whole rows or (c.hub_scatter) their ids scattered by partition.
 template <int WK> void launch_hub_part(Ctx &c, AggArgs a, int64_t n7_ub, int64_t a7_ub, bool a32) {
   n7_ub = std::max<int64_t>(n7_ub, 1);
+  const int64_t a7 = std::max<int64_t>(a7_ub, 1);
   int64_t *cstart = c.buf<int64_t>("hp.cstart", (size_t)n7_ub + 1);
   int64_t *xoff = c.buf<int64_t>("hp.xoff", (size_t)n7_ub + 1);
   int64_t *pstart = c.buf<int64_t>("hp.pstart", (size_t)n7_ub + 1);
   int64_t *tot = c.buf<int64_t>("hp.tot", 4);
-  int32_t *xs = c.buf<int32_t>("hp.xs", (size_t)std::max<int64_t>(a7_ub, 1));
-  // partitions: cdiv(2 (d + 1), HP_LIMIT) <= 2 (d + 1) / HP_LIMIT + 1 per row
+  int32_t *xs = c.buf<int32_t>("hp.xs", (size_t)a7);
+  // partitions: at most cdiv(2 (d + 1), HP_LIMIT) <= 2 (d + 1) / HP_LIMIT + 1 per row
   const int64_t parts_ub = 2 * (a7_ub + n7_ub) / HP_LIMIT + n7_ub + 1;
   SegBest *part = c.buf<SegBest>("hp.part", (size_t)parts_ub);
   hipLaunchKernelGGL(k_hp_layout, dim3(1), dim3(B7L_NT), 0, c.stream, a, cstart, xoff, pstart, tot);
   LAUNCHCHECK();
   const int64_t chunks = a7_ub / B7_CHUNK + n7_ub;
-  hipLaunchKernelGGL(k_hp_gather, dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(chunks, (int64_t)c.num_cu * 8))),
-                     dim3(B7_NT), 0, c.stream, a, (const int64_t *)tot, (const int64_t *)cstart,
-                     (const int64_t *)xoff, xs);
-  LAUNCHCHECK();
+  const dim3 gc((unsigned)std::max<int64_t>(1, std::min<int64_t>(chunks, (int64_t)c.num_cu * 8)));
+  const bool seg = c.hub_scatter;
+  int64_t *pcnt = nullptr, *segstart = nullptr, *ws = nullptr;
+  int32_t *ys = xs;
+  if (!seg) {
+    hipLaunchKernelGGL(k_hp_gather, gc, dim3(B7_NT), 0, c.stream, a, (const int64_t *)tot, (const int64_t *)cstart,
+                       (const int64_t *)xoff, xs);
+    LAUNCHCHECK();
+  } else {
+    pcnt = c.buf<int64_t>("hps.cnt", (size_t)parts_ub);
+    int64_t *cursor = c.buf<int64_t>("hps.cur", (size_t)parts_ub);
+    segstart = c.buf<int64_t>("hps.seg", (size_t)parts_ub);
+    ys = c.buf<int32_t>("hps.ys", (size_t)a7);
+    ws = c.buf<int64_t>("hps.ws", (size_t)a7);
+    HIPCHECK(hipMemsetAsync(pcnt, 0, (size_t)parts_ub * sizeof(int64_t), c.stream));
+    HIPCHECK(hipMemsetAsync(cursor, 0, (size_t)parts_ub * sizeof(int64_t), c.stream));
+    hipLaunchKernelGGL(k_hps_count, gc, dim3(B7_NT), 0, c.stream, a, (const int64_t *)tot, (const int64_t *)cstart,
+                       (const int64_t *)xoff, (const int64_t *)pstart, xs, pcnt);
+    LAUNCHCHECK();
+    scan<int64_t, int64_t>(c, pcnt, segstart, parts_ub, false, (int64_t *)nullptr);
+    hipLaunchKernelGGL((k_hps_scatter<WK>), gc, dim3(B7_NT), 0, c.stream, a, (const int64_t *)tot,
+                       (const int64_t *)cstart, (const int64_t *)xoff, (const int64_t *)pstart, (const int32_t *)xs,
+                       (const int64_t *)segstart, cursor, ys, ws);
+    LAUNCHCHECK();
+  }
   const size_t bytes = hp_lds_bytes(a32);
   const dim3 gp((unsigned)std::max<int64_t>(1, std::min<int64_t>(parts_ub, (int64_t)c.num_cu * 2)));
-  if (a32) {
-    allow_lds(c, k_hp_part<WK, true>, bytes);
-    hipLaunchKernelGGL((k_hp_part<WK, true>), gp, dim3(HP_NT), bytes, c.stream, a, (const int64_t *)tot,
-                       (const int64_t *)xoff, (const int64_t *)pstart, (const int32_t *)xs, part);
-  } else {
-    allow_lds(c, k_hp_part<WK, false>, bytes);
-    hipLaunchKernelGGL((k_hp_part<WK, false>), gp, dim3(HP_NT), bytes, c.stream, a, (const int64_t *)tot,
-                       (const int64_t *)xoff, (const int64_t *)pstart, (const int32_t *)xs, part);
-  }
+#define LCC_HP_PART(A32_, SEG_)                                                                                  \
+  do {                                                                                                          \
+    allow_lds(c, k_hp_part<WK, A32_, SEG_>, bytes);                                                            \
+    hipLaunchKernelGGL((k_hp_part<WK, A32_, SEG_>), gp, dim3(HP_NT), bytes, c.stream, a, (const int64_t *)tot,  \
+                       (const int64_t *)xoff, (const int64_t *)pstart, (const int32_t *)ys, part,               \
+                       (const int64_t *)segstart, (const int64_t *)pcnt, (const int64_t *)ws);                  \
+  } while (0)
+  if (a32 && seg) LCC_HP_PART(true, true);
+  else if (a32) LCC_HP_PART(true, false);
+  else if (seg) LCC_HP_PART(false, true);
+  else LCC_HP_PART(false, false);
+#undef LCC_HP_PART
   LAUNCHCHECK();
   hipLaunchKernelGGL(k_b7_final, dim3((unsigned)std::min<int64_t>(n7_ub, (int64_t)c.num_cu * 4)), dim3(B7_NT), 0,
                      c.stream, a, (const int64_t *)pstart, (const SegBest *)part);
@@ -2829,7 +2977,8 @@ void best_moves(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_para
                 int32_t phase, int32_t *C, const BMShape &shape, lcc_bm_stats &st, const BatchLevel *bl) {
   const int64_t wide_max = wide_slots(c, shape.acc32) * 7 / 10 - 1;
   c.hub_partition = false;
-  if (g.n <= 0 || shape.maxdeg <= wide_max || shape.maxdeg > HP_MAX_DEG) {
+  c.hub_scatter = shape.maxdeg > HP_MAX_DEG;
+  if (g.n <= 0 || shape.maxdeg <= wide_max) {
     best_moves_run(c, g, p, q, prm, level, phase, C, shape, st, bl);
     return;
   }

@@ -115,6 +115,7 @@ struct Ctx {
   // rows beyond the LDS tables go through LDS hash partitions in the current
   // Best-Moves call (else through global tables)
   bool hub_partition = false;
+  bool hub_scatter = false;  // ... scattered by partition first (levels with very wide rows)
   hipStream_t stream = nullptr;
   bool timing = false;
   std::map<std::string, KernelClass> kstats;

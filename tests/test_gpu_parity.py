@@ -263,6 +263,17 @@ def test_hub_partition_overflow_redoes_the_call(ctx):
             assert_same_bm(Co, so, Cd.cpu().numpy(), sd)
 
 
+def test_hub_rows_wider_than_65536(ctx):
+    """Rows wider than 65536 make the level scatter each hub row's ids by
+    partition before aggregating; with and without a forced redo the result
+    is the oracle's."""
+    h = H.hub_graph(n=150000, m=200000, hubs=(70000, 90000, 20000), seed=31)
+    lo, No, _ = O.cluster(H.to_oracle(h), 1, 80, oparams())
+    for limit in [0, 64]:
+        ld, Nd, _ = L.lcc_cluster(ctx, dev(h), 1, 80, dparams(hub_limit=limit))
+        assert np.array_equal(lo, ld.cpu().numpy()) and No == Nd, limit
+
+
 def test_tiny_and_degenerate_graphs(ctx):
     cases_ = [
         G.HostGraph(np.zeros(1, np.int64), np.zeros(0, np.int32), np.zeros(0, np.int64)),  # empty
