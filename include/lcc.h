@@ -114,6 +114,11 @@ typedef struct lcc_lambda {
   int64_t q;
 } lcc_lambda;
 
+/* Default and largest lcc_params.hub_limit: 7/10 of the 12288 slots of a hub
+ * partition's LDS table (a partition stops claiming slots at 10240, so a
+ * larger limit could let it drop clusters unnoticed). */
+#define LCC_HUB_LIMIT_MAX 8601
+
 /* Parameters.  The "semantic" fields define the result (two runs with equal
  * semantic fields and inputs return identical results); the "tuning" fields
  * never change a result. */
@@ -130,9 +135,10 @@ typedef struct lcc_params {
   /* tuning */
   int32_t validate; /* 1 = run the device validation pass on input graphs (default) */
   int32_t timing;   /* 1 = time every kernel launch with HIP events (see lcc_ctx_kernel_stats) */
-  int32_t hub_limit; /* 0 = default; > 0: distinct clusters a hash partition of a row beyond the LDS
-                        tables may hold before the call is redone with global tables (lowering it
-                        forces that path, for tests) */
+  int32_t hub_limit; /* 0 = default (LCC_HUB_LIMIT_MAX); 1 .. LCC_HUB_LIMIT_MAX: distinct clusters a
+                        hash partition of a row beyond the LDS tables may hold before the call is
+                        redone with global tables (lowering it forces that path, for tests); larger
+                        values are rejected with LCC_ERR_INVALID_ARG */
   int32_t reserved[5];
 } lcc_params;
 

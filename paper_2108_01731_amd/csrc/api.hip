@@ -100,7 +100,8 @@ static void check_params(const lcc_params *prm) {
   if (prm->allow_isolate != 0 && prm->allow_isolate != 1) fail(LCC_ERR_INVALID_ARG, "allow_isolate must be 0 or 1");
   if (prm->refine != 0 && prm->refine != 1) fail(LCC_ERR_INVALID_ARG, "refine must be 0 or 1");
   if (prm->stop_after_subrounds < 0) fail(LCC_ERR_INVALID_ARG, "stop_after_subrounds must be >= 0");
-  if (prm->hub_limit < 0) fail(LCC_ERR_INVALID_ARG, "hub_limit must be >= 0");
+  if (prm->hub_limit < 0 || prm->hub_limit > LCC_HUB_LIMIT_MAX)
+    fail(LCC_ERR_INVALID_ARG, "hub_limit must be in [0, " + std::to_string(LCC_HUB_LIMIT_MAX) + "]");
 }
 
 // --------------------------------------------------------- device validation

@@ -21,6 +21,7 @@ LCC_OK, LCC_ERR_INVALID_ARG, LCC_ERR_OVERFLOW, LCC_ERR_OUT_OF_MEMORY, LCC_ERR_DE
 LCC_WT_UNIT, LCC_WT_I16, LCC_WT_I32, LCC_WT_I64 = range(4)
 LCC_FRONTIER_ALL, LCC_FRONTIER_NBR = 0, 1
 LCC_TERM_NO_MOVES, LCC_TERM_NUM_ITER, LCC_TERM_STOPPED = 0, 1, 2
+LCC_HUB_LIMIT_MAX = 8601  # default and largest Params.hub_limit
 MAX_ITER_STATS = 64
 MAX_LEVELS = 64
 

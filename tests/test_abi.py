@@ -101,3 +101,18 @@ def test_product_package_never_touches_the_oracle():
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
                 assert "lcc_oracle" not in text and "orc_" not in text, f
+
+
+def test_hub_limit_bound_matches_the_kernel_tables():
+    """lcc.h's LCC_HUB_LIMIT_MAX (and the binding's copy) equals the hub
+    partition's default limit, and stays below the claim stop of its LDS
+    table: a partition that refuses a claim must then count as overflowing."""
+    hdr = open(HEADER).read()
+    header_max = int(re.search(r"#define LCC_HUB_LIMIT_MAX (\d+)", hdr).group(1))
+    src = open(os.path.join(ROOT, "paper_2108_01731_amd", "csrc", "bestmove.hip")).read()
+    slots = int(re.search(r"constexpr int HP_SLOTS = (\d+);", src).group(1))
+    nt = int(re.search(r"constexpr int HP_NT = (\d+);", src).group(1))
+    assert re.search(r"constexpr int HP_LIMIT = HP_SLOTS \* 7 / 10;", src)
+    assert re.search(r"constexpr int HP_STOP = HP_SLOTS - 2 \* HP_NT;", src)
+    assert header_max == slots * 7 // 10 == L.LCC_HUB_LIMIT_MAX
+    assert header_max < slots - 2 * nt

@@ -335,6 +335,18 @@ def test_invalid_inputs_are_rejected_before_any_output(ctx):
     host_c = torch.arange(100, dtype=torch.int32)
     with pytest.raises(L.LccError):
         L.lcc_best_move(ctx, g, 1, 2, dparams(), host_c)
+    # a hub partition limit above the default could drop clusters unnoticed
+    for bad_limit in (L.LCC_HUB_LIMIT_MAX + 1, -1):
+        with pytest.raises(L.LccError) as e:
+            L.lcc_cluster(ctx, g, 1, 2, dparams(hub_limit=bad_limit))
+        assert e.value.code == L.LCC_ERR_INVALID_ARG
+        with pytest.raises(L.LccError) as e:
+            L.lcc_best_move(ctx, g, 1, 2, dparams(hub_limit=bad_limit), C)
+        assert e.value.code == L.LCC_ERR_INVALID_ARG
+    assert torch.equal(C, torch.arange(100, dtype=torch.int32, device="cuda"))
+    lo, No, _ = O.cluster(H.to_oracle(h), 1, 2, oparams())
+    ld, Nd, _ = L.lcc_cluster(ctx, g, 1, 2, dparams(hub_limit=L.LCC_HUB_LIMIT_MAX))
+    assert np.array_equal(lo, ld.cpu().numpy()) and No == Nd
 
 
 def test_full_size_modularity_graph_sampled(ctx):
