@@ -115,6 +115,23 @@ def test_P2_decision_7_vertices_unit_weights():
                 assert D[v] == B.best_single_move(W, E, g.k, p, q, part, v)
 
 
+def test_P2_decision_8_vertices_signed_weights_every_partition():
+    """Same on an 8-vertex graph with signed weights and vertex weights
+    0..3, over all 4,140 partitions, with and without the empty cluster."""
+    n = 8
+    g = small(n, 18, 4242, wmin=-3, wmax=4, kmax=3)
+    W, E = B.dense(g)
+    U = np.arange(n, dtype=np.int32)
+    checked = 0
+    for (p, q), allow in [((2, 5), True), ((1, 4), False)]:
+        for part in B.partitions(n):
+            D = O.decide_many(g, p, q, part, U, allow_isolate=int(allow))
+            for v in range(n):
+                assert D[v] == B.best_single_move(W, E, g.k, p, q, part, v, allow_iso=allow), (part, v)
+                checked += 1
+    assert checked == 2 * 4140 * n
+
+
 # ------------------------------------------------------------ search sanity
 
 
