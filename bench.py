@@ -184,6 +184,7 @@ def main():
                      "avg_launch_ms": dom["ms"] / dom["launches"], "launches": dom["launches"]},
         "cpu_baseline": cpu,
     }
+    with_copy_peak(out["roofline"], dev)
     print(json.dumps(out), flush=True)
 
 
@@ -217,6 +218,36 @@ def measured_traffic(workload, kernel_class):
         if e.get("workload") == workload and e.get("class") == kernel_class and e.get("source_sha1") == sha:
             return e["fetch_bytes_per_launch"] + e["write_bytes_per_launch"]
     return None
+
+
+def copy_bandwidth_gbs(dev, nbytes=1 << 30, reps=5):
+    """Device-to-device copy rate (bytes read + written per second, GB/s):
+    the HBM rate a plain streaming kernel reaches on this GPU, measured after
+    the timed steps and reported next to the nominal peak."""
+    import torch
+
+    src = torch.empty(nbytes, dtype=torch.uint8, device=dev).fill_(1)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    b.record()
+    b.synchronize()
+    gbs = 2.0 * nbytes * reps / (a.elapsed_time(b) * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return gbs
+
+
+def with_copy_peak(roof, dev):
+    gbs = copy_bandwidth_gbs(dev)
+    log(f"device copy: {gbs:.0f} GB/s (read + write)")
+    roof["copy_gbs_measured"] = gbs
+    roof["frac_of_copy"] = roof["achieved"] / gbs
+    return roof
 
 
 def dominant_kernel(ks):
@@ -354,7 +385,7 @@ def run_batch(args, dev):
                    "speedup_vs_plain": dt_p / dt_b, "jobs_per_s_batched": J / dt_b,
                    "jobs_per_s_plain": J / dt_p, "identical_results": same,
                    **({"packed_batch_ms": dt_pk * 1e3, "speedup_vs_packed_batch": dt_pk / dt_b} if sweep else {})},
-        "roofline": dominant_kernel(ks),
+        "roofline": with_copy_peak(dominant_kernel(ks), dev),
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
