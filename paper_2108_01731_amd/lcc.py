@@ -297,11 +297,16 @@ def _bm_stats(st: _BMStats) -> dict:
 # ------------------------------------------------------------- entry points
 
 
+def _check_ids(C: torch.Tensor):
+    """A clustering argument: the library reads it as int32[n] in place."""
+    if not isinstance(C, torch.Tensor) or C.dtype != torch.int32 or not C.is_contiguous():
+        raise TypeError("C must be a contiguous int32 tensor")
+
+
 def lcc_best_move(ctx: Context, g: DeviceGraph, p: int, q: int, params: Params, C: torch.Tensor, level: int = 0,
                   phase: int = 0, stream=None) -> dict:
     """Best-Moves from clustering C (int32 device tensor, updated in place)."""
-    if C.dtype != torch.int32 or not C.is_contiguous():
-        raise TypeError("C must be a contiguous int32 tensor")
+    _check_ids(C)
     st = _BMStats()
     cg, cp = g._c(), params._c()
     _check(_lib.lcc_best_move(ctx._h, ctypes.byref(cg), _lam(p, q), ctypes.byref(cp), level, phase,
@@ -322,6 +327,7 @@ def _hip_copy(dst: torch.Tensor, src_ptr: int, nbytes: int):
 
 def lcc_compress(ctx: Context, g: DeviceGraph, C: torch.Tensor, stream=None):
     """Returns (contracted DeviceGraph, map int32 tensor)."""
+    _check_ids(C)
     dev = g.off.device
     mp = torch.empty(g.n, dtype=torch.int32, device=dev)
     h = ctypes.c_void_p()
@@ -356,6 +362,7 @@ def _num(o: _Objective) -> int:
 
 def lcc_objective(ctx: Context, g: DeviceGraph, p: int, q: int, C: torch.Tensor, stream=None) -> int:
     """Exact numerator N of the objective (value N / q)."""
+    _check_ids(C)
     o = _Objective()
     cg = g._c()
     _check(_lib.lcc_objective(ctx._h, ctypes.byref(cg), _lam(p, q), C.data_ptr() if C.numel() else None,

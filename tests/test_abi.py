@@ -116,3 +116,20 @@ def test_hub_limit_bound_matches_the_kernel_tables():
     assert re.search(r"constexpr int HP_STOP = HP_SLOTS - 2 \* HP_NT;", src)
     assert header_max == slots * 7 // 10 == L.LCC_HUB_LIMIT_MAX
     assert header_max < slots - 2 * nt
+
+
+def test_binding_rejects_clusterings_of_the_wrong_type():
+    """The library reads a clustering as int32[n]: the binding refuses other
+    dtypes and non-contiguous views before anything reaches the C ABI."""
+    import torch
+
+    g = L.DeviceGraph(off=torch.zeros(5, dtype=torch.int64), col=torch.zeros(0, dtype=torch.int32),
+                      k=torch.ones(4, dtype=torch.int64))
+    bad = [torch.zeros(4, dtype=torch.int64), torch.zeros(8, dtype=torch.int32)[::2], [0, 0, 0, 0]]
+    for C in bad:
+        with pytest.raises(TypeError):
+            L.lcc_best_move(None, g, 1, 2, L.Params(), C)
+        with pytest.raises(TypeError):
+            L.lcc_compress(None, g, C)
+        with pytest.raises(TypeError):
+            L.lcc_objective(None, g, 1, 2, C)
