@@ -223,6 +223,50 @@ def test_P4_modularity_special_case(seed):
         assert intra_arcs % 2 == 0
 
 
+def _modularity_exact(src, dst, deg, m, C):
+    """Textbook modularity sum_X [L_X/m - (D_X/2m)^2] as an exact fraction."""
+    Q = Fraction(0)
+    for X in set(C.tolist()):
+        L2 = int(((C[src] == X) & (C[dst] == X)).sum())  # each intra edge twice
+        DX = int(deg[C == X].sum())
+        Q += Fraction(L2, 2 * m) - Fraction(DX * DX, 4 * m * m)
+    return Q
+
+
+@pytest.mark.parametrize("seed", range(2))
+def test_P4_decisions_are_best_modularity_moves(seed):
+    """Modularity setting (k = degree, lambda = 1/(2m), no empty cluster):
+    every oracle decision against a clustering is the Louvain-style best
+    single move, found by recomputing the textbook modularity of the
+    clustering after each candidate move (exact fractions): the neighbor
+    cluster with the largest gain, ties to the lowest id, and a move only
+    when that gain is positive."""
+    h = G.sbm([20, 20, 20], 0.3, 0.03, seed + 11)
+    g = og(h)
+    deg = np.diff(g.off)
+    g.k = deg.astype(np.int64)
+    m = int(deg.sum()) // 2
+    p, q = 1, 2 * m
+    src = np.repeat(np.arange(g.n), deg)
+    rng = np.random.default_rng(seed)
+    C = rng.integers(0, 8, g.n).astype(np.int32)
+    D = O.decide_many(g, p, q, C, np.arange(g.n, dtype=np.int32), allow_isolate=0)
+    Q0 = _modularity_exact(src, g.col, deg, m, C)
+    moved = 0
+    for v in range(g.n):
+        c = int(C[v])
+        best, best_gain = c, Fraction(0)
+        for X in sorted({int(C[u]) for u in g.col[g.off[v]:g.off[v + 1]]} - {c}):
+            C2 = C.copy()
+            C2[v] = X
+            gain = _modularity_exact(src, g.col, deg, m, C2) - Q0
+            if gain > best_gain:
+                best, best_gain = X, gain
+        assert D[v] == best, (v, D[v], best)
+        moved += best != c
+    assert moved > 0
+
+
 # ------------------------------------------------------------------ compress
 
 
