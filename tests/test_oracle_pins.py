@@ -180,6 +180,30 @@ def test_P3_all_frontier_ends_in_single_move_local_optimum(seed):
         assert B.best_single_move(W, E, g.k, p, q, list(C), v) == C[v]
 
 
+def test_P3_refinement_ends_in_single_move_local_optimum():
+    """Sec. 3.2.3: refinement runs Best-Moves again on each level after the
+    coarse clustering is flattened onto it, so with frontier = all vertices
+    and a final call that ends without moves, the labels returned are a
+    single-move local optimum of the input graph (brute force).  Without
+    refinement some of the same runs are not, so the check has teeth."""
+    p, q = 1, 6
+    refined_checked, unrefined_not_optimal = 0, 0
+    for seed in range(12):
+        g = small(20, 60, 900 + seed, wmin=-2, wmax=5, kmax=3)
+        W, E = B.dense(g)
+        kw = dict(S=3, num_iter=200, frontier=O.FRONTIER_ALL, seed=seed)
+        lab, _, st = O.cluster(g, p, q, O.Params(refine=1, **kw))
+        if st["levels"] < 2 or st["iters_refine"][0] >= 200:
+            continue
+        for v in range(g.n):
+            assert B.best_single_move(W, E, g.k, p, q, list(lab), v) == lab[v], (seed, v)
+        refined_checked += 1
+        lab0, _, _ = O.cluster(g, p, q, O.Params(refine=0, **kw))
+        if any(B.best_single_move(W, E, g.k, p, q, list(lab0), v) != lab0[v] for v in range(g.n)):
+            unrefined_not_optimal += 1
+    assert refined_checked >= 10 and unrefined_not_optimal >= 3, (refined_checked, unrefined_not_optimal)
+
+
 def test_P3_cluster_vs_exhaustive_n10():
     """One 10-vertex case against all 115,975 partitions."""
     g = small(10, 20, 77, wmin=0, wmax=3, kmax=2)
