@@ -19,7 +19,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "liblcc.so")
 BUILD = os.path.join(ROOT, "_build", "lcc")
 
-ARCH = os.environ.get("LCC_OFFLOAD_ARCH", "gfx950")
+ARCH = "gfx950"  # MI355X (CDNA4)
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 
 CFLAGS = [
