@@ -133,3 +133,10 @@ def test_binding_rejects_clusterings_of_the_wrong_type():
             L.lcc_compress(None, g, C)
         with pytest.raises(TypeError):
             L.lcc_objective(None, g, 1, 2, C)
+
+
+def test_missing_library_fails_loudly(tmp_path, monkeypatch):
+    """There is no fallback: without liblcc.so the binding raises."""
+    monkeypatch.setattr(L, "_lib", None)
+    with pytest.raises(RuntimeError, match="not built"):
+        L.load_library(str(tmp_path / "liblcc.so"))
