@@ -133,7 +133,11 @@ typedef struct lcc_params {
   int32_t max_levels;           /* cap on the number of graphs in the hierarchy, 1..64 */
   int64_t stop_after_subrounds; /* > 0: lcc_best_move stops after this many sub-rounds */
   /* tuning */
-  int32_t validate; /* 1 = run the device validation pass on input graphs (default) */
+  int32_t validate; /* 1 = run the device validation pass on input graphs (default).  0 skips its
+                       per-arc checks (column range, self-loops, row order; offsets, k, kk and
+                       the overflow bounds are always checked): the caller then guarantees a
+                       valid graph, and a column id outside [0, n) is undefined behaviour
+                       (an out-of-bounds device read) */
   int32_t timing;   /* 1 = time every kernel launch with HIP events (see lcc_ctx_kernel_stats) */
   int32_t hub_limit; /* 0 = default (LCC_HUB_LIMIT_MAX); 1 .. LCC_HUB_LIMIT_MAX: distinct clusters a
                         hash partition of a row beyond the LDS tables may hold before the call is
