@@ -5,9 +5,12 @@ TEST INFRASTRUCTURE ONLY: the test suite, ``__graft_entry__.smoke()`` and the
 (``paper_2108_01731_amd``) never imports this package, and this package never
 imports the product library.
 
-The arithmetic lives in ``lcc_oracle.c`` (plain single-threaded C, integer
-only; see its header for the paper passages it follows).  This module only
-marshals numpy arrays through ctypes.
+The arithmetic lives in ``lcc_oracle.c`` (plain C, integer only; see its
+header for the paper passages it follows).  It is built twice from the same
+source: ``liblcc_oracle.so`` single-threaded, and ``liblcc_oracle_omp.so``
+with OpenMP, whose only parallel loop is the per-vertex decisions of a
+sub-round against one snapshot (identical results; ``use_openmp()`` selects
+it).  This module only marshals numpy arrays through ctypes.
 """
 from __future__ import annotations
 
@@ -22,9 +25,10 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "lcc_oracle.c")
 _LIB = os.path.join(_HERE, "liblcc_oracle.so")
+_LIB_OMP = os.path.join(_HERE, "liblcc_oracle_omp.so")
 
 OK, INVALID, OVERFLOW, NOMEM = 0, 1, 2, 3
-FRONTIER_ALL, FRONTIER_NBR = 0, 1
+FRONTIER_ALL, FRONTIER_NBR, FRONTIER_CLUSTERS = 0, 1, 2
 TERM_NO_MOVES, TERM_NUM_ITER, TERM_STOPPED = 0, 1, 2
 ISO = -1
 MAX_ITER_STATS = 64
@@ -38,14 +42,29 @@ class OracleError(RuntimeError):
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (plain C11, -O2)."""
-    if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp"
-        subprocess.check_call(
-            ["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-shared", "-fPIC", _SRC, "-o", tmp]
-        )
-        os.replace(tmp, _LIB)
+    """Compile the oracle with gcc (plain C11, -O2): the single-threaded
+    library and the OpenMP one."""
+    for out, extra in ((_LIB, ["-Wno-unknown-pragmas"]), (_LIB_OMP, ["-fopenmp"])):
+        if force or not os.path.exists(out):
+            tmp = out + ".tmp"
+            subprocess.check_call(
+                ["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", *extra, "-shared", "-fPIC", _SRC, "-o", tmp]
+            )
+            os.replace(tmp, out)
     return _LIB
+
+
+def use_openmp(on: bool = True):
+    """Route the module-level functions to the OpenMP build (True) or the
+    single-threaded one (False).  Returns the previous selection."""
+    if on and not os.path.exists(_LIB_OMP):
+        build(force=True)
+    return use_library(_LIB_OMP if on else None)
+
+
+def num_threads() -> int:
+    """Threads the selected build's decision loop uses (1 single-threaded)."""
+    return int(_load().orc_num_threads())
 
 
 class _Graph(ctypes.Structure):
@@ -155,6 +174,7 @@ def _load():
         gp = ctypes.POINTER(_Graph)
         sig = {
             "orc_mix64": (u64, [u64]),
+            "orc_num_threads": (ctypes.c_int, []),
             "orc_round_hash": (u64, [u64, i32, i32, i32]),
             "orc_color": (i32, [u64, i64, i32]),
             "orc_validate": (ctypes.c_int, [gp]),

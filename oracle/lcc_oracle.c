@@ -1,8 +1,13 @@
 /*
- * lcc_oracle.c -- plain, slow, single-threaded CPU reference for the LambdaCC
- * best-move local search, graph compression, objective and the multi-level
- * driver (Shi, Dhulipala, Eisenstat, Lacki, Mirrokni, "Scalable Community
- * Detection via Parallel Correlation Clustering", arXiv 2108.01731).
+ * lcc_oracle.c -- plain, slow CPU reference for the LambdaCC best-move local
+ * search, graph compression, objective and the multi-level driver (Shi,
+ * Dhulipala, Eisenstat, Lacki, Mirrokni, "Scalable Community Detection via
+ * Parallel Correlation Clustering", arXiv 2108.01731).
+ *
+ * It is single-threaded C.  Built with -fopenmp, the one parallel loop is the
+ * per-vertex decisions of a sub-round (each thread with its own scratch):
+ * those decisions read one fixed snapshot and write only their own slot, so
+ * the build returns exactly what the single-threaded build returns.
  *
  * TEST INFRASTRUCTURE ONLY.  This file is the parity oracle: only the test
  * suite, the smoke check and the CPU-baseline leg of the benchmark may load it.
@@ -45,6 +50,10 @@
  *     so every clustering seen between iterations uses ids in [0, n).
  *   - Frontier "neighbors of moved vertices": the union of N(v) over every v
  *     that moved in any sub-round of the iteration (v itself is not added).
+ *   - Frontier "neighbors of clusters" (Sec. 3.2.2, the clusters the movers
+ *     left): the union of N(u) over every u that, at the end of the
+ *     iteration, belongs to a cluster some vertex moved out of during the
+ *     iteration (moves in any sub-round; a cluster left empty adds nothing).
  *   - Compress numbers clusters by the rank of their id among non-empty ids;
  *     self-loops of the contracted graph are kept out of the adjacency, in a
  *     per-vertex self weight s, and kk (sum of k^2 over original members) is
@@ -56,6 +65,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 typedef __int128 i128;
 
@@ -66,6 +78,7 @@ typedef __int128 i128;
 
 #define ORC_FRONTIER_ALL 0
 #define ORC_FRONTIER_NBR 1
+#define ORC_FRONTIER_CLUSTERS 2
 
 #define ORC_TERM_NO_MOVES 0
 #define ORC_TERM_NUM_ITER 1
@@ -287,6 +300,39 @@ static int scratch_init(decide_scratch *d, int64_t n) {
 }
 static void scratch_free(decide_scratch *d) { free(d->acc); free(d->seen); free(d->list); }
 
+/* One scratch per thread of the decision loop (one without OpenMP). */
+#ifdef _OPENMP
+static int orc_threads(void) { return omp_get_max_threads(); }
+static int orc_thread(void) { return omp_get_thread_num(); }
+#else
+static int orc_threads(void) { return 1; }
+static int orc_thread(void) { return 0; }
+#endif
+
+static decide_scratch *scratch_init_all(int64_t n, int *count) {
+  int t = orc_threads();
+  decide_scratch *d = (decide_scratch *)calloc((size_t)t, sizeof(decide_scratch));
+  if (!d) return NULL;
+  for (int i = 0; i < t; i++) {
+    if (scratch_init(&d[i], n)) {
+      for (int j = 0; j <= i; j++) scratch_free(&d[j]);
+      free(d);
+      return NULL;
+    }
+  }
+  *count = t;
+  return d;
+}
+
+static void scratch_free_all(decide_scratch *d, int count) {
+  if (!d) return;
+  for (int i = 0; i < count; i++) scratch_free(&d[i]);
+  free(d);
+}
+
+/* Number of oracle threads the decision loop uses (1 in the plain build). */
+int orc_num_threads(void) { return orc_threads(); }
+
 /* The best move of v against a fixed snapshot (C, K, cnt), Algorithm 1's
  * per-vertex step with the Appendix A change in objective.  The change for
  * moving v from c to X != c, scaled by q, is
@@ -402,14 +448,17 @@ int orc_decide_many(const orc_graph *g, int64_t p, int64_t q, int32_t allow_iso,
   int64_t n = g->n;
   int64_t *K = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n ? 2 * n : 1));
   int32_t *cnt = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n ? 2 * n : 1));
-  decide_scratch sc;
+  int nsc = 0;
+  decide_scratch *sc = NULL;
   int rc = ORC_NOMEM;
-  if (!K || !cnt || scratch_init(&sc, n)) goto out;
+  if (!K || !cnt || !(sc = scratch_init_all(n, &nsc))) goto out;
   rc = cluster_totals(g, C, K, cnt);
-  if (!rc)
-    for (int64_t i = 0; i < nu; i++) D_out[i] = decide(g, p, q, allow_iso, C, K, cnt, U[i], &sc);
-  scratch_free(&sc);
+  if (!rc) {
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < nu; i++) D_out[i] = decide(g, p, q, allow_iso, C, K, cnt, U[i], &sc[orc_thread()]);
+  }
 out:
+  scratch_free_all(sc, nsc);
   free(K); free(cnt);
   return rc;
 }
@@ -436,6 +485,7 @@ static int best_move_impl(const orc_graph *g, int64_t p, int64_t q, const orc_pa
   if (!st) st = &local;
   memset(st, 0, sizeof(*st));
   if (prm->S < 1 || prm->num_iter < 0) return ORC_INVALID;
+  if (prm->frontier < ORC_FRONTIER_ALL || prm->frontier > ORC_FRONTIER_CLUSTERS) return ORC_INVALID;
   size_t nn = (size_t)(n ? n : 1);
   int64_t *K = (int64_t *)malloc(sizeof(int64_t) * 2 * nn);
   int32_t *cnt = (int32_t *)malloc(sizeof(int32_t) * 2 * nn);
@@ -444,11 +494,14 @@ static int best_move_impl(const orc_graph *g, int64_t p, int64_t q, const orc_pa
   int32_t *newid = (int32_t *)malloc(sizeof(int32_t) * nn);
   int32_t *U = (int32_t *)malloc(sizeof(int32_t) * nn);
   int32_t *D = (int32_t *)malloc(sizeof(int32_t) * nn);
-  decide_scratch sc;
+  /* clusters (ids in [0, 2n)) that a vertex moved out of in this iteration */
+  uint8_t *left = (uint8_t *)calloc(2 * nn, 1);
+  int nsc = 0;
+  decide_scratch *sc = NULL;
   int rc = ORC_NOMEM;
-  if (!K || !cnt || !active || !next || !newid || !U || !D || scratch_init(&sc, n)) goto out;
+  if (!K || !cnt || !active || !next || !newid || !U || !D || !left || !(sc = scratch_init_all(n, &nsc))) goto out;
   rc = cluster_totals(g, C, K, cnt);
-  if (rc) { scratch_free(&sc); goto out; }
+  if (rc) goto out;
   memset(active, 1, nn);
   st->term = ORC_TERM_NUM_ITER;
   for (int32_t it = 0; it < prm->num_iter; it++) {
@@ -466,17 +519,31 @@ static int best_move_impl(const orc_graph *g, int64_t p, int64_t q, const orc_pa
       for (int64_t v = 0; v < n; v++)
         if (active[v] && orc_color(h, v, prm->S) == s) U[nu++] = (int32_t)v;
       /* every decision of the sub-round reads the same snapshot */
+      int64_t arcs = 0;
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : arcs)
       for (int64_t i = 0; i < nu; i++) {
-        D[i] = decide(g, p, q, prm->allow_isolate, C, K, cnt, U[i], &sc);
-        st->arcs_scanned += g->off[U[i] + 1] - g->off[U[i]];
+        D[i] = decide(g, p, q, prm->allow_isolate, C, K, cnt, U[i], &sc[orc_thread()]);
+        arcs += g->off[U[i] + 1] - g->off[U[i]];
       }
+      st->arcs_scanned += arcs;
       st->vertices_processed += nu;
-      for (int64_t i = 0; i < nu; i++)
-        if (D[i] != C[U[i]]) orc_frontier_nbr(g, &U[i], 1, next);
+      for (int64_t i = 0; i < nu; i++) {
+        if (D[i] == C[U[i]]) continue;
+        if (prm->frontier == ORC_FRONTIER_NBR) orc_frontier_nbr(g, &U[i], 1, next);
+        left[C[U[i]]] = 1;
+      }
       int64_t mv = apply_moves(g, C, K, cnt, U, nu, D);
       moved_it += mv;
       st->subrounds++;
     }
+    if (prm->frontier == ORC_FRONTIER_CLUSTERS) {
+      /* neighbors of every vertex now in a cluster that someone left (ids
+       * are those of this iteration, before the fresh ones are renamed) */
+      for (int64_t u = 0; u < n; u++)
+        if (left[C[u]])
+          for (int64_t e = g->off[u]; e < g->off[u + 1]; e++) next[g->col[e]] = 1;
+    }
+    memset(left, 0, 2 * nn);
     rename_fresh(g, C, K, cnt, newid);
     if (it < ORC_MAX_ITER_STATS) { st->active_per_iter[it] = active_it; st->moves_per_iter[it] = moved_it; }
     st->moves += moved_it;
@@ -498,10 +565,10 @@ done:
     st->moves += mv;
     if (mv) st->moved_any = 1;
   }
-  scratch_free(&sc);
   rc = ORC_OK;
 out:
-  free(K); free(cnt); free(active); free(next); free(newid); free(U); free(D);
+  scratch_free_all(sc, nsc);
+  free(K); free(cnt); free(active); free(next); free(newid); free(U); free(D); free(left);
   return rc;
 }
 

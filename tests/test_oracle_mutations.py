@@ -41,15 +41,19 @@ MUTATIONS = {
                            "z = (z ^ (z >> 27)) * 0x94D049BB133111EDULL;"),
     "refine_skipped": ("    if (prm->refine) {\n      orc_bm_stats st;",
                        "    if (0 && prm->refine) {\n      orc_bm_stats st;"),
-    "frontier_from_stayers": ("        if (D[i] != C[U[i]]) orc_frontier_nbr(g, &U[i], 1, next);",
-                              "        if (D[i] == C[U[i]]) orc_frontier_nbr(g, &U[i], 1, next);"),
+    "frontier_from_stayers": ("        if (D[i] == C[U[i]]) continue;\n        if (prm->frontier == ORC_FRONTIER_NBR)",
+                              "        if (D[i] != C[U[i]]) continue;\n        if (prm->frontier == ORC_FRONTIER_NBR)"),
+    "clusters_frontier_from_targets": ("        left[C[U[i]]] = 1;",
+                                       "        left[D[i] == ORC_ISO ? g->n + U[i] : D[i]] = 1;"),
+    "clusters_frontier_marks_members": ("          for (int64_t e = g->off[u]; e < g->off[u + 1]; e++) next[g->col[e]] = 1;",
+                                        "          next[u] = 1;"),
     "apply_source_volume_kept": ("    K[c] -= g->k[v];\n    cnt[c] -= 1;", "    K[c] -= 0;\n    cnt[c] -= 1;"),
     "compress_self_weight_dropped": ("    intra[cv] += 2 * (i128)S_of(g, v);", "    intra[cv] += 0 * (i128)S_of(g, v);"),
     "labels_by_largest_member": ("    if ((int32_t)v < minv[C[v]]) minv[C[v]] = (int32_t)v;",
                                  "    if ((int32_t)v > minv[C[v]] || minv[C[v]] == INT32_MAX) minv[C[v]] = (int32_t)v;"),
     "moves_applied_at_once": (
-        "        st->arcs_scanned += g->off[U[i] + 1] - g->off[U[i]];\n",
-        "        st->arcs_scanned += g->off[U[i] + 1] - g->off[U[i]];\n"
+        "        arcs += g->off[U[i] + 1] - g->off[U[i]];\n",
+        "        arcs += g->off[U[i] + 1] - g->off[U[i]];\n"
         "        if (D[i] != C[U[i]]) { orc_frontier_nbr(g, &U[i], 1, next);"
         " moved_it += apply_moves(g, C, K, cnt, &U[i], 1, &D[i]); D[i] = C[U[i]]; }\n"),
     "flatten_drops_coarse_clustering": ("    for (int64_t v = 0; v < G[l].n; v++) Cl[l][v] = Cl[l + 1][map[l][v]];",
@@ -74,7 +78,9 @@ def _pins():
     checks += [P.test_P7_figure1_simultaneous_moves_lower_objective, P.test_P8_star_frontier_footnote,
                P.test_P9_symmetric_pair_swaps_or_merges, P.test_second_iteration_uses_neighbors_of_movers,
                P.test_isolation_takes_smallest_empty_ids, P.test_P3_refinement_ends_in_single_move_local_optimum,
-               P.test_P5_two_level_compress_invariant, P.test_canonical_labels_order_by_min_member]
+               P.test_P5_two_level_compress_invariant, P.test_canonical_labels_order_by_min_member,
+               P.test_clusters_frontier_reconsiders_neighbors_of_the_left_cluster,
+               P.test_clusters_frontier_second_iteration_matches_definition]
     for s in range(2):
         checks.append(lambda s=s: P.test_P4_decisions_are_best_modularity_moves(s))
     return checks

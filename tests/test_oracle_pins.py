@@ -517,6 +517,111 @@ def test_second_iteration_uses_neighbors_of_movers():
     assert np.array_equal(C, Cb)
 
 
+def test_clusters_frontier_reconsiders_neighbors_of_the_left_cluster():
+    """Sec. 3.2.2, "neighbors of clusters": after v leaves X = {v, u}, the
+    next iteration considers the neighbors of u (X's remaining member) even
+    when they are not neighbors of v.  Here w (adjacent to u only) is held
+    out of X by K_X = 2 and joins once v has left; the neighbors-of-moved
+    rule never reconsiders w and u moves to w instead (same partition,
+    other cluster ids).  k = 1, lambda = 2, S = 1, start {v,u}, {w}, {z,z2}."""
+    v, u, w, z, z2 = range(5)
+    g = _graph_from_edges(5, [(v, u, 4), (u, w, 3), (v, z, 10), (z, z2, 20)])
+    C0 = np.array([0, 0, 2, 3, 3], np.int32)
+    p, q = 2, 1
+    # iteration 0 by hand: v's best target is Z (10 - 2*2 = 6 > stay 4 - 2 = 2),
+    # w stays (3 - 2*2 < 0), u stays (4 - 2 > 3 - 2), z and z2 stay
+    W, E = B.dense(g)
+    for x in range(5):
+        want = 3 if x == v else C0[x]
+        assert B.best_single_move(W, E, g.k, p, q, list(C0), x) == want
+    Cc, sc = O.best_move(g, p, q, O.Params(S=1, frontier=O.FRONTIER_CLUSTERS), C0)
+    Cn, sn = O.best_move(g, p, q, O.Params(S=1, frontier=O.FRONTIER_NBR), C0)
+    # clusters rule: iteration 1 considers N(u) = {v, w}; w joins u's cluster 0
+    assert list(Cc) == [3, 0, 0, 3, 3] and sc["moves_per_iter"][:2] == [1, 1]
+    # neighbors-of-moved rule: iteration 1 considers N(v) = {u, z}; u joins w's cluster 2
+    assert list(Cn) == [3, 2, 2, 3, 3] and sn["moves_per_iter"][:2] == [1, 1]
+    assert sc["active_per_iter"][1] == 2 and sn["active_per_iter"][1] == 2
+    assert list(O.canonical_labels(Cc)) == list(O.canonical_labels(Cn))
+
+
+def test_clusters_frontier_second_iteration_matches_definition():
+    """Best-Moves with the neighbors-of-clusters rule equals explicit
+    sub-rounds whose second-iteration active set is built here from the
+    definition: the neighbors of every vertex that, at the end of the first
+    iteration, is in a cluster some mover left."""
+    g = og(G.sbm([30, 30, 30, 30], 0.12, 0.01, 6))
+    p, q, S, seed = 1, 8, 2, 9
+    C = np.arange(g.n, dtype=np.int32)
+    left = set()
+    movers = []
+    h = O.round_hash(seed, 0, 0, 0)
+    for s in range(S):
+        U = np.array([x for x in range(g.n) if O.color(h, x, S) == s], np.int32)
+        Cn, D, _ = O.subround(g, p, q, C, U, allow_isolate=0)
+        for x, d in zip(U, D):
+            if d != C[x]:
+                left.add(int(C[x]))
+                movers.append(int(x))
+        C = Cn
+    active = np.zeros(g.n, bool)
+    for x in range(g.n):
+        if int(C[x]) in left:
+            active[g.col[g.off[x]:g.off[x + 1]]] = True
+    nbr = O.frontier_nbr(g, movers).astype(bool)
+    assert not np.array_equal(active, nbr)  # the two rules differ on this input
+    h1 = O.round_hash(seed, 0, 0, 1)
+    U = np.array([x for x in range(g.n) if active[x] and O.color(h1, x, S) == 0], np.int32)
+    C, _, _ = O.subround(g, p, q, C, U, allow_isolate=0)
+    prm = O.Params(S=S, seed=seed, frontier=O.FRONTIER_CLUSTERS, allow_isolate=0, stop_after_subrounds=S + 1)
+    Cb, st = O.best_move(g, p, q, prm)
+    assert np.array_equal(C, Cb) and st["active_per_iter"][1] == int(active.sum())
+
+
+def test_openmp_build_returns_the_plain_results():
+    """The OpenMP build parallelizes only the decisions of a sub-round (one
+    snapshot): clusterings, objectives, statistics and decisions are those of
+    the single-threaded build."""
+    cases = [(og(G.chung_lu_planted(3000, 20000, 2.1, 0.3, seed=3)), 1, 40000),
+             (small(300, 1500, 5, wmin=-3, wmax=6, kmax=3), 1, 9),
+             (og(G.c1_sbm(1)), 1, 100)]
+    for g, p, q in cases:
+        for prm in (O.Params(), O.Params(S=1, frontier=O.FRONTIER_ALL, refine=0),
+                    O.Params(S=3, frontier=O.FRONTIER_CLUSTERS)):
+            prev = O.use_openmp(False)
+            try:
+                a = O.cluster(g, p, q, prm)
+                ba = O.best_move(g, p, q, prm)
+                da = O.decide_many(g, p, q, a[0], np.arange(g.n, dtype=np.int32))
+                O.use_openmp(True)
+                assert O.num_threads() >= 1
+                b = O.cluster(g, p, q, prm)
+                bb = O.best_move(g, p, q, prm)
+                db = O.decide_many(g, p, q, a[0], np.arange(g.n, dtype=np.int32))
+            finally:
+                O.use_library(prev)
+            assert np.array_equal(a[0], b[0]) and a[1] == b[1] and a[2] == b[2]
+            assert np.array_equal(ba[0], bb[0]) and ba[1] == bb[1]
+            assert np.array_equal(da, db)
+
+
+def test_precheck_negative_weight_bound_at_its_edge():
+    """The combined bound that applies once a weight is negative: a score of
+    a vertex with negative weights can reach -(q*Wabs + p*floor(Ktot^2/4)),
+    which must fit in int64.  One edge of weight -1, k = (1, 1): Wabs = 1,
+    Ktot = 2, floor(Ktot^2/4) = 1.  q + p = 2^63 - 1 is accepted, one more
+    is rejected, while every single bound holds; with the weight +1 the
+    combined bound does not apply."""
+    lim = 2**63 - 1
+    p = 2**62 - 1
+    neg = _graph_from_edges(2, [(0, 1, -1)])
+    pos = _graph_from_edges(2, [(0, 1, 1)])
+    assert O.precheck(neg, p, lim - p) == O.OK
+    assert O.precheck(neg, p, lim - p + 1) == O.OVERFLOW
+    assert O.precheck(pos, p, lim - p + 1) == O.OK
+    # each separate bound at the same p, q: q*Wabs, p*Ktot, p*floor(Ktot^2/4)
+    assert (lim - p + 1) * 1 <= lim and p * 2 <= lim and p * 1 <= lim
+
+
 def test_row_order_invariance_and_determinism():
     """Shuffling the arcs inside each row changes nothing."""
     h = G.random_signed(60, 200, 8, wmin=-2, wmax=4, kmax=3)
