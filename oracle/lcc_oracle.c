@@ -592,7 +592,58 @@ void orc_graph_free(orc_graph_out *o) {
  * k'(c) = K_c; kk'(c) = sum of kk over members; s'(c) = sum of members' s plus
  * the weight of the edges inside c; the edges between two clusters are
  * combined into one edge carrying the summed weight (kept even when the sum
- * is 0).  Rows of the output are sorted by neighbor id. */
+ * is 0).  Rows of the output are sorted by neighbor id.
+ *
+ * The row of coarse vertex c is formed from c's members (the vertices with
+ * map[v] = c): every arc to another cluster adds its weight to a dense
+ * accumulator indexed by the neighbor's number; the numbers it touched,
+ * sorted, with their sums, are the row.  A first pass over the rows only
+ * counts their lengths (so the output is allocated once), a second fills
+ * them.  Built with OpenMP, rows are formed in parallel, each thread with
+ * its own accumulator; a row is computed the same way by any thread. */
+typedef struct {
+  int64_t *acc;   /* weight sum per neighbor number, valid where stamp == row */
+  int64_t *stamp; /* row that last touched the number */
+  int32_t *list;  /* numbers touched by the current row */
+} row_scratch;
+
+static int row_scratch_init(row_scratch *r, int64_t n2) {
+  size_t m = (size_t)(n2 ? n2 : 1);
+  r->acc = (int64_t *)malloc(m * sizeof(int64_t));
+  r->stamp = (int64_t *)malloc(m * sizeof(int64_t));
+  r->list = (int32_t *)malloc(m * sizeof(int32_t));
+  if (!r->acc || !r->stamp || !r->list) return ORC_NOMEM;
+  for (size_t x = 0; x < m; x++) r->stamp[x] = -1;
+  return ORC_OK;
+}
+static void row_scratch_free(row_scratch *r) { free(r->acc); free(r->stamp); free(r->list); }
+
+static int cmp_i32(const void *a, const void *b) {
+  int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+  return (x > y) - (x < y);
+}
+
+/* Sums the arcs of c's members into r by neighbor number (arcs inside c
+ * skipped); returns the number of distinct neighbor numbers, listed in r. */
+static int64_t coarse_row(const orc_graph *g, const int32_t *map, const int64_t *mstart, const int32_t *members,
+                          int64_t c, row_scratch *r) {
+  int64_t cnt = 0;
+  for (int64_t i = mstart[c]; i < mstart[c + 1]; i++) {
+    int32_t v = members[i];
+    for (int64_t e = g->off[v]; e < g->off[v + 1]; e++) {
+      int32_t x = map[g->col[e]];
+      if ((int64_t)x == c) continue;
+      if (r->stamp[x] != c) {
+        r->stamp[x] = c;
+        r->acc[x] = 0;
+        r->list[cnt++] = x;
+      }
+      r->acc[x] += W(g, e);
+    }
+  }
+  return cnt;
+}
+
 int orc_compress(const orc_graph *g, const int32_t *C, orc_graph_out *out, int32_t *map) {
   int64_t n = g->n;
   memset(out, 0, sizeof(*out));
@@ -600,9 +651,10 @@ int orc_compress(const orc_graph *g, const int32_t *C, orc_graph_out *out, int32
   size_t nn = (size_t)(n ? n : 1);
   int32_t *rank = (int32_t *)malloc(sizeof(int32_t) * nn);
   uint8_t *present = (uint8_t *)calloc(nn, 1);
-  int64_t *trip = NULL;
+  int64_t *mstart = NULL, *len = NULL;
+  int32_t *members = NULL;
   i128 *intra = NULL;
-  int rc = ORC_NOMEM;
+  int rc = ORC_NOMEM, failed = 0;
   if (!rank || !present) goto fail;
   for (int64_t v = 0; v < n; v++) {
     if (C[v] < 0 || (int64_t)C[v] >= n) { rc = ORC_INVALID; goto fail; }
@@ -618,54 +670,72 @@ int orc_compress(const orc_graph *g, const int32_t *C, orc_graph_out *out, int32
   out->kk = (int64_t *)calloc(n2s, sizeof(int64_t));
   out->off = (int64_t *)calloc(n2s + 1, sizeof(int64_t));
   intra = (i128 *)calloc(n2s, sizeof(i128));
-  if (!out->k || !out->s || !out->kk || !out->off || !intra) goto fail;
-  int64_t ninter = 0;
+  mstart = (int64_t *)calloc(n2s + 1, sizeof(int64_t));
+  len = (int64_t *)calloc(n2s, sizeof(int64_t));
+  members = (int32_t *)malloc(sizeof(int32_t) * nn);
+  if (!out->k || !out->s || !out->kk || !out->off || !intra || !mstart || !len || !members) goto fail;
   for (int64_t v = 0; v < n; v++) {
     int32_t cv = map[v];
     out->k[cv] += g->k[v];
     out->kk[cv] += (int64_t)KK_of(g, v);
     intra[cv] += 2 * (i128)S_of(g, v);
-    for (int64_t e = g->off[v]; e < g->off[v + 1]; e++) {
+    for (int64_t e = g->off[v]; e < g->off[v + 1]; e++)
       if (map[g->col[e]] == cv) intra[cv] += W(g, e);
-      else ninter++;
-    }
   }
   /* each intra edge was seen from both endpoints, each self weight doubled */
   for (int64_t c = 0; c < n2; c++) out->s[c] = (int64_t)(intra[c] / 2);
-  trip = (int64_t *)malloc(sizeof(int64_t) * 3 * (size_t)(ninter ? ninter : 1));
-  if (!trip) goto fail;
-  int64_t t = 0;
-  for (int64_t v = 0; v < n; v++)
-    for (int64_t e = g->off[v]; e < g->off[v + 1]; e++) {
-      int32_t a = map[v], b = map[g->col[e]];
-      if (a == b) continue;
-      trip[3 * t] = a; trip[3 * t + 1] = b; trip[3 * t + 2] = W(g, e);
-      t++;
+  /* the members of every coarse vertex, in vertex order */
+  for (int64_t v = 0; v < n; v++) mstart[map[v] + 1]++;
+  for (int64_t c = 0; c < n2; c++) mstart[c + 1] += mstart[c];
+  for (int64_t c = 0; c < n2; c++) len[c] = mstart[c];
+  for (int64_t v = 0; v < n; v++) members[len[map[v]]++] = (int32_t)v;
+  /* row lengths */
+#pragma omp parallel
+  {
+    row_scratch r;
+    int ok = row_scratch_init(&r, n2) == ORC_OK;
+    if (!ok) {
+#pragma omp atomic write
+      failed = 1;
     }
-  /* sort by (row, column); the weight in the third slot only makes the order total */
-  qsort(trip, (size_t)ninter, 3 * sizeof(int64_t), cmp_triple);
-  int64_t m2 = 0;
-  for (int64_t i = 0; i < ninter; i++)
-    if (i == 0 || trip[3 * i] != trip[3 * (i - 1)] || trip[3 * i + 1] != trip[3 * (i - 1) + 1]) m2++;
+#pragma omp for schedule(dynamic, 64)
+    for (int64_t c = 0; c < n2; c++)
+      if (ok) len[c] = coarse_row(g, map, mstart, members, c, &r);
+    row_scratch_free(&r);
+  }
+  if (failed) goto fail;
+  for (int64_t c = 0; c < n2; c++) out->off[c + 1] = out->off[c] + len[c];
+  int64_t m2 = out->off[n2];
   out->arcs = m2;
   out->col = (int32_t *)malloc(sizeof(int32_t) * (size_t)(m2 ? m2 : 1));
   out->wt = (int64_t *)malloc(sizeof(int64_t) * (size_t)(m2 ? m2 : 1));
   if (!out->col || !out->wt) goto fail;
-  int64_t j = -1;
-  for (int64_t i = 0; i < ninter; i++) {
-    if (i == 0 || trip[3 * i] != trip[3 * (i - 1)] || trip[3 * i + 1] != trip[3 * (i - 1) + 1]) {
-      j++;
-      out->col[j] = (int32_t)trip[3 * i + 1];
-      out->wt[j] = 0;
-      out->off[trip[3 * i] + 1]++;
+  /* rows: sorted neighbor numbers with their summed weights */
+#pragma omp parallel
+  {
+    row_scratch r;
+    int ok = row_scratch_init(&r, n2) == ORC_OK;
+    if (!ok) {
+#pragma omp atomic write
+      failed = 1;
     }
-    out->wt[j] += trip[3 * i + 2];
+#pragma omp for schedule(dynamic, 64)
+    for (int64_t c = 0; c < n2; c++) {
+      if (!ok) continue;
+      int64_t cnt = coarse_row(g, map, mstart, members, c, &r);
+      qsort(r.list, (size_t)cnt, sizeof(int32_t), cmp_i32);
+      for (int64_t i = 0; i < cnt; i++) {
+        out->col[out->off[c] + i] = r.list[i];
+        out->wt[out->off[c] + i] = r.acc[r.list[i]];
+      }
+    }
+    row_scratch_free(&r);
   }
-  for (int64_t c = 0; c < n2; c++) out->off[c + 1] += out->off[c];
-  free(rank); free(present); free(trip); free(intra);
+  if (failed) goto fail;
+  free(rank); free(present); free(intra); free(mstart); free(len); free(members);
   return ORC_OK;
 fail:
-  free(rank); free(present); free(trip); free(intra);
+  free(rank); free(present); free(intra); free(mstart); free(len); free(members);
   orc_graph_free(out);
   return rc;
 }

@@ -28,8 +28,8 @@ MUTATIONS = {
                                   "out->s[c] = (int64_t)(intra[c]);"),
     "compress_kk_overwritten": ("out->kk[cv] += (int64_t)KK_of(g, v);",
                                 "out->kk[cv] = (int64_t)KK_of(g, v);"),
-    "compress_rows_unsorted": ("qsort(trip, (size_t)ninter, 3 * sizeof(int64_t), cmp_triple);",
-                               "qsort(trip, (size_t)ninter / 2, 3 * sizeof(int64_t), cmp_triple);"),
+    "compress_rows_unsorted": ("qsort(r.list, (size_t)cnt, sizeof(int32_t), cmp_i32);",
+                               "qsort(r.list, (size_t)cnt / 2, sizeof(int32_t), cmp_i32);"),
     "frontier_adds_mover": ("for (int64_t e = g->off[v]; e < g->off[v + 1]; e++) flags[g->col[e]] = 1;",
                             "flags[v] = 1; for (int64_t e = g->off[v]; e < g->off[v + 1]; e++) flags[g->col[e]] = 1;"),
     "fresh_ids_skip_first_empty": ("    while (cnt[x] != 0) x++;\n    newid[t] = (int32_t)x;",
