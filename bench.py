@@ -46,6 +46,10 @@ BATCH_WORKLOADS = {
 
 HBM_PEAK_GBS = 8000.0
 
+# Reports beyond the headline (see their functions): the paper's scalability
+# study on rMAT graphs and its quality study against ground truth.
+REPORTS = {}  # filled below: name -> (function, description)
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -56,8 +60,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="chung_lu_4m",
-                    choices=sorted(WORKLOADS) + sorted(BATCH_WORKLOADS) + ["serve_mixed"])
+    ap.add_argument("--workload", default="chung_lu_65m",
+                    choices=sorted(WORKLOADS) + sorted(BATCH_WORKLOADS) + ["serve_mixed"] + sorted(REPORTS))
     ap.add_argument("--slots", type=int, default=3, help="serve_mixed: concurrent batches")
     ap.add_argument("--jobs", type=int, default=0, help="batch workloads: use only the first JOBS jobs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -86,6 +90,8 @@ def main():
         del src, dst
     if args.workload in BATCH_WORKLOADS:
         return run_batch(args, dev)
+    if args.workload in REPORTS:
+        return REPORTS[args.workload][0](args, dev)
     if args.workload == "serve_mixed":
         return run_serve(args, dev)
     gen_kw, desc = WORKLOADS[args.workload]
@@ -126,6 +132,10 @@ def main():
     ctx.reset_kernel_stats()
     _, N_t, st_t = lcc.lcc_cluster(ctx, g, p, q, lcc.Params(timing=1))
     log(f"instrumented step: {st_t['ms_total']:.1f} ms")
+    log("levels (n, arcs, coarsening iterations, refinement iterations):")
+    for lv in range(st_t["levels"]):
+        log(f"  {lv:2d} n={st_t['n_level'][lv]:>10d} arcs={st_t['arcs_level'][lv]:>11d} "
+            f"it={st_t['iters_coarsen'][lv]:2d} ref={st_t['iters_refine'][lv]:2d}")
     if N_t != Ns[-1]:
         log(f"WARNING: the instrumented step's objective numerator {N_t} differs from {Ns[-1]}")
     ks = ctx.kernel_stats()
@@ -134,7 +144,9 @@ def main():
         log(f"  {name:24s} launches={v['launches']:6d} ms/step={v['ms']:8.2f} "
             f"GB/s={(v['bytes'] / sec / 1e9) if sec > 0 else 0:8.1f} "
             f"Gitems/s={(v['items'] / sec / 1e9) if sec > 0 else 0:7.2f}")
-    agg = {k: v for k, v in ks.items() if k.startswith(("bm_aggregate", "bm_single"))}
+    # the dominant kernel class among every aggregation class of Best-Moves
+    # (the hub-row class bm_flat_seq* is a short sequence of launches timed as one)
+    agg = {k: v for k, v in ks.items() if k.startswith(AGG_CLASSES)}
     dom_name, dom = max(agg.items(), key=lambda kv: kv[1]["ms"])
     achieved = dom["bytes"] / (dom["ms"] * 1e-3) / 1e9
     traffic = measured_traffic(args.workload, dom_name)
@@ -147,18 +159,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        import oracle as O
-
-        hn = h.numpy()
-        g_o = O.Graph(off=hn.off, col=hn.col, k=hn.k, wt=None if hn.wt is None else hn.wt.astype(np.int64))
-        S = prm.S
-        t1 = time.perf_counter()
-        _, so = O.best_move(g_o, p, q, O.Params(S=S, stop_after_subrounds=S))
-        cdt = time.perf_counter() - t1
-        cpu = {"value": so["arcs_scanned"] / cdt, "unit": "edges/s", "cores": 1, "kind": "oracle",
-               "sample": f"first Best-Moves iteration of level 0 ({S} sub-rounds over all {g.n} vertices, "
-                         f"{so['arcs_scanned']} arcs scanned) on the same graph, {cdt:.1f} s single-threaded"}
-        log(f"cpu oracle: {cpu['value']:.3e} arcs/s over {cdt:.1f}s")
+        cpu = cpu_baseline(h, p, q, prm.S)
 
     out = {
         "metric": "best-move edges/s",
@@ -186,6 +187,68 @@ def main():
     }
     with_copy_peak(out["roofline"], dev)
     print(json.dumps(out), flush=True)
+
+
+AGG_CLASSES = ("bm_aggregate", "bm_single", "bm_flat_seq")
+
+
+def host_cpu():
+    """(logical CPUs this process may run on, CPU model name)."""
+    try:
+        ncpu = len(os.sched_getaffinity(0))
+    except AttributeError:
+        ncpu = os.cpu_count() or 1
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return ncpu, model
+
+
+def cpu_baseline(h, p, q, S):
+    """The oracle timed on this host on a bounded sample of the workload:
+    level 0's first Best-Moves iteration (every vertex, S sub-rounds) with
+    the oracle's OpenMP build on all the threads OpenMP gives it (its results
+    equal the single-threaded build's), and, for reference, the
+    single-threaded build deciding a prefix of the vertices."""
+    import numpy as np
+
+    import oracle as O
+
+    hn = h.numpy()
+    g_o = O.Graph(off=hn.off, col=hn.col, k=hn.k, wt=None if hn.wt is None else hn.wt.astype(np.int64))
+    ncpu, model = host_cpu()
+    prev = O.use_openmp(True)
+    try:
+        threads = O.num_threads()
+        t1 = time.perf_counter()
+        _, so = O.best_move(g_o, p, q, O.Params(S=S, num_iter=1))
+        cdt = time.perf_counter() - t1
+    finally:
+        O.use_library(prev)
+    # single-threaded: decisions of the lowest-numbered vertices against the
+    # singleton clustering (the snapshot of level 0's first sub-round), up to
+    # about 1.5e8 arcs
+    deg = np.diff(hn.off)
+    U = np.arange(g_o.n, dtype=np.int64)[np.cumsum(deg) <= 150_000_000].astype(np.int32)
+    t2 = time.perf_counter()
+    O.decide_many(g_o, p, q, np.arange(g_o.n, dtype=np.int32), U)
+    sdt = time.perf_counter() - t2
+    one = float(deg[U].sum()) / sdt if sdt > 0 else None
+    out = {"value": so["arcs_scanned"] / cdt, "unit": "edges/s", "cores": threads, "kind": "oracle",
+           "sample": f"first Best-Moves iteration of level 0 ({S} sub-rounds over all {g_o.n} vertices, "
+                     f"{so['arcs_scanned']} arcs scanned) on the same graph, {cdt:.1f} s with the oracle's "
+                     f"OpenMP build on {threads} threads; single-threaded build deciding {len(U)} vertices "
+                     f"against the singleton clustering ({int(deg[U].sum())} arcs): {one:.3e} arcs/s",
+           "single_thread_value": one, "host_cpus": ncpu, "cpu_model": model}
+    log(f"cpu oracle: {out['value']:.3e} arcs/s over {cdt:.1f}s on {threads} threads "
+        f"({one:.3e} arcs/s single-threaded); host: {ncpu} CPUs, {model}")
+    return out
 
 
 KERNEL_SOURCES = ("common.hpp", "prims.hpp", "ops.hpp", "bestmove.hip")
@@ -251,7 +314,7 @@ def with_copy_peak(roof, dev):
 
 
 def dominant_kernel(ks):
-    agg = {k: v for k, v in ks.items() if k.startswith(("bm_aggregate", "bm_single"))}
+    agg = {k: v for k, v in ks.items() if k.startswith(AGG_CLASSES)}
     name, d = max(agg.items(), key=lambda kv: kv[1]["ms"])
     achieved = d["bytes"] / (d["ms"] * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -476,6 +539,253 @@ def run_serve(args, dev):
     print(json.dumps(out), flush=True)
     if not same:
         sys.exit(1)
+
+
+def sweep_labels(ctx, g, lams, prm):
+    """Labels of g under every (p, q) of lams, through lcc_sweep calls of at
+    most 16 resolutions each; returns (labels list, per-lambda job dicts)."""
+    from paper_2108_01731_amd import lcc
+
+    labs, jobs = [], []
+    for a in range(0, len(lams), lcc.SWEEP_MAX):
+        lab, jb, _ = lcc.lcc_sweep(ctx, g, lams[a:a + lcc.SWEEP_MAX], prm)
+        labs += list(lab.cpu().numpy())
+        jobs += jb
+    return labs, jobs
+
+
+def run_quality(args, dev):
+    """Average precision / recall against the planted communities of a
+    Chung-Lu graph (1M vertices, 10M edges, degree exponent 2.1, mixing 0.3),
+    the synthetic counterpart of the paper's quality curves (Sec. 4.3): the
+    correlation-clustering objective (k = 1) over lambda in {0.01 x : x = 1..99}
+    and modularity (k = degree) over gamma in {0.02 * 1.2^x : x = 1..99}
+    (lambda = gamma / 2m), keeping the gamma values within the int64 bounds.
+    Each community is matched to the cluster sharing most of its vertices;
+    the 5000 largest communities are scored."""
+    import numpy as np
+    import torch
+
+    from paper_2108_01731_amd import graphgen as G
+    from paper_2108_01731_amd import lcc
+    from paper_2108_01731_amd import quality as Q
+
+    t0 = time.time()
+    h, comm = G.chung_lu_planted(1_000_000, 10_000_000, 2.1, 0.3, seed=1, device=dev, k_is_degree=False,
+                                 return_communities=True)
+    g_cc = lcc.DeviceGraph.from_host(h, dev)
+    deg = (g_cc.off[1:] - g_cc.off[:-1]).contiguous()
+    g_mod = lcc.DeviceGraph(off=g_cc.off, col=g_cc.col, k=deg)
+    m2 = g_cc.arcs
+    log(f"quality workload: n={g_cc.n} arcs={m2} communities={len(np.unique(comm))} "
+        f"generated in {time.time() - t0:.1f}s")
+    ctx = lcc.context(0)
+    prm = lcc.Params()
+    lam_cc = [(x, 100) for x in range(1, 100)]
+    # modularity: lambda = gamma / (2m) = (gamma * 1000) / (2m * 1000), within
+    # q * sum|w| <= 2^63 - 1 and p * floor((sum k)^2 / 4) <= 2^63 - 1
+    lim = (1 << 63) - 1
+    q_mod = m2 * 1000
+    lam_mod, gam = [], []
+    for x in range(1, 100):
+        gmm = 0.02 * 1.2 ** x
+        pm = max(1, int(round(gmm * 1000)))
+        if q_mod * (m2 // 2) <= lim and pm * ((m2 * m2) // 4) <= lim:
+            lam_mod.append((pm, q_mod))
+            gam.append(gmm)
+    curves = {}
+    for name, g, lams, xs in (("cc", g_cc, lam_cc, [p / 100 for p, _ in lam_cc]), ("mod", g_mod, lam_mod, gam)):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        labs, jobs = sweep_labels(ctx, g, lams, prm)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        rows = []
+        for x, lab, jb in zip(xs, labs, jobs):
+            pr, rc, nc = Q.precision_recall(lab, comm, top=5000)
+            rows.append({"param": x, "precision": pr, "recall": rc, "clusters": jb["clusters"]})
+        curves[name] = {"rows": rows, "seconds": dt}
+        log(f"{name}: {len(lams)} resolutions in {dt:.2f}s")
+        for r in rows[:: max(1, len(rows) // 12)]:
+            log(f"  {'lambda' if name == 'cc' else 'gamma'}={r['param']:<10.4g} precision={r['precision']:.3f} "
+                f"recall={r['recall']:.3f} clusters={r['clusters']}")
+
+    def f1(r):
+        s = r["precision"] + r["recall"]
+        return 2 * r["precision"] * r["recall"] / s if s > 0 else 0.0
+
+    best = max(curves["cc"]["rows"], key=f1)
+    out = {"metric": "average precision / recall vs planted communities", "value": f1(best),
+           "unit": "F1 of the best lambda", "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
+           "dtype": "int64", "config": {"workload": args.workload, "description": REPORTS[args.workload][1],
+                                        "n": g_cc.n, "arcs": m2, "best_cc": best, "curves": curves}}
+    print(json.dumps(out), flush=True)
+
+
+def run_rmat(args, dev):
+    """The paper's scalability study (Sec. 4.2) on one GPU: rMAT graphs
+    (a = 0.5, b = c = 0.1, d = 0.3) with m = 5n, 50n and n^1.5 edge draws,
+    clustered with the correlation objective (k = 1) at lambda = 0.01 and
+    0.85; end-to-end time of lcc_cluster against the number of edges."""
+    import torch
+
+    from paper_2108_01731_amd import graphgen as G
+    from paper_2108_01731_amd import lcc
+
+    ctx = lcc.context(0)
+    prm = lcc.Params()
+    sizes = [(16, "5n"), (16, "50n"), (16, "n^1.5"), (18, "5n"), (18, "50n"), (18, "n^1.5"), (20, "5n"),
+             (20, "50n"), (22, "5n"), (22, "50n"), (20, "n^1.5")]
+    rows = []
+    for scale, kind in sizes:
+        n = 1 << scale
+        m = 5 * n if kind == "5n" else 50 * n if kind == "50n" else int(round(n ** 1.5))
+        t0 = time.time()
+        h = G.rmat(scale, m, seed=scale, device=dev)
+        g = lcc.DeviceGraph.from_host(h, dev)
+        del h
+        gen_s = time.time() - t0
+        for p, q in ((1, 100), (85, 100)):
+            lcc.lcc_cluster(ctx, g, p, q, prm)  # warm
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            reps = 3
+            for _ in range(reps):
+                _, N, st = lcc.lcc_cluster(ctx, g, p, q, prm)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t1) * 1e3 / reps
+            rows.append({"scale": scale, "m_rule": kind, "n": g.n, "edges": g.arcs // 2, "lambda": p / q,
+                         "ms": ms, "levels": st["levels"], "clusters": st["clusters"],
+                         "best_move_arcs": st["arcs_scanned_total"]})
+            log(f"rmat scale={scale} m={kind:6s} edges={g.arcs // 2:>11d} lambda={p / q:.2f}: {ms:9.2f} ms "
+                f"levels={st['levels']} clusters={st['clusters']} (generated in {gen_s:.1f}s)")
+        del g
+        torch.cuda.empty_cache()
+    big = max(rows, key=lambda r: (r["edges"], -r["lambda"]))
+    out = {"metric": "end-to-end cluster time vs edges (rMAT)", "value": big["edges"] / (big["ms"] * 1e-3),
+           "unit": "edges/s (largest graph, lambda 0.01)", "n_gpus": 1, "higher_is_better": True,
+           "data": "synthetic", "dtype": "int64",
+           "config": {"workload": args.workload, "description": REPORTS[args.workload][1], "rows": rows}}
+    print(json.dumps(out), flush=True)
+
+
+def run_ablation(args, dev):
+    """The S / frontier / refine ablation (the deterministic analog of the
+    paper's tuning study, Sec. 4.1): every combination of S in {1, 2, 4, 8},
+    frontier in {all vertices, neighbors of movers, neighbors of clusters}
+    and refinement on/off, on the 10k-vertex SBM (lambda = 1/100) and the
+    4M-vertex Chung-Lu modularity graph; end-to-end time, objective,
+    hierarchy depth and Best-Moves arcs per configuration."""
+    import torch
+
+    from paper_2108_01731_amd import graphgen as G
+    from paper_2108_01731_amd import lcc
+
+    ctx = lcc.context(0)
+    graphs = []
+    h = G.c1_sbm(1, device=dev)
+    graphs.append(("sbm_10k", lcc.DeviceGraph.from_host(h, dev), 1, 100))
+    h = G.chung_lu_planted(4_000_000, 100_000_000, 2.1, 0.3, seed=1, device=dev)
+    graphs.append(("chung_lu_4m", lcc.DeviceGraph.from_host(h, dev), 1, int(h.arcs)))
+    del h
+    names = {0: "all", 1: "nbr_movers", 2: "nbr_clusters"}
+    rows = []
+    for gname, g, p, q in graphs:
+        for S in (1, 2, 4, 8):
+            for fr in (0, 1, 2):
+                for rf in (0, 1):
+                    prm = lcc.Params(S=S, frontier=fr, refine=rf)
+                    lcc.lcc_cluster(ctx, g, p, q, prm)  # warm
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    _, N, st = lcc.lcc_cluster(ctx, g, p, q, prm)
+                    torch.cuda.synchronize()
+                    ms = (time.perf_counter() - t0) * 1e3
+                    rows.append({"graph": gname, "S": S, "frontier": names[fr], "refine": rf, "ms": ms,
+                                 "objective": N / q, "levels": st["levels"], "top_moved": st["top_moved"],
+                                 "clusters": st["clusters"], "best_move_arcs": st["arcs_scanned_total"]})
+                    log(f"{gname:12s} S={S} frontier={names[fr]:12s} refine={rf}: {ms:8.1f} ms "
+                        f"objective={N / q:.6g} levels={st['levels']:2d} clusters={st['clusters']} "
+                        f"arcs={st['arcs_scanned_total']}")
+    ref = [r for r in rows if r["graph"] == "chung_lu_4m" and r["S"] == 4 and r["frontier"] == "nbr_movers"
+           and r["refine"] == 1][0]
+    out = {"metric": "ablation: time and objective per (S, frontier, refine)", "value": ref["ms"],
+           "unit": "ms (4M-vertex graph, default settings)", "n_gpus": 1, "higher_is_better": False,
+           "data": "synthetic", "dtype": "int64",
+           "config": {"workload": args.workload, "description": REPORTS[args.workload][1], "rows": rows}}
+    print(json.dumps(out), flush=True)
+
+
+def run_async(args, dev):
+    """The asynchronous mode against the deterministic schedule (the paper
+    reports its asynchronous setting as the better one, Sec. 3.2.1, 4.1):
+    the 4M-vertex Chung-Lu modularity graph and the 65.6M-vertex one, five
+    seeds each, end-to-end time and objective (modularity-scaled) of the
+    default deterministic schedule (S = 4) and of asynchronous moves (S = 1,
+    the paper's setting, and S = 4).
+    The asynchronous results differ from run to run; the report gives their
+    distribution."""
+    import numpy as np
+    import torch
+
+    from paper_2108_01731_amd import graphgen as G
+    from paper_2108_01731_amd import lcc
+
+    ctx = lcc.context(0)
+    rows = []
+    for gname, kw in (("chung_lu_4m", WORKLOADS["chung_lu_4m"][0]), ("chung_lu_65m", WORKLOADS["chung_lu_65m"][0])):
+        kw = dict(kw)
+        h = G.chung_lu_planted(kw.pop("n"), kw.pop("m"), kw.pop("gamma"), kw.pop("mixing"), kw.pop("seed"),
+                               device=dev)
+        g = lcc.DeviceGraph.from_host(h, dev)
+        p, q = 1, int(h.arcs)
+        del h
+        torch.cuda.empty_cache()
+        for mode, base in (("sync", dict()), ("async", dict(S=1, async_moves=1)),
+                           ("async_s4", dict(S=4, async_moves=1))):
+            lcc.lcc_cluster(ctx, g, p, q, lcc.Params(**base))  # warm
+            for seed in range(1, 6):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, N, st = lcc.lcc_cluster(ctx, g, p, q, lcc.Params(seed=seed, **base))
+                torch.cuda.synchronize()
+                ms = (time.perf_counter() - t0) * 1e3
+                mod = N / q / (g.arcs / 2)
+                rows.append({"graph": gname, "mode": mode, "seed": seed, "ms": ms, "modularity_scaled": mod,
+                             "levels": st["levels"], "clusters": st["clusters"]})
+                log(f"{gname:12s} {mode:5s} seed={seed}: {ms:8.1f} ms objective/m={mod:.6f} "
+                    f"levels={st['levels']} clusters={st['clusters']}")
+        del g
+        torch.cuda.empty_cache()
+    summ = {}
+    for gname in ("chung_lu_4m", "chung_lu_65m"):
+        for mode in ("sync", "async", "async_s4"):
+            r = [x for x in rows if x["graph"] == gname and x["mode"] == mode]
+            summ[f"{gname}/{mode}"] = {"ms_mean": float(np.mean([x["ms"] for x in r])),
+                                       "objective_mean": float(np.mean([x["modularity_scaled"] for x in r])),
+                                       "objective_min": float(min(x["modularity_scaled"] for x in r)),
+                                       "objective_max": float(max(x["modularity_scaled"] for x in r))}
+            log(f"{gname}/{mode}: {summ[f'{gname}/{mode}']}")
+    big = summ["chung_lu_65m/async"]
+    out = {"metric": "asynchronous vs deterministic schedule: time and objective over seeds",
+           "value": big["ms_mean"], "unit": "ms (65.6M-vertex graph, asynchronous, mean of 5 seeds)",
+           "n_gpus": 1, "higher_is_better": False, "data": "synthetic", "dtype": "int64",
+           "config": {"workload": args.workload, "description": REPORTS[args.workload][1], "summary": summ,
+                      "rows": rows}}
+    print(json.dumps(out), flush=True)
+
+
+REPORTS.update({
+    "async_vs_sync": (run_async, "asynchronous moves (S=1 and S=4) vs the deterministic schedule (S=4) on the 4M "
+                                 "and 65.6M-vertex Chung-Lu modularity graphs, 5 seeds each"),
+    "ablation": (run_ablation, "S in {1,2,4,8} x frontier {all, neighbors of movers, neighbors of clusters} x "
+                               "refine {0,1} on the 10k SBM and the 4M Chung-Lu modularity graph"),
+    "quality_chung_lu_1m": (run_quality, "average precision/recall vs planted communities on a 1M-vertex, 10M-edge "
+                                         "Chung-Lu graph (mixing 0.3), lambda grid 0.01..0.99 (k=1) and gamma "
+                                         "grid 0.02*1.2^x (k=degree)"),
+    "rmat_scaling": (run_rmat, "rMAT a=0.5 b=c=0.1 d=0.3, n = 2^16..2^22, m = 5n, 50n, n^1.5 edge draws; "
+                               "k=1, lambda 0.01 and 0.85; end-to-end lcc_cluster time vs edges"),
+})
 
 
 if __name__ == "__main__":

@@ -42,6 +42,7 @@
 #ifndef LCC_H
 #define LCC_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -66,10 +67,14 @@ enum {
   LCC_WT_I64 = 3   /* int64 per arc */
 };
 
-/* Frontier rule between iterations of Best-Moves (paper Sec. 3.2.2). */
+/* Frontier rule between iterations of Best-Moves (paper Sec. 3.2.2, the two
+ * ways of shrinking the set of vertices considered). */
 enum {
-  LCC_FRONTIER_ALL = 0, /* every vertex is considered in every iteration */
-  LCC_FRONTIER_NBR = 1  /* neighbors of the vertices that moved in the last iteration */
+  LCC_FRONTIER_ALL = 0,     /* every vertex is considered in every iteration */
+  LCC_FRONTIER_NBR = 1,     /* neighbors of the vertices that moved in the last iteration */
+  LCC_FRONTIER_CLUSTERS = 2 /* neighbors of every vertex that, at the end of the last iteration, is in a
+                               cluster some vertex moved out of during it (a cluster left empty adds
+                               nothing; ids are those before fresh ids are renamed) */
 };
 
 /* Why a Best-Moves call stopped. */
@@ -143,12 +148,32 @@ typedef struct lcc_params {
                         hash partition of a row beyond the LDS tables may hold before the call is
                         redone with global tables (lowering it forces that path, for tests); larger
                         values are rejected with LCC_ERR_INVALID_ARG */
-  int32_t reserved[5];
+  int32_t queue_ahead; /* 0 = automatic; k > 0: Best-Moves queues k iterations on the device between
+                          two reads of its counters (an iteration queued after the one that ends the
+                          call changes nothing: every vertex stays, or the frontier is empty) */
+  int32_t small_level; /* 0 = default (LCC_SMALL_LEVEL_MAX); 1 .. LCC_SMALL_LEVEL_MAX: levels of at most
+                          this many vertices run their iterations through the single-block partition
+                          and iteration-end kernels (larger values are rejected) */
+  int32_t low_merge;   /* 0 = default (32768); k > 0: a level with at most k rows of degree < 256 takes
+                          them in one launch instead of one per degree bin */
+  /* mode (changes results) */
+  int32_t async_moves; /* 1 = the paper's asynchronous setting (Sec. 3.2.1): a vertex's move is applied
+                          the moment it is decided, so the other decisions of its sub-round see it or
+                          not as the hardware happens to order them.  The result is a valid clustering
+                          with its exact objective, but it is not deterministic and is not the oracle's
+                          (the deterministic schedule above is the default, 0) */
+  int32_t no_graph_replay; /* 0 = default: a small level's chunk of iterations that repeats exactly (a
+                              repeated call on the same buffers) runs as one cached HIP graph; 1 = every
+                              launch goes out on its own */
 } lcc_params;
+
+/* Largest lcc_params.small_level (one block of 1024 threads partitions a
+ * level this size). */
+#define LCC_SMALL_LEVEL_MAX 8192
 
 /* Fills the defaults: S = 4, num_iter = 10, seed = 1, frontier = NBR,
  * refine = 1, allow_isolate = 1, max_levels = 64, stop_after_subrounds = 0,
- * validate = 1, timing = 0. */
+ * validate = 1, timing = 0, and 0 (automatic) for the other tuning fields. */
 void lcc_params_default(lcc_params *prm);
 
 typedef struct lcc_bm_stats {
@@ -189,10 +214,32 @@ typedef struct lcc_cluster_stats {
 typedef struct lcc_ctx lcc_ctx;
 typedef struct lcc_graph_owned lcc_graph_owned;
 
+/* Device memory supplied by the caller (for instance a caching allocator such
+ * as torch's) for a context's scratch and for the graphs it returns, so that
+ * growing a buffer never calls hipFree, which waits for the whole device.
+ *   alloc(user, bytes, stream): at least `bytes` bytes of memory of the
+ *     context's device, 256-byte aligned, for work queued on `stream` (the
+ *     stream of the call that needs it); NULL means out of memory
+ *     (LCC_ERR_OUT_OF_MEMORY)
+ *   free(user, ptr, bytes, stream): returns a block with the size and stream
+ *     it was allocated for.  Before returning a block during a call, the
+ *     library drains the call's stream, so nothing queued still reads it.
+ * Both are called on the thread that called into the library.  A context
+ * that uses one stream for all its calls suits a stream-ordered allocator
+ * (blocks are reused on the stream they were allocated for). */
+typedef struct lcc_allocator {
+  void *(*alloc)(void *user, size_t bytes, void *stream);
+  void (*free)(void *user, void *ptr, size_t bytes, void *stream);
+  void *user;
+} lcc_allocator;
+
 /* Creates a context bound to HIP device `device`.  Scratch memory is
  * allocated lazily, grows to the largest graph seen, and is kept until
- * lcc_ctx_destroy.  Errors: INVALID_ARG (NULL out), DEVICE. */
-lcc_status lcc_ctx_create(int32_t device, lcc_ctx **out);
+ * lcc_ctx_destroy.  alloc (host, nullable, copied) supplies the device
+ * memory; NULL = hipMalloc / hipFree.  Graphs returned by lcc_compress are
+ * freed with lcc_graph_owned_free before the context is destroyed.
+ * Errors: INVALID_ARG (NULL out, alloc with a NULL callback), DEVICE. */
+lcc_status lcc_ctx_create(int32_t device, const lcc_allocator *alloc, lcc_ctx **out);
 lcc_status lcc_ctx_destroy(lcc_ctx *ctx);
 
 /* Thread-local message for the last failed call on this thread ("" if none). */

@@ -95,21 +95,22 @@ static void check_params(const lcc_params *prm) {
   if (!prm) fail(LCC_ERR_INVALID_ARG, "params is NULL");
   if (prm->S < 1 || prm->S > 64) fail(LCC_ERR_INVALID_ARG, "S must be in [1, 64]");
   if (prm->num_iter < 0) fail(LCC_ERR_INVALID_ARG, "num_iter must be >= 0");
-  if (prm->frontier != LCC_FRONTIER_ALL && prm->frontier != LCC_FRONTIER_NBR)
+  if (prm->frontier != LCC_FRONTIER_ALL && prm->frontier != LCC_FRONTIER_NBR &&
+      prm->frontier != LCC_FRONTIER_CLUSTERS)
     fail(LCC_ERR_INVALID_ARG, "unknown frontier rule");
   if (prm->allow_isolate != 0 && prm->allow_isolate != 1) fail(LCC_ERR_INVALID_ARG, "allow_isolate must be 0 or 1");
   if (prm->refine != 0 && prm->refine != 1) fail(LCC_ERR_INVALID_ARG, "refine must be 0 or 1");
   if (prm->stop_after_subrounds < 0) fail(LCC_ERR_INVALID_ARG, "stop_after_subrounds must be >= 0");
   if (prm->hub_limit < 0 || prm->hub_limit > LCC_HUB_LIMIT_MAX)
     fail(LCC_ERR_INVALID_ARG, "hub_limit must be in [0, " + std::to_string(LCC_HUB_LIMIT_MAX) + "]");
+  if (prm->queue_ahead < 0) fail(LCC_ERR_INVALID_ARG, "queue_ahead must be >= 0");
+  if (prm->small_level < 0 || prm->small_level > LCC_SMALL_LEVEL_MAX)
+    fail(LCC_ERR_INVALID_ARG, "small_level must be in [0, " + std::to_string(LCC_SMALL_LEVEL_MAX) + "]");
+  if (prm->low_merge < 0) fail(LCC_ERR_INVALID_ARG, "low_merge must be >= 0");
+  if (prm->async_moves != 0 && prm->async_moves != 1) fail(LCC_ERR_INVALID_ARG, "async_moves must be 0 or 1");
 }
 
 // --------------------------------------------------------- device validation
-
-__device__ __forceinline__ uint64_t sat_add(uint64_t a, uint64_t b) {
-  uint64_t s = a + b;
-  return s < a ? ~0ull : s;
-}
 
 __device__ __forceinline__ uint64_t wave_sat_sum(uint64_t x) {
 #pragma unroll
@@ -136,16 +137,15 @@ enum : uint64_t {
 };
 
 constexpr int VA_NT = 256;
-constexpr int NPART = 8;  // err, ktot, kksum, sabs, neg, maxdeg, wabs2, (spare)
 
-// Per-vertex checks and sums.  part[b*NPART + i].
+// Per-vertex checks and sums: one row of VAL_VROW values per block.
 __global__ __launch_bounds__(VA_NT) void k_validate_vertices(const int64_t *__restrict__ off, int64_t n, int64_t arcs,
                                                              const int64_t *__restrict__ k,
                                                              const int64_t *__restrict__ kk,
                                                              const int64_t *__restrict__ s,
                                                              const int32_t *__restrict__ C,
                                                              uint64_t *__restrict__ part) {
-  __shared__ uint64_t red[NPART][VA_NT / WAVE];
+  __shared__ uint64_t red[VAL_VROW][VA_NT / WAVE];
   uint64_t err = 0, ktot = 0, kks = 0, sabs = 0, neg = 0, maxdeg = 0;
   if (blockIdx.x == 0 && threadIdx.x == 0 && (off[0] != 0 || off[n] != arcs)) err |= E_ENDS;
   for (int64_t v = (int64_t)blockIdx.x * VA_NT + threadIdx.x; v < n; v += (int64_t)gridDim.x * VA_NT) {
@@ -173,14 +173,14 @@ __global__ __launch_bounds__(VA_NT) void k_validate_vertices(const int64_t *__re
     }
     if (C && (C[v] < 0 || (int64_t)C[v] >= n)) err |= E_C;
   }
-  uint64_t vals[NPART] = {wave_or(err), wave_sat_sum(ktot), wave_sat_sum(kks), wave_sat_sum(sabs), wave_or(neg),
+  uint64_t vals[VAL_VROW] = {wave_or(err), wave_sat_sum(ktot), wave_sat_sum(kks), wave_sat_sum(sabs), wave_or(neg),
                           wave_max(maxdeg), 0, 0};
   const int w = threadIdx.x / WAVE;
   if (lane_id() == 0)
-    for (int i = 0; i < NPART; i++) red[i][w] = vals[i];
+    for (int i = 0; i < VAL_VROW; i++) red[i][w] = vals[i];
   __syncthreads();
   if (threadIdx.x == 0) {
-    uint64_t r[NPART] = {0};
+    uint64_t r[VAL_VROW] = {0};
     for (int j = 0; j < VA_NT / WAVE; j++) {
       r[0] |= red[0][j];
       r[1] = sat_add(r[1], red[1][j]);
@@ -189,7 +189,7 @@ __global__ __launch_bounds__(VA_NT) void k_validate_vertices(const int64_t *__re
       r[4] |= red[4][j];
       r[5] = red[5][j] > r[5] ? red[5][j] : r[5];
     }
-    for (int i = 0; i < NPART; i++) part[(int64_t)blockIdx.x * NPART + i] = r[i];
+    for (int i = 0; i < VAL_VROW; i++) part[(int64_t)blockIdx.x * VAL_VROW + i] = r[i];
   }
 }
 
@@ -256,11 +256,6 @@ __global__ __launch_bounds__(VA_NT) void k_validate_arcs(const int64_t *__restri
   }
 }
 
-static uint64_t host_sat_add(uint64_t a, uint64_t b) {
-  uint64_t s = a + b;
-  return s < a ? ~0ull : s;
-}
-
 static std::string err_text(uint64_t e) {
   std::string s;
   if (e & E_ENDS) s += "off[0] must be 0 and off[n] must equal arcs; ";
@@ -273,68 +268,81 @@ static std::string err_text(uint64_t e) {
   return s;
 }
 
+void launch_validate_vertices(hipStream_t stream, const lcc_graph &g, const int32_t *C, int64_t nb, uint64_t *part) {
+  hipLaunchKernelGGL(k_validate_vertices, dim3((unsigned)nb), dim3(VA_NT), 0, stream, g.off, g.n, g.arcs, g.k, g.kk,
+                     g.s, C, part);
+  LAUNCHCHECK();
+}
+
+void launch_validate_arcs(hipStream_t stream, const lcc_graph &g, bool check, int64_t nb, uint64_t *part) {
+  switch (g.wt_kind) {
+    case LCC_WT_UNIT:
+      hipLaunchKernelGGL((k_validate_arcs<LCC_WT_UNIT>), dim3((unsigned)nb), dim3(VA_NT), 0, stream, g.off, g.col,
+                         g.wt, g.n, (int)check, part);
+      break;
+    case LCC_WT_I16:
+      hipLaunchKernelGGL((k_validate_arcs<LCC_WT_I16>), dim3((unsigned)nb), dim3(VA_NT), 0, stream, g.off, g.col,
+                         g.wt, g.n, (int)check, part);
+      break;
+    case LCC_WT_I32:
+      hipLaunchKernelGGL((k_validate_arcs<LCC_WT_I32>), dim3((unsigned)nb), dim3(VA_NT), 0, stream, g.off, g.col,
+                         g.wt, g.n, (int)check, part);
+      break;
+    default:
+      hipLaunchKernelGGL((k_validate_arcs<LCC_WT_I64>), dim3((unsigned)nb), dim3(VA_NT), 0, stream, g.off, g.col,
+                         g.wt, g.n, (int)check, part);
+  }
+  LAUNCHCHECK();
+}
+
+bool summary_from_vertex_row(const uint64_t r[VAL_VROW], GraphSummary &s) {
+  s.ktot = r[1];
+  s.kksum = r[2];
+  s.sabs = r[3];
+  s.negative = r[4] != 0;
+  s.maxdeg = (int64_t)r[5];
+  if (r[0]) {
+    s.ok = false;
+    s.why = err_text(r[0]);
+  }
+  return s.ok;
+}
+
+void summary_from_arc_row(const uint64_t r[VAL_AROW], bool check, GraphSummary &s) {
+  s.wabs2 = r[1];
+  s.negative = s.negative || r[2] != 0;
+  s.sorted_rows = check && !(r[0] & F_UNSORTED);
+  const uint64_t e2 = r[0] & ~(uint64_t)F_UNSORTED;
+  if (e2) {
+    s.ok = false;
+    s.why = err_text(e2);
+  }
+}
+
+int64_t validation_blocks(const Ctx &c, int64_t n) { return std::min<int64_t>(cdiv(n, VA_NT), (int64_t)c.num_cu * 4); }
+
 GraphSummary summarize_graph(Ctx &c, const lcc_graph &g, const int32_t *C, bool check_structure) {
   GraphSummary s;
   const int64_t n = g.n;
   if (n == 0) return s;
   Ctx::Timer tm(&c, "validate", (double)n * 40.0 + (double)g.arcs * (4.0 + wt_bytes(g.wt_kind)), (double)g.arcs);
-  const int64_t nb = std::min<int64_t>(cdiv(n, VA_NT), (int64_t)c.num_cu * 4);
-  uint64_t *part = c.buf<uint64_t>("va.part", (size_t)(nb * NPART));
-  hipLaunchKernelGGL(k_validate_vertices, dim3((unsigned)nb), dim3(VA_NT), 0, c.stream, g.off, n, g.arcs, g.k, g.kk,
-                     g.s, C, part);
-  LAUNCHCHECK();
-  std::vector<uint64_t> h((size_t)(nb * NPART));
+  const int64_t nb = validation_blocks(c, n);
+  uint64_t *part = c.buf<uint64_t>("va.part", (size_t)(nb * VAL_VROW));
+  launch_validate_vertices(c.stream, g, C, nb, part);
+  std::vector<uint64_t> h((size_t)(nb * VAL_VROW));
   d2h(c, h.data(), part, h.size() * sizeof(uint64_t));
-  uint64_t err = 0;
-  for (int64_t b = 0; b < nb; b++) {
-    const uint64_t *r = &h[(size_t)(b * NPART)];
-    err |= r[0];
-    s.ktot = host_sat_add(s.ktot, r[1]);
-    s.kksum = host_sat_add(s.kksum, r[2]);
-    s.sabs = host_sat_add(s.sabs, r[3]);
-    s.negative = s.negative || r[4];
-    s.maxdeg = std::max<int64_t>(s.maxdeg, (int64_t)r[5]);
-  }
-  if (err) {
-    // offsets or ids are unusable: stop before touching arcs
-    s.ok = false;
-    s.why = err_text(err);
-    return s;
-  }
+  uint64_t r[VAL_VROW] = {0};
+  for (int64_t b = 0; b < nb; b++) combine_vertex_row(r, &h[(size_t)(b * VAL_VROW)]);
+  // offsets or ids unusable: stop before touching arcs
+  if (!summary_from_vertex_row(r, s)) return s;
   if (g.arcs > 0 && (check_structure || g.wt_kind != LCC_WT_UNIT)) {
-    uint64_t *pa = c.buf<uint64_t>("va.parta", (size_t)(nb * 3));
-    switch (g.wt_kind) {
-      case LCC_WT_UNIT:
-        hipLaunchKernelGGL((k_validate_arcs<LCC_WT_UNIT>), dim3((unsigned)nb), dim3(VA_NT), 0, c.stream, g.off, g.col,
-                           g.wt, n, (int)check_structure, pa);
-        break;
-      case LCC_WT_I16:
-        hipLaunchKernelGGL((k_validate_arcs<LCC_WT_I16>), dim3((unsigned)nb), dim3(VA_NT), 0, c.stream, g.off, g.col,
-                           g.wt, n, (int)check_structure, pa);
-        break;
-      case LCC_WT_I32:
-        hipLaunchKernelGGL((k_validate_arcs<LCC_WT_I32>), dim3((unsigned)nb), dim3(VA_NT), 0, c.stream, g.off, g.col,
-                           g.wt, n, (int)check_structure, pa);
-        break;
-      default:
-        hipLaunchKernelGGL((k_validate_arcs<LCC_WT_I64>), dim3((unsigned)nb), dim3(VA_NT), 0, c.stream, g.off, g.col,
-                           g.wt, n, (int)check_structure, pa);
-    }
-    LAUNCHCHECK();
-    std::vector<uint64_t> ha((size_t)(nb * 3));
+    uint64_t *pa = c.buf<uint64_t>("va.parta", (size_t)(nb * VAL_AROW));
+    launch_validate_arcs(c.stream, g, check_structure, nb, pa);
+    std::vector<uint64_t> ha((size_t)(nb * VAL_AROW));
     d2h(c, ha.data(), pa, ha.size() * sizeof(uint64_t));
-    uint64_t e2 = 0;
-    for (int64_t b = 0; b < nb; b++) {
-      e2 |= ha[(size_t)(b * 3)];
-      s.wabs2 = host_sat_add(s.wabs2, ha[(size_t)(b * 3 + 1)]);
-      s.negative = s.negative || ha[(size_t)(b * 3 + 2)];
-    }
-    s.sorted_rows = check_structure && !(e2 & F_UNSORTED);
-    e2 &= ~(uint64_t)F_UNSORTED;
-    if (e2) {
-      s.ok = false;
-      s.why = err_text(e2);
-    }
+    uint64_t ra[VAL_AROW] = {0};
+    for (int64_t b = 0; b < nb; b++) combine_arc_row(ra, &ha[(size_t)(b * VAL_AROW)]);
+    summary_from_arc_row(ra, check_structure, s);
   } else {
     s.wabs2 = (uint64_t)g.arcs;  // unit weights
     s.sorted_rows = g.arcs == 0;
@@ -415,10 +423,11 @@ void lcc_params_default(lcc_params *prm) {
 
 const char *lcc_last_error(void) { return g_last_error.c_str(); }
 
-lcc_status lcc_ctx_create(int32_t device, lcc_ctx **out) {
+lcc_status lcc_ctx_create(int32_t device, const lcc_allocator *alloc, lcc_ctx **out) {
   return guarded([&] {
     if (!out) fail(LCC_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
+    if (alloc && (!alloc->alloc || !alloc->free)) fail(LCC_ERR_INVALID_ARG, "allocator with a NULL callback");
     int count = 0;
     HIPCHECK(hipGetDeviceCount(&count));
     if (device < 0 || device >= count) fail(LCC_ERR_INVALID_ARG, "no such device");
@@ -429,6 +438,7 @@ lcc_status lcc_ctx_create(int32_t device, lcc_ctx **out) {
     ctx->c.device = device;
     ctx->c.num_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
     ctx->c.lds_per_block = prop.sharedMemPerBlock > 0 ? prop.sharedMemPerBlock : 65536;
+    if (alloc) ctx->c.alloc = *alloc;
     *out = ctx.release();
   });
 }
@@ -536,9 +546,10 @@ lcc_status lcc_cluster(lcc_ctx *ctx, const lcc_graph *g, lcc_lambda lam, const l
     // per-level arrays live in the context and are reused by later calls
     std::vector<lcc_graph> G;
     std::vector<int32_t *> Cl, maps;
-    std::vector<int64_t> maxdeg;
+    std::vector<int64_t> maxdeg, mindeg;
     G.push_back(*g);
     maxdeg.push_back(s.maxdeg);
+    mindeg.push_back(0);
     int top = 0;
     double ms_bm = 0, ms_cp = 0;
     for (int l = 0;; l++) {
@@ -553,7 +564,7 @@ lcc_status lcc_cluster(lcc_ctx *ctx, const lcc_graph *g, lcc_lambda lam, const l
       auto a = clk::now();
       // compressed levels have strictly ascending rows by construction
       const bool simple = l > 0 || s.sorted_rows;
-      best_moves(c, G[l], lam.p, lam.q, *prm, l, 0, C, BMShape{maxdeg[l], !wide, true, simple}, st);
+      best_moves(c, G[l], lam.p, lam.q, *prm, l, 0, C, BMShape{maxdeg[l], !wide, true, simple, mindeg[l]}, st);
       ms_bm += std::chrono::duration<double, std::milli>(clk::now() - a).count();
       cs.iters_coarsen[l] = st.iterations;
       cs.moves_total += st.moves;
@@ -565,12 +576,13 @@ lcc_status lcc_cluster(lcc_ctx *ctx, const lcc_graph *g, lcc_lambda lam, const l
       }
       maps.push_back(c.buf<int32_t>("lv.map" + std::to_string(l), (size_t)(n > 0 ? n : 1)));
       OwnedGraph &next = c.level_graph((size_t)l + 1);
-      int64_t md = 0;
+      int64_t md = 0, mnd = 0;
       a = clk::now();
-      compress_graph(c, G[l], C, next, maps.back(), wide, &md);
+      compress_graph(c, G[l], C, next, maps.back(), wide, &md, nullptr, &mnd);
       ms_cp += std::chrono::duration<double, std::milli>(clk::now() - a).count();
       G.push_back(next.view());
       maxdeg.push_back(md);
+      mindeg.push_back(mnd);
     }
     for (int l = top - 1; l >= 0; l--) {
       int32_t *C = Cl[l];
@@ -578,7 +590,7 @@ lcc_status lcc_cluster(lcc_ctx *ctx, const lcc_graph *g, lcc_lambda lam, const l
       if (prm->refine) {
         lcc_bm_stats st;
         auto a = clk::now();
-        best_moves(c, G[l], lam.p, lam.q, *prm, l, 1, C, BMShape{maxdeg[l], !wide, false, false}, st);
+        best_moves(c, G[l], lam.p, lam.q, *prm, l, 1, C, BMShape{maxdeg[l], !wide, false, false, mindeg[l]}, st);
         ms_bm += std::chrono::duration<double, std::milli>(clk::now() - a).count();
         cs.iters_refine[l] = st.iterations;
         cs.moves_total += st.moves;
@@ -613,12 +625,13 @@ static void batch_levels(Ctx &c, const lcc_graph *g, int64_t J, const std::vecto
   std::vector<int32_t *> jidl, Cl, maps;
   std::vector<int64_t *> jbasel;
   std::vector<lcc_graph> G;
-  std::vector<int64_t> maxdeg;
+  std::vector<int64_t> maxdeg, mindeg;
   jidl.push_back(c.buf<int32_t>("lv.jid0", (size_t)g->n));
   batch_fill_jid(c, d_start, J, g->n, jidl.back());
   jbasel.push_back(d_start);
   G.push_back(*g);
   maxdeg.push_back(s.maxdeg);
+  mindeg.push_back(0);
   std::vector<uint8_t> run((size_t)J), cont((size_t)J), moved((size_t)J);
   std::vector<int32_t> top((size_t)J, 0), iters((size_t)J);
   for (int64_t j = 0; j < J; j++) run[(size_t)j] = hstart[(size_t)j + 1] > hstart[(size_t)j];
@@ -645,7 +658,7 @@ static void batch_levels(Ctx &c, const lcc_graph *g, int64_t J, const std::vecto
     lcc_bm_stats st;
     auto a = clk::now();
     const bool simple = l > 0 || s.sorted_rows;
-    best_moves(c, G[l], 0, 1, *prm, l, 0, C, BMShape{maxdeg[l], !wide, true, simple}, st, &bl);
+    best_moves(c, G[l], 0, 1, *prm, l, 0, C, BMShape{maxdeg[l], !wide, true, simple, mindeg[l]}, st, &bl);
     ms_bm += std::chrono::duration<double, std::milli>(clk::now() - a).count();
     bs.moves_total += st.moves;
     bs.arcs_scanned_total += st.arcs_scanned;
@@ -679,10 +692,12 @@ static void batch_levels(Ctx &c, const lcc_graph *g, int64_t J, const std::vecto
     cj.jbase_next = jbasel[l + 1];
     int64_t md = 0;
     a = clk::now();
-    compress_graph(c, G[l], C, next, maps.back(), wide, &md, &cj);
+    int64_t mnd = 0;
+    compress_graph(c, G[l], C, next, maps.back(), wide, &md, &cj, &mnd);
     ms_cp += std::chrono::duration<double, std::milli>(clk::now() - a).count();
     G.push_back(next.view());
     maxdeg.push_back(md);
+    mindeg.push_back(mnd);
     run = cont;
   }
   for (int l = maxtop - 1; l >= 0; l--) {
@@ -708,7 +723,7 @@ static void batch_levels(Ctx &c, const lcc_graph *g, int64_t J, const std::vecto
       bl.shared_n = l == 0 ? shared_n1 : 0;
       lcc_bm_stats st;
       auto a = clk::now();
-      best_moves(c, G[l], 0, 1, *prm, l, 1, C, BMShape{maxdeg[l], !wide, false, false}, st, &bl);
+      best_moves(c, G[l], 0, 1, *prm, l, 1, C, BMShape{maxdeg[l], !wide, false, false, mindeg[l]}, st, &bl);
       ms_bm += std::chrono::duration<double, std::milli>(clk::now() - a).count();
       bs.moves_total += st.moves;
       bs.arcs_scanned_total += st.arcs_scanned;

@@ -23,10 +23,6 @@ __global__ void k_fill_jid(const int64_t *__restrict__ jstart, int64_t jobs, int
   }
 }
 
-__device__ __forceinline__ uint64_t bt_sat_add(uint64_t a, uint64_t b) {
-  uint64_t s = a + b;
-  return s < a ? ~0ull : s;
-}
 
 template <class T, class F> __device__ __forceinline__ T block_reduce(T x, F op) {
   __shared__ T red[BT_NT / WAVE];
@@ -56,7 +52,7 @@ __global__ __launch_bounds__(BT_NT) void k_job_vsums(const int64_t *__restrict__
   const int lane = lane_id();
   for (int64_t v = vb + threadIdx.x / WAVE; v < ve; v += BT_NT / WAVE) {
     if (WK == LCC_WT_UNIT && !check) {
-      if (lane == 0) wabs = bt_sat_add(wabs, (uint64_t)(off[v + 1] - off[v]));
+      if (lane == 0) wabs = sat_add(wabs, (uint64_t)(off[v + 1] - off[v]));
     } else {
       for (int64_t e = off[v] + lane; e < off[v + 1]; e += WAVE) {
         const int32_t u = col[e];
@@ -64,24 +60,24 @@ __global__ __launch_bounds__(BT_NT) void k_job_vsums(const int64_t *__restrict__
         const int64_t w = load_w<WK>(wt, e);
         if (w < 0) {
           neg = 1;
-          wabs = bt_sat_add(wabs, w == INT64_MIN ? (1ull << 63) : (uint64_t)(-w));
+          wabs = sat_add(wabs, w == INT64_MIN ? (1ull << 63) : (uint64_t)(-w));
         } else {
-          wabs = bt_sat_add(wabs, (uint64_t)w);
+          wabs = sat_add(wabs, (uint64_t)w);
         }
       }
     }
     if (lane == 0) {
       const uint64_t kv = (uint64_t)k[v];
-      kt = bt_sat_add(kt, kv);
-      kks = bt_sat_add(kks, kk ? (uint64_t)kk[v] : (kv > 0xFFFFFFFFull ? ~0ull : kv * kv));
+      kt = sat_add(kt, kv);
+      kks = sat_add(kks, kk ? (uint64_t)kk[v] : (kv > 0xFFFFFFFFull ? ~0ull : kv * kv));
       if (s) {
         const int64_t sv = s[v];
         if (sv < 0) neg = 1;
-        sabs = bt_sat_add(sabs, sv < 0 ? (sv == INT64_MIN ? (1ull << 63) : (uint64_t)(-sv)) : (uint64_t)sv);
+        sabs = sat_add(sabs, sv < 0 ? (sv == INT64_MIN ? (1ull << 63) : (uint64_t)(-sv)) : (uint64_t)sv);
       }
     }
   }
-  auto sat = [](uint64_t a, uint64_t b) { return bt_sat_add(a, b); };
+  auto sat = [](uint64_t a, uint64_t b) { return sat_add(a, b); };
   auto orr = [](uint64_t a, uint64_t b) { return a | b; };
   wabs = block_reduce<uint64_t>(wabs, sat);
   kt = block_reduce<uint64_t>(kt, sat);
@@ -323,8 +319,8 @@ lcc_graph batch_replicate(Ctx &c, const lcc_graph &g1, int64_t J, OwnedGraph &ou
   out.n = n;
   out.arcs = arcs;
   out.wt_kind = g1.wt_kind;
-  out.off.ensure((size_t)(n + 1) * sizeof(int64_t));
-  out.col.ensure((size_t)(arcs > 0 ? arcs : 1) * sizeof(int32_t));
+  c.ensure(out.off, (size_t)(n + 1) * sizeof(int64_t));
+  c.ensure(out.col, (size_t)(arcs > 0 ? arcs : 1) * sizeof(int32_t));
   const unsigned grid_v = (unsigned)std::min<int64_t>(std::max<int64_t>(1, cdiv(n + 1, BT_NT)), 65536);
   const unsigned grid_a = (unsigned)std::min<int64_t>(std::max<int64_t>(1, cdiv(arcs, BT_NT)), 65536);
   if (n1 > 0) {
@@ -346,7 +342,7 @@ lcc_graph batch_replicate(Ctx &c, const lcc_graph &g1, int64_t J, OwnedGraph &ou
   g.wt_kind = g1.wt_kind;
   const size_t wb = (size_t)wt_bytes(g1.wt_kind);
   auto copies = [&](DevBuf &dst, const void *src, size_t each) {
-    dst.ensure(each * (size_t)J);
+    c.ensure(dst, each * (size_t)J);
     for (int64_t j = 0; j < J && each > 0; j++)
       HIPCHECK(hipMemcpyAsync(static_cast<char *>(dst.p) + (size_t)j * each, src, each, hipMemcpyDeviceToDevice,
                               c.stream));

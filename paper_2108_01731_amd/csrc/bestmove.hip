@@ -84,7 +84,8 @@ struct AggArgs {
   const int32_t *list;
   int64_t count;
   int32_t *D;
-  uint8_t *next_flag;  // nullptr: frontier = all vertices, no marking
+  uint8_t *next_flag;  // neighbors-of-movers frontier: movers mark their neighbors here
+  uint8_t *left_flag;  // neighbors-of-clusters frontier: movers mark the cluster they left here
   int64_t *ctr;        // NSPREAD x NCTR counters of this launch
   int32_t *gkeys;      // global tables (bin 7)
   int64_t *gvals;
@@ -99,6 +100,8 @@ struct AggArgs {
   // applies its own moves to the other (Cw, Kw, cntw), into which it also
   // replays the previous sub-round's moves (buckets rb0 .. rb1-1 of list;
   // none when rb1 <= rb0).  Cw == nullptr: a separate apply kernel runs.
+  // Asynchronous moves: Cw, Kw, cntw are C, K, cnt themselves, so a move is
+  // applied to the state the other decisions read the moment it is decided.
   int32_t *Cw;
   int64_t *Kw;
   int32_t *cntw;
@@ -330,7 +333,7 @@ __global__ __launch_bounds__(BM_NT) void k_bm_group(AggArgs a) {
   const int32_t *list;
   int64_t count;
   work_of(a, list, count);
-  int64_t c_movers = 0, c_cands = 0, c_marcs = 0;
+  int64_t c_movers = 0, c_cands = 0, c_marcs = 0, c_iso = 0;
   for (int64_t g0 = (int64_t)blockIdx.x * GPB; g0 < count; g0 += (int64_t)gridDim.x * GPB) {
     const int64_t gi = g0 + grp;
     const bool valid = gi < count;
@@ -429,6 +432,8 @@ __global__ __launch_bounds__(BM_NT) void k_bm_group(AggArgs a) {
       const int32_t d = decide(best_s, best_id, stay, a.allow_iso && cntc >= 2, c);
       moved = d != c;
       if (gl == 0) a.D[v] = d;
+      if (moved && gl == 0 && a.left_flag) a.left_flag[c] = 1;
+      if (moved && gl == 0 && a.Cw) own_move(a, v, c, d, kv, c_iso);
       if (moved && a.next_flag) {
         if constexpr (ONE_PASS) {
           if (u0 >= 0) a.next_flag[u0] = 1;
@@ -442,6 +447,7 @@ __global__ __launch_bounds__(BM_NT) void k_bm_group(AggArgs a) {
     c_marcs += (moved && gl == 0) ? end - beg : 0;
     __syncthreads();  // the tables are cleared again for the next vertices
   }
+  if (c_iso) atomic_add_i64(a.iso_ctr, c_iso);
   flush_counters<BM_NT>(a.ctr, c_movers, c_cands, c_marcs);
 }
 
@@ -541,6 +547,7 @@ __global__ __launch_bounds__(NT) void k_bm_wide(AggArgs a) {
       if (d != c) {
         movers += 1;
         marcs += end - beg;
+        if (a.left_flag) a.left_flag[c] = 1;
         if (a.Cw) own_move(a, v, c, d, kv, niso);
       }
     }
@@ -762,6 +769,7 @@ __global__ __launch_bounds__(BM_NT) void k_bm_shared(AggArgs a, const int32_t *_
         if (gl == 0) {
           c_movers++;
           c_marcs += end - beg;
+          if (a.left_flag) a.left_flag[c] = 1;
         }
       }
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -853,6 +861,7 @@ __global__ __launch_bounds__(NT) void k_bm_single(AggArgs a) {
     const bool moved = valid && d != v;
     if (valid && gl == 0) a.D[v] = d;
     if (moved && gl == 0 && a.Cw) own_move(a, v, v, d, kv, c_iso);
+    if (moved && gl == 0 && a.left_flag) a.left_flag[v] = 1;
     if (moved && a.next_flag)
       for (int64_t e = beg + gl; e < end; e += G) a.next_flag[a.col[e]] = 1;
     c_movers += (moved && gl == 0) ? 1 : 0;
@@ -1131,7 +1140,7 @@ __global__ __launch_bounds__(B7_NT) void k_b7_final(AggArgs a, const int64_t *__
   const int32_t *list;
   int64_t n7;
   work_of(a, list, n7);
-  int64_t movers = 0, marcs = 0, cands = 0;
+  int64_t movers = 0, marcs = 0, cands = 0, niso = 0;
   for (int64_t i = blockIdx.x; i < n7; i += gridDim.x) {
     const int32_t v = list[i];
     const int64_t beg = a.off[v], end = a.off[v + 1];
@@ -1161,6 +1170,8 @@ __global__ __launch_bounds__(B7_NT) void k_b7_final(AggArgs a, const int64_t *__
       if (d != c) {
         movers += 1;
         marcs += end - beg;
+        if (a.left_flag) a.left_flag[c] = 1;
+        if (a.Cw) own_move(a, v, c, d, kv, niso);
       }
     }
     __syncthreads();
@@ -1168,6 +1179,7 @@ __global__ __launch_bounds__(B7_NT) void k_b7_final(AggArgs a, const int64_t *__
       for (int64_t e = beg + t; e < end; e += B7_NT) a.next_flag[a.col[e]] = 1;
     __syncthreads();  // sh_d is reused by the next row
   }
+  if (t == 0 && niso) atomic_add_i64(a.iso_ctr, niso);
   flush_counters<B7_NT>(a.ctr, movers, cands, marcs);
 }
 
@@ -1520,6 +1532,43 @@ __global__ __launch_bounds__(B7_NT) void k_hps_scatter(AggArgs a, const int64_t 
 size_t hp_lds_bytes(bool a32) { return (size_t)HP_SLOTS * (sizeof(int32_t) + (a32 ? 4 : 8)); }
 
 
+// ------------------------------------------ neighbors-of-clusters frontier
+
+// End of an iteration under the neighbors-of-clusters rule (Sec. 3.2.2):
+// every vertex v whose cluster (at the end of the iteration, before fresh
+// ids are renamed) is one that a vertex moved out of during the iteration
+// marks its neighbors in `next`.  Lane i of a wave tests vertex base + i;
+// the wave then walks the rows of the marked vertices one after another,
+// coalesced.  The left flags alternate between two arrays: this launch
+// reads `left` and clears `left_next`, which the next iteration's moves fill
+// (the previous iteration's launch, the last reader of left_next, is done).
+constexpr int LN_NT = 256;
+__global__ __launch_bounds__(LN_NT) void k_mark_left_nbrs(const int64_t *__restrict__ off,
+                                                          const int32_t *__restrict__ col,
+                                                          const int32_t *__restrict__ C, int64_t n,
+                                                          const uint8_t *__restrict__ left,
+                                                          uint8_t *__restrict__ left_next, uint8_t *__restrict__ next) {
+  const int lane = lane_id();
+  const int64_t stride = (int64_t)gridDim.x * LN_NT;
+  for (int64_t base = (int64_t)blockIdx.x * LN_NT + (threadIdx.x - lane); base < n; base += stride) {
+    const int64_t v = base + lane;
+    bool mark = false;
+    if (v < n) {
+      left_next[v] = 0;
+      const int32_t x = C[v];
+      mark = x < n && left[x];
+    }
+    uint64_t m = __ballot(mark);
+    while (m) {
+      const int i = __ffsll((unsigned long long)m) - 1;
+      m &= m - 1;
+      const int64_t u = base + i;
+      const int64_t e1 = off[u + 1];
+      for (int64_t e = off[u] + lane; e < e1; e += WAVE) next[col[e]] = 1;
+    }
+  }
+}
+
 // -------------------------------------------------------------- apply
 
 // Applies the sub-round's decisions; an isolating vertex v takes the fresh
@@ -1823,12 +1872,63 @@ __global__ __launch_bounds__(BM_NT) void k_part_count(const int32_t *__restrict_
   }
 }
 
+// Stable placement of one tile of NT consecutive items into NB buckets (b
+// = NOBUCKET: not placed): returns run[b] plus the item's rank among the
+// tile's earlier items of bucket b (-1 when not placed), then advances run[b]
+// by the tile's count.  Ranks inside a wave come from ballots over the bits
+// of b, waves are taken in order, so buckets keep the items' order and the
+// partition is the same on every run.  wcnt (LDS, NT / WAVE x NB int32) is
+// zero on entry and on exit.  Every thread of the block calls it.
+template <int NT>
+__device__ __forceinline__ int64_t tile_stable_pos(int b, int NB, int32_t *wcnt, int64_t *run) {
+  constexpr int NW = NT / WAVE;
+  const int w = threadIdx.x / WAVE;
+  const bool valid = b != NOBUCKET;
+  int bits = 1;
+  while ((1 << bits) < NB) bits++;
+  uint64_t peers = __ballot(valid);
+  for (int k = 0; k < bits; k++) {
+    const uint64_t bb = __ballot((b >> k) & 1);
+    peers &= ((b >> k) & 1) ? bb : ~bb;
+  }
+  const int rank = __popcll(peers & __lanemask_lt());
+  const int cntp = __popcll(peers);
+  if (valid && rank == cntp - 1) wcnt[w * NB + b] = cntp;
+  __syncthreads();
+  int64_t pos = -1;
+  if (valid) {
+    pos = run[b] + rank;
+    for (int q = 0; q < w; q++) pos += wcnt[q * NB + b];
+  }
+  __syncthreads();
+  for (int x = threadIdx.x; x < NB; x += NT) {
+    int32_t t = 0;
+#pragma unroll
+    for (int q = 0; q < NW; q++) {
+      t += wcnt[q * NB + x];
+      wcnt[q * NB + x] = 0;
+    }
+    run[x] += t;
+  }
+  __syncthreads();
+  return pos;
+}
+
+// LDS of the stable placement: NB running positions and NT / WAVE x NB counts.
+__host__ __device__ constexpr size_t stable_lds_bytes(int NB, int NT) {
+  return (size_t)NB * sizeof(int64_t) + (size_t)(NT / WAVE) * NB * sizeof(int32_t);
+}
+
 // The partition of a small level in one block and one launch: bucket counts
 // and arcs, bucket starts (NB + 1) and the bucket lists.
 constexpr int PS_NT = 1024;
-constexpr int64_t SMALL_LEVEL = 8192;
+constexpr int64_t SMALL_LEVEL = LCC_SMALL_LEVEL_MAX;
 
-// One block of PS_NT threads; sm holds 2 * S * NBINS int64.
+// One block of PS_NT threads; sm holds 2 * NB int64 then the placement counts
+// (part_small_lds_bytes).
+__host__ __device__ constexpr size_t part_small_lds_bytes(int NB) {
+  return (size_t)NB * sizeof(int64_t) + stable_lds_bytes(NB, PS_NT);
+}
 __device__ __forceinline__ void part_small_body(const int32_t *__restrict__ list, int64_t na0,
                                                 const int64_t *__restrict__ na_dev, const int64_t *__restrict__ off,
                                                 uint64_t h, int32_t S, int64_t wide_max, const JobView &jv,
@@ -1838,7 +1938,9 @@ __device__ __forceinline__ void part_small_body(const int32_t *__restrict__ list
   const int NB = S * NBINS;
   int64_t *lc = sm;       // members, then cursor
   int64_t *la = sm + NB;  // arcs
+  int32_t *wcnt = reinterpret_cast<int32_t *>(sm + 2 * NB);
   for (int i = threadIdx.x; i < 2 * NB; i += PS_NT) sm[i] = 0;
+  for (int i = threadIdx.x; i < (PS_NT / WAVE) * NB; i += PS_NT) wcnt[i] = 0;
   __syncthreads();
   const int64_t na = active_count(na0, na_dev);
   for (int64_t i = threadIdx.x; i < na; i += PS_NT) {
@@ -1873,11 +1975,11 @@ __device__ __forceinline__ void part_small_body(const int32_t *__restrict__ list
     dstart[NB] = t;
   }
   __syncthreads();
-  for (int64_t i = threadIdx.x; i < na; i += PS_NT) {
-    const int b = bucket_of[i];
-    if (b == NOBUCKET) continue;
-    const int64_t pos = (int64_t)atomicAdd(reinterpret_cast<unsigned long long *>(&lc[b]), 1ull);
-    out[pos] = list ? list[i] : (int32_t)i;
+  for (int64_t x0 = 0; x0 < na; x0 += PS_NT) {
+    const int64_t i = x0 + threadIdx.x;
+    const int b = i < na ? (int)bucket_of[i] : (int)NOBUCKET;
+    const int64_t pos = tile_stable_pos<PS_NT>(b, NB, wcnt, lc);
+    if (pos >= 0) out[pos] = list ? list[i] : (int32_t)i;
   }
 }
 
@@ -2023,9 +2125,9 @@ __global__ __launch_bounds__(BM_NT) void k_part_offsets(const int64_t *__restric
   }
 }
 
-// Order inside one block's share of a bucket is whatever the LDS atomics
-// give: no result depends on it (decisions read a fixed snapshot; apply adds
-// commute; isolation ranks by vertex id).
+// Stable: a bucket lists its members in the order of the active list (no
+// result depends on the order, but it makes the assignment of vertices to
+// the blocks of the aggregation launches the same on every run).
 __global__ __launch_bounds__(BM_NT) void k_part_scatter(const int32_t *__restrict__ list, int64_t na0,
                                                         const int64_t *__restrict__ na_dev,
                                                         const uint16_t *__restrict__ bucket_of, int32_t S,
@@ -2033,21 +2135,19 @@ __global__ __launch_bounds__(BM_NT) void k_part_scatter(const int32_t *__restric
                                                         int32_t *__restrict__ out) {
   extern __shared__ int64_t sm[];
   const int NB = S * NBINS;
-  int64_t *lc = sm;          // members placed so far per bucket
-  int64_t *lbase = sm + NB;  // this block's first position per bucket
-  for (int i = threadIdx.x; i < NB; i += BM_NT) {
-    lc[i] = 0;
-    lbase[i] = cursor[(int64_t)i * gridDim.x + blockIdx.x];
-  }
+  int64_t *run = sm;  // next position per bucket
+  int32_t *wcnt = reinterpret_cast<int32_t *>(sm + NB);
+  for (int i = threadIdx.x; i < NB; i += BM_NT) run[i] = cursor[(int64_t)i * gridDim.x + blockIdx.x];
+  for (int i = threadIdx.x; i < (BM_NT / WAVE) * NB; i += BM_NT) wcnt[i] = 0;
   __syncthreads();
   const int64_t na = active_count(na0, na_dev);
   int64_t beg, end;
   part_range(na, beg, end);
-  for (int64_t i = beg + threadIdx.x; i < end; i += BM_NT) {
-    const int b = bucket_of[i];
-    if (b == NOBUCKET) continue;
-    const int64_t r = (int64_t)atomicAdd(reinterpret_cast<unsigned long long *>(&lc[b]), 1ull);
-    out[lbase[b] + r] = list ? list[i] : (int32_t)i;
+  for (int64_t i0 = beg; i0 < end; i0 += BM_NT) {
+    const int64_t i = i0 + threadIdx.x;
+    const int b = i < end ? (int)bucket_of[i] : (int)NOBUCKET;
+    const int64_t pos = tile_stable_pos<BM_NT>(b, NB, wcnt, run);
+    if (pos >= 0) out[pos] = list ? list[i] : (int32_t)i;
   }
 }
 
@@ -2432,7 +2532,26 @@ void best_moves_run(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_
   const int64_t wslots = wide_slots(c, acc32);
   const int64_t wide_max = wslots * 7 / 10 - 1;
   const int wb = wt_bytes(g.wt_kind);
-  const bool nbr = prm.frontier == LCC_FRONTIER_NBR;
+  // a frontier list after the first iteration (neighbors of movers, or of
+  // the clusters movers left); movers mark neighbors, or the left clusters
+  const bool nbr = prm.frontier != LCC_FRONTIER_ALL;
+  const bool mark_left = prm.frontier == LCC_FRONTIER_CLUSTERS;
+  // asynchronous moves: every deciding launch applies its moves to the one
+  // state (no apply launch, no second copy, no singleton shortcut)
+  const bool async = prm.async_moves != 0;
+  uint8_t *left = nullptr, *left_cur = nullptr;
+  if (mark_left) {
+    left = c.buf<uint8_t>("bm.left", 2 * nn);
+    HIPCHECK(hipMemsetAsync(left, 0, nn, c.stream));
+  }
+  // marks the neighbors of the vertices in a left cluster (end of iteration it)
+  auto mark_left_nbrs = [&](const int32_t *Cnow, int32_t it) {
+    uint8_t *cur = left + (size_t)(it & 1) * nn, *other = left + (size_t)((it + 1) & 1) * nn;
+    Ctx::Timer tm(&c, "bm_frontier_clusters", 0.0, (double)n, true);
+    c.launch(k_mark_left_nbrs, dim3((unsigned)std::min<int64_t>(cdiv(n, LN_NT), (int64_t)c.num_cu * 8)),
+             dim3(LN_NT), 0, g.off, g.col, Cnow, n, (const uint8_t *)cur, other, next);
+    LAUNCHCHECK();
+  };
   const int LC = NSPREAD * NCTR;
   static const char *wk_tag[4] = {"_unit", "_i16", "_i32", "_i64"};
 
@@ -2446,7 +2565,9 @@ void best_moves_run(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_
   const int64_t part_grid = std::min<int64_t>(std::max<int64_t>(1, cdiv(n, BM_NT * 8)), (int64_t)c.num_cu * 8);
   int32_t *blkcnt = c.buf<int32_t>("bm.pblk", (size_t)(part_grid * NB));
   int64_t *pcur = c.buf<int64_t>("bm.pcur", (size_t)(part_grid * NB));
-  const size_t part_smem = (size_t)2 * NB * sizeof(int64_t);
+  const size_t part_smem = (size_t)2 * NB * sizeof(int64_t);  // k_part_count
+  const size_t scatter_smem = stable_lds_bytes(NB, BM_NT);      // k_part_scatter
+  const size_t small_smem = part_small_lds_bytes(NB);           // k_part_small, k_iter_end_small
 
   auto agg_args = [&](int bi, const int64_t *dstart, int64_t *ctr) {
     AggArgs a;
@@ -2464,7 +2585,14 @@ void best_moves_run(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_
     a.hub_limit = prm.hub_limit;
     a.list = blist;
     a.D = D;
-    a.next_flag = nbr ? next : nullptr;
+    a.next_flag = prm.frontier == LCC_FRONTIER_NBR ? next : nullptr;
+    a.left_flag = left_cur;
+    if (async) {
+      a.Cw = C;
+      a.Kw = K;
+      a.cntw = cnt;
+      a.nlev = n;
+    }
     a.ctr = ctr + (size_t)LC * bi;
     a.jv = jv;
     a.dstart = dstart;
@@ -2496,7 +2624,8 @@ void best_moves_run(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_
     // sub-round covers every degree bin (fewer launches where the host's
     // launch rate, not the work, sets the pace).  Larger levels: one launch
     // per degree bin present in the level.
-    const bool small = n <= SMALL_LEVEL && shape.maxdeg <= wide_max;
+    const int64_t small_max = prm.small_level > 0 ? prm.small_level : SMALL_LEVEL;
+    const bool small = !async && n <= small_max && shape.maxdeg <= wide_max;
     // degree histogram of the level (larger levels launch one kernel per
     // non-empty bin); a small level needs only the largest degree: its
     // narrow launch (degree < 2048) always runs, empty or not
@@ -2512,13 +2641,15 @@ void best_moves_run(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_
     // tables of the small-level kernels: MID_SLOTS below degree 2048, else
     // room for the widest row of the level
     const bool wide_rows = small ? shape.maxdeg > bin_limit_fixed(5) : hist[6] > 0;
-    bool narrow_rows = small;
+    // (a small level whose shortest row has 2048 arcs or more skips the narrow launch)
+    bool narrow_rows = small && shape.mindeg <= bin_limit_fixed(5);
     for (int b = 0; b < 6; b++) narrow_rows = narrow_rows || hist[b] > 0;
     const int64_t small_slots = std::min<int64_t>(pow2_host(2 * (shape.maxdeg + 1)), wslots);
     // lambda sweeps: rows of degree < 256 read once for all jobs (see k_bm_shared)
     bool shared_rows = false;
     for (int b = 0; b <= SH_BIN_HI; b++) shared_rows = shared_rows || hist[b] > 0;
-    shared_rows = shared_rows && bl && bl->shared_n > 0 && !small && J >= 2 && J <= SH_MAXJ && J * bl->shared_n == n;
+    shared_rows = shared_rows && bl && bl->shared_n > 0 && !small && !async && J >= 2 && J <= SH_MAXJ &&
+                  J * bl->shared_n == n;
     const int64_t n1 = shared_rows ? bl->shared_n : 0;
     // rows of degree < 256 (bins 0-4): one launch when they are few
     int64_t low_rows = 0;
@@ -2527,7 +2658,7 @@ void best_moves_run(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_
       low_rows += hist[b];
       low_bins += hist[b] > 0;
     }
-    const bool low_merged = !small && low_bins > 1 && low_rows <= 32768;
+    const bool low_merged = !small && low_bins > 1 && low_rows <= (prm.low_merge > 0 ? prm.low_merge : 32768);
     int32_t *C16 = nullptr, *seglist = nullptr;
     uint32_t *shmask = nullptr;
     if (shared_rows) {
@@ -2575,12 +2706,19 @@ void best_moves_run(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_
     std::vector<int64_t> h((size_t)(NI * IB));
     // (with the all-vertices rule an iteration past the end redoes all the
     // work, so only the neighbor frontier queues ahead)
-    int32_t queued = 0, chunk = small && nbr ? std::max<int32_t>(1, c.small_iter_hint[phase & 1]) : 1;
+    const bool fixed_chunk = prm.queue_ahead > 0;
+    int32_t queued = 0,
+            chunk = fixed_chunk ? prm.queue_ahead : small && nbr ? std::max<int32_t>(1, c.small_iter_hint[phase & 1]) : 1;
     bool done = false;
+    // a small level's chunk of iterations is a fixed sequence of launches
+    // through c.launch: recorded, and replayed as a graph when repeated
+    const bool replay = small && !c.timing && !prm.no_graph_replay;
     while (!done && queued < prm.num_iter) {
       const int32_t first = queued, last = std::min<int32_t>(prm.num_iter, queued + chunk);
+      if (replay) c.begin_record();
       for (int32_t it = first; it < last; it++) {
         int64_t *blk = ctrs + (size_t)it * IB;
+        if (mark_left) left_cur = left + (size_t)(it & 1) * nn;
         const uint64_t hh = round_hash(prm.seed, level, phase, it);
         // the first iteration and the "all vertices" rule take every vertex
         const bool all = it == 0 || !nbr;
@@ -2589,8 +2727,9 @@ void best_moves_run(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_
         if (small) {
           // later iterations were partitioned at the end of the previous one
           if (it == 0) {
-            hipLaunchKernelGGL(k_part_small, dim3(1), dim3(PS_NT), part_smem, c.stream, list, n, na_dev, g.off, hh, S,
-                               wide_max, jv, bucket_of, blk + o_bcnt, blk + o_barcs, blk + o_start, blist);
+            c.launch(k_part_small, dim3(1), dim3(PS_NT), small_smem, list, (int64_t)n, na_dev,
+                     (const int64_t *)g.off, hh, (int32_t)S, wide_max, jv, bucket_of, blk + o_bcnt, blk + o_barcs,
+                     blk + o_start, blist);
             LAUNCHCHECK();
           }
         } else {
@@ -2600,12 +2739,12 @@ void best_moves_run(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_
           hipLaunchKernelGGL(k_part_offsets, dim3((unsigned)NB), dim3(BM_NT), 0, c.stream, blk + o_bcnt, blkcnt,
                              part_grid, pcur, blk + o_start);
           LAUNCHCHECK();
-          hipLaunchKernelGGL(k_part_scatter, dim3((unsigned)part_grid), dim3(BM_NT), part_smem, c.stream, list, n,
+          hipLaunchKernelGGL(k_part_scatter, dim3((unsigned)part_grid), dim3(BM_NT), scatter_smem, c.stream, list, n,
                              na_dev, bucket_of, S, pcur, blist);
           LAUNCHCHECK();
         }
         for (int s = 0; s < S; s++) {
-          const bool single = it == 0 && s == 0 && identity && shape.simple;
+          const bool single = it == 0 && s == 0 && identity && shape.simple && !async;
           if (small) {
             // bins 0-5 (degree < 2048), then bin 6 if the level has wider rows
             // sub-round s reads copy s % 2 and applies to the other, into
@@ -2675,6 +2814,7 @@ void best_moves_run(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_
             if (!hist[b] || (sh_now && b <= SH_BIN_HI)) continue;
             const int bi = s * NBINS + b;
             AggArgs a = agg_args(bi, blk + o_start, blk + o_lctr);
+            if (async) a.iso_ctr = blk + o_isoc + s;
             // few rows below degree 256 in the level: their buckets (consecutive)
             // go to bin 4's kernel in one launch
             const bool merged = b <= SH_BIN_HI && !sh_now && low_merged;
@@ -2689,7 +2829,7 @@ void best_moves_run(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_
             if (c.timing) timed.push_back({pidx, it, bi, a.nbuckets, single});
             if (merged) b = SH_BIN_HI;
           }
-          if (!small) {
+          if (!small && !async) {
             Ctx::Timer tm(&c, "bm_apply", 0.0, 0.0, true);
             c.launch(k_bm_apply, dim3((unsigned)apply_grid), dim3(BM_NT), 0, (const int32_t *)blist, (int64_t)0,
                      (const int64_t *)(blk + o_start), (int32_t)(s * NBINS), (int32_t)((s + 1) * NBINS),
@@ -2697,6 +2837,8 @@ void best_moves_run(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_
             LAUNCHCHECK();
           }
         }
+        // (on small levels the state copy the last sub-round wrote)
+        if (mark_left) mark_left_nbrs(small && (S - 1) % 2 == 0 ? C2 : C, it);
         if (small) {
           IterEndSmall e;
           std::memset(&e, 0, sizeof(e));
@@ -2743,7 +2885,7 @@ void best_moves_run(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_
             e.dstart = nb + o_start;
           }
           Ctx::Timer tm(&c, "bm_iter_end_small", 0.0, (double)n, true);
-          c.launch(k_iter_end_small, dim3(1), dim3(PS_NT), part_smem, e, n, (int32_t)S, jv);
+          c.launch(k_iter_end_small, dim3(1), dim3(PS_NT), small_smem, e, n, (int32_t)S, jv);
           LAUNCHCHECK();
         } else {
           if (nbr) compact_flags(c, next, n, active, blk + o_nact, true, "bm.cmp");
@@ -2755,6 +2897,7 @@ void best_moves_run(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_
           }
         }
       }
+      if (replay) c.end_record();
       queued = last;
       d2h(c, h.data() + (size_t)first * IB, ctrs + (size_t)first * IB, (size_t)(last - first) * IB * sizeof(int64_t));
       for (int32_t it = first; it < last && !done; it++) {
@@ -2787,7 +2930,7 @@ void best_moves_run(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_
         }
       }
       // later chunks are longer only where a finished call leaves no work
-      if (nbr) chunk++;
+      if (nbr && !fixed_chunk) chunk++;
     }
     if (c.timing) {
       for (const Timed &t : timed) {
@@ -2834,6 +2977,7 @@ void best_moves_run(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_
   bool stopped = false;
   for (int32_t it = 0; it < prm.num_iter && !stopped; it++) {
     const uint64_t hh = round_hash(prm.seed, level, phase, it);
+    if (mark_left) left_cur = left + (size_t)(it & 1) * nn;
     st.iterations++;
     HIPCHECK(hipMemsetAsync(dctr, 0, nctr * sizeof(int64_t), c.stream));
     if (bl) {
@@ -2848,7 +2992,7 @@ void best_moves_run(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_
       hipLaunchKernelGGL(k_part_offsets, dim3((unsigned)NB), dim3(BM_NT), 0, c.stream, bcnt, blkcnt, part_grid, pcur,
                          dstart);
       LAUNCHCHECK();
-      hipLaunchKernelGGL(k_part_scatter, dim3((unsigned)part_grid), dim3(BM_NT), part_smem, c.stream, list, na,
+      hipLaunchKernelGGL(k_part_scatter, dim3((unsigned)part_grid), dim3(BM_NT), scatter_smem, c.stream, list, na,
                          (const int64_t *)nullptr, bucket_of, S, pcur, blist);
       LAUNCHCHECK();
     }
@@ -2872,11 +3016,12 @@ void best_moves_run(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_
         AggArgs a = agg_args(bi, nullptr, lctr);
         a.list = blist + start[bi];
         a.count = cntb;
+        if (async) a.iso_ctr = isoc + s;
         const int64_t arcs_i = hctr[NB + bi];
         const double arcs_b = (double)arcs_i;
         // first sub-round from singletons on rows without repeats: no
         // aggregation (later sub-rounds see the moves of earlier ones)
-        const bool single = it == 0 && s == 0 && identity && shape.simple;
+        const bool single = it == 0 && s == 0 && identity && shape.simple && !async;
         size_t pidx = c.pending.size();
         {
           // algorithmic bytes: per vertex list, offsets, C, k, K, cnt, D (48 B);
@@ -2892,7 +3037,7 @@ void best_moves_run(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_
         st.vertices_processed += cntb;
         st.arcs_scanned += hctr[NB + bi];
       }
-      if (total_s > 0) {
+      if (total_s > 0 && !async) {
         Ctx::Timer tm(&c, "bm_apply", (double)total_s * 12.0, (double)total_s);
         hipLaunchKernelGGL(k_bm_apply, dim3((unsigned)cdiv(total_s, BM_NT)), dim3(BM_NT), 0, c.stream,
                            blist + start[s * NBINS], total_s, (const int64_t *)nullptr, 0, 0, D, C, K, cnt, g.k, n,
@@ -2902,6 +3047,7 @@ void best_moves_run(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_
       st.subrounds++;
     }
     // next frontier
+    if (mark_left && !stopped && n > 0) mark_left_nbrs(C, it);
     if (nbr && n > 0) compact_flags(c, next, n, active, nact, true, "bm.cmp");
     d2h(c, hctr.data() + o_lctr, lctr, (size_t)(LC * NB + S + 2) * sizeof(int64_t));
     const int64_t *hl = hctr.data() + o_lctr;

@@ -41,30 +41,54 @@ inline void hip_check(hipError_t e, const char *what, const char *file, int line
 
 // ----------------------------------------------------------------- buffers
 
-// Owning device allocation (hipMalloc), movable, grows on demand.
+// Owning device allocation, movable, grows on demand.  Memory comes from
+// the caller's allocator when the context has one (lcc_ctx_create), else from
+// hipMalloc; a buffer keeps the callbacks and the stream it was allocated on
+// and returns its memory the same way.
 struct DevBuf {
   void *p = nullptr;
   size_t bytes = 0;
+  lcc_allocator al{};          // al.alloc == nullptr: hipMalloc / hipFree
+  hipStream_t stream = nullptr;  // the stream of the call that allocated it
   DevBuf() = default;
   DevBuf(const DevBuf &) = delete;
   DevBuf &operator=(const DevBuf &) = delete;
-  DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes), al(o.al), stream(o.stream) { o.p = nullptr; o.bytes = 0; }
   DevBuf &operator=(DevBuf &&o) noexcept {
-    if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+    if (this != &o) {
+      release();
+      p = o.p; bytes = o.bytes; al = o.al; stream = o.stream;
+      o.p = nullptr; o.bytes = 0;
+    }
     return *this;
   }
   ~DevBuf() { release(); }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) {
+      if (al.alloc) al.free(al.user, p, bytes, (void *)stream);
+      else (void)hipFree(p);
+    }
     p = nullptr;
     bytes = 0;
   }
-  // Ensures capacity >= b bytes (contents are not preserved on growth).
-  void ensure(size_t b) {
+  // Ensures capacity >= b bytes (contents are not preserved on growth), from
+  // allocator a (a.alloc == nullptr: hipMalloc) for work on stream s.  Work
+  // already queued on s may still read the old block, so with the caller's
+  // allocator s is drained before the block goes back (a wait on one stream,
+  // where hipFree waits for the whole device).
+  void ensure(size_t b, const lcc_allocator &a, hipStream_t s) {
     if (b <= bytes && p) return;
+    if (p && al.alloc) HIPCHECK(hipStreamSynchronize(s));
     release();
-    size_t want = b < 256 ? 256 : b;
-    HIPCHECK(hipMalloc(&p, want));
+    size_t want = b < 256 ? 256 : (b + 255) & ~(size_t)255;
+    al = a;
+    stream = s;
+    if (al.alloc) {
+      p = al.alloc(al.user, want, (void *)s);
+      if (!p) fail(LCC_ERR_OUT_OF_MEMORY, "the caller's allocator returned NULL for " + std::to_string(want) + " bytes");
+    } else {
+      HIPCHECK(hipMalloc(&p, want));
+    }
     bytes = want;
   }
   template <class T> T *as() const { return static_cast<T *>(p); }
@@ -104,6 +128,37 @@ struct PendingEvent {
   double bytes, items;
 };
 
+// One recorded kernel launch: its function, shape and argument bytes (each
+// argument at its own aligned offset), enough to add it to a HIP graph.
+struct LaunchRec {
+  const void *func;
+  dim3 grid, block;
+  uint32_t shmem;
+  std::vector<char> args;
+  std::vector<size_t> off;
+};
+
+// Replays of recorded launch sequences as HIP graphs.  A sequence is keyed
+// by its exact bytes (functions, shapes, argument values); the first time a
+// sequence is seen its launches go out one by one, from its second
+// occurrence on it runs as one instantiated graph (a repeated clustering
+// issues the same sequences: same buffers, same arguments).
+struct GraphCache {
+  struct Entry {
+    std::string blob;
+    int seen = 0;
+    hipGraphExec_t exec = nullptr;
+    uint64_t used = 0;
+  };
+  std::map<uint64_t, Entry> entries;
+  uint64_t clock = 0;
+  static constexpr size_t MAX_ENTRIES = 512;
+  ~GraphCache() {
+    for (auto &kv : entries)
+      if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+  }
+};
+
 // ------------------------------------------------------------------- context
 
 struct Ctx {
@@ -131,6 +186,12 @@ struct Ctx {
   int32_t small_iter_hint[2] = {1, 1};
   // contracted graphs of the hierarchy levels, reused across calls
   std::vector<std::unique_ptr<OwnedGraph>> level_graphs;
+  // launches recorded for replay as a graph (see begin_record / end_record)
+  bool recording = false;
+  std::vector<LaunchRec> recs;
+  GraphCache graphs;
+  // the caller's allocator (alloc == nullptr: hipMalloc / hipFree)
+  lcc_allocator alloc{};
 
   OwnedGraph &level_graph(size_t l) {
     while (level_graphs.size() <= l) level_graphs.emplace_back(new OwnedGraph());
@@ -139,9 +200,11 @@ struct Ctx {
 
   template <class T> T *buf(const std::string &name, size_t count) {
     DevBuf &b = scratch[name];
-    b.ensure(count * sizeof(T));
+    b.ensure(count * sizeof(T), alloc, stream);
     return b.as<T>();
   }
+  // A library-owned array (graph arrays) from the context's allocator.
+  void ensure(DevBuf &b, size_t bytes) { b.ensure(bytes, alloc, stream); }
 
   hipEvent_t get_event() {
     if (!event_pool.empty()) {
@@ -191,9 +254,21 @@ struct Ctx {
   Timer *dispatch_timer = nullptr;
 
   // Launches a kernel on the context stream; inside an on-dispatch Timer the
-  // launch carries the timer's events.
-  template <class F, class... Args>
-  void launch(F kernel, dim3 grid, dim3 block, size_t shmem, Args... args) {
+  // launch carries the timer's events; while recording it is only recorded.
+  template <class... KArgs, class... Args>
+  void launch(void (*kernel)(KArgs...), dim3 grid, dim3 block, size_t shmem, Args... args) {
+    static_assert(sizeof...(KArgs) == sizeof...(Args), "argument count of the kernel");
+    if (recording) {
+      LaunchRec r;
+      r.func = reinterpret_cast<const void *>(kernel);
+      r.grid = grid;
+      r.block = block;
+      r.shmem = (uint32_t)shmem;
+      // each argument as the kernel's own parameter type
+      (record_arg<typename std::decay<KArgs>::type>(r, static_cast<typename std::decay<KArgs>::type>(args)), ...);
+      recs.push_back(std::move(r));
+      return;
+    }
     Timer *t = dispatch_timer;
     if (t && !t->used) {
       t->used = true;
@@ -201,6 +276,93 @@ struct Ctx {
     } else {
       hipLaunchKernelGGL(kernel, grid, block, shmem, stream, args...);
     }
+  }
+
+  template <class T> static void record_arg(LaunchRec &r, const T &x) {
+    size_t o = (r.args.size() + alignof(T) - 1) / alignof(T) * alignof(T);
+    r.args.resize(o + sizeof(T));
+    std::memcpy(r.args.data() + o, &x, sizeof(T));
+    r.off.push_back(o);
+  }
+
+  // Starts recording the launches made through launch().
+  void begin_record() {
+    recs.clear();
+    recording = true;
+  }
+
+  // Ends recording and runs the recorded launches on the stream: one by one
+  // the first time this exact sequence is seen, as a cached graph after.
+  void end_record() {
+    recording = false;
+    if (recs.empty()) return;
+    std::string blob;
+    for (const LaunchRec &r : recs) {
+      blob.append(reinterpret_cast<const char *>(&r.func), sizeof(r.func));
+      blob.append(reinterpret_cast<const char *>(&r.grid), sizeof(r.grid));
+      blob.append(reinterpret_cast<const char *>(&r.block), sizeof(r.block));
+      blob.append(reinterpret_cast<const char *>(&r.shmem), sizeof(r.shmem));
+      blob.append(r.args.data(), r.args.size());
+    }
+    uint64_t h = 1469598103934665603ull;  // FNV-1a
+    for (unsigned char ch : blob) h = (h ^ ch) * 1099511628211ull;
+    GraphCache::Entry &e = graphs.entries[h];
+    e.used = ++graphs.clock;
+    if (e.seen && e.blob != blob) {  // a hash collision: start over
+      if (e.exec) (void)hipGraphExecDestroy(e.exec);
+      e = GraphCache::Entry{};
+      e.used = graphs.clock;
+    }
+    if (!e.seen) e.blob = blob;
+    e.seen++;
+    if (e.seen >= 2 && !e.exec) e.exec = instantiate();
+    if (e.exec) {
+      HIPCHECK(hipGraphLaunch(e.exec, stream));
+    } else {
+      for (const LaunchRec &r : recs) {
+        std::vector<void *> params(r.off.size());
+        for (size_t i = 0; i < r.off.size(); i++) params[i] = const_cast<char *>(r.args.data() + r.off[i]);
+        HIPCHECK(hipLaunchKernel(r.func, r.grid, r.block, params.data(), r.shmem, stream));
+      }
+    }
+    recs.clear();
+    if (graphs.entries.size() > GraphCache::MAX_ENTRIES) {  // drop the least recently used
+      auto lru = graphs.entries.begin();
+      for (auto it = graphs.entries.begin(); it != graphs.entries.end(); ++it)
+        if (it->second.used < lru->second.used) lru = it;
+      if (lru->second.exec) (void)hipGraphExecDestroy(lru->second.exec);
+      graphs.entries.erase(lru);
+    }
+  }
+
+  // A graph of the recorded launches as one dependency chain.
+  hipGraphExec_t instantiate() {
+    hipGraph_t g = nullptr;
+    HIPCHECK(hipGraphCreate(&g, 0));
+    hipGraphNode_t prev = nullptr;
+    for (const LaunchRec &r : recs) {
+      std::vector<void *> params(r.off.size());
+      for (size_t i = 0; i < r.off.size(); i++) params[i] = const_cast<char *>(r.args.data() + r.off[i]);
+      hipKernelNodeParams kp;
+      std::memset(&kp, 0, sizeof(kp));
+      kp.func = const_cast<void *>(r.func);
+      kp.gridDim = r.grid;
+      kp.blockDim = r.block;
+      kp.sharedMemBytes = r.shmem;
+      kp.kernelParams = params.data();
+      hipGraphNode_t node = nullptr;
+      const hipError_t e = hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
+      if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        hip_check(e, "hipGraphAddKernelNode", __FILE__, __LINE__);
+      }
+      prev = node;
+    }
+    hipGraphExec_t x = nullptr;
+    const hipError_t e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    HIPCHECK(e);
+    return x;
   }
 
   // Resolves recorded events (the stream must have been synchronized).

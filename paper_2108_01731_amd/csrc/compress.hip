@@ -364,29 +364,41 @@ __global__ void k_cp_offsets(const int32_t *__restrict__ row, int64_t U, int64_t
   }
 }
 
-__global__ void k_max_deg(const int64_t *__restrict__ off, int64_t n, unsigned long long *__restrict__ out) {
-  unsigned long long m = 0;
+// out[0] = largest row length (atomicMax), out[1] = smallest (atomicMin).
+__global__ void k_deg_range(const int64_t *__restrict__ off, int64_t n, unsigned long long *__restrict__ out) {
+  unsigned long long m = 0, lo = ~0ull;
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
     unsigned long long d = (unsigned long long)(off[v + 1] - off[v]);
     m = d > m ? d : m;
+    lo = d < lo ? d : lo;
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
     unsigned long long y = __shfl_xor(m, o, WAVE);
     m = y > m ? y : m;
+    y = __shfl_xor(lo, o, WAVE);
+    lo = y < lo ? y : lo;
   }
-  if (lane_id() == 0 && m) atomicMax(out, m);
+  if (lane_id() == 0) {
+    if (m) atomicMax(&out[0], m);
+    atomicMin(&out[1], lo);
+  }
 }
 
-int64_t max_degree(Ctx &c, const int64_t *off, int64_t n) {
-  if (n <= 0) return 0;
-  unsigned long long *d = c.buf<unsigned long long>("maxdeg", 1);
-  HIPCHECK(hipMemsetAsync(d, 0, sizeof(unsigned long long), c.stream));
-  hipLaunchKernelGGL(k_max_deg, dim3(grid_for(n)), dim3(256), 0, c.stream, off, n, d);
+int64_t max_degree(Ctx &c, const int64_t *off, int64_t n, int64_t *min_out) {
+  if (n <= 0) {
+    if (min_out) *min_out = 0;
+    return 0;
+  }
+  unsigned long long *d = c.buf<unsigned long long>("maxdeg", 2);
+  const unsigned long long init[2] = {0ull, ~0ull};
+  h2d(c, d, init, sizeof(init));
+  hipLaunchKernelGGL(k_deg_range, dim3(grid_for(n)), dim3(256), 0, c.stream, off, n, d);
   LAUNCHCHECK();
-  unsigned long long h = 0;
-  d2h(c, &h, d, sizeof(h));
-  return (int64_t)h;
+  unsigned long long h[2] = {0, 0};
+  d2h(c, h, d, sizeof(h));
+  if (min_out) *min_out = (int64_t)h[1];
+  return (int64_t)h[0];
 }
 
 namespace {
@@ -635,12 +647,12 @@ void compress_dense(Ctx &c, const lcc_graph &g, const int32_t *C, OwnedGraph &ou
   Ctx::Timer tm(&c, "cp_dense", 40.0 * (double)n + (8.0 + wt_bytes(g.wt_kind)) * (double)g.arcs, (double)g.arcs);
   // capacities from host-known bounds: n' <= n, coarse arcs <= min(arcs, n^2)
   const int64_t ub = std::max<int64_t>(1, std::min<int64_t>(g.arcs, n * n));
-  out.off.ensure((nn + 1) * sizeof(int64_t));
-  out.col.ensure((size_t)ub * sizeof(int32_t));
-  out.wt.ensure((size_t)ub * (wide ? 8 : 4));
-  out.k.ensure((nn + 1) * sizeof(int64_t));
-  out.s.ensure((nn + 1) * sizeof(int64_t));
-  out.kk.ensure((nn + 1) * sizeof(int64_t));
+  c.ensure(out.off, (nn + 1) * sizeof(int64_t));
+  c.ensure(out.col, (size_t)ub * sizeof(int32_t));
+  c.ensure(out.wt, (size_t)ub * (wide ? 8 : 4));
+  c.ensure(out.k, (nn + 1) * sizeof(int64_t));
+  c.ensure(out.s, (nn + 1) * sizeof(int64_t));
+  c.ensure(out.kk, (nn + 1) * sizeof(int64_t));
   int64_t *info = c.buf<int64_t>("dn.info", 4);
   uint32_t *F = c.buf<uint32_t>("dn.F", nn * nn);
   int64_t *W = weighted ? c.buf<int64_t>("dn.W", nn * nn) : nullptr;
@@ -682,7 +694,8 @@ void compress_dense(Ctx &c, const lcc_graph &g, const int32_t *C, OwnedGraph &ou
 }  // namespace
 
 void compress_graph(Ctx &c, const lcc_graph &g, const int32_t *C, OwnedGraph &out, int32_t *map, bool wide,
-                    int64_t *maxdeg_out, const CompressJobs *cj) {
+                    int64_t *maxdeg_out, const CompressJobs *cj, int64_t *mindeg_out) {
+  if (mindeg_out) *mindeg_out = 0;  // unknown: rows of every length may be present
   const int32_t *jid = cj ? cj->jid : nullptr;
   const uint8_t *jcont = cj ? cj->jcont : nullptr;
   const int64_t n = g.n;
@@ -690,7 +703,7 @@ void compress_graph(Ctx &c, const lcc_graph &g, const int32_t *C, OwnedGraph &ou
   out.arcs = 0;
   out.wt_kind = wide ? LCC_WT_I64 : LCC_WT_I32;
   if (n <= 0) {
-    out.off.ensure(sizeof(int64_t));
+    c.ensure(out.off, sizeof(int64_t));
     HIPCHECK(hipMemsetAsync(out.off.p, 0, sizeof(int64_t), c.stream));
     if (maxdeg_out) *maxdeg_out = 0;
     return;
@@ -762,13 +775,13 @@ void compress_graph(Ctx &c, const lcc_graph &g, const int32_t *C, OwnedGraph &ou
     d2h(c, &U, tots + 2, sizeof(int64_t));
   }
   out.arcs = U;
-  out.off.ensure((size_t)(n2 + 1) * sizeof(int64_t));
-  out.col.ensure((size_t)(U > 0 ? U : 1) * sizeof(int32_t));
-  out.wt.ensure((size_t)(U > 0 ? U : 1) * (wide ? 8 : 4));
+  c.ensure(out.off, (size_t)(n2 + 1) * sizeof(int64_t));
+  c.ensure(out.col, (size_t)(U > 0 ? U : 1) * sizeof(int32_t));
+  c.ensure(out.wt, (size_t)(U > 0 ? U : 1) * (wide ? 8 : 4));
   // one extra slot: the per-cluster sums park dropped vertices at key n2
-  out.k.ensure((size_t)(n2 + 1) * sizeof(int64_t));
-  out.s.ensure((size_t)(n2 + 1) * sizeof(int64_t));
-  out.kk.ensure((size_t)(n2 + 1) * sizeof(int64_t));
+  c.ensure(out.k, (size_t)(n2 + 1) * sizeof(int64_t));
+  c.ensure(out.s, (size_t)(n2 + 1) * sizeof(int64_t));
+  c.ensure(out.kk, (size_t)(n2 + 1) * sizeof(int64_t));
   int32_t *orow = c.buf<int32_t>("cp.row", (size_t)(U > 0 ? U : 1));
   if (U > 0) {
     Ctx::Timer tm(&c, "cp_unique", (double)U * (8.0 + 8.0 + 4.0 + 4.0 + (wide ? 8 : 4)), (double)U);
@@ -818,7 +831,7 @@ void compress_graph(Ctx &c, const lcc_graph &g, const int32_t *C, OwnedGraph &ou
                        cj->jobs, cj->jbase_next);
     LAUNCHCHECK();
   }
-  if (maxdeg_out) *maxdeg_out = max_degree(c, out.off.as<int64_t>(), n2);
+  if (maxdeg_out) *maxdeg_out = max_degree(c, out.off.as<int64_t>(), n2, mindeg_out);
 }
 
 }  // namespace lcc

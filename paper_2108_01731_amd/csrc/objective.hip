@@ -63,6 +63,35 @@ __global__ __launch_bounds__(OB_NT) void k_obj_intra(const int64_t *__restrict__
   }
 }
 
+void launch_objective_partials(hipStream_t stream, const lcc_graph &g, const int32_t *C, const int64_t *K,
+                               const int64_t *KK, int64_t nb, u128 *part) {
+  const int64_t n = g.n;
+  hipLaunchKernelGGL(k_obj_pairs, dim3((unsigned)nb), dim3(OB_NT), 0, stream, K, KK, n, part);
+  LAUNCHCHECK();
+  switch (g.wt_kind) {
+    case LCC_WT_UNIT:
+      hipLaunchKernelGGL((k_obj_intra<LCC_WT_UNIT>), dim3((unsigned)nb), dim3(OB_NT), 0, stream, g.off, g.col, g.wt,
+                         g.s, C, n, part + nb, part + 2 * nb);
+      break;
+    case LCC_WT_I16:
+      hipLaunchKernelGGL((k_obj_intra<LCC_WT_I16>), dim3((unsigned)nb), dim3(OB_NT), 0, stream, g.off, g.col, g.wt,
+                         g.s, C, n, part + nb, part + 2 * nb);
+      break;
+    case LCC_WT_I32:
+      hipLaunchKernelGGL((k_obj_intra<LCC_WT_I32>), dim3((unsigned)nb), dim3(OB_NT), 0, stream, g.off, g.col, g.wt,
+                         g.s, C, n, part + nb, part + 2 * nb);
+      break;
+    default:
+      hipLaunchKernelGGL((k_obj_intra<LCC_WT_I64>), dim3((unsigned)nb), dim3(OB_NT), 0, stream, g.off, g.col, g.wt,
+                         g.s, C, n, part + nb, part + 2 * nb);
+  }
+  LAUNCHCHECK();
+}
+
+i128 objective_from_sums(int64_t p, int64_t q, i128 pairs2, i128 win2, i128 ssum) {
+  return (i128)q * (ssum + win2 / 2) - (i128)p * (pairs2 / 2);
+}
+
 i128 objective_num(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const int32_t *C) {
   const int64_t n = g.n;
   if (n <= 0) return 0;
@@ -72,26 +101,7 @@ i128 objective_num(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const int32
   cluster_sums_k_kk(c, g, C, K, KK);
   const int64_t nb = std::min<int64_t>(cdiv(n, OB_NT), (int64_t)c.num_cu * 4);
   u128 *part = c.buf<u128>("ob.part", (size_t)(3 * nb));
-  hipLaunchKernelGGL(k_obj_pairs, dim3((unsigned)nb), dim3(OB_NT), 0, c.stream, K, KK, n, part);
-  LAUNCHCHECK();
-  switch (g.wt_kind) {
-    case LCC_WT_UNIT:
-      hipLaunchKernelGGL((k_obj_intra<LCC_WT_UNIT>), dim3((unsigned)nb), dim3(OB_NT), 0, c.stream, g.off, g.col, g.wt,
-                         g.s, C, n, part + nb, part + 2 * nb);
-      break;
-    case LCC_WT_I16:
-      hipLaunchKernelGGL((k_obj_intra<LCC_WT_I16>), dim3((unsigned)nb), dim3(OB_NT), 0, c.stream, g.off, g.col, g.wt,
-                         g.s, C, n, part + nb, part + 2 * nb);
-      break;
-    case LCC_WT_I32:
-      hipLaunchKernelGGL((k_obj_intra<LCC_WT_I32>), dim3((unsigned)nb), dim3(OB_NT), 0, c.stream, g.off, g.col, g.wt,
-                         g.s, C, n, part + nb, part + 2 * nb);
-      break;
-    default:
-      hipLaunchKernelGGL((k_obj_intra<LCC_WT_I64>), dim3((unsigned)nb), dim3(OB_NT), 0, c.stream, g.off, g.col, g.wt,
-                         g.s, C, n, part + nb, part + 2 * nb);
-  }
-  LAUNCHCHECK();
+  launch_objective_partials(c.stream, g, C, K, KK, nb, part);
   std::vector<u128> h((size_t)(3 * nb));
   d2h(c, h.data(), part, h.size() * sizeof(u128));
   i128 pairs2 = 0, win2 = 0, ssum = 0;
@@ -100,7 +110,7 @@ i128 objective_num(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const int32
     win2 += (i128)h[nb + i];
     ssum += (i128)h[2 * nb + i];
   }
-  return (i128)q * (ssum + win2 / 2) - (i128)p * (pairs2 / 2);
+  return objective_from_sums(p, q, pairs2, win2, ssum);
 }
 
 }  // namespace lcc

@@ -25,6 +25,39 @@ struct GraphSummary {
 // overflow bounds need.
 GraphSummary summarize_graph(Ctx &c, const lcc_graph &g, const int32_t *C, bool check_structure);
 
+// The validation pass in pieces, for callers that bring their own scratch:
+// the vertex pass writes one row of VAL_VROW values per block {error bits,
+// sum k, sum kk, sum |s|, negative s, largest degree, 0, 0}, the arc pass one
+// row of VAL_AROW values {error bits, sum |w|, negative w}; rows combine with
+// combine_*_row (sums saturate at 2^64 - 1) and the combined rows fill a
+// summary.  summary_from_vertex_row returns false when the offsets, k, kk or
+// ids are unusable (the arc pass must then not run).
+constexpr int VAL_VROW = 8;
+constexpr int VAL_AROW = 3;
+
+__host__ __device__ inline uint64_t sat_add(uint64_t a, uint64_t b) {
+  const uint64_t s = a + b;
+  return s < a ? ~0ull : s;
+}
+__host__ __device__ inline void combine_vertex_row(uint64_t *acc, const uint64_t *r) {
+  acc[0] |= r[0];
+  acc[1] = sat_add(acc[1], r[1]);
+  acc[2] = sat_add(acc[2], r[2]);
+  acc[3] = sat_add(acc[3], r[3]);
+  acc[4] |= r[4];
+  acc[5] = r[5] > acc[5] ? r[5] : acc[5];
+}
+__host__ __device__ inline void combine_arc_row(uint64_t *acc, const uint64_t *r) {
+  acc[0] |= r[0];
+  acc[1] = sat_add(acc[1], r[1]);
+  acc[2] |= r[2];
+}
+int64_t validation_blocks(const Ctx &c, int64_t n);
+void launch_validate_vertices(hipStream_t stream, const lcc_graph &g, const int32_t *C, int64_t nb, uint64_t *part);
+void launch_validate_arcs(hipStream_t stream, const lcc_graph &g, bool check, int64_t nb, uint64_t *part);
+bool summary_from_vertex_row(const uint64_t *r, GraphSummary &s);
+void summary_from_arc_row(const uint64_t *r, bool check, GraphSummary &s);
+
 // Checks the int64 bounds; returns LCC_OK or LCC_ERR_OVERFLOW.
 lcc_status overflow_bounds(const GraphSummary &s, int64_t p, int64_t q, std::string *why);
 
@@ -38,6 +71,7 @@ struct BMShape {
   bool acc32;       // every row's sum of |w| is below 2^31 (32-bit accumulators)
   bool identity;    // C[v] = v on entry
   bool simple;      // no row repeats a neighbor
+  int64_t mindeg = 0;  // a lower bound of the shortest row length
 };
 
 // Jobs of a batched run at one level: the graph holds the jobs' vertices
@@ -78,12 +112,21 @@ struct CompressJobs {
 };
 
 // Compress g by C into `out` (library-owned arrays); map (device int32[n]).
-// `wide` selects int64 output weights (else int32).
+// `wide` selects int64 output weights (else int32).  maxdeg_out / mindeg_out
+// (nullable) receive the longest and shortest row of the output (the
+// shortest may be reported as 0 when it is not computed).
 void compress_graph(Ctx &c, const lcc_graph &g, const int32_t *C, OwnedGraph &out, int32_t *map, bool wide,
-                    int64_t *maxdeg_out, const CompressJobs *cj = nullptr);
+                    int64_t *maxdeg_out, const CompressJobs *cj = nullptr, int64_t *mindeg_out = nullptr);
 
 // Exact objective numerator of clustering C (ids in [0, n)).
 i128 objective_num(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const int32_t *C);
+
+// The objective from caller-given per-cluster sums K, KK (ids in [0, n)):
+// 3 * nb block partials in `part` (sum over clusters of K^2 - KK, then the
+// intra-cluster arc weight, then sum s), combined by objective_from_sums.
+void launch_objective_partials(hipStream_t stream, const lcc_graph &g, const int32_t *C, const int64_t *K,
+                               const int64_t *KK, int64_t nb, u128 *part);
+i128 objective_from_sums(int64_t p, int64_t q, i128 pairs2, i128 win2, i128 ssum);
 
 // labels[v] = rank of C[v]'s cluster in the order of smallest members.
 // Returns the number of clusters.
@@ -92,8 +135,8 @@ int64_t canonical_labels(Ctx &c, int64_t n, const int32_t *C, int32_t *labels);
 // Per-cluster sums of k and kk (kk = k^2 when absent) for ids in [0, n).
 void cluster_sums_k_kk(Ctx &c, const lcc_graph &g, const int32_t *C, int64_t *K, int64_t *KK);
 
-// Largest row length of a CSR offset array.
-int64_t max_degree(Ctx &c, const int64_t *off, int64_t n);
+// Largest row length of a CSR offset array (and, min_out, the smallest).
+int64_t max_degree(Ctx &c, const int64_t *off, int64_t n, int64_t *min_out = nullptr);
 
 // C[v] = Cnext[map[v]] for v < n with map[v] >= 0.
 void flatten(Ctx &c, int64_t n, const int32_t *map, const int32_t *Cnext, int32_t *C);

@@ -306,7 +306,7 @@ def _community_sizes(n: int, smin: int, smax: int, tau: float, rng: np.random.Ge
 
 def chung_lu_planted(n: int, m: int, gamma: float, mixing: float, seed: int, device="cpu",
                      comm_min: int = 20, comm_max: int = 5000, comm_tau: float = 2.0,
-                     k_is_degree: bool = True, max_rounds: int = 8) -> HostGraph:
+                     k_is_degree: bool = True, max_rounds: int = 8, return_communities: bool = False):
     """Chung-Lu graph with planted communities.
 
     Expected degrees follow a power law with exponent ``gamma`` (max capped at
@@ -321,7 +321,9 @@ def chung_lu_planted(n: int, m: int, gamma: float, mixing: float, seed: int, dev
     to expected degree inside the first endpoint's community.  Self-loops and
     repeats are dropped; the final edge set is a uniform subset of size m (or
     everything drawn, if ``max_rounds`` runs out first).  k = degree (the
-    modularity setting) unless ``k_is_degree`` is False (then k = 1)."""
+    modularity setting) unless ``k_is_degree`` is False (then k = 1).  With
+    ``return_communities`` returns (graph, comm) where comm (int64 numpy, in
+    the relabelled vertex ids) is each vertex's planted community."""
     device = torch.device(device)
     gen = _gen(seed, device)
     rng = np.random.default_rng(seed)
@@ -385,6 +387,51 @@ def chung_lu_planted(n: int, m: int, gamma: float, mixing: float, seed: int, dev
     perm = _hash_perm(n, 2 * seed + 2, device)
     off, col = csr_relabeled(n, u, v, perm)
     del u, v
+    deg = off[1:] - off[:-1]
+    k = deg.clone() if k_is_degree else torch.ones(n, dtype=torch.int64, device=device)
+    if return_communities:
+        comm = np.empty(n, dtype=np.int64)
+        comm[perm.cpu().numpy()[slot_vertex_np]] = comm_of_slot_np
+        return HostGraph(off, col, k), comm
+    return HostGraph(off, col, k)
+
+
+# ------------------------------------------------------------------- rMAT
+
+def rmat(scale: int, m: int, seed: int, a: float = 0.5, b: float = 0.1, c: float = 0.1, device="cpu",
+         k_is_degree: bool = False, chunk: int = 1 << 24) -> HostGraph:
+    """rMAT graph (Chakrabarti, Zhan, Faloutsos 2004) on n = 2^scale vertices:
+    m edge draws, each descending `scale` levels of the adjacency matrix and
+    taking the quadrant (top-left, top-right, bottom-left, bottom-right) with
+    probabilities (a, b, c, 1 - a - b - c); the paper's scalability graphs
+    use a = 0.5, b = c = 0.1.  Self-loops and repeated edges are dropped (so
+    fewer than m edges remain), then vertices get a seeded random relabel.
+    k = 1 (the correlation-clustering setting) unless k_is_degree."""
+    device = torch.device(device)
+    gen = _gen(seed, device)
+    n = 1 << scale
+    parts = []
+    done = 0
+    while done < m:
+        cnt = min(chunk, m - done)
+        u = torch.zeros(cnt, dtype=torch.int64, device=device)
+        v = torch.zeros(cnt, dtype=torch.int64, device=device)
+        for _ in range(scale):
+            r = torch.rand(cnt, generator=gen, device=device, dtype=torch.float64)
+            down = (r >= a + b).to(torch.int64)  # bottom half: quadrants c and d
+            right = ((r >= a) & (r < a + b) | (r >= a + b + c)).to(torch.int64)  # quadrants b and d
+            u = (u << 1) | down
+            v = (v << 1) | right
+        keep = u != v
+        u, v = u[keep], v[keep]
+        parts.append(torch.unique(torch.minimum(u, v) * n + torch.maximum(u, v)))
+        done += cnt
+    keys = torch.unique(torch.cat(parts))
+    del parts
+    u, v = keys // n, keys % n
+    del keys
+    perm = _hash_perm(n, 2 * seed + 2, device)
+    off, col = csr_relabeled(n, u, v, perm)
     deg = off[1:] - off[:-1]
     k = deg.clone() if k_is_degree else torch.ones(n, dtype=torch.int64, device=device)
     return HostGraph(off, col, k)

@@ -19,9 +19,10 @@ LIB_PATH = os.path.join(_HERE, "liblcc.so")
 
 LCC_OK, LCC_ERR_INVALID_ARG, LCC_ERR_OVERFLOW, LCC_ERR_OUT_OF_MEMORY, LCC_ERR_DEVICE, LCC_ERR_UNSUPPORTED = range(6)
 LCC_WT_UNIT, LCC_WT_I16, LCC_WT_I32, LCC_WT_I64 = range(4)
-LCC_FRONTIER_ALL, LCC_FRONTIER_NBR = 0, 1
+LCC_FRONTIER_ALL, LCC_FRONTIER_NBR, LCC_FRONTIER_CLUSTERS = 0, 1, 2
 LCC_TERM_NO_MOVES, LCC_TERM_NUM_ITER, LCC_TERM_STOPPED = 0, 1, 2
 LCC_HUB_LIMIT_MAX = 8601  # default and largest Params.hub_limit
+LCC_SMALL_LEVEL_MAX = 8192  # largest Params.small_level
 MAX_ITER_STATS = 64
 MAX_LEVELS = 64
 
@@ -53,7 +54,8 @@ class _Params(ctypes.Structure):
         ("frontier", ctypes.c_int32), ("refine", ctypes.c_int32), ("allow_isolate", ctypes.c_int32),
         ("max_levels", ctypes.c_int32), ("stop_after_subrounds", ctypes.c_int64),
         ("validate", ctypes.c_int32), ("timing", ctypes.c_int32), ("hub_limit", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 5),
+        ("queue_ahead", ctypes.c_int32), ("small_level", ctypes.c_int32), ("low_merge", ctypes.c_int32),
+        ("async_moves", ctypes.c_int32), ("no_graph_replay", ctypes.c_int32),
     ]
 
 
@@ -95,6 +97,14 @@ class _BatchStats(ctypes.Structure):
     ]
 
 
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+
+
+class _Allocator(ctypes.Structure):
+    _fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("user", ctypes.c_void_p)]
+
+
 class _KernelStat(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 64), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double),
                 ("bytes", ctypes.c_double), ("items", ctypes.c_double)]
@@ -102,8 +112,8 @@ class _KernelStat(ctypes.Structure):
 
 EXPORTS = (
     "lcc_params_default", "lcc_last_error", "lcc_ctx_create", "lcc_ctx_destroy", "lcc_best_move", "lcc_compress",
-    "lcc_graph_owned_view", "lcc_graph_owned_free", "lcc_objective", "lcc_cluster", "lcc_cluster_batch",
-    "lcc_sweep", "lcc_ctx_kernel_stats", "lcc_ctx_reset_kernel_stats",
+    "lcc_graph_owned_view", "lcc_graph_owned_free", "lcc_objective", "lcc_cluster",
+    "lcc_cluster_batch", "lcc_sweep", "lcc_ctx_kernel_stats", "lcc_ctx_reset_kernel_stats",
 )
 
 _lib = None
@@ -124,7 +134,7 @@ def load_library(path: str = LIB_PATH):
     lib.lcc_last_error.restype = ctypes.c_char_p
     lib.lcc_last_error.argtypes = []
     lib.lcc_ctx_create.restype = st
-    lib.lcc_ctx_create.argtypes = [i32, ctypes.POINTER(P)]
+    lib.lcc_ctx_create.argtypes = [i32, ctypes.POINTER(_Allocator), ctypes.POINTER(P)]
     lib.lcc_ctx_destroy.restype = st
     lib.lcc_ctx_destroy.argtypes = [P]
     lib.lcc_best_move.restype = st
@@ -224,6 +234,11 @@ class Params:
     validate: int = 1
     timing: int = 0
     hub_limit: int = 0
+    queue_ahead: int = 0
+    small_level: int = 0
+    low_merge: int = 0
+    async_moves: int = 0
+    no_graph_replay: int = 0
 
     def _c(self) -> _Params:
         p = _Params()
@@ -231,6 +246,8 @@ class Params:
         p.frontier, p.refine, p.allow_isolate = self.frontier, self.refine, self.allow_isolate
         p.max_levels, p.stop_after_subrounds = self.max_levels, self.stop_after_subrounds
         p.validate, p.timing, p.hub_limit = self.validate, self.timing, self.hub_limit
+        p.queue_ahead, p.small_level, p.low_merge = self.queue_ahead, self.small_level, self.low_merge
+        p.async_moves, p.no_graph_replay = self.async_moves, self.no_graph_replay
         return p
 
 
@@ -240,14 +257,47 @@ def _stream_ptr(stream):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
-class Context:
-    """An lcc_ctx bound to one GPU."""
+class TorchAllocator:
+    """lcc_allocator callbacks backed by torch's caching allocator: the
+    library's scratch and contracted graphs come from the same pool as the
+    caller's tensors, and a growing buffer goes back to the pool instead of
+    through hipFree.  The callbacks must outlive the context that uses them
+    (Context keeps a reference)."""
 
     def __init__(self, device: int = 0):
+        self.device = device
+        self.live = {}  # ptr -> bytes, for diagnostics and tests
+
+        def alloc(user, nbytes, stream):
+            try:
+                ptr = torch.cuda.caching_allocator_alloc(int(nbytes), self.device, int(stream or 0))
+            except Exception:  # out of memory: the library reports LCC_ERR_OUT_OF_MEMORY
+                return None
+            self.live[ptr] = int(nbytes)
+            return ptr
+
+        def free(user, ptr, nbytes, stream):
+            try:
+                self.live.pop(ptr, None)
+                torch.cuda.caching_allocator_delete(ptr)
+            except Exception:
+                pass
+
+        self._alloc_fn = _ALLOC_FN(alloc)
+        self._free_fn = _FREE_FN(free)
+        self.c = _Allocator(self._alloc_fn, self._free_fn, None)
+
+
+class Context:
+    """An lcc_ctx bound to one GPU; `allocator` (a TorchAllocator, or None
+    for hipMalloc) supplies its device memory."""
+
+    def __init__(self, device: int = 0, allocator: Optional[TorchAllocator] = None):
         lib = load_library()
         self.device = device
+        self.allocator = allocator
         h = ctypes.c_void_p()
-        _check(lib.lcc_ctx_create(device, ctypes.byref(h)))
+        _check(lib.lcc_ctx_create(device, ctypes.byref(allocator.c) if allocator else None, ctypes.byref(h)))
         self._h = h
 
     def close(self):

@@ -181,12 +181,14 @@ class Server:
     """Continuous-batching server on one GPU.
 
     slots: concurrent batches (each a library context + HIP stream);
+    torch_pool: the contexts take device memory from torch's caching allocator;
     hbm_budget: bytes of HBM estimates admitted requests may hold together;
     max_jobs / max_arcs: caps of one batch; plain: one request at a time
     through lcc_cluster on one slot (the comparison path)."""
 
     def __init__(self, device: int = 0, slots: int = 2, hbm_budget: int = 64 << 30, max_jobs: int = 4096,
-                 max_arcs: int = 1_500_000_000, params: Optional[lcc.Params] = None, plain: bool = False):
+                 max_arcs: int = 1_500_000_000, params: Optional[lcc.Params] = None, plain: bool = False,
+                 torch_pool: bool = True):
         self.device = device
         self.plain = plain
         self.slots = 1 if plain else slots
@@ -194,7 +196,11 @@ class Server:
         self.max_jobs = 1 if plain else max_jobs
         self.max_arcs = max_arcs
         self.params = params or lcc.Params()
-        self.ctxs = [lcc.Context(device) for _ in range(self.slots)]
+        # each slot's context takes its scratch from torch's caching allocator
+        # (torch_pool): a buffer that grows goes back to the pool instead of
+        # through hipFree, which would wait for every slot's work
+        self.ctxs = [lcc.Context(device, lcc.TorchAllocator(device) if torch_pool else None)
+                     for _ in range(self.slots)]
         self.streams = [torch.cuda.Stream(device=device) for _ in range(self.slots)]
         self.up_stream = torch.cuda.Stream(device=device)
 

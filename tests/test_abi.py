@@ -49,6 +49,7 @@ def test_struct_layout_matches_header(tmp_path):
         "lcc_job_out": (L._JobOut, ["obj", "clusters", "levels", "top_moved"]),
         "lcc_batch_stats": (L._BatchStats, ["levels", "n_level", "arcs_level", "moves_total", "ms_total"]),
         "lcc_kernel_stat": (L._KernelStat, ["name", "launches", "total_ms", "bytes", "items"]),
+        "lcc_allocator": (L._Allocator, ["alloc", "free", "user"]),
     }
     src = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void) {"]
     for s, (_, fl) in fields.items():
@@ -77,7 +78,12 @@ def test_params_default(lib):
 
 
 def test_host_side_argument_errors(lib):
-    assert lib.lcc_ctx_create(0, None) == L.LCC_ERR_INVALID_ARG
+    assert lib.lcc_ctx_create(0, None, None) == L.LCC_ERR_INVALID_ARG
+    # an allocator needs both callbacks (checked before any device call)
+    half = L._Allocator(L._ALLOC_FN(lambda u, b, s: None), L._FREE_FN(), None)
+    h = ctypes.c_void_p()
+    assert lib.lcc_ctx_create(0, ctypes.byref(half), ctypes.byref(h)) == L.LCC_ERR_INVALID_ARG
+    assert b"callback" in lib.lcc_last_error()
     assert b"NULL" in lib.lcc_last_error()
     g = L._Graph()
     p = L._Params()

@@ -59,7 +59,7 @@ def sbm_jobs(count, seed, nmax=1500):
     return graphs, lams
 
 
-CFGS = [dict(), dict(S=2, refine=0), dict(S=8, frontier=0, num_iter=20), dict(allow_isolate=0),
+CFGS = [dict(), dict(S=2, refine=0), dict(S=8, frontier=0, num_iter=20), dict(frontier=2), dict(allow_isolate=0),
         dict(max_levels=2), dict(S=1, num_iter=6, max_levels=4), dict(num_iter=1)]
 
 
@@ -153,3 +153,22 @@ def test_batch_rejects_invalid_input(ctx):
     E = G.HostGraph(np.zeros(1, np.int64), np.zeros(0, np.int32), np.zeros(0, np.int64))
     lab, jobs, st = L.lcc_cluster_batch(ctx, dev(E), [0], [], L.Params())
     assert lab.numel() == 0 and jobs == []
+
+
+def test_config_batch_sampled_jobs_equal_the_oracle(ctx):
+    """The 4096-job SBM batch at its full shape (n log-uniform in [100,
+    50000], average degree in [8, 40], each job its own lambda), in the one
+    lcc_cluster_batch call the benchmark times: a sample of jobs (the largest,
+    the smallest and six seeded others) equals the oracle's clustering of the
+    job alone, labels, numerator and cluster count."""
+    graphs, lams = G.sbm_batch(4096, 0, device="cuda")
+    P, start = G.pack_torch(graphs, "cuda")
+    lab, jobs, _ = L.lcc_cluster_batch(ctx, dev(P), start, lams, L.Params())
+    lab = lab.cpu().numpy()
+    ns = [g.n for g in graphs]
+    pick = {int(np.argmax(ns)), int(np.argmin(ns))}
+    pick |= set(int(x) for x in np.random.default_rng(3).choice(len(graphs), 6, replace=False))
+    for j in sorted(pick):
+        lo, No, so = O.cluster(H.to_oracle(graphs[j]), *lams[j], O.Params())
+        assert np.array_equal(lab[start[j]:start[j + 1]], lo), f"job {j} (n={ns[j]}) differs from the oracle"
+        assert jobs[j]["N"] == No and jobs[j]["clusters"] == so["clusters"], j

@@ -87,11 +87,19 @@ def test_subround_by_subround_parity(ctx, idx):
     for stop in range(1, 2 * S + 2):
         Co, so, Cd, sd = run_pair_best_move(ctx, h, p, q, S=S, seed=7, stop_after_subrounds=stop)
         assert_same_bm(Co, so, Cd, sd)
+    # the neighbors-of-clusters frontier, from a clustering with multi-vertex
+    # clusters, into the third iteration
+    C0 = np.random.default_rng(idx).integers(0, max(1, h.n // 20), size=h.n).astype(np.int32)
+    for stop in (S + 1, 2 * S + 1):
+        Co, so, Cd, sd = run_pair_best_move(ctx, h, p, q, C0=C0, S=S, seed=3, frontier=2,
+                                            stop_after_subrounds=stop)
+        assert_same_bm(Co, so, Cd, sd)
 
 
 @pytest.mark.parametrize("idx", range(8))
 @pytest.mark.parametrize("cfg", [dict(S=4), dict(S=1, num_iter=4), dict(S=2, frontier=0), dict(S=8, allow_isolate=0),
-                                 dict(S=4, seed=12345, num_iter=25)])
+                                 dict(S=4, seed=12345, num_iter=25), dict(S=4, frontier=2),
+                                 dict(S=3, frontier=2, seed=99, num_iter=25)])
 def test_best_move_parity(ctx, idx, cfg):
     name, h, p, q = cases()[idx]
     Co, so, Cd, sd = run_pair_best_move(ctx, h, p, q, **cfg)
@@ -183,7 +191,7 @@ def test_objective_parity(ctx, idx):
 
 
 @pytest.mark.parametrize("idx", range(8))
-@pytest.mark.parametrize("cfg", [dict(), dict(S=2, refine=0), dict(S=8, frontier=0, num_iter=20)])
+@pytest.mark.parametrize("cfg", [dict(), dict(S=2, refine=0), dict(S=8, frontier=0, num_iter=20), dict(frontier=2)])
 def test_cluster_parity(ctx, idx, cfg):
     name, h, p, q = cases()[idx]
     lo, No, so = O.cluster(H.to_oracle(h), p, q, oparams(**cfg))
@@ -388,45 +396,124 @@ def test_full_size_modularity_graph_sampled(ctx):
     assert O.objective(g_o, p, q, lo) == No
 
 
-def test_full_size_billion_edge_graph(ctx):
-    """The 65.6M-vertex / 1.8B-edge Chung-Lu workload (3.6B arcs, beyond
-    2^31), in the launch configurations the benchmark uses: sampled vertices
-    of the first sub-round equal the oracle's one-by-one decision; a whole
-    level-0 iteration through the device-driven launches equals the same
-    iteration through the host-driven launches (whose first sub-round the
-    sample checks); the full clustering's objective equals the oracle's
-    evaluation of the returned labels."""
-    h = G.chung_lu_planted(65_608_366, 1_806_067_135, 2.2, 0.4, seed=1, device="cuda")
-    g_d = dev(h)
+def assert_same_graph_chunked(go, gd, chunk=1 << 27):
+    """assert_same_graph for graphs of billions of arcs, compared in chunks."""
+    assert gd.n == go.n and gd.arcs == len(go.col)
+    for name in ("off", "k", "s", "kk"):
+        assert np.array_equal(getattr(go, name), getattr(gd, name).cpu().numpy()), name
+    for a in range(0, len(go.col), chunk):
+        b = min(a + chunk, len(go.col))
+        assert np.array_equal(go.col[a:b], gd.col[a:b].cpu().numpy()), ("col", a)
+        assert np.array_equal(go.wt[a:b], gd.wt[a:b].cpu().numpy().astype(np.int64)), ("wt", a)
+
+
+# The 65.6M-vertex / 1.8B-edge Chung-Lu workload (3.6B arcs, beyond 2^31)
+# against the oracle element by element (its OpenMP build, whose results equal
+# the single-threaded build's), in steps that share one generated graph: the
+# whole first sub-round (host-driven launches), the whole first level-0
+# iteration through the device-driven launches the benchmark uses, the
+# level-0 contraction of that clustering (every array), and the full
+# clustering (its objective evaluated by the oracle on the returned labels;
+# with LCC_FULL_ORACLE=1 also labels and hierarchy against the oracle's own
+# full clustering).
+
+def progress(msg):
+    print(f"[billion-edge] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def c3():
+    state = {}
+    yield state
+    state.clear()
     torch.cuda.empty_cache()
-    p, q = 1, h.arcs
+
+
+def c3_graph(state):
+    if "g_d" not in state:
+        progress("generating the graph")
+        h = G.chung_lu_planted(65_608_366, 1_806_067_135, 2.2, 0.4, seed=1, device="cuda")
+        state["g_d"] = dev(h)
+        torch.cuda.empty_cache()
+        state["p"], state["q"] = 1, h.arcs
+        hh = h.numpy()
+        del h
+        state["g_o"] = H.to_oracle(hh)
+        progress(f"n={state['g_o'].n} arcs={state['g_o'].arcs}")
+    return state["g_d"], state["g_o"], state["p"], state["q"]
+
+
+def test_billion_edge_first_subround(ctx, c3):
+    g_d, g_o, p, q = c3_graph(c3)
     S = 4
-    hh = h.numpy()
-    del h
-    g_o = H.to_oracle(hh)
-    n = g_o.n
-    # first sub-round (stopping inside an iteration: host-driven launches)
-    C = torch.arange(n, dtype=torch.int32, device="cuda")
-    L.lcc_best_move(ctx, g_d, p, q, dparams(S=S, stop_after_subrounds=1), C)
-    Cd1 = C.cpu().numpy()
-    hr = O.round_hash(1, 0, 0, 0)
-    rng = np.random.default_rng(1)
-    cand = rng.choice(n, size=20000, replace=False)
-    U = np.array([v for v in cand if O.color(hr, int(v), S) == 0], dtype=np.int32)[:4000]
-    D = O.decide_many(g_o, p, q, np.arange(n, dtype=np.int32), U)
-    assert np.array_equal(D, Cd1[U])
-    del Cd1
-    # one whole iteration: device-driven launches vs host-driven launches
-    Ca = torch.arange(n, dtype=torch.int32, device="cuda")
-    sa = L.lcc_best_move(ctx, g_d, p, q, dparams(S=S, num_iter=1), Ca)
-    Cb = torch.arange(n, dtype=torch.int32, device="cuda")
-    sb = L.lcc_best_move(ctx, g_d, p, q, dparams(S=S, stop_after_subrounds=S), Cb)
-    assert torch.equal(Ca, Cb)
-    for key in ("moves", "arcs_scanned", "candidates", "vertices_processed"):
-        assert sa[key] == sb[key], (key, sa[key], sb[key])
-    del Ca, Cb, C
-    # full clustering: the objective of the returned labels, evaluated by the oracle
+    prev = O.use_openmp(True)
+    try:
+        C = torch.arange(g_o.n, dtype=torch.int32, device="cuda")
+        sd = L.lcc_best_move(ctx, g_d, p, q, dparams(S=S, stop_after_subrounds=1), C)
+        progress("oracle: first sub-round")
+        Co, so = O.best_move(g_o, p, q, oparams(S=S, stop_after_subrounds=1))
+        assert np.array_equal(Co, C.cpu().numpy())
+        assert so["moves"] == sd["moves"] and so["arcs_scanned"] == sd["arcs_scanned"]
+    finally:
+        O.use_library(prev)
+
+
+def test_billion_edge_first_iteration(ctx, c3):
+    g_d, g_o, p, q = c3_graph(c3)
+    S = 4
+    prev = O.use_openmp(True)
+    try:
+        C = torch.arange(g_o.n, dtype=torch.int32, device="cuda")
+        sd = L.lcc_best_move(ctx, g_d, p, q, dparams(S=S, num_iter=1), C)
+        progress("oracle: first iteration")
+        Co, so = O.best_move(g_o, p, q, oparams(S=S, num_iter=1))
+        assert np.array_equal(Co, C.cpu().numpy())
+        for key in ("iterations", "subrounds", "moves", "arcs_scanned", "vertices_processed", "term"):
+            assert so[key] == sd[key], (key, so[key], sd[key])
+        c3["C1"] = Co
+    finally:
+        O.use_library(prev)
+
+
+def test_billion_edge_level0_contraction(ctx, c3):
+    g_d, g_o, p, q = c3_graph(c3)
+    if "C1" not in c3:
+        pytest.skip("needs the first-iteration clustering of the previous step")
+    C1 = c3.pop("C1")
+    prev = O.use_openmp(True)
+    try:
+        g2d, map_d = L.lcc_compress(ctx, g_d, torch.from_numpy(C1).cuda())
+        progress(f"contracted on the GPU: n={g2d.n} arcs={g2d.arcs}; oracle contraction")
+        g2o, map_o = O.compress(g_o, C1)
+        assert np.array_equal(map_o, map_d.cpu().numpy())
+        del map_d, map_o
+        progress("comparing the contracted graphs")
+        assert_same_graph_chunked(g2o, g2d)
+    finally:
+        O.use_library(prev)
+    del g2d, g2o
+    torch.cuda.empty_cache()
+
+
+def test_billion_edge_full_clustering(ctx, c3):
+    import os
+
+    g_d, g_o, p, q = c3_graph(c3)
     lab, N, st = L.lcc_cluster(ctx, g_d, p, q, dparams())
     labh = lab.cpu().numpy()
     assert labh.min() == 0 and labh.max() == st["clusters"] - 1
+    progress("oracle: objective of the labels")
     assert O.objective(g_o, p, q, labh) == N
+    if os.environ.get("LCC_FULL_ORACLE") == "1":
+        prev = O.use_openmp(True)
+        try:
+            progress("oracle: full clustering")
+            lo, No, so = O.cluster(g_o, p, q, oparams())
+        finally:
+            O.use_library(prev)
+        assert np.array_equal(lo, labh) and No == N
+        for key in ("levels", "top_moved", "n_level", "arcs_level", "iters_coarsen", "iters_refine",
+                    "moves_total", "arcs_scanned_total", "clusters"):
+            assert so[key] == st[key], (key, so[key], st[key])
+    c3.clear()
+    torch.cuda.empty_cache()

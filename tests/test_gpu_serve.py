@@ -1,12 +1,14 @@
 """Serving loop: requests of mixed kinds arrive as a seeded Poisson stream and
 are served by continuous batching; every request's labels and objective must
-equal the same request run alone."""
+equal the same request run alone, and the CPU oracle's clustering of it."""
 import numpy as np
 import pytest
 import torch
 
+import oracle as O
 from paper_2108_01731_amd import lcc as L
 from paper_2108_01731_amd import serve as V
+from tests import helpers as H
 
 pytestmark = pytest.mark.gpu
 
@@ -24,6 +26,14 @@ def alone(tr):
         lab, N, st = L.lcc_cluster(ctx, L.DeviceGraph.from_host(r.graph, "cuda"), r.p, r.q, L.Params())
         out[r.rid] = (lab.cpu().numpy(), N, st["clusters"])
     ctx.close()
+    return out
+
+
+def oracle_ref(tr):
+    out = {}
+    for r in tr:
+        lab, N, st = O.cluster(H.to_oracle(r.graph), r.p, r.q, O.Params())
+        out[r.rid] = (lab, N, st["clusters"])
     return out
 
 
@@ -45,6 +55,8 @@ def test_served_results_equal_each_request_alone(trace):
     finally:
         srv.close()
     check(st, ref)
+    # and every served request equals the oracle's clustering of it
+    check(st, oracle_ref(trace))
     # requests were batched: fewer batches than requests
     assert st.batches < len(trace)
     assert max(d.batch_jobs for d in st.done) > 1

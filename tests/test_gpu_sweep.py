@@ -56,7 +56,7 @@ def knn():
     return G.knn_gaussian(2500, 25, 16, 10, 0.4, seed=7).numpy()
 
 
-CFGS = [dict(), dict(S=2, refine=0), dict(S=8, frontier=0, num_iter=20), dict(allow_isolate=0),
+CFGS = [dict(), dict(S=2, refine=0), dict(S=8, frontier=0, num_iter=20), dict(frontier=2), dict(allow_isolate=0),
         dict(max_levels=2), dict(S=1, num_iter=6), dict(num_iter=1)]
 
 
@@ -113,3 +113,23 @@ def test_sweep_edge_cases(ctx, knn):
     with pytest.raises(L.LccError) as e:
         L.lcc_sweep(ctx, d, [(1, 2), (3, 4), (2**62, 1)], L.Params())
     assert e.value.code == L.LCC_ERR_OVERFLOW and "lambda 2" in str(e.value)
+
+
+def test_config_sweep_ends_equal_the_oracle(ctx):
+    """The 16-value sweep on the 1M-point cosine kNN graph at its full shape
+    (1000-center 64-d Gaussian mixture, k = 50, Q1.15 weights), in the one
+    lcc_sweep call the benchmark times: the two ends of the lambda grid equal
+    the oracle's clustering (its OpenMP build) of the graph at that lambda."""
+    h = G.knn_gaussian(1_000_000, 1000, 64, 50, 1.0, seed=1, device="cuda")
+    lams = knn_lambdas(16)
+    lab, jobs, _ = L.lcc_sweep(ctx, dev(h), lams, L.Params())
+    lab = lab.cpu().numpy()
+    g_o = H.to_oracle(h)
+    prev = O.use_openmp(True)
+    try:
+        for j in (0, len(lams) - 1):
+            lo, No, so = O.cluster(g_o, *lams[j], O.Params())
+            assert np.array_equal(lab[j], lo), f"resolution {j} differs from the oracle"
+            assert jobs[j]["N"] == No and jobs[j]["clusters"] == so["clusters"], j
+    finally:
+        O.use_library(prev)

@@ -1,0 +1,112 @@
+"""Tuning fields never change a result.  Graph replay (a repeated
+small-level chunk of iterations runs as a cached HIP graph from its second
+occurrence) gives the results of launching one by one, call after call.
+Every combination of queue_ahead
+(iterations queued on the device between counter reads: iterations past the
+end of a call must change nothing), small_level (which levels take the
+single-block partition and iteration-end path) and low_merge (when the
+low-degree bins share one launch) gives labels and objective numerators
+identical to the defaults and to the oracle, under each frontier rule, on
+graphs that take every path (small levels, degree bins, hub rows, signed
+weights); so does the autotuner's choice, which checks every setting it
+tries."""
+import itertools
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2108_01731_amd import autotune as T
+from paper_2108_01731_amd import graphgen as G
+from paper_2108_01731_amd import lcc as L
+from tests import helpers as H
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return L.context(0)
+
+
+def cases():
+    cl = G.chung_lu_planted(60000, 900000, 2.1, 0.3, seed=8)
+    return [
+        ("sbm_c1", G.c1_sbm(1), 1, 100),
+        ("chung_lu", cl, 1, int(cl.arcs)),
+        ("hubs", H.hub_graph(n=40000, m=60000, hubs=(16000, 25000, 31000, 14500), seed=21), 1, 60),
+        ("signed", G.random_signed(5000, 30000, 3, wmin=-4, wmax=6, kmax=3), 1, 9),
+    ]
+
+
+@pytest.mark.parametrize("idx", range(4))
+@pytest.mark.parametrize("frontier", [0, 1, 2])
+def test_every_tuning_combination_gives_the_same_result(ctx, idx, frontier):
+    name, h, p, q = cases()[idx]
+    g = L.DeviceGraph.from_host(h, "cuda")
+    lo, No, _ = O.cluster(H.to_oracle(h), p, q, O.Params(frontier=frontier))
+    ref, Nref, _ = L.lcc_cluster(ctx, g, p, q, L.Params(frontier=frontier))
+    assert np.array_equal(ref.cpu().numpy(), lo) and Nref == No
+    for qa, sl, lm in itertools.product([1, 3, 10], [0, 256, 8192], [1, 0, 1 << 20]):
+        lab, N, _ = L.lcc_cluster(ctx, g, p, q, L.Params(frontier=frontier, queue_ahead=qa, small_level=sl,
+                                                         low_merge=lm))
+        assert torch.equal(lab, ref) and N == Nref, (name, frontier, qa, sl, lm)
+
+
+@pytest.mark.parametrize("idx", range(4))
+def test_graph_replay_equals_single_launches(ctx, idx):
+    name, h, p, q = cases()[idx]
+    g = L.DeviceGraph.from_host(h, "cuda")
+    ref, Nref, sref = L.lcc_cluster(ctx, g, p, q, L.Params(no_graph_replay=1))
+    for rep in range(3):  # the second and third calls replay cached graphs
+        for fr in (1, 2):
+            lab, N, st = L.lcc_cluster(ctx, g, p, q, L.Params(frontier=fr))
+            if fr == 1:
+                assert torch.equal(lab, ref) and N == Nref, (name, rep)
+                assert st["iters_coarsen"] == sref["iters_coarsen"], (name, rep)
+    # a batch (small levels of many jobs) twice
+    graphs = [h, G.c1_sbm(5), G.random_signed(700, 3000, 9, wmin=-2, wmax=5, kmax=2)]
+    lams = [(p, q), (1, 100), (1, 7)]
+    P, start = G.pack([G.HostGraph(x.numpy().off, x.numpy().col, x.numpy().k, None, None, None) for x in graphs])
+    d = L.DeviceGraph.from_host(P, "cuda")
+    a, ja, _ = L.lcc_cluster_batch(ctx, d, start, lams, L.Params(no_graph_replay=1))
+    for _ in range(2):
+        b, jb, _ = L.lcc_cluster_batch(ctx, d, start, lams, L.Params())
+        assert torch.equal(a, b) and [j["N"] for j in ja] == [j["N"] for j in jb]
+
+
+def test_batch_tuning_combinations(ctx):
+    graphs, lams = [], []
+    rng = np.random.default_rng(6)
+    for i in range(40):
+        n = int(rng.integers(50, 3000))
+        graphs.append(G.sbm_blocks(n, 120, float(rng.uniform(6, 20)), 0.2, seed=600 + i))
+        lams.append((int(rng.integers(1, 501)), 1000))
+    P, start = G.pack(graphs)
+    d = L.DeviceGraph.from_host(P, "cuda")
+    ref, jr, _ = L.lcc_cluster_batch(ctx, d, start, lams, L.Params())
+    for qa, sl, lm in [(1, 0, 0), (10, 256, 1), (3, 8192, 1 << 20)]:
+        lab, jb, _ = L.lcc_cluster_batch(ctx, d, start, lams, L.Params(queue_ahead=qa, small_level=sl, low_merge=lm))
+        assert torch.equal(lab, ref) and [j["N"] for j in jb] == [j["N"] for j in jr]
+
+
+def test_autotuner_choice_is_result_invariant(ctx):
+    name, h, p, q = cases()[1]
+    g = L.DeviceGraph.from_host(h, "cuda")
+    run = T.cluster_runner(ctx, g, p, q)
+    best, table = T.tune(run, reps=1, budget_s=60)
+    assert len(table) >= 2
+    lab, N, _ = L.lcc_cluster(ctx, g, p, q, best)
+    ref, Nref, _ = L.lcc_cluster(ctx, g, p, q, L.Params())
+    assert torch.equal(lab, ref) and N == Nref
+
+
+def test_invalid_tuning_values_are_rejected(ctx):
+    g = L.DeviceGraph.from_host(G.c1_sbm(1), "cuda")
+    for bad in (dict(queue_ahead=-1), dict(small_level=L.LCC_SMALL_LEVEL_MAX + 1), dict(small_level=-2),
+                dict(low_merge=-1)):
+        with pytest.raises(L.LccError) as e:
+            L.lcc_cluster(ctx, g, 1, 100, L.Params(**bad))
+        assert e.value.code == L.LCC_ERR_INVALID_ARG
