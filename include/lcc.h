@@ -308,6 +308,25 @@ lcc_status lcc_graph_owned_free(lcc_ctx *ctx, lcc_graph_owned *h);
 lcc_status lcc_objective(lcc_ctx *ctx, const lcc_graph *g, lcc_lambda lam, const int32_t *C,
                          lcc_objective_out *out, void *stream);
 
+/* Largest graph (vertices) that lcc_objective_noalloc accepts. */
+#define LCC_NOALLOC_MAX_N 1048576
+
+/* lcc_objective for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, checks, errors and result as lcc_objective, for graphs of
+ * at most LCC_NOALLOC_MAX_N vertices; it calls no hipMalloc, hipFree or other
+ * allocating routine.  Its scratch (per-cluster int64 sums for
+ * LCC_NOALLOC_MAX_N ids plus block partials, 16.9 MB) is one static device
+ * array of the library, which every device the library runs on holds until
+ * the process ends; lcc_ctx_create looks up its address on the context's
+ * device.  All calls on one device share that array, so calls that overlap
+ * on one device race: the caller serializes them (one stream, or a lock).
+ * Like lcc_objective it reads a few values back and synchronizes the stream.
+ * Errors: as lcc_objective, plus INVALID_ARG for n > LCC_NOALLOC_MAX_N
+ * (raised before any launch). */
+lcc_status lcc_objective_noalloc(lcc_ctx *ctx, const lcc_graph *g, lcc_lambda lam, const int32_t *C,
+                                 lcc_objective_out *out, void *stream);
+
 /* Parallel-CC (paper Algorithm 1, bottom, with Sec. 3.2.3 refinement):
  * Best-Moves from singletons at level 0; while it moved anything and fewer
  * than max_levels graphs exist, compress and repeat on the contracted graph;

@@ -439,6 +439,7 @@ lcc_status lcc_ctx_create(int32_t device, const lcc_allocator *alloc, lcc_ctx **
     ctx->c.num_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
     ctx->c.lds_per_block = prop.sharedMemPerBlock > 0 ? prop.sharedMemPerBlock : 65536;
     if (alloc) ctx->c.alloc = *alloc;
+    noalloc_setup(device);
     *out = ctx.release();
   });
 }
@@ -520,6 +521,25 @@ lcc_status lcc_objective(lcc_ctx *ctx, const lcc_graph *g, lcc_lambda lam, const
     check_dev(c, C, (size_t)g->n * sizeof(int32_t), "C");
     (void)checked_summary(c, *g, C, true, lam.p, lam.q);
     i128 N = objective_num(c, *g, lam.p, lam.q, C);
+    c.sync();
+    fill_objective(N, lam.q, out);
+  });
+}
+
+lcc_status lcc_objective_noalloc(lcc_ctx *ctx, const lcc_graph *g, lcc_lambda lam, const int32_t *C,
+                                 lcc_objective_out *out, void *stream) {
+  return guarded([&] {
+    if (!ctx) fail(LCC_ERR_INVALID_ARG, "ctx is NULL");
+    if (!out) fail(LCC_ERR_INVALID_ARG, "out is NULL");
+    Ctx &c = ctx->c;
+    check_lambda(lam);
+    begin(c, stream, nullptr);
+    check_graph_args(c, g);
+    if (g->n > LCC_NOALLOC_MAX_N)
+      fail(LCC_ERR_INVALID_ARG, "n = " + std::to_string(g->n) + " exceeds LCC_NOALLOC_MAX_N = " +
+                                    std::to_string((int64_t)LCC_NOALLOC_MAX_N));
+    check_dev(c, C, (size_t)g->n * sizeof(int32_t), "C");
+    i128 N = objective_num_noalloc(c, *g, lam.p, lam.q, C);
     c.sync();
     fill_objective(N, lam.q, out);
   });

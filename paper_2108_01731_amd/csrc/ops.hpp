@@ -128,6 +128,12 @@ void launch_objective_partials(hipStream_t stream, const lcc_graph &g, const int
                                const int64_t *KK, int64_t nb, u128 *part);
 i128 objective_from_sums(int64_t p, int64_t q, i128 pairs2, i128 win2, i128 ssum);
 
+// The allocation-free objective (lcc_objective_noalloc): every scratch array
+// lives in a static device array of the library; noalloc_setup records its
+// address on the current device (called once per device by lcc_ctx_create).
+void noalloc_setup(int device);
+i128 objective_num_noalloc(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const int32_t *C);
+
 // labels[v] = rank of C[v]'s cluster in the order of smallest members.
 // Returns the number of clusters.
 int64_t canonical_labels(Ctx &c, int64_t n, const int32_t *C, int32_t *labels);

@@ -22,6 +22,7 @@ LCC_WT_UNIT, LCC_WT_I16, LCC_WT_I32, LCC_WT_I64 = range(4)
 LCC_FRONTIER_ALL, LCC_FRONTIER_NBR, LCC_FRONTIER_CLUSTERS = 0, 1, 2
 LCC_TERM_NO_MOVES, LCC_TERM_NUM_ITER, LCC_TERM_STOPPED = 0, 1, 2
 LCC_HUB_LIMIT_MAX = 8601  # default and largest Params.hub_limit
+LCC_NOALLOC_MAX_N = 1048576  # largest graph lcc_objective_noalloc accepts
 LCC_SMALL_LEVEL_MAX = 8192  # largest Params.small_level
 MAX_ITER_STATS = 64
 MAX_LEVELS = 64
@@ -112,7 +113,7 @@ class _KernelStat(ctypes.Structure):
 
 EXPORTS = (
     "lcc_params_default", "lcc_last_error", "lcc_ctx_create", "lcc_ctx_destroy", "lcc_best_move", "lcc_compress",
-    "lcc_graph_owned_view", "lcc_graph_owned_free", "lcc_objective", "lcc_cluster",
+    "lcc_graph_owned_view", "lcc_graph_owned_free", "lcc_objective", "lcc_objective_noalloc", "lcc_cluster",
     "lcc_cluster_batch", "lcc_sweep", "lcc_ctx_kernel_stats", "lcc_ctx_reset_kernel_stats",
 )
 
@@ -147,6 +148,8 @@ def load_library(path: str = LIB_PATH):
     lib.lcc_graph_owned_free.argtypes = [P, P]
     lib.lcc_objective.restype = st
     lib.lcc_objective.argtypes = [P, gp, _Lambda, P, ctypes.POINTER(_Objective), P]
+    lib.lcc_objective_noalloc.restype = st
+    lib.lcc_objective_noalloc.argtypes = [P, gp, _Lambda, P, ctypes.POINTER(_Objective), P]
     lib.lcc_cluster.restype = st
     lib.lcc_cluster.argtypes = [P, gp, _Lambda, ctypes.POINTER(_Params), P, ctypes.POINTER(_Objective),
                                 ctypes.POINTER(_ClusterStats), P]
@@ -417,6 +420,17 @@ def lcc_objective(ctx: Context, g: DeviceGraph, p: int, q: int, C: torch.Tensor,
     cg = g._c()
     _check(_lib.lcc_objective(ctx._h, ctypes.byref(cg), _lam(p, q), C.data_ptr() if C.numel() else None,
                               ctypes.byref(o), _stream_ptr(stream)))
+    return _num(o)
+
+
+def lcc_objective_noalloc(ctx: Context, g: DeviceGraph, p: int, q: int, C: torch.Tensor, stream=None) -> int:
+    """As lcc_objective, through the entry point that allocates no device
+    memory (graphs of at most LCC_NOALLOC_MAX_N vertices)."""
+    _check_ids(C)
+    o = _Objective()
+    cg = g._c()
+    _check(_lib.lcc_objective_noalloc(ctx._h, ctypes.byref(cg), _lam(p, q), C.data_ptr() if C.numel() else None,
+                                      ctypes.byref(o), _stream_ptr(stream)))
     return _num(o)
 
 
