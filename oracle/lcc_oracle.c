@@ -54,6 +54,9 @@
  *     left): the union of N(u) over every u that, at the end of the
  *     iteration, belongs to a cluster some vertex moved out of during the
  *     iteration (moves in any sub-round; a cluster left empty adds nothing).
+ *   - Parallel-CC recurses when the coarsening Best-Moves call changed the
+ *     partition: a call that only exchanged the ids of singletons (every
+ *     vertex still alone) counts as a call without moves.
  *   - Compress numbers clusters by the rank of their id among non-empty ids;
  *     self-loops of the contracted graph are kept out of the adjacency, in a
  *     per-vertex self weight s, and kk (sum of k^2 over original members) is
@@ -803,6 +806,17 @@ int orc_canonical_labels(int64_t n, const int32_t *C, int32_t *labels) {
  * not reached) compress and recurse; on the way back flatten each level's
  * clustering through its map and, with refinement, run Best-Moves again on
  * that level.  Writes canonical labels and the objective numerator. */
+/* Number of distinct cluster ids in C (ids in [0, n)). */
+static int64_t count_clusters(const int32_t *C, int64_t n) {
+  uint8_t *seen = (uint8_t *)calloc((size_t)(n ? n : 1), 1);
+  if (!seen) return -1;
+  int64_t k = 0;
+  for (int64_t v = 0; v < n; v++)
+    if (!seen[C[v]]) { seen[C[v]] = 1; k++; }
+  free(seen);
+  return k;
+}
+
 int orc_cluster(const orc_graph *g0, int64_t p, int64_t q, const orc_params *prm, int32_t *labels,
                 int64_t *num_hi, uint64_t *num_lo, orc_cluster_stats *cs) {
   int rc = orc_precheck(g0, p, q);
@@ -835,9 +849,19 @@ int orc_cluster(const orc_graph *g0, int64_t p, int64_t q, const orc_params *prm
     cs->iters_coarsen[l] = st.iterations;
     cs->moves_total += st.moves;
     cs->arcs_scanned_total += st.arcs_scanned;
-    if (!st.moved_any || l + 1 == prm->max_levels) {
+    /* Algorithm 1 recurses only when Best-Moves made a move.  This call
+     * started from singletons; if every vertex ends alone in its cluster, the
+     * moves only exchanged the ids of singletons (the synchronous sub-rounds
+     * allow such swaps, the paper's immediate moves do not) and the partition
+     * is the one the call started from: no move changed it, and its
+     * contraction would be the same graph renumbered.  The recursion ends
+     * there as it does after a call without moves. */
+    int64_t ncl = st.moved_any ? count_clusters(Cl[l], n) : n;
+    if (ncl < 0) { rc = ORC_NOMEM; goto out; }
+    int changed = st.moved_any && ncl < n;
+    if (!changed || l + 1 == prm->max_levels) {
       top = l;
-      cs->top_moved = st.moved_any;
+      cs->top_moved = changed;
       break;
     }
     map[l] = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n ? n : 1));

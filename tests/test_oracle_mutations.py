@@ -56,6 +56,7 @@ MUTATIONS = {
         "        arcs += g->off[U[i] + 1] - g->off[U[i]];\n"
         "        if (D[i] != C[U[i]]) { orc_frontier_nbr(g, &U[i], 1, next);"
         " moved_it += apply_moves(g, C, K, cnt, &U[i], 1, &D[i]); D[i] = C[U[i]]; }\n"),
+    "recursion_on_id_swaps": ("    int changed = st.moved_any && ncl < n;", "    int changed = st.moved_any;"),
     "flatten_drops_coarse_clustering": ("    for (int64_t v = 0; v < G[l].n; v++) Cl[l][v] = Cl[l + 1][map[l][v]];",
                                         "    for (int64_t v = 0; v < G[l].n; v++) Cl[l][v] = map[l][v];"),
 }
@@ -80,7 +81,8 @@ def _pins():
                P.test_isolation_takes_smallest_empty_ids, P.test_P3_refinement_ends_in_single_move_local_optimum,
                P.test_P5_two_level_compress_invariant, P.test_canonical_labels_order_by_min_member,
                P.test_clusters_frontier_reconsiders_neighbors_of_the_left_cluster,
-               P.test_clusters_frontier_second_iteration_matches_definition]
+               P.test_clusters_frontier_second_iteration_matches_definition,
+               P.test_recursion_ends_when_only_singleton_ids_were_exchanged]
     for s in range(2):
         checks.append(lambda s=s: P.test_P4_decisions_are_best_modularity_moves(s))
     return checks

@@ -481,6 +481,22 @@ def test_P9_symmetric_pair_swaps_or_merges():
     assert st["term"] == O.TERM_NUM_ITER and st["moves"] == 10 and list(C) == [1, 0]
 
 
+def test_recursion_ends_when_only_singleton_ids_were_exchanged():
+    """Algorithm 1 (Parallel-CC) recurses only after a Best-Moves call that
+    made a move.  Two singletons joined by a positive edge and scheduled
+    together (S = 1) exchange ids in every iteration (P9): the partition
+    never changes, so the recursion ends at level 0 with both vertices alone,
+    and the stats say the top level stopped without a change.  Two triangles
+    joined by one edge do contract (a change), so the recursion goes on."""
+    g = _graph_from_edges(2, [(0, 1, 1)])
+    lab, N, st = O.cluster(g, 0, 1, O.Params(S=1))
+    assert st["levels"] == 1 and st["top_moved"] == 0 and list(lab) == [0, 1]
+    assert st["iters_coarsen"][0] == 10 and st["moves_total"] == 20
+    g2 = _graph_from_edges(6, [(0, 1, 1), (1, 2, 1), (0, 2, 1), (3, 4, 1), (4, 5, 1), (3, 5, 1), (2, 3, 1)])
+    lab2, N2, st2 = O.cluster(g2, 1, 10, O.Params(S=2))
+    assert st2["levels"] >= 2 and st2["n_level"][1] < 6
+
+
 # -------------------------------------------------------- schedule details
 
 
