@@ -589,9 +589,13 @@ lcc_status lcc_cluster(lcc_ctx *ctx, const lcc_graph *g, lcc_lambda lam, const l
       cs.iters_coarsen[l] = st.iterations;
       cs.moves_total += st.moves;
       cs.arcs_scanned_total += st.arcs_scanned;
-      if (!st.moved_any || l + 1 == prm->max_levels) {
+      // the recursion goes on only if the call changed the partition: moves
+      // that merely exchanged the ids of singletons (every vertex still
+      // alone) count as no move
+      const bool changed = st.moved_any && job_cluster_counts(c, n, C, 1, nullptr)[0] < n;
+      if (!changed || l + 1 == prm->max_levels) {
         top = l;
-        cs.top_moved = st.moved_any;
+        cs.top_moved = changed;
         break;
       }
       maps.push_back(c.buf<int32_t>("lv.map" + std::to_string(l), (size_t)(n > 0 ? n : 1)));
@@ -682,6 +686,17 @@ static void batch_levels(Ctx &c, const lcc_graph *g, int64_t J, const std::vecto
     ms_bm += std::chrono::duration<double, std::milli>(clk::now() - a).count();
     bs.moves_total += st.moves;
     bs.arcs_scanned_total += st.arcs_scanned;
+    // a job goes on only if its call changed its partition (fewer clusters
+    // than vertices; ids exchanged between singletons count as no move)
+    bool any_moved = false;
+    for (int64_t j = 0; j < J; j++) any_moved = any_moved || (run[(size_t)j] && moved[(size_t)j]);
+    if (any_moved) {
+      const std::vector<int64_t> ncl = job_cluster_counts(c, n, C, J, jbasel[l]);
+      std::vector<int64_t> jb((size_t)(J + 1));
+      d2h(c, jb.data(), jbasel[l], jb.size() * sizeof(int64_t));
+      for (int64_t j = 0; j < J; j++)
+        if (moved[(size_t)j] && ncl[(size_t)j] >= jb[(size_t)(j + 1)] - jb[(size_t)j]) moved[(size_t)j] = 0;
+    }
     bool any = false;
     for (int64_t j = 0; j < J; j++) {
       cont[(size_t)j] = 0;

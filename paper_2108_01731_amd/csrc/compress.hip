@@ -221,6 +221,47 @@ __global__ void k_map(const int32_t *__restrict__ C, const int32_t *__restrict__
     map[v] = kept(jid, jcont, v) ? rank[C[v]] : -1;
 }
 
+// Distinct cluster ids of a clustering (the recursion of Parallel-CC goes on
+// only if a coarsening call changed the partition, i.e. left fewer clusters
+// than vertices).
+__global__ void k_flag_ids(const int32_t *__restrict__ C, int64_t n, uint8_t *__restrict__ present) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+    present[C[v]] = 1;
+}
+
+// out[j] = rank[jbase[j]], out[J + 1 + j] = jbase[j] for j <= J.
+__global__ void k_rank_at(const int32_t *__restrict__ rank, const int64_t *__restrict__ jbase, int64_t J,
+                          int64_t *__restrict__ out) {
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j <= J; j += (int64_t)gridDim.x * blockDim.x) {
+    out[j] = rank[jbase[j]];
+    out[J + 1 + j] = jbase[j];
+  }
+}
+
+std::vector<int64_t> job_cluster_counts(Ctx &c, int64_t n, const int32_t *C, int64_t J, const int64_t *jbase) {
+  std::vector<int64_t> counts((size_t)J, 0);
+  if (n <= 0 || J <= 0) return counts;
+  uint8_t *present = c.buf<uint8_t>("cc.present", (size_t)n);
+  int32_t *rank = c.buf<int32_t>("cc.rank", (size_t)n + 1);
+  int64_t *out = c.buf<int64_t>("cc.out", (size_t)(2 * (J + 1)));
+  HIPCHECK(hipMemsetAsync(present, 0, (size_t)n, c.stream));
+  hipLaunchKernelGGL(k_flag_ids, dim3(grid_for(n)), dim3(256), 0, c.stream, C, n, present);
+  LAUNCHCHECK();
+  scan<uint8_t, int32_t>(c, present, rank, n, false, rank + n);
+  if (jbase) {
+    hipLaunchKernelGGL(k_rank_at, dim3(grid_for(J + 1)), dim3(256), 0, c.stream, (const int32_t *)rank, jbase, J, out);
+    LAUNCHCHECK();
+    std::vector<int64_t> h((size_t)(2 * (J + 1)));
+    d2h(c, h.data(), out, h.size() * sizeof(int64_t));
+    for (int64_t j = 0; j < J; j++) counts[(size_t)j] = h[(size_t)(j + 1)] - h[(size_t)j];
+  } else {
+    int32_t t = 0;
+    d2h(c, &t, rank + n, sizeof(t));
+    counts[0] = t;
+  }
+  return counts;
+}
+
 // Sort keys for the per-cluster sums: dropped vertices go to the extra key n2.
 __global__ void k_keys_with_sentinel(const int32_t *__restrict__ map, int64_t n, int32_t n2, int32_t *__restrict__ key) {
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)

@@ -141,6 +141,11 @@ int64_t canonical_labels(Ctx &c, int64_t n, const int32_t *C, int32_t *labels);
 // Per-cluster sums of k and kk (kk = k^2 when absent) for ids in [0, n).
 void cluster_sums_k_kk(Ctx &c, const lcc_graph &g, const int32_t *C, int64_t *K, int64_t *KK);
 
+// Number of distinct cluster ids of C (ids in [0, n)): per job when jbase
+// (device, J + 1 job bases, a job's ids inside its own range) is given, else
+// one count (J = 1).
+std::vector<int64_t> job_cluster_counts(Ctx &c, int64_t n, const int32_t *C, int64_t J, const int64_t *jbase);
+
 // Largest row length of a CSR offset array (and, min_out, the smallest).
 int64_t max_degree(Ctx &c, const int64_t *off, int64_t n, int64_t *min_out = nullptr);
 

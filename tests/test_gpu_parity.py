@@ -204,12 +204,15 @@ def test_cluster_parity(ctx, idx, cfg):
 
 
 def test_cluster_parity_synchronous_pathology(ctx):
-    """S = 1 (the paper's synchronous setting) oscillates; the level cap ends it."""
+    """S = 1 (the paper's synchronous setting) oscillates: at the fourth level
+    every vertex ends alone (ids exchanged in pairs), so the recursion ends
+    there, as the oracle's does; with a cap of two levels the cap ends it."""
     h = G.c1_sbm(1)
-    cfg = dict(S=1, max_levels=6)
-    lo, No, so = O.cluster(H.to_oracle(h), 1, 100, oparams(**cfg))
-    ld, Nd, sd = L.lcc_cluster(ctx, dev(h), 1, 100, dparams(**cfg))
-    assert np.array_equal(lo, ld.cpu().numpy()) and No == Nd and so["levels"] == sd["levels"] == 6
+    for cfg, levels, top_moved in ((dict(S=1), 4, 0), (dict(S=1, max_levels=2), 2, 1)):
+        lo, No, so = O.cluster(H.to_oracle(h), 1, 100, oparams(**cfg))
+        ld, Nd, sd = L.lcc_cluster(ctx, dev(h), 1, 100, dparams(**cfg))
+        assert np.array_equal(lo, ld.cpu().numpy()) and No == Nd
+        assert so["levels"] == sd["levels"] == levels and so["top_moved"] == sd["top_moved"] == top_moved
 
 
 def test_determinism_and_row_order_invariance(ctx):
