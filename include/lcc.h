@@ -156,6 +156,11 @@ typedef struct lcc_params {
                           and iteration-end kernels (larger values are rejected) */
   int32_t low_merge;   /* 0 = default (32768); k > 0: a level with at most k rows of degree < 256 takes
                           them in one launch instead of one per degree bin */
+  int32_t hub_row_limit; /* rows beyond the LDS tables are first aggregated one block per row, in one
+                            pass, when they meet at most this many distinct clusters (the others take the
+                            hash partitions): 0 = automatic (three quarters of the block's table, the
+                            largest value used; larger values are lowered to it), -1 = never (every such
+                            row takes the partitions); values below -1 are rejected */
   /* mode (changes results) */
   int32_t async_moves; /* 1 = the paper's asynchronous setting (Sec. 3.2.1): a vertex's move is applied
                           the moment it is decided, so the other decisions of its sub-round see it or

@@ -109,6 +109,7 @@ struct AggArgs {
   int64_t *iso_ctr;   // isolations of the sub-round
   int32_t rb0, rb1;
   int32_t hub_limit;  // distinct clusters a hub partition may hold (see k_hp_part)
+  int32_t hub_row_limit;  // one-pass hub rows: 0 automatic, -1 never, k > 0 at most k clusters (k_hub_row)
 };
 
 // The launch's vertex list and count (host-given, or read from the bucket
@@ -1134,7 +1135,8 @@ __global__ __launch_bounds__(B7_NT) void k_b7_segscore(AggArgs a, const int64_t 
 
 // One block per row: combines the row's segments, decides, marks the frontier.
 __global__ __launch_bounds__(B7_NT) void k_b7_final(AggArgs a, const int64_t *__restrict__ sstart,
-                                                    const SegBest *__restrict__ part) {
+                                                    const SegBest *__restrict__ part,
+                                                    const uint8_t *__restrict__ done) {
   __shared__ int32_t sh_d;
   const int t = threadIdx.x;
   const int32_t *list;
@@ -1142,6 +1144,7 @@ __global__ __launch_bounds__(B7_NT) void k_b7_final(AggArgs a, const int64_t *__
   work_of(a, list, n7);
   int64_t movers = 0, marcs = 0, cands = 0, niso = 0;
   for (int64_t i = blockIdx.x; i < n7; i += gridDim.x) {
+    if (done && done[i]) continue;  // decided by k_hub_row (block-uniform)
     const int32_t v = list[i];
     const int64_t beg = a.off[v], end = a.off[v + 1];
     const int32_t c = a.C[v];
@@ -1220,7 +1223,7 @@ __device__ __forceinline__ uint32_t part_of(int32_t X, uint32_t P) {
 // tot = {chunks, arcs, partitions, n7}.
 __global__ __launch_bounds__(B7L_NT) void k_hp_layout(AggArgs a, int64_t *__restrict__ cstart,
                                                       int64_t *__restrict__ xoff, int64_t *__restrict__ pstart,
-                                                      int64_t *__restrict__ tot) {
+                                                      int64_t *__restrict__ tot, const uint8_t *__restrict__ done) {
   const int32_t *list;
   int64_t n7;
   work_of(a, list, n7);
@@ -1228,7 +1231,7 @@ __global__ __launch_bounds__(B7L_NT) void k_hp_layout(AggArgs a, int64_t *__rest
   for (int64_t i0 = 0; i0 < n7; i0 += B7L_NT) {
     const int64_t i = i0 + threadIdx.x;
     int64_t nc = 0, d = 0, np = 0;
-    if (i < n7) {
+    if (i < n7 && !done[i]) {  // rows decided in one pass take no chunks or partitions
       const int32_t v = list[i];
       d = a.off[v + 1] - a.off[v];
       nc = cdiv(d, B7_CHUNK);
@@ -1530,6 +1533,155 @@ __global__ __launch_bounds__(B7_NT) void k_hps_scatter(AggArgs a, const int64_t 
 }
 
 size_t hp_lds_bytes(bool a32) { return (size_t)HP_SLOTS * (sizeof(int32_t) + (a32 ? 4 : 8)); }
+
+// Hub rows in one pass.  A row's degree bounds its distinct clusters, but
+// once clusters have formed a hub row meets far fewer clusters than it has
+// arcs (on a contracted power-law graph, a sixth or less after the first
+// iteration), so most hub rows fit one block's LDS table after all.  One
+// block per row streams the row once into a table of H slots whose claims
+// stop at `limit` keys: a row that stays within the limit is scored and
+// decided here exactly as the per-row kernels do (done[i] = 1); a row that
+// meets more clusters stops reading at once and is left to the hash
+// partitions (done[i] = 0), which k_hp_layout and k_b7_final then take alone.
+__device__ __forceinline__ bool lds_insert_upto(int32_t *keys, int32_t *vals32, int64_t *vals64, bool a32,
+                                                uint32_t H, int32_t X, int64_t w, int32_t *nclaim,
+                                                int32_t stop) {
+  uint32_t h = slot_of(X, H);
+  while (true) {
+    int32_t cur = keys[h];
+    if (cur == -1) {
+      if (atomicAdd(nclaim, 1) >= stop) return false;
+      cur = atomicCAS(&keys[h], -1, X);
+      if (cur == -1) {
+        cur = X;
+      } else {
+        atomicSub(nclaim, 1);  // another key took the slot first
+      }
+    }
+    if (cur == X) {
+      if (w) {
+        if (a32)
+          atomicAdd(&vals32[h], (int32_t)w);
+        else
+          atomicAdd(reinterpret_cast<unsigned long long *>(&vals64[h]), (unsigned long long)w);
+      }
+      return true;
+    }
+    h = (h + 1 == H) ? 0 : h + 1;
+  }
+}
+
+constexpr int HR_NT = 1024;
+
+template <int WK, bool A32>
+__global__ __launch_bounds__(HR_NT) void k_hub_row(AggArgs a, uint8_t *__restrict__ done, int32_t limit) {
+  using Acc = typename std::conditional<A32, int32_t, int64_t>::type;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const uint32_t H = (uint32_t)a.hcap;
+  int32_t *keys = reinterpret_cast<int32_t *>(smem);
+  Acc *vals = reinterpret_cast<Acc *>(smem + ((a.hcap * 4 + 15) & ~15ll));
+  __shared__ int32_t nclaim, sh_d;
+  const int t = threadIdx.x;
+  const int32_t *list;
+  int64_t n7;
+  work_of(a, list, n7);
+  // claims stop one block's worth of inserts below the table size, so a
+  // probe always meets an empty slot and every insert ends
+  const int32_t stop = (int32_t)H - HR_NT;
+  int64_t movers = 0, marcs = 0, cands = 0, niso = 0;
+  for (int64_t i = blockIdx.x; i < n7; i += gridDim.x) {
+    const int32_t v = list[i];
+    const int64_t beg = a.off[v], end = a.off[v + 1];
+    const int32_t c = a.C[v];
+    const int64_t kv = a.k[v], Kc = a.K[c];
+    const int32_t cntc = a.cnt[c];
+    for (uint32_t j = t; j < H; j += HR_NT) {
+      keys[j] = -1;
+      vals[j] = 0;
+    }
+    if (t == 0) nclaim = 0;
+    __syncthreads();
+    if (t == 0)
+      lds_insert_upto(keys, reinterpret_cast<int32_t *>(vals), reinterpret_cast<int64_t *>(vals), A32, H, c, 0,
+                      &nclaim, stop);
+    bool ok = true;
+    for (int64_t base = beg + t; base < end && ok; base += 4 * HR_NT) {
+      int32_t u[4], X[4];
+      int64_t w[4];
+#pragma unroll
+      for (int j = 0; j < 4; j++) {
+        const int64_t e = base + j * HR_NT;
+        u[j] = e < end ? a.col[e] : -1;
+        w[j] = e < end ? load_w<WK>(a.wt, e) : 0;
+      }
+#pragma unroll
+      for (int j = 0; j < 4; j++) X[j] = u[j] >= 0 ? a.C[u[j]] : -1;
+#pragma unroll
+      for (int j = 0; j < 4; j++)
+        if (X[j] >= 0)
+          ok = lds_insert_upto(keys, reinterpret_cast<int32_t *>(vals), reinterpret_cast<int64_t *>(vals), A32, H,
+                               X[j], w[j], &nclaim, stop) && ok;
+      // another lane's overflow ends this lane's reading too (a stale read
+      // of the counter only delays that)
+      ok = ok && *(volatile int32_t *)&nclaim <= limit;
+    }
+    __syncthreads();
+    const bool fits = nclaim <= limit;  // block-uniform
+    if (!fits) {
+      if (t == 0) done[i] = 0;
+      __syncthreads();  // the table and nclaim are reused by the next row
+      continue;
+    }
+    int64_t lp, lq;
+    int32_t job;
+    job_lambda(a, v, lp, lq, job);
+    const int64_t pk = lp * kv;
+    int64_t best_s = INT64_MIN, wc = 0;
+    int32_t best_id = ISO_ID;
+    for (uint32_t j = t; j < H; j += HR_NT) {
+      const int32_t X = keys[j];
+      if (X < 0) continue;
+      cands++;
+      const int64_t wx = (int64_t)vals[j];
+      if (X == c) {
+        wc = wx;
+      } else {
+        const int64_t sc = lq * wx - pk * a.K[X];
+        if (better(sc, X, best_s, best_id)) {
+          best_s = sc;
+          best_id = X;
+        }
+      }
+    }
+    block_best<HR_NT>(best_s, best_id, wc);
+    if (t == 0) {
+      const int64_t stay = lq * wc - pk * (Kc - kv);
+      const int32_t d = decide(best_s, best_id, stay, a.allow_iso && cntc >= 2, c);
+      a.D[v] = d;
+      done[i] = 1;
+      sh_d = d;
+      if (d != c) {
+        movers += 1;
+        marcs += end - beg;
+        if (a.left_flag) a.left_flag[c] = 1;
+        if (a.Cw) own_move(a, v, c, d, kv, niso);
+      }
+    }
+    __syncthreads();
+    if (sh_d != c && a.next_flag)
+      for (int64_t e = beg + t; e < end; e += HR_NT) a.next_flag[a.col[e]] = 1;
+    __syncthreads();  // the table, nclaim and sh_d are reused by the next row
+  }
+  if (t == 0 && niso) atomic_add_i64(a.iso_ctr, niso);
+  flush_counters<HR_NT>(a.ctr, movers, cands, marcs);
+}
+
+// Table of the one-pass hub kernel: as many slots as the per-block LDS holds
+// beside its reduction arrays; rows may fill three quarters of it.
+int64_t hub_row_slots(const Ctx &c, bool a32) {
+  const int64_t budget = (int64_t)c.lds_per_block - 4096;
+  return (budget - 16) / (a32 ? 8 : 12);
+}
 
 
 // ------------------------------------------ neighbors-of-clusters frontier
@@ -2277,7 +2429,7 @@ template <int WK, bool PK> void launch_flat_pk(Ctx &c, AggArgs a, int64_t n7_ub,
                      c.stream, a, tot, tstart, sstart, part);
   LAUNCHCHECK();
   hipLaunchKernelGGL(k_b7_final, dim3((unsigned)std::min<int64_t>(n7_ub, (int64_t)c.num_cu * 4)), dim3(B7_NT), 0,
-                     c.stream, a, sstart, part);
+                     c.stream, a, sstart, part, (const uint8_t *)nullptr);
   LAUNCHCHECK();
 }
 
@@ -2294,7 +2446,28 @@ template <int WK> void launch_hub_part(Ctx &c, AggArgs a, int64_t n7_ub, int64_t
   // partitions: at most cdiv(2 (d + 1), HP_LIMIT) <= 2 (d + 1) / HP_LIMIT + 1 per row
   const int64_t parts_ub = 2 * (a7_ub + n7_ub) / HP_LIMIT + n7_ub + 1;
   SegBest *part = c.buf<SegBest>("hp.part", (size_t)parts_ub);
-  hipLaunchKernelGGL(k_hp_layout, dim3(1), dim3(B7L_NT), 0, c.stream, a, cstart, xoff, pstart, tot);
+  // first every row in one pass where its clusters fit one block's table
+  uint8_t *done = c.buf<uint8_t>("hp.done", (size_t)n7_ub);
+  if (a.hub_row_limit < 0) {  // every row takes the partitions
+    HIPCHECK(hipMemsetAsync(done, 0, (size_t)n7_ub, c.stream));
+  } else {
+    AggArgs ah = a;
+    ah.hcap = hub_row_slots(c, a32);
+    int32_t limit = (int32_t)(ah.hcap * 3 / 4);
+    if (a.hub_row_limit > 0 && a.hub_row_limit < limit) limit = a.hub_row_limit;
+    const size_t bytes = wide_lds_bytes(ah.hcap, a32, false);
+    const dim3 gh((unsigned)std::min<int64_t>(n7_ub, (int64_t)1 << 20));
+    if (a32) {
+      allow_lds(c, k_hub_row<WK, true>, bytes);
+      hipLaunchKernelGGL((k_hub_row<WK, true>), gh, dim3(HR_NT), bytes, c.stream, ah, done, limit);
+    } else {
+      allow_lds(c, k_hub_row<WK, false>, bytes);
+      hipLaunchKernelGGL((k_hub_row<WK, false>), gh, dim3(HR_NT), bytes, c.stream, ah, done, limit);
+    }
+    LAUNCHCHECK();
+  }
+  hipLaunchKernelGGL(k_hp_layout, dim3(1), dim3(B7L_NT), 0, c.stream, a, cstart, xoff, pstart, tot,
+                     (const uint8_t *)done);
   LAUNCHCHECK();
   const int64_t chunks = a7_ub / B7_CHUNK + n7_ub;
   const dim3 gc((unsigned)std::max<int64_t>(1, std::min<int64_t>(chunks, (int64_t)c.num_cu * 8)));
@@ -2338,7 +2511,7 @@ template <int WK> void launch_hub_part(Ctx &c, AggArgs a, int64_t n7_ub, int64_t
 #undef LCC_HP_PART
   LAUNCHCHECK();
   hipLaunchKernelGGL(k_b7_final, dim3((unsigned)std::min<int64_t>(n7_ub, (int64_t)c.num_cu * 4)), dim3(B7_NT), 0,
-                     c.stream, a, (const int64_t *)pstart, (const SegBest *)part);
+                     c.stream, a, (const int64_t *)pstart, (const SegBest *)part, (const uint8_t *)done);
   LAUNCHCHECK();
 }
 
@@ -2583,6 +2756,7 @@ void best_moves_run(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_
     a.q = q;
     a.allow_iso = prm.allow_isolate;
     a.hub_limit = prm.hub_limit;
+    a.hub_row_limit = prm.hub_row_limit;
     a.list = blist;
     a.D = D;
     a.next_flag = prm.frontier == LCC_FRONTIER_NBR ? next : nullptr;

@@ -42,7 +42,8 @@ def test_struct_layout_matches_header(tmp_path):
     """sizeof / offsetof of the ABI structs from a C compiler vs ctypes."""
     fields = {
         "lcc_graph": (L._Graph, ["n", "arcs", "off", "col", "wt", "wt_kind", "k", "s", "kk"]),
-        "lcc_params": (L._Params, ["S", "num_iter", "seed", "frontier", "stop_after_subrounds", "validate", "timing"]),
+        "lcc_params": (L._Params, ["S", "num_iter", "seed", "frontier", "stop_after_subrounds", "validate", "timing",
+                                   "hub_limit", "low_merge", "hub_row_limit", "async_moves", "no_graph_replay"]),
         "lcc_bm_stats": (L._BMStats, ["iterations", "moves", "candidates", "active_per_iter", "moves_per_iter"]),
         "lcc_objective_out": (L._Objective, ["num_hi", "num_lo", "den", "value"]),
         "lcc_cluster_stats": (L._ClusterStats, ["levels", "n_level", "iters_refine", "clusters", "ms_total"]),

@@ -250,17 +250,24 @@ def test_hub_rows_with_64_bit_sums(ctx):
         assert np.array_equal(lo, ld.cpu().numpy()) and No == Nd
 
 
+# (hub_limit, hub_row_limit): the default; every hub row through the hash
+# partitions; partitions that overflow (the call is redone with the global
+# tables); one-pass rows up to 64 clusters, the others through partitions
+HUB_PATHS = [(0, 0), (0, -1), (64, -1), (0, 64)]
+
+
 def test_hub_partition_overflow_redoes_the_call(ctx):
-    """Rows beyond the LDS tables are aggregated in hash partitions; a tiny
+    """Rows beyond the LDS tables are aggregated one block per row in one
+    pass when their clusters fit its table, else in hash partitions; a tiny
     hub_limit makes partitions overflow, so the call is redone from its saved
-    clustering with the global tables.  Both ways give the oracle's result."""
+    clustering with the global tables.  Every way gives the oracle's result."""
     graphs = [H.hub_graph(n=40000, m=60000, hubs=(16000, 25000, 31000, 14500), seed=21),
               H.hub_graph(n=40000, m=60000, hubs=(16000, 25000), seed=22, weighted=False)]
     for h in graphs:
         lo, No, _ = O.cluster(H.to_oracle(h), 1, 60, oparams())
-        for limit in [0, 64]:
-            ld, Nd, _ = L.lcc_cluster(ctx, dev(h), 1, 60, dparams(hub_limit=limit))
-            assert np.array_equal(lo, ld.cpu().numpy()) and No == Nd, limit
+        for limit, row_limit in HUB_PATHS:
+            ld, Nd, _ = L.lcc_cluster(ctx, dev(h), 1, 60, dparams(hub_limit=limit, hub_row_limit=row_limit))
+            assert np.array_equal(lo, ld.cpu().numpy()) and No == Nd, (limit, row_limit)
     # a single call from a given clustering, device-driven and stopped inside
     # an iteration (host-driven)
     h = graphs[0]
@@ -268,21 +275,43 @@ def test_hub_partition_overflow_redoes_the_call(ctx):
     C0 = np.random.default_rng(3).integers(0, 200, size=h.n).astype(np.int32)
     for cfg in [dict(S=3), dict(S=3, stop_after_subrounds=5)]:
         Co, so = O.best_move(g_o, 1, 60, oparams(**cfg), C0, 2, 1)
-        for limit in [0, 64]:
+        for limit, row_limit in HUB_PATHS:
             Cd = torch.from_numpy(C0.copy()).cuda()
-            sd = L.lcc_best_move(ctx, g_d, 1, 60, dparams(hub_limit=limit, **cfg), Cd, 2, 1)
+            sd = L.lcc_best_move(ctx, g_d, 1, 60, dparams(hub_limit=limit, hub_row_limit=row_limit, **cfg), Cd, 2, 1)
             assert_same_bm(Co, so, Cd.cpu().numpy(), sd)
+
+
+def test_hub_rows_one_pass_and_partitions_in_one_launch(ctx):
+    """Starting clusterings whose hub rows meet from a few dozen to over
+    20,000 distinct clusters: with one-pass limits between those counts,
+    some hub rows of a launch are decided in one pass and the others by the
+    partitions (the launch after them skips the former); every mix equals
+    the oracle, 32- and 64-bit sums alike."""
+    hs = [H.hub_graph(n=60000, m=60000, hubs=(16000, 25000, 31000, 14500, 22000), seed=24),
+          H.with_weights(H.hub_graph(n=60000, m=60000, hubs=(16000, 25000), seed=25, weighted=False), "i64",
+                         seed=6, lo=1 << 27, hi=1 << 28)]
+    rng = np.random.default_rng(8)
+    for h in hs:
+        g_o, g_d = H.to_oracle(h), dev(h)
+        # hub i's neighbors fall in about min(deg, ncl) clusters
+        for ncl in [50, 3000, 60000]:
+            C0 = rng.integers(0, ncl, size=h.n).astype(np.int32)
+            Co, so = O.best_move(g_o, 1, 60, oparams(S=2, num_iter=2), C0, 1, 0)
+            for row_limit in [0, -1, 1000, 12000]:
+                Cd = torch.from_numpy(C0.copy()).cuda()
+                sd = L.lcc_best_move(ctx, g_d, 1, 60, dparams(S=2, num_iter=2, hub_row_limit=row_limit), Cd, 1, 0)
+                assert_same_bm(Co, so, Cd.cpu().numpy(), sd)
 
 
 def test_hub_rows_wider_than_65536(ctx):
     """Rows wider than 65536 make the level scatter each hub row's ids by
-    partition before aggregating; with and without a forced redo the result
-    is the oracle's."""
+    partition before aggregating; with and without one-pass rows and a
+    forced redo the result is the oracle's."""
     h = H.hub_graph(n=150000, m=200000, hubs=(70000, 90000, 20000), seed=31)
     lo, No, _ = O.cluster(H.to_oracle(h), 1, 80, oparams())
-    for limit in [0, 64]:
-        ld, Nd, _ = L.lcc_cluster(ctx, dev(h), 1, 80, dparams(hub_limit=limit))
-        assert np.array_equal(lo, ld.cpu().numpy()) and No == Nd, limit
+    for limit, row_limit in HUB_PATHS:
+        ld, Nd, _ = L.lcc_cluster(ctx, dev(h), 1, 80, dparams(hub_limit=limit, hub_row_limit=row_limit))
+        assert np.array_equal(lo, ld.cpu().numpy()) and No == Nd, (limit, row_limit)
 
 
 def test_tiny_and_degenerate_graphs(ctx):
