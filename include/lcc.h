@@ -161,6 +161,11 @@ typedef struct lcc_params {
                             hash partitions): 0 = automatic (three quarters of the block's table, the
                             largest value used; larger values are lowered to it), -1 = never (every such
                             row takes the partitions); values below -1 are rejected */
+  int32_t score_pruning; /* skip the cluster-total read of every candidate whose arc weight alone cannot
+                            reach the score of the vertex's heaviest candidate (such a candidate can
+                            neither win nor tie): 0 = automatic (on levels of at least 2^23 vertices,
+                            in the kernels where it pays), 1 = on every level, -1 = never; other values
+                            are rejected */
   /* mode (changes results) */
   int32_t async_moves; /* 1 = the paper's asynchronous setting (Sec. 3.2.1): a vertex's move is applied
                           the moment it is decided, so the other decisions of its sub-round see it or

@@ -1,6 +1,7 @@
 """Autotuner over the tuning fields of lcc_params.
 
-The tuning fields (queue_ahead, small_level, low_merge) choose launch shapes
+The tuning fields (queue_ahead, small_level, low_merge, hub_row_limit,
+score_pruning) choose launch shapes
 and schedules, never results: every choice must return the same labels and
 objective.  The tuner times a workload under candidate settings, one field at
 a time (coordinate descent from the defaults), keeps the fastest, and checks
@@ -27,6 +28,8 @@ SPACE: Dict[str, List[int]] = {
     "queue_ahead": [0, 1, 2, 4, 10],
     "small_level": [0, 1024, 4096],
     "low_merge": [0, 4096, 262144],
+    "hub_row_limit": [0, -1],
+    "score_pruning": [0, 1, -1],
 }
 
 

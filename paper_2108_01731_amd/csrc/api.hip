@@ -108,6 +108,8 @@ static void check_params(const lcc_params *prm) {
     fail(LCC_ERR_INVALID_ARG, "small_level must be in [0, " + std::to_string(LCC_SMALL_LEVEL_MAX) + "]");
   if (prm->low_merge < 0) fail(LCC_ERR_INVALID_ARG, "low_merge must be >= 0");
   if (prm->hub_row_limit < -1) fail(LCC_ERR_INVALID_ARG, "hub_row_limit must be >= -1");
+  if (prm->score_pruning < -1 || prm->score_pruning > 1)
+    fail(LCC_ERR_INVALID_ARG, "score_pruning must be -1, 0 or 1");
   if (prm->async_moves != 0 && prm->async_moves != 1) fail(LCC_ERR_INVALID_ARG, "async_moves must be 0 or 1");
 }
 

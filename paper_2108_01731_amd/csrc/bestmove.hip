@@ -110,6 +110,7 @@ struct AggArgs {
   int32_t rb0, rb1;
   int32_t hub_limit;  // distinct clusters a hub partition may hold (see k_hp_part)
   int32_t hub_row_limit;  // one-pass hub rows: 0 automatic, -1 never, k > 0 at most k clusters (k_hub_row)
+  int32_t prune;          // 1 = pruned scoring (see score_floor) in the kernels that use it
 };
 
 // The launch's vertex list and count (host-given, or read from the bucket
@@ -175,6 +176,50 @@ template <int NT> __device__ __forceinline__ void replay_prev(const AggArgs &a) 
 // (score, id) order: higher score first, then lower id.
 __device__ __forceinline__ bool better(int64_t s, int32_t id, int64_t bs, int32_t bid) {
   return s > bs || (s == bs && id < bid);
+}
+
+// Pruned scoring.  With p >= 0 and every k >= 0, a candidate's score
+// q*w_X - p*k_v*K_X never exceeds q*w_X.  The heaviest candidate other than
+// the vertex's own cluster, X*, has a score L that the best score reaches at
+// least, so a candidate with q*w_X < L scores strictly below the best and can
+// neither win nor tie: its K_X is never read.  On level 0 most candidates
+// share a single arc with the vertex while the few clusters it belongs with
+// share many, so nearly all K gathers go away.  The decision is unchanged.
+// It pays where K misses the caches (a level of at least PRUNE_MIN_N
+// vertices) and rows are long enough that the extra pass over the table is
+// small beside the gathers it saves (the block-per-row kernels and the
+// 512-slot lane groups); elsewhere the kernels score every candidate.
+constexpr int64_t PRUNE_MIN_N = (int64_t)1 << 23;
+__device__ __forceinline__ void heavier(int64_t w, int32_t X, int64_t &bw, int32_t &bX) {
+  if (w > bw || (w == bw && X < bX)) {
+    bw = w;
+    bX = X;
+  }
+}
+
+// (weight, id) of the heaviest candidate over the G lanes of a group.
+template <int G> __device__ __forceinline__ void group_heaviest(int64_t &bw, int32_t &bX) {
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) heavier(__shfl_xor(bw, o, WAVE), __shfl_xor(bX, o, WAVE), bw, bX);
+}
+
+// The same over a block of NT threads; every thread gets the result.
+template <int NT> __device__ __forceinline__ void block_heaviest(int64_t &bw, int32_t &bX) {
+  group_heaviest<WAVE>(bw, bX);
+  __shared__ int64_t hw[NT / WAVE];
+  __shared__ int32_t hx[NT / WAVE];
+  if (lane_id() == 0) {
+    hw[threadIdx.x / WAVE] = bw;
+    hx[threadIdx.x / WAVE] = bX;
+  }
+  __syncthreads();
+  for (int i = 0; i < NT / WAVE; i++) heavier(hw[i], hx[i], bw, bX);
+}
+
+// L from the heaviest candidate (INT64_MIN when the vertex has none).
+__device__ __forceinline__ int64_t score_floor(const int64_t *__restrict__ K, int64_t lq, int64_t pk, int64_t bw,
+                                               int32_t bX) {
+  return bX == INT32_MAX ? INT64_MIN : lq * bw - pk * K[bX];
 }
 
 // Multiplicative hash reduced to [0, H) (H need not be a power of two).
@@ -400,7 +445,18 @@ __global__ __launch_bounds__(BM_NT) void k_bm_group(AggArgs a) {
     int32_t job = 0;
     if (valid) job_lambda(a, v, lp, lq, job);
     const int64_t pk = lp * kv;
+    int64_t hw = INT64_MIN;
+    int32_t hX = INT32_MAX;
+    if (HMAX >= 512 && a.prune) {
+      if (valid)
+        for (uint32_t j = gl; j < H; j += G) {
+          const int32_t X = keys[j];
+          if (X >= 0 && X != c) heavier((int64_t)vals[j], X, hw, hX);
+        }
+      group_heaviest<G>(hw, hX);
+    }
     if (valid) {
+      const int64_t L = score_floor(a.K, lq, pk, hw, hX);
       for (uint32_t j = gl; j < H; j += G) {
         const int32_t X = keys[j];
         if (X < 0) continue;
@@ -408,7 +464,7 @@ __global__ __launch_bounds__(BM_NT) void k_bm_group(AggArgs a) {
         const int64_t wx = (int64_t)vals[j];
         if (X == c) {
           wc = wx;
-        } else {
+        } else if (lq * wx >= L) {
           const int64_t s = lq * wx - pk * a.K[X];
           if (better(s, X, best_s, best_id)) {
             best_s = s;
@@ -523,6 +579,17 @@ __global__ __launch_bounds__(NT) void k_bm_wide(AggArgs a) {
     int64_t best_s = INT64_MIN, wc = 0;
     int32_t best_id = ISO_ID;
     const int32_t nocc = LIST ? occ_n : (int32_t)H;
+    int64_t hw = INT64_MIN;
+    int32_t hX = INT32_MAX;
+    if (a.prune) {  // uniform: a launch argument
+      for (int32_t j = t; j < nocc; j += NT) {
+        const uint32_t h = LIST ? occ[j] : (uint32_t)j;
+        const int32_t X = keys[h];
+        if (X >= 0 && X != c) heavier((int64_t)vals[h], X, hw, hX);
+      }
+      block_heaviest<NT>(hw, hX);
+    }
+    const int64_t L = score_floor(a.K, lq, pk, hw, hX);
     for (int32_t j = t; j < nocc; j += NT) {
       const uint32_t h = LIST ? occ[j] : (uint32_t)j;
       const int32_t X = keys[h];
@@ -531,7 +598,7 @@ __global__ __launch_bounds__(NT) void k_bm_wide(AggArgs a) {
       const int64_t wx = (int64_t)vals[h];
       if (X == c) {
         wc = wx;
-      } else {
+      } else if (lq * wx >= L) {
         const int64_t s = lq * wx - pk * a.K[X];
         if (better(s, X, best_s, best_id)) {
           best_s = s;
@@ -730,6 +797,16 @@ __global__ __launch_bounds__(BM_NT) void k_bm_shared(AggArgs a, const int32_t *_
       const int64_t pk = lp * kv;
       int64_t best_s = INT64_MIN, wc = 0;
       int32_t best_id = ISO_ID;
+      int64_t hw = INT64_MIN;
+      int32_t hX = INT32_MAX;
+      if (a.prune) {
+        for (uint32_t s = gl; s < H; s += WAVE) {
+          const int32_t X = keys[s];
+          if (X >= 0 && X != c) heavier((int64_t)vals[s], X, hw, hX);
+        }
+        group_heaviest<WAVE>(hw, hX);
+      }
+      const int64_t L = score_floor(a.K, lq, pk, hw, hX);
       for (uint32_t s = gl; s < H; s += WAVE) {
         const int32_t X = keys[s];
         if (X < 0) continue;
@@ -739,7 +816,7 @@ __global__ __launch_bounds__(BM_NT) void k_bm_shared(AggArgs a, const int32_t *_
         c_cands++;
         if (X == c) {
           wc = wx;
-        } else {
+        } else if (lq * wx >= L) {
           const int64_t sc = lq * wx - pk * a.K[X];
           if (better(sc, X, best_s, best_id)) {
             best_s = sc;
@@ -1394,6 +1471,19 @@ __global__ __launch_bounds__(HP_NT) void k_hp_part(AggArgs a, const int64_t *__r
     const int64_t pk = lp * a.k[v];
     int64_t best_s = INT64_MIN, wc = 0, cands = 0;
     int32_t best_id = ISO_ID;
+    // pruned as the per-row kernels are, against this partition's heaviest
+    // candidate (a partition's best is exact; the row's is their maximum)
+    int64_t hw = INT64_MIN;
+    int32_t hX = INT32_MAX;
+    if (a.prune) {
+      if (!over)
+        for (int s = t; s < HP_SLOTS; s += HP_NT) {
+          const int32_t X = keys[s];
+          if (X >= 0 && X != c) heavier((int64_t)vals[s], X, hw, hX);
+        }
+      block_heaviest<HP_NT>(hw, hX);
+    }
+    const int64_t L = score_floor(a.K, lq, pk, hw, hX);
     if (!over) {
       for (int s = t; s < HP_SLOTS; s += HP_NT) {
         const int32_t X = keys[s];
@@ -1402,7 +1492,7 @@ __global__ __launch_bounds__(HP_NT) void k_hp_part(AggArgs a, const int64_t *__r
         const int64_t wx = (int64_t)vals[s];
         if (X == c) {
           wc = wx;
-        } else {
+        } else if (lq * wx >= L) {
           const int64_t sc = lq * wx - pk * a.K[X];
           if (better(sc, X, best_s, best_id)) {
             best_s = sc;
@@ -1638,6 +1728,16 @@ __global__ __launch_bounds__(HR_NT) void k_hub_row(AggArgs a, uint8_t *__restric
     const int64_t pk = lp * kv;
     int64_t best_s = INT64_MIN, wc = 0;
     int32_t best_id = ISO_ID;
+    int64_t hw = INT64_MIN;
+    int32_t hX = INT32_MAX;
+    if (a.prune) {
+      for (uint32_t j = t; j < H; j += HR_NT) {
+        const int32_t X = keys[j];
+        if (X >= 0 && X != c) heavier((int64_t)vals[j], X, hw, hX);
+      }
+      block_heaviest<HR_NT>(hw, hX);
+    }
+    const int64_t L = score_floor(a.K, lq, pk, hw, hX);
     for (uint32_t j = t; j < H; j += HR_NT) {
       const int32_t X = keys[j];
       if (X < 0) continue;
@@ -1645,7 +1745,7 @@ __global__ __launch_bounds__(HR_NT) void k_hub_row(AggArgs a, uint8_t *__restric
       const int64_t wx = (int64_t)vals[j];
       if (X == c) {
         wc = wx;
-      } else {
+      } else if (lq * wx >= L) {
         const int64_t sc = lq * wx - pk * a.K[X];
         if (better(sc, X, best_s, best_id)) {
           best_s = sc;
@@ -2757,6 +2857,7 @@ void best_moves_run(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_
     a.allow_iso = prm.allow_isolate;
     a.hub_limit = prm.hub_limit;
     a.hub_row_limit = prm.hub_row_limit;
+    a.prune = prm.score_pruning > 0 || (prm.score_pruning == 0 && g.n >= PRUNE_MIN_N) ? 1 : 0;
     a.list = blist;
     a.D = D;
     a.next_flag = prm.frontier == LCC_FRONTIER_NBR ? next : nullptr;

@@ -265,13 +265,20 @@ __global__ __launch_bounds__(RS_NT) void k_rs_hist(const K *__restrict__ keys, i
 }
 
 // Stable scatter: every block walks its contiguous range in order, in tiles
-// of RS_TILE keys.  A tile is first counted per digit (LDS), then ranked row
-// by row (256 keys; ranks among equal digits inside a wave come from 8
-// ballots, rows and waves in input order), placed in LDS in digit order, and
-// finally written out run by run, so consecutive threads store consecutive
-// addresses of one digit's output range.
+// of RS_TILE keys.  Wave w of the block takes the w-th contiguous part of a
+// tile (RS_IPT rows of 64 keys, lane l holding key row * 64 + l), so the
+// order (wave, row, lane) is the input order.  A wave ranks its keys among
+// equal digits by itself: per row, the lanes of one digit find each other
+// with RS_BITS ballots, and a per-wave LDS counter per digit carries the
+// count of earlier rows (one wave executes its LDS reads and writes in
+// program order, so no barrier is needed inside the row loop).  The tile
+// start of each digit and each wave's offset inside it then come from one
+// scan over the per-wave counts; keys are placed in LDS in digit order and
+// written out run by run, so consecutive threads store consecutive addresses
+// of one digit's output range.
 constexpr int RS_IPT = 8;
 constexpr int RS_TILE = RS_NT * RS_IPT;
+static_assert(RS_NT == RS_BINS, "one thread per digit in the per-tile scan");
 
 template <class K, class V, bool HASV>
 __global__ __launch_bounds__(RS_NT) void k_rs_scatter(const K *__restrict__ keys, const V *__restrict__ vals,
@@ -279,46 +286,30 @@ __global__ __launch_bounds__(RS_NT) void k_rs_scatter(const K *__restrict__ keys
                                                       int shift, int64_t per_block,
                                                       const int64_t *__restrict__ offs) {
   constexpr int NW = RS_NT / WAVE;
-  __shared__ int64_t base[RS_BINS];  // output position of the block's next key of digit d
-  __shared__ int cnt[RS_BINS];       // keys of digit d in the tile
-  __shared__ int tstart[RS_BINS];    // first tile slot of digit d
-  __shared__ int run[RS_BINS];       // tile keys of digit d placed so far
-  __shared__ int wcnt[NW][RS_BINS];
+  constexpr int WKEYS = RS_IPT * WAVE;  // keys of one wave's part of a tile
+  __shared__ int64_t base[RS_BINS];     // output position of the block's next key of digit d
+  __shared__ int cnt[RS_BINS];          // keys of digit d in the tile
+  __shared__ int tstart[RS_BINS];       // first tile slot of digit d
+  __shared__ int wcnt[NW][RS_BINS];     // per wave: keys of digit d so far, then the wave's offset
   __shared__ K sk[RS_TILE];
   __shared__ V sv[HASV ? RS_TILE : 1];
-  const int t = threadIdx.x, w = t / WAVE;
-  for (int d = t; d < RS_BINS; d += RS_NT) {
-    base[d] = offs[(int64_t)d * gridDim.x + blockIdx.x];
-    for (int j = 0; j < NW; j++) wcnt[j][d] = 0;
-  }
+  const int t = threadIdx.x, w = t / WAVE, l = lane_id();
+  for (int d = t; d < RS_BINS; d += RS_NT) base[d] = offs[(int64_t)d * gridDim.x + blockIdx.x];
   const int64_t beg = (int64_t)blockIdx.x * per_block;
   const int64_t end = beg + per_block < n ? beg + per_block : n;
   const uint64_t lt = __lanemask_lt();
   for (int64_t tb = beg; tb < end; tb += RS_TILE) {
     const int tn = (int)(end - tb < RS_TILE ? end - tb : RS_TILE);
-    for (int d = t; d < RS_BINS; d += RS_NT) {
-      cnt[d] = 0;
-      run[d] = 0;
-    }
+    for (int d = t; d < RS_BINS; d += RS_NT)
+      for (int q = 0; q < NW; q++) wcnt[q][d] = 0;
     __syncthreads();
     K key[RS_IPT];
+    int rank[RS_IPT];
 #pragma unroll
     for (int j = 0; j < RS_IPT; j++) {
-      const int r = j * RS_NT + t;
-      key[j] = r < tn ? keys[tb + r] : (K)0;
-      if (r < tn) atomicAdd(&cnt[(int)((key[j] >> shift) & (RS_BINS - 1))], 1);
-    }
-    __syncthreads();
-    {
-      int tot;
-      const int pre = block_excl_scan<int, RS_NT>(t < RS_BINS ? cnt[t] : 0, &tot);
-      if (t < RS_BINS) tstart[t] = pre;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < RS_IPT; j++) {
-      const int r = j * RS_NT + t;
+      const int r = w * WKEYS + j * WAVE + l;
       const bool valid = r < tn;
+      key[j] = valid ? keys[tb + r] : (K)0;
       const int d = (int)((key[j] >> shift) & (RS_BINS - 1));
       uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -326,27 +317,40 @@ __global__ __launch_bounds__(RS_NT) void k_rs_scatter(const K *__restrict__ keys
         const uint64_t bb = __ballot((d >> b) & 1);
         peers &= ((d >> b) & 1) ? bb : ~bb;
       }
-      const int rank = __popcll(peers & lt);
-      const int cntp = __popcll(peers);
-      if (valid && rank == cntp - 1) wcnt[w][d] = cntp;
-      __syncthreads();
-      if (valid) {
-        int pos = tstart[d] + run[d] + rank;
-        for (int q = 0; q < w; q++) pos += wcnt[q][d];
+      const int below = __popcll(peers & lt);
+      const int before = valid ? wcnt[w][d] : 0;
+      rank[j] = before + below;
+      if (valid && below == __popcll(peers) - 1) wcnt[w][d] = before + below + 1;
+    }
+    __syncthreads();
+    // per digit: the tile count, and each wave's offset among the digit's keys
+    int c = 0;
+    if (t < RS_BINS)
+      for (int q = 0; q < NW; q++) {
+        const int x = wcnt[q][t];
+        wcnt[q][t] = c;
+        c += x;
+      }
+    {
+      int tot;
+      const int pre = block_excl_scan<int, RS_NT>(t < RS_BINS ? c : 0, &tot);
+      if (t < RS_BINS) {
+        tstart[t] = pre;
+        cnt[t] = c;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < RS_IPT; j++) {
+      const int r = w * WKEYS + j * WAVE + l;
+      if (r < tn) {
+        const int d = (int)((key[j] >> shift) & (RS_BINS - 1));
+        const int pos = tstart[d] + wcnt[w][d] + rank[j];
         sk[pos] = key[j];
         if constexpr (HASV) sv[pos] = vals[tb + r];
       }
-      __syncthreads();
-      for (int dd = t; dd < RS_BINS; dd += RS_NT) {
-        int s2 = 0;
-        for (int q = 0; q < NW; q++) {
-          s2 += wcnt[q][dd];
-          wcnt[q][dd] = 0;
-        }
-        run[dd] += s2;
-      }
-      __syncthreads();
     }
+    __syncthreads();
     for (int p = t; p < tn; p += RS_NT) {
       const K k2 = sk[p];
       const int d = (int)((k2 >> shift) & (RS_BINS - 1));

@@ -56,7 +56,7 @@ class _Params(ctypes.Structure):
         ("max_levels", ctypes.c_int32), ("stop_after_subrounds", ctypes.c_int64),
         ("validate", ctypes.c_int32), ("timing", ctypes.c_int32), ("hub_limit", ctypes.c_int32),
         ("queue_ahead", ctypes.c_int32), ("small_level", ctypes.c_int32), ("low_merge", ctypes.c_int32),
-        ("hub_row_limit", ctypes.c_int32), ("async_moves", ctypes.c_int32), ("no_graph_replay", ctypes.c_int32),
+        ("hub_row_limit", ctypes.c_int32), ("score_pruning", ctypes.c_int32), ("async_moves", ctypes.c_int32), ("no_graph_replay", ctypes.c_int32),
     ]
 
 
@@ -241,6 +241,7 @@ class Params:
     small_level: int = 0
     low_merge: int = 0
     hub_row_limit: int = 0
+    score_pruning: int = 0
     async_moves: int = 0
     no_graph_replay: int = 0
 
@@ -251,7 +252,7 @@ class Params:
         p.max_levels, p.stop_after_subrounds = self.max_levels, self.stop_after_subrounds
         p.validate, p.timing, p.hub_limit = self.validate, self.timing, self.hub_limit
         p.queue_ahead, p.small_level, p.low_merge = self.queue_ahead, self.small_level, self.low_merge
-        p.hub_row_limit = self.hub_row_limit
+        p.hub_row_limit, p.score_pruning = self.hub_row_limit, self.score_pruning
         p.async_moves, p.no_graph_replay = self.async_moves, self.no_graph_replay
         return p
 

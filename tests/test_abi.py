@@ -43,7 +43,8 @@ def test_struct_layout_matches_header(tmp_path):
     fields = {
         "lcc_graph": (L._Graph, ["n", "arcs", "off", "col", "wt", "wt_kind", "k", "s", "kk"]),
         "lcc_params": (L._Params, ["S", "num_iter", "seed", "frontier", "stop_after_subrounds", "validate", "timing",
-                                   "hub_limit", "low_merge", "hub_row_limit", "async_moves", "no_graph_replay"]),
+                                   "hub_limit", "low_merge", "hub_row_limit", "score_pruning", "async_moves",
+                                   "no_graph_replay"]),
         "lcc_bm_stats": (L._BMStats, ["iterations", "moves", "candidates", "active_per_iter", "moves_per_iter"]),
         "lcc_objective_out": (L._Objective, ["num_hi", "num_lo", "den", "value"]),
         "lcc_cluster_stats": (L._ClusterStats, ["levels", "n_level", "iters_refine", "clusters", "ms_total"]),

@@ -107,6 +107,30 @@ def test_best_move_parity(ctx, idx, cfg):
 
 
 @pytest.mark.parametrize("idx", range(8))
+def test_pruned_scoring_parity(ctx, idx):
+    """Scoring that skips the cluster totals of candidates whose arc weight
+    alone cannot reach the heaviest candidate's score (on every level here,
+    not only on the large ones where it is automatic) and scoring without it
+    both equal the oracle: from singletons, from a given clustering with a
+    large lambda (isolations), and over a whole clustering."""
+    name, h, p, q = cases()[idx]
+    g_o, g_d = H.to_oracle(h), dev(h)
+    C0 = np.random.default_rng(idx + 40).integers(0, max(1, h.n // 30), size=h.n).astype(np.int32)
+    for start, (pp, qq), cfg in [(None, (p, q), dict(S=4)), (C0, (p * 50, q), dict(S=3, frontier=2)),
+                                 (C0, (p, q), dict(S=2, frontier=0))]:
+        Cs = np.arange(h.n, dtype=np.int32) if start is None else start
+        Co, so = O.best_move(g_o, pp, qq, oparams(**cfg), Cs, 1, 0)
+        for sp in (1, -1):
+            Cd = torch.from_numpy(Cs.copy()).cuda()
+            sd = L.lcc_best_move(ctx, g_d, pp, qq, dparams(score_pruning=sp, **cfg), Cd, 1, 0)
+            assert_same_bm(Co, so, Cd.cpu().numpy(), sd)
+    lo, No, _ = O.cluster(g_o, p, q, oparams())
+    for sp in (1, -1):
+        ld, Nd, _ = L.lcc_cluster(ctx, g_d, p, q, dparams(score_pruning=sp))
+        assert np.array_equal(lo, ld.cpu().numpy()) and No == Nd, sp
+
+
+@pytest.mark.parametrize("idx", range(8))
 def test_best_move_from_given_clustering(ctx, idx):
     """Refinement-style start: an arbitrary clustering, level 3, phase 1, and a
     large lambda so isolation happens."""

@@ -53,6 +53,9 @@ def test_every_tuning_combination_gives_the_same_result(ctx, idx, frontier):
         lab, N, _ = L.lcc_cluster(ctx, g, p, q, L.Params(frontier=frontier, queue_ahead=qa, small_level=sl,
                                                          low_merge=lm))
         assert torch.equal(lab, ref) and N == Nref, (name, frontier, qa, sl, lm)
+    for sp, hrl in itertools.product([-1, 1], [-1, 0, 64]):
+        lab, N, _ = L.lcc_cluster(ctx, g, p, q, L.Params(frontier=frontier, score_pruning=sp, hub_row_limit=hrl))
+        assert torch.equal(lab, ref) and N == Nref, (name, frontier, sp, hrl)
 
 
 @pytest.mark.parametrize("idx", range(4))
