@@ -111,6 +111,7 @@ struct AggArgs {
   int32_t hub_limit;  // distinct clusters a hub partition may hold (see k_hp_part)
   int32_t hub_row_limit;  // one-pass hub rows: 0 automatic, -1 never, k > 0 at most k clusters (k_hub_row)
   int32_t prune;          // 1 = pruned scoring (see score_floor) in the kernels that use it
+  int32_t *hub_seen;      // per vertex: distinct clusters its hub row met when last decided (k_hub_row)
 };
 
 // The launch's vertex list and count (host-given, or read from the bucket
@@ -1405,9 +1406,42 @@ __device__ __forceinline__ bool lds_insert_bounded(int32_t *keys, Acc *vals, int
   }
 }
 
+// lds_insert_bounded that also reports a slot it claimed (-1 otherwise).
+template <class Acc>
+__device__ __forceinline__ bool lds_insert_bounded_claim(int32_t *keys, Acc *vals, int32_t X, int64_t w,
+                                                         int32_t *nclaim, int32_t stop, int32_t &claimed) {
+  uint32_t h = slot_of(X, HP_SLOTS);
+  while (true) {
+    int32_t cur = keys[h];
+    if (cur == -1) {
+      if (atomicAdd(nclaim, 1) >= stop) return false;
+      cur = atomicCAS(&keys[h], -1, X);
+      if (cur == -1) {
+        cur = X;
+        claimed = (int32_t)h;
+      } else {
+        atomicSub(nclaim, 1);  // another key took the slot first
+      }
+    }
+    if (cur == X) {
+      if (w) {
+        if constexpr (sizeof(Acc) == 8)
+          atomicAdd(reinterpret_cast<unsigned long long *>(&vals[h]), (unsigned long long)w);
+        else
+          atomicAdd(&vals[h], (Acc)w);
+      }
+      return true;
+    }
+    h = (h + 1 == (uint32_t)HP_SLOTS) ? 0 : h + 1;
+  }
+}
+
 // One block per partition: its clusters' weights summed in LDS, then scored
 // (as the per-row kernels do) into part[partition]; an overflow counts in
-// counter 6 of the launch.
+// counter 6 of the launch.  With 32-bit sums the table (96 KB) leaves room
+// for a list of the claimed slots (24 KB): the table is cleared once per
+// block, and scoring and the reset for the next partition touch only the
+// listed slots, a few thousand instead of all 12288.
 template <int WK, bool A32, bool SEG>
 __global__ __launch_bounds__(HP_NT) void k_hp_part(AggArgs a, const int64_t *__restrict__ tot,
                                                    const int64_t *__restrict__ xoff,
@@ -1420,7 +1454,9 @@ __global__ __launch_bounds__(HP_NT) void k_hp_part(AggArgs a, const int64_t *__r
   extern __shared__ __align__(16) unsigned char smem[];
   int32_t *keys = reinterpret_cast<int32_t *>(smem);
   Acc *vals = reinterpret_cast<Acc *>(smem + (size_t)HP_SLOTS * sizeof(int32_t));
-  __shared__ int32_t nclaim;
+  constexpr bool LIST = A32;
+  uint16_t *occ = reinterpret_cast<uint16_t *>(smem + (size_t)HP_SLOTS * (sizeof(int32_t) + sizeof(Acc)));
+  __shared__ int32_t nclaim, occ_n;
   __shared__ int64_t sh_row;
   const int t = threadIdx.x;
   const int32_t *list;
@@ -1429,12 +1465,20 @@ __global__ __launch_bounds__(HP_NT) void k_hp_part(AggArgs a, const int64_t *__r
   const int64_t np = tot[2], n7 = tot[3];
   const int32_t limit = a.hub_limit > 0 ? a.hub_limit : HP_LIMIT;
   int64_t overflows = 0;
-  for (int64_t pi = blockIdx.x; pi < np; pi += gridDim.x) {
-    __syncthreads();  // the table, nclaim and sh_row are reused
+  if (LIST) {
     for (int s = t; s < HP_SLOTS; s += HP_NT) {
       keys[s] = -1;
       vals[s] = 0;
     }
+    if (t == 0) occ_n = 0;
+  }
+  for (int64_t pi = blockIdx.x; pi < np; pi += gridDim.x) {
+    __syncthreads();  // the table, nclaim and sh_row are reused
+    if (!LIST)
+      for (int s = t; s < HP_SLOTS; s += HP_NT) {
+        keys[s] = -1;
+        vals[s] = 0;
+      }
     if (t == 0) {
       nclaim = 0;
       int64_t lo = 0, hi = n7 - 1;
@@ -1452,19 +1496,36 @@ __global__ __launch_bounds__(HP_NT) void k_hp_part(AggArgs a, const int64_t *__r
     const uint32_t P = (uint32_t)(pstart[i + 1] - pstart[i]), p = (uint32_t)(pi - pstart[i]);
     const int32_t c = a.C[v];
     const int32_t *x = SEG ? xs : xs + xoff[i];
-    if (t == 0 && part_of(c, P) == p) lds_insert_bounded<Acc>(keys, vals, c, 0, &nclaim, HP_STOP);
+    if (t == 0 && part_of(c, P) == p) {
+      int32_t h0 = -1;
+      lds_insert_bounded_claim<Acc>(keys, vals, c, 0, &nclaim, HP_STOP, h0);
+      if (LIST && h0 >= 0) occ[atomicAdd(&occ_n, 1)] = (uint16_t)h0;
+    }
     if constexpr (SEG) {  // this partition's ids and weights, scattered
       const int64_t s0 = segstart[pi], s1 = s0 + pcnt[pi];
-      for (int64_t j = s0 + t; j < s1; j += HP_NT) lds_insert_bounded<Acc>(keys, vals, xs[j], ws[j], &nclaim, HP_STOP);
+      // every lane of a wave runs the same trips (the claims are listed per wave)
+      for (int64_t j0 = s0; j0 < s1; j0 += HP_NT) {
+        const int64_t j = j0 + t;
+        int32_t h = -1;
+        if (j < s1) lds_insert_bounded_claim<Acc>(keys, vals, xs[j], ws[j], &nclaim, HP_STOP, h);
+        if (LIST) list_claims(h, occ, &occ_n);
+      }
     } else {
-      for (int64_t j = t; j < deg; j += HP_NT) {
-        const int32_t X = x[j];
-        if (part_of(X, P) != p) continue;
-        lds_insert_bounded<Acc>(keys, vals, X, load_w<WK>(a.wt, beg + j), &nclaim, HP_STOP);
+      for (int64_t j0 = 0; j0 < deg; j0 += HP_NT) {
+        const int64_t j = j0 + t;
+        int32_t h = -1;
+        if (j < deg) {
+          const int32_t X = x[j];
+          if (part_of(X, P) == p)
+            lds_insert_bounded_claim<Acc>(keys, vals, X, load_w<WK>(a.wt, beg + j), &nclaim, HP_STOP, h);
+        }
+        if (LIST) list_claims(h, occ, &occ_n);
       }
     }
     __syncthreads();
+    const int32_t nocc = LIST ? occ_n : HP_SLOTS;
     const bool over = nclaim > limit;  // block-uniform
+    if (t == 0 && a.hub_seen) atomicAdd(&a.hub_seen[v], nclaim);
     int64_t lp, lq;
     int32_t job;
     job_lambda(a, v, lp, lq, job);
@@ -1477,7 +1538,8 @@ __global__ __launch_bounds__(HP_NT) void k_hp_part(AggArgs a, const int64_t *__r
     int32_t hX = INT32_MAX;
     if (a.prune) {
       if (!over)
-        for (int s = t; s < HP_SLOTS; s += HP_NT) {
+        for (int j = t; j < nocc; j += HP_NT) {
+          const int s = LIST ? occ[j] : j;
           const int32_t X = keys[s];
           if (X >= 0 && X != c) heavier((int64_t)vals[s], X, hw, hX);
         }
@@ -1485,7 +1547,8 @@ __global__ __launch_bounds__(HP_NT) void k_hp_part(AggArgs a, const int64_t *__r
     }
     const int64_t L = score_floor(a.K, lq, pk, hw, hX);
     if (!over) {
-      for (int s = t; s < HP_SLOTS; s += HP_NT) {
+      for (int j = t; j < nocc; j += HP_NT) {
+        const int s = LIST ? occ[j] : j;
         const int32_t X = keys[s];
         if (X < 0) continue;
         cands++;
@@ -1510,6 +1573,13 @@ __global__ __launch_bounds__(HP_NT) void k_hp_part(AggArgs a, const int64_t *__r
       for (int k = 0; k < HP_NT / WAVE; k++) tc += rc[k];
       part[pi] = SegBest{best_s, wc, tc, best_id, 0};
       overflows += over ? 1 : 0;
+    }
+    if (LIST) {  // leave the table clean for the next partition (block_best passed a barrier)
+      for (int j = t; j < nocc; j += HP_NT) {
+        keys[occ[j]] = -1;
+        vals[occ[j]] = 0;
+      }
+      if (t == 0) occ_n = 0;
     }
   }
   if (t == 0 && overflows) atomic_add_i64(&a.ctr[(blockIdx.x % NSPREAD) * NCTR + 6], overflows);
@@ -1622,7 +1692,8 @@ __global__ __launch_bounds__(B7_NT) void k_hps_scatter(AggArgs a, const int64_t 
   }
 }
 
-size_t hp_lds_bytes(bool a32) { return (size_t)HP_SLOTS * (sizeof(int32_t) + (a32 ? 4 : 8)); }
+// keys, values, and (32-bit sums) the claimed-slot list of k_hp_part
+size_t hp_lds_bytes(bool a32) { return (size_t)HP_SLOTS * (sizeof(int32_t) + (a32 ? 4 + 2 : 8)); }
 
 // Hub rows in one pass.  A row's degree bounds its distinct clusters, but
 // once clusters have formed a hub row meets far fewer clusters than it has
@@ -1633,6 +1704,11 @@ size_t hp_lds_bytes(bool a32) { return (size_t)HP_SLOTS * (sizeof(int32_t) + (a3
 // decided here exactly as the per-row kernels do (done[i] = 1); a row that
 // meets more clusters stops reading at once and is left to the hash
 // partitions (done[i] = 0), which k_hp_layout and k_b7_final then take alone.
+// hub_seen[v] keeps the number of distinct clusters v's row met when it was
+// last decided (here, or summed over its partitions by k_hp_part); a row
+// that met more than the limit then goes straight to the partitions instead
+// of reading most of itself again before it overflows.  The count is a hint
+// about speed only: either way the row is decided the same.
 __device__ __forceinline__ bool lds_insert_upto(int32_t *keys, int32_t *vals32, int64_t *vals64, bool a32,
                                                 uint32_t H, int32_t X, int64_t w, int32_t *nclaim,
                                                 int32_t stop) {
@@ -1681,6 +1757,14 @@ __global__ __launch_bounds__(HR_NT) void k_hub_row(AggArgs a, uint8_t *__restric
   int64_t movers = 0, marcs = 0, cands = 0, niso = 0;
   for (int64_t i = blockIdx.x; i < n7; i += gridDim.x) {
     const int32_t v = list[i];
+    if (a.hub_seen && a.hub_seen[v] > limit) {  // uniform: one address
+      __syncthreads();  // every thread has read the hint before it is cleared
+      if (t == 0) {
+        done[i] = 0;
+        a.hub_seen[v] = 0;  // k_hp_part adds this time's count
+      }
+      continue;
+    }
     const int64_t beg = a.off[v], end = a.off[v + 1];
     const int32_t c = a.C[v];
     const int64_t kv = a.k[v], Kc = a.K[c];
@@ -1718,10 +1802,14 @@ __global__ __launch_bounds__(HR_NT) void k_hub_row(AggArgs a, uint8_t *__restric
     __syncthreads();
     const bool fits = nclaim <= limit;  // block-uniform
     if (!fits) {
-      if (t == 0) done[i] = 0;
+      if (t == 0) {
+        done[i] = 0;
+        if (a.hub_seen) a.hub_seen[v] = 0;  // k_hp_part adds this time's count
+      }
       __syncthreads();  // the table and nclaim are reused by the next row
       continue;
     }
+    if (t == 0 && a.hub_seen) a.hub_seen[v] = nclaim;
     int64_t lp, lq;
     int32_t job;
     job_lambda(a, v, lp, lq, job);
@@ -1821,10 +1909,100 @@ __global__ __launch_bounds__(LN_NT) void k_mark_left_nbrs(const int64_t *__restr
   }
 }
 
+// ------------------------------------- neighbors-of-movers frontier, pulled
+
+// End of an iteration under the neighbors-of-movers rule on levels above the
+// small-level size (Sec. 3.2.2): next[u] = 1 for every u adjacent to a vertex
+// that moved during the iteration (moved[v] = 1, set by k_bm_apply).  The
+// deciding kernels do not mark neighbors on these levels; this launch builds
+// the set in one of two ways, chosen from the iteration's mover count (the
+// launches' counters, so every block takes the same branch):
+// * many movers (at least 1/FR_DENSE of the vertices): every vertex looks
+//   through its own row for a neighbor that moved and stops at the first, in
+//   groups of FR_G lanes.  When most vertices move, nearly every row has a
+//   mover among its first arcs, so this reads a few arcs per vertex instead
+//   of storing one flag per arc of every mover;
+// * few movers: one wave takes 64 vertices, lists the movers among them by
+//   ballot and marks each mover's row with all 64 lanes (what the deciding
+//   kernels would store, without their lane-group shapes).
+// Both give the same set because the graph is symmetric: u is adjacent to v
+// exactly when v is adjacent to u.  Movers of degree 2048 or more are not
+// flagged: they marked their neighbors as they decided, so both ways only
+// add to `next` (cleared by the compaction of the previous iteration).
+constexpr int FR_NT = 256;
+constexpr int FR_G = 8;
+constexpr int64_t FR_DENSE = 8;
+
+__global__ __launch_bounds__(FR_NT) void k_frontier(const int64_t *__restrict__ off, const int32_t *__restrict__ col,
+                                                    int64_t n, const uint8_t *__restrict__ moved,
+                                                    const int64_t *__restrict__ lctr, int32_t nlaunch,
+                                                    uint8_t *__restrict__ next) {
+  __shared__ int sh_pull;
+  __shared__ int64_t sh_m[FR_NT / WAVE];
+  {
+    // movers: counter 0 of every copy of every launch, summed by the block
+    int64_t m = 0;
+    for (int64_t i = threadIdx.x; i < (int64_t)nlaunch * NSPREAD; i += FR_NT) m += lctr[i * NCTR];
+    m = wave_sum(m);
+    if (lane_id() == 0) sh_m[threadIdx.x / WAVE] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int64_t tot = 0;
+      for (int w = 0; w < FR_NT / WAVE; w++) tot += sh_m[w];
+      sh_pull = tot * FR_DENSE >= n ? 1 : 0;
+    }
+    __syncthreads();
+  }
+  const int lane = lane_id();
+  if (sh_pull) {
+    const int gl = lane % FR_G;
+    const uint64_t gmask = ((1ull << FR_G) - 1) << (lane - gl);
+    for (int64_t v0 = (int64_t)blockIdx.x * (FR_NT / FR_G); v0 < n; v0 += (int64_t)gridDim.x * (FR_NT / FR_G)) {
+      const int64_t v = v0 + threadIdx.x / FR_G;
+      int64_t beg = 0, end = 0;
+      if (v < n) {
+        beg = off[v];
+        end = off[v + 1];
+      }
+      bool found = false;
+      // group-uniform trip count: the group's lanes share v
+      for (int64_t e0 = beg; e0 < end && !found; e0 += FR_G) {
+        const int64_t e = e0 + gl;
+        const bool m = e < end && moved[col[e]] != 0;
+        found = (__ballot(m) & gmask) != 0;
+      }
+      if (v < n && gl == 0 && found) next[v] = 1;  // (wide movers may have marked v already)
+    }
+  } else {
+    const int64_t wid = ((int64_t)blockIdx.x * FR_NT + threadIdx.x) / WAVE;
+    const int64_t nw = (int64_t)gridDim.x * FR_NT / WAVE;
+    for (int64_t v0 = wid * WAVE; v0 < n; v0 += nw * WAVE) {
+      const int64_t v = v0 + lane;
+      uint64_t mk = __ballot(v < n && moved[v] != 0);
+      while (mk) {
+        const int j = __ffsll((unsigned long long)mk) - 1;
+        mk &= mk - 1;
+        const int64_t beg = off[v0 + j], end = off[v0 + j + 1];
+        for (int64_t e = beg + lane; e < end; e += 4 * WAVE) {
+          int32_t u[4];
+#pragma unroll
+          for (int r = 0; r < 4; r++) u[r] = e + r * WAVE < end ? col[e + r * WAVE] : -1;
+#pragma unroll
+          for (int r = 0; r < 4; r++)
+            if (u[r] >= 0) next[u[r]] = 1;
+        }
+      }
+    }
+  }
+}
+
+
 // -------------------------------------------------------------- apply
 
 // Applies the sub-round's decisions; an isolating vertex v takes the fresh
-// id n + v.
+// id n + v.  With `moved`, every mover of degree below 2048 is also flagged
+// there (the frontier of the iteration is then built from these flags by
+// k_frontier; wider rows marked their neighbors when they decided).
 //
 // Batched runs (jid set) also flag the jobs that moved: the list keeps vertex
 // order within each bin, so a block's movers mostly share a few consecutive
@@ -1836,7 +2014,8 @@ __global__ __launch_bounds__(BM_NT) void k_bm_apply(const int32_t *__restrict__ 
                                                     int64_t *__restrict__ K, int32_t *__restrict__ cnt,
                                                     const int64_t *__restrict__ k, int64_t n,
                                                     int64_t *__restrict__ iso_ctr, const int32_t *__restrict__ jid,
-                                                    int64_t *__restrict__ jmoved) {
+                                                    int64_t *__restrict__ jmoved, uint8_t *__restrict__ moved,
+                                                    const int64_t *__restrict__ off) {
   constexpr int JW = 64;  // jobs flagged in LDS per block
   __shared__ int32_t j0;
   __shared__ int32_t jflag[JW];
@@ -1865,6 +2044,7 @@ __global__ __launch_bounds__(BM_NT) void k_bm_apply(const int32_t *__restrict__ 
       }
       if (d != c) {
         const int64_t kv = k[v];
+        if (moved && off[v + 1] - off[v] <= bin_limit_fixed(5)) moved[v] = 1;
         if (d < 0) {
           d = (int32_t)(n + v);
           niso++;
@@ -2550,6 +2730,7 @@ template <int WK> void launch_hub_part(Ctx &c, AggArgs a, int64_t n7_ub, int64_t
   uint8_t *done = c.buf<uint8_t>("hp.done", (size_t)n7_ub);
   if (a.hub_row_limit < 0) {  // every row takes the partitions
     HIPCHECK(hipMemsetAsync(done, 0, (size_t)n7_ub, c.stream));
+    a.hub_seen = nullptr;
   } else {
     AggArgs ah = a;
     ah.hcap = hub_row_slots(c, a32);
@@ -2827,6 +3008,10 @@ void best_moves_run(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_
   };
   const int LC = NSPREAD * NCTR;
   static const char *wk_tag[4] = {"_unit", "_i16", "_i32", "_i64"};
+  // neighbors-of-movers frontier built at the end of each iteration by
+  // k_frontier (device-driven iterations on levels above the small size)
+  // instead of by the deciding kernels
+  bool pulled_front = false;
 
   // Per-iteration device counters: bucket counts, bucket arcs, bucket starts
   // (NB + 1), per-launch counters, per-sub-round isolations, next-frontier
@@ -2842,6 +3027,12 @@ void best_moves_run(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_
   const size_t scatter_smem = stable_lds_bytes(NB, BM_NT);      // k_part_scatter
   const size_t small_smem = part_small_lds_bytes(NB);           // k_part_small, k_iter_end_small
 
+  // rows beyond the LDS tables remember how many clusters they met (k_hub_row)
+  int32_t *hub_seen = nullptr;
+  if (n > 0 && shape.maxdeg > wide_max) {
+    hub_seen = c.buf<int32_t>("bm.hubseen", nn);
+    HIPCHECK(hipMemsetAsync(hub_seen, 0, nn * sizeof(int32_t), c.stream));
+  }
   auto agg_args = [&](int bi, const int64_t *dstart, int64_t *ctr) {
     AggArgs a;
     std::memset(&a, 0, sizeof(a));
@@ -2858,9 +3049,13 @@ void best_moves_run(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_
     a.hub_limit = prm.hub_limit;
     a.hub_row_limit = prm.hub_row_limit;
     a.prune = prm.score_pruning > 0 || (prm.score_pruning == 0 && g.n >= PRUNE_MIN_N) ? 1 : 0;
+    a.hub_seen = hub_seen;
     a.list = blist;
     a.D = D;
-    a.next_flag = prm.frontier == LCC_FRONTIER_NBR ? next : nullptr;
+    // (with the pulled frontier, rows of 2048 arcs or more still mark their
+    // neighbors as they decide: their kernels spread a row over a whole block,
+    // which one wave of k_frontier could not)
+    a.next_flag = prm.frontier == LCC_FRONTIER_NBR && (!pulled_front || bi % NBINS >= 6) ? next : nullptr;
     a.left_flag = left_cur;
     if (async) {
       a.Cw = C;
@@ -2901,6 +3096,8 @@ void best_moves_run(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_
     // per degree bin present in the level.
     const int64_t small_max = prm.small_level > 0 ? prm.small_level : SMALL_LEVEL;
     const bool small = !async && n <= small_max && shape.maxdeg <= wide_max;
+    pulled_front = !small && !async && prm.frontier == LCC_FRONTIER_NBR;
+    uint8_t *moved = pulled_front ? c.buf<uint8_t>("bm.moved", nn) : nullptr;
     // degree histogram of the level (larger levels launch one kernel per
     // non-empty bin); a small level needs only the largest degree: its
     // narrow launch (degree < 2048) always runs, empty or not
@@ -2995,6 +3192,7 @@ void best_moves_run(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_
         int64_t *blk = ctrs + (size_t)it * IB;
         if (mark_left) left_cur = left + (size_t)(it & 1) * nn;
         const uint64_t hh = round_hash(prm.seed, level, phase, it);
+        if (moved) HIPCHECK(hipMemsetAsync(moved, 0, nn, c.stream));
         // the first iteration and the "all vertices" rule take every vertex
         const bool all = it == 0 || !nbr;
         const int32_t *list = all ? nullptr : active;
@@ -3108,9 +3306,17 @@ void best_moves_run(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_
             Ctx::Timer tm(&c, "bm_apply", 0.0, 0.0, true);
             c.launch(k_bm_apply, dim3((unsigned)apply_grid), dim3(BM_NT), 0, (const int32_t *)blist, (int64_t)0,
                      (const int64_t *)(blk + o_start), (int32_t)(s * NBINS), (int32_t)((s + 1) * NBINS),
-                     (const int32_t *)D, C, K, cnt, g.k, n, blk + o_isoc + s, jv.jid, jv.jmoved);
+                     (const int32_t *)D, C, K, cnt, g.k, n, blk + o_isoc + s, jv.jid, jv.jmoved, moved,
+                     (const int64_t *)g.off);
             LAUNCHCHECK();
           }
+        }
+        if (moved) {
+          Ctx::Timer tm(&c, "bm_frontier", 0.0, (double)n, true);
+          c.launch(k_frontier, dim3((unsigned)std::min<int64_t>(cdiv(n, FR_NT / FR_G), (int64_t)c.num_cu * 16)),
+                   dim3(FR_NT), 0, (const int64_t *)g.off, (const int32_t *)g.col, n, (const uint8_t *)moved,
+                   (const int64_t *)(blk + o_lctr), (int32_t)NB, next);
+          LAUNCHCHECK();
         }
         // (on small levels the state copy the last sub-round wrote)
         if (mark_left) mark_left_nbrs(small && (S - 1) % 2 == 0 ? C2 : C, it);
@@ -3218,7 +3424,8 @@ void best_moves_run(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_
         }
         const double per_arc = t.single ? 12.0 + wb : 8.0 + wb;
         // candidates gather K (8 B each); movers store one flag per neighbor
-        const double extra = 8.0 * (double)launch_sums(hb + o_lctr, t.bi, 1) + (double)launch_sums(hb + o_lctr, t.bi, 2);
+        const double extra = 8.0 * (double)launch_sums(hb + o_lctr, t.bi, 1) +
+                             (pulled_front ? 0.0 : (double)launch_sums(hb + o_lctr, t.bi, 2));
         if (t.shared_s >= 0) {
           // per listed vertex: list, mask, offsets, k (32 B); per row arc,
           // once for all jobs: col, weight, the 64-byte id line; per (vertex,
@@ -3316,7 +3523,7 @@ void best_moves_run(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_
         Ctx::Timer tm(&c, "bm_apply", (double)total_s * 12.0, (double)total_s);
         hipLaunchKernelGGL(k_bm_apply, dim3((unsigned)cdiv(total_s, BM_NT)), dim3(BM_NT), 0, c.stream,
                            blist + start[s * NBINS], total_s, (const int64_t *)nullptr, 0, 0, D, C, K, cnt, g.k, n,
-                           isoc + s, jv.jid, jv.jmoved);
+                           isoc + s, jv.jid, jv.jmoved, (uint8_t *)nullptr, (const int64_t *)nullptr);
         LAUNCHCHECK();
       }
       st.subrounds++;
