@@ -1918,10 +1918,11 @@ __global__ __launch_bounds__(LN_NT) void k_mark_left_nbrs(const int64_t *__restr
 // the set in one of two ways, chosen from the iteration's mover count (the
 // launches' counters, so every block takes the same branch):
 // * many movers (at least 1/FR_DENSE of the vertices): every vertex looks
-//   through its own row for a neighbor that moved and stops at the first, in
-//   groups of FR_G lanes.  When most vertices move, nearly every row has a
-//   mover among its first arcs, so this reads a few arcs per vertex instead
-//   of storing one flag per arc of every mover;
+//   through its own row for a neighbor that moved and stops at the first
+//   (a lane per vertex for the first arcs, a group of lanes for the rest
+//   of a row).  When most vertices move, nearly every row has a mover among its
+//   first arcs, so this reads a few arcs per vertex instead of storing one
+//   flag per arc of every mover;
 // * few movers: one wave takes 64 vertices, lists the movers among them by
 //   ballot and marks each mover's row with all 64 lanes (what the deciding
 //   kernels would store, without their lane-group shapes).
@@ -1930,7 +1931,8 @@ __global__ __launch_bounds__(LN_NT) void k_mark_left_nbrs(const int64_t *__restr
 // flagged: they marked their neighbors as they decided, so both ways only
 // add to `next` (cleared by the compaction of the previous iteration).
 constexpr int FR_NT = 256;
-constexpr int FR_G = 8;
+constexpr int FR_FIRST = 4;  // arcs a lane checks alone before a group takes the row
+constexpr int FR_G = 8;      // lanes per group walking the rest of a row
 constexpr int64_t FR_DENSE = 8;
 
 __global__ __launch_bounds__(FR_NT) void k_frontier(const int64_t *__restrict__ off, const int32_t *__restrict__ col,
@@ -1954,28 +1956,45 @@ __global__ __launch_bounds__(FR_NT) void k_frontier(const int64_t *__restrict__ 
     __syncthreads();
   }
   const int lane = lane_id();
+  const int64_t wid = ((int64_t)blockIdx.x * FR_NT + threadIdx.x) / WAVE;
+  const int64_t nw = (int64_t)gridDim.x * FR_NT / WAVE;
   if (sh_pull) {
-    const int gl = lane % FR_G;
-    const uint64_t gmask = ((1ull << FR_G) - 1) << (lane - gl);
-    for (int64_t v0 = (int64_t)blockIdx.x * (FR_NT / FR_G); v0 < n; v0 += (int64_t)gridDim.x * (FR_NT / FR_G)) {
-      const int64_t v = v0 + threadIdx.x / FR_G;
+    // a lane checks its own vertex's first FR_FIRST arcs; the rows that
+    // have more and no moved neighbor among those are then walked by groups
+    // of FR_G lanes, FR_G rows at a time, each until a moved neighbor shows
+    const int gi = lane / FR_G, gl = lane % FR_G;
+    const uint64_t gmask = ((1ull << FR_G) - 1) << (gi * FR_G);
+    for (int64_t v0 = wid * WAVE; v0 < n; v0 += nw * WAVE) {
+      const int64_t v = v0 + lane;
       int64_t beg = 0, end = 0;
       if (v < n) {
         beg = off[v];
         end = off[v + 1];
       }
-      bool found = false;
-      // group-uniform trip count: the group's lanes share v
-      for (int64_t e0 = beg; e0 < end && !found; e0 += FR_G) {
-        const int64_t e = e0 + gl;
-        const bool m = e < end && moved[col[e]] != 0;
-        found = (__ballot(m) & gmask) != 0;
+      int32_t u[FR_FIRST];
+#pragma unroll
+      for (int r = 0; r < FR_FIRST; r++) u[r] = beg + r < end ? col[beg + r] : -1;
+      uint32_t mv = 0;  // every gather issued before any is tested
+#pragma unroll
+      for (int r = 0; r < FR_FIRST; r++) mv |= u[r] >= 0 ? (uint32_t)moved[u[r]] : 0u;
+      const bool found = mv != 0;
+      if (found) next[v] = 1;
+      uint64_t mk = __ballot(!found && end - beg > FR_FIRST);
+      while (mk) {
+        // group gi takes the gi-th lowest listed row, if there is one
+        uint64_t m2 = mk;
+        for (int k = 0; k < gi && m2; k++) m2 &= m2 - 1;
+        const int j = m2 ? __ffsll((unsigned long long)m2) - 1 : 0;
+        for (int k = 0; k < WAVE / FR_G && mk; k++) mk &= mk - 1;
+        const int64_t bj = __shfl(beg, j, WAVE), ej = __shfl(end, j, WAVE);
+        const int64_t b = m2 ? bj + FR_FIRST : 0, e1 = m2 ? ej : 0;
+        bool hit = false;
+        for (int64_t e0 = b; e0 < e1 && !hit; e0 += FR_G)  // group-uniform trips
+          hit = (__ballot(e0 + gl < e1 && moved[col[e0 + gl]] != 0) & gmask) != 0;
+        if (hit && gl == 0) next[v0 + j] = 1;
       }
-      if (v < n && gl == 0 && found) next[v] = 1;  // (wide movers may have marked v already)
     }
   } else {
-    const int64_t wid = ((int64_t)blockIdx.x * FR_NT + threadIdx.x) / WAVE;
-    const int64_t nw = (int64_t)gridDim.x * FR_NT / WAVE;
     for (int64_t v0 = wid * WAVE; v0 < n; v0 += nw * WAVE) {
       const int64_t v = v0 + lane;
       uint64_t mk = __ballot(v < n && moved[v] != 0);
@@ -3313,7 +3332,7 @@ void best_moves_run(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_
         }
         if (moved) {
           Ctx::Timer tm(&c, "bm_frontier", 0.0, (double)n, true);
-          c.launch(k_frontier, dim3((unsigned)std::min<int64_t>(cdiv(n, FR_NT / FR_G), (int64_t)c.num_cu * 16)),
+          c.launch(k_frontier, dim3((unsigned)std::min<int64_t>(cdiv(n, FR_NT), (int64_t)c.num_cu * 16)),
                    dim3(FR_NT), 0, (const int64_t *)g.off, (const int32_t *)g.col, n, (const uint8_t *)moved,
                    (const int64_t *)(blk + o_lctr), (int32_t)NB, next);
           LAUNCHCHECK();

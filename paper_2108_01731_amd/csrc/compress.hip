@@ -320,12 +320,14 @@ __global__ __launch_bounds__(CP_NT) void k_cp_count(const int64_t *__restrict__ 
 }
 
 // G lanes per vertex: writes the vertex's inter-cluster arcs, in row order,
-// as (map[v] << b | map[u], w) starting at eoff[v].
-template <int G, int WK, bool WEIGHTED>
+// as (map[v] << b | map[u], w) starting at eoff[v].  K / V: 64-bit keys and
+// weights, or 32-bit ones where 2b <= 32 and the weights are at most 32-bit
+// (the sort then moves half the bytes).
+template <int G, int WK, bool WEIGHTED, class K, class V>
 __global__ __launch_bounds__(CP_NT) void k_cp_emit(const int64_t *__restrict__ off, const int32_t *__restrict__ mu,
                                                    const void *__restrict__ wt, const int32_t *__restrict__ map,
                                                    int64_t n, const int64_t *__restrict__ eoff, int b,
-                                                   uint64_t *__restrict__ keys, int64_t *__restrict__ vals) {
+                                                   K *__restrict__ keys, V *__restrict__ vals) {
   const int gl = threadIdx.x % G;
   const int lane = lane_id();
   const int g0 = lane - gl;
@@ -358,14 +360,15 @@ __global__ __launch_bounds__(CP_NT) void k_cp_emit(const int64_t *__restrict__ o
     const uint64_t bal = (__ballot(is_inter) >> g0) & gmask;
     if (is_inter) {
       const int64_t at = pos + __popcll(bal & ((1ull << gl) - 1));
-      keys[at] = ((uint64_t)(uint32_t)mv << b) | (uint64_t)(uint32_t)m;
-      if constexpr (WEIGHTED) vals[at] = load_w<WK>(wt, e);
+      keys[at] = ((K)(uint32_t)mv << b) | (K)(uint32_t)m;
+      if constexpr (WEIGHTED) vals[at] = (V)load_w<WK>(wt, e);
     }
     pos += __popcll(bal);
   }
 }
 
-__global__ void k_cp_heads(const uint64_t *__restrict__ keys, int64_t T, uint8_t *__restrict__ head) {
+template <class K>
+__global__ void k_cp_heads(const K *__restrict__ keys, int64_t T, uint8_t *__restrict__ head) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < T; i += (int64_t)gridDim.x * blockDim.x)
     head[i] = (i == 0 || keys[i] != keys[i - 1]) ? 1 : 0;
 }
@@ -376,15 +379,15 @@ __global__ void k_cp_ustart(const uint8_t *__restrict__ head, const int64_t *__r
     if (head[i]) ustart[uidx[i]] = i;
 }
 
-template <class WOut>
-__global__ void k_cp_unique(const uint64_t *__restrict__ keys, const int64_t *__restrict__ ustart, int64_t U,
+template <class K, class WOut>
+__global__ void k_cp_unique(const K *__restrict__ keys, const int64_t *__restrict__ ustart, int64_t U,
                             int64_t T, const int64_t *__restrict__ P, int b, int32_t *__restrict__ ocol,
                             int32_t *__restrict__ orow, WOut *__restrict__ owt) {
   const uint64_t mask = (b >= 64) ? ~0ull : ((1ull << b) - 1);
   for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < U; j += (int64_t)gridDim.x * blockDim.x) {
     const int64_t s = ustart[j];
     const int64_t e = j + 1 < U ? ustart[j + 1] : T;
-    const uint64_t key = keys[s];
+    const uint64_t key = (uint64_t)keys[s];
     ocol[j] = (int32_t)(key & mask);
     orow[j] = (int32_t)(key >> b);
     const int64_t sum = P ? (P[e - 1] - (s > 0 ? P[s - 1] : 0)) : (e - s);
@@ -461,34 +464,47 @@ void launch_count(Ctx &c, const lcc_graph &g, const int32_t *map, int64_t *inter
 
 template <int G, int WK>
 void launch_emit(Ctx &c, const lcc_graph &g, const int32_t *map, const int32_t *mu, const int64_t *eoff, int b,
-                 uint64_t *keys, int64_t *vals) {
-  if (WK == LCC_WT_UNIT)
-    hipLaunchKernelGGL((k_cp_emit<G, WK, false>), dim3((unsigned)cdiv(g.n, CP_NT / G)), dim3(CP_NT), 0, c.stream,
-                       g.off, mu, g.wt, map, g.n, eoff, b, keys, vals);
-  else
-    hipLaunchKernelGGL((k_cp_emit<G, WK, true>), dim3((unsigned)cdiv(g.n, CP_NT / G)), dim3(CP_NT), 0, c.stream,
-                       g.off, mu, g.wt, map, g.n, eoff, b, keys, vals);
+                 uint64_t *keys, int64_t *vals, bool narrow) {
+  const dim3 gr((unsigned)cdiv(g.n, CP_NT / G));
+  if (narrow) {
+    uint32_t *k32 = reinterpret_cast<uint32_t *>(keys);
+    int32_t *v32 = reinterpret_cast<int32_t *>(vals);
+    if (WK == LCC_WT_UNIT)
+      hipLaunchKernelGGL((k_cp_emit<G, WK, false, uint32_t, int32_t>), gr, dim3(CP_NT), 0, c.stream, g.off, mu, g.wt,
+                         map, g.n, eoff, b, k32, v32);
+    else if (WK != LCC_WT_I64)
+      hipLaunchKernelGGL((k_cp_emit<G, WK, true, uint32_t, int32_t>), gr, dim3(CP_NT), 0, c.stream, g.off, mu, g.wt,
+                         map, g.n, eoff, b, k32, v32);
+    else
+      fail(LCC_ERR_DEVICE, "internal: 64-bit weights take 64-bit sort values");
+  } else if (WK == LCC_WT_UNIT) {
+    hipLaunchKernelGGL((k_cp_emit<G, WK, false, uint64_t, int64_t>), gr, dim3(CP_NT), 0, c.stream, g.off, mu, g.wt,
+                       map, g.n, eoff, b, keys, vals);
+  } else {
+    hipLaunchKernelGGL((k_cp_emit<G, WK, true, uint64_t, int64_t>), gr, dim3(CP_NT), 0, c.stream, g.off, mu, g.wt,
+                       map, g.n, eoff, b, keys, vals);
+  }
   LAUNCHCHECK();
 }
 
 template <int WK>
 void count_and_emit(Ctx &c, const lcc_graph &g, const int32_t *map, int32_t *mu, int64_t *inter, int64_t *intra,
-                    const int64_t *eoff, int b, uint64_t *keys, int64_t *vals, bool emit) {
+                    const int64_t *eoff, int b, uint64_t *keys, int64_t *vals, bool emit, bool narrow) {
   switch (lanes_for(g)) {
-    case 8: emit ? launch_emit<8, WK>(c, g, map, mu, eoff, b, keys, vals) : launch_count<8, WK>(c, g, map, inter, intra, mu); break;
-    case 16: emit ? launch_emit<16, WK>(c, g, map, mu, eoff, b, keys, vals) : launch_count<16, WK>(c, g, map, inter, intra, mu); break;
-    case 32: emit ? launch_emit<32, WK>(c, g, map, mu, eoff, b, keys, vals) : launch_count<32, WK>(c, g, map, inter, intra, mu); break;
-    default: emit ? launch_emit<64, WK>(c, g, map, mu, eoff, b, keys, vals) : launch_count<64, WK>(c, g, map, inter, intra, mu); break;
+    case 8: emit ? launch_emit<8, WK>(c, g, map, mu, eoff, b, keys, vals, narrow) : launch_count<8, WK>(c, g, map, inter, intra, mu); break;
+    case 16: emit ? launch_emit<16, WK>(c, g, map, mu, eoff, b, keys, vals, narrow) : launch_count<16, WK>(c, g, map, inter, intra, mu); break;
+    case 32: emit ? launch_emit<32, WK>(c, g, map, mu, eoff, b, keys, vals, narrow) : launch_count<32, WK>(c, g, map, inter, intra, mu); break;
+    default: emit ? launch_emit<64, WK>(c, g, map, mu, eoff, b, keys, vals, narrow) : launch_count<64, WK>(c, g, map, inter, intra, mu); break;
   }
 }
 
 void dispatch_ce(Ctx &c, const lcc_graph &g, const int32_t *map, int32_t *mu, int64_t *inter, int64_t *intra,
-                 const int64_t *eoff, int b, uint64_t *keys, int64_t *vals, bool emit) {
+                 const int64_t *eoff, int b, uint64_t *keys, int64_t *vals, bool emit, bool narrow = false) {
   switch (g.wt_kind) {
-    case LCC_WT_UNIT: count_and_emit<LCC_WT_UNIT>(c, g, map, mu, inter, intra, eoff, b, keys, vals, emit); break;
-    case LCC_WT_I16: count_and_emit<LCC_WT_I16>(c, g, map, mu, inter, intra, eoff, b, keys, vals, emit); break;
-    case LCC_WT_I32: count_and_emit<LCC_WT_I32>(c, g, map, mu, inter, intra, eoff, b, keys, vals, emit); break;
-    default: count_and_emit<LCC_WT_I64>(c, g, map, mu, inter, intra, eoff, b, keys, vals, emit); break;
+    case LCC_WT_UNIT: count_and_emit<LCC_WT_UNIT>(c, g, map, mu, inter, intra, eoff, b, keys, vals, emit, narrow); break;
+    case LCC_WT_I16: count_and_emit<LCC_WT_I16>(c, g, map, mu, inter, intra, eoff, b, keys, vals, emit, narrow); break;
+    case LCC_WT_I32: count_and_emit<LCC_WT_I32>(c, g, map, mu, inter, intra, eoff, b, keys, vals, emit, narrow); break;
+    default: count_and_emit<LCC_WT_I64>(c, g, map, mu, inter, intra, eoff, b, keys, vals, emit, narrow); break;
   }
 }
 
@@ -783,25 +799,36 @@ void compress_graph(Ctx &c, const lcc_graph &g, const int32_t *C, OwnedGraph &ou
   out.n = n2;
   const int b = bits_for(n2 > 1 ? n2 - 1 : 1);
   const bool weighted = g.wt_kind != LCC_WT_UNIT;
+  // 32-bit keys and weights when both fit: half the sort's bytes
+  const bool narrow = 2 * b <= 32 && g.wt_kind != LCC_WT_I64;
+  const double kb = narrow ? 4.0 : 8.0, vb = weighted ? kb : 0.0;
   uint64_t *k0 = c.buf<uint64_t>("cp.k0", (size_t)(T > 0 ? T : 1));
   uint64_t *k1 = c.buf<uint64_t>("cp.k1", (size_t)(T > 0 ? T : 1));
   int64_t *v0 = weighted ? c.buf<int64_t>("cp.v0", (size_t)(T > 0 ? T : 1)) : nullptr;
   int64_t *v1 = weighted ? c.buf<int64_t>("cp.v1", (size_t)(T > 0 ? T : 1)) : nullptr;
   if (T > 0) {
-    Ctx::Timer tm(&c, "cp_emit", 28.0 * (double)n + (4.0 + wb) * (double)g.arcs + (8.0 + (weighted ? 8 : 0)) * (double)T,
+    Ctx::Timer tm(&c, "cp_emit", 28.0 * (double)n + (4.0 + wb) * (double)g.arcs + (kb + vb) * (double)T,
                   (double)g.arcs);
-    dispatch_ce(c, g, map, mu, inter, intra, inter, b, k0, v0, true);
+    dispatch_ce(c, g, map, mu, inter, intra, inter, b, k0, v0, true, narrow);
   }
   uint64_t *ks = k0;
-  int64_t *vs = v0;
+  int64_t *vs = v0, *vfree = v1;  // vfree: the value buffer the sorted data left
   if (T > 1) {
-    Ctx::Timer tm(&c, "cp_sort", 2.0 * (8.0 + (weighted ? 8 : 0)) * (double)T * (double)cdiv(2 * b, RS_BITS),
-                  (double)T);
-    bool flip = weighted ? radix_sort<uint64_t, int64_t, true>(c, k0, v0, k1, v1, T, 2 * b, "cp.rs")
-                         : radix_sort<uint64_t, int64_t, false>(c, k0, nullptr, k1, nullptr, T, 2 * b, "cp.rs");
+    Ctx::Timer tm(&c, "cp_sort", 2.0 * (kb + vb) * (double)T * (double)cdiv(2 * b, RS_BITS), (double)T);
+    bool flip;
+    if (narrow) {
+      uint32_t *a0 = reinterpret_cast<uint32_t *>(k0), *a1 = reinterpret_cast<uint32_t *>(k1);
+      int32_t *w0 = reinterpret_cast<int32_t *>(v0), *w1 = reinterpret_cast<int32_t *>(v1);
+      flip = weighted ? radix_sort<uint32_t, int32_t, true>(c, a0, w0, a1, w1, T, 2 * b, "cp.rs")
+                      : radix_sort<uint32_t, int32_t, false>(c, a0, nullptr, a1, nullptr, T, 2 * b, "cp.rs");
+    } else {
+      flip = weighted ? radix_sort<uint64_t, int64_t, true>(c, k0, v0, k1, v1, T, 2 * b, "cp.rs")
+                      : radix_sort<uint64_t, int64_t, false>(c, k0, nullptr, k1, nullptr, T, 2 * b, "cp.rs");
+    }
     if (flip) {
       ks = k1;
       vs = v1;
+      vfree = v0;
     }
   }
   // unique coarse arcs
@@ -810,7 +837,12 @@ void compress_graph(Ctx &c, const lcc_graph &g, const int32_t *C, OwnedGraph &ou
   int64_t *uidx = c.buf<int64_t>("cp.uidx", (size_t)(T > 0 ? T : 1));
   if (T > 0) {
     Ctx::Timer tm(&c, "cp_reduce", (double)T * (8.0 + 1.0 + 8.0), (double)T);
-    hipLaunchKernelGGL(k_cp_heads, dim3(grid_for(T)), dim3(256), 0, c.stream, ks, T, head);
+    if (narrow)
+      hipLaunchKernelGGL(k_cp_heads<uint32_t>, dim3(grid_for(T)), dim3(256), 0, c.stream,
+                         (const uint32_t *)reinterpret_cast<uint32_t *>(ks), T, head);
+    else
+      hipLaunchKernelGGL(k_cp_heads<uint64_t>, dim3(grid_for(T)), dim3(256), 0, c.stream, (const uint64_t *)ks, T,
+                         head);
     LAUNCHCHECK();
     scan<uint8_t, int64_t>(c, head, uidx, T, false, tots + 2);
     d2h(c, &U, tots + 2, sizeof(int64_t));
@@ -830,16 +862,28 @@ void compress_graph(Ctx &c, const lcc_graph &g, const int32_t *C, OwnedGraph &ou
     hipLaunchKernelGGL(k_cp_ustart, dim3(grid_for(T)), dim3(256), 0, c.stream, head, uidx, T, ustart);
     LAUNCHCHECK();
     int64_t *P = nullptr;
-    if (weighted) {
+    if (weighted && narrow) {  // run sums from a 64-bit prefix of the 32-bit weights
+      scan<int32_t, int64_t>(c, reinterpret_cast<const int32_t *>(vs), vfree, T, true, (int64_t *)nullptr);
+      P = vfree;
+    } else if (weighted) {
       scan<int64_t, int64_t>(c, vs, vs, T, true, (int64_t *)nullptr);
       P = vs;
     }
-    if (wide)
-      hipLaunchKernelGGL((k_cp_unique<int64_t>), dim3(grid_for(U)), dim3(256), 0, c.stream, ks, ustart, U, T, P, b,
-                         out.col.as<int32_t>(), orow, out.wt.as<int64_t>());
+    const uint32_t *ks32 = reinterpret_cast<const uint32_t *>(ks);
+    if (narrow && wide)
+      hipLaunchKernelGGL((k_cp_unique<uint32_t, int64_t>), dim3(grid_for(U)), dim3(256), 0, c.stream, ks32, ustart, U,
+                         T, (const int64_t *)P, b, out.col.as<int32_t>(), orow, out.wt.as<int64_t>());
+    else if (narrow)
+      hipLaunchKernelGGL((k_cp_unique<uint32_t, int32_t>), dim3(grid_for(U)), dim3(256), 0, c.stream, ks32, ustart, U,
+                         T, (const int64_t *)P, b, out.col.as<int32_t>(), orow, out.wt.as<int32_t>());
+    else if (wide)
+      hipLaunchKernelGGL((k_cp_unique<uint64_t, int64_t>), dim3(grid_for(U)), dim3(256), 0, c.stream,
+                         (const uint64_t *)ks, ustart, U, T, (const int64_t *)P, b, out.col.as<int32_t>(), orow,
+                         out.wt.as<int64_t>());
     else
-      hipLaunchKernelGGL((k_cp_unique<int32_t>), dim3(grid_for(U)), dim3(256), 0, c.stream, ks, ustart, U, T, P, b,
-                         out.col.as<int32_t>(), orow, out.wt.as<int32_t>());
+      hipLaunchKernelGGL((k_cp_unique<uint64_t, int32_t>), dim3(grid_for(U)), dim3(256), 0, c.stream,
+                         (const uint64_t *)ks, ustart, U, T, (const int64_t *)P, b, out.col.as<int32_t>(), orow,
+                         out.wt.as<int32_t>());
     LAUNCHCHECK();
   }
   hipLaunchKernelGGL(k_cp_offsets, dim3(grid_for(n2 + 1)), dim3(256), 0, c.stream, orow, U, n2,
