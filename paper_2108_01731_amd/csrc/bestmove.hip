@@ -223,9 +223,25 @@ __device__ __forceinline__ int64_t score_floor(const int64_t *__restrict__ K, in
   return bX == INT32_MAX ? INT64_MIN : lq * bw - pk * K[bX];
 }
 
+
 // Multiplicative hash reduced to [0, H) (H need not be a power of two).
 __device__ __forceinline__ uint32_t slot_of(int32_t X, uint32_t H) {
   return (uint32_t)(((uint64_t)((uint32_t)X * 0x9E3779B1u) * (uint64_t)H) >> 32);
+}
+
+// Pruned scoring, the bound that needs no gather at all (the other one is
+// score_floor's): a vertex moves only to a target scoring strictly above its
+// stay score, so a candidate with q*w_X <= stay can never be the one it
+// moves to; and leaving such candidates out cannot change whether the empty
+// cluster (score 0) is taken instead, since that needs 0 > stay as well.
+// The stay score comes from the vertex's own cluster weight, read from its
+// slot of the table (the own cluster is always inserted), and K_c, loaded
+// with the vertex.
+template <class Acc>
+__device__ __forceinline__ int64_t own_weight(const int32_t *keys, const Acc *vals, uint32_t H, int32_t c) {
+  uint32_t h = slot_of(c, H);
+  while (keys[h] != c) h = (h + 1 == H) ? 0 : h + 1;
+  return (int64_t)vals[h];
 }
 
 __device__ __forceinline__ uint32_t pow2_at_least(int64_t x) {
@@ -458,6 +474,7 @@ __global__ __launch_bounds__(BM_NT) void k_bm_group(AggArgs a) {
     }
     if (valid) {
       const int64_t L = score_floor(a.K, lq, pk, hw, hX);
+      const int64_t stay0 = lq * own_weight(keys, vals, H, c) - pk * (Kc - kv);
       for (uint32_t j = gl; j < H; j += G) {
         const int32_t X = keys[j];
         if (X < 0) continue;
@@ -465,7 +482,7 @@ __global__ __launch_bounds__(BM_NT) void k_bm_group(AggArgs a) {
         const int64_t wx = (int64_t)vals[j];
         if (X == c) {
           wc = wx;
-        } else if (lq * wx >= L) {
+        } else if (lq * wx >= L && lq * wx > stay0) {
           const int64_t s = lq * wx - pk * a.K[X];
           if (better(s, X, best_s, best_id)) {
             best_s = s;
@@ -591,6 +608,7 @@ __global__ __launch_bounds__(NT) void k_bm_wide(AggArgs a) {
       block_heaviest<NT>(hw, hX);
     }
     const int64_t L = score_floor(a.K, lq, pk, hw, hX);
+    const int64_t stay0 = lq * own_weight(keys, vals, H, c) - pk * (Kc - kv);
     for (int32_t j = t; j < nocc; j += NT) {
       const uint32_t h = LIST ? occ[j] : (uint32_t)j;
       const int32_t X = keys[h];
@@ -599,7 +617,7 @@ __global__ __launch_bounds__(NT) void k_bm_wide(AggArgs a) {
       const int64_t wx = (int64_t)vals[h];
       if (X == c) {
         wc = wx;
-      } else if (lq * wx >= L) {
+      } else if (lq * wx >= L && lq * wx > stay0) {
         const int64_t s = lq * wx - pk * a.K[X];
         if (better(s, X, best_s, best_id)) {
           best_s = s;
@@ -798,6 +816,7 @@ __global__ __launch_bounds__(BM_NT) void k_bm_shared(AggArgs a, const int32_t *_
       const int64_t pk = lp * kv;
       int64_t best_s = INT64_MIN, wc = 0;
       int32_t best_id = ISO_ID;
+      const int64_t stay0 = lq * own_weight(keys, vals, H, c) - pk * (Kc - kv);  // (before the scan clears)
       int64_t hw = INT64_MIN;
       int32_t hX = INT32_MAX;
       if (a.prune) {
@@ -817,7 +836,7 @@ __global__ __launch_bounds__(BM_NT) void k_bm_shared(AggArgs a, const int32_t *_
         c_cands++;
         if (X == c) {
           wc = wx;
-        } else if (lq * wx >= L) {
+        } else if (lq * wx >= L && lq * wx > stay0) {
           const int64_t sc = lq * wx - pk * a.K[X];
           if (better(sc, X, best_s, best_id)) {
             best_s = sc;
@@ -1826,6 +1845,7 @@ __global__ __launch_bounds__(HR_NT) void k_hub_row(AggArgs a, uint8_t *__restric
       block_heaviest<HR_NT>(hw, hX);
     }
     const int64_t L = score_floor(a.K, lq, pk, hw, hX);
+    const int64_t stay0 = lq * own_weight(keys, vals, H, c) - pk * (Kc - kv);
     for (uint32_t j = t; j < H; j += HR_NT) {
       const int32_t X = keys[j];
       if (X < 0) continue;
@@ -1833,7 +1853,7 @@ __global__ __launch_bounds__(HR_NT) void k_hub_row(AggArgs a, uint8_t *__restric
       const int64_t wx = (int64_t)vals[j];
       if (X == c) {
         wc = wx;
-      } else if (lq * wx >= L) {
+      } else if (lq * wx >= L && lq * wx > stay0) {
         const int64_t sc = lq * wx - pk * a.K[X];
         if (better(sc, X, best_s, best_id)) {
           best_s = sc;
