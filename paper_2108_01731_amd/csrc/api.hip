@@ -611,9 +611,20 @@ lcc_status lcc_cluster(lcc_ctx *ctx, const lcc_graph *g, lcc_lambda lam, const l
       maxdeg.push_back(md);
       mindeg.push_back(mnd);
     }
+    // The objective: contraction keeps it, so the clustering flattened onto
+    // level 0 scores what the level-1 clustering scores on the level-1 graph
+    // (summed over 850M instead of 3.6G arcs on the benchmark graph); only
+    // the arcs of the vertices that level 0's refinement moves are read again.
+    ObjectiveParts parts1;
+    int32_t *P0 = nullptr;
     for (int l = top - 1; l >= 0; l--) {
       int32_t *C = Cl[l];
+      if (l == 0 && obj) parts1 = objective_parts(c, G[1], Cl[1]);
       flatten(c, G[l].n, maps[l], Cl[l + 1], C);
+      if (l == 0 && obj && prm->refine) {
+        P0 = c.buf<int32_t>("ob.P", (size_t)G[0].n);
+        HIPCHECK(hipMemcpyAsync(P0, C, (size_t)G[0].n * sizeof(int32_t), hipMemcpyDeviceToDevice, c.stream));
+      }
       if (prm->refine) {
         lcc_bm_stats st;
         auto a = clk::now();
@@ -626,7 +637,13 @@ lcc_status lcc_cluster(lcc_ctx *ctx, const lcc_graph *g, lcc_lambda lam, const l
     }
     cs.clusters = canonical_labels(c, g->n, Cl[0], labels_out);
     if (obj) {
-      i128 N = objective_num(c, *g, lam.p, lam.q, labels_out);
+      i128 N;
+      if (top == 0)
+        N = objective_num(c, *g, lam.p, lam.q, Cl[0]);
+      else if (P0)
+        N = objective_after_refine(c, *g, lam.p, lam.q, P0, Cl[0], parts1);
+      else  // no refinement: level 0 is the flattened level-1 clustering
+        N = objective_from_sums(lam.p, lam.q, parts1.pairs2, parts1.win2, parts1.ssum);
       fill_objective(N, lam.q, obj);
     }
     c.sync();

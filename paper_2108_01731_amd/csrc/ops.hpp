@@ -121,6 +121,20 @@ void compress_graph(Ctx &c, const lcc_graph &g, const int32_t *C, OwnedGraph &ou
 // Exact objective numerator of clustering C (ids in [0, n)).
 i128 objective_num(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const int32_t *C);
 
+// Its sums: over clusters of K^2 - KK, over intra-cluster arcs of w, of s.
+struct ObjectiveParts {
+  i128 pairs2 = 0, win2 = 0, ssum = 0;
+};
+ObjectiveParts objective_parts(Ctx &c, const lcc_graph &g, const int32_t *C);
+
+// The objective of clustering F of g from the sums of a clustering P of the
+// same graph, or of any graph P contracts to (contraction keeps s + win2 / 2
+// per clustering): F's volume term is computed, and its intra-cluster
+// weight is P's plus the change over the arcs of the vertices whose cluster
+// differs between P and F (P and F: ids in [0, n)).
+i128 objective_after_refine(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const int32_t *P, const int32_t *F,
+                            const ObjectiveParts &before);
+
 // The objective from caller-given per-cluster sums K, KK (ids in [0, n)):
 // 3 * nb block partials in `part` (sum over clusters of K^2 - KK, then the
 // intra-cluster arc weight, then sum s), combined by objective_from_sums.
