@@ -67,7 +67,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one 1 GiB device-to-device copy, a reference for HBM byte counters")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="summarize two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE, each with "
+                         "--calibrate-copy) per kernel and exit")
     args = ap.parse_args()
+    if args.pmc_summary:
+        return pmc_summary(*args.pmc_summary)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); sharding this path over several "
               "GPUs is described, not implemented", file=sys.stderr)
@@ -283,6 +288,49 @@ def measured_traffic(workload, kernel_class):
     return None
 
 
+def read_counter_csv(path):
+    """{kernel name: [values per dispatch]} of one counter from a rocprofv3
+    counter-collection CSV (column names located by keyword)."""
+    import csv
+
+    out = {}
+    with open(path, newline="") as f:
+        rd = csv.DictReader(f)
+        cols = rd.fieldnames or []
+        kcol = next(c for c in cols if "Kernel_Name" in c)
+        vcol = next(c for c in cols if "Counter_Value" in c)
+        for row in rd:
+            out.setdefault(row[kcol], []).append(float(row[vcol]))
+    return out
+
+
+def pmc_summary(fetch_csv, write_csv):
+    """Per-kernel HBM traffic from FETCH_SIZE and WRITE_SIZE counter runs
+    (KiB per dispatch), scaled by what the same counters read for the 1 GiB
+    calibration copy (the copy reads and writes 1073741824 bytes).  Prints a
+    markdown table, heaviest kernels first."""
+    fe = read_counter_csv(fetch_csv)
+    wr = read_counter_csv(write_csv)
+    copy = next(k for k in fe if "copyBuffer" in k)
+    kib = (1 << 30) / 1024.0
+    fs = kib / fe[copy][0]
+    ws = kib / wr[copy][0]
+    print(f"calibration copy: FETCH_SIZE {fe[copy][0]:.2f} KiB -> scale {fs:.4f}; "
+          f"WRITE_SIZE {wr[copy][0]:.2f} KiB -> scale {ws:.4f}")
+    print("| kernel | dispatches | fetch bytes / dispatch | write bytes / dispatch | total GB |")
+    print("|---|---:|---:|---:|---:|")
+    rows = []
+    for k, v in fe.items():
+        if k == copy:
+            continue
+        w = wr.get(k, [0.0])
+        f_b = sum(v) / len(v) * 1024 * fs
+        w_b = sum(w) / len(w) * 1024 * ws
+        rows.append((f_b * len(v) + w_b * len(w), k, len(v), f_b, w_b))
+    for tot, k, nd, f_b, w_b in sorted(rows, reverse=True)[:40]:
+        print(f"| `{k[:90]}` | {nd} | {f_b:,.0f} | {w_b:,.0f} | {tot / 1e9:.3f} |")
+
+
 def copy_bandwidth_gbs(dev, nbytes=1 << 30, reps=5):
     """Device-to-device copy rate (bytes read + written per second, GB/s):
     the HBM rate a plain streaming kernel reaches on this GPU, measured after
@@ -310,6 +358,11 @@ def with_copy_peak(roof, dev):
     log(f"device copy: {gbs:.0f} GB/s (read + write)")
     roof["copy_gbs_measured"] = gbs
     roof["frac_of_copy"] = roof["achieved"] / gbs
+    if roof.get("traffic"):
+        # the counter-measured bytes per launch over the same launch time:
+        # the rate the kernel actually moves through the fabric
+        roof["traffic_gbs"] = roof["traffic"] / (roof["avg_launch_ms"] * 1e-3) / 1e9
+        roof["traffic_frac"] = roof["traffic_gbs"] / HBM_PEAK_GBS
     return roof
 
 
