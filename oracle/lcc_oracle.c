@@ -66,6 +66,7 @@
  *   - Final labels: dense rank of each cluster's smallest member.
  */
 #include <stdint.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 #ifdef _OPENMP
@@ -550,6 +551,10 @@ static int best_move_impl(const orc_graph *g, int64_t p, int64_t q, const orc_pa
     rename_fresh(g, C, K, cnt, newid);
     if (it < ORC_MAX_ITER_STATS) { st->active_per_iter[it] = active_it; st->moves_per_iter[it] = moved_it; }
     st->moves += moved_it;
+    /* progress for long runs (ORC_PROGRESS set): one line per iteration */
+    if (getenv("ORC_PROGRESS"))
+      fprintf(stderr, "[oracle] level %d phase %d iteration %d: %lld active, %lld moved\n", (int)level, (int)phase,
+              (int)it, (long long)active_it, (long long)moved_it);
     if (moved_it == 0) { st->term = ORC_TERM_NO_MOVES; break; }
     st->moved_any = 1;
     if (prm->frontier == ORC_FRONTIER_ALL) {
@@ -866,6 +871,7 @@ int orc_cluster(const orc_graph *g0, int64_t p, int64_t q, const orc_params *prm
     }
     map[l] = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n ? n : 1));
     if (!map[l]) { rc = ORC_NOMEM; goto out; }
+    if (getenv("ORC_PROGRESS")) fprintf(stderr, "[oracle] level %d: contracting\n", (int)l);
     rc = orc_compress(&G[l], Cl[l], &owned[l + 1], map[l]);
     if (rc) goto out;
     orc_graph_out *o = &owned[l + 1];
