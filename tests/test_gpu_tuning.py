@@ -109,7 +109,7 @@ def test_autotuner_choice_is_result_invariant(ctx):
 def test_invalid_tuning_values_are_rejected(ctx):
     g = L.DeviceGraph.from_host(G.c1_sbm(1), "cuda")
     for bad in (dict(queue_ahead=-1), dict(small_level=L.LCC_SMALL_LEVEL_MAX + 1), dict(small_level=-2),
-                dict(low_merge=-1)):
+                dict(low_merge=-1), dict(hub_row_limit=-2), dict(score_pruning=2), dict(score_pruning=-2)):
         with pytest.raises(L.LccError) as e:
             L.lcc_cluster(ctx, g, 1, 100, L.Params(**bad))
         assert e.value.code == L.LCC_ERR_INVALID_ARG
