@@ -413,6 +413,43 @@ def test_invalid_inputs_are_rejected_before_any_output(ctx):
     assert np.array_equal(lo, ld.cpu().numpy()) and No == Nd
 
 
+def test_validation_covers_every_arc(ctx):
+    """The arc checks split a block's arcs into per-thread chunks: a bad
+    column at the very last arc, a self-loop in the middle of a hub row and
+    a repeated arc in the middle of a long row (rows are then not strictly
+    ascending, so the singleton shortcut that assumes distinct neighbors
+    must not be taken) are all seen."""
+    h = H.hub_graph(n=20000, m=40000, hubs=(9000, 3000, 600), seed=41)
+    g = dev(h)
+    last = L.DeviceGraph(off=g.off, col=g.col.clone(), k=g.k, wt=g.wt)
+    last.col[-1] = h.n + 5
+    with pytest.raises(L.LccError) as e:
+        L.lcc_cluster(ctx, last, 1, 40, dparams())
+    assert e.value.code == L.LCC_ERR_INVALID_ARG
+    loop = L.DeviceGraph(off=g.off, col=g.col.clone(), k=g.k, wt=g.wt)
+    mid = int(h.off[0]) + 4500  # vertex 0 is the 9000-arc hub
+    loop.col[mid] = 0
+    with pytest.raises(L.LccError) as e:
+        L.lcc_cluster(ctx, loop, 1, 40, dparams())
+    assert e.value.code == L.LCC_ERR_INVALID_ARG
+    # a repeated neighbor in the middle of the hub row (symmetric: the
+    # neighbor gets the reverse arc twice as well), rows sorted otherwise
+    hn = h.numpy()
+    off, col = hn.off.astype(np.int64), hn.col.astype(np.int32)
+    wt = None if hn.wt is None else hn.wt.copy()
+    rows = [np.sort(col[off[v]:off[v + 1]]) for v in range(hn.n)]
+    u = int(rows[0][4500])
+    rows[0] = np.sort(np.append(rows[0], u))
+    rows[u] = np.sort(np.append(rows[u], 0))
+    deg = np.array([len(r) for r in rows], np.int64)
+    off2 = np.concatenate([[0], np.cumsum(deg)]).astype(np.int64)
+    col2 = np.concatenate(rows).astype(np.int32)
+    rep = G.HostGraph(off2, col2, hn.k)
+    lo, No, _ = O.cluster(H.to_oracle(rep), 1, 40, oparams())
+    ld, Nd, _ = L.lcc_cluster(ctx, dev(rep), 1, 40, dparams())
+    assert np.array_equal(lo, ld.cpu().numpy()) and No == Nd
+
+
 def test_full_size_modularity_graph_sampled(ctx):
     """The 4M-vertex / 100M-edge Chung-Lu modularity workload, in the launch
     configuration the benchmark uses: sampled vertices of the first sub-round
