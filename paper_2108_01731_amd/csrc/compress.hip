@@ -2,15 +2,22 @@
 // canonical labels and per-cluster totals on gfx950.
 //
 // Compress: clusters are renumbered by the rank of their id among non-empty
-// ids (a prefix sum over presence flags); every inter-cluster arc becomes a
-// 64-bit key (map[u] << b | map[v]) carrying its weight; a stable LSD radix
-// sort over the 2b significant bits groups equal endpoint pairs; heads of
-// equal-key runs give the unique coarse arcs, and run sums come from an
-// inclusive prefix sum (differences at run boundaries, exact in int64) or,
-// for unit weights, from run lengths.  Row offsets are lower bounds of each
-// coarse vertex in the sorted row ids.  Per-cluster sums of k, kk and the
-// self weight come from a radix sort of the vertices by cluster followed by
-// prefix-sum differences: no atomics, so huge clusters cost nothing extra.
+// ids (a prefix sum over presence flags).  The input graph is symmetric with
+// equal weights both ways, so the coarse weight of a cluster pair X < Y is
+// the sum over the arcs from X into Y alone: only those "upper" arcs become
+// keys (X << b | Y, 64-bit, or 32-bit when 2b <= 32) carrying their weight.
+// A stable LSD radix sort over the 2b significant bits groups equal pairs;
+// heads of equal-key runs give the unique upper pairs, and run sums come from
+// an inclusive prefix sum (differences at run boundaries, exact in int64) or,
+// for unit weights, from run lengths.  The unique pairs, in (X, Y) order, are
+// the upper part of each coarse row.  Re-keyed as Y << b | X and sorted
+// stably on the high b bits they come out in (Y, X) order: the lower part of
+// each row, already in column order.  Row r of the coarse graph is its lower
+// part followed by its upper part, so its offset is the number of upper pairs
+// with X < r plus the number of lower entries with Y < r (two lower bounds).
+// Per-cluster sums of k, kk and the self weight come from a radix sort of the
+// vertices by cluster followed by prefix-sum differences: no atomics, so huge
+// clusters cost nothing extra.
 #include "ops.hpp"
 #include "prims.hpp"
 
@@ -288,9 +295,9 @@ __global__ void k_next_jbase(const int32_t *__restrict__ jid_next, int64_t n2, i
   }
 }
 
-// G lanes per vertex: number of inter-cluster arcs and weight of intra arcs;
-// mu[e] = map[col[e]] is kept for the emit pass, which then streams it
-// instead of gathering map a second time.
+// G lanes per vertex: number of upper arcs (into a cluster of higher rank)
+// and weight of intra arcs; mu[e] = map[col[e]] is kept for the emit pass,
+// which then streams it instead of gathering map a second time.
 template <int G, int WK>
 __global__ __launch_bounds__(CP_NT) void k_cp_count(const int64_t *__restrict__ off, const int32_t *__restrict__ col,
                                                     const void *__restrict__ wt, const int32_t *__restrict__ map,
@@ -304,8 +311,8 @@ __global__ __launch_bounds__(CP_NT) void k_cp_count(const int64_t *__restrict__ 
     for (int64_t e = off[v] + gl; e < off[v + 1]; e += G) {
       const int32_t m = map[col[e]];
       mu[e] = m;
-      if (m != mv) ni++;
-      else wi += load_w<WK>(wt, e);
+      if (m > mv) ni++;
+      else if (m == mv) wi += load_w<WK>(wt, e);
     }
   }
 #pragma unroll
@@ -319,8 +326,8 @@ __global__ __launch_bounds__(CP_NT) void k_cp_count(const int64_t *__restrict__ 
   }
 }
 
-// G lanes per vertex: writes the vertex's inter-cluster arcs, in row order,
-// as (map[v] << b | map[u], w) starting at eoff[v].  K / V: 64-bit keys and
+// G lanes per vertex: writes the vertex's upper arcs (map[u] > map[v]), in
+// row order, as (map[v] << b | map[u], w) starting at eoff[v].  K / V: 64-bit keys and
 // weights, or 32-bit ones where 2b <= 32 and the weights are at most 32-bit
 // (the sort then moves half the bytes).
 template <int G, int WK, bool WEIGHTED, class K, class V>
@@ -351,14 +358,14 @@ __global__ __launch_bounds__(CP_NT) void k_cp_emit(const int64_t *__restrict__ o
   }
   for (int64_t r = 0; r < maxr; r++) {
     const int64_t e = beg + r * G + gl;
-    bool is_inter = false;
+    bool is_up = false;
     int32_t m = 0;
     if (e < end) {
       m = mu[e];
-      is_inter = m != mv;
+      is_up = m > mv;
     }
-    const uint64_t bal = (__ballot(is_inter) >> g0) & gmask;
-    if (is_inter) {
+    const uint64_t bal = (__ballot(is_up) >> g0) & gmask;
+    if (is_up) {
       const int64_t at = pos + __popcll(bal & ((1ull << gl) - 1));
       keys[at] = ((K)(uint32_t)mv << b) | (K)(uint32_t)m;
       if constexpr (WEIGHTED) vals[at] = (V)load_w<WK>(wt, e);
@@ -379,32 +386,65 @@ __global__ void k_cp_ustart(const uint8_t *__restrict__ head, const int64_t *__r
     if (head[i]) ustart[uidx[i]] = i;
 }
 
+// Unique upper pair j = (X, Y), X < Y, from the sorted run starting at
+// ustart[j]: re-keyed as Y << b | X with its summed weight, into two copies
+// (one kept for placing the upper parts, one sorted into the lower parts).
 template <class K, class WOut>
-__global__ void k_cp_unique(const K *__restrict__ keys, const int64_t *__restrict__ ustart, int64_t U,
-                            int64_t T, const int64_t *__restrict__ P, int b, int32_t *__restrict__ ocol,
-                            int32_t *__restrict__ orow, WOut *__restrict__ owt) {
-  const uint64_t mask = (b >= 64) ? ~0ull : ((1ull << b) - 1);
+__global__ void k_cp_pairs(const K *__restrict__ keys, const int64_t *__restrict__ ustart, int64_t U, int64_t T,
+                           const int64_t *__restrict__ P, int b, K *__restrict__ tkeep, K *__restrict__ tsort,
+                           WOut *__restrict__ wkeep, WOut *__restrict__ wsort) {
+  const uint64_t mask = (1ull << b) - 1;
   for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < U; j += (int64_t)gridDim.x * blockDim.x) {
     const int64_t s = ustart[j];
     const int64_t e = j + 1 < U ? ustart[j + 1] : T;
     const uint64_t key = (uint64_t)keys[s];
-    ocol[j] = (int32_t)(key & mask);
-    orow[j] = (int32_t)(key >> b);
-    const int64_t sum = P ? (P[e - 1] - (s > 0 ? P[s - 1] : 0)) : (e - s);
-    owt[j] = (WOut)sum;
+    const K t = (K)(((key & mask) << b) | (key >> b));
+    const WOut w = (WOut)(P ? (P[e - 1] - (s > 0 ? P[s - 1] : 0)) : (e - s));
+    tkeep[j] = t;
+    tsort[j] = t;
+    wkeep[j] = w;
+    wsort[j] = w;
   }
 }
 
-// off[r] = first j with row[j] >= r, for r in [0, n2].
-__global__ void k_cp_offsets(const int32_t *__restrict__ row, int64_t U, int64_t n2, int64_t *__restrict__ off) {
+// start[r] = first i with ((keys[i] >> shift) & mask) >= r, for r in
+// [0, n2]; the field is non-decreasing over the U keys.
+template <class K>
+__global__ void k_cp_bounds(const K *__restrict__ keys, int64_t U, int shift, int b, int64_t n2,
+                            int64_t *__restrict__ start) {
+  const uint64_t mask = (1ull << b) - 1;
   for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r <= n2; r += (int64_t)gridDim.x * blockDim.x) {
     int64_t lo = 0, hi = U;
     while (lo < hi) {
-      int64_t mid = (lo + hi) >> 1;
-      if (row[mid] < r) lo = mid + 1;
+      const int64_t mid = (lo + hi) >> 1;
+      if ((int64_t)(((uint64_t)keys[mid] >> shift) & mask) < r) lo = mid + 1;
       else hi = mid;
     }
-    off[r] = lo;
+    start[r] = lo;
+  }
+}
+
+// off[r] = upper pairs of rows < r plus lower entries of rows < r.
+__global__ void k_cp_offsets(const int64_t *__restrict__ urow, const int64_t *__restrict__ lrow, int64_t n2,
+                             int64_t *__restrict__ off) {
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r <= n2; r += (int64_t)gridDim.x * blockDim.x)
+    off[r] = urow[r] + lrow[r];
+}
+
+// Places the coarse arcs.  Upper pair j (key Y << b | X, in (X, Y) order)
+// goes to row X after the row's lower part: off[X] + (lrow[X + 1] - lrow[X])
+// + (j - urow[X]) = j + lrow[X + 1].  Lower entry t of the (Y, X)-sorted
+// copy goes to row Y at off[Y] + (t - lrow[Y]) = t + urow[Y].
+template <class K, class WOut, bool UPPER>
+__global__ void k_cp_place(const K *__restrict__ tk, const WOut *__restrict__ tw, int64_t U, int b,
+                           const int64_t *__restrict__ other, int32_t *__restrict__ col, WOut *__restrict__ wt) {
+  const uint64_t mask = (1ull << b) - 1;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < U; j += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t key = (uint64_t)tk[j];
+    const int64_t hi = (int64_t)(key >> b), lo = (int64_t)(key & mask);
+    const int64_t at = UPPER ? j + other[lo + 1] : j + other[hi];
+    col[at] = (int32_t)(UPPER ? hi : lo);
+    wt[at] = tw[j];
   }
 }
 
@@ -748,6 +788,49 @@ void compress_dense(Ctx &c, const lcc_graph &g, const int32_t *C, OwnedGraph &ou
   if (maxdeg_out) *maxdeg_out = h[2];
 }
 
+// From the U unique upper pairs (sorted keys ks, runs at ustart, run sums
+// from the prefix P or run lengths) to the coarse CSR: both halves of every
+// row, row offsets included.
+template <class K, class WOut>
+void mirror_pairs(Ctx &c, const K *ks, const int64_t *ustart, int64_t U, int64_t T, const int64_t *P, int b,
+                  int64_t n2, OwnedGraph &out) {
+  int64_t *urow = c.buf<int64_t>("cp.urow", (size_t)(n2 + 1));
+  int64_t *lrow = c.buf<int64_t>("cp.lrow", (size_t)(n2 + 1));
+  int64_t *off = out.off.as<int64_t>();
+  Ctx::Timer tm(&c, "cp_mirror",
+                (double)U * (3.0 * (sizeof(K) + sizeof(WOut)) + 2.0 * (sizeof(K) + sizeof(WOut)) * cdiv(b, RS_BITS) +
+                             2.0 * (sizeof(K) + sizeof(WOut)) + 2.0 * (4.0 + sizeof(WOut))),
+                (double)U);
+  const size_t u = (size_t)(U > 0 ? U : 1);
+  K *tkk = c.buf<K>("cp.tkk", u), *tk0 = c.buf<K>("cp.tk0", u), *tk1 = c.buf<K>("cp.tk1", u);
+  WOut *twk = c.buf<WOut>("cp.twk", u), *tw0 = c.buf<WOut>("cp.tw0", u), *tw1 = c.buf<WOut>("cp.tw1", u);
+  bool flip = false;
+  if (U > 0) {
+    hipLaunchKernelGGL((k_cp_pairs<K, WOut>), dim3(grid_for(U)), dim3(256), 0, c.stream, ks, ustart, U, T, P, b,
+                       tkk, tk0, twk, tw0);
+    LAUNCHCHECK();
+    // stable on the high b bits (Y): the (X, Y) order becomes (Y, X)
+    flip = radix_sort<K, WOut, true>(c, tk0, tw0, tk1, tw1, U, 2 * b, "cp.ms", b);
+  }
+  const K *tl = flip ? tk1 : tk0;
+  const WOut *wl = flip ? tw1 : tw0;
+  hipLaunchKernelGGL((k_cp_bounds<K>), dim3(grid_for(n2 + 1)), dim3(256), 0, c.stream, tkk, U, 0, b, n2, urow);
+  LAUNCHCHECK();
+  hipLaunchKernelGGL((k_cp_bounds<K>), dim3(grid_for(n2 + 1)), dim3(256), 0, c.stream, tl, U, b, b, n2, lrow);
+  LAUNCHCHECK();
+  hipLaunchKernelGGL(k_cp_offsets, dim3(grid_for(n2 + 1)), dim3(256), 0, c.stream, urow, lrow, n2, off);
+  LAUNCHCHECK();
+  if (U <= 0) return;
+  int32_t *col = out.col.as<int32_t>();
+  WOut *wt = out.wt.as<WOut>();
+  hipLaunchKernelGGL((k_cp_place<K, WOut, true>), dim3(grid_for(U)), dim3(256), 0, c.stream, tkk, twk, U, b, lrow,
+                     col, wt);
+  LAUNCHCHECK();
+  hipLaunchKernelGGL((k_cp_place<K, WOut, false>), dim3(grid_for(U)), dim3(256), 0, c.stream, tl, wl, U, b, urow,
+                     col, wt);
+  LAUNCHCHECK();
+}
+
 }  // namespace
 
 void compress_graph(Ctx &c, const lcc_graph &g, const int32_t *C, OwnedGraph &out, int32_t *map, bool wide,
@@ -831,7 +914,7 @@ void compress_graph(Ctx &c, const lcc_graph &g, const int32_t *C, OwnedGraph &ou
       vfree = v0;
     }
   }
-  // unique coarse arcs
+  // unique upper pairs
   int64_t U = 0;
   uint8_t *head = c.buf<uint8_t>("cp.head", (size_t)(T > 0 ? T : 1));
   int64_t *uidx = c.buf<int64_t>("cp.uidx", (size_t)(T > 0 ? T : 1));
@@ -847,21 +930,21 @@ void compress_graph(Ctx &c, const lcc_graph &g, const int32_t *C, OwnedGraph &ou
     scan<uint8_t, int64_t>(c, head, uidx, T, false, tots + 2);
     d2h(c, &U, tots + 2, sizeof(int64_t));
   }
-  out.arcs = U;
+  out.arcs = 2 * U;
   c.ensure(out.off, (size_t)(n2 + 1) * sizeof(int64_t));
-  c.ensure(out.col, (size_t)(U > 0 ? U : 1) * sizeof(int32_t));
-  c.ensure(out.wt, (size_t)(U > 0 ? U : 1) * (wide ? 8 : 4));
+  c.ensure(out.col, (size_t)(U > 0 ? 2 * U : 1) * sizeof(int32_t));
+  c.ensure(out.wt, (size_t)(U > 0 ? 2 * U : 1) * (wide ? 8 : 4));
   // one extra slot: the per-cluster sums park dropped vertices at key n2
   c.ensure(out.k, (size_t)(n2 + 1) * sizeof(int64_t));
   c.ensure(out.s, (size_t)(n2 + 1) * sizeof(int64_t));
   c.ensure(out.kk, (size_t)(n2 + 1) * sizeof(int64_t));
-  int32_t *orow = c.buf<int32_t>("cp.row", (size_t)(U > 0 ? U : 1));
+  const int64_t *P = nullptr;
+  int64_t *ustart = c.buf<int64_t>("cp.ustart", (size_t)(U > 0 ? U : 1));
   if (U > 0) {
-    Ctx::Timer tm(&c, "cp_unique", (double)U * (8.0 + 8.0 + 4.0 + 4.0 + (wide ? 8 : 4)), (double)U);
-    int64_t *ustart = c.buf<int64_t>("cp.ustart", (size_t)U);
+    Ctx::Timer tm(&c, "cp_unique", (double)U * 8.0 + (double)T * (weighted ? (narrow ? 12.0 : 16.0) : 0.0),
+                  (double)U);
     hipLaunchKernelGGL(k_cp_ustart, dim3(grid_for(T)), dim3(256), 0, c.stream, head, uidx, T, ustart);
     LAUNCHCHECK();
-    int64_t *P = nullptr;
     if (weighted && narrow) {  // run sums from a 64-bit prefix of the 32-bit weights
       scan<int32_t, int64_t>(c, reinterpret_cast<const int32_t *>(vs), vfree, T, true, (int64_t *)nullptr);
       P = vfree;
@@ -869,26 +952,15 @@ void compress_graph(Ctx &c, const lcc_graph &g, const int32_t *C, OwnedGraph &ou
       scan<int64_t, int64_t>(c, vs, vs, T, true, (int64_t *)nullptr);
       P = vs;
     }
-    const uint32_t *ks32 = reinterpret_cast<const uint32_t *>(ks);
-    if (narrow && wide)
-      hipLaunchKernelGGL((k_cp_unique<uint32_t, int64_t>), dim3(grid_for(U)), dim3(256), 0, c.stream, ks32, ustart, U,
-                         T, (const int64_t *)P, b, out.col.as<int32_t>(), orow, out.wt.as<int64_t>());
-    else if (narrow)
-      hipLaunchKernelGGL((k_cp_unique<uint32_t, int32_t>), dim3(grid_for(U)), dim3(256), 0, c.stream, ks32, ustart, U,
-                         T, (const int64_t *)P, b, out.col.as<int32_t>(), orow, out.wt.as<int32_t>());
-    else if (wide)
-      hipLaunchKernelGGL((k_cp_unique<uint64_t, int64_t>), dim3(grid_for(U)), dim3(256), 0, c.stream,
-                         (const uint64_t *)ks, ustart, U, T, (const int64_t *)P, b, out.col.as<int32_t>(), orow,
-                         out.wt.as<int64_t>());
-    else
-      hipLaunchKernelGGL((k_cp_unique<uint64_t, int32_t>), dim3(grid_for(U)), dim3(256), 0, c.stream,
-                         (const uint64_t *)ks, ustart, U, T, (const int64_t *)P, b, out.col.as<int32_t>(), orow,
-                         out.wt.as<int32_t>());
-    LAUNCHCHECK();
   }
-  hipLaunchKernelGGL(k_cp_offsets, dim3(grid_for(n2 + 1)), dim3(256), 0, c.stream, orow, U, n2,
-                     out.off.as<int64_t>());
-  LAUNCHCHECK();
+  if (narrow && wide)
+    mirror_pairs<uint32_t, int64_t>(c, reinterpret_cast<const uint32_t *>(ks), ustart, U, T, P, b, n2, out);
+  else if (narrow)
+    mirror_pairs<uint32_t, int32_t>(c, reinterpret_cast<const uint32_t *>(ks), ustart, U, T, P, b, n2, out);
+  else if (wide)
+    mirror_pairs<uint64_t, int64_t>(c, ks, ustart, U, T, P, b, n2, out);
+  else
+    mirror_pairs<uint64_t, int32_t>(c, ks, ustart, U, T, P, b, n2, out);
   // per-cluster k', kk', s'
   {
     Ctx::Timer tm(&c, "cp_totals", 0.0, (double)n);

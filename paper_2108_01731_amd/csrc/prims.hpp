@@ -363,12 +363,12 @@ __global__ __launch_bounds__(RS_NT) void k_rs_scatter(const K *__restrict__ keys
   }
 }
 
-// Stable LSD sort of n keys on their low `bits` bits, carrying vals when
-// HASV.  Sorts between (keys, vals) and (tk, tv); returns true when the
-// sorted data ended in (tk, tv).
+// Stable LSD sort of n keys on bits [lo, bits), carrying vals when HASV.
+// Sorts between (keys, vals) and (tk, tv); returns true when the sorted data
+// ended in (tk, tv).
 template <class K, class V, bool HASV>
-bool radix_sort(Ctx &c, K *keys, V *vals, K *tk, V *tv, int64_t n, int bits, const char *tag = "rs") {
-  if (n <= 1 || bits <= 0) return false;
+bool radix_sort(Ctx &c, K *keys, V *vals, K *tk, V *tv, int64_t n, int bits, const char *tag = "rs", int lo = 0) {
+  if (n <= 1 || bits <= lo) return false;
   int64_t P = cdiv(n, 4096);
   int64_t maxP = (int64_t)c.num_cu * 8;
   if (P > maxP) P = maxP;
@@ -379,7 +379,7 @@ bool radix_sort(Ctx &c, K *keys, V *vals, K *tk, V *tv, int64_t n, int bits, con
   bool flip = false;
   K *ka = keys, *kb = tk;
   V *va = vals, *vb = tv;
-  for (int shift = 0; shift < bits; shift += RS_BITS) {
+  for (int shift = lo; shift < bits; shift += RS_BITS) {
     hipLaunchKernelGGL((k_rs_hist<K>), dim3((unsigned)P), dim3(RS_NT), 0, c.stream, ka, n, shift, per, hist);
     LAUNCHCHECK();
     scan<int64_t, int64_t>(c, hist, hist, P * RS_BINS, false, (int64_t *)nullptr, 1);
