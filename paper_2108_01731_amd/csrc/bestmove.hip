@@ -2622,6 +2622,56 @@ __global__ __launch_bounds__(BM_NT) void k_part_scatter(const int32_t *__restric
   }
 }
 
+// Orders each sub-round's hub bucket (rows wider than the degree-sized LDS
+// bins) by decreasing degree, ties by list position.  The hub kernels give
+// one block per row and blocks start in index order, so the longest rows now
+// start first instead of ending the launch on one long row started last.
+// Only the order of the list changes: every row is decided the same.  A
+// bucket of at most `spread` rows (they all start at once) or more than
+// HO_MAX rows keeps its order.  One block per sub-round.
+constexpr int HO_NT = 1024;
+constexpr int HO_MAX = 4096;
+static_assert(HO_MAX == 1 << 12, "the sort key keeps the list position in its low 12 bits");
+__global__ __launch_bounds__(HO_NT) void k_hub_order(const int64_t *__restrict__ dstart,
+                                                     const int64_t *__restrict__ off, int64_t spread,
+                                                     int32_t *__restrict__ blist) {
+  __shared__ uint64_t key[HO_MAX];
+  __shared__ int32_t vid[HO_MAX];
+  const int t = threadIdx.x;
+  const int b = blockIdx.x * NBINS + NBINS - 1;
+  const int64_t beg = dstart[b], m = dstart[b + 1] - beg;
+  if (m <= spread || m > HO_MAX) return;  // uniform
+  int P = 1;
+  while (P < m) P <<= 1;
+  for (int i = t; i < P; i += HO_NT) {
+    if (i < m) {
+      const int32_t v = blist[beg + i];
+      const int64_t deg = off[v + 1] - off[v];
+      const int64_t d = deg < INT32_MAX ? deg : INT32_MAX;
+      key[i] = ((uint64_t)(INT32_MAX - d) << 12) | (uint64_t)i;  // below 2^43, padding sorts last
+      vid[i] = v;
+    } else {
+      key[i] = ~0ull;
+    }
+  }
+  __syncthreads();
+  for (int k = 2; k <= P; k <<= 1)
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = t; i < P; i += HO_NT) {
+        const int x = i ^ j;
+        if (x > i) {
+          const uint64_t a = key[i], c = key[x];
+          if ((a > c) == ((i & k) == 0)) {
+            key[i] = c;
+            key[x] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  for (int i = t; i < m; i += HO_NT) blist[beg + i] = vid[key[i] & (HO_MAX - 1)];
+}
+
 __global__ void k_init_identity(const int64_t *__restrict__ k, int64_t *__restrict__ K, int32_t *__restrict__ cnt,
                                 int64_t n) {
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
@@ -3254,6 +3304,11 @@ void best_moves_run(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_
           hipLaunchKernelGGL(k_part_scatter, dim3((unsigned)part_grid), dim3(BM_NT), scatter_smem, c.stream, list, n,
                              na_dev, bucket_of, S, pcur, blist);
           LAUNCHCHECK();
+          if (shape.maxdeg > wide_max) {
+            hipLaunchKernelGGL(k_hub_order, dim3((unsigned)S), dim3(HO_NT), 0, c.stream,
+                               (const int64_t *)(blk + o_start), g.off, (int64_t)c.num_cu, blist);
+            LAUNCHCHECK();
+          }
         }
         for (int s = 0; s < S; s++) {
           const bool single = it == 0 && s == 0 && identity && shape.simple && !async;
@@ -3516,6 +3571,11 @@ void best_moves_run(Ctx &c, const lcc_graph &g, int64_t p, int64_t q, const lcc_
       hipLaunchKernelGGL(k_part_scatter, dim3((unsigned)part_grid), dim3(BM_NT), scatter_smem, c.stream, list, na,
                          (const int64_t *)nullptr, bucket_of, S, pcur, blist);
       LAUNCHCHECK();
+      if (shape.maxdeg > wide_max) {
+        hipLaunchKernelGGL(k_hub_order, dim3((unsigned)S), dim3(HO_NT), 0, c.stream, (const int64_t *)dstart, g.off,
+                           (int64_t)c.num_cu, blist);
+        LAUNCHCHECK();
+      }
     }
     d2h(c, hctr.data(), dctr, (size_t)2 * NB * sizeof(int64_t));
     std::vector<int64_t> start(NB + 1, 0);
