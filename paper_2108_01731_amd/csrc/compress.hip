@@ -327,10 +327,12 @@ __global__ __launch_bounds__(CP_NT) void k_cp_count(const int64_t *__restrict__ 
 }
 
 // G lanes per vertex: writes the vertex's upper arcs (map[u] > map[v]), in
-// row order, as (map[v] << b | map[u], w) starting at eoff[v].  K / V: 64-bit keys and
+// row order, as (map[v] << b | map[u], w) starting at eoff[v].  U rounds of
+// G arcs are loaded before any is written, so a wave keeps U loads per lane
+// in flight for each of its 64 / G vertices.  K / V: 64-bit keys and
 // weights, or 32-bit ones where 2b <= 32 and the weights are at most 32-bit
 // (the sort then moves half the bytes).
-template <int G, int WK, bool WEIGHTED, class K, class V>
+template <int G, int U, int WK, bool WEIGHTED, class K, class V>
 __global__ __launch_bounds__(CP_NT) void k_cp_emit(const int64_t *__restrict__ off, const int32_t *__restrict__ mu,
                                                    const void *__restrict__ wt, const int32_t *__restrict__ map,
                                                    int64_t n, const int64_t *__restrict__ eoff, int b,
@@ -349,28 +351,32 @@ __global__ __launch_bounds__(CP_NT) void k_cp_emit(const int64_t *__restrict__ o
     mv = map[v];
   }
   // every lane of the wave runs the same number of rounds (ballots need it)
-  int64_t rounds = cdiv(end - beg, G);
-  int64_t maxr = rounds;
+  int64_t maxr = cdiv(end - beg, G);
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
     int64_t y = __shfl_xor(maxr, o, WAVE);
     maxr = y > maxr ? y : maxr;
   }
-  for (int64_t r = 0; r < maxr; r++) {
-    const int64_t e = beg + r * G + gl;
-    bool is_up = false;
-    int32_t m = 0;
-    if (e < end) {
-      m = mu[e];
-      is_up = m > mv;
+  for (int64_t r = 0; r < maxr; r += U) {
+    int32_t m[U];
+    int64_t w[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const int64_t e = beg + (r + u) * G + gl;
+      m[u] = e < end ? mu[e] : mv;  // mv: not an upper arc
+      w[u] = WEIGHTED && e < end ? load_w<WK>(wt, e) : 0;
     }
-    const uint64_t bal = (__ballot(is_up) >> g0) & gmask;
-    if (is_up) {
-      const int64_t at = pos + __popcll(bal & ((1ull << gl) - 1));
-      keys[at] = ((K)(uint32_t)mv << b) | (K)(uint32_t)m;
-      if constexpr (WEIGHTED) vals[at] = (V)load_w<WK>(wt, e);
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const bool is_up = m[u] > mv;
+      const uint64_t bal = (__ballot(is_up) >> g0) & gmask;
+      if (is_up) {
+        const int64_t at = pos + __popcll(bal & ((1ull << gl) - 1));
+        keys[at] = ((K)(uint32_t)mv << b) | (K)(uint32_t)m[u];
+        if constexpr (WEIGHTED) vals[at] = (V)w[u];
+      }
+      pos += __popcll(bal);
     }
-    pos += __popcll(bal);
   }
 }
 
@@ -502,26 +508,29 @@ void launch_count(Ctx &c, const lcc_graph &g, const int32_t *map, int64_t *inter
   LAUNCHCHECK();
 }
 
-template <int G, int WK>
+// The emit covers the count pass's G arcs per vertex and round with at most
+// 16 lanes and G / 16 rounds loaded together.
+template <int GC, int WK>
 void launch_emit(Ctx &c, const lcc_graph &g, const int32_t *map, const int32_t *mu, const int64_t *eoff, int b,
                  uint64_t *keys, int64_t *vals, bool narrow) {
+  constexpr int G = GC > 16 ? 16 : GC, U = GC / G;
   const dim3 gr((unsigned)cdiv(g.n, CP_NT / G));
   if (narrow) {
     uint32_t *k32 = reinterpret_cast<uint32_t *>(keys);
     int32_t *v32 = reinterpret_cast<int32_t *>(vals);
     if (WK == LCC_WT_UNIT)
-      hipLaunchKernelGGL((k_cp_emit<G, WK, false, uint32_t, int32_t>), gr, dim3(CP_NT), 0, c.stream, g.off, mu, g.wt,
+      hipLaunchKernelGGL((k_cp_emit<G, U, WK, false, uint32_t, int32_t>), gr, dim3(CP_NT), 0, c.stream, g.off, mu, g.wt,
                          map, g.n, eoff, b, k32, v32);
     else if (WK != LCC_WT_I64)
-      hipLaunchKernelGGL((k_cp_emit<G, WK, true, uint32_t, int32_t>), gr, dim3(CP_NT), 0, c.stream, g.off, mu, g.wt,
+      hipLaunchKernelGGL((k_cp_emit<G, U, WK, true, uint32_t, int32_t>), gr, dim3(CP_NT), 0, c.stream, g.off, mu, g.wt,
                          map, g.n, eoff, b, k32, v32);
     else
       fail(LCC_ERR_DEVICE, "internal: 64-bit weights take 64-bit sort values");
   } else if (WK == LCC_WT_UNIT) {
-    hipLaunchKernelGGL((k_cp_emit<G, WK, false, uint64_t, int64_t>), gr, dim3(CP_NT), 0, c.stream, g.off, mu, g.wt,
+    hipLaunchKernelGGL((k_cp_emit<G, U, WK, false, uint64_t, int64_t>), gr, dim3(CP_NT), 0, c.stream, g.off, mu, g.wt,
                        map, g.n, eoff, b, keys, vals);
   } else {
-    hipLaunchKernelGGL((k_cp_emit<G, WK, true, uint64_t, int64_t>), gr, dim3(CP_NT), 0, c.stream, g.off, mu, g.wt,
+    hipLaunchKernelGGL((k_cp_emit<G, U, WK, true, uint64_t, int64_t>), gr, dim3(CP_NT), 0, c.stream, g.off, mu, g.wt,
                        map, g.n, eoff, b, keys, vals);
   }
   LAUNCHCHECK();
