@@ -140,6 +140,7 @@ enum : uint64_t {
 };
 
 constexpr int VA_NT = 256;
+constexpr int VA_U = 4;  // arcs per thread and step of the arc pass
 
 // Per-vertex checks and sums: one row of VAL_VROW values per block.
 __global__ __launch_bounds__(VA_NT) void k_validate_vertices(const int64_t *__restrict__ off, int64_t n, int64_t arcs,
@@ -214,25 +215,39 @@ __global__ __launch_bounds__(VA_NT) void k_validate_arcs(const int64_t *__restri
     for (int i = threadIdx.x; i <= nv; i += VA_NT) so[i] = off[vb + i];
     __syncthreads();
     const int64_t eb = so[0], ee = so[nv];
-    for (int64_t e = eb + threadIdx.x; e < ee; e += VA_NT) {
-      if (check) {
-        int lo = 0, hi = nv - 1;  // the row: last r with so[r] <= e
-        while (lo < hi) {
-          const int mid = (lo + hi + 1) >> 1;
-          if (so[mid] <= e) lo = mid;
-          else hi = mid - 1;
-        }
-        const int32_t u = col[e];
-        if (u < 0 || (int64_t)u >= n) err |= E_COL;
-        if ((int64_t)u == vb + lo) err |= E_SELF;
-        if (e > so[lo] && u <= col[e - 1]) err |= F_UNSORTED;
+    // VA_U strided arcs per thread at a time: their loads are in flight together
+    for (int64_t e0 = eb + threadIdx.x; e0 < ee; e0 += VA_U * VA_NT) {
+      int32_t u[VA_U], prev[VA_U];
+      int64_t w[VA_U];
+#pragma unroll
+      for (int j = 0; j < VA_U; j++) {
+        const int64_t e = e0 + (int64_t)j * VA_NT;
+        const bool in = e < ee;
+        u[j] = in && check ? col[e] : 0;
+        prev[j] = in && check && e > eb ? col[e - 1] : 0;
+        w[j] = in ? load_w<WK>(wt, e) : 0;
       }
-      const int64_t w = load_w<WK>(wt, e);
-      if (w < 0) {
-        neg = 1;
-        wabs = sat_add(wabs, w == INT64_MIN ? (1ull << 63) : (uint64_t)(-w));
-      } else {
-        wabs = sat_add(wabs, (uint64_t)w);
+#pragma unroll
+      for (int j = 0; j < VA_U; j++) {
+        const int64_t e = e0 + (int64_t)j * VA_NT;
+        if (e >= ee) break;
+        if (check) {
+          int lo = 0, hi = nv - 1;  // the row: last r with so[r] <= e
+          while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (so[mid] <= e) lo = mid;
+            else hi = mid - 1;
+          }
+          if (u[j] < 0 || (int64_t)u[j] >= n) err |= E_COL;
+          if ((int64_t)u[j] == vb + lo) err |= E_SELF;
+          if (e > so[lo] && u[j] <= prev[j]) err |= F_UNSORTED;
+        }
+        if (w[j] < 0) {
+          neg = 1;
+          wabs = sat_add(wabs, w[j] == INT64_MIN ? (1ull << 63) : (uint64_t)(-w[j]));
+        } else {
+          wabs = sat_add(wabs, (uint64_t)w[j]);
+        }
       }
     }
   }
@@ -322,7 +337,7 @@ void summary_from_arc_row(const uint64_t r[VAL_AROW], bool check, GraphSummary &
   }
 }
 
-int64_t validation_blocks(const Ctx &c, int64_t n) { return std::min<int64_t>(cdiv(n, VA_NT), (int64_t)c.num_cu * 4); }
+int64_t validation_blocks(const Ctx &c, int64_t n) { return std::min<int64_t>(cdiv(n, VA_NT), (int64_t)c.num_cu * 8); }
 
 GraphSummary summarize_graph(Ctx &c, const lcc_graph &g, const int32_t *C, bool check_structure) {
   GraphSummary s;

@@ -297,8 +297,9 @@ __global__ void k_next_jbase(const int32_t *__restrict__ jid_next, int64_t n2, i
 
 // G lanes per vertex: number of upper arcs (into a cluster of higher rank)
 // and weight of intra arcs; mu[e] = map[col[e]] is kept for the emit pass,
-// which then streams it instead of gathering map a second time.
-template <int G, int WK>
+// which then streams it instead of gathering map a second time.  U rounds of
+// G arcs are loaded, and their map entries gathered, together.
+template <int G, int U, int WK>
 __global__ __launch_bounds__(CP_NT) void k_cp_count(const int64_t *__restrict__ off, const int32_t *__restrict__ col,
                                                     const void *__restrict__ wt, const int32_t *__restrict__ map,
                                                     int64_t n, int64_t *__restrict__ inter,
@@ -308,11 +309,25 @@ __global__ __launch_bounds__(CP_NT) void k_cp_count(const int64_t *__restrict__ 
   int64_t ni = 0, wi = 0;
   if (v < n && map[v] >= 0) {
     const int32_t mv = map[v];
-    for (int64_t e = off[v] + gl; e < off[v + 1]; e += G) {
-      const int32_t m = map[col[e]];
-      mu[e] = m;
-      if (m > mv) ni++;
-      else if (m == mv) wi += load_w<WK>(wt, e);
+    const int64_t end = off[v + 1];
+    for (int64_t e0 = off[v] + gl; e0 < end; e0 += U * G) {
+      int32_t u[U], m[U];
+#pragma unroll
+      for (int j = 0; j < U; j++) {
+        const int64_t e = e0 + j * G;
+        u[j] = e < end ? col[e] : -1;
+      }
+#pragma unroll
+      for (int j = 0; j < U; j++) m[j] = u[j] >= 0 ? map[u[j]] : 0;
+#pragma unroll
+      for (int j = 0; j < U; j++) {
+        const int64_t e = e0 + j * G;
+        if (e < end) {
+          mu[e] = m[j];
+          if (m[j] > mv) ni++;
+          else if (m[j] == mv) wi += load_w<WK>(wt, e);
+        }
+      }
     }
   }
 #pragma unroll
@@ -501,9 +516,11 @@ int lanes_for(const lcc_graph &g) {
   return 64;
 }
 
+// One round at a time: the pass is bound by its map gathers, and narrower
+// lane groups with more rounds in flight measured slower.
 template <int G, int WK>
 void launch_count(Ctx &c, const lcc_graph &g, const int32_t *map, int64_t *inter, int64_t *intra, int32_t *mu) {
-  hipLaunchKernelGGL((k_cp_count<G, WK>), dim3((unsigned)cdiv(g.n, CP_NT / G)), dim3(CP_NT), 0, c.stream, g.off,
+  hipLaunchKernelGGL((k_cp_count<G, 1, WK>), dim3((unsigned)cdiv(g.n, CP_NT / G)), dim3(CP_NT), 0, c.stream, g.off,
                      g.col, g.wt, map, g.n, inter, intra, mu);
   LAUNCHCHECK();
 }
