@@ -202,6 +202,28 @@ def test_compress_parity_small_graphs(ctx, kind):
             assert_same_graph(go2, gd2)
 
 
+@pytest.mark.parametrize("n,ncl", [(5000, 700), (70000, 0)])
+def test_compress_parity_64_bit_coarse_weights(ctx, n, ncl):
+    """The sorting path (more than 2048 vertices) when the coarse weights need
+    64 bits (sum |w| >= 2^31): with 32-bit sort keys (700 clusters, 2b <= 32)
+    and with 64-bit ones (identity clustering of 70000 vertices); every output
+    array equals the oracle's, and so does a second level."""
+    h = G.random_signed(n, 6 * n, seed=n, wmin=-3, wmax=3, kmax=4)
+    h = H.with_weights(h, "i32", seed=1, lo=-(1 << 26), hi=1 << 26)
+    rng = np.random.default_rng(n)
+    C0 = (rng.integers(0, ncl, size=n) if ncl else np.arange(n)).astype(np.int32)
+    go, mo = O.compress(H.to_oracle(h), C0)
+    gd, md = L.lcc_compress(ctx, dev(h), torch.from_numpy(C0).cuda())
+    assert gd.wt.dtype == torch.int64
+    assert np.array_equal(mo, md.cpu().numpy())
+    assert_same_graph(go, gd)
+    C1 = rng.integers(0, max(1, go.n // 5), size=go.n).astype(np.int32)
+    go2, mo2 = O.compress(go, C1)
+    gd2, md2 = L.lcc_compress(ctx, gd, torch.from_numpy(C1).cuda())
+    assert np.array_equal(mo2, md2.cpu().numpy())
+    assert_same_graph(go2, gd2)
+
+
 @pytest.mark.parametrize("idx", range(8))
 def test_objective_parity(ctx, idx):
     name, h, p, q = cases()[idx]
