@@ -164,8 +164,9 @@ typedef struct lcc_params {
   int32_t score_pruning; /* skip the cluster-total read of every candidate whose arc weight alone cannot
                             reach the score of the vertex's heaviest candidate (such a candidate can
                             neither win nor tie): 0 = automatic (on levels of at least 2^23 vertices,
-                            in the kernels where it pays), 1 = on every level, -1 = never; other values
-                            are rejected */
+                            in the kernels where it pays; in lcc_cluster_batch and lcc_sweep only when
+                            a job has that many), 1 = on every level, -1 = never; other values are
+                            rejected */
   /* mode (changes results) */
   int32_t async_moves; /* 1 = the paper's asynchronous setting (Sec. 3.2.1): a vertex's move is applied
                           the moment it is decided, so the other decisions of its sub-round see it or
